@@ -1,0 +1,244 @@
+/*
+ * ocpamg -- AMG-preconditioned CG for the P1 finite element system of the
+ * reduced optimality equation of elliptic optimal control with energy
+ * regularization, on one MI355X (gfx950).
+ *
+ * The problem (Section 1, eq. (6)): find u with  -rho*Lap(u) + u = ubar  in
+ * Omega and u = 0 on Gamma, for a regularization parameter rho > 0 and a
+ * target ubar in L2(Omega).  Its Galerkin discretization with continuous
+ * piecewise-linear elements on a tetrahedral mesh (Section 2, discrete
+ * variational problem; Section 3, system (linsys)) is the sparse SPD system
+ *
+ *     (rho*K + M) u = f,   K_ij = int grad(phi_j).grad(phi_i),
+ *                          M_ij = int phi_j phi_i,   f_i = int ubar phi_i,
+ *
+ * over the interior vertices.  It is solved by preconditioned CG (Section 5)
+ * with an algebraic multigrid V(1,1)-cycle as preconditioner (Section 4.1).
+ *
+ * Conventions for every entry point below:
+ *   - Every function returns an int status: 0 success, negative on error
+ *     (OCP_ERR_*), pcg_solve may also return OCP_MAXIT (+1).  No exception
+ *     crosses this interface.  ocp_last_error() gives a message.
+ *   - Pointers documented as "device" point to memory on the context's GPU;
+ *     "host" pointers are ordinary CPU memory.  Arrays are dense, C order.
+ *   - All work is enqueued on the context's HIP stream.  Calls that return a
+ *     size or a status computed on the GPU synchronize that stream.
+ *   - Library-owned device memory comes from the allocator given to
+ *     ocp_ctx_create (or hipMalloc/hipFree when none is given).
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef OCPAMG_H
+#define OCPAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define OCP_OK 0
+#define OCP_MAXIT 1              /* pcg_solve: iteration cap reached (not an error) */
+#define OCP_ERR_INVALID_ARG (-1) /* NULL pointer, size <= 0, rho <= 0 or not finite, ... */
+#define OCP_ERR_BAD_MESH (-2)    /* vertex index out of range, degenerate tet, no interior vertex */
+#define OCP_ERR_OOM (-3)         /* the allocator returned NULL */
+#define OCP_ERR_BREAKDOWN (-4)   /* CG breakdown: p^T A p <= 0, r^T z <= 0, or non-finite */
+#define OCP_ERR_HIP (-5)         /* a HIP runtime call failed */
+#define OCP_ERR_UNSUPPORTED (-6) /* a size limit of the implementation was exceeded */
+
+/* --------------------------------------------------------------- context */
+typedef struct ocp_ctx ocp_ctx;
+typedef struct ocp_system ocp_system;
+typedef struct ocp_hierarchy ocp_hierarchy;
+
+/* Device allocator callbacks: alloc returns a device pointer of at least
+ * `bytes` bytes (256-byte aligned) or NULL; free releases it.  `user` is
+ * passed through.  Both may be NULL: then hipMalloc / hipFree are used. */
+typedef void *(*ocp_alloc_fn)(size_t bytes, void *user);
+typedef void (*ocp_free_fn)(void *ptr, void *user);
+
+/* Create a context bound to the current HIP device and to `stream`
+ * (a hipStream_t; NULL = the default stream).  The caller keeps ownership of
+ * the stream.  *out is freed by ocp_ctx_destroy. */
+int ocp_ctx_create(void *stream, ocp_alloc_fn alloc, ocp_free_fn free_fn, void *user,
+                   ocp_ctx **out);
+void ocp_ctx_destroy(ocp_ctx *ctx);
+/* Message of the last failed call on this context ("" if none).  Owned by the
+ * context; valid until the next call on it. */
+const char *ocp_last_error(const ocp_ctx *ctx);
+/* Library version string (static storage). */
+const char *ocp_version(void);
+
+/* ------------------------------------------------------------------ mesh */
+/* A tetrahedral mesh of Omega (Section 2: an admissible, shape-regular
+ * simplicial decomposition).  All arrays are device memory, borrowed for the
+ * duration of the call that receives the mesh. */
+typedef struct {
+    int32_t n_vertices;
+    int32_t n_tets;
+    const double *xyz;        /* device [n_vertices][3] vertex coordinates */
+    const int32_t *tets;      /* device [n_tets][4] vertex ids, any orientation */
+    const uint8_t *dirichlet; /* device [n_vertices], 1 = vertex on Gamma (u = 0) */
+} ocp_mesh;
+
+/* ---------------------------------------------------------------- target */
+#define OCP_TARGET_SINE_MODES 0 /* ubar = offset + sum_m amp[m] prod_d sin(k[m][d] pi x_d) */
+#define OCP_TARGET_BOX 1        /* ubar = 1 on the open box (lo, hi), 0 elsewhere */
+#define OCP_TARGET_NODAL 2      /* ubar = sum_v nodal[v] phi_v (P1 interpolant) */
+
+/* Target function ubar (Section 1).  Mode tables are host memory, copied by
+ * the call; `nodal` is device memory [n_vertices], borrowed for the call. */
+typedef struct {
+    int32_t kind;
+    int32_t n_modes;       /* SINE_MODES: number of modes, 1..4096 */
+    const int32_t *k;      /* host [n_modes][3], wave numbers 1..1024 */
+    const double *amp;     /* host [n_modes] */
+    double offset;
+    double lo[3], hi[3];   /* BOX */
+    const double *nodal;   /* NODAL: device [n_vertices] */
+} ocp_target;
+
+/* -------------------------------------------------------------- assembly */
+#define OCP_KEEP_KM 1 /* keep K and M values separately so fe_set_rho can re-weight */
+
+/* Assemble A = rho*K + M and f (Section 3, system (linsys)) on the interior
+ * vertices of `mesh` into CSR on the device.  Element matrices are exact; f
+ * uses the 4-point degree-2 rule on each tetrahedron.  The assembly is
+ * row-owned (one owner per row, no atomics on values) and bitwise
+ * deterministic.  Unknowns are the interior vertices in increasing vertex id.
+ * Errors: INVALID_ARG (NULL, counts <= 0, rho <= 0 or not finite, bad target),
+ * BAD_MESH (index out of range, |det| <= 1e-12 * longest edge^3, no interior
+ * vertex), UNSUPPORTED (a vertex with more than 255 incident tets or a row
+ * with more than 128 entries), OOM, HIP.  *out is freed by ocp_system_destroy. */
+int fe_assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_target *target,
+                int32_t flags, ocp_system **out);
+void ocp_system_destroy(ocp_system *sys);
+
+/* Replace rho: A = rho*K + M (needs OCP_KEEP_KM at assembly). */
+int fe_set_rho(ocp_ctx *ctx, ocp_system *sys, double rho);
+
+/* Load vector of another target on the same mesh: f_dev (device [n_dofs],
+ * caller-owned) receives f_i = int ubar phi_i.  The mesh given at assembly
+ * must still be alive. */
+int fe_load(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *mesh, const ocp_target *target,
+            double *f_dev);
+
+/* Read-only view of an assembled system (device pointers owned by `sys`). */
+typedef struct {
+    int32_t n_vertices;
+    int32_t n_dofs;             /* interior unknowns */
+    int64_t nnz;
+    double rho;
+    const int32_t *row_ptr;     /* device [n_dofs+1] */
+    const int32_t *col;         /* device [nnz], sorted within each row */
+    const double *val;          /* device [nnz] */
+    const double *f;            /* device [n_dofs] */
+    const int32_t *dof_of_vertex; /* device [n_vertices], -1 on Gamma */
+    const int32_t *vertex_of_dof; /* device [n_dofs] */
+} ocp_system_view;
+int ocp_system_get_view(const ocp_system *sys, ocp_system_view *view);
+
+/* y = A x for device vectors x, y of length n_dofs (the CSR SpMV kernel of
+ * the CG iteration). */
+int ocp_spmv(ocp_ctx *ctx, const ocp_system *sys, const double *x, double *y);
+
+/* ------------------------------------------------------------ AMG setup */
+#define OCP_PREC_FP64 0  /* hierarchy values and V-cycle in double */
+#define OCP_PREC_MIXED 1 /* hierarchy values and V-cycle in float, CG in double */
+
+#define OCP_SMOOTH_L1JACOBI 0
+#define OCP_SMOOTH_CHEBYSHEV 1
+
+typedef struct {
+    int32_t precision;   /* OCP_PREC_* */
+    int32_t smoother;    /* OCP_SMOOTH_* */
+    int32_t degree;      /* Chebyshev degree (>= 1); ignored by L1-Jacobi */
+    int32_t coarse_max;  /* stop coarsening at n <= coarse_max (dense solve there), <= 2048 */
+    int32_t max_levels;  /* 1..16 */
+    double theta;        /* strength threshold: |a_ij| >= theta sqrt(a_ii a_jj) */
+    double omega;        /* prolongator smoothing: omega/lambda_max(D^-1 A), 4/3 default */
+} ocp_amg_params;
+
+/* Fill `p` with the defaults (FP64, L1-Jacobi, coarse_max 512, 10 levels,
+ * theta 0.08, omega 4/3). */
+void amg_default_params(ocp_amg_params *p);
+
+/* Build a smoothed-aggregation hierarchy for the system's A (Section 4.1:
+ * coarse spaces from a coarsening of the matrix graph, interpolation P, and
+ * Galerkin coarse operators A_c = P^T A P, applied recursively).  NULL params
+ * means defaults.  The hierarchy must not outlive `sys`.
+ * Errors: INVALID_ARG, UNSUPPORTED (SpGEMM row too long), OOM, HIP. */
+int amg_setup(ocp_ctx *ctx, const ocp_system *sys, const ocp_amg_params *params,
+              ocp_hierarchy **out);
+void ocp_hierarchy_destroy(ocp_hierarchy *h);
+
+/* Read-only view of one level (device pointers owned by the hierarchy).
+ * Level 0 is the fine level (A is the system's matrix). P, R and agg are
+ * NULL on the last level; dense_inv is non-NULL only there. */
+typedef struct {
+    int32_t n_levels;
+    int32_t level;
+    int32_t n;                 /* rows of A on this level */
+    int32_t n_coarse;          /* columns of P (rows of the next level) */
+    int64_t nnz_A, nnz_P;
+    const int32_t *A_row_ptr, *A_col;
+    const double *A_val;
+    const int32_t *P_row_ptr, *P_col;
+    const double *P_val;
+    const int32_t *R_row_ptr, *R_col;
+    const double *R_val;
+    const int32_t *agg;        /* device [n], aggregate of each row */
+    const double *dense_inv;   /* device [n][n] inverse of A on the last level */
+    double lambda_max;         /* Gershgorin bound of D^-1 A used for omega */
+} ocp_level_view;
+int ocp_hierarchy_get_level(const ocp_hierarchy *h, int32_t level, ocp_level_view *view);
+
+/* z = B r: one V(1,1)-cycle with zero initial guess (Section 4.1, two-grid
+ * operator applied recursively).  r, z: device [n_dofs]. */
+int amg_vcycle(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r, double *z);
+
+/* ---------------------------------------------------------------- solve */
+#define OCP_STOP_L2 0      /* stop when ||r_k||_2 <= rtol ||f||_2 (default) */
+#define OCP_STOP_PRECOND 1 /* stop when sqrt(r_k^T z_k) <= rtol sqrt(r_0^T z_0) */
+
+typedef struct {
+    int32_t iterations;
+    int32_t status;         /* same value pcg_solve returns */
+    double rel_res_l2;      /* ||r_k|| / ||f|| of the CG recurrence */
+    double rel_res_precond; /* sqrt(r_k^T z_k / r_0^T z_0) */
+    double true_rel_res;    /* ||f - A u|| / ||f|| recomputed in double at exit */
+    double solve_ms;        /* GPU time of the solve (events on the context stream) */
+} ocp_solve_info;
+
+/* Preconditioned CG from u = 0 (Section 5: PCG, one V(1,1)-cycle per
+ * iteration as preconditioner; tolerance 1e-8 in the paper).
+ *   h      hierarchy from amg_setup, or NULL for Jacobi preconditioning
+ *   f      device [n_dofs] right-hand side, or NULL for the system's f
+ *   u      device [n_vertices] output, caller-owned; Dirichlet entries set 0
+ *   rtol   > 0;  maxit >= 1;  flags: OCP_STOP_L2 or OCP_STOP_PRECOND
+ * Blocks until converged or capped.  Returns 0 (converged), OCP_MAXIT (u holds
+ * the last iterate), OCP_ERR_BREAKDOWN, or another error. */
+int pcg_solve(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, const double *f,
+              double *u, double rtol, int32_t maxit, int32_t flags, ocp_solve_info *info);
+
+/* ------------------------------------------------------- kernel timing */
+#define OCP_KERNEL_CG_SPMV 0      /* q = A p with p.q, FP64 CSR (the CG iteration's SpMV) */
+#define OCP_KERNEL_VC_PRE0 1      /* fine-level pre-smoother fused with the residual */
+#define OCP_KERNEL_VC_POST0 2     /* fine-level post-smoother with r.z */
+#define OCP_KERNEL_VC_RESTRICT0 3 /* fine-level restriction R r */
+#define OCP_KERNEL_VC_PROLONG0 4  /* fine-level prolongation D^-1 b + P e */
+
+/* Live timing of selected kernels with HIP events on the context stream.
+ * ocp_profile_enable(ctx, 1) clears the counters and brackets every launch of
+ * the kernels above inside pcg_solve with an event pair; launches of the
+ * solve's final iteration (which may return early after convergence) are not
+ * counted.  ocp_profile_read returns the number of counted launches and their
+ * summed duration in milliseconds. */
+int ocp_profile_enable(ocp_ctx *ctx, int32_t on);
+int ocp_profile_read(ocp_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OCPAMG_H */

@@ -1,0 +1,455 @@
+"""ctypes binding of libocpamg.so -- argument marshalling only.
+
+Every computation runs in the HIP library; this module converts torch tensors
+and target descriptors to the C structures of ``include/ocpamg.h`` and back.
+PyTorch supplies device memory (through the library's allocator callbacks)
+and the stream.  There is no CPU fallback: if the library is missing, every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libocpamg.so")
+
+OK, MAXIT = 0, 1
+ERR_INVALID_ARG, ERR_BAD_MESH, ERR_OOM, ERR_BREAKDOWN, ERR_HIP, ERR_UNSUPPORTED = -1, -2, -3, -4, -5, -6
+KEEP_KM = 1
+PREC_FP64, PREC_MIXED = 0, 1
+SMOOTH_L1JACOBI, SMOOTH_CHEBYSHEV = 0, 1
+STOP_L2, STOP_PRECOND = 0, 1
+TARGET_SINE, TARGET_BOX, TARGET_NODAL = 0, 1, 2
+
+
+class OcpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ocpamg error {code}: {msg}")
+        self.code = code
+
+
+# --------------------------------------------------------------- structures
+class _Mesh(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_tets", C.c_int32), ("xyz", C.c_void_p),
+                ("tets", C.c_void_p), ("dirichlet", C.c_void_p)]
+
+
+class _Target(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_modes", C.c_int32), ("k", C.POINTER(C.c_int32)),
+                ("amp", C.POINTER(C.c_double)), ("offset", C.c_double),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("nodal", C.c_void_p)]
+
+
+class _SystemView(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_dofs", C.c_int32), ("nnz", C.c_int64),
+                ("rho", C.c_double), ("row_ptr", C.c_void_p), ("col", C.c_void_p),
+                ("val", C.c_void_p), ("f", C.c_void_p), ("dof_of_vertex", C.c_void_p),
+                ("vertex_of_dof", C.c_void_p)]
+
+
+class _AmgParams(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("smoother", C.c_int32), ("degree", C.c_int32),
+                ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("theta", C.c_double),
+                ("omega", C.c_double)]
+
+
+class _LevelView(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("level", C.c_int32), ("n", C.c_int32),
+                ("n_coarse", C.c_int32), ("nnz_A", C.c_int64), ("nnz_P", C.c_int64),
+                ("A_row_ptr", C.c_void_p), ("A_col", C.c_void_p), ("A_val", C.c_void_p),
+                ("P_row_ptr", C.c_void_p), ("P_col", C.c_void_p), ("P_val", C.c_void_p),
+                ("R_row_ptr", C.c_void_p), ("R_col", C.c_void_p), ("R_val", C.c_void_p),
+                ("agg", C.c_void_p), ("dense_inv", C.c_void_p), ("lambda_max", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("status", C.c_int32), ("rel_res_l2", C.c_double),
+                ("rel_res_precond", C.c_double), ("true_rel_res", C.c_double),
+                ("solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+# every exported entry point and its ctypes signature
+_SIGS = {
+    "ocp_version": (C.c_char_p, []),
+    "ocp_ctx_create": (C.c_int, [C.c_void_p, ALLOC_FN, FREE_FN, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "ocp_ctx_destroy": (None, [C.c_void_p]),
+    "ocp_last_error": (C.c_char_p, [C.c_void_p]),
+    "fe_assemble": (C.c_int, [C.c_void_p, C.POINTER(_Mesh), C.c_double, C.POINTER(_Target), C.c_int32,
+                              C.POINTER(C.c_void_p)]),
+    "ocp_system_destroy": (None, [C.c_void_p]),
+    "fe_set_rho": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double]),
+    "fe_load": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(_Mesh), C.POINTER(_Target), C.c_void_p]),
+    "ocp_system_get_view": (C.c_int, [C.c_void_p, C.POINTER(_SystemView)]),
+    "ocp_spmv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "amg_default_params": (None, [C.POINTER(_AmgParams)]),
+    "amg_setup": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(_AmgParams), C.POINTER(C.c_void_p)]),
+    "ocp_hierarchy_destroy": (None, [C.c_void_p]),
+    "ocp_hierarchy_get_level": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(_LevelView)]),
+    "amg_vcycle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pcg_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                            C.c_int32, C.c_int32, C.POINTER(SolveInfo)]),
+    "ocp_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ocp_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+}
+
+KERNEL_CG_SPMV, KERNEL_VC_PRE0, KERNEL_VC_POST0, KERNEL_VC_RESTRICT0, KERNEL_VC_PROLONG0 = 0, 1, 2, 3, 4
+
+_lib = None
+
+
+def lib():
+    """Load libocpamg.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+# ---------------------------------------------------------------- helpers
+def _torch():
+    import torch
+    return torch
+
+
+_hip = None
+
+
+def _hip_runtime():
+    global _hip
+    if _hip is None:
+        _torch()  # the HIP runtime is loaded with torch
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.restype = C.c_int
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipDeviceSynchronize.restype = C.c_int
+    return _hip
+
+
+_DT = {"i4": ("int32", 4), "f8": ("float64", 8), "f4": ("float32", 4), "u1": ("uint8", 1)}
+
+
+def device_view(ptr: int, shape, dtype: str):
+    """A torch tensor holding a copy of library-owned device memory."""
+    torch = _torch()
+    shape = (int(shape),) if np.isscalar(shape) else tuple(int(s) for s in shape)
+    name, size = _DT[dtype]
+    out = torch.zeros(shape, dtype=getattr(torch, name), device="cuda")
+    nbytes = int(np.prod(shape)) * size
+    if ptr and nbytes:
+        hip = _hip_runtime()
+        if hip.hipDeviceSynchronize() != 0:
+            raise RuntimeError("hipDeviceSynchronize failed")
+        rc = hip.hipMemcpy(C.c_void_p(out.data_ptr()), C.c_void_p(int(ptr)), nbytes, 4)  # hipMemcpyDefault
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpy failed ({rc})")
+    return out
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+# ---------------------------------------------------------------- context
+class Context:
+    """Library context bound to a torch stream and torch's caching allocator."""
+
+    def __init__(self, stream=None, torch_allocator: bool = True):
+        torch = _torch()
+        L = lib()
+        self.device = torch.cuda.current_device()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        sp = int(self.stream.cuda_stream)
+        if torch_allocator:
+            dev, st = self.device, self.stream
+
+            def _alloc(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, st)
+                except Exception:
+                    return None
+
+            def _free(ptr, user):
+                try:
+                    torch.cuda.caching_allocator_delete(int(ptr))
+                except Exception:
+                    pass
+
+            self._alloc = ALLOC_FN(_alloc)
+            self._free = FREE_FN(_free)
+        else:
+            self._alloc = ALLOC_FN()
+            self._free = FREE_FN()
+        h = C.c_void_p()
+        rc = L.ocp_ctx_create(C.c_void_p(sp), self._alloc, self._free, None, C.byref(h))
+        if rc != OK:
+            raise OcpError(rc, "context creation failed")
+        self.handle = h
+
+    def last_error(self) -> str:
+        return lib().ocp_last_error(self.handle).decode()
+
+    def check(self, rc: int, ok=(OK,)):
+        if rc not in ok:
+            raise OcpError(rc, self.last_error())
+        return rc
+
+    def profile(self, on: bool = True):
+        self.check(lib().ocp_profile_enable(self.handle, int(bool(on))))
+
+    def kernel_timing(self, kernel: int):
+        """(launches, total milliseconds) of a profiled kernel."""
+        n = C.c_int64()
+        ms = C.c_double()
+        self.check(lib().ocp_profile_read(self.handle, int(kernel), C.byref(n), C.byref(ms)))
+        return int(n.value), float(ms.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ocp_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------- mesh
+@dataclass
+class DeviceMesh:
+    xyz: object        # torch float64 [nv,3] on the GPU
+    tets: object       # torch int32 [nt,4]
+    dirichlet: object  # torch uint8 [nv]
+
+    @property
+    def n_vertices(self):
+        return int(self.xyz.shape[0])
+
+    @property
+    def n_tets(self):
+        return int(self.tets.shape[0])
+
+    def struct(self) -> _Mesh:
+        return _Mesh(self.n_vertices, self.n_tets, _ptr(self.xyz), _ptr(self.tets), _ptr(self.dirichlet))
+
+
+def upload_mesh(mesh) -> DeviceMesh:
+    """Copy an ``ocp_inputs.Mesh`` to the GPU."""
+    torch = _torch()
+    return DeviceMesh(xyz=torch.from_numpy(np.ascontiguousarray(mesh.xyz)).cuda(),
+                      tets=torch.from_numpy(np.ascontiguousarray(mesh.tets, dtype=np.int32)).cuda(),
+                      dirichlet=torch.from_numpy(np.ascontiguousarray(mesh.dirichlet, dtype=np.uint8)).cuda())
+
+
+def target_struct(target, keep: list) -> _Target:
+    t = _Target()
+    if target.kind == "sine":
+        k = np.ascontiguousarray(target.k, dtype=np.int32)
+        a = np.ascontiguousarray(target.amp, dtype=np.float64)
+        keep += [k, a]
+        t.kind = TARGET_SINE
+        t.n_modes = int(k.shape[0])
+        t.k = k.ctypes.data_as(C.POINTER(C.c_int32))
+        t.amp = a.ctypes.data_as(C.POINTER(C.c_double))
+        t.offset = float(target.offset)
+    elif target.kind == "box":
+        t.kind = TARGET_BOX
+        for d in range(3):
+            t.lo[d] = float(target.lo[d])
+            t.hi[d] = float(target.hi[d])
+    elif target.kind == "nodal":
+        torch = _torch()
+        v = target.values
+        if not (hasattr(v, "is_cuda") and v.is_cuda):
+            v = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).cuda()
+        keep.append(v)
+        t.kind = TARGET_NODAL
+        t.nodal = _ptr(v)
+    else:
+        raise ValueError(f"unknown target kind {target.kind!r}")
+    return t
+
+
+# ----------------------------------------------------------------- system
+class System:
+    def __init__(self, ctx: Context, handle, mesh: DeviceMesh):
+        self.ctx = ctx
+        self.handle = handle
+        self.mesh = mesh   # keeps the device mesh alive (fe_load reads it)
+
+    def view(self) -> _SystemView:
+        v = _SystemView()
+        self.ctx.check(lib().ocp_system_get_view(self.handle, C.byref(v)))
+        return v
+
+    @property
+    def n(self) -> int:
+        return int(self.view().n_dofs)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.view().nnz)
+
+    def csr(self):
+        """(row_ptr, col, val) as torch tensors viewing the library's arrays."""
+        v = self.view()
+        return (device_view(v.row_ptr, (v.n_dofs + 1,), "i4"), device_view(v.col, (v.nnz,), "i4"),
+                device_view(v.val, (v.nnz,), "f8"))
+
+    def f(self):
+        v = self.view()
+        return device_view(v.f, (v.n_dofs,), "f8")
+
+    def dof_of_vertex(self):
+        v = self.view()
+        return device_view(v.dof_of_vertex, (v.n_vertices,), "i4")
+
+    def vertex_of_dof(self):
+        v = self.view()
+        return device_view(v.vertex_of_dof, (v.n_dofs,), "i4")
+
+    def spmv(self, x, y=None):
+        torch = _torch()
+        if y is None:
+            y = torch.empty_like(x)
+        self.ctx.check(lib().ocp_spmv(self.ctx.handle, self.handle, _ptr(x), _ptr(y)))
+        return y
+
+    def set_rho(self, rho: float):
+        self.ctx.check(lib().fe_set_rho(self.ctx.handle, self.handle, float(rho)))
+
+    def load(self, target, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        keep = []
+        t = target_struct(target, keep)
+        m = self.mesh.struct()
+        self.ctx.check(lib().fe_load(self.ctx.handle, self.handle, C.byref(m), C.byref(t), _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ocp_system_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fe_assemble(ctx: Context, mesh: DeviceMesh, rho: float, target, flags: int = 0) -> System:
+    keep = []
+    t = target_struct(target, keep)
+    m = mesh.struct()
+    h = C.c_void_p()
+    ctx.check(lib().fe_assemble(ctx.handle, C.byref(m), float(rho), C.byref(t), int(flags), C.byref(h)))
+    return System(ctx, h, mesh)
+
+
+# -------------------------------------------------------------- hierarchy
+def default_params() -> _AmgParams:
+    p = _AmgParams()
+    lib().amg_default_params(C.byref(p))
+    return p
+
+
+class Hierarchy:
+    def __init__(self, ctx: Context, handle, system: System, params: _AmgParams):
+        self.ctx = ctx
+        self.handle = handle
+        self.system = system
+        self.params = params
+
+    def level(self, l: int) -> _LevelView:
+        v = _LevelView()
+        self.ctx.check(lib().ocp_hierarchy_get_level(self.handle, int(l), C.byref(v)))
+        return v
+
+    @property
+    def n_levels(self) -> int:
+        return int(self.level(0).n_levels)
+
+    def level_arrays(self, l: int) -> dict:
+        v = self.level(l)
+        out = {"n": v.n, "nc": v.n_coarse, "lambda_max": v.lambda_max,
+               "A": (device_view(v.A_row_ptr, (v.n + 1,), "i4"), device_view(v.A_col, (v.nnz_A,), "i4"),
+                     device_view(v.A_val, (v.nnz_A,), "f8"))}
+        if v.P_row_ptr:
+            out["P"] = (device_view(v.P_row_ptr, (v.n + 1,), "i4"), device_view(v.P_col, (v.nnz_P,), "i4"),
+                        device_view(v.P_val, (v.nnz_P,), "f8"))
+            out["R"] = (device_view(v.R_row_ptr, (v.n_coarse + 1,), "i4"), device_view(v.R_col, (v.nnz_P,), "i4"),
+                        device_view(v.R_val, (v.nnz_P,), "f8"))
+            out["agg"] = device_view(v.agg, (v.n,), "i4")
+        if v.dense_inv:
+            out["dense_inv"] = device_view(v.dense_inv, (v.n, v.n), "f8")
+        return out
+
+    def vcycle(self, r, z=None):
+        torch = _torch()
+        if z is None:
+            z = torch.empty_like(r)
+        self.ctx.check(lib().amg_vcycle(self.ctx.handle, self.handle, _ptr(r), _ptr(z)))
+        return z
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ocp_hierarchy_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def amg_setup(ctx: Context, system: System, precision: int = PREC_FP64, **kw) -> Hierarchy:
+    p = default_params()
+    p.precision = int(precision)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    h = C.c_void_p()
+    ctx.check(lib().amg_setup(ctx.handle, system.handle, C.byref(p), C.byref(h)))
+    return Hierarchy(ctx, h, system, p)
+
+
+# ------------------------------------------------------------------ solve
+def pcg_solve(ctx: Context, system: System, hierarchy: Optional[Hierarchy] = None, f=None, u=None,
+              rtol: float = 1e-8, maxit: int = 500, stop: int = STOP_L2, raise_on_maxit: bool = False):
+    """Returns (u on all vertices, SolveInfo, status)."""
+    torch = _torch()
+    nv = system.view().n_vertices
+    if u is None:
+        u = torch.empty(nv, dtype=torch.float64, device="cuda")
+    info = SolveInfo()
+    rc = lib().pcg_solve(ctx.handle, system.handle, hierarchy.handle if hierarchy is not None else None,
+                         _ptr(f), _ptr(u), float(rtol), int(maxit), int(stop), C.byref(info))
+    ok = (OK,) if raise_on_maxit else (OK, MAXIT)
+    ctx.check(rc, ok=ok)
+    return u, info, rc

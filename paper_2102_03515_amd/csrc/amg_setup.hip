@@ -1,0 +1,714 @@
+// Smoothed-aggregation AMG setup on the GPU.
+//
+// Section 4.1 builds the coarse space from a greedy colouring of the matrix
+// graph (pick an unmarked dof as coarse, mark its neighbours fine, repeat),
+// interpolates by averaging, and forms Galerkin coarse operators
+// A_c = P^T A P recursively.  Here the same three ingredients are realised as
+// smoothed aggregation:
+//
+//   strength   j ~ i  if  |a_ij| >= theta * sqrt(a_ii a_jj)
+//   coarsening roots = a maximal distance-2 independent set of the strength
+//              graph, chosen greedily in the order of a fixed hash priority
+//              (the parallel rounds below select exactly the set the
+//              sequential greedy pass in that order selects); every node
+//              joins the aggregate of an adjacent root, else of an adjacent
+//              node that did
+//   P_tent     one entry per row, 1/sqrt(|aggregate|) (constant near-kernel)
+//   P          (I - omega/lambda D^-1 A) P_tent, lambda = Gershgorin bound of
+//              D^-1 A (max_i sum_j |a_ij| / a_ii)
+//   R = P^T,   A_c = R (A P)
+//
+// Every step is deterministic: integer atomics only count, lists filled in
+// arbitrary order are sorted, and the sparse products accumulate each output
+// entry in a fixed order.  The last level (n <= coarse_max) is inverted
+// densely with Gauss-Jordan elimination in one workgroup.
+#include <algorithm>
+#include <cmath>
+
+#include "kernels.h"
+#include "system.h"
+
+namespace ocp {
+
+constexpr int kDenseMax = 2048;
+
+// ------------------------------------------------------------------ hashing
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// MIS key: class (in=3 > undecided=2 > out=1), 30-bit priority, node id
+__device__ __forceinline__ uint64_t mis_key(int i, int8_t state, uint32_t salt) {
+    const uint64_t cls = state == 1 ? 3u : (state == 0 ? 2u : 1u);
+    const uint64_t pr = mix32((uint32_t)i ^ salt) >> 2;
+    return (cls << 62) | (pr << 32) | (uint32_t)i;
+}
+
+// ------------------------------------------------------------- diagnostics
+// diag[i] = a_ii, dl1[i] = 1 / sum_j |a_ij|, gersh[i] = sum_j |a_ij| / a_ii
+__global__ void k_level_diag(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                             const double *__restrict__ val, double *__restrict__ diag, double *__restrict__ dl1,
+                             double *__restrict__ gersh, int32_t *flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double d = 0.0, s = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const double v = val[k];
+        s += fabs(v);
+        if (col[k] == i) d = v;
+    }
+    if (!(d > 0.0) || !isfinite(s)) {
+        atomicOr(flag, 8);
+        d = 1.0;
+        s = 1.0;
+    }
+    diag[i] = d;
+    dl1[i] = 1.0 / s;
+    gersh[i] = s / d;
+}
+
+__global__ void k_strength(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                           const double *__restrict__ val, const double *__restrict__ diag, double theta,
+                           uint8_t *__restrict__ strong) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double di = diag[i];
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = col[k];
+        const double a = fabs(val[k]);
+        strong[k] = (j != i && a > 0.0 && a >= theta * sqrt(di * diag[j])) ? 1 : 0;
+    }
+}
+
+// ------------------------------------------------------------------- MIS-2
+__global__ void k_mis_m1(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                         const uint8_t *__restrict__ strong, const int8_t *__restrict__ state, uint32_t salt,
+                         uint64_t *__restrict__ m1) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t m = mis_key(i, state[i], salt);
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+        if (strong[k]) {
+            const int j = col[k];
+            const uint64_t kj = mis_key(j, state[j], salt);
+            m = kj > m ? kj : m;
+        }
+    m1[i] = m;
+}
+
+__global__ void k_mis_m2(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                         const uint8_t *__restrict__ strong, int8_t *__restrict__ state, uint32_t salt,
+                         const uint64_t *__restrict__ m1, int32_t *undecided) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (state[i] != 0) return;
+    uint64_t m = m1[i];
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+        if (strong[k]) {
+            const uint64_t v = m1[col[k]];
+            m = v > m ? v : m;
+        }
+    if (m == mis_key(i, 0, salt))
+        state[i] = 1;
+    else if ((m >> 62) == 3u)
+        state[i] = 2;
+    else
+        atomicAdd(undecided, 1);
+}
+
+__global__ void k_root_flags(int32_t n, const int8_t *__restrict__ state, int32_t *__restrict__ fl) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) fl[i] = state[i] == 1 ? 1 : 0;
+}
+
+// roots and their strong neighbours
+__global__ void k_agg1(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                       const uint8_t *__restrict__ strong, const int8_t *__restrict__ state,
+                       const int32_t *__restrict__ root_pos, uint32_t salt, int32_t *__restrict__ agg,
+                       int8_t *__restrict__ assigned) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (state[i] == 1) {
+        agg[i] = root_pos[i];
+        assigned[i] = 1;
+        return;
+    }
+    uint64_t best = 0;
+    int bj = -1;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+        if (strong[k]) {
+            const int j = col[k];
+            if (state[j] == 1) {
+                const uint64_t kj = mis_key(j, 1, salt);
+                if (kj > best) {
+                    best = kj;
+                    bj = j;
+                }
+            }
+        }
+    agg[i] = bj >= 0 ? root_pos[bj] : -1;
+    assigned[i] = bj >= 0 ? 2 : 0;
+}
+
+// nodes two steps from a root join a neighbour's aggregate
+__global__ void k_agg2(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                       const uint8_t *__restrict__ strong, int8_t *__restrict__ assigned, uint32_t salt,
+                       int32_t *__restrict__ agg, int32_t *flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (assigned[i] != 0) return;
+    uint64_t best = 0;
+    int bj = -1;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+        if (strong[k]) {
+            const int j = col[k];
+            if (assigned[j] == 2) {
+                const uint64_t kj = mis_key(j, 2, salt);
+                if (kj > best) {
+                    best = kj;
+                    bj = j;
+                }
+            }
+        }
+    if (bj < 0) {
+        atomicOr(flag, 16);
+        return;
+    }
+    agg[i] = agg[bj];
+    assigned[i] = 3;
+}
+
+__global__ void k_agg_sizes(int32_t n, const int32_t *__restrict__ agg, int32_t *__restrict__ size) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&size[agg[i]], 1);
+}
+
+__global__ void k_ptent(int32_t n, const int32_t *__restrict__ agg, const int32_t *__restrict__ size,
+                        int32_t *__restrict__ rp, int32_t *__restrict__ col, double *__restrict__ val) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    rp[i] = i;
+    if (i == n) return;
+    col[i] = agg[i];
+    val[i] = 1.0 / sqrt((double)size[agg[i]]);
+}
+
+// P = P_tent - w D^-1 (A P_tent), in place over the entries of A P_tent
+__global__ void k_smooth_p(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                           double *__restrict__ val, const double *__restrict__ diag, const int32_t *__restrict__ agg,
+                           const double *__restrict__ ptent, double w) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double s = w / diag[i];
+    const int a = agg[i];
+    for (int k = rp[i]; k < rp[i + 1]; ++k) val[k] = (col[k] == a ? ptent[i] : 0.0) - s * val[k];
+}
+
+// ------------------------------------------------------------------ SpGEMM
+// C = A B, row by row.  Each row's distinct columns go into an LDS hash
+// table; values are accumulated per slot over the entries of the A row in
+// ascending order (at each step the lanes hold distinct columns of one B row,
+// so no two lanes touch one slot), then the columns are ranked and written in
+// ascending order.
+__global__ void k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp, const int32_t *__restrict__ acol,
+                            const int32_t *__restrict__ brp, int32_t *__restrict__ ub) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int64_t s = 0;
+    for (int k = arp[i]; k < arp[i + 1]; ++k) {
+        const int c = acol[k];
+        s += brp[c + 1] - brp[c];
+    }
+    ub[i] = (int32_t)(s > INT32_MAX ? INT32_MAX : s);
+}
+
+__global__ void k_bin_rows(int32_t m, const int32_t *__restrict__ ub, int32_t lim0, int32_t lim1,
+                           int32_t *__restrict__ counts, int32_t *__restrict__ lists) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int u = ub[i];
+    const int c = u <= lim0 ? 0 : (u <= lim1 ? 1 : 2);
+    const int pos = atomicAdd(&counts[c], 1);
+    lists[(int64_t)c * m + pos] = i;
+}
+
+template <int H>
+__device__ __forceinline__ int hash_slot(int key) {
+    return (int)(((uint32_t)key * 2654435761u) >> (32 - __builtin_ctz(H)));
+}
+
+template <int H>
+__device__ __forceinline__ int hash_insert(int *keys, int key, int *count) {
+    int s = hash_slot<H>(key);
+    for (;;) {
+        const int prev = atomicCAS(&keys[s], -1, key);
+        if (prev == -1) {
+            if (count) atomicAdd(count, 1);
+            return s;
+        }
+        if (prev == key) return s;
+        s = (s + 1) & (H - 1);
+    }
+}
+
+template <int H>
+__global__ void __launch_bounds__(64) k_spgemm_count(const int32_t *__restrict__ rows, int32_t nrows,
+                                                     const int32_t *__restrict__ arp, const int32_t *__restrict__ acol,
+                                                     const int32_t *__restrict__ brp, const int32_t *__restrict__ bcol,
+                                                     int32_t *__restrict__ cnt, int32_t *flag) {
+    __shared__ int keys[H];
+    __shared__ int count;
+    const int lane = threadIdx.x;
+    for (int r = blockIdx.x; r < nrows; r += gridDim.x) {
+        const int i = rows[r];
+        for (int s = lane; s < H; s += 64) keys[s] = -1;
+        if (lane == 0) count = 0;
+        __syncthreads();
+        for (int k = arp[i]; k < arp[i + 1]; ++k) {
+            const int c = acol[k];
+            for (int t = brp[c] + lane; t < brp[c + 1]; t += 64) {
+                if (*(volatile int *)&count > (3 * H) / 4) break;
+                hash_insert<H>(keys, bcol[t], &count);
+            }
+            __syncthreads();
+        }
+        if (lane == 0) {
+            cnt[i] = count;
+            if (count > (3 * H) / 4) atomicOr(flag, 32);
+        }
+        __syncthreads();
+    }
+}
+
+template <int H>
+__global__ void __launch_bounds__(64) k_spgemm_fill(const int32_t *__restrict__ rows, int32_t nrows,
+                                                    const int32_t *__restrict__ arp, const int32_t *__restrict__ acol,
+                                                    const double *__restrict__ aval, const int32_t *__restrict__ brp,
+                                                    const int32_t *__restrict__ bcol, const double *__restrict__ bval,
+                                                    const int32_t *__restrict__ crp, int32_t *__restrict__ ccol,
+                                                    double *__restrict__ cval) {
+    __shared__ int keys[H];
+    __shared__ double vals[H];
+    __shared__ int list[H];
+    __shared__ int count;
+    const int lane = threadIdx.x;
+    for (int r = blockIdx.x; r < nrows; r += gridDim.x) {
+        const int i = rows[r];
+        for (int s = lane; s < H; s += 64) {
+            keys[s] = -1;
+            vals[s] = 0.0;
+        }
+        if (lane == 0) count = 0;
+        __syncthreads();
+        for (int k = arp[i]; k < arp[i + 1]; ++k) {
+            const int c = acol[k];
+            const double a = aval[k];
+            for (int t = brp[c] + lane; t < brp[c + 1]; t += 64) {
+                const int s = hash_insert<H>(keys, bcol[t], nullptr);
+                vals[s] += a * bval[t];
+            }
+            __syncthreads();
+        }
+        // compact occupied slots
+        for (int s = lane; s < H; s += 64)
+            if (keys[s] >= 0) list[atomicAdd(&count, 1)] = s;
+        __syncthreads();
+        const int nc = count;
+        const int base = crp[i];
+        for (int e = lane; e < nc; e += 64) {
+            const int se = list[e];
+            const int ke = keys[se];
+            int rank = 0;
+            for (int f = 0; f < nc; ++f) rank += keys[list[f]] < ke;
+            ccol[base + rank] = ke;
+            cval[base + rank] = vals[se];
+        }
+        __syncthreads();
+    }
+}
+
+struct Csr {
+    int32_t rows = 0, cols = 0;
+    int64_t nnz = 0;
+    DevBuf<int32_t> rp, col;
+    DevBuf<double> val;
+};
+
+static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, const int32_t *acol, const double *aval,
+                   const int32_t *brp, const int32_t *bcol, const double *bval, Csr &C) {
+    hipStream_t s = ctx->stream;
+    DevBuf<int32_t> ub(ctx, (size_t)m + 1);
+    k_spgemm_ub<<<grid_for(m, 256), 256, 0, s>>>(m, arp, acol, brp, ub.get());
+    OCP_LAUNCH_CHECK();
+    DevBuf<int32_t> counts(ctx, 4);
+    fill_zero_bytes(ctx, counts.get(), 16);
+    DevBuf<int32_t> lists(ctx, (size_t)3 * m);
+    constexpr int H0 = 256, H1 = 1024, H2 = 2048;
+    k_bin_rows<<<grid_for(m, 256), 256, 0, s>>>(m, ub.get(), H0 / 2, H1 / 2, counts.get(), lists.get());
+    OCP_LAUNCH_CHECK();
+    int32_t hc[4];
+    read_back(ctx, hc, counts.get(), 16);
+    DevBuf<int32_t> cnt(ctx, (size_t)m + 1);
+    fill_zero_bytes(ctx, ctx->dev_flag, 4);
+    const unsigned gmax = 65536;
+    auto g = [&](int32_t nr) { return (unsigned)std::min<int64_t>(std::max<int32_t>(nr, 1), gmax); };
+    if (hc[0]) k_spgemm_count<H0><<<g(hc[0]), 64, 0, s>>>(lists.get(), hc[0], arp, acol, brp, bcol, cnt.get(), ctx->dev_flag);
+    if (hc[1]) k_spgemm_count<H1><<<g(hc[1]), 64, 0, s>>>(lists.get() + m, hc[1], arp, acol, brp, bcol, cnt.get(), ctx->dev_flag);
+    if (hc[2]) k_spgemm_count<H2><<<g(hc[2]), 64, 0, s>>>(lists.get() + 2 * (int64_t)m, hc[2], arp, acol, brp, bcol, cnt.get(), ctx->dev_flag);
+    OCP_LAUNCH_CHECK();
+    int32_t fl = 0;
+    read_back(ctx, &fl, ctx->dev_flag, 4);
+    if (fl & 32) fail(OCP_ERR_UNSUPPORTED, "sparse product row with more than 1536 entries");
+    C.rows = m;
+    C.cols = ncols;
+    C.rp.reset(ctx, (size_t)m + 1);
+    C.nnz = scan_exclusive(ctx, cnt.get(), C.rp.get(), m);
+    C.col.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
+    C.val.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
+    if (hc[0]) k_spgemm_fill<H0><<<g(hc[0]), 64, 0, s>>>(lists.get(), hc[0], arp, acol, aval, brp, bcol, bval, C.rp.get(), C.col.get(), C.val.get());
+    if (hc[1]) k_spgemm_fill<H1><<<g(hc[1]), 64, 0, s>>>(lists.get() + m, hc[1], arp, acol, aval, brp, bcol, bval, C.rp.get(), C.col.get(), C.val.get());
+    if (hc[2]) k_spgemm_fill<H2><<<g(hc[2]), 64, 0, s>>>(lists.get() + 2 * (int64_t)m, hc[2], arp, acol, aval, brp, bcol, bval, C.rp.get(), C.col.get(), C.val.get());
+    OCP_LAUNCH_CHECK();
+}
+
+// --------------------------------------------------------------- transpose
+__global__ void k_count_cols(int64_t nnz, const int32_t *__restrict__ col, int32_t *__restrict__ cnt) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz) atomicAdd(&cnt[col[k]], 1);
+}
+
+__global__ void k_fill_t(int32_t m, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                         const double *__restrict__ val, const int32_t *__restrict__ trp, int32_t *__restrict__ fill,
+                         int32_t *__restrict__ tcol, double *__restrict__ tval) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = col[k];
+        const int pos = trp[j] + atomicAdd(&fill[j], 1);
+        tcol[pos] = i;
+        tval[pos] = val[k];
+    }
+}
+
+constexpr int kSortCap = 2048;
+
+// Sort each row by column (keys unique within a row): rank sort in LDS.
+__global__ void __launch_bounds__(256) k_sort_rows(int32_t m, const int32_t *__restrict__ rp, int32_t *__restrict__ col,
+                                                   double *__restrict__ val, int32_t *flag) {
+    __shared__ int keys[kSortCap];
+    __shared__ double vals[kSortCap];
+    for (int i = blockIdx.x; i < m; i += gridDim.x) {
+        const int b = rp[i], len = rp[i + 1] - b;
+        if (len > kSortCap) {
+            if (threadIdx.x == 0) atomicOr(flag, 64);
+            continue;
+        }
+        for (int e = threadIdx.x; e < len; e += blockDim.x) {
+            keys[e] = col[b + e];
+            vals[e] = val[b + e];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < len; e += blockDim.x) {
+            const int ke = keys[e];
+            int rank = 0;
+            for (int f = 0; f < len; ++f) rank += keys[f] < ke;
+            col[b + rank] = ke;
+            val[b + rank] = vals[e];
+        }
+        __syncthreads();
+    }
+}
+
+static void transpose(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t nnz, const int32_t *rp, const int32_t *col,
+                      const double *val, Csr &T) {
+    hipStream_t s = ctx->stream;
+    DevBuf<int32_t> cnt(ctx, (size_t)ncols + 1);
+    fill_zero_bytes(ctx, cnt.get(), sizeof(int32_t) * ((size_t)ncols + 1));
+    k_count_cols<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, col, cnt.get());
+    OCP_LAUNCH_CHECK();
+    T.rows = ncols;
+    T.cols = m;
+    T.rp.reset(ctx, (size_t)ncols + 1);
+    T.nnz = scan_exclusive(ctx, cnt.get(), T.rp.get(), ncols);
+    T.col.reset(ctx, (size_t)std::max<int64_t>(T.nnz, 1));
+    T.val.reset(ctx, (size_t)std::max<int64_t>(T.nnz, 1));
+    fill_zero_bytes(ctx, cnt.get(), sizeof(int32_t) * ((size_t)ncols + 1));
+    k_fill_t<<<grid_for(m, 256), 256, 0, s>>>(m, rp, col, val, T.rp.get(), cnt.get(), T.col.get(), T.val.get());
+    OCP_LAUNCH_CHECK();
+    fill_zero_bytes(ctx, ctx->dev_flag, 4);
+    k_sort_rows<<<(unsigned)std::min<int64_t>(std::max<int32_t>(ncols, 1), 65536), 256, 0, s>>>(
+        ncols, T.rp.get(), T.col.get(), T.val.get(), ctx->dev_flag);
+    OCP_LAUNCH_CHECK();
+    int32_t fl = 0;
+    read_back(ctx, &fl, ctx->dev_flag, 4);
+    if (fl & 64) fail(OCP_ERR_UNSUPPORTED, "transpose row with more than 2048 entries");
+}
+
+// ------------------------------------------------------------ dense inverse
+__global__ void k_csr_to_dense(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                               const double *__restrict__ val, double *__restrict__ D) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) D[(int64_t)i * n + col[k]] = val[k];
+}
+
+// In-place Gauss-Jordan inversion of an SPD matrix (no pivoting needed), one
+// workgroup.  Step k: save column k and the scaled row k, then update all
+// other entries.
+__global__ void __launch_bounds__(1024) k_gauss_jordan(int32_t n, double *__restrict__ D) {
+    __shared__ double colk[kDenseMax];
+    __shared__ double rowk[kDenseMax];
+    for (int k = 0; k < n; ++k) {
+        const double p = 1.0 / D[(int64_t)k * n + k];
+        for (int t = threadIdx.x; t < n; t += blockDim.x) {
+            colk[t] = D[(int64_t)t * n + k];
+            rowk[t] = D[(int64_t)k * n + t] * p;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const int i = e / n, j = e - i * n;
+            double v;
+            if (i == k)
+                v = (j == k) ? p : rowk[j];
+            else
+                v = (j == k) ? -colk[i] * p : D[e] - colk[i] * rowk[j];
+            D[e] = v;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_to_float(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+static void to_float(ocp_ctx *ctx, const double *a, DevBuf<float> &b, int64_t n) {
+    b.reset(ctx, (size_t)std::max<int64_t>(n, 1));
+    if (n > 0) {
+        k_to_float<<<grid_for(n, 256), 256, 0, ctx->stream>>>(n, a, b.get());
+        OCP_LAUNCH_CHECK();
+    }
+}
+
+// ------------------------------------------------------------------- setup
+static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
+    hipStream_t s = ctx->stream;
+    const ocp_amg_params &pr = h->params;
+    auto l0 = std::make_unique<Level>();
+    l0->n = sys->n;
+    l0->nnzA = sys->nnz;
+    l0->A_rp = sys->row_ptr.get();
+    l0->A_col = sys->col.get();
+    l0->A_val = sys->val.get();
+    h->levels.push_back(std::move(l0));
+
+    for (int lev = 0;; ++lev) {
+        Level &L = *h->levels.back();
+        const int32_t n = L.n;
+        L.gA = level_lanes(L.nnzA, n);
+        DevBuf<double> diag(ctx, n), gersh(ctx, n);
+        L.dinv.reset(ctx, n);
+        fill_zero_bytes(ctx, ctx->dev_flag, 4);
+        k_level_diag<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, L.A_val, diag.get(), L.dinv.get(),
+                                                      gersh.get(), ctx->dev_flag);
+        OCP_LAUNCH_CHECK();
+        int32_t fl = 0;
+        read_back(ctx, &fl, ctx->dev_flag, 4);
+        if (fl & 8) fail(OCP_ERR_INVALID_ARG, "matrix has a non-positive diagonal entry");
+        L.lambda_max = reduce_max_abs(ctx, gersh.get(), n);
+
+        const bool last = (n <= pr.coarse_max) || (lev + 1 >= pr.max_levels);
+        int32_t nc = 0;
+        DevBuf<uint8_t> strong;
+        if (!last) {
+            // strength and distance-2 maximal independent set
+            strong.reset(ctx, (size_t)L.nnzA);
+            k_strength<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, L.A_val, diag.get(), pr.theta, strong.get());
+            OCP_LAUNCH_CHECK();
+            DevBuf<int8_t> state(ctx, n);
+            fill_zero_bytes(ctx, state.get(), (size_t)n);
+            DevBuf<uint64_t> m1(ctx, n);
+            const uint32_t salt = 0x9E3779B9u * (uint32_t)(lev + 1);
+            for (int round = 0;; ++round) {
+                if (round > 1000) fail(OCP_ERR_HIP, "independent-set rounds did not terminate");
+                fill_zero_bytes(ctx, ctx->dev_flag, 4);
+                k_mis_m1<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get());
+                k_mis_m2<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get(),
+                                                          ctx->dev_flag);
+                OCP_LAUNCH_CHECK();
+                int32_t und = 0;
+                read_back(ctx, &und, ctx->dev_flag, 4);
+                if (und == 0) break;
+            }
+            // aggregates
+            DevBuf<int32_t> rflag(ctx, (size_t)n + 1), rpos(ctx, (size_t)n + 1);
+            k_root_flags<<<grid_for(n, 256), 256, 0, s>>>(n, state.get(), rflag.get());
+            OCP_LAUNCH_CHECK();
+            nc = (int32_t)scan_exclusive(ctx, rflag.get(), rpos.get(), n);
+            L.agg.reset(ctx, n);
+            DevBuf<int8_t> assigned(ctx, n);
+            k_agg1<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), rpos.get(), salt,
+                                                    L.agg.get(), assigned.get());
+            fill_zero_bytes(ctx, ctx->dev_flag, 4);
+            k_agg2<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), assigned.get(), salt, L.agg.get(),
+                                                    ctx->dev_flag);
+            OCP_LAUNCH_CHECK();
+            read_back(ctx, &fl, ctx->dev_flag, 4);
+            if (fl & 16) fail(OCP_ERR_HIP, "aggregation left a node unassigned");
+        }
+        if (last || nc <= 0 || nc >= n) {
+            // last level: dense inverse (or Jacobi when too large)
+            L.agg.release();
+            if (n <= kDenseMax) {
+                L.dense_inv.reset(ctx, (size_t)n * n);
+                fill_zero_bytes(ctx, L.dense_inv.get(), sizeof(double) * (size_t)n * n);
+                k_csr_to_dense<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, L.A_val, L.dense_inv.get());
+                k_gauss_jordan<<<1, 1024, 0, s>>>(n, L.dense_inv.get());
+                OCP_LAUNCH_CHECK();
+            }
+            break;
+        }
+
+        // tentative prolongator
+        DevBuf<int32_t> size(ctx, nc);
+        fill_zero_bytes(ctx, size.get(), sizeof(int32_t) * (size_t)nc);
+        k_agg_sizes<<<grid_for(n, 256), 256, 0, s>>>(n, L.agg.get(), size.get());
+        DevBuf<int32_t> trp(ctx, (size_t)n + 1), tcol(ctx, n);
+        DevBuf<double> tval(ctx, n);
+        k_ptent<<<grid_for(n + 1, 256), 256, 0, s>>>(n, L.agg.get(), size.get(), trp.get(), tcol.get(), tval.get());
+        OCP_LAUNCH_CHECK();
+        // smoothed prolongator P = (I - w D^-1 A) P_tent
+        Csr P;
+        spgemm(ctx, n, nc, L.A_rp, L.A_col, L.A_val, trp.get(), tcol.get(), tval.get(), P);
+        const double w = pr.omega / L.lambda_max;
+        k_smooth_p<<<grid_for(n, 256), 256, 0, s>>>(n, P.rp.get(), P.col.get(), P.val.get(), diag.get(), L.agg.get(),
+                                                    tval.get(), w);
+        OCP_LAUNCH_CHECK();
+        // restriction and Galerkin product
+        Csr R;
+        transpose(ctx, n, nc, P.nnz, P.rp.get(), P.col.get(), P.val.get(), R);
+        Csr AP, Ac;
+        spgemm(ctx, n, nc, L.A_rp, L.A_col, L.A_val, P.rp.get(), P.col.get(), P.val.get(), AP);
+        spgemm(ctx, nc, nc, R.rp.get(), R.col.get(), R.val.get(), AP.rp.get(), AP.col.get(), AP.val.get(), Ac);
+        sync(ctx);
+
+        L.nc = nc;
+        L.nnzP = P.nnz;
+        L.P_rp = std::move(P.rp);
+        L.P_col = std::move(P.col);
+        L.P_val = std::move(P.val);
+        L.R_rp = std::move(R.rp);
+        L.R_col = std::move(R.col);
+        L.R_val = std::move(R.val);
+        L.gP = level_lanes(L.nnzP, n);
+        L.gR = level_lanes(L.nnzP, nc);
+
+        auto nxt = std::make_unique<Level>();
+        nxt->n = nc;
+        nxt->nnzA = Ac.nnz;
+        nxt->own_rp = std::move(Ac.rp);
+        nxt->own_col = std::move(Ac.col);
+        nxt->own_val = std::move(Ac.val);
+        nxt->A_rp = nxt->own_rp.get();
+        nxt->A_col = nxt->own_col.get();
+        nxt->A_val = nxt->own_val.get();
+        h->levels.push_back(std::move(nxt));
+    }
+
+    // precision copies and work vectors
+    const bool mixed = pr.precision == OCP_PREC_MIXED;
+    const size_t es = mixed ? sizeof(float) : sizeof(double);
+    for (size_t l = 0; l < h->levels.size(); ++l) {
+        Level &L = *h->levels[l];
+        if (mixed) {
+            to_float(ctx, L.A_val, L.A_val32, L.nnzA);
+            to_float(ctx, L.dinv.get(), L.dinv32, L.n);
+            if (L.P_val.get()) to_float(ctx, L.P_val.get(), L.P_val32, L.nnzP);
+            if (L.R_val.get()) to_float(ctx, L.R_val.get(), L.R_val32, L.nnzP);
+            if (L.dense_inv.get()) to_float(ctx, L.dense_inv.get(), L.dense_inv32, (int64_t)L.n * L.n);
+        }
+        L.vr.reset(ctx, es * L.n);
+        L.vxp.reset(ctx, es * L.n);
+        if (l > 0) {
+            L.vb.reset(ctx, es * L.n);
+            L.vx.reset(ctx, es * L.n);
+        }
+    }
+    sync(ctx);
+}
+
+}  // namespace ocp
+
+using namespace ocp;
+
+extern "C" void amg_default_params(ocp_amg_params *p) {
+    if (!p) return;
+    p->precision = OCP_PREC_FP64;
+    p->smoother = OCP_SMOOTH_L1JACOBI;
+    p->degree = 2;
+    p->coarse_max = 512;
+    p->max_levels = 10;
+    p->theta = 0.08;
+    p->omega = 4.0 / 3.0;
+}
+
+extern "C" int amg_setup(ocp_ctx *ctx, const ocp_system *sys, const ocp_amg_params *params, ocp_hierarchy **out) {
+    if (!ctx) return OCP_ERR_INVALID_ARG;
+    if (out) *out = nullptr;
+    ocp_hierarchy *h = nullptr;
+    int rc = run_guarded(ctx, [&] {
+        if (!sys || !out) fail(OCP_ERR_INVALID_ARG, "system and out must not be NULL");
+        h = new ocp_hierarchy();
+        h->ctx = ctx;
+        h->sys = sys;
+        if (params)
+            h->params = *params;
+        else
+            amg_default_params(&h->params);
+        const ocp_amg_params &p = h->params;
+        if (p.precision != OCP_PREC_FP64 && p.precision != OCP_PREC_MIXED) fail(OCP_ERR_INVALID_ARG, "bad precision");
+        if (p.smoother != OCP_SMOOTH_L1JACOBI) fail(OCP_ERR_UNSUPPORTED, "only the L1-Jacobi smoother is available");
+        if (p.coarse_max < 1 || p.coarse_max > kDenseMax) fail(OCP_ERR_INVALID_ARG, "coarse_max must be in 1..2048");
+        if (p.max_levels < 1 || p.max_levels > 16) fail(OCP_ERR_INVALID_ARG, "max_levels must be in 1..16");
+        if (!(p.theta >= 0.0) || !(p.omega > 0.0)) fail(OCP_ERR_INVALID_ARG, "theta >= 0 and omega > 0 required");
+        setup(ctx, sys, h);
+    });
+    if (rc != OCP_OK) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return OCP_OK;
+}
+
+extern "C" void ocp_hierarchy_destroy(ocp_hierarchy *h) { delete h; }
+
+extern "C" int ocp_hierarchy_get_level(const ocp_hierarchy *h, int32_t level, ocp_level_view *v) {
+    if (!h || !v || level < 0 || level >= (int32_t)h->levels.size()) return OCP_ERR_INVALID_ARG;
+    const Level &L = *h->levels[level];
+    v->n_levels = (int32_t)h->levels.size();
+    v->level = level;
+    v->n = L.n;
+    v->n_coarse = L.nc;
+    v->nnz_A = L.nnzA;
+    v->nnz_P = L.nnzP;
+    v->A_row_ptr = L.A_rp;
+    v->A_col = L.A_col;
+    v->A_val = L.A_val;
+    v->P_row_ptr = L.P_rp.get();
+    v->P_col = L.P_col.get();
+    v->P_val = L.P_val.get();
+    v->R_row_ptr = L.R_rp.get();
+    v->R_col = L.R_col.get();
+    v->R_val = L.R_val.get();
+    v->agg = L.agg.get();
+    v->dense_inv = L.dense_inv.get();
+    v->lambda_max = L.lambda_max;
+    return OCP_OK;
+}

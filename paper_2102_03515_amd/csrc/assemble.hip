@@ -1,0 +1,645 @@
+// Finite element assembly of A = rho*K + M and f = (int ubar phi_i) into CSR
+// (Section 3, system (linsys) and the entries K_ij, M_ij, f_i defined there).
+//
+// Row-owned, atomic-free on values: every interior vertex owns its row and
+// visits its incident tetrahedra in increasing tet id, recomputing the needed
+// element entries on the fly.  The result is bitwise deterministic.
+//
+//   1. per tet: index/degeneracy checks, incidence counts   (int atomics)
+//   2. scan -> incidence pointers; fill; sort each list      (vertex -> tets)
+//   3. dof numbering of interior vertices (scan)
+//   4. symbolic rows: sorted union of the interior vertices of incident tets
+//   5. per tet: load contributions fe[4] by the 4-point degree-2 rule
+//   6. numeric rows: sum rho*K_e + M_e (and fe) over incident tets
+#include <cfloat>
+#include <climits>
+#include <cmath>
+
+#include "common.h"
+#include "system.h"
+
+namespace ocp {
+
+constexpr int kAsmBlock = 64;
+constexpr int kRowCap = 128;       // max entries of one assembled row
+constexpr int kSineTable = 16;     // sin(k pi x) by recurrence for k <= 16
+
+// ----------------------------------------------------------------- geometry
+// Barycentric gradients g[a] and signed determinant of the edge matrix of a
+// tetrahedron p[0..3].  lambda_{c+1}(x) = (B^{-1}(x - p0))_c with
+// B = [p1-p0, p2-p0, p3-p0], so grad lambda_{c+1} is row c of B^{-1} and
+// grad lambda_0 = -(sum of the others).
+__device__ __forceinline__ double tet_gradients(const double p[4][3], double g[4][3]) {
+    double e[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) e[r][c] = p[c + 1][r] - p[0][r];
+    // cofactors
+    const double c00 = e[1][1] * e[2][2] - e[1][2] * e[2][1];
+    const double c01 = e[1][2] * e[2][0] - e[1][0] * e[2][2];
+    const double c02 = e[1][0] * e[2][1] - e[1][1] * e[2][0];
+    const double det = e[0][0] * c00 + e[0][1] * c01 + e[0][2] * c02;
+    const double id = 1.0 / det;
+    // rows of B^{-1} = adj(B)/det, adj = cofactor^T
+    g[1][0] = c00 * id;
+    g[1][1] = (e[0][2] * e[2][1] - e[0][1] * e[2][2]) * id;
+    g[1][2] = (e[0][1] * e[1][2] - e[0][2] * e[1][1]) * id;
+    g[2][0] = c01 * id;
+    g[2][1] = (e[0][0] * e[2][2] - e[0][2] * e[2][0]) * id;
+    g[2][2] = (e[0][2] * e[1][0] - e[0][0] * e[1][2]) * id;
+    g[3][0] = c02 * id;
+    g[3][1] = (e[0][1] * e[2][0] - e[0][0] * e[2][1]) * id;
+    g[3][2] = (e[0][0] * e[1][1] - e[0][1] * e[1][0]) * id;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+    return det;
+}
+
+__device__ __forceinline__ void load_tet(const double *__restrict__ xyz, const int4 tv,
+                                         double p[4][3]) {
+    const int v[4] = {tv.x, tv.y, tv.z, tv.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) p[a][d] = xyz[3 * (int64_t)v[a] + d];
+}
+
+// ------------------------------------------------------- 1. check + count
+__global__ void k_tet_check_count(const int4 *__restrict__ tets, int64_t nt,
+                                  const double *__restrict__ xyz, int32_t nv,
+                                  int32_t *__restrict__ inc_cnt, int32_t *__restrict__ flag) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nt) return;
+    const int4 tv = tets[e];
+    const int v[4] = {tv.x, tv.y, tv.z, tv.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+        if (v[a] < 0 || v[a] >= nv) {
+            atomicOr(flag, 1);
+            return;
+        }
+    double p[4][3], g[4][3];
+    load_tet(xyz, tv, p);
+    double l2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a + 1; b < 4; ++b) {
+            double s = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) s += (p[a][d] - p[b][d]) * (p[a][d] - p[b][d]);
+            l2 = fmax(l2, s);
+        }
+    double e3[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) e3[r][c] = p[c + 1][r] - p[0][r];
+    const double det = e3[0][0] * (e3[1][1] * e3[2][2] - e3[1][2] * e3[2][1]) -
+                       e3[0][1] * (e3[1][0] * e3[2][2] - e3[1][2] * e3[2][0]) +
+                       e3[0][2] * (e3[1][0] * e3[2][1] - e3[1][1] * e3[2][0]);
+    (void)g;
+    if (!(fabs(det) > 1e-12 * l2 * sqrt(l2))) {
+        atomicOr(flag, 2);
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) atomicAdd(&inc_cnt[v[a]], 1);
+}
+
+// ------------------------------------------------------ 2. incidence lists
+__global__ void k_tet_fill(const int4 *__restrict__ tets, int64_t nt, const int32_t *__restrict__ inc_ptr,
+                           int32_t *__restrict__ fill, int32_t *__restrict__ inc) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nt) return;
+    const int4 tv = tets[e];
+    const int v[4] = {tv.x, tv.y, tv.z, tv.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        int pos = atomicAdd(&fill[v[a]], 1);
+        inc[inc_ptr[v[a]] + pos] = (int32_t)e;
+    }
+}
+
+// Sort each vertex's list of incident tets ascending: a 32-wide sorting
+// network in registers for the common case, insertion sort otherwise.
+__global__ void k_inc_sort(const int32_t *__restrict__ inc_ptr, int32_t *__restrict__ inc, int32_t nv) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const int b = inc_ptr[v], len = inc_ptr[v + 1] - b;
+    if (len <= 1) return;
+    if (len <= 32) {
+        int r[32];
+#pragma unroll
+        for (int i = 0; i < 32; ++i) r[i] = i < len ? inc[b + i] : INT_MAX;
+        // bitonic sorting network on 32 keys
+#pragma unroll
+        for (int k = 2; k <= 32; k <<= 1)
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+                for (int i = 0; i < 32; ++i) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const bool up = (i & k) == 0;
+                        const int x = r[i], y = r[l];
+                        const bool sw = up ? (x > y) : (x < y);
+                        r[i] = sw ? y : x;
+                        r[l] = sw ? x : y;
+                    }
+                }
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+            if (i < len) inc[b + i] = r[i];
+    } else {
+        for (int i = 1; i < len; ++i) {
+            const int x = inc[b + i];
+            int j = i - 1;
+            while (j >= 0 && inc[b + j] > x) {
+                inc[b + j + 1] = inc[b + j];
+                --j;
+            }
+            inc[b + j + 1] = x;
+        }
+    }
+}
+
+// ----------------------------------------------------------- 3. dof maps
+__global__ void k_interior_flags(const uint8_t *__restrict__ dirichlet, int32_t nv, int32_t *__restrict__ fl) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < nv) fl[v] = dirichlet[v] ? 0 : 1;
+}
+
+__global__ void k_dof_maps(const uint8_t *__restrict__ dirichlet, const int32_t *__restrict__ pos, int32_t nv,
+                           int32_t *__restrict__ dof_of_vertex, int32_t *__restrict__ vertex_of_dof) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    if (dirichlet[v]) {
+        dof_of_vertex[v] = -1;
+    } else {
+        dof_of_vertex[v] = pos[v];
+        vertex_of_dof[pos[v]] = v;
+    }
+}
+
+// ---------------------------------------------------- 4. symbolic rows
+// pass 0: row_cnt[i] = number of distinct interior neighbours (incl. i)
+// pass 1: write them, sorted, to col[row_ptr[i] ..]
+__global__ void __launch_bounds__(kAsmBlock) k_row_symbolic(
+    int pass, int32_t n, const int32_t *__restrict__ vertex_of_dof, const int32_t *__restrict__ dof_of_vertex,
+    const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc, const int4 *__restrict__ tets,
+    int32_t *__restrict__ row_cnt, const int32_t *__restrict__ row_ptr, int32_t *__restrict__ col,
+    int32_t *__restrict__ flag) {
+    __shared__ int32_t lst[kRowCap][kAsmBlock];
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * kAsmBlock + t;
+    if (i >= n) return;
+    const int vi = vertex_of_dof[i];
+    int cnt = 0;
+    for (int q = inc_ptr[vi]; q < inc_ptr[vi + 1]; ++q) {
+        const int4 tv = tets[inc[q]];
+        const int vv[4] = {tv.x, tv.y, tv.z, tv.w};
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int d = dof_of_vertex[vv[a]];
+            if (d < 0) continue;
+            // insert d into the sorted list lst[0..cnt)
+            int s = cnt - 1;
+            while (s >= 0 && lst[s][t] > d) --s;
+            if (s >= 0 && lst[s][t] == d) continue;
+            if (cnt == kRowCap) {
+                atomicOr(flag, 4);
+                return;
+            }
+            for (int u = cnt - 1; u > s; --u) lst[u + 1][t] = lst[u][t];
+            lst[s + 1][t] = d;
+            ++cnt;
+        }
+    }
+    if (pass == 0) {
+        row_cnt[i] = cnt;
+    } else {
+        const int b = row_ptr[i];
+        for (int s = 0; s < cnt; ++s) col[b + s] = lst[s][t];
+    }
+}
+
+// --------------------------------------------------------- 5. element loads
+struct TargetDev {
+    int32_t kind;
+    int32_t n_modes;
+    int32_t kmax_table;   // largest wave number handled by the recurrence table
+    const int32_t *k;     // device [n_modes][3]
+    const double *amp;    // device [n_modes]
+    double offset;
+    double lo[3], hi[3];
+    const double *nodal;  // device [n_vertices]
+};
+
+// ubar(x) for sine modes.  sin(k pi x_d) for k <= kmax_table comes from the
+// three-term recurrence s_{k+1} = 2 cos(pi x) s_k - s_{k-1}, seeded with
+// sinpi/cospi; larger wave numbers call sinpi directly.
+__device__ double eval_sine(const TargetDev &t, const double x[3], double *tab, int stride) {
+    const int K = t.kmax_table;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double s, c;
+        sincospi(x[d], &s, &c);
+        double sm1 = 0.0, sk = s;
+        for (int k = 1; k <= K; ++k) {
+            tab[(d * kSineTable + (k - 1)) * stride] = sk;
+            const double sn = 2.0 * c * sk - sm1;
+            sm1 = sk;
+            sk = sn;
+        }
+    }
+    double u = t.offset;
+    for (int m = 0; m < t.n_modes; ++m) {
+        double prod = t.amp[m];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int k = t.k[3 * m + d];
+            prod *= (k <= K) ? tab[(d * kSineTable + (k - 1)) * stride] : sinpi((double)k * x[d]);
+        }
+        u += prod;
+    }
+    return u;
+}
+
+__global__ void __launch_bounds__(kAsmBlock) k_tet_load(const int4 *__restrict__ tets, int64_t nt,
+                                                        const double *__restrict__ xyz, TargetDev tg,
+                                                        double4 *__restrict__ fe) {
+    __shared__ double tab[3 * kSineTable * kAsmBlock];
+    const int64_t e = (int64_t)blockIdx.x * kAsmBlock + threadIdx.x;
+    if (e >= nt) return;
+    const int4 tv = tets[e];
+    double p[4][3];
+    load_tet(xyz, tv, p);
+    double e3[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) e3[r][c] = p[c + 1][r] - p[0][r];
+    const double det = e3[0][0] * (e3[1][1] * e3[2][2] - e3[1][2] * e3[2][1]) -
+                       e3[0][1] * (e3[1][0] * e3[2][2] - e3[1][2] * e3[2][0]) +
+                       e3[0][2] * (e3[1][0] * e3[2][1] - e3[1][1] * e3[2][0]);
+    const double w = fabs(det) / 6.0 / 4.0;  // |tau|/4 per quadrature point
+    // barycentric points (a,b,b,b) and permutations
+    const double qa = 0.5854101966249685;   // (5 + 3 sqrt5) / 20
+    const double qb = 0.1381966011250105;   // (5 - sqrt5) / 20
+    const int vv[4] = {tv.x, tv.y, tv.z, tv.w};
+    double f[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double x[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) s += (a == q ? qa : qb) * p[a][d];
+            x[d] = s;
+        }
+        double u;
+        if (tg.kind == OCP_TARGET_SINE_MODES) {
+            u = eval_sine(tg, x, tab + threadIdx.x, kAsmBlock);
+        } else if (tg.kind == OCP_TARGET_BOX) {
+            u = (x[0] > tg.lo[0] && x[0] < tg.hi[0] && x[1] > tg.lo[1] && x[1] < tg.hi[1] &&
+                 x[2] > tg.lo[2] && x[2] < tg.hi[2])
+                    ? 1.0
+                    : 0.0;
+        } else {
+            u = 0.0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) u += (a == q ? qa : qb) * tg.nodal[vv[a]];
+        }
+        const double wu = w * u;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) f[a] += wu * (a == q ? qa : qb);
+    }
+    fe[e] = make_double4(f[0], f[1], f[2], f[3]);
+}
+
+// ---------------------------------------------------------- 6. numeric rows
+__global__ void __launch_bounds__(kAsmBlock) k_row_numeric(
+    int32_t n, double rho, const int32_t *__restrict__ vertex_of_dof, const int32_t *__restrict__ dof_of_vertex,
+    const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc, const int4 *__restrict__ tets,
+    const double *__restrict__ xyz, const double4 *__restrict__ fe, const int32_t *__restrict__ row_ptr,
+    const int32_t *__restrict__ col, double *__restrict__ val, double *__restrict__ valK,
+    double *__restrict__ valM, double *__restrict__ f) {
+    const int i = blockIdx.x * kAsmBlock + threadIdx.x;
+    if (i >= n) return;
+    const int vi = vertex_of_dof[i];
+    const int rb = row_ptr[i], re = row_ptr[i + 1];
+    for (int s = rb; s < re; ++s) {
+        val[s] = 0.0;
+        if (valK) {
+            valK[s] = 0.0;
+            valM[s] = 0.0;
+        }
+    }
+    double fi = 0.0;
+    for (int q = inc_ptr[vi]; q < inc_ptr[vi + 1]; ++q) {
+        const int e = inc[q];
+        const int4 tv = tets[e];
+        const int vv[4] = {tv.x, tv.y, tv.z, tv.w};
+        double p[4][3], g[4][3];
+        load_tet(xyz, tv, p);
+        const double det = tet_gradients(p, g);
+        const double vol = fabs(det) / 6.0;
+        int a = 0;
+#pragma unroll
+        for (int c = 1; c < 4; ++c)
+            if (vv[c] == vi) a = c;
+        const double4 fv = fe[e];
+        fi += (a == 0) ? fv.x : (a == 1) ? fv.y : (a == 2) ? fv.z : fv.w;
+        double ga[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ga[d] = (a == 0) ? g[0][d] : (a == 1) ? g[1][d] : (a == 2) ? g[2][d] : g[3][d];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int j = dof_of_vertex[vv[b]];
+            if (j < 0) continue;
+            const double kab = vol * (ga[0] * g[b][0] + ga[1] * g[b][1] + ga[2] * g[b][2]);
+            const double mab = vol / 20.0 * (b == a ? 2.0 : 1.0);
+            // binary search of column j in the sorted row
+            int lo = rb, hi = re - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (col[mid] < j)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            val[lo] += rho * kab + mab;
+            if (valK) {
+                valK[lo] += kab;
+                valM[lo] += mab;
+            }
+        }
+    }
+    f[i] = fi;
+}
+
+__global__ void k_set_rho(int64_t nnz, double rho, const double *__restrict__ valK,
+                          const double *__restrict__ valM, double *__restrict__ val) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nnz) val[s] = rho * valK[s] + valM[s];
+}
+
+// -------------------------------------------------------------- host side
+static void check_target(const ocp_target *t, int32_t nv) {
+    if (!t) fail(OCP_ERR_INVALID_ARG, "target is NULL");
+    if (t->kind == OCP_TARGET_SINE_MODES) {
+        if (t->n_modes < 1 || t->n_modes > 4096 || !t->k || !t->amp)
+            fail(OCP_ERR_INVALID_ARG, "sine-mode target needs 1..4096 modes with k and amp");
+        for (int m = 0; m < t->n_modes; ++m) {
+            for (int d = 0; d < 3; ++d)
+                if (t->k[3 * m + d] < 1 || t->k[3 * m + d] > 1024)
+                    fail(OCP_ERR_INVALID_ARG, "wave numbers must lie in 1..1024");
+            if (!std::isfinite(t->amp[m])) fail(OCP_ERR_INVALID_ARG, "non-finite amplitude");
+        }
+        if (!std::isfinite(t->offset)) fail(OCP_ERR_INVALID_ARG, "non-finite offset");
+    } else if (t->kind == OCP_TARGET_BOX) {
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(t->lo[d]) || !std::isfinite(t->hi[d]))
+                fail(OCP_ERR_INVALID_ARG, "non-finite box bounds");
+    } else if (t->kind == OCP_TARGET_NODAL) {
+        if (!t->nodal) fail(OCP_ERR_INVALID_ARG, "nodal target needs device values");
+    } else {
+        fail(OCP_ERR_INVALID_ARG, "unknown target kind");
+    }
+    (void)nv;
+}
+
+// Upload the target description; the returned buffers must outlive the launch.
+struct TargetUpload {
+    DevBuf<int32_t> k;
+    DevBuf<double> amp;
+    TargetDev dev{};
+};
+
+static void upload_target(ocp_ctx *ctx, const ocp_target *t, TargetUpload &up) {
+    up.dev.kind = t->kind;
+    up.dev.offset = t->offset;
+    for (int d = 0; d < 3; ++d) {
+        up.dev.lo[d] = t->lo[d];
+        up.dev.hi[d] = t->hi[d];
+    }
+    up.dev.nodal = t->nodal;
+    if (t->kind == OCP_TARGET_SINE_MODES) {
+        const int m = t->n_modes;
+        up.k.reset(ctx, (size_t)m * 3);
+        up.amp.reset(ctx, (size_t)m);
+        OCP_HIP(hipMemcpyAsync(up.k.get(), t->k, sizeof(int32_t) * 3 * m, hipMemcpyHostToDevice, ctx->stream));
+        OCP_HIP(hipMemcpyAsync(up.amp.get(), t->amp, sizeof(double) * m, hipMemcpyHostToDevice, ctx->stream));
+        int kmax = 0;
+        for (int q = 0; q < 3 * m; ++q) kmax = t->k[q] > kmax ? t->k[q] : kmax;
+        up.dev.kmax_table = kmax < kSineTable ? kmax : kSineTable;
+        up.dev.n_modes = m;
+        up.dev.k = up.k.get();
+        up.dev.amp = up.amp.get();
+        sync(ctx);  // the host arrays may be released after the call returns
+    }
+}
+
+static void compute_loads(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *mesh, const ocp_target *t,
+                          double *f_out) {
+    TargetUpload up;
+    upload_target(ctx, t, up);
+    DevBuf<double4> fe(ctx, (size_t)sys->nt);
+    const int4 *tets = reinterpret_cast<const int4 *>(mesh->tets);
+    k_tet_load<<<grid_for(sys->nt, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(tets, sys->nt, mesh->xyz, up.dev,
+                                                                            fe.get());
+    OCP_LAUNCH_CHECK();
+    // row sums of the element loads (reuse the numeric kernel's f output
+    // through a dedicated pass that only accumulates f)
+    extern void row_loads(ocp_ctx *, const ocp_system *, const double4 *, double *);
+    row_loads(ctx, sys, fe.get(), f_out);
+    sync(ctx);
+}
+
+__global__ void __launch_bounds__(kAsmBlock) k_row_loads(int32_t n, const int32_t *__restrict__ vertex_of_dof,
+                                                         const int32_t *__restrict__ inc_ptr,
+                                                         const int32_t *__restrict__ inc,
+                                                         const int4 *__restrict__ tets,
+                                                         const double4 *__restrict__ fe, double *__restrict__ f) {
+    const int i = blockIdx.x * kAsmBlock + threadIdx.x;
+    if (i >= n) return;
+    const int vi = vertex_of_dof[i];
+    double fi = 0.0;
+    for (int q = inc_ptr[vi]; q < inc_ptr[vi + 1]; ++q) {
+        const int e = inc[q];
+        const int4 tv = tets[e];
+        const double4 fv = fe[e];
+        fi += (tv.x == vi) ? fv.x : (tv.y == vi) ? fv.y : (tv.z == vi) ? fv.z : fv.w;
+    }
+    f[i] = fi;
+}
+
+void row_loads(ocp_ctx *ctx, const ocp_system *sys, const double4 *fe, double *f) {
+    k_row_loads<<<grid_for(sys->n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
+        sys->n, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(),
+        reinterpret_cast<const int4 *>(sys->tets_ref), fe, f);
+    OCP_LAUNCH_CHECK();
+}
+
+static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_target *t, int32_t flags,
+                     ocp_system *sys) {
+    const int32_t nv = mesh->n_vertices;
+    const int64_t nt = mesh->n_tets;
+    sys->nv = nv;
+    sys->nt = nt;
+    sys->rho = rho;
+    sys->tets_ref = mesh->tets;
+    const int4 *tets = reinterpret_cast<const int4 *>(mesh->tets);
+    if (reinterpret_cast<uintptr_t>(mesh->tets) % 16 != 0)
+        fail(OCP_ERR_INVALID_ARG, "tets must be 16-byte aligned");
+
+    // 1. checks and incidence counts
+    DevBuf<int32_t> cnt(ctx, (size_t)nv + 1);
+    fill_zero_bytes(ctx, cnt.get(), sizeof(int32_t) * ((size_t)nv + 1));
+    fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
+    k_tet_check_count<<<grid_for(nt, 256), 256, 0, ctx->stream>>>(tets, nt, mesh->xyz, nv, cnt.get(),
+                                                                  ctx->dev_flag);
+    OCP_LAUNCH_CHECK();
+    int32_t fl = 0;
+    read_back(ctx, &fl, ctx->dev_flag, sizeof(fl));
+    if (fl & 1) fail(OCP_ERR_BAD_MESH, "tet vertex index out of range");
+    if (fl & 2) fail(OCP_ERR_BAD_MESH, "degenerate tetrahedron (|det| <= 1e-12 * longest edge^3)");
+
+    // 2. incidence lists
+    sys->inc_ptr.reset(ctx, (size_t)nv + 1);
+    const int64_t ninc = scan_exclusive(ctx, cnt.get(), sys->inc_ptr.get(), nv);
+    sys->inc.reset(ctx, (size_t)ninc);
+    fill_zero_bytes(ctx, cnt.get(), sizeof(int32_t) * (size_t)nv);
+    k_tet_fill<<<grid_for(nt, 256), 256, 0, ctx->stream>>>(tets, nt, sys->inc_ptr.get(), cnt.get(),
+                                                           sys->inc.get());
+    OCP_LAUNCH_CHECK();
+    k_inc_sort<<<grid_for(nv, 64), 64, 0, ctx->stream>>>(sys->inc_ptr.get(), sys->inc.get(), nv);
+    OCP_LAUNCH_CHECK();
+
+    // 3. dof numbering
+    k_interior_flags<<<grid_for(nv, 256), 256, 0, ctx->stream>>>(mesh->dirichlet, nv, cnt.get());
+    OCP_LAUNCH_CHECK();
+    DevBuf<int32_t> pos(ctx, (size_t)nv + 1);
+    const int64_t n = scan_exclusive(ctx, cnt.get(), pos.get(), nv);
+    if (n < 1) fail(OCP_ERR_BAD_MESH, "mesh has no interior vertex");
+    sys->n = (int32_t)n;
+    sys->dof_of_vertex.reset(ctx, (size_t)nv);
+    sys->vertex_of_dof.reset(ctx, (size_t)n);
+    k_dof_maps<<<grid_for(nv, 256), 256, 0, ctx->stream>>>(mesh->dirichlet, pos.get(), nv, sys->dof_of_vertex.get(),
+                                                           sys->vertex_of_dof.get());
+    OCP_LAUNCH_CHECK();
+    pos.release();
+
+    // 4. symbolic rows
+    DevBuf<int32_t> rcnt(ctx, (size_t)n + 1);
+    k_row_symbolic<<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
+        0, sys->n, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
+        rcnt.get(), nullptr, nullptr, ctx->dev_flag);
+    OCP_LAUNCH_CHECK();
+    read_back(ctx, &fl, ctx->dev_flag, sizeof(fl));
+    if (fl & 4) fail(OCP_ERR_UNSUPPORTED, "an assembled row has more than 128 entries");
+    sys->row_ptr.reset(ctx, (size_t)n + 1);
+    sys->nnz = scan_exclusive(ctx, rcnt.get(), sys->row_ptr.get(), n);
+    rcnt.release();
+    sys->col.reset(ctx, (size_t)sys->nnz);
+    k_row_symbolic<<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
+        1, sys->n, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
+        nullptr, sys->row_ptr.get(), sys->col.get(), ctx->dev_flag);
+    OCP_LAUNCH_CHECK();
+
+    // 5. element loads
+    TargetUpload up;
+    upload_target(ctx, t, up);
+    DevBuf<double4> fe(ctx, (size_t)nt);
+    k_tet_load<<<grid_for(nt, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(tets, nt, mesh->xyz, up.dev, fe.get());
+    OCP_LAUNCH_CHECK();
+
+    // 6. numeric rows
+    sys->val.reset(ctx, (size_t)sys->nnz);
+    sys->f.reset(ctx, (size_t)n);
+    if (flags & OCP_KEEP_KM) {
+        sys->valK.reset(ctx, (size_t)sys->nnz);
+        sys->valM.reset(ctx, (size_t)sys->nnz);
+    }
+    k_row_numeric<<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
+        sys->n, rho, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
+        mesh->xyz, fe.get(), sys->row_ptr.get(), sys->col.get(), sys->val.get(), sys->valK.get(), sys->valM.get(),
+        sys->f.get());
+    OCP_LAUNCH_CHECK();
+    sync(ctx);
+}
+
+}  // namespace ocp
+
+using namespace ocp;
+
+extern "C" int fe_assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_target *target,
+                           int32_t flags, ocp_system **out) {
+    if (!ctx) return OCP_ERR_INVALID_ARG;
+    if (out) *out = nullptr;
+    ocp_system *sys = nullptr;
+    int rc = run_guarded(ctx, [&] {
+        if (!mesh || !out) fail(OCP_ERR_INVALID_ARG, "mesh and out must not be NULL");
+        if (mesh->n_vertices <= 0 || mesh->n_tets <= 0 || !mesh->xyz || !mesh->tets || !mesh->dirichlet)
+            fail(OCP_ERR_INVALID_ARG, "mesh needs positive counts and xyz, tets, dirichlet arrays");
+        if ((int64_t)mesh->n_tets * 4 > INT32_MAX) fail(OCP_ERR_UNSUPPORTED, "more than 2^29 tetrahedra");
+        if (!(rho > 0.0) || !std::isfinite(rho)) fail(OCP_ERR_INVALID_ARG, "rho must be positive and finite");
+        check_target(target, mesh->n_vertices);
+        sys = new ocp_system();
+        sys->ctx = ctx;
+        assemble(ctx, mesh, rho, target, flags, sys);
+    });
+    if (rc != OCP_OK) {
+        delete sys;
+        return rc;
+    }
+    *out = sys;
+    return OCP_OK;
+}
+
+extern "C" void ocp_system_destroy(ocp_system *sys) { delete sys; }
+
+extern "C" int fe_set_rho(ocp_ctx *ctx, ocp_system *sys, double rho) {
+    if (!ctx) return OCP_ERR_INVALID_ARG;
+    return run_guarded(ctx, [&] {
+        if (!sys) fail(OCP_ERR_INVALID_ARG, "system is NULL");
+        if (!(rho > 0.0) || !std::isfinite(rho)) fail(OCP_ERR_INVALID_ARG, "rho must be positive and finite");
+        if (!sys->valK.get()) fail(OCP_ERR_INVALID_ARG, "system was assembled without OCP_KEEP_KM");
+        k_set_rho<<<grid_for(sys->nnz, 256), 256, 0, ctx->stream>>>(sys->nnz, rho, sys->valK.get(), sys->valM.get(),
+                                                                    sys->val.get());
+        OCP_LAUNCH_CHECK();
+        sys->rho = rho;
+        sys->invalidate_derived();
+        sync(ctx);
+    });
+}
+
+extern "C" int fe_load(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *mesh, const ocp_target *target,
+                       double *f_dev) {
+    if (!ctx) return OCP_ERR_INVALID_ARG;
+    return run_guarded(ctx, [&] {
+        if (!sys || !mesh || !f_dev) fail(OCP_ERR_INVALID_ARG, "system, mesh and f must not be NULL");
+        if (mesh->n_vertices != sys->nv || mesh->n_tets != sys->nt || mesh->tets != sys->tets_ref)
+            fail(OCP_ERR_INVALID_ARG, "mesh differs from the one the system was assembled on");
+        check_target(target, mesh->n_vertices);
+        compute_loads(ctx, sys, mesh, target, f_dev);
+    });
+}
+
+extern "C" int ocp_system_get_view(const ocp_system *sys, ocp_system_view *v) {
+    if (!sys || !v) return OCP_ERR_INVALID_ARG;
+    v->n_vertices = sys->nv;
+    v->n_dofs = sys->n;
+    v->nnz = sys->nnz;
+    v->rho = sys->rho;
+    v->row_ptr = sys->row_ptr.get();
+    v->col = sys->col.get();
+    v->val = sys->val.get();
+    v->f = sys->f.get();
+    v->dof_of_vertex = sys->dof_of_vertex.get();
+    v->vertex_of_dof = sys->vertex_of_dof.get();
+    return OCP_OK;
+}

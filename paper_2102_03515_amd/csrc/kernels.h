@@ -1,0 +1,141 @@
+// Device building blocks shared by the SpMV, CG and V-cycle kernels.
+//
+// Rows are processed by groups of G consecutive lanes of a 64-wide wavefront
+// (G = 4/8/16/32/64), each lane striding over the row's entries and the group
+// reducing with cross-lane shuffles.  A block of 256 threads handles a tile of
+// consecutive rows; tiles are assigned to blocks so that the 8 XCDs (which
+// receive blocks round-robin) each stream one contiguous slab of rows, which
+// keeps the gathered x-vector entries of a slab in that XCD's L2.
+// Matrix values and column indices are read with non-temporal loads so that
+// the single-use matrix stream does not evict the reused x-vector from cache.
+#pragma once
+
+#include "common.h"
+
+namespace ocp {
+
+constexpr int kBlock = 256;
+constexpr int kMaxPartials = 16384;   // per reduction slot
+
+struct RowLaunch {
+    unsigned blocks;
+    int iters;       // row passes per block
+    int rows_per_pass;
+};
+
+// Tile shape for n rows with G lanes per row: at most kMaxPartials/2 blocks so
+// that the grid reductions stay cheap.
+inline RowLaunch row_launch(int64_t n, int G) {
+    RowLaunch L;
+    L.rows_per_pass = kBlock / G;
+    const int64_t max_blocks = kMaxPartials / 2;
+    int64_t iters = (n + (int64_t)L.rows_per_pass * max_blocks - 1) / ((int64_t)L.rows_per_pass * max_blocks);
+    if (iters < 1) iters = 1;
+    L.iters = (int)iters;
+    int64_t rows_per_block = (int64_t)L.rows_per_pass * L.iters;
+    int64_t b = (n + rows_per_block - 1) / rows_per_block;
+    L.blocks = (unsigned)(b < 1 ? 1 : b);
+    return L;
+}
+
+// Elementwise tile shape: one element per thread and pass.
+inline RowLaunch vec_launch(int64_t n) { return row_launch(n, 1); }
+
+#ifdef __HIPCC__
+namespace dev {
+
+// Logical tile of physical block b: XCD x = b mod 8 gets a contiguous run of
+// tiles.  A bijection on [0, nb) for any nb.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
+    const unsigned q = nb >> 3, r = nb & 7u, x = b & 7u, k = b >> 3;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+template <typename T>
+__device__ __forceinline__ T ldnt(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+
+// sum_k val[k] * xf(col[k]) over one row, by G lanes; result in every lane of
+// the group.  Accumulates in the value type.
+template <int G, typename VT, typename XF>
+__device__ __forceinline__ VT row_sum(int rb, int re, int lane, const int32_t *__restrict__ col,
+                                      const VT *__restrict__ val, XF xf) {
+    VT s = VT(0);
+    for (int k = rb + lane; k < re; k += G) s += ldnt(val + k) * xf(ldnt(col + k));
+    return group_sum<G>(s);
+}
+
+// Two block partials summed at once (fixed order), valid in thread 0.
+template <int BLOCK>
+__device__ __forceinline__ double2 block_sum2(double a, double b) {
+    __shared__ double ws[2][BLOCK / 64];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        ws[0][wid] = a;
+        ws[1][wid] = b;
+    }
+    __syncthreads();
+    double2 s = make_double2(0.0, 0.0);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w) {
+            s.x += ws[0][w];
+            s.y += ws[1][w];
+        }
+    }
+    __syncthreads();
+    return s;
+}
+
+// Grid sum of two values: as grid_sum_last, with partials[2*b], partials[2*b+1].
+template <int BLOCK>
+__device__ __forceinline__ bool grid_sum2_last(double2 bp, double *partials, unsigned *counter, double2 *total) {
+    __shared__ bool am_last;
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = bp.x;
+        partials[2 * blockIdx.x + 1] = bp.y;
+        __threadfence();
+        unsigned t = atomicAdd(counter, 1u);
+        am_last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!am_last) return false;
+    __threadfence();
+    double a = 0.0, b = 0.0;
+    for (unsigned k = threadIdx.x; k < gridDim.x; k += BLOCK) {
+        a += __hip_atomic_load(&partials[2 * k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        b += __hip_atomic_load(&partials[2 * k + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    double2 s = block_sum2<BLOCK>(a, b);
+    if (threadIdx.x == 0) {
+        *total = s;
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return true;
+}
+
+// After r.z of the new preconditioned residual is known (thread 0 of the
+// last block): beta = rz / gamma, gamma = rz; first call records gamma0; the
+// preconditioned stop test and the breakdown test live here.
+__device__ __forceinline__ void cg_after_precond(CgScalars *cg, double rz) {
+    if (cg->iter == 0) cg->gamma0 = rz;
+    if (!(rz > 0.0) || !isfinite(rz)) {
+        cg->flag = (rz == 0.0 && cg->rr == 0.0) ? 1 : 2;
+        cg->beta = 0.0;
+        return;
+    }
+    cg->beta = (cg->iter == 0) ? 0.0 : rz / cg->gamma;
+    cg->gamma = rz;
+    cg->rz_new = rz;
+    if (cg->stop_mode == OCP_STOP_PRECOND) {
+        if (cg->iter == 0) cg->tol2 = cg->tol2 * rz;   // tol2 held rtol^2 until now
+        else if (rz <= cg->tol2) cg->flag = 1;
+    }
+}
+
+}  // namespace dev
+#endif
+}  // namespace ocp

@@ -1,0 +1,356 @@
+// Preconditioned conjugate gradients for A u = f (Section 5: PCG with the
+// AMG V-cycle as preconditioner, stopped at a relative residual tolerance).
+//
+// All scalars (alpha, beta, gamma, residual norms, the stop flag) live on the
+// device: the last block of each reducing kernel finishes the reduction in a
+// fixed order and updates them, so an iteration is a chain of kernels with no
+// host round trip.  The host enqueues a few iterations at a time and then
+// reads the flag; kernels enqueued after convergence return immediately.
+#include <cmath>
+
+#include "kernels.h"
+#include "system.h"
+
+namespace ocp {
+
+constexpr int kSpmvLanes = 16;  // lanes per row of the fine-level SpMV (15-point rows)
+
+// ------------------------------------------------------------------ SpMV
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_spmv(int32_t n, int iters, const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                 const double *__restrict__ x, double *__restrict__ y) {
+    constexpr int RPP = kBlock / G;
+    const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x % G, grp = threadIdx.x / G;
+    const int base = (int)tile * RPP * iters;
+    for (int it = 0; it < iters; ++it) {
+        const int row = base + it * RPP + grp;
+        if (row < n) {
+            const double s = dev::row_sum<G>(rp[row], rp[row + 1], lane, col, val, [&](int c) { return x[c]; });
+            if (lane == 0) y[row] = s;
+        }
+    }
+}
+
+// q = A p and alpha = gamma / (p.q)
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_cg_spmv_pq(int32_t n, int iters, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col,
+                                                       const double *__restrict__ val, const double *__restrict__ p,
+                                                       double *__restrict__ q, CgScalars *cg, double *partials,
+                                                       unsigned *counter) {
+    if (cg->flag) return;
+    constexpr int RPP = kBlock / G;
+    const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x % G, grp = threadIdx.x / G;
+    const int base = (int)tile * RPP * iters;
+    double acc = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        const int row = base + it * RPP + grp;
+        if (row < n) {
+            const double s = dev::row_sum<G>(rp[row], rp[row + 1], lane, col, val, [&](int c) { return p[c]; });
+            if (lane == 0) {
+                q[row] = s;
+                acc += s * p[row];
+            }
+        }
+    }
+    acc = dev::block_sum<kBlock>(acc);
+    double tot;
+    if (dev::grid_sum_last<kBlock>(acc, partials, counter, &tot) && threadIdx.x == 0) {
+        cg->pq = tot;
+        if (!(tot > 0.0) || !isfinite(tot)) {
+            cg->flag = 2;
+            cg->alpha = 0.0;
+        } else {
+            cg->alpha = cg->gamma / tot;
+        }
+    }
+}
+
+// x += alpha p, r -= alpha q, r.r; with JAC also z = dinv r and r.z.
+template <bool JAC>
+__global__ void __launch_bounds__(kBlock) k_cg_update(int32_t n, int iters, double *__restrict__ x,
+                                                      double *__restrict__ r, const double *__restrict__ p,
+                                                      const double *__restrict__ q, const double *__restrict__ dinv,
+                                                      double *__restrict__ z, CgScalars *cg, double *partials,
+                                                      unsigned *counter) {
+    if (cg->flag) return;
+    const double alpha = cg->alpha;
+    const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
+    const int base = (int)tile * kBlock * iters;
+    double rr = 0.0, rz = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        const int i = base + it * kBlock + threadIdx.x;
+        if (i < n) {
+            x[i] += alpha * p[i];
+            const double ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            rr += ri * ri;
+            if (JAC) {
+                const double zi = dinv[i] * ri;
+                z[i] = zi;
+                rz += ri * zi;
+            }
+        }
+    }
+    double2 bs = dev::block_sum2<kBlock>(rr, rz);
+    double2 tot;
+    if (dev::grid_sum2_last<kBlock>(bs, partials, counter, &tot) && threadIdx.x == 0) {
+        cg->rr = tot.x;
+        cg->iter += 1;
+        if (cg->stop_mode == OCP_STOP_L2 && tot.x <= cg->tol2) {
+            cg->flag = 1;
+        } else if (!isfinite(tot.x)) {
+            cg->flag = 2;
+        } else {
+            if (JAC) dev::cg_after_precond(cg, tot.y);
+            if (cg->flag == 0 && cg->iter >= cg->maxit) cg->flag = 3;
+        }
+    }
+}
+
+// p = z + beta p
+__global__ void __launch_bounds__(kBlock) k_cg_pupdate(int32_t n, double *__restrict__ p, const double *__restrict__ z,
+                                                       const CgScalars *cg) {
+    if (cg->flag) return;
+    const double beta = cg->beta;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = z[i] + beta * p[i];
+}
+
+// x = 0, r = f, p = 0, f.f and the initial scalars
+__global__ void __launch_bounds__(kBlock) k_cg_init(int32_t n, int iters, const double *__restrict__ f,
+                                                    double *__restrict__ x, double *__restrict__ r,
+                                                    double *__restrict__ p, CgScalars *cg, double rtol, int mode,
+                                                    int maxit, double *partials, unsigned *counter) {
+    const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
+    const int base = (int)tile * kBlock * iters;
+    double ff = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        const int i = base + it * kBlock + threadIdx.x;
+        if (i < n) {
+            const double fi = f[i];
+            x[i] = 0.0;
+            r[i] = fi;
+            p[i] = 0.0;
+            ff += fi * fi;
+        }
+    }
+    ff = dev::block_sum<kBlock>(ff);
+    double tot;
+    if (dev::grid_sum_last<kBlock>(ff, partials, counter, &tot) && threadIdx.x == 0) {
+        cg->ff = tot;
+        cg->rr = tot;
+        cg->tol2 = (mode == OCP_STOP_L2) ? rtol * rtol * tot : rtol * rtol;
+        cg->gamma = 1.0;
+        cg->gamma0 = 0.0;
+        cg->alpha = 0.0;
+        cg->beta = 0.0;
+        cg->pq = 0.0;
+        cg->rz_new = 0.0;
+        cg->iter = 0;
+        cg->stop_mode = mode;
+        cg->maxit = maxit;
+        cg->flag = (tot == 0.0) ? 1 : (isfinite(tot) ? 0 : 2);
+    }
+}
+
+// z = dinv r and r.z (Jacobi preconditioner at the start)
+__global__ void __launch_bounds__(kBlock) k_cg_jacobi(int32_t n, int iters, const double *__restrict__ r,
+                                                      const double *__restrict__ dinv, double *__restrict__ z,
+                                                      CgScalars *cg, double *partials, unsigned *counter) {
+    if (cg->flag) return;
+    const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
+    const int base = (int)tile * kBlock * iters;
+    double rz = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        const int i = base + it * kBlock + threadIdx.x;
+        if (i < n) {
+            const double zi = dinv[i] * r[i];
+            z[i] = zi;
+            rz += r[i] * zi;
+        }
+    }
+    rz = dev::block_sum<kBlock>(rz);
+    double tot;
+    if (dev::grid_sum_last<kBlock>(rz, partials, counter, &tot) && threadIdx.x == 0) dev::cg_after_precond(cg, tot);
+}
+
+// sum_i (f_i - (A x)_i)^2
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_resid2(int32_t n, int iters, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                   const double *__restrict__ x, const double *__restrict__ f,
+                                                   double *out, double *partials, unsigned *counter) {
+    constexpr int RPP = kBlock / G;
+    const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x % G, grp = threadIdx.x / G;
+    const int base = (int)tile * RPP * iters;
+    double acc = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        const int row = base + it * RPP + grp;
+        if (row < n) {
+            const double s = dev::row_sum<G>(rp[row], rp[row + 1], lane, col, val, [&](int c) { return x[c]; });
+            if (lane == 0) {
+                const double d = f[row] - s;
+                acc += d * d;
+            }
+        }
+    }
+    acc = dev::block_sum<kBlock>(acc);
+    double tot;
+    if (dev::grid_sum_last<kBlock>(acc, partials, counter, &tot) && threadIdx.x == 0) *out = tot;
+}
+
+__global__ void k_scatter(int32_t nv, const int32_t *__restrict__ dof_of_vertex, const double *__restrict__ x,
+                          double *__restrict__ u) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const int d = dof_of_vertex[v];
+    u[v] = d >= 0 ? x[d] : 0.0;
+}
+
+__global__ void k_diag_inv(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                           const double *__restrict__ val, double *__restrict__ dinv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double d = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+        if (col[k] == i) d = val[k];
+    dinv[i] = 1.0 / d;
+}
+
+// --------------------------------------------------------------- host side
+void spmv_enqueue(ocp_ctx *ctx, int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                  const double *x, double *y) {
+    const RowLaunch L = row_launch(n, kSpmvLanes);
+    k_spmv<kSpmvLanes><<<L.blocks, kBlock, 0, ctx->stream>>>(n, L.iters, rp, col, val, x, y);
+    OCP_LAUNCH_CHECK();
+}
+
+const double *system_dinv(ocp_ctx *ctx, ocp_system *sys) {
+    if (!sys->dinv.get()) {
+        sys->dinv.reset(ctx, (size_t)sys->n);
+        k_diag_inv<<<grid_for(sys->n, 256), 256, 0, ctx->stream>>>(sys->n, sys->row_ptr.get(), sys->col.get(),
+                                                                   sys->val.get(), sys->dinv.get());
+        OCP_LAUNCH_CHECK();
+    }
+    return sys->dinv.get();
+}
+
+static void solve(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, const double *f_in, double *u,
+                  double rtol, int32_t maxit, int32_t flags, ocp_solve_info *info, int *status) {
+    const int32_t n = sys->n;
+    const double *f = f_in ? f_in : sys->f.get();
+    DevBuf<double> x(ctx, n), r(ctx, n), p(ctx, n), q(ctx, n), z(ctx, n);
+    const double *dinv = h ? nullptr : system_dinv(ctx, sys);
+    const int mode = (flags & OCP_STOP_PRECOND) ? OCP_STOP_PRECOND : OCP_STOP_L2;
+    CgScalars *cg = ctx->cg;
+    double *part0 = ctx->red_partials;
+    double *part1 = ctx->red_partials + kRedBlocks;
+    double *part2 = ctx->red_partials + 2 * kRedBlocks;
+    unsigned *cnt0 = ctx->red_counters, *cnt1 = ctx->red_counters + 1, *cnt2 = ctx->red_counters + 2;
+    const RowLaunch LS = row_launch(n, kSpmvLanes);
+    const RowLaunch LV = vec_launch(n);
+    const unsigned gp = grid_for(n, kBlock);
+
+    ctx->prof_iter = -1;   // the initial preconditioner application
+    OCP_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+    k_cg_init<<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, f, x.get(), r.get(), p.get(), cg, rtol, mode, maxit,
+                                                     part0, cnt0);
+    OCP_LAUNCH_CHECK();
+    if (h)
+        vcycle_enqueue(ctx, h, r.get(), z.get(), cg);
+    else
+        k_cg_jacobi<<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, r.get(), dinv, z.get(), cg, part1, cnt1);
+    OCP_LAUNCH_CHECK();
+    k_cg_pupdate<<<gp, kBlock, 0, ctx->stream>>>(n, p.get(), z.get(), cg);
+    OCP_LAUNCH_CHECK();
+
+    CgScalars hs{};
+    int chunk = 2;
+    ctx->prof_iter = 0;
+    for (;;) {
+        read_back(ctx, &hs, cg, sizeof(hs));
+        if (hs.flag != 0) break;
+        for (int k = 0; k < chunk; ++k) {
+            const int pr = prof_begin(ctx, OCP_KERNEL_CG_SPMV);
+            k_cg_spmv_pq<kSpmvLanes><<<LS.blocks, kBlock, 0, ctx->stream>>>(
+                n, LS.iters, sys->row_ptr.get(), sys->col.get(), sys->val.get(), p.get(), q.get(), cg, part0, cnt0);
+            prof_end(ctx, pr);
+            if (h) {
+                k_cg_update<false><<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, x.get(), r.get(), p.get(),
+                                                                          q.get(), nullptr, nullptr, cg, part1, cnt1);
+                vcycle_enqueue(ctx, h, r.get(), z.get(), cg);
+            } else {
+                k_cg_update<true><<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, x.get(), r.get(), p.get(),
+                                                                         q.get(), dinv, z.get(), cg, part1, cnt1);
+            }
+            k_cg_pupdate<<<gp, kBlock, 0, ctx->stream>>>(n, p.get(), z.get(), cg);
+            ++ctx->prof_iter;
+        }
+        OCP_LAUNCH_CHECK();
+        if (chunk < 8) chunk *= 2;
+    }
+    OCP_HIP(hipEventRecord(ctx->ev1, ctx->stream));
+
+    // true residual in double, then u on all vertices
+    k_resid2<kSpmvLanes><<<LS.blocks, kBlock, 0, ctx->stream>>>(n, LS.iters, sys->row_ptr.get(), sys->col.get(),
+                                                                sys->val.get(), x.get(), f, ctx->red_out + 1, part2,
+                                                                cnt2);
+    OCP_LAUNCH_CHECK();
+    k_scatter<<<grid_for(sys->nv, 256), 256, 0, ctx->stream>>>(sys->nv, sys->dof_of_vertex.get(), x.get(), u);
+    OCP_LAUNCH_CHECK();
+    double res2 = 0.0;
+    read_back(ctx, &res2, ctx->red_out + 1, sizeof(res2));
+    float ms = 0.f;
+    OCP_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    // every kernel of host iterations 0 .. iter-2 did its full work
+    prof_resolve(ctx, hs.iter - 1);
+
+    int st = OCP_OK;
+    if (hs.flag == 2) st = OCP_ERR_BREAKDOWN;
+    else if (hs.flag == 3) st = OCP_MAXIT;
+    if (info) {
+        info->iterations = hs.iter;
+        info->status = st;
+        info->rel_res_l2 = hs.ff > 0 ? std::sqrt(hs.rr / hs.ff) : 0.0;
+        info->rel_res_precond = hs.gamma0 > 0 ? std::sqrt(hs.gamma / hs.gamma0) : 0.0;
+        info->true_rel_res = hs.ff > 0 ? std::sqrt(res2 / hs.ff) : 0.0;
+        info->solve_ms = ms;
+    }
+    *status = st;
+}
+
+}  // namespace ocp
+
+using namespace ocp;
+
+extern "C" int ocp_spmv(ocp_ctx *ctx, const ocp_system *sys, const double *x, double *y) {
+    if (!ctx) return OCP_ERR_INVALID_ARG;
+    return run_guarded(ctx, [&] {
+        if (!sys || !x || !y) fail(OCP_ERR_INVALID_ARG, "system, x and y must not be NULL");
+        spmv_enqueue(ctx, sys->n, sys->row_ptr.get(), sys->col.get(), sys->val.get(), x, y);
+    });
+}
+
+extern "C" int pcg_solve(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, const double *f, double *u,
+                         double rtol, int32_t maxit, int32_t flags, ocp_solve_info *info) {
+    if (!ctx) return OCP_ERR_INVALID_ARG;
+    int status = OCP_OK;
+    int rc = run_guarded(ctx, [&] {
+        if (!sys || !u) fail(OCP_ERR_INVALID_ARG, "system and u must not be NULL");
+        if (!(rtol > 0.0) || !std::isfinite(rtol)) fail(OCP_ERR_INVALID_ARG, "rtol must be positive");
+        if (maxit < 1) fail(OCP_ERR_INVALID_ARG, "maxit must be >= 1");
+        if (h && h->sys != sys) fail(OCP_ERR_INVALID_ARG, "hierarchy belongs to another system");
+        solve(ctx, const_cast<ocp_system *>(sys), h, f, u, rtol, maxit, flags, info, &status);
+    });
+    if (rc != OCP_OK) {
+        if (info) info->status = rc;
+        return rc;
+    }
+    if (status == OCP_ERR_BREAKDOWN) ctx->last_error = "CG breakdown (p^T A p <= 0, r^T z <= 0 or non-finite)";
+    return status;
+}

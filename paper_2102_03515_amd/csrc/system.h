@@ -1,0 +1,68 @@
+// Library-side objects behind the opaque handles of the C interface: the
+// assembled system and the AMG hierarchy.
+#pragma once
+
+#include "common.h"
+
+struct ocp_system {
+    ocp_ctx *ctx = nullptr;
+    int32_t nv = 0;           // mesh vertices
+    int32_t n = 0;            // interior unknowns
+    int64_t nt = 0;           // tetrahedra
+    int64_t nnz = 0;
+    double rho = 0.0;
+    const int32_t *tets_ref = nullptr;  // mesh tets the system was assembled from (borrowed)
+    ocp::DevBuf<int32_t> inc_ptr, inc;  // vertex -> incident tets, ascending
+    ocp::DevBuf<int32_t> dof_of_vertex, vertex_of_dof;
+    ocp::DevBuf<int32_t> row_ptr, col;
+    ocp::DevBuf<double> val, valK, valM, f;
+    // derived data, rebuilt on demand and dropped when the values change
+    ocp::DevBuf<double> dinv;   // 1 / a_ii
+    void invalidate_derived() { dinv.release(); }
+};
+
+namespace ocp {
+
+// One level of the smoothed-aggregation hierarchy.  Level 0 borrows the
+// system's CSR; coarser levels own theirs.
+struct Level {
+    int32_t n = 0, nc = 0;
+    int64_t nnzA = 0, nnzP = 0;
+    const int32_t *A_rp = nullptr, *A_col = nullptr;
+    const double *A_val = nullptr;
+    DevBuf<int32_t> own_rp, own_col;
+    DevBuf<double> own_val;
+    DevBuf<int32_t> P_rp, P_col, R_rp, R_col, agg;
+    DevBuf<double> P_val, R_val;
+    DevBuf<double> dinv;       // smoother diagonal inverse (L1-Jacobi: 1/(sum_j |a_ij|))
+    DevBuf<double> dense_inv;  // last level only: A^{-1}, dense row-major
+    // single-precision copies (mixed precision)
+    DevBuf<float> A_val32, P_val32, R_val32, dinv32, dense_inv32;
+    // V-cycle work vectors in the hierarchy's precision (bytes)
+    DevBuf<char> vb, vr, vx, vxp;
+    double lambda_max = 0.0;   // Gershgorin bound of D^-1 A
+    int gA = 16, gP = 4, gR = 64;  // lanes per row of the A, P and R kernels
+};
+
+}  // namespace ocp
+
+struct ocp_hierarchy {
+    ocp_ctx *ctx = nullptr;
+    const ocp_system *sys = nullptr;
+    ocp_amg_params params{};
+    std::vector<std::unique_ptr<ocp::Level>> levels;
+};
+
+namespace ocp {
+// Enqueue z = B r (one V-cycle).  If cg != nullptr the level-0 post-smoother
+// also forms r.z and updates the CG scalars, and every kernel returns at once
+// when cg->flag is set.
+void vcycle_enqueue(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r, double *z, CgScalars *cg);
+// y = A x on the system's matrix.
+void spmv_enqueue(ocp_ctx *ctx, int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                  const double *x, double *y);
+// Lanes per row for a matrix with the given average row length.
+int level_lanes(int64_t nnz, int64_t rows);
+// Build 1/a_ii of the system if missing.
+const double *system_dinv(ocp_ctx *ctx, ocp_system *sys);
+}  // namespace ocp

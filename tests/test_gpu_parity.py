@@ -1,0 +1,300 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C interface.
+
+Bars (stated per test): integer outputs (CSR pattern, dof maps, aggregates)
+bit-exact; assembled values and SpMV within a few units of rounding of the
+row scale; the FP64 solve at a tight tolerance within 1e-10 relative error of
+the oracle's discrete solution; the mixed-precision solve reaching the
+1e-8 relative residual with its error against the FP64 oracle reported.
+"""
+import numpy as np
+import pytest
+
+import ocp_inputs as I
+import oracle as O
+from oracle import amg as OA
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2102_03515_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    return P.Context()
+
+
+def _target(name):
+    return {"sine111": I.single_sine(), "box": I.box_indicator(),
+            "modes": I.random_sine_modes(1000, n_modes=64),
+            "offset": I.single_sine(offset=1.0)}[name]
+
+
+def _gpu_system(P, ctx, mesh, rho, target, flags=0):
+    dm = P.upload_mesh(mesh)
+    return P.fe_assemble(ctx, dm, rho, target, flags), dm
+
+
+def _host_csr(sys_):
+    rp, col, val = sys_.csr()
+    return rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+
+
+ASM_CASES = [
+    ("cube16_sine111", 16, 0.0, 1.0 / 256, "sine111"),
+    ("cube12_jitter_box", 12, 0.15, 1e-2, "box"),
+    ("cube9_jitter_modes64", 9, 0.15, 1e-6, "modes"),
+    ("cube7_offset", 7, 0.0, 1.0, "offset"),
+]
+
+
+@pytest.mark.parametrize("name,N,jit,rho,tgt", ASM_CASES, ids=[c[0] for c in ASM_CASES])
+def test_assembly_matches_oracle(P, ctx, name, N, jit, rho, tgt):
+    print(f"[assembly] {name} N={N} jitter={jit} rho={rho}", flush=True)
+    mesh = I.kuhn_mesh(N, jitter=jit, seed=1)
+    target = _target(tgt)
+    s, _ = _gpu_system(P, ctx, mesh, rho, target)
+    o = O.assemble(mesh, rho, target)
+    rp, col, val = _host_csr(s)
+    np.testing.assert_array_equal(rp, o.row_ptr)
+    np.testing.assert_array_equal(col, o.col)
+    np.testing.assert_array_equal(s.dof_of_vertex().cpu().numpy(), o.dof_of_vertex)
+    np.testing.assert_array_equal(s.vertex_of_dof().cpu().numpy(), o.vertex_of_dof)
+    scale = np.abs(o.val).max()
+    np.testing.assert_allclose(val, o.val, rtol=0, atol=1e-14 * scale)
+    f = s.f().cpu().numpy()
+    np.testing.assert_allclose(f, o.f, rtol=0, atol=1e-13 * max(np.abs(o.f).max(), 1e-300))
+
+
+def test_nodal_target_and_fe_load(P, ctx):
+    print("[fe_load] cube6 nodal + sine", flush=True)
+    import torch
+    mesh = I.kuhn_mesh(6, jitter=0.15, seed=3)
+    rng = np.random.default_rng(5)
+    vals = rng.standard_normal(mesh.n_vertices)
+    s, dm = _gpu_system(P, ctx, mesh, 0.1, I.Nodal(values=vals))
+    o = O.assemble(mesh, 0.1, I.Nodal(values=vals))
+    np.testing.assert_allclose(s.f().cpu().numpy(), o.f, atol=1e-14 * np.abs(o.f).max())
+    tgt2 = I.random_sine_modes(7, n_modes=10)
+    f2 = s.load(tgt2).cpu().numpy()
+    o2 = O.assemble(mesh, 0.1, tgt2)
+    np.testing.assert_allclose(f2, o2.f, atol=1e-14 * np.abs(o2.f).max())
+
+
+def test_set_rho_reweights(P, ctx):
+    print("[fe_set_rho] cube8", flush=True)
+    mesh = I.kuhn_mesh(8, jitter=0.15, seed=2)
+    s, _ = _gpu_system(P, ctx, mesh, 1.0, I.single_sine(), flags=P.capi.KEEP_KM)
+    s.set_rho(1e-3)
+    o = O.assemble(mesh, 1e-3, I.single_sine())
+    _, _, val = _host_csr(s)
+    np.testing.assert_allclose(val, o.val, atol=1e-14 * np.abs(o.val).max())
+
+
+def test_spmv_matches_oracle(P, ctx):
+    import torch
+    print("[spmv] cube20 jitter", flush=True)
+    mesh = I.kuhn_mesh(20, jitter=0.15, seed=4)
+    s, _ = _gpu_system(P, ctx, mesh, 1e-2, I.single_sine())
+    o = O.assemble(mesh, 1e-2, I.single_sine())
+    x = np.random.default_rng(0).standard_normal(o.n)
+    y = s.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
+    yo = O.spmv(o, x)
+    # each row sums 15 products of size <= |a|max |x|max
+    bound = 32 * 2.2e-16 * np.abs(o.val).max() * np.abs(x).max()
+    assert np.abs(y - yo).max() <= bound
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("N,jit,rho,tgt", [(10, 0.15, 1e-2, "box"), (16, 0.0, 1.0 / 256, "sine111")])
+def test_jacobi_pcg_matches_oracle(P, ctx, N, jit, rho, tgt):
+    print(f"[pcg jacobi] N={N} rho={rho} {tgt}", flush=True)
+    mesh = I.kuhn_mesh(N, jitter=jit, seed=7)
+    target = _target(tgt)
+    s, _ = _gpu_system(P, ctx, mesh, rho, target)
+    u, info, rc = P.pcg_solve(ctx, s, None, rtol=1e-13, maxit=5000)
+    assert rc == 0, info.as_dict()
+    x, o, it, rr = O.solve(mesh, rho, target, rtol=1e-14)
+    uo = O.to_vertices(o, x, mesh.n_vertices)
+    assert _rel(u.cpu().numpy(), uo) < 1e-10
+    assert info.true_rel_res < 1e-12
+
+
+AMG_CASES = [
+    ("cube16_sine111_rho_h2", 16, 0.0, 1.0 / 256, "sine111"),
+    ("cube24_jitter_box_rho1e-2", 24, 0.15, 1e-2, "box"),
+    ("cube24_jitter_box_rho1e-6", 24, 0.15, 1e-6, "box"),
+    ("cube20_modes_rho1", 20, 0.0, 1.0, "modes"),
+]
+
+
+@pytest.mark.parametrize("name,N,jit,rho,tgt", AMG_CASES, ids=[c[0] for c in AMG_CASES])
+def test_amg_pcg_fp64_matches_oracle(P, ctx, name, N, jit, rho, tgt):
+    print(f"[pcg amg fp64] {name}", flush=True)
+    mesh = I.kuhn_mesh(N, jitter=jit, seed=11)
+    target = _target(tgt)
+    s, _ = _gpu_system(P, ctx, mesh, rho, target)
+    h = P.amg_setup(ctx, s, coarse_max=64)
+    assert h.n_levels >= 2
+    u, info, rc = P.pcg_solve(ctx, s, h, rtol=1e-13, maxit=500)
+    assert rc == 0, info.as_dict()
+    x, o, it, rr = O.solve(mesh, rho, target, rtol=1e-14)
+    uo = O.to_vertices(o, x, mesh.n_vertices)
+    err = _rel(u.cpu().numpy(), uo)
+    print(f"    levels={h.n_levels} its={info.iterations} true_res={info.true_rel_res:.2e} err={err:.2e}")
+    assert err < 1e-10
+    # at the paper's tolerance the AMG iteration count stays small
+    u8, info8, rc8 = P.pcg_solve(ctx, s, h, rtol=1e-8, maxit=500)
+    assert rc8 == 0 and info8.true_rel_res <= 1.0001e-8 and info8.iterations <= 30, info8.as_dict()
+
+
+@pytest.mark.parametrize("N,jit,rho,tgt", [(24, 0.15, 1.0 / 576, "box"), (16, 0.0, 1.0, "sine111")])
+def test_amg_pcg_mixed_reaches_tolerance(P, ctx, N, jit, rho, tgt):
+    print(f"[pcg amg mixed] N={N} rho={rho}", flush=True)
+    mesh = I.kuhn_mesh(N, jitter=jit, seed=13)
+    target = _target(tgt)
+    s, _ = _gpu_system(P, ctx, mesh, rho, target)
+    h = P.amg_setup(ctx, s, precision=P.capi.PREC_MIXED, coarse_max=64)
+    u, info, rc = P.pcg_solve(ctx, s, h, rtol=1e-8, maxit=500)
+    assert rc == 0, info.as_dict()
+    assert info.true_rel_res <= 1.0001e-8
+    x, o, it, rr = O.solve(mesh, rho, target, rtol=1e-14)
+    uo = O.to_vertices(o, x, mesh.n_vertices)
+    # the true residual bounds the error by cond(A) * 1e-8; record it
+    err = _rel(u.cpu().numpy(), uo)
+    print(f"    mixed its={info.iterations} true_res={info.true_rel_res:.2e} err_vs_fp64_oracle={err:.2e}")
+    assert err < 1e-6
+
+
+def test_vcycle_is_symmetric_positive(P, ctx):
+    import torch
+    print("[vcycle spd] cube20 jitter", flush=True)
+    mesh = I.kuhn_mesh(20, jitter=0.15, seed=17)
+    s, _ = _gpu_system(P, ctx, mesh, 1.0 / 400, I.single_sine())
+    h = P.amg_setup(ctx, s, coarse_max=64)
+    rng = np.random.default_rng(1)
+    n = s.n
+    for _ in range(3):
+        x = torch.from_numpy(rng.standard_normal(n)).cuda()
+        y = torch.from_numpy(rng.standard_normal(n)).cuda()
+        bx = h.vcycle(x)
+        by = h.vcycle(y)
+        lhs = float(torch.dot(bx, y))
+        rhs = float(torch.dot(x, by))
+        assert abs(lhs - rhs) <= 1e-12 * float(bx.norm() * y.norm())
+        assert float(torch.dot(bx, x)) > 0
+
+
+def test_hierarchy_matches_oracle_definitions(P, ctx):
+    """Aggregates bit-exact against the greedy definition; P, R = P^T and
+    A_c = P^T A P within rounding."""
+    import scipy.sparse as sp
+    print("[amg setup] cube14 rho=h^2", flush=True)
+    N = 14
+    rho = 1.0 / N ** 2
+    mesh = I.kuhn_mesh(N, jitter=0.0)
+    s, _ = _gpu_system(P, ctx, mesh, rho, I.single_sine())
+    h = P.amg_setup(ctx, s, coarse_max=32)
+    o = O.assemble(mesh, rho, I.single_sine())
+    A0 = o.csr()
+    assert OA.strength_margin(A0, 0.08) > 1e-6
+    ol = OA.build_hierarchy(A0, theta=0.08, coarse_max=32)
+    assert len(ol) == h.n_levels
+    for lev in range(h.n_levels - 1):
+        g = h.level_arrays(lev)
+        agg = g["agg"].cpu().numpy()
+        if lev == 0:
+            np.testing.assert_array_equal(agg, ol[0]["agg"])
+        n, nc = g["n"], g["nc"]
+        Pg = sp.csr_matrix((g["P"][2].cpu().numpy(), g["P"][1].cpu().numpy(), g["P"][0].cpu().numpy()),
+                           shape=(n, nc))
+        Rg = sp.csr_matrix((g["R"][2].cpu().numpy(), g["R"][1].cpu().numpy(), g["R"][0].cpu().numpy()),
+                           shape=(nc, n))
+        assert (Rg != Pg.T.tocsr()).nnz == 0, "R is not exactly P^T"
+        Ag = sp.csr_matrix((g["A"][2].cpu().numpy(), g["A"][1].cpu().numpy(), g["A"][0].cpu().numpy()),
+                           shape=(n, n))
+        # prolongator from its definition, on the GPU's own A and aggregates
+        Pt = OA.tentative_prolongator(agg, nc)
+        Pdef = OA.smoothed_prolongator(Ag, Pt, 4.0 / 3.0)
+        assert abs(Pdef - Pg).max() <= 1e-14 * abs(Pdef).max()
+        # Galerkin product of the next level
+        nxt = h.level_arrays(lev + 1)
+        Ac = sp.csr_matrix((nxt["A"][2].cpu().numpy(), nxt["A"][1].cpu().numpy(), nxt["A"][0].cpu().numpy()),
+                           shape=(nc, nc))
+        Adef = (Pg.T @ Ag @ Pg).tocsr()
+        assert abs(Adef - Ac).max() <= 1e-13 * abs(Adef).max()
+        if lev == 0:
+            Aorc1 = ol[1]["A"]
+            assert abs(Aorc1 - Ac).max() <= 1e-12 * abs(Aorc1).max()
+    last = h.level_arrays(h.n_levels - 1)
+    if "dense_inv" in last:
+        Ad = sp.csr_matrix((last["A"][2].cpu().numpy(), last["A"][1].cpu().numpy(), last["A"][0].cpu().numpy()),
+                           shape=(last["n"], last["n"])).toarray()
+        Ainv = last["dense_inv"].cpu().numpy()
+        np.testing.assert_allclose(Ainv @ Ad, np.eye(last["n"]), atol=1e-10)
+
+
+def test_solve_is_deterministic(P, ctx):
+    print("[determinism] cube18 jitter box", flush=True)
+    mesh = I.kuhn_mesh(18, jitter=0.15, seed=21)
+    outs = []
+    for _ in range(2):
+        s, _ = _gpu_system(P, ctx, mesh, 1e-3, I.box_indicator())
+        h = P.amg_setup(ctx, s, coarse_max=64)
+        u, info, rc = P.pcg_solve(ctx, s, h, rtol=1e-10)
+        outs.append((u.cpu().numpy().copy(), info.iterations, _host_csr(s)[2].copy()))
+    assert np.array_equal(outs[0][2], outs[1][2])
+    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][0], outs[1][0])
+
+
+def test_error_paths(P, ctx):
+    import torch
+    print("[errors] invalid inputs", flush=True)
+    mesh = I.kuhn_mesh(4)
+    dm = P.upload_mesh(mesh)
+    with pytest.raises(P.OcpError) as e:
+        P.fe_assemble(ctx, dm, -1.0, I.single_sine())
+    assert e.value.code == P.capi.ERR_INVALID_ARG
+    with pytest.raises(P.OcpError) as e:
+        P.fe_assemble(ctx, dm, float("nan"), I.single_sine())
+    assert e.value.code == P.capi.ERR_INVALID_ARG
+    bad = I.SineModes(k=np.array([[1, 1, 1]], dtype=np.int32), amp=np.array([np.nan]))
+    with pytest.raises(P.OcpError) as e:
+        P.fe_assemble(ctx, dm, 1.0, bad)
+    assert e.value.code == P.capi.ERR_INVALID_ARG
+    # vertex index out of range (caught by the host-visible check kernel)
+    tets = mesh.tets.copy()
+    tets[3, 2] = mesh.n_vertices + 5
+    dm2 = P.capi.DeviceMesh(dm.xyz, torch.from_numpy(tets).cuda(), dm.dirichlet)
+    with pytest.raises(P.OcpError) as e:
+        P.fe_assemble(ctx, dm2, 1.0, I.single_sine())
+    assert e.value.code == P.capi.ERR_BAD_MESH
+    # degenerate tetrahedron: collapse one vertex onto another
+    xyz = mesh.xyz.copy()
+    t0 = mesh.tets[0]
+    xyz[t0[1]] = xyz[t0[0]]
+    dm3 = P.capi.DeviceMesh(torch.from_numpy(xyz).cuda(), dm.tets, dm.dirichlet)
+    with pytest.raises(P.OcpError) as e:
+        P.fe_assemble(ctx, dm3, 1.0, I.single_sine())
+    assert e.value.code == P.capi.ERR_BAD_MESH
+    # iteration cap: status MAXIT, not an error
+    s = P.fe_assemble(ctx, dm, 1.0, I.single_sine())
+    u, info, rc = P.pcg_solve(ctx, s, None, rtol=1e-14, maxit=1)
+    assert rc == P.capi.MAXIT and info.iterations == 1
+    with pytest.raises(P.OcpError) as e:
+        P.pcg_solve(ctx, s, None, rtol=0.0)
+    assert e.value.code == P.capi.ERR_INVALID_ARG
+    # zero right-hand side: converged at once with u = 0
+    z = torch.zeros(s.n, dtype=torch.float64, device="cuda")
+    u, info, rc = P.pcg_solve(ctx, s, None, f=z)
+    assert rc == 0 and info.iterations == 0 and float(u.abs().max()) == 0.0

@@ -35,22 +35,30 @@ WORKLOADS = {
 }
 
 
-def kernel_bytes(kernel: int, n: int, nnz: int, nnz_p: int, mixed: bool) -> float:
-    """Algorithmic HBM bytes of one launch: the matrix read once, every vector
-    read or written once (gathered vectors counted once)."""
-    vs = 4 if mixed else 8          # V-cycle value and vector size
-    if kernel == 0:    # q = A p, p.q: col + val(8) + row_ptr + p + q
+def kernel_bytes(kernel: int, n: int, nnz: int, mixed: bool) -> float:
+    """Algorithmic HBM bytes of one launch of a fine-level kernel: every matrix
+    entry (4-byte column + value) read once, the row pointers once, and every
+    vector read or written once (a gathered vector counts once).  CG vectors
+    are double; V-cycle values and vectors are float in mixed precision."""
+    vs = 4 if mixed else 8
+    mat = (4 + vs) * nnz + 4.0 * (n + 1)
+    if kernel == 0:    # q = A p, p.q: 8-byte values, p gathered, q written
         return 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n
-    if kernel == 1:    # r = b - A D^-1 b: col + val + row_ptr + b(8) + d + r
-        return (4 + vs) * nnz + 4.0 * (n + 1) + 8.0 * n + 2.0 * vs * n
-    if kernel == 2:    # z = xp + D^-1 (b - A xp), r.z: col + val + row_ptr + xp + d + b(8) + z(8)
-        return (4 + vs) * nnz + 4.0 * (n + 1) + 2.0 * vs * n + 16.0 * n
+    if kernel == 1:    # r1 = b - A (a D^-1 b): b(8) d r1
+        return mat + 8.0 * n + 2.0 * vs * n
+    if kernel == 5:    # r2 = b - A D^-1 (c1 b + c2 r1): b(8) d r1 r2
+        return mat + 8.0 * n + 3.0 * vs * n
+    if kernel == 6:    # r0 = b - A xp: b(8) xp r0
+        return mat + 8.0 * n + 2.0 * vs * n
+    if kernel == 2:    # z = xp + D^-1 (c1 r0 + c2 r1), r1 = b - A (xp + a D^-1 r0), b.z: b(8) xp r0 d z(8)
+        return mat + 16.0 * n + 3.0 * vs * n
     raise ValueError(kernel)
 
 
-KERNEL_NAMES = {0: "cg_spmv_pq (FP64 CSR SpMV + p.q)", 1: "vcycle_pre_smooth_residual (level 0)",
-                2: "vcycle_post_smooth_rz (level 0)", 3: "vcycle_restrict (level 0)",
-                4: "vcycle_prolong (level 0)"}
+KERNEL_NAMES = {0: "cg_spmv_pq (FP64 CSR SpMV + p.q)", 1: "vc_pre_smooth_1 (level 0)",
+                2: "vc_post_smooth_final_rz (level 0)", 3: "vc_restrict (level 0)",
+                4: "vc_prolong (level 0)", 5: "vc_pre_smooth_2 (level 0)", 6: "vc_post_residual (level 0)"}
+MATRIX_KERNELS = (0, 1, 2, 5, 6)
 
 
 def cpu_baseline(target_seed: int, N_sample: int = 64):
@@ -135,23 +143,22 @@ def main():
         print(f"[bench] step {k}: {json.dumps(metas[-1])}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ctx.profile(False) if False else None
     n, nnz = metas[0]["n"], metas[0]["nnz"]
     ms_per_step = 1e3 * (t1 - t0) / args.steps
     value = n * args.steps / (t1 - t0)
 
     # dominant kernel of the timed region, live event timings
-    timings = {k: ctx.kernel_timing(k) for k in range(5)}
-    dom = max((k for k in (0, 1, 2)), key=lambda k: timings[k][1])
+    timings = {k: ctx.kernel_timing(k) for k in range(7)}
+    dom = max(MATRIX_KERNELS, key=lambda k: timings[k][1])
     launches, tot_ms = timings[dom]
     avg_ms = tot_ms / max(launches, 1)
-    alg = kernel_bytes(dom, n, nnz, metas[0]["nnz_P0"], mixed=(dom != 0))
+    alg = kernel_bytes(dom, n, nnz, mixed=(dom != 0))
     achieved = alg / (avg_ms * 1e-3) / 1e9
     kernels = {KERNEL_NAMES[k]: {"launches": timings[k][0],
                                  "avg_us": 1e3 * timings[k][1] / max(timings[k][0], 1)}
-               for k in range(5)}
-    for k in (0, 1, 2):
-        b = kernel_bytes(k, n, nnz, metas[0]["nnz_P0"], mixed=(k != 0))
+               for k in range(7)}
+    for k in MATRIX_KERNELS:
+        b = kernel_bytes(k, n, nnz, mixed=(k != 0))
         t = timings[k][1] / max(timings[k][0], 1)
         kernels[KERNEL_NAMES[k]]["alg_bytes"] = b
         kernels[KERNEL_NAMES[k]]["alg_GBps"] = b / (t * 1e-3) / 1e9 if t > 0 else None

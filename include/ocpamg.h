@@ -153,15 +153,16 @@ int ocp_spmv(ocp_ctx *ctx, const ocp_system *sys, const double *x, double *y);
 typedef struct {
     int32_t precision;   /* OCP_PREC_* */
     int32_t smoother;    /* OCP_SMOOTH_* */
-    int32_t degree;      /* Chebyshev degree (>= 1); ignored by L1-Jacobi */
+    int32_t degree;      /* Chebyshev degree, 1 or 2; L1-Jacobi uses 1 */
     int32_t coarse_max;  /* stop coarsening at n <= coarse_max (dense solve there), <= 2048 */
     int32_t max_levels;  /* 1..16 */
     double theta;        /* strength threshold: |a_ij| >= theta sqrt(a_ii a_jj) */
     double omega;        /* prolongator smoothing: omega/lambda_max(D^-1 A), 4/3 default */
+    double cheb_ratio;   /* Chebyshev interval [lambda/cheb_ratio, lambda], lambda = Gershgorin bound */
 } ocp_amg_params;
 
-/* Fill `p` with the defaults (FP64, L1-Jacobi, coarse_max 512, 10 levels,
- * theta 0.08, omega 4/3). */
+/* Fill `p` with the defaults (FP64, Chebyshev degree 2 on [lambda/10, lambda],
+ * coarse_max 512, 10 levels, theta 0, omega 4/3). */
 void amg_default_params(ocp_amg_params *p);
 
 /* Build a smoothed-aggregation hierarchy for the system's A (Section 4.1:
@@ -194,8 +195,9 @@ typedef struct {
 } ocp_level_view;
 int ocp_hierarchy_get_level(const ocp_hierarchy *h, int32_t level, ocp_level_view *view);
 
-/* z = B r: one V(1,1)-cycle with zero initial guess (Section 4.1, two-grid
- * operator applied recursively).  r, z: device [n_dofs]. */
+/* z = B r: one V-cycle with zero initial guess (Section 4.1, two-grid
+ * operator applied recursively), the same polynomial smoother before and
+ * after the coarse correction so that B is symmetric.  r, z: device [n_dofs]. */
 int amg_vcycle(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r, double *z);
 
 /* ---------------------------------------------------------------- solve */
@@ -224,10 +226,12 @@ int pcg_solve(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, const
 
 /* ------------------------------------------------------- kernel timing */
 #define OCP_KERNEL_CG_SPMV 0      /* q = A p with p.q, FP64 CSR (the CG iteration's SpMV) */
-#define OCP_KERNEL_VC_PRE0 1      /* fine-level pre-smoother fused with the residual */
-#define OCP_KERNEL_VC_POST0 2     /* fine-level post-smoother with r.z */
+#define OCP_KERNEL_VC_PRE0 1      /* fine-level first smoothing step fused with the residual */
+#define OCP_KERNEL_VC_POST0 2     /* fine-level last post-smoothing pass with r.z */
 #define OCP_KERNEL_VC_RESTRICT0 3 /* fine-level restriction R r */
-#define OCP_KERNEL_VC_PROLONG0 4  /* fine-level prolongation D^-1 b + P e */
+#define OCP_KERNEL_VC_PROLONG0 4  /* fine-level prolongation D^-1 (...) + P e */
+#define OCP_KERNEL_VC_PRE0_B 5    /* fine-level second pre-smoothing pass (degree 2) */
+#define OCP_KERNEL_VC_POST0_A 6   /* fine-level first post-smoothing residual (degree 2) */
 
 /* Live timing of selected kernels with HIP events on the context stream.
  * ocp_profile_enable(ctx, 1) clears the counters and brackets every launch of

@@ -23,6 +23,8 @@ definition per function, so that the GPU setup can be compared with it:
   lambda       max_i sum_j |a_ij| / a_ii   (Gershgorin bound of D^-1 A)
   P            (I - (omega/lambda) D^-1 A) P_tent
   A_c          P^T A P
+  levels       stop at n <= coarse_max, at max_levels, or where the
+               aggregation leaves more than half of the nodes
 The sparse products use scipy.sparse (a library primitive).  Only for small
 problems: the loops are plain Python.
 """
@@ -128,7 +130,7 @@ def smoothed_prolongator(A: sp.csr_matrix, Pt: sp.csr_matrix, omega: float) -> s
     return (S @ Pt).tocsr()
 
 
-def build_hierarchy(A: sp.csr_matrix, theta: float = 0.08, omega: float = 4.0 / 3.0,
+def build_hierarchy(A: sp.csr_matrix, theta: float = 0.0, omega: float = 4.0 / 3.0,
                     coarse_max: int = 512, max_levels: int = 10):
     """Levels as dicts {A, agg, P, nc}; the last has only A."""
     levels = []
@@ -142,7 +144,7 @@ def build_hierarchy(A: sp.csr_matrix, theta: float = 0.08, omega: float = 4.0 / 
         nbrs = strong_neighbours(A, theta)
         root = greedy_mis2(nbrs, salt)
         agg, nc = aggregate(nbrs, root, salt)
-        if nc <= 0 or nc >= n:
+        if nc <= 0 or 2 * nc > n:
             levels.append({"A": A})
             break
         Pt = tentative_prolongator(agg, nc)

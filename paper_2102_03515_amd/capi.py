@@ -55,7 +55,7 @@ class _SystemView(C.Structure):
 class _AmgParams(C.Structure):
     _fields_ = [("precision", C.c_int32), ("smoother", C.c_int32), ("degree", C.c_int32),
                 ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("theta", C.c_double),
-                ("omega", C.c_double)]
+                ("omega", C.c_double), ("cheb_ratio", C.c_double)]
 
 
 class _LevelView(C.Structure):
@@ -103,7 +103,8 @@ _SIGS = {
     "ocp_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
 }
 
-KERNEL_CG_SPMV, KERNEL_VC_PRE0, KERNEL_VC_POST0, KERNEL_VC_RESTRICT0, KERNEL_VC_PROLONG0 = 0, 1, 2, 3, 4
+(KERNEL_CG_SPMV, KERNEL_VC_PRE0, KERNEL_VC_POST0, KERNEL_VC_RESTRICT0, KERNEL_VC_PROLONG0, KERNEL_VC_PRE0_B,
+ KERNEL_VC_POST0_A) = range(7)
 
 _lib = None
 

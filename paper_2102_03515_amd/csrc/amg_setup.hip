@@ -72,6 +72,11 @@ __global__ void k_level_diag(int32_t n, const int32_t *__restrict__ rp, const in
     gersh[i] = s / d;
 }
 
+__global__ void k_recip(int32_t n, const double *__restrict__ a, double *__restrict__ b) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = 1.0 / a[i];
+}
+
 __global__ void k_strength(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                            const double *__restrict__ val, const double *__restrict__ diag, double theta,
                            uint8_t *__restrict__ strong) {
@@ -512,16 +517,32 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
         Level &L = *h->levels.back();
         const int32_t n = L.n;
         L.gA = level_lanes(L.nnzA, n);
-        DevBuf<double> diag(ctx, n), gersh(ctx, n);
-        L.dinv.reset(ctx, n);
+        DevBuf<double> diag(ctx, n), gersh(ctx, n), dl1(ctx, n);
         fill_zero_bytes(ctx, ctx->dev_flag, 4);
-        k_level_diag<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, L.A_val, diag.get(), L.dinv.get(),
+        k_level_diag<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, L.A_val, diag.get(), dl1.get(),
                                                       gersh.get(), ctx->dev_flag);
         OCP_LAUNCH_CHECK();
         int32_t fl = 0;
         read_back(ctx, &fl, ctx->dev_flag, 4);
         if (fl & 8) fail(OCP_ERR_INVALID_ARG, "matrix has a non-positive diagonal entry");
         L.lambda_max = reduce_max_abs(ctx, gersh.get(), n);
+        // smoother diagonal and polynomial coefficients
+        if (pr.smoother == OCP_SMOOTH_CHEBYSHEV) {
+            L.dinv.reset(ctx, n);
+            k_recip<<<grid_for(n, 256), 256, 0, s>>>(n, diag.get(), L.dinv.get());
+            OCP_LAUNCH_CHECK();
+            const double lmax = L.lambda_max, lmin = lmax / pr.cheb_ratio;
+            const double th = 0.5 * (lmax + lmin), de = 0.5 * (lmax - lmin);
+            const double sg = th / de, r1 = 1.0 / sg, r2 = 1.0 / (2.0 * sg - r1);
+            L.deg = pr.degree;
+            L.cheb_a = 1.0 / th;
+            L.cheb_c1 = (1.0 + r2 * r1) / th;
+            L.cheb_c2 = 2.0 * r2 / de;
+        } else {
+            L.dinv = std::move(dl1);
+            L.deg = 1;
+            L.cheb_a = 1.0;
+        }
 
         const bool last = (n <= pr.coarse_max) || (lev + 1 >= pr.max_levels);
         int32_t nc = 0;
@@ -562,7 +583,8 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
             read_back(ctx, &fl, ctx->dev_flag, 4);
             if (fl & 16) fail(OCP_ERR_HIP, "aggregation left a node unassigned");
         }
-        if (last || nc <= 0 || nc >= n) {
+        // stop where aggregation no longer halves the level
+        if (last || nc <= 0 || 2 * (int64_t)nc > n) {
             // last level: dense inverse (or Jacobi when too large)
             L.agg.release();
             if (n <= kDenseMax) {
@@ -634,6 +656,7 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
             if (L.dense_inv.get()) to_float(ctx, L.dense_inv.get(), L.dense_inv32, (int64_t)L.n * L.n);
         }
         L.vr.reset(ctx, es * L.n);
+        L.vr2.reset(ctx, es * L.n);
         L.vxp.reset(ctx, es * L.n);
         if (l > 0) {
             L.vb.reset(ctx, es * L.n);
@@ -650,12 +673,13 @@ using namespace ocp;
 extern "C" void amg_default_params(ocp_amg_params *p) {
     if (!p) return;
     p->precision = OCP_PREC_FP64;
-    p->smoother = OCP_SMOOTH_L1JACOBI;
+    p->smoother = OCP_SMOOTH_CHEBYSHEV;
     p->degree = 2;
     p->coarse_max = 512;
     p->max_levels = 10;
-    p->theta = 0.08;
+    p->theta = 0.0;
     p->omega = 4.0 / 3.0;
+    p->cheb_ratio = 10.0;
 }
 
 extern "C" int amg_setup(ocp_ctx *ctx, const ocp_system *sys, const ocp_amg_params *params, ocp_hierarchy **out) {
@@ -673,7 +697,12 @@ extern "C" int amg_setup(ocp_ctx *ctx, const ocp_system *sys, const ocp_amg_para
             amg_default_params(&h->params);
         const ocp_amg_params &p = h->params;
         if (p.precision != OCP_PREC_FP64 && p.precision != OCP_PREC_MIXED) fail(OCP_ERR_INVALID_ARG, "bad precision");
-        if (p.smoother != OCP_SMOOTH_L1JACOBI) fail(OCP_ERR_UNSUPPORTED, "only the L1-Jacobi smoother is available");
+        if (p.smoother != OCP_SMOOTH_L1JACOBI && p.smoother != OCP_SMOOTH_CHEBYSHEV)
+            fail(OCP_ERR_INVALID_ARG, "unknown smoother");
+        if (p.smoother == OCP_SMOOTH_CHEBYSHEV && (p.degree < 1 || p.degree > 2))
+            fail(OCP_ERR_UNSUPPORTED, "Chebyshev degree must be 1 or 2");
+        if (p.smoother == OCP_SMOOTH_CHEBYSHEV && !(p.cheb_ratio > 1.0))
+            fail(OCP_ERR_INVALID_ARG, "cheb_ratio must exceed 1");
         if (p.coarse_max < 1 || p.coarse_max > kDenseMax) fail(OCP_ERR_INVALID_ARG, "coarse_max must be in 1..2048");
         if (p.max_levels < 1 || p.max_levels > 16) fail(OCP_ERR_INVALID_ARG, "max_levels must be in 1..16");
         if (!(p.theta >= 0.0) || !(p.omega > 0.0)) fail(OCP_ERR_INVALID_ARG, "theta >= 0 and omega > 0 required");

@@ -34,13 +34,17 @@ struct Level {
     DevBuf<double> own_val;
     DevBuf<int32_t> P_rp, P_col, R_rp, R_col, agg;
     DevBuf<double> P_val, R_val;
-    DevBuf<double> dinv;       // smoother diagonal inverse (L1-Jacobi: 1/(sum_j |a_ij|))
+    DevBuf<double> dinv;       // smoother diagonal: 1/a_ii (Chebyshev) or 1/sum_j |a_ij| (L1-Jacobi)
     DevBuf<double> dense_inv;  // last level only: A^{-1}, dense row-major
     // single-precision copies (mixed precision)
     DevBuf<float> A_val32, P_val32, R_val32, dinv32, dense_inv32;
     // V-cycle work vectors in the hierarchy's precision (bytes)
-    DevBuf<char> vb, vr, vx, vxp;
+    DevBuf<char> vb, vr, vr2, vx, vxp;
     double lambda_max = 0.0;   // Gershgorin bound of D^-1 A
+    // polynomial smoother: first step x = a D^-1 r; degree 2 adds
+    // x = D^-1 (c1 r0 + c2 r1) with r1 the residual after the first step
+    int deg = 1;
+    double cheb_a = 1.0, cheb_c1 = 0.0, cheb_c2 = 0.0;
     int gA = 16, gP = 4, gR = 64;  // lanes per row of the A, P and R kernels
 };
 

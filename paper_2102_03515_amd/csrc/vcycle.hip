@@ -2,18 +2,22 @@
 // initial guess (Section 4.1: pre-smoothing, restriction with P^T, recursive
 // coarse correction with zero start, prolongation with P, post-smoothing).
 //
-// The smoother is L1-Jacobi, S = I - D1^{-1} A with D1_ii = sum_j |a_ij|; it
-// is symmetric, so pre- and post-smoothing are adjoint and B is SPD.  With a
-// zero initial guess the pre-smoothed iterate is x = D1^{-1} b, so the
-// pre-smoother and the residual r = b - A D1^{-1} b form one pass over A that
-// recomputes the neighbours' x on the fly; x itself is never stored.  The
-// prolongation rebuilds it, xp = D1^{-1} b + P e, and the post-smoother
-// x = xp + D1^{-1}(b - A xp) is the second pass over A.  On the fine level the
-// post-smoother also forms r.z for CG.
+// The smoother is a polynomial in D^-1 A: Chebyshev of degree 1 or 2 on
+// [lambda/ratio, lambda] (lambda a Gershgorin bound of D^-1 A, D = diag A), or
+// L1-Jacobi (degree 1, D_ii = sum_j |a_ij|).  Pre- and post-smoothing apply the
+// same polynomial, which is self-adjoint in the A inner product, so B is SPD.
+// From a zero initial guess the smoothed iterate is a combination of vectors
+// already in memory (x1 = a D^-1 b; x2 = D^-1 (c1 b + c2 r1) for degree 2), so
+// each smoothing step and the following residual form one pass over A that
+// rebuilds the neighbours' iterate on the fly; the iterate itself is never
+// stored.  The prolongation rebuilds it once more and adds P e; post-smoothing
+// takes one pass per degree.  On the fine level the last pass also forms r.z
+// for CG.
 //
 // Values are double (FP64 hierarchy) or float (mixed precision); the CG
 // vectors entering and leaving the cycle are always double.
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.h"
 #include "system.h"
@@ -41,17 +45,51 @@ namespace ocp {
     }                  \
     }
 
-// r = b - A (d .* b)
-template <int G, typename T, typename BT>
-__global__ void __launch_bounds__(kBlock) k_vc_pre(int32_t n, int iters, const int32_t *__restrict__ rp,
+// Residual with the iterate formed on the fly from vectors already in memory:
+//   x_j = [X0_j] + d_j (alpha u_j [+ beta v_j]),   r_i = b_i - sum_j a_ij x_j
+// MODE 0 writes r; MODE 1 writes z_i = [X0_i] + d_i (e1 u_i + e2 r_i) (and with
+// DOT also accumulates b.z for CG).  Every smoothing step of the V-cycle is
+// one instance of this kernel, i.e. one pass over the level matrix.
+template <int G, typename T, typename BT, typename UT, typename OT, bool HX0, bool HU, bool HV, int MODE, bool DOT>
+__global__ void __launch_bounds__(kBlock) k_smooth(int32_t n, int iters, const int32_t *__restrict__ rp,
                                                    const int32_t *__restrict__ col, const T *__restrict__ val,
                                                    const T *__restrict__ d, const BT *__restrict__ b,
-                                                   T *__restrict__ r, const CgScalars *cg) {
+                                                   const T *__restrict__ x0, const UT *__restrict__ u,
+                                                   const T *__restrict__ v, T alpha, T beta, T e1, T e2,
+                                                   OT *__restrict__ out, CgScalars *cg, double *partials,
+                                                   unsigned *counter) {
     if (cg && cg->flag) return;
+    double acc = 0.0;
     OCP_ROWS_BEGIN(G)
-    const T s = dev::row_sum<G>(rp[row], rp[row + 1], lane, col, val, [&](int c) { return d[c] * (T)b[c]; });
-    if (lane == 0) r[row] = (T)b[row] - s;
+    const T s = dev::row_sum<G>(rp[row], rp[row + 1], lane, col, val, [&](int c) {
+        T x = HX0 ? x0[c] : T(0);
+        if (HU) {
+            T w = alpha * (T)u[c];
+            if (HV) w += beta * v[c];
+            x += d[c] * w;
+        }
+        return x;
+    });
+    if (lane == 0) {
+        const BT bi = b[row];
+        const T r = (T)bi - s;
+        if (MODE == 0) {
+            out[row] = (OT)r;
+        } else {
+            T w = e2 * r;
+            if (HU) w += e1 * (T)u[row];
+            const T z = (HX0 ? x0[row] : T(0)) + d[row] * w;
+            out[row] = (OT)z;
+            if (DOT) acc += (double)bi * (double)z;
+        }
+    }
     OCP_ROWS_END()
+    if (DOT) {
+        acc = dev::block_sum<kBlock>(acc);
+        double tot;
+        if (dev::grid_sum_last<kBlock>(acc, partials, counter, &tot) && threadIdx.x == 0)
+            dev::cg_after_precond(cg, tot);
+    }
 }
 
 // y = M x for a level matrix (restriction with R = P^T)
@@ -67,44 +105,24 @@ __global__ void __launch_bounds__(kBlock) k_vc_spmv(int32_t n, int iters, const 
     OCP_ROWS_END()
 }
 
-// xp = d .* b + P xc
-template <int G, typename T, typename BT>
+// xp = d .* (alpha b [+ beta v]) + P xc: the pre-smoothed iterate rebuilt from
+// the vectors that defined it, plus the coarse-grid correction
+template <int G, typename T, typename BT, bool HV>
 __global__ void __launch_bounds__(kBlock) k_vc_prolong(int32_t n, int iters, const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ col, const T *__restrict__ val,
                                                        const T *__restrict__ d, const BT *__restrict__ b,
+                                                       const T *__restrict__ v, T alpha, T beta,
                                                        const T *__restrict__ xc, T *__restrict__ xp,
                                                        const CgScalars *cg) {
     if (cg && cg->flag) return;
     OCP_ROWS_BEGIN(G)
     const T s = dev::row_sum<G>(rp[row], rp[row + 1], lane, col, val, [&](int c) { return xc[c]; });
-    if (lane == 0) xp[row] = d[row] * (T)b[row] + s;
-    OCP_ROWS_END()
-}
-
-// z = xp + d .* (b - A xp); with DOT also r.z -> CG scalars
-template <int G, typename T, typename BT, typename ZT, bool DOT>
-__global__ void __launch_bounds__(kBlock) k_vc_post(int32_t n, int iters, const int32_t *__restrict__ rp,
-                                                    const int32_t *__restrict__ col, const T *__restrict__ val,
-                                                    const T *__restrict__ d, const BT *__restrict__ b,
-                                                    const T *__restrict__ xp, ZT *__restrict__ z, CgScalars *cg,
-                                                    double *partials, unsigned *counter) {
-    if (cg && cg->flag) return;
-    double acc = 0.0;
-    OCP_ROWS_BEGIN(G)
-    const T s = dev::row_sum<G>(rp[row], rp[row + 1], lane, col, val, [&](int c) { return xp[c]; });
     if (lane == 0) {
-        const BT bi = b[row];
-        const T zi = xp[row] + d[row] * ((T)bi - s);
-        z[row] = (ZT)zi;
-        if (DOT) acc += (double)bi * (double)zi;
+        T w = alpha * (T)b[row];
+        if (HV) w += beta * v[row];
+        xp[row] = d[row] * w + s;
     }
     OCP_ROWS_END()
-    if (DOT) {
-        acc = dev::block_sum<kBlock>(acc);
-        double tot;
-        if (dev::grid_sum_last<kBlock>(acc, partials, counter, &tot) && threadIdx.x == 0)
-            dev::cg_after_precond(cg, tot);
-    }
 }
 
 // x = Ainv b on the last level (dense, one wavefront per row)
@@ -178,6 +196,7 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
     hipStream_t s = ctx->stream;
     double *part = ctx->red_partials + 3 * kRedBlocks;
     unsigned *cnt = ctx->red_counters + 3;
+    const T zero = T(0);
 
     if (L == 1) {
         const Level &l0 = *lv[0];
@@ -195,31 +214,45 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
         return;
     }
 
-    // ---- down
-    for (int l = 0; l < L - 1; ++l) {
+    // ---- down: pre-smoothing from zero, residual, restriction
+    auto down = [&](int l, auto bptr) {
+        using BT = std::remove_const_t<std::remove_pointer_t<decltype(bptr)>>;
         const Level &cur = *lv[l];
         const Level &nxt = *lv[l + 1];
         const auto a = arrays<T>(cur);
-        T *r = reinterpret_cast<T *>(cur.vr.get());
+        T *r1 = reinterpret_cast<T *>(cur.vr.get());
+        T *r2 = reinterpret_cast<T *>(cur.vr2.get());
         const RowLaunch LA = row_launch(cur.n, cur.gA);
-        if (l == 0) {
-            const int pr = cg ? prof_begin(ctx, OCP_KERNEL_VC_PRE0) : -1;
-            OCP_DISPATCH_G(cur.gA, (k_vc_pre<G, T, double><<<LA.blocks, kBlock, 0, s>>>(
-                                       cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, r_in, r, cg)));
-            prof_end(ctx, pr);
-        } else {
-            const T *b = reinterpret_cast<const T *>(cur.vb.get());
-            OCP_DISPATCH_G(cur.gA, (k_vc_pre<G, T, T><<<LA.blocks, kBlock, 0, s>>>(cur.n, LA.iters, cur.A_rp,
-                                                                                    cur.A_col, a.A, a.d, b, r, cg)));
-        }
+        const T ca = (T)cur.cheb_a, c1 = (T)cur.cheb_c1, c2 = (T)cur.cheb_c2;
+        const int pr = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_PRE0) : -1;
+        OCP_DISPATCH_G(cur.gA, (k_smooth<G, T, BT, BT, T, false, true, false, 0, false><<<LA.blocks, kBlock, 0, s>>>(
+                                   cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, bptr, nullptr, bptr, nullptr, ca,
+                                   zero, zero, zero, r1, cg, nullptr, nullptr)));
+        prof_end(ctx, pr);
         OCP_LAUNCH_CHECK();
+        const T *rr = r1;
+        if (cur.deg == 2) {
+            const int pr2 = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_PRE0_B) : -1;
+            OCP_DISPATCH_G(cur.gA, (k_smooth<G, T, BT, BT, T, false, true, true, 0, false><<<LA.blocks, kBlock, 0, s>>>(
+                                       cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, bptr, nullptr, bptr, r1, c1, c2,
+                                       zero, zero, r2, cg, nullptr, nullptr)));
+            prof_end(ctx, pr2);
+            OCP_LAUNCH_CHECK();
+            rr = r2;
+        }
         T *bn = reinterpret_cast<T *>(nxt.vb.get());
         const RowLaunch LR = row_launch(nxt.n, cur.gR);
         const int prr = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_RESTRICT0) : -1;
         OCP_DISPATCH_G(cur.gR, (k_vc_spmv<G, T><<<LR.blocks, kBlock, 0, s>>>(nxt.n, LR.iters, cur.R_rp.get(),
-                                                                              cur.R_col.get(), a.R, r, bn, cg)));
+                                                                              cur.R_col.get(), a.R, rr, bn, cg)));
         prof_end(ctx, prr);
         OCP_LAUNCH_CHECK();
+    };
+    for (int l = 0; l < L - 1; ++l) {
+        if (l == 0)
+            down(0, r_in);
+        else
+            down(l, reinterpret_cast<const T *>(lv[l]->vb.get()));
     }
     // ---- coarsest
     {
@@ -233,43 +266,72 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
             k_vc_diag<T, T, T><<<grid_for(cl.n, 256), 256, 0, s>>>(cl.n, a.d, b, x, cg);
         OCP_LAUNCH_CHECK();
     }
-    // ---- up
-    for (int l = L - 2; l >= 0; --l) {
+    // ---- up: prolongation + correction, post-smoothing
+    auto up = [&](int l, auto bptr, auto outptr, bool dot) {
+        using BT = std::remove_const_t<std::remove_pointer_t<decltype(bptr)>>;
+        using OT = std::remove_pointer_t<decltype(outptr)>;
         const Level &cur = *lv[l];
         const Level &nxt = *lv[l + 1];
         const auto a = arrays<T>(cur);
         const T *xc = reinterpret_cast<const T *>(nxt.vx.get());
         T *xp = reinterpret_cast<T *>(cur.vxp.get());
+        T *r1 = reinterpret_cast<T *>(cur.vr.get());
+        T *r0 = reinterpret_cast<T *>(cur.vr2.get());
+        const T ca = (T)cur.cheb_a, c1 = (T)cur.cheb_c1, c2 = (T)cur.cheb_c2;
         const RowLaunch LP = row_launch(cur.n, cur.gP);
         const RowLaunch LA = row_launch(cur.n, cur.gA);
-        if (l == 0) {
-            const int prp = cg ? prof_begin(ctx, OCP_KERNEL_VC_PROLONG0) : -1;
-            OCP_DISPATCH_G(cur.gP, (k_vc_prolong<G, T, double><<<LP.blocks, kBlock, 0, s>>>(
-                                       cur.n, LP.iters, cur.P_rp.get(), cur.P_col.get(), a.P, a.d, r_in, xc, xp, cg)));
-            prof_end(ctx, prp);
+        const int prp = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_PROLONG0) : -1;
+        if (cur.deg == 2) {
+            OCP_DISPATCH_G(cur.gP, (k_vc_prolong<G, T, BT, true><<<LP.blocks, kBlock, 0, s>>>(
+                                       cur.n, LP.iters, cur.P_rp.get(), cur.P_col.get(), a.P, a.d, bptr, r1, c1, c2,
+                                       xc, xp, cg)));
+        } else {
+            OCP_DISPATCH_G(cur.gP, (k_vc_prolong<G, T, BT, false><<<LP.blocks, kBlock, 0, s>>>(
+                                       cur.n, LP.iters, cur.P_rp.get(), cur.P_col.get(), a.P, a.d, bptr, nullptr, ca,
+                                       zero, xc, xp, cg)));
+        }
+        prof_end(ctx, prp);
+        OCP_LAUNCH_CHECK();
+        int pro = -1;
+        if (cur.deg == 2) {
+            // r0 = b - A xp, then z = xp + D^-1 (c1 r0 + c2 r1) with r1 = b - A (xp + a D^-1 r0)
+            const int pra = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_POST0_A) : -1;
+            OCP_DISPATCH_G(cur.gA, (k_smooth<G, T, BT, T, T, true, false, false, 0, false><<<LA.blocks, kBlock, 0, s>>>(
+                                       cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, bptr, xp, nullptr, nullptr,
+                                       zero, zero, zero, zero, r0, cg, nullptr, nullptr)));
+            prof_end(ctx, pra);
             OCP_LAUNCH_CHECK();
-            if (cg) {
-                const int pro = prof_begin(ctx, OCP_KERNEL_VC_POST0);
-                OCP_DISPATCH_G(cur.gA, (k_vc_post<G, T, double, double, true><<<LA.blocks, kBlock, 0, s>>>(
-                                           cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, r_in, xp, z_out, cg, part,
-                                           cnt)));
-                prof_end(ctx, pro);
+            pro = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_POST0) : -1;
+            if (dot) {
+                OCP_DISPATCH_G(cur.gA, (k_smooth<G, T, BT, T, OT, true, true, false, 1, true><<<LA.blocks, kBlock, 0, s>>>(
+                                           cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, bptr, xp, r0, nullptr, ca,
+                                           zero, c1, c2, outptr, cg, part, cnt)));
             } else {
-                OCP_DISPATCH_G(cur.gA, (k_vc_post<G, T, double, double, false><<<LA.blocks, kBlock, 0, s>>>(
-                                           cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, r_in, xp, z_out, nullptr,
-                                           nullptr, nullptr)));
+                OCP_DISPATCH_G(cur.gA, (k_smooth<G, T, BT, T, OT, true, true, false, 1, false><<<LA.blocks, kBlock, 0, s>>>(
+                                           cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, bptr, xp, r0, nullptr, ca,
+                                           zero, c1, c2, outptr, cg, nullptr, nullptr)));
             }
         } else {
-            const T *b = reinterpret_cast<const T *>(cur.vb.get());
-            T *x = reinterpret_cast<T *>(cur.vx.get());
-            OCP_DISPATCH_G(cur.gP, (k_vc_prolong<G, T, T><<<LP.blocks, kBlock, 0, s>>>(
-                                       cur.n, LP.iters, cur.P_rp.get(), cur.P_col.get(), a.P, a.d, b, xc, xp, cg)));
-            OCP_LAUNCH_CHECK();
-            OCP_DISPATCH_G(cur.gA, (k_vc_post<G, T, T, T, false><<<LA.blocks, kBlock, 0, s>>>(
-                                       cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, b, xp, x, cg, nullptr,
-                                       nullptr)));
+            // z = xp + a D^-1 (b - A xp)
+            pro = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_POST0) : -1;
+            if (dot) {
+                OCP_DISPATCH_G(cur.gA, (k_smooth<G, T, BT, T, OT, true, false, false, 1, true><<<LA.blocks, kBlock, 0, s>>>(
+                                           cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, bptr, xp, nullptr, nullptr,
+                                           zero, zero, zero, ca, outptr, cg, part, cnt)));
+            } else {
+                OCP_DISPATCH_G(cur.gA, (k_smooth<G, T, BT, T, OT, true, false, false, 1, false><<<LA.blocks, kBlock, 0, s>>>(
+                                           cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, bptr, xp, nullptr, nullptr,
+                                           zero, zero, zero, ca, outptr, cg, nullptr, nullptr)));
+            }
         }
+        prof_end(ctx, pro);
         OCP_LAUNCH_CHECK();
+    };
+    for (int l = L - 2; l >= 0; --l) {
+        if (l == 0)
+            up(0, r_in, z_out, cg != nullptr);
+        else
+            up(l, reinterpret_cast<const T *>(lv[l]->vb.get()), reinterpret_cast<T *>(lv[l]->vx.get()), false);
     }
 }
 

@@ -62,7 +62,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(capi._Mesh) == 4 + 4 + 3 * 8
     assert ctypes.sizeof(capi._Target) == 4 + 4 + 8 + 8 + 8 + 48 + 8
     assert ctypes.sizeof(capi.SolveInfo) == 8 + 4 * 8
-    assert ctypes.sizeof(capi._AmgParams) == 5 * 4 + 4 + 2 * 8
+    assert ctypes.sizeof(capi._AmgParams) == 5 * 4 + 4 + 3 * 8
 
 
 def test_package_has_no_cpu_fallback():

@@ -175,12 +175,13 @@ def test_amg_pcg_mixed_reaches_tolerance(P, ctx, N, jit, rho, tgt):
     assert err < 1e-6
 
 
-def test_vcycle_is_symmetric_positive(P, ctx):
+@pytest.mark.parametrize("smoother,degree", [(0, 1), (1, 1), (1, 2)])
+def test_vcycle_is_symmetric_positive(P, ctx, smoother, degree):
     import torch
-    print("[vcycle spd] cube20 jitter", flush=True)
+    print(f"[vcycle spd] cube20 jitter smoother={smoother} degree={degree}", flush=True)
     mesh = I.kuhn_mesh(20, jitter=0.15, seed=17)
     s, _ = _gpu_system(P, ctx, mesh, 1.0 / 400, I.single_sine())
-    h = P.amg_setup(ctx, s, coarse_max=64)
+    h = P.amg_setup(ctx, s, coarse_max=64, smoother=smoother, degree=degree)
     rng = np.random.default_rng(1)
     n = s.n
     for _ in range(3):
@@ -194,20 +195,20 @@ def test_vcycle_is_symmetric_positive(P, ctx):
         assert float(torch.dot(bx, x)) > 0
 
 
-def test_hierarchy_matches_oracle_definitions(P, ctx):
+@pytest.mark.parametrize("theta,N,jit", [(0.0, 14, 0.15), (0.08, 14, 0.0), (0.0, 24, 0.0)])
+def test_hierarchy_matches_oracle_definitions(P, ctx, theta, N, jit):
     """Aggregates bit-exact against the greedy definition; P, R = P^T and
     A_c = P^T A P within rounding."""
     import scipy.sparse as sp
-    print("[amg setup] cube14 rho=h^2", flush=True)
-    N = 14
+    print(f"[amg setup] cube{N} jitter={jit} theta={theta} rho=h^2", flush=True)
     rho = 1.0 / N ** 2
-    mesh = I.kuhn_mesh(N, jitter=0.0)
+    mesh = I.kuhn_mesh(N, jitter=jit, seed=3)
     s, _ = _gpu_system(P, ctx, mesh, rho, I.single_sine())
-    h = P.amg_setup(ctx, s, coarse_max=32)
+    h = P.amg_setup(ctx, s, coarse_max=32, theta=theta)
     o = O.assemble(mesh, rho, I.single_sine())
     A0 = o.csr()
-    assert OA.strength_margin(A0, 0.08) > 1e-6
-    ol = OA.build_hierarchy(A0, theta=0.08, coarse_max=32)
+    assert OA.strength_margin(A0, theta) > 1e-6
+    ol = OA.build_hierarchy(A0, theta=theta, coarse_max=32)
     assert len(ol) == h.n_levels
     for lev in range(h.n_levels - 1):
         g = h.level_arrays(lev)

@@ -91,39 +91,73 @@ __global__ void k_strength(int32_t n, const int32_t *__restrict__ rp, const int3
 }
 
 // ------------------------------------------------------------------- MIS-2
-__global__ void k_mis_m1(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                         const uint8_t *__restrict__ strong, const int8_t *__restrict__ state, uint32_t salt,
-                         uint64_t *__restrict__ m1) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Round of the distance-2 independent set, G lanes per row:
+//   m1[i] = max key over i and its strong neighbours
+//   m2    = max m1 over i and its strong neighbours; an undecided i joins
+//           if m2 is its own key and leaves if m2 belongs to a joined node.
+template <int G>
+__device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        const uint64_t w = __shfl_xor(v, o, G);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_mis_m1(int32_t n, const int32_t *__restrict__ rp,
+                                                const int32_t *__restrict__ col, const uint8_t *__restrict__ strong,
+                                                const int8_t *__restrict__ state, uint32_t salt,
+                                                uint64_t *__restrict__ m1) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / G), lane = (int)(t % G);
     if (i >= n) return;
-    uint64_t m = mis_key(i, state[i], salt);
-    for (int k = rp[i]; k < rp[i + 1]; ++k)
+    uint64_t m = 0;
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += G)
         if (strong[k]) {
             const int j = col[k];
             const uint64_t kj = mis_key(j, state[j], salt);
             m = kj > m ? kj : m;
         }
-    m1[i] = m;
+    m = group_max_u64<G>(m);
+    if (lane == 0) {
+        const uint64_t ki = mis_key(i, state[i], salt);
+        m1[i] = ki > m ? ki : m;
+    }
 }
 
-__global__ void k_mis_m2(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                         const uint8_t *__restrict__ strong, int8_t *__restrict__ state, uint32_t salt,
-                         const uint64_t *__restrict__ m1, int32_t *undecided) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+template <int G>
+__global__ void __launch_bounds__(256) k_mis_m2(int32_t n, const int32_t *__restrict__ rp,
+                                                const int32_t *__restrict__ col, const uint8_t *__restrict__ strong,
+                                                int8_t *__restrict__ state, uint32_t salt,
+                                                const uint64_t *__restrict__ m1, int32_t *undecided) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / G), lane = (int)(t % G);
     if (i >= n) return;
-    if (state[i] != 0) return;
-    uint64_t m = m1[i];
-    for (int k = rp[i]; k < rp[i + 1]; ++k)
+    if (state[i] != 0) return;   // uniform over the group
+    uint64_t m = 0;
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += G)
         if (strong[k]) {
             const uint64_t v = m1[col[k]];
             m = v > m ? v : m;
         }
-    if (m == mis_key(i, 0, salt))
-        state[i] = 1;
-    else if ((m >> 62) == 3u)
-        state[i] = 2;
-    else
-        atomicAdd(undecided, 1);
+    m = group_max_u64<G>(m);
+    bool still = false;
+    if (lane == 0) {
+        const uint64_t mi = m1[i];
+        m = mi > m ? mi : m;
+        if (m == mis_key(i, 0, salt))
+            state[i] = 1;
+        else if ((m >> 62) == 3u)
+            state[i] = 2;
+        else
+            still = true;
+    }
+    // "some node is still undecided": every writer stores the same value, so
+    // one plain store per wavefront suffices (no contended atomic)
+    const unsigned long long any = __ballot(still);
+    if (any != 0ull && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)any) - 1)) *undecided = 1;
 }
 
 __global__ void k_root_flags(int32_t n, const int8_t *__restrict__ state, int32_t *__restrict__ fl) {
@@ -215,11 +249,21 @@ __global__ void k_smooth_p(int32_t n, const int32_t *__restrict__ rp, const int3
 }
 
 // ------------------------------------------------------------------ SpGEMM
-// C = A B, row by row.  Each row's distinct columns go into an LDS hash
-// table; values are accumulated per slot over the entries of the A row in
-// ascending order (at each step the lanes hold distinct columns of one B row,
-// so no two lanes touch one slot), then the columns are ranked and written in
-// ascending order.
+// C = A B, row by row.  A group of G lanes owns one output row and an LDS
+// hash table of H slots (G and H chosen per row from the bound
+// ub_i = sum_k nnz(B row k) over the entries of A row i).  The group walks
+// the entries of its A row in ascending order; at each step its lanes take
+// distinct columns of one B row, so no two lanes touch one slot and every
+// output entry is accumulated in the fixed order of the A row.  Finally the
+// occupied slots are ranked by column and written in ascending order.  The
+// lanes of a group live in one wavefront; their LDS accesses are ordered with
+// wavefront-scope fences instead of workgroup barriers.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ void k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp, const int32_t *__restrict__ acol,
                             const int32_t *__restrict__ brp, int32_t *__restrict__ ub) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -232,24 +276,38 @@ __global__ void k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp, const in
     ub[i] = (int32_t)(s > INT32_MAX ? INT32_MAX : s);
 }
 
-__global__ void k_bin_rows(int32_t m, const int32_t *__restrict__ ub, int32_t lim0, int32_t lim1,
-                           int32_t *__restrict__ counts, int32_t *__restrict__ lists) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    const int u = ub[i];
-    const int c = u <= lim0 ? 0 : (u <= lim1 ? 1 : 2);
-    const int pos = atomicAdd(&counts[c], 1);
-    lists[(int64_t)c * m + pos] = i;
-}
+constexpr int kSpgemmClasses = 5;
+__constant__ int c_class_ub[kSpgemmClasses - 1] = {16, 64, 256, 1024};
 
-template <int H>
-__device__ __forceinline__ int hash_slot(int key) {
-    return (int)(((uint32_t)key * 2654435761u) >> (32 - __builtin_ctz(H)));
+// Row lists per size class; one atomic per class per wavefront.
+__global__ void k_bin_rows(int32_t m, const int32_t *__restrict__ ub, int32_t *__restrict__ counts,
+                           int32_t *__restrict__ lists) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int c = kSpgemmClasses;
+    if (i < m) {
+        const int u = ub[i];
+        c = kSpgemmClasses - 1;
+        for (int q = 0; q < kSpgemmClasses - 1; ++q)
+            if (u <= c_class_ub[q]) {
+                c = q;
+                break;
+            }
+    }
+    for (int q = 0; q < kSpgemmClasses; ++q) {
+        const unsigned long long mask = __ballot(c == q);
+        if (mask == 0ull) continue;
+        const int leader = __ffsll((long long)mask) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&counts[q], __popcll(mask));
+        base = __shfl(base, leader, 64);
+        if (c == q) lists[(int64_t)q * m + base + __popcll(mask & ((1ull << lane) - 1ull))] = i;
+    }
 }
 
 template <int H>
 __device__ __forceinline__ int hash_insert(int *keys, int key, int *count) {
-    int s = hash_slot<H>(key);
+    int s = (int)(((uint32_t)key * 2654435761u) >> (32 - __builtin_ctz(H)));
     for (;;) {
         const int prev = atomicCAS(&keys[s], -1, key);
         if (prev == -1) {
@@ -261,79 +319,66 @@ __device__ __forceinline__ int hash_insert(int *keys, int key, int *count) {
     }
 }
 
-template <int H>
-__global__ void __launch_bounds__(64) k_spgemm_count(const int32_t *__restrict__ rows, int32_t nrows,
-                                                     const int32_t *__restrict__ arp, const int32_t *__restrict__ acol,
-                                                     const int32_t *__restrict__ brp, const int32_t *__restrict__ bcol,
-                                                     int32_t *__restrict__ cnt, int32_t *flag) {
-    __shared__ int keys[H];
-    __shared__ int count;
-    const int lane = threadIdx.x;
-    for (int r = blockIdx.x; r < nrows; r += gridDim.x) {
-        const int i = rows[r];
-        for (int s = lane; s < H; s += 64) keys[s] = -1;
-        if (lane == 0) count = 0;
-        __syncthreads();
-        for (int k = arp[i]; k < arp[i + 1]; ++k) {
-            const int c = acol[k];
-            for (int t = brp[c] + lane; t < brp[c + 1]; t += 64) {
-                if (*(volatile int *)&count > (3 * H) / 4) break;
-                hash_insert<H>(keys, bcol[t], &count);
-            }
-            __syncthreads();
-        }
-        if (lane == 0) {
-            cnt[i] = count;
-            if (count > (3 * H) / 4) atomicOr(flag, 32);
-        }
-        __syncthreads();
+// NUMERIC = false: cnt[i] = number of distinct columns of C row i.
+// NUMERIC = true : write C row i (columns ascending) at crp[i].
+template <int G, int H, bool NUMERIC>
+__global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ rows, int32_t nrows,
+                                                   const int32_t *__restrict__ arp, const int32_t *__restrict__ acol,
+                                                   const double *__restrict__ aval, const int32_t *__restrict__ brp,
+                                                   const int32_t *__restrict__ bcol, const double *__restrict__ bval,
+                                                   const int32_t *__restrict__ crp, int32_t *__restrict__ cnt,
+                                                   int32_t *__restrict__ ccol, double *__restrict__ cval,
+                                                   int32_t *flag) {
+    constexpr int RPW = 64 / G;
+    __shared__ int keys[RPW][H];
+    __shared__ double vals[NUMERIC ? RPW : 1][NUMERIC ? H : 1];
+    __shared__ int list[NUMERIC ? RPW : 1][NUMERIC ? H : 1];
+    __shared__ int count[RPW];
+    const int g = threadIdx.x / G, lane = threadIdx.x % G;
+    const int r = blockIdx.x * RPW + g;
+    const bool active = r < nrows;
+    const int i = active ? rows[r] : 0;
+    for (int q = lane; q < H; q += G) {
+        keys[g][q] = -1;
+        if (NUMERIC) vals[g][q] = 0.0;
     }
-}
-
-template <int H>
-__global__ void __launch_bounds__(64) k_spgemm_fill(const int32_t *__restrict__ rows, int32_t nrows,
-                                                    const int32_t *__restrict__ arp, const int32_t *__restrict__ acol,
-                                                    const double *__restrict__ aval, const int32_t *__restrict__ brp,
-                                                    const int32_t *__restrict__ bcol, const double *__restrict__ bval,
-                                                    const int32_t *__restrict__ crp, int32_t *__restrict__ ccol,
-                                                    double *__restrict__ cval) {
-    __shared__ int keys[H];
-    __shared__ double vals[H];
-    __shared__ int list[H];
-    __shared__ int count;
-    const int lane = threadIdx.x;
-    for (int r = blockIdx.x; r < nrows; r += gridDim.x) {
-        const int i = rows[r];
-        for (int s = lane; s < H; s += 64) {
-            keys[s] = -1;
-            vals[s] = 0.0;
-        }
-        if (lane == 0) count = 0;
-        __syncthreads();
-        for (int k = arp[i]; k < arp[i + 1]; ++k) {
+    if (lane == 0) count[g] = 0;
+    wave_sync();
+    if (active) {
+        const int ke = arp[i + 1];
+        for (int k = arp[i]; k < ke; ++k) {
             const int c = acol[k];
-            const double a = aval[k];
-            for (int t = brp[c] + lane; t < brp[c + 1]; t += 64) {
-                const int s = hash_insert<H>(keys, bcol[t], nullptr);
-                vals[s] += a * bval[t];
+            const double a = NUMERIC ? aval[k] : 0.0;
+            const int te = brp[c + 1];
+            for (int t = brp[c] + lane; t < te; t += G) {
+                if (!NUMERIC && *(volatile int *)&count[g] > (3 * H) / 4) break;
+                const int q = hash_insert<H>(keys[g], bcol[t], NUMERIC ? nullptr : &count[g]);
+                if (NUMERIC) vals[g][q] += a * bval[t];
             }
-            __syncthreads();
+            wave_sync();
         }
-        // compact occupied slots
-        for (int s = lane; s < H; s += 64)
-            if (keys[s] >= 0) list[atomicAdd(&count, 1)] = s;
-        __syncthreads();
-        const int nc = count;
-        const int base = crp[i];
-        for (int e = lane; e < nc; e += 64) {
-            const int se = list[e];
-            const int ke = keys[se];
-            int rank = 0;
-            for (int f = 0; f < nc; ++f) rank += keys[list[f]] < ke;
-            ccol[base + rank] = ke;
-            cval[base + rank] = vals[se];
+    }
+    if (!NUMERIC) {
+        if (active && lane == 0) {
+            cnt[i] = count[g];
+            if (count[g] > (3 * H) / 4) atomicOr(flag, 32);
         }
-        __syncthreads();
+        return;
+    }
+    // compact the occupied slots, rank them by column, write the row
+    for (int q = lane; q < H; q += G)
+        if (keys[g][q] >= 0) list[g][atomicAdd(&count[g], 1)] = q;
+    wave_sync();
+    if (!active) return;
+    const int nc = count[g];
+    const int base = crp[i];
+    for (int e = lane; e < nc; e += G) {
+        const int se = list[g][e];
+        const int kk = keys[g][se];
+        int rank = 0;
+        for (int f = 0; f < nc; ++f) rank += keys[g][list[g][f]] < kk;
+        ccol[base + rank] = kk;
+        cval[base + rank] = vals[g][se];
     }
 }
 
@@ -344,41 +389,63 @@ struct Csr {
     DevBuf<double> val;
 };
 
+template <int G, int H, bool NUMERIC>
+static void launch_grp(ocp_ctx *ctx, const int32_t *rows, int32_t nrows, const int32_t *arp, const int32_t *acol,
+                       const double *aval, const int32_t *brp, const int32_t *bcol, const double *bval,
+                       const int32_t *crp, int32_t *cnt, int32_t *ccol, double *cval) {
+    if (nrows <= 0) return;
+    constexpr int RPW = 64 / G;
+    const unsigned blocks = (unsigned)((nrows + RPW - 1) / RPW);
+    k_spgemm_grp<G, H, NUMERIC><<<blocks, 64, 0, ctx->stream>>>(rows, nrows, arp, acol, aval, brp, bcol, bval, crp,
+                                                                 cnt, ccol, cval, ctx->dev_flag);
+    OCP_LAUNCH_CHECK();
+}
+
+template <bool NUMERIC>
+static void spgemm_pass(ocp_ctx *ctx, const int32_t *lists, const int32_t *hc, int32_t m, const int32_t *arp,
+                        const int32_t *acol, const double *aval, const int32_t *brp, const int32_t *bcol,
+                        const double *bval, const int32_t *crp, int32_t *cnt, int32_t *ccol, double *cval) {
+    const int64_t M = m;
+    launch_grp<4, 32, NUMERIC>(ctx, lists, hc[0], arp, acol, aval, brp, bcol, bval, crp, cnt, ccol, cval);
+    launch_grp<8, 128, NUMERIC>(ctx, lists + M, hc[1], arp, acol, aval, brp, bcol, bval, crp, cnt, ccol, cval);
+    launch_grp<16, 512, NUMERIC>(ctx, lists + 2 * M, hc[2], arp, acol, aval, brp, bcol, bval, crp, cnt, ccol, cval);
+    launch_grp<64, 2048, NUMERIC>(ctx, lists + 3 * M, hc[3], arp, acol, aval, brp, bcol, bval, crp, cnt, ccol, cval);
+    launch_grp<64, 4096, NUMERIC>(ctx, lists + 4 * M, hc[4], arp, acol, aval, brp, bcol, bval, crp, cnt, ccol, cval);
+}
+
 static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, const int32_t *acol, const double *aval,
                    const int32_t *brp, const int32_t *bcol, const double *bval, Csr &C) {
     hipStream_t s = ctx->stream;
     DevBuf<int32_t> ub(ctx, (size_t)m + 1);
     k_spgemm_ub<<<grid_for(m, 256), 256, 0, s>>>(m, arp, acol, brp, ub.get());
     OCP_LAUNCH_CHECK();
-    DevBuf<int32_t> counts(ctx, 4);
-    fill_zero_bytes(ctx, counts.get(), 16);
-    DevBuf<int32_t> lists(ctx, (size_t)3 * m);
-    constexpr int H0 = 256, H1 = 1024, H2 = 2048;
-    k_bin_rows<<<grid_for(m, 256), 256, 0, s>>>(m, ub.get(), H0 / 2, H1 / 2, counts.get(), lists.get());
+    DevBuf<int32_t> counts(ctx, 8);
+    fill_zero_bytes(ctx, counts.get(), 32);
+    DevBuf<int32_t> lists(ctx, (size_t)kSpgemmClasses * m);
+    k_bin_rows<<<grid_for(m, 256), 256, 0, s>>>(m, ub.get(), counts.get(), lists.get());
     OCP_LAUNCH_CHECK();
-    int32_t hc[4];
-    read_back(ctx, hc, counts.get(), 16);
+    int32_t hc[8];
+    read_back(ctx, hc, counts.get(), 32);
     DevBuf<int32_t> cnt(ctx, (size_t)m + 1);
     fill_zero_bytes(ctx, ctx->dev_flag, 4);
-    const unsigned gmax = 65536;
-    auto g = [&](int32_t nr) { return (unsigned)std::min<int64_t>(std::max<int32_t>(nr, 1), gmax); };
-    if (hc[0]) k_spgemm_count<H0><<<g(hc[0]), 64, 0, s>>>(lists.get(), hc[0], arp, acol, brp, bcol, cnt.get(), ctx->dev_flag);
-    if (hc[1]) k_spgemm_count<H1><<<g(hc[1]), 64, 0, s>>>(lists.get() + m, hc[1], arp, acol, brp, bcol, cnt.get(), ctx->dev_flag);
-    if (hc[2]) k_spgemm_count<H2><<<g(hc[2]), 64, 0, s>>>(lists.get() + 2 * (int64_t)m, hc[2], arp, acol, brp, bcol, cnt.get(), ctx->dev_flag);
-    OCP_LAUNCH_CHECK();
+    spgemm_pass<false>(ctx, lists.get(), hc, m, arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(), nullptr,
+                       nullptr);
     int32_t fl = 0;
     read_back(ctx, &fl, ctx->dev_flag, 4);
-    if (fl & 32) fail(OCP_ERR_UNSUPPORTED, "sparse product row with more than 1536 entries");
+    if (fl & 32) fail(OCP_ERR_UNSUPPORTED, "sparse product row with more than 3072 entries");
     C.rows = m;
     C.cols = ncols;
     C.rp.reset(ctx, (size_t)m + 1);
     C.nnz = scan_exclusive(ctx, cnt.get(), C.rp.get(), m);
     C.col.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
     C.val.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
-    if (hc[0]) k_spgemm_fill<H0><<<g(hc[0]), 64, 0, s>>>(lists.get(), hc[0], arp, acol, aval, brp, bcol, bval, C.rp.get(), C.col.get(), C.val.get());
-    if (hc[1]) k_spgemm_fill<H1><<<g(hc[1]), 64, 0, s>>>(lists.get() + m, hc[1], arp, acol, aval, brp, bcol, bval, C.rp.get(), C.col.get(), C.val.get());
-    if (hc[2]) k_spgemm_fill<H2><<<g(hc[2]), 64, 0, s>>>(lists.get() + 2 * (int64_t)m, hc[2], arp, acol, aval, brp, bcol, bval, C.rp.get(), C.col.get(), C.val.get());
+    // the numeric pass sizes each row's table by its exact distinct count
+    fill_zero_bytes(ctx, counts.get(), 32);
+    k_bin_rows<<<grid_for(m, 256), 256, 0, s>>>(m, cnt.get(), counts.get(), lists.get());
     OCP_LAUNCH_CHECK();
+    read_back(ctx, hc, counts.get(), 32);
+    spgemm_pass<true>(ctx, lists.get(), hc, m, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr, C.col.get(),
+                      C.val.get());
 }
 
 // --------------------------------------------------------------- transpose
@@ -559,9 +626,25 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
             for (int round = 0;; ++round) {
                 if (round > 1000) fail(OCP_ERR_HIP, "independent-set rounds did not terminate");
                 fill_zero_bytes(ctx, ctx->dev_flag, 4);
-                k_mis_m1<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get());
-                k_mis_m2<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get(),
-                                                          ctx->dev_flag);
+                const int gm = std::min(L.gA, 16);
+                const unsigned gb = grid_for((int64_t)n * gm, 256);
+                switch (gm) {
+                    case 4:
+                        k_mis_m1<4><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get());
+                        k_mis_m2<4><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get(),
+                                                       ctx->dev_flag);
+                        break;
+                    case 8:
+                        k_mis_m1<8><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get());
+                        k_mis_m2<8><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get(),
+                                                       ctx->dev_flag);
+                        break;
+                    default:
+                        k_mis_m1<16><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get());
+                        k_mis_m2<16><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt,
+                                                        m1.get(), ctx->dev_flag);
+                        break;
+                }
                 OCP_LAUNCH_CHECK();
                 int32_t und = 0;
                 read_back(ctx, &und, ctx->dev_flag, 4);

@@ -1,9 +1,10 @@
 // Finite element assembly of A = rho*K + M and f = (int ubar phi_i) into CSR
 // (Section 3, system (linsys) and the entries K_ij, M_ij, f_i defined there).
 //
-// Row-owned, atomic-free on values: every interior vertex owns its row and
-// visits its incident tetrahedra in increasing tet id, recomputing the needed
-// element entries on the fly.  The result is bitwise deterministic.
+// Row-owned, atomic-free on values: every interior vertex owns its row; the
+// lanes of its group recompute the element entries of its incident
+// tetrahedra on the fly and sum them in a fixed order.  The result is
+// bitwise deterministic (and A bitwise symmetric).
 //
 //   1. per tet: index/degeneracy checks, incidence counts   (int atomics)
 //   2. scan -> incidence pointers; fill; sort each list      (vertex -> tets)
@@ -22,7 +23,7 @@ namespace ocp {
 
 constexpr int kAsmBlock = 64;
 constexpr int kRowCap = 128;       // max entries of one assembled row
-constexpr int kSineTable = 16;     // sin(k pi x) by recurrence for k <= 16
+constexpr int kSineTable = 8;      // sin(k pi x) by recurrence for k <= 8
 
 // ----------------------------------------------------------------- geometry
 // Barycentric gradients g[a] and signed determinant of the edge matrix of a
@@ -184,13 +185,16 @@ __global__ void k_dof_maps(const uint8_t *__restrict__ dirichlet, const int32_t 
 }
 
 // ---------------------------------------------------- 4. symbolic rows
-// pass 0: row_cnt[i] = number of distinct interior neighbours (incl. i)
-// pass 1: write them, sorted, to col[row_ptr[i] ..]
+// pass 0: row_cnt[i] = number of distinct interior neighbours (incl. i); rows
+//         of at most kPadW entries are also written, sorted, to pad[i][.]
+// pass 1: write the sorted list to col[row_ptr[i] ..] (only needed when some
+//         row exceeded kPadW)
+constexpr int kPadW = 32;
 __global__ void __launch_bounds__(kAsmBlock) k_row_symbolic(
     int pass, int32_t n, const int32_t *__restrict__ vertex_of_dof, const int32_t *__restrict__ dof_of_vertex,
     const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc, const int4 *__restrict__ tets,
     int32_t *__restrict__ row_cnt, const int32_t *__restrict__ row_ptr, int32_t *__restrict__ col,
-    int32_t *__restrict__ flag) {
+    int32_t *__restrict__ pad, int32_t *__restrict__ flag) {
     __shared__ int32_t lst[kRowCap][kAsmBlock];
     const int t = threadIdx.x;
     const int i = blockIdx.x * kAsmBlock + t;
@@ -219,10 +223,25 @@ __global__ void __launch_bounds__(kAsmBlock) k_row_symbolic(
     }
     if (pass == 0) {
         row_cnt[i] = cnt;
+        if (cnt <= kPadW) {
+            for (int s = 0; s < cnt; ++s) pad[(int64_t)i * kPadW + s] = lst[s][t];
+        } else {
+            atomicOr(flag, 128);
+        }
     } else {
         const int b = row_ptr[i];
         for (int s = 0; s < cnt; ++s) col[b + s] = lst[s][t];
     }
+}
+
+// copy the padded sorted lists into CSR
+__global__ void k_pad_to_csr(int32_t n, const int32_t *__restrict__ pad, const int32_t *__restrict__ row_ptr,
+                             int32_t *__restrict__ col) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / kPadW), s = (int)(t % kPadW);
+    if (i >= n) return;
+    const int b = row_ptr[i];
+    if (s < row_ptr[i + 1] - b) col[b + s] = pad[t];
 }
 
 // --------------------------------------------------------- 5. element loads
@@ -267,11 +286,12 @@ __device__ double eval_sine(const TargetDev &t, const double x[3], double *tab, 
     return u;
 }
 
-__global__ void __launch_bounds__(kAsmBlock) k_tet_load(const int4 *__restrict__ tets, int64_t nt,
-                                                        const double *__restrict__ xyz, TargetDev tg,
-                                                        double4 *__restrict__ fe) {
-    __shared__ double tab[3 * kSineTable * kAsmBlock];
-    const int64_t e = (int64_t)blockIdx.x * kAsmBlock + threadIdx.x;
+constexpr int kLoadBlock = 128;
+__global__ void __launch_bounds__(kLoadBlock) k_tet_load(const int4 *__restrict__ tets, int64_t nt,
+                                                         const double *__restrict__ xyz, TargetDev tg,
+                                                         double4 *__restrict__ fe) {
+    __shared__ double tab[3 * kSineTable * kLoadBlock];
+    const int64_t e = (int64_t)blockIdx.x * kLoadBlock + threadIdx.x;
     if (e >= nt) return;
     const int4 tv = tets[e];
     double p[4][3];
@@ -302,7 +322,7 @@ __global__ void __launch_bounds__(kAsmBlock) k_tet_load(const int4 *__restrict__
         }
         double u;
         if (tg.kind == OCP_TARGET_SINE_MODES) {
-            u = eval_sine(tg, x, tab + threadIdx.x, kAsmBlock);
+            u = eval_sine(tg, x, tab + threadIdx.x, kLoadBlock);
         } else if (tg.kind == OCP_TARGET_BOX) {
             u = (x[0] > tg.lo[0] && x[0] < tg.hi[0] && x[1] > tg.lo[1] && x[1] < tg.hi[1] &&
                  x[2] > tg.lo[2] && x[2] < tg.hi[2])
@@ -321,26 +341,44 @@ __global__ void __launch_bounds__(kAsmBlock) k_tet_load(const int4 *__restrict__
 }
 
 // ---------------------------------------------------------- 6. numeric rows
-__global__ void __launch_bounds__(kAsmBlock) k_row_numeric(
+// G lanes per row.  Lane l takes the incident tets with id = l (mod G) in
+// ascending order and accumulates rho*K_e + M_e into register slots (one per
+// row entry, matched by column); the lanes' partial rows are then added in a
+// fixed butterfly order.  Entry (i,j) and entry (j,i) therefore sum the same
+// element terms in the same order: the assembled A is bitwise symmetric.
+constexpr int kNumG = 8;
+template <int MAXS, bool KM>
+__global__ void __launch_bounds__(256) k_row_numeric(
     int32_t n, double rho, const int32_t *__restrict__ vertex_of_dof, const int32_t *__restrict__ dof_of_vertex,
     const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc, const int4 *__restrict__ tets,
     const double *__restrict__ xyz, const double4 *__restrict__ fe, const int32_t *__restrict__ row_ptr,
     const int32_t *__restrict__ col, double *__restrict__ val, double *__restrict__ valK,
     double *__restrict__ valM, double *__restrict__ f) {
-    const int i = blockIdx.x * kAsmBlock + threadIdx.x;
+    // No FMA contraction here: the unrolled copies of the element-entry
+    // expression for different local indices must round identically, so that
+    // entry (i,j) and entry (j,i) get the same bits.
+#pragma clang fp contract(off)
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(tid / kNumG), lane = (int)(tid % kNumG);
     if (i >= n) return;
     const int vi = vertex_of_dof[i];
-    const int rb = row_ptr[i], re = row_ptr[i + 1];
-    for (int s = rb; s < re; ++s) {
-        val[s] = 0.0;
-        if (valK) {
-            valK[s] = 0.0;
-            valM[s] = 0.0;
+    const int rb = row_ptr[i], len = row_ptr[i + 1] - rb;
+    int cols[MAXS];
+    double acc[MAXS], aK[KM ? MAXS : 1], aM[KM ? MAXS : 1];
+#pragma unroll
+    for (int q = 0; q < MAXS; ++q) {
+        cols[q] = q < len ? col[rb + q] : -1;
+        acc[q] = 0.0;
+        if (KM) {
+            aK[q] = 0.0;
+            aM[q] = 0.0;
         }
     }
     double fi = 0.0;
-    for (int q = inc_ptr[vi]; q < inc_ptr[vi + 1]; ++q) {
+    const int qe = inc_ptr[vi + 1];
+    for (int q = inc_ptr[vi]; q < qe; ++q) {
         const int e = inc[q];
+        if ((e % kNumG) != lane) continue;
         const int4 tv = tets[e];
         const int vv[4] = {tv.x, tv.y, tv.z, tv.w};
         double p[4][3], g[4][3];
@@ -362,23 +400,53 @@ __global__ void __launch_bounds__(kAsmBlock) k_row_numeric(
             if (j < 0) continue;
             const double kab = vol * (ga[0] * g[b][0] + ga[1] * g[b][1] + ga[2] * g[b][2]);
             const double mab = vol / 20.0 * (b == a ? 2.0 : 1.0);
-            // binary search of column j in the sorted row
-            int lo = rb, hi = re - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (col[mid] < j)
-                    lo = mid + 1;
-                else
-                    hi = mid;
-            }
-            val[lo] += rho * kab + mab;
-            if (valK) {
-                valK[lo] += kab;
-                valM[lo] += mab;
-            }
+            const double v = rho * kab + mab;
+#pragma unroll
+            for (int s2 = 0; s2 < MAXS; ++s2)
+                if (cols[s2] == j) {
+                    acc[s2] += v;
+                    if (KM) {
+                        aK[s2] += kab;
+                        aM[s2] += mab;
+                    }
+                }
         }
     }
-    f[i] = fi;
+    fi = dev::group_sum<kNumG>(fi);
+#pragma unroll
+    for (int q = 0; q < MAXS; ++q) {
+        acc[q] = dev::group_sum<kNumG>(acc[q]);
+        if (KM) {
+            aK[q] = dev::group_sum<kNumG>(aK[q]);
+            aM[q] = dev::group_sum<kNumG>(aM[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < MAXS; ++q)
+        if (q < len && (q % kNumG) == lane) {
+            val[rb + q] = acc[q];
+            if (KM) {
+                valK[rb + q] = aK[q];
+                valM[rb + q] = aM[q];
+            }
+        }
+    if (lane == 0) f[i] = fi;
+}
+
+template <int MAXS>
+static void launch_numeric(ocp_ctx *ctx, ocp_system *sys, double rho, const int4 *tets, const double *xyz,
+                           const double4 *fe) {
+    const unsigned g = grid_for((int64_t)sys->n * kNumG, 256);
+    if (sys->valK.get())
+        k_row_numeric<MAXS, true><<<g, 256, 0, ctx->stream>>>(
+            sys->n, rho, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
+            xyz, fe, sys->row_ptr.get(), sys->col.get(), sys->val.get(), sys->valK.get(), sys->valM.get(),
+            sys->f.get());
+    else
+        k_row_numeric<MAXS, false><<<g, 256, 0, ctx->stream>>>(
+            sys->n, rho, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
+            xyz, fe, sys->row_ptr.get(), sys->col.get(), sys->val.get(), nullptr, nullptr, sys->f.get());
+    OCP_LAUNCH_CHECK();
 }
 
 __global__ void k_set_rho(int64_t nnz, double rho, const double *__restrict__ valK,
@@ -449,8 +517,8 @@ static void compute_loads(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *m
     upload_target(ctx, t, up);
     DevBuf<double4> fe(ctx, (size_t)sys->nt);
     const int4 *tets = reinterpret_cast<const int4 *>(mesh->tets);
-    k_tet_load<<<grid_for(sys->nt, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(tets, sys->nt, mesh->xyz, up.dev,
-                                                                            fe.get());
+    k_tet_load<<<grid_for(sys->nt, kLoadBlock), kLoadBlock, 0, ctx->stream>>>(tets, sys->nt, mesh->xyz, up.dev,
+                                                                              fe.get());
     OCP_LAUNCH_CHECK();
     // row sums of the element loads (reuse the numeric kernel's f output
     // through a dedicated pass that only accumulates f)
@@ -482,6 +550,22 @@ void row_loads(ocp_ctx *ctx, const ocp_system *sys, const double4 *fe, double *f
         sys->n, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(),
         reinterpret_cast<const int4 *>(sys->tets_ref), fe, f);
     OCP_LAUNCH_CHECK();
+}
+
+__global__ void k_row_lengths(int32_t n, const int32_t *__restrict__ rp, double *__restrict__ len) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) len[i] = (double)(rp[i + 1] - rp[i]);
+}
+
+// longest row of the assembled pattern (cached on the system)
+static int max_row_len(ocp_ctx *ctx, ocp_system *sys) {
+    if (sys->max_row_len < 0) {
+        DevBuf<double> len(ctx, (size_t)sys->n);
+        k_row_lengths<<<grid_for(sys->n, 256), 256, 0, ctx->stream>>>(sys->n, sys->row_ptr.get(), len.get());
+        OCP_LAUNCH_CHECK();
+        sys->max_row_len = (int)reduce_max_abs(ctx, len.get(), sys->n);
+    }
+    return sys->max_row_len;
 }
 
 static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_target *t, int32_t flags,
@@ -535,26 +619,35 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
 
     // 4. symbolic rows
     DevBuf<int32_t> rcnt(ctx, (size_t)n + 1);
+    DevBuf<int32_t> pad(ctx, (size_t)n * kPadW);
+    fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
     k_row_symbolic<<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
         0, sys->n, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
-        rcnt.get(), nullptr, nullptr, ctx->dev_flag);
+        rcnt.get(), nullptr, nullptr, pad.get(), ctx->dev_flag);
     OCP_LAUNCH_CHECK();
     read_back(ctx, &fl, ctx->dev_flag, sizeof(fl));
     if (fl & 4) fail(OCP_ERR_UNSUPPORTED, "an assembled row has more than 128 entries");
     sys->row_ptr.reset(ctx, (size_t)n + 1);
     sys->nnz = scan_exclusive(ctx, rcnt.get(), sys->row_ptr.get(), n);
-    rcnt.release();
     sys->col.reset(ctx, (size_t)sys->nnz);
-    k_row_symbolic<<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
-        1, sys->n, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
-        nullptr, sys->row_ptr.get(), sys->col.get(), ctx->dev_flag);
+    if (fl & 128) {
+        k_row_symbolic<<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
+            1, sys->n, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
+            nullptr, sys->row_ptr.get(), sys->col.get(), nullptr, ctx->dev_flag);
+    } else {
+        k_pad_to_csr<<<grid_for((int64_t)n * kPadW, 256), 256, 0, ctx->stream>>>(sys->n, pad.get(),
+                                                                                  sys->row_ptr.get(), sys->col.get());
+    }
     OCP_LAUNCH_CHECK();
+    pad.release();
+    const int maxlen = (fl & 128) ? kRowCap : kPadW;
+    rcnt.release();
 
     // 5. element loads
     TargetUpload up;
     upload_target(ctx, t, up);
     DevBuf<double4> fe(ctx, (size_t)nt);
-    k_tet_load<<<grid_for(nt, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(tets, nt, mesh->xyz, up.dev, fe.get());
+    k_tet_load<<<grid_for(nt, kLoadBlock), kLoadBlock, 0, ctx->stream>>>(tets, nt, mesh->xyz, up.dev, fe.get());
     OCP_LAUNCH_CHECK();
 
     // 6. numeric rows
@@ -564,10 +657,14 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
         sys->valK.reset(ctx, (size_t)sys->nnz);
         sys->valM.reset(ctx, (size_t)sys->nnz);
     }
-    k_row_numeric<<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
-        sys->n, rho, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
-        mesh->xyz, fe.get(), sys->row_ptr.get(), sys->col.get(), sys->val.get(), sys->valK.get(), sys->valM.get(),
-        sys->f.get());
+    if (maxlen <= 16 || max_row_len(ctx, sys) <= 16)
+        launch_numeric<16>(ctx, sys, rho, tets, mesh->xyz, fe.get());
+    else if (max_row_len(ctx, sys) <= 32)
+        launch_numeric<32>(ctx, sys, rho, tets, mesh->xyz, fe.get());
+    else if (max_row_len(ctx, sys) <= 64)
+        launch_numeric<64>(ctx, sys, rho, tets, mesh->xyz, fe.get());
+    else
+        launch_numeric<128>(ctx, sys, rho, tets, mesh->xyz, fe.get());
     OCP_LAUNCH_CHECK();
     sync(ctx);
 }

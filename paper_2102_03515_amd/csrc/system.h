@@ -11,6 +11,7 @@ struct ocp_system {
     int64_t nt = 0;           // tetrahedra
     int64_t nnz = 0;
     double rho = 0.0;
+    int max_row_len = -1;     // longest assembled row (computed on demand)
     const int32_t *tets_ref = nullptr;  // mesh tets the system was assembled from (borrowed)
     ocp::DevBuf<int32_t> inc_ptr, inc;  // vertex -> incident tets, ascending
     ocp::DevBuf<int32_t> dof_of_vertex, vertex_of_dof;

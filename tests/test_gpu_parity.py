@@ -299,3 +299,15 @@ def test_error_paths(P, ctx):
     z = torch.zeros(s.n, dtype=torch.float64, device="cuda")
     u, info, rc = P.pcg_solve(ctx, s, None, f=z)
     assert rc == 0 and info.iterations == 0 and float(u.abs().max()) == 0.0
+
+
+def test_assembled_matrix_is_bitwise_symmetric(P, ctx):
+    import scipy.sparse as sp
+    print("[symmetry] cube10 jitter", flush=True)
+    mesh = I.kuhn_mesh(10, jitter=0.15, seed=8)
+    s, _ = _gpu_system(P, ctx, mesh, 3e-3, I.single_sine())
+    rp, col, val = _host_csr(s)
+    A = sp.csr_matrix((val, col, rp), shape=(s.n, s.n))
+    D = (A - A.T).tocoo()
+    print(f"    asymmetric entries {(A != A.T.tocsr()).nnz}, max |a_ij - a_ji| {abs(D.data).max() if D.nnz else 0.0}")
+    assert (A != A.T.tocsr()).nnz == 0

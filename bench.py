@@ -44,14 +44,14 @@ def kernel_bytes(kernel: int, n: int, nnz: int, mixed: bool) -> float:
     mat = (4 + vs) * nnz + 4.0 * (n + 1)
     if kernel == 0:    # q = A p, p.q: 8-byte values, p gathered, q written
         return 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n
-    if kernel == 1:    # r1 = b - A (a D^-1 b): b(8) d r1
+    if kernel == 1:    # x2 = D^-1 (c1 b + c2 r1), r1 = b - A (a D^-1 b): b(8) d x2
         return mat + 8.0 * n + 2.0 * vs * n
-    if kernel == 5:    # r2 = b - A D^-1 (c1 b + c2 r1): b(8) d r1 r2
-        return mat + 8.0 * n + 3.0 * vs * n
-    if kernel == 6:    # r0 = b - A xp: b(8) xp r0
+    if kernel == 5:    # r2 = b - A x2: x2 b(8) r2
         return mat + 8.0 * n + 2.0 * vs * n
-    if kernel == 2:    # z = xp + D^-1 (c1 r0 + c2 r1), r1 = b - A (xp + a D^-1 r0), b.z: b(8) xp r0 d z(8)
-        return mat + 16.0 * n + 3.0 * vs * n
+    if kernel == 6:    # r0 = b - A xp, x1 = xp + a D^-1 r0: xp b(8) d r0 x1
+        return mat + 8.0 * n + 4.0 * vs * n
+    if kernel == 2:    # r1 = b - A x1, z = xp + D^-1 (c1 r0 + c2 r1), b.z: x1 b(8) xp r0 d z(8)
+        return mat + 16.0 * n + 4.0 * vs * n
     raise ValueError(kernel)
 
 

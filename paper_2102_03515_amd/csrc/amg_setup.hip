@@ -733,14 +733,18 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
         Level &L = *h->levels[l];
         if (mixed) {
             to_float(ctx, L.A_val, L.A_val32, L.nnzA);
+            if (l == 0) sell_values32(ctx, system_sell(ctx, sys), L.A_rp, L.A_val32.get(), L.sell_val32);
             to_float(ctx, L.dinv.get(), L.dinv32, L.n);
             if (L.P_val.get()) to_float(ctx, L.P_val.get(), L.P_val32, L.nnzP);
             if (L.R_val.get()) to_float(ctx, L.R_val.get(), L.R_val32, L.nnzP);
             if (L.dense_inv.get()) to_float(ctx, L.dense_inv.get(), L.dense_inv32, (int64_t)L.n * L.n);
         }
         L.vr.reset(ctx, es * L.n);
-        L.vr2.reset(ctx, es * L.n);
         L.vxp.reset(ctx, es * L.n);
+        if (L.deg == 2) {
+            L.vx1.reset(ctx, es * L.n);
+            L.vx2.reset(ctx, es * L.n);
+        }
         if (l > 0) {
             L.vb.reset(ctx, es * L.n);
             L.vx.reset(ctx, es * L.n);

@@ -666,6 +666,8 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
     else
         launch_numeric<128>(ctx, sys, rho, tets, mesh->xyz, fe.get());
     OCP_LAUNCH_CHECK();
+    // sliced-ELL copy for the solve phase
+    system_sell(ctx, sys);
     sync(ctx);
 }
 
@@ -710,6 +712,7 @@ extern "C" int fe_set_rho(ocp_ctx *ctx, ocp_system *sys, double rho) {
         OCP_LAUNCH_CHECK();
         sys->rho = rho;
         sys->invalidate_derived();
+        system_sell(ctx, sys);
         sync(ctx);
     });
 }

@@ -117,6 +117,30 @@ __device__ __forceinline__ bool grid_sum2_last(double2 bp, double *partials, uns
     return true;
 }
 
+// Block partials of a grid reduction: thread 0 stores the block's value
+// (valid in thread 0) with a plain store; a one-block finalize kernel
+// launched next on the stream sums them in block order.  (A last-block
+// epilogue would need an agent-scope release fence in every block, which
+// writes back the XCD's L2 each time.)
+__device__ __forceinline__ void store_partial(double v, double *partials) {
+    if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+__device__ __forceinline__ void store_partial2(double2 v, double *partials) {
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = v.x;
+        partials[2 * blockIdx.x + 1] = v.y;
+    }
+}
+
+// Sum of nb partials in a fixed order (one block of kBlock threads; result
+// valid in thread 0).
+template <int BLOCK>
+__device__ __forceinline__ double sum_partials(const double *partials, unsigned nb, int stride = 1, int off = 0) {
+    double s = 0.0;
+    for (unsigned b = threadIdx.x; b < nb; b += BLOCK) s += partials[(size_t)b * stride + off];
+    return block_sum<BLOCK>(s);
+}
+
 // After r.z of the new preconditioned residual is known (thread 0 of the
 // last block): beta = rz / gamma, gamma = rz; first call records gamma0; the
 // preconditioned stop test and the breakdown test live here.
@@ -139,3 +163,75 @@ __device__ __forceinline__ void cg_after_precond(CgScalars *cg, double rz) {
 }  // namespace dev
 #endif
 }  // namespace ocp
+
+// ------------------------------------------------------------ sliced ELL
+// Fine-level copy of a CSR matrix in sliced ELLPACK with slices of 64 rows
+// (one wavefront): entry j of row 64*s + lane sits at ptr[s] + 64*j + lane,
+// slice s has width w[s] = its longest row, shorter rows are padded with
+// value 0 and column = the row itself.  A thread owns a row; each load
+// instruction of a wavefront reads 64 consecutive entries, and a thread
+// issues the loads of a whole chunk of its row before consuming them.
+namespace ocp {
+
+constexpr int kSellC = 64;
+constexpr int kSellChunk = 16;
+
+struct SellLaunch {
+    unsigned blocks;
+    int slices_per_block;   // multiple of kBlock / kSellC
+};
+
+inline SellLaunch sell_launch(int64_t nslices) {
+    constexpr int WPB = kBlock / kSellC;
+    const int64_t max_blocks = kMaxPartials / 2;
+    int64_t spb = (nslices + max_blocks - 1) / max_blocks;
+    spb = ((spb + WPB - 1) / WPB) * WPB;
+    if (spb < WPB) spb = WPB;
+    SellLaunch L;
+    L.slices_per_block = (int)spb;
+    int64_t b = (nslices + spb - 1) / spb;
+    L.blocks = (unsigned)(b < 1 ? 1 : b);
+    return L;
+}
+
+#ifdef __HIPCC__
+namespace dev {
+
+// sum_j val * xf(col) over the row held by this lane of slice (base = its
+// offset); w is the slice width (uniform over the wavefront)
+template <typename VT, typename XF>
+__device__ __forceinline__ VT sell_row(const int32_t *__restrict__ col, const VT *__restrict__ val, int64_t base,
+                                       int w, XF xf) {
+    VT acc = VT(0);
+    for (int j0 = 0; j0 < w; j0 += kSellChunk) {
+        int c[kSellChunk];
+        VT v[kSellChunk];
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j)
+            if (j0 + j < w) {
+                c[j] = ldnt(col + base + (int64_t)(j0 + j) * kSellC);
+                v[j] = ldnt(val + base + (int64_t)(j0 + j) * kSellC);
+            }
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j)
+            if (j0 + j < w) acc += v[j] * xf(c[j]);
+    }
+    return acc;
+}
+
+}  // namespace dev
+#endif
+}  // namespace ocp
+
+// Loop header for SELL kernels: `row` and `base` for each slice this
+// wavefront owns (slices contiguous per XCD), `lane` = lane in the slice.
+#define OCP_SELL_BEGIN(nslices, spb)                                                 \
+    const unsigned tile_ = ::ocp::dev::xcd_tile(blockIdx.x, gridDim.x);              \
+    const int lane = threadIdx.x & 63, wv_ = threadIdx.x >> 6;                       \
+    for (int s0_ = 0; s0_ < (spb); s0_ += ::ocp::kBlock / ::ocp::kSellC) {            \
+        const int64_t slice = (int64_t)tile_ * (spb) + s0_ + wv_;                    \
+        if (slice >= (nslices)) break;                                               \
+        const int w = sw[slice];                                                     \
+        const int64_t base = sp[slice] + lane;                                       \
+        const int row = (int)(slice * ::ocp::kSellC) + lane;
+#define OCP_SELL_END() }

@@ -16,49 +16,43 @@ namespace ocp {
 constexpr int kSpmvLanes = 16;  // lanes per row of the fine-level SpMV (15-point rows)
 
 // ------------------------------------------------------------------ SpMV
-template <int G>
-__global__ void __launch_bounds__(kBlock) k_spmv(int32_t n, int iters, const int32_t *__restrict__ rp,
-                                                 const int32_t *__restrict__ col, const double *__restrict__ val,
-                                                 const double *__restrict__ x, double *__restrict__ y) {
-    constexpr int RPP = kBlock / G;
-    const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x % G, grp = threadIdx.x / G;
-    const int base = (int)tile * RPP * iters;
-    for (int it = 0; it < iters; ++it) {
-        const int row = base + it * RPP + grp;
-        if (row < n) {
-            const double s = dev::row_sum<G>(rp[row], rp[row + 1], lane, col, val, [&](int c) { return x[c]; });
-            if (lane == 0) y[row] = s;
-        }
-    }
+// y = A x on the sliced-ELL copy
+__global__ void __launch_bounds__(kBlock) k_spmv_sell(int32_t n, int64_t nslices, int spb, const int32_t *__restrict__ sp,
+                                                      const int32_t *__restrict__ sw, const int32_t *__restrict__ col,
+                                                      const double *__restrict__ val, const double *__restrict__ x,
+                                                      double *__restrict__ y) {
+    OCP_SELL_BEGIN(nslices, spb)
+    const double s = dev::sell_row(col, val, base, w, [&](int c) { return x[c]; });
+    if (row < n) y[row] = s;
+    OCP_SELL_END()
 }
 
-// q = A p and alpha = gamma / (p.q)
-template <int G>
-__global__ void __launch_bounds__(kBlock) k_cg_spmv_pq(int32_t n, int iters, const int32_t *__restrict__ rp,
-                                                       const int32_t *__restrict__ col,
-                                                       const double *__restrict__ val, const double *__restrict__ p,
-                                                       double *__restrict__ q, CgScalars *cg, double *partials,
-                                                       unsigned *counter) {
+// q = A p and alpha = gamma / (p.q), sliced-ELL fine matrix
+__global__ void __launch_bounds__(kBlock) k_cg_spmv_pq_sell(int32_t n, int64_t nslices, int spb,
+                                                            const int32_t *__restrict__ sp,
+                                                            const int32_t *__restrict__ sw,
+                                                            const int32_t *__restrict__ col,
+                                                            const double *__restrict__ val,
+                                                            const double *__restrict__ p, double *__restrict__ q,
+                                                            CgScalars *cg, double *partials) {
     if (cg->flag) return;
-    constexpr int RPP = kBlock / G;
-    const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x % G, grp = threadIdx.x / G;
-    const int base = (int)tile * RPP * iters;
     double acc = 0.0;
-    for (int it = 0; it < iters; ++it) {
-        const int row = base + it * RPP + grp;
-        if (row < n) {
-            const double s = dev::row_sum<G>(rp[row], rp[row + 1], lane, col, val, [&](int c) { return p[c]; });
-            if (lane == 0) {
-                q[row] = s;
-                acc += s * p[row];
-            }
-        }
+    OCP_SELL_BEGIN(nslices, spb)
+    const double s = dev::sell_row(col, val, base, w, [&](int c) { return p[c]; });
+    if (row < n) {
+        q[row] = s;
+        acc += s * p[row];
     }
+    OCP_SELL_END()
     acc = dev::block_sum<kBlock>(acc);
-    double tot;
-    if (dev::grid_sum_last<kBlock>(acc, partials, counter, &tot) && threadIdx.x == 0) {
+    dev::store_partial(acc, partials);
+}
+
+// alpha = gamma / (p.q) from the partials of k_cg_spmv_pq_sell
+__global__ void __launch_bounds__(kBlock) k_fin_alpha(unsigned nb, const double *partials, CgScalars *cg) {
+    if (cg->flag) return;
+    const double tot = dev::sum_partials<kBlock>(partials, nb);
+    if (threadIdx.x == 0) {
         cg->pq = tot;
         if (!(tot > 0.0) || !isfinite(tot)) {
             cg->flag = 2;
@@ -69,13 +63,34 @@ __global__ void __launch_bounds__(kBlock) k_cg_spmv_pq(int32_t n, int iters, con
     }
 }
 
+// sum_i (f_i - (A x)_i)^2 on the sliced-ELL copy
+__global__ void __launch_bounds__(kBlock) k_resid2_sell(int32_t n, int64_t nslices, int spb, const int32_t *__restrict__ sp,
+                                                        const int32_t *__restrict__ sw, const int32_t *__restrict__ col,
+                                                        const double *__restrict__ val, const double *__restrict__ x,
+                                                        const double *__restrict__ f, double *partials) {
+    double acc = 0.0;
+    OCP_SELL_BEGIN(nslices, spb)
+    const double s = dev::sell_row(col, val, base, w, [&](int c) { return x[c]; });
+    if (row < n) {
+        const double d = f[row] - s;
+        acc += d * d;
+    }
+    OCP_SELL_END()
+    acc = dev::block_sum<kBlock>(acc);
+    dev::store_partial(acc, partials);
+}
+
+__global__ void __launch_bounds__(kBlock) k_fin_store(unsigned nb, const double *partials, double *out) {
+    const double tot = dev::sum_partials<kBlock>(partials, nb);
+    if (threadIdx.x == 0) *out = tot;
+}
+
 // x += alpha p, r -= alpha q, r.r; with JAC also z = dinv r and r.z.
 template <bool JAC>
 __global__ void __launch_bounds__(kBlock) k_cg_update(int32_t n, int iters, double *__restrict__ x,
                                                       double *__restrict__ r, const double *__restrict__ p,
                                                       const double *__restrict__ q, const double *__restrict__ dinv,
-                                                      double *__restrict__ z, CgScalars *cg, double *partials,
-                                                      unsigned *counter) {
+                                                      double *__restrict__ z, CgScalars *cg, double *partials) {
     if (cg->flag) return;
     const double alpha = cg->alpha;
     const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
@@ -96,8 +111,17 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int32_t n, int iters, doub
         }
     }
     double2 bs = dev::block_sum2<kBlock>(rr, rz);
-    double2 tot;
-    if (dev::grid_sum2_last<kBlock>(bs, partials, counter, &tot) && threadIdx.x == 0) {
+    dev::store_partial2(bs, partials);
+}
+
+// r.r (and r.z with JAC) from the partials of k_cg_update: stop tests
+template <bool JAC>
+__global__ void __launch_bounds__(kBlock) k_fin_update(unsigned nb, const double *partials, CgScalars *cg) {
+    if (cg->flag) return;
+    const double rr = dev::sum_partials<kBlock>(partials, nb, 2, 0);
+    const double rz = JAC ? dev::sum_partials<kBlock>(partials, nb, 2, 1) : 0.0;
+    if (threadIdx.x == 0) {
+        const double2 tot = make_double2(rr, rz);
         cg->rr = tot.x;
         cg->iter += 1;
         if (cg->stop_mode == OCP_STOP_L2 && tot.x <= cg->tol2) {
@@ -123,8 +147,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(int32_t n, double *__rest
 // x = 0, r = f, p = 0, f.f and the initial scalars
 __global__ void __launch_bounds__(kBlock) k_cg_init(int32_t n, int iters, const double *__restrict__ f,
                                                     double *__restrict__ x, double *__restrict__ r,
-                                                    double *__restrict__ p, CgScalars *cg, double rtol, int mode,
-                                                    int maxit, double *partials, unsigned *counter) {
+                                                    double *__restrict__ p, double *partials) {
     const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
     const int base = (int)tile * kBlock * iters;
     double ff = 0.0;
@@ -139,8 +162,13 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(int32_t n, int iters, const 
         }
     }
     ff = dev::block_sum<kBlock>(ff);
-    double tot;
-    if (dev::grid_sum_last<kBlock>(ff, partials, counter, &tot) && threadIdx.x == 0) {
+    dev::store_partial(ff, partials);
+}
+
+__global__ void __launch_bounds__(kBlock) k_fin_init(unsigned nb, const double *partials, CgScalars *cg, double rtol,
+                                                     int mode, int maxit) {
+    const double tot = dev::sum_partials<kBlock>(partials, nb);
+    if (threadIdx.x == 0) {
         cg->ff = tot;
         cg->rr = tot;
         cg->tol2 = (mode == OCP_STOP_L2) ? rtol * rtol * tot : rtol * rtol;
@@ -160,7 +188,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(int32_t n, int iters, const 
 // z = dinv r and r.z (Jacobi preconditioner at the start)
 __global__ void __launch_bounds__(kBlock) k_cg_jacobi(int32_t n, int iters, const double *__restrict__ r,
                                                       const double *__restrict__ dinv, double *__restrict__ z,
-                                                      CgScalars *cg, double *partials, unsigned *counter) {
+                                                      CgScalars *cg, double *partials) {
     if (cg->flag) return;
     const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
     const int base = (int)tile * kBlock * iters;
@@ -174,34 +202,14 @@ __global__ void __launch_bounds__(kBlock) k_cg_jacobi(int32_t n, int iters, cons
         }
     }
     rz = dev::block_sum<kBlock>(rz);
-    double tot;
-    if (dev::grid_sum_last<kBlock>(rz, partials, counter, &tot) && threadIdx.x == 0) dev::cg_after_precond(cg, tot);
+    dev::store_partial(rz, partials);
 }
 
-// sum_i (f_i - (A x)_i)^2
-template <int G>
-__global__ void __launch_bounds__(kBlock) k_resid2(int32_t n, int iters, const int32_t *__restrict__ rp,
-                                                   const int32_t *__restrict__ col, const double *__restrict__ val,
-                                                   const double *__restrict__ x, const double *__restrict__ f,
-                                                   double *out, double *partials, unsigned *counter) {
-    constexpr int RPP = kBlock / G;
-    const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x % G, grp = threadIdx.x / G;
-    const int base = (int)tile * RPP * iters;
-    double acc = 0.0;
-    for (int it = 0; it < iters; ++it) {
-        const int row = base + it * RPP + grp;
-        if (row < n) {
-            const double s = dev::row_sum<G>(rp[row], rp[row + 1], lane, col, val, [&](int c) { return x[c]; });
-            if (lane == 0) {
-                const double d = f[row] - s;
-                acc += d * d;
-            }
-        }
-    }
-    acc = dev::block_sum<kBlock>(acc);
-    double tot;
-    if (dev::grid_sum_last<kBlock>(acc, partials, counter, &tot) && threadIdx.x == 0) *out = tot;
+// r.z from the partials of a preconditioner application
+__global__ void __launch_bounds__(kBlock) k_fin_rz(unsigned nb, const double *partials, CgScalars *cg) {
+    if (cg->flag) return;
+    const double tot = dev::sum_partials<kBlock>(partials, nb);
+    if (threadIdx.x == 0) dev::cg_after_precond(cg, tot);
 }
 
 __global__ void k_scatter(int32_t nv, const int32_t *__restrict__ dof_of_vertex, const double *__restrict__ x,
@@ -223,11 +231,11 @@ __global__ void k_diag_inv(int32_t n, const int32_t *__restrict__ rp, const int3
 }
 
 // --------------------------------------------------------------- host side
-void spmv_enqueue(ocp_ctx *ctx, int32_t n, const int32_t *rp, const int32_t *col, const double *val,
-                  const double *x, double *y) {
-    const RowLaunch L = row_launch(n, kSpmvLanes);
-    k_spmv<kSpmvLanes><<<L.blocks, kBlock, 0, ctx->stream>>>(n, L.iters, rp, col, val, x, y);
-    OCP_LAUNCH_CHECK();
+const Sell &system_sell(ocp_ctx *ctx, const ocp_system *csys) {
+    ocp_system *sys = const_cast<ocp_system *>(csys);
+    if (!sys->sell.col.get())
+        sell_build(ctx, sys->sell, sys->n, sys->row_ptr.get(), sys->col.get(), sys->val.get());
+    return sys->sell;
 }
 
 const double *system_dinv(ocp_ctx *ctx, ocp_system *sys) {
@@ -251,20 +259,22 @@ static void solve(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, const d
     double *part0 = ctx->red_partials;
     double *part1 = ctx->red_partials + kRedBlocks;
     double *part2 = ctx->red_partials + 2 * kRedBlocks;
-    unsigned *cnt0 = ctx->red_counters, *cnt1 = ctx->red_counters + 1, *cnt2 = ctx->red_counters + 2;
-    const RowLaunch LS = row_launch(n, kSpmvLanes);
+    const Sell &A = system_sell(ctx, sys);
+    const SellLaunch LS = sell_launch(A.nslices);
     const RowLaunch LV = vec_launch(n);
     const unsigned gp = grid_for(n, kBlock);
 
     ctx->prof_iter = -1;   // the initial preconditioner application
     OCP_HIP(hipEventRecord(ctx->ev0, ctx->stream));
-    k_cg_init<<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, f, x.get(), r.get(), p.get(), cg, rtol, mode, maxit,
-                                                     part0, cnt0);
+    k_cg_init<<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, f, x.get(), r.get(), p.get(), part0);
+    k_fin_init<<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part0, cg, rtol, mode, maxit);
     OCP_LAUNCH_CHECK();
-    if (h)
+    if (h) {
         vcycle_enqueue(ctx, h, r.get(), z.get(), cg);
-    else
-        k_cg_jacobi<<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, r.get(), dinv, z.get(), cg, part1, cnt1);
+    } else {
+        k_cg_jacobi<<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, r.get(), dinv, z.get(), cg, part1);
+        k_fin_rz<<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part1, cg);
+    }
     OCP_LAUNCH_CHECK();
     k_cg_pupdate<<<gp, kBlock, 0, ctx->stream>>>(n, p.get(), z.get(), cg);
     OCP_LAUNCH_CHECK();
@@ -277,16 +287,20 @@ static void solve(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, const d
         if (hs.flag != 0) break;
         for (int k = 0; k < chunk; ++k) {
             const int pr = prof_begin(ctx, OCP_KERNEL_CG_SPMV);
-            k_cg_spmv_pq<kSpmvLanes><<<LS.blocks, kBlock, 0, ctx->stream>>>(
-                n, LS.iters, sys->row_ptr.get(), sys->col.get(), sys->val.get(), p.get(), q.get(), cg, part0, cnt0);
+            k_cg_spmv_pq_sell<<<LS.blocks, kBlock, 0, ctx->stream>>>(n, A.nslices, LS.slices_per_block, A.sp.get(),
+                                                                     A.sw.get(), A.col.get(), A.val.get(), p.get(),
+                                                                     q.get(), cg, part0);
             prof_end(ctx, pr);
+            k_fin_alpha<<<1, kBlock, 0, ctx->stream>>>(LS.blocks, part0, cg);
             if (h) {
                 k_cg_update<false><<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, x.get(), r.get(), p.get(),
-                                                                          q.get(), nullptr, nullptr, cg, part1, cnt1);
+                                                                          q.get(), nullptr, nullptr, cg, part1);
+                k_fin_update<false><<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part1, cg);
                 vcycle_enqueue(ctx, h, r.get(), z.get(), cg);
             } else {
                 k_cg_update<true><<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, x.get(), r.get(), p.get(),
-                                                                         q.get(), dinv, z.get(), cg, part1, cnt1);
+                                                                         q.get(), dinv, z.get(), cg, part1);
+                k_fin_update<true><<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part1, cg);
             }
             k_cg_pupdate<<<gp, kBlock, 0, ctx->stream>>>(n, p.get(), z.get(), cg);
             ++ctx->prof_iter;
@@ -297,9 +311,9 @@ static void solve(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, const d
     OCP_HIP(hipEventRecord(ctx->ev1, ctx->stream));
 
     // true residual in double, then u on all vertices
-    k_resid2<kSpmvLanes><<<LS.blocks, kBlock, 0, ctx->stream>>>(n, LS.iters, sys->row_ptr.get(), sys->col.get(),
-                                                                sys->val.get(), x.get(), f, ctx->red_out + 1, part2,
-                                                                cnt2);
+    k_resid2_sell<<<LS.blocks, kBlock, 0, ctx->stream>>>(n, A.nslices, LS.slices_per_block, A.sp.get(), A.sw.get(),
+                                                         A.col.get(), A.val.get(), x.get(), f, part2);
+    k_fin_store<<<1, kBlock, 0, ctx->stream>>>(LS.blocks, part2, ctx->red_out + 1);
     OCP_LAUNCH_CHECK();
     k_scatter<<<grid_for(sys->nv, 256), 256, 0, ctx->stream>>>(sys->nv, sys->dof_of_vertex.get(), x.get(), u);
     OCP_LAUNCH_CHECK();
@@ -332,7 +346,11 @@ extern "C" int ocp_spmv(ocp_ctx *ctx, const ocp_system *sys, const double *x, do
     if (!ctx) return OCP_ERR_INVALID_ARG;
     return run_guarded(ctx, [&] {
         if (!sys || !x || !y) fail(OCP_ERR_INVALID_ARG, "system, x and y must not be NULL");
-        spmv_enqueue(ctx, sys->n, sys->row_ptr.get(), sys->col.get(), sys->val.get(), x, y);
+        const Sell &A = system_sell(ctx, sys);
+        const SellLaunch L = sell_launch(A.nslices);
+        k_spmv_sell<<<L.blocks, kBlock, 0, ctx->stream>>>(sys->n, A.nslices, L.slices_per_block, A.sp.get(),
+                                                          A.sw.get(), A.col.get(), A.val.get(), x, y);
+        OCP_LAUNCH_CHECK();
     });
 }
 

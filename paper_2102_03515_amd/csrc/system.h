@@ -4,6 +4,21 @@
 
 #include "common.h"
 
+namespace ocp {
+// Sliced-ELL copy of the fine-level matrix (64-row slices, see kernels.h).
+struct Sell {
+    int32_t n = 0;
+    int64_t nslices = 0;
+    int64_t nnz_padded = 0;
+    DevBuf<int32_t> sp;    // [nslices+1] element offset of each slice
+    DevBuf<int32_t> sw;    // [nslices]   slice width
+    DevBuf<int32_t> col;   // [nnz_padded]
+    DevBuf<double> val;    // [nnz_padded]
+};
+void sell_build(ocp_ctx *ctx, Sell &S, int32_t n, const int32_t *rp, const int32_t *col, const double *val);
+void sell_values32(ocp_ctx *ctx, const Sell &S, const int32_t *rp, const float *val32, DevBuf<float> &out);
+}  // namespace ocp
+
 struct ocp_system {
     ocp_ctx *ctx = nullptr;
     int32_t nv = 0;           // mesh vertices
@@ -19,7 +34,11 @@ struct ocp_system {
     ocp::DevBuf<double> val, valK, valM, f;
     // derived data, rebuilt on demand and dropped when the values change
     ocp::DevBuf<double> dinv;   // 1 / a_ii
-    void invalidate_derived() { dinv.release(); }
+    ocp::Sell sell;             // sliced-ELL copy of A for the solve phase
+    void invalidate_derived() {
+        dinv.release();
+        sell = ocp::Sell();
+    }
 };
 
 namespace ocp {
@@ -39,8 +58,10 @@ struct Level {
     DevBuf<double> dense_inv;  // last level only: A^{-1}, dense row-major
     // single-precision copies (mixed precision)
     DevBuf<float> A_val32, P_val32, R_val32, dinv32, dense_inv32;
+    // level 0: values of the system's sliced-ELL copy in the hierarchy's precision
+    DevBuf<float> sell_val32;
     // V-cycle work vectors in the hierarchy's precision (bytes)
-    DevBuf<char> vb, vr, vr2, vx, vxp;
+    DevBuf<char> vb, vr, vx, vxp, vx1, vx2;
     double lambda_max = 0.0;   // Gershgorin bound of D^-1 A
     // polynomial smoother: first step x = a D^-1 r; degree 2 adds
     // x = D^-1 (c1 r0 + c2 r1) with r1 the residual after the first step
@@ -60,14 +81,13 @@ struct ocp_hierarchy {
 
 namespace ocp {
 // Enqueue z = B r (one V-cycle).  If cg != nullptr the level-0 post-smoother
-// also forms r.z and updates the CG scalars, and every kernel returns at once
-// when cg->flag is set.
+// also forms r.z and updates the CG scalars (through a one-block finalize
+// kernel), and every kernel returns at once when cg->flag is set.
 void vcycle_enqueue(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r, double *z, CgScalars *cg);
-// y = A x on the system's matrix.
-void spmv_enqueue(ocp_ctx *ctx, int32_t n, const int32_t *rp, const int32_t *col, const double *val,
-                  const double *x, double *y);
 // Lanes per row for a matrix with the given average row length.
 int level_lanes(int64_t nnz, int64_t rows);
 // Build 1/a_ii of the system if missing.
 const double *system_dinv(ocp_ctx *ctx, ocp_system *sys);
+// Build the sliced-ELL copy of the system's matrix if missing.
+const Sell &system_sell(ocp_ctx *ctx, const ocp_system *sys);
 }  // namespace ocp

@@ -45,51 +45,83 @@ namespace ocp {
     }                  \
     }
 
-// Residual with the iterate formed on the fly from vectors already in memory:
-//   x_j = [X0_j] + d_j (alpha u_j [+ beta v_j]),   r_i = b_i - sum_j a_ij x_j
-// MODE 0 writes r; MODE 1 writes z_i = [X0_i] + d_i (e1 u_i + e2 r_i) (and with
-// DOT also accumulates b.z for CG).  Every smoothing step of the V-cycle is
-// one instance of this kernel, i.e. one pass over the level matrix.
-template <int G, typename T, typename BT, typename UT, typename OT, bool HX0, bool HU, bool HV, int MODE, bool DOT>
+// One pass over a level matrix: r_i = b_i - sum_j a_ij x_j, where the
+// gathered iterate is either a stored vector (GDB = false: x_j = g_j) or the
+// first smoothing step from zero, rebuilt on the fly (GDB = true:
+// x_j = a d_j b_j).  The epilogue (row i only) writes, by MODE:
+//   kR     out1 = r
+//   kX2    out1 = d_i (c1 b_i + c2 r_i)          second pre-smoothing iterate
+//   kPostA out1 = r, out2 = xp_i + a d_i r_i     post residual and first step
+//   kZ     out1 = xp_i + d_i (c1 u_i + c2 r_i)   last post step (u = r0), and
+//          with DOT also b.out1 for CG
+// so every smoothing step of the V-cycle is one such pass and every pass
+// gathers a single vector.
+enum { kR = 0, kX2 = 1, kPostA = 2, kZ = 3 };
+
+template <typename T, typename BT, typename OT, bool GDB, int MODE, bool DOT>
+struct SmoothOps {
+    const T *d;
+    const BT *b;
+    const T *g;
+    const T *xp;
+    const T *u;
+    T a, c1, c2;
+    OT *out1;
+    T *out2;
+    __device__ __forceinline__ T gather(int c) const {
+        if (GDB) return a * d[c] * (T)b[c];
+        return g[c];
+    }
+    // writes row i's outputs; returns its b.z contribution (DOT)
+    __device__ __forceinline__ double finish(int i, T s) const {
+        const BT bi = b[i];
+        const T r = (T)bi - s;
+        if (MODE == kR) {
+            out1[i] = (OT)r;
+        } else if (MODE == kX2) {
+            out1[i] = (OT)(d[i] * (c1 * (T)bi + c2 * r));
+        } else if (MODE == kPostA) {
+            out1[i] = (OT)r;
+            out2[i] = xp[i] + a * d[i] * r;
+        } else {
+            T w = c2 * r;
+            if (u) w += c1 * u[i];
+            const T z = xp[i] + d[i] * w;
+            out1[i] = (OT)z;
+            if (DOT) return (double)bi * (double)z;
+        }
+        return 0.0;
+    }
+};
+
+template <int G, typename T, typename BT, typename OT, bool GDB, int MODE, bool DOT>
 __global__ void __launch_bounds__(kBlock) k_smooth(int32_t n, int iters, const int32_t *__restrict__ rp,
                                                    const int32_t *__restrict__ col, const T *__restrict__ val,
-                                                   const T *__restrict__ d, const BT *__restrict__ b,
-                                                   const T *__restrict__ x0, const UT *__restrict__ u,
-                                                   const T *__restrict__ v, T alpha, T beta, T e1, T e2,
-                                                   OT *__restrict__ out, CgScalars *cg, double *partials,
-                                                   unsigned *counter) {
+                                                   SmoothOps<T, BT, OT, GDB, MODE, DOT> ops, CgScalars *cg,
+                                                   double *partials) {
     if (cg && cg->flag) return;
     double acc = 0.0;
     OCP_ROWS_BEGIN(G)
-    const T s = dev::row_sum<G>(rp[row], rp[row + 1], lane, col, val, [&](int c) {
-        T x = HX0 ? x0[c] : T(0);
-        if (HU) {
-            T w = alpha * (T)u[c];
-            if (HV) w += beta * v[c];
-            x += d[c] * w;
-        }
-        return x;
-    });
-    if (lane == 0) {
-        const BT bi = b[row];
-        const T r = (T)bi - s;
-        if (MODE == 0) {
-            out[row] = (OT)r;
-        } else {
-            T w = e2 * r;
-            if (HU) w += e1 * (T)u[row];
-            const T z = (HX0 ? x0[row] : T(0)) + d[row] * w;
-            out[row] = (OT)z;
-            if (DOT) acc += (double)bi * (double)z;
-        }
-    }
+    const T s = dev::row_sum<G>(rp[row], rp[row + 1], lane, col, val, [&](int c) { return ops.gather(c); });
+    if (lane == 0) acc += ops.finish(row, s);
     OCP_ROWS_END()
-    if (DOT) {
-        acc = dev::block_sum<kBlock>(acc);
-        double tot;
-        if (dev::grid_sum_last<kBlock>(acc, partials, counter, &tot) && threadIdx.x == 0)
-            dev::cg_after_precond(cg, tot);
-    }
+    if (DOT) dev::store_partial(dev::block_sum<kBlock>(acc), partials);
+}
+
+// the same pass on the sliced-ELL copy of the fine-level matrix
+template <typename T, typename BT, typename OT, bool GDB, int MODE, bool DOT>
+__global__ void __launch_bounds__(kBlock) k_smooth_sell(int32_t n, int64_t nslices, int spb,
+                                                        const int32_t *__restrict__ sp, const int32_t *__restrict__ sw,
+                                                        const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                        SmoothOps<T, BT, OT, GDB, MODE, DOT> ops, CgScalars *cg,
+                                                        double *partials) {
+    if (cg && cg->flag) return;
+    double acc = 0.0;
+    OCP_SELL_BEGIN(nslices, spb)
+    const T s = dev::sell_row(col, val, base, w, [&](int c) { return ops.gather(c); });
+    if (row < n) acc += ops.finish(row, s);
+    OCP_SELL_END()
+    if (DOT) dev::store_partial(dev::block_sum<kBlock>(acc), partials);
 }
 
 // y = M x for a level matrix (restriction with R = P^T)
@@ -105,23 +137,17 @@ __global__ void __launch_bounds__(kBlock) k_vc_spmv(int32_t n, int iters, const 
     OCP_ROWS_END()
 }
 
-// xp = d .* (alpha b [+ beta v]) + P xc: the pre-smoothed iterate rebuilt from
-// the vectors that defined it, plus the coarse-grid correction
-template <int G, typename T, typename BT, bool HV>
+// xp = base + P xc, base = the stored pre-smoothed iterate (HX) or a d .* b
+template <int G, typename T, typename BT, bool HX>
 __global__ void __launch_bounds__(kBlock) k_vc_prolong(int32_t n, int iters, const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ col, const T *__restrict__ val,
                                                        const T *__restrict__ d, const BT *__restrict__ b,
-                                                       const T *__restrict__ v, T alpha, T beta,
-                                                       const T *__restrict__ xc, T *__restrict__ xp,
-                                                       const CgScalars *cg) {
+                                                       const T *__restrict__ xs, T a, const T *__restrict__ xc,
+                                                       T *__restrict__ xp, const CgScalars *cg) {
     if (cg && cg->flag) return;
     OCP_ROWS_BEGIN(G)
     const T s = dev::row_sum<G>(rp[row], rp[row + 1], lane, col, val, [&](int c) { return xc[c]; });
-    if (lane == 0) {
-        T w = alpha * (T)b[row];
-        if (HV) w += beta * v[row];
-        xp[row] = d[row] * w + s;
-    }
+    if (lane == 0) xp[row] = (HX ? xs[row] : a * d[row] * (T)b[row]) + s;
     OCP_ROWS_END()
 }
 
@@ -150,8 +176,7 @@ __global__ void k_vc_diag(int32_t n, const T *__restrict__ d, const BT *__restri
 
 // r.z after a one-level "cycle"
 __global__ void __launch_bounds__(kBlock) k_cg_rz(int32_t n, int iters, const double *__restrict__ r,
-                                                  const double *__restrict__ z, CgScalars *cg, double *partials,
-                                                  unsigned *counter) {
+                                                  const double *__restrict__ z, CgScalars *cg, double *partials) {
     if (cg->flag) return;
     const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
     const int base = (int)tile * kBlock * iters;
@@ -160,9 +185,13 @@ __global__ void __launch_bounds__(kBlock) k_cg_rz(int32_t n, int iters, const do
         const int i = base + it * kBlock + threadIdx.x;
         if (i < n) acc += r[i] * z[i];
     }
-    acc = dev::block_sum<kBlock>(acc);
-    double tot;
-    if (dev::grid_sum_last<kBlock>(acc, partials, counter, &tot) && threadIdx.x == 0) dev::cg_after_precond(cg, tot);
+    dev::store_partial(dev::block_sum<kBlock>(acc), partials);
+}
+
+__global__ void __launch_bounds__(kBlock) k_vc_fin_rz(unsigned nb, const double *partials, CgScalars *cg) {
+    if (cg->flag) return;
+    const double tot = dev::sum_partials<kBlock>(partials, nb);
+    if (threadIdx.x == 0) dev::cg_after_precond(cg, tot);
 }
 
 // ------------------------------------------------------------------ driver
@@ -170,6 +199,17 @@ template <typename T>
 struct LevelArrays {
     const T *A, *P, *R, *d, *inv;
 };
+
+template <typename T>
+static const T *sell_values(const ocp_hierarchy *h, const Sell &S);
+template <>
+const double *sell_values<double>(const ocp_hierarchy *h, const Sell &S) {
+    return S.val.get();
+}
+template <>
+const float *sell_values<float>(const ocp_hierarchy *h, const Sell &S) {
+    return h->levels[0]->sell_val32.get();
+}
 
 template <typename T>
 static LevelArrays<T> arrays(const Level &L);
@@ -195,8 +235,9 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
     const int L = (int)lv.size();
     hipStream_t s = ctx->stream;
     double *part = ctx->red_partials + 3 * kRedBlocks;
-    unsigned *cnt = ctx->red_counters + 3;
-    const T zero = T(0);
+    const Sell &S = system_sell(ctx, h->sys);
+    const T *sval = sell_values<T>(h, S);
+    const SellLaunch LSL = sell_launch(S.nslices);
 
     if (L == 1) {
         const Level &l0 = *lv[0];
@@ -208,11 +249,32 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
         OCP_LAUNCH_CHECK();
         if (cg) {
             const RowLaunch LV = vec_launch(l0.n);
-            k_cg_rz<<<LV.blocks, kBlock, 0, s>>>(l0.n, LV.iters, r_in, z_out, cg, part, cnt);
+            k_cg_rz<<<LV.blocks, kBlock, 0, s>>>(l0.n, LV.iters, r_in, z_out, cg, part);
+            k_vc_fin_rz<<<1, kBlock, 0, s>>>(LV.blocks, part, cg);
             OCP_LAUNCH_CHECK();
         }
         return;
     }
+
+    // one pass over level l's matrix (sliced ELL on level 0, CSR with G lanes
+    // per row on the coarser levels)
+    auto pass = [&](int l, auto ops, bool dot) {
+        const Level &cur = *lv[l];
+        unsigned nb;
+        if (l == 0) {
+            nb = LSL.blocks;
+            k_smooth_sell<<<LSL.blocks, kBlock, 0, s>>>(S.n, S.nslices, LSL.slices_per_block, S.sp.get(), S.sw.get(),
+                                                         S.col.get(), sval, ops, cg, dot ? part : nullptr);
+        } else {
+            const auto a = arrays<T>(cur);
+            const RowLaunch LA = row_launch(cur.n, cur.gA);
+            nb = LA.blocks;
+            OCP_DISPATCH_G(cur.gA, (k_smooth<G><<<LA.blocks, kBlock, 0, s>>>(cur.n, LA.iters, cur.A_rp, cur.A_col,
+                                                                            a.A, ops, cg, dot ? part : nullptr)));
+        }
+        OCP_LAUNCH_CHECK();
+        return nb;
+    };
 
     // ---- down: pre-smoothing from zero, residual, restriction
     auto down = [&](int l, auto bptr) {
@@ -220,31 +282,31 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
         const Level &cur = *lv[l];
         const Level &nxt = *lv[l + 1];
         const auto a = arrays<T>(cur);
-        T *r1 = reinterpret_cast<T *>(cur.vr.get());
-        T *r2 = reinterpret_cast<T *>(cur.vr2.get());
-        const RowLaunch LA = row_launch(cur.n, cur.gA);
+        T *rres = reinterpret_cast<T *>(cur.vr.get());
+        T *x2 = reinterpret_cast<T *>(cur.vx2.get());
         const T ca = (T)cur.cheb_a, c1 = (T)cur.cheb_c1, c2 = (T)cur.cheb_c2;
-        const int pr = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_PRE0) : -1;
-        OCP_DISPATCH_G(cur.gA, (k_smooth<G, T, BT, BT, T, false, true, false, 0, false><<<LA.blocks, kBlock, 0, s>>>(
-                                   cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, bptr, nullptr, bptr, nullptr, ca,
-                                   zero, zero, zero, r1, cg, nullptr, nullptr)));
-        prof_end(ctx, pr);
-        OCP_LAUNCH_CHECK();
-        const T *rr = r1;
         if (cur.deg == 2) {
+            // x2 = D^-1 (c1 b + c2 r1), r1 = b - A (a D^-1 b); then r2 = b - A x2
+            const int pr = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_PRE0) : -1;
+            pass(l, SmoothOps<T, BT, T, true, kX2, false>{a.d, bptr, nullptr, nullptr, nullptr, ca, c1, c2, x2, nullptr},
+                 false);
+            prof_end(ctx, pr);
             const int pr2 = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_PRE0_B) : -1;
-            OCP_DISPATCH_G(cur.gA, (k_smooth<G, T, BT, BT, T, false, true, true, 0, false><<<LA.blocks, kBlock, 0, s>>>(
-                                       cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, bptr, nullptr, bptr, r1, c1, c2,
-                                       zero, zero, r2, cg, nullptr, nullptr)));
+            pass(l, SmoothOps<T, BT, T, false, kR, false>{a.d, bptr, x2, nullptr, nullptr, ca, c1, c2, rres, nullptr},
+                 false);
             prof_end(ctx, pr2);
-            OCP_LAUNCH_CHECK();
-            rr = r2;
+        } else {
+            // r1 = b - A (a D^-1 b)
+            const int pr = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_PRE0) : -1;
+            pass(l, SmoothOps<T, BT, T, true, kR, false>{a.d, bptr, nullptr, nullptr, nullptr, ca, c1, c2, rres, nullptr},
+                 false);
+            prof_end(ctx, pr);
         }
         T *bn = reinterpret_cast<T *>(nxt.vb.get());
         const RowLaunch LR = row_launch(nxt.n, cur.gR);
         const int prr = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_RESTRICT0) : -1;
         OCP_DISPATCH_G(cur.gR, (k_vc_spmv<G, T><<<LR.blocks, kBlock, 0, s>>>(nxt.n, LR.iters, cur.R_rp.get(),
-                                                                              cur.R_col.get(), a.R, rr, bn, cg)));
+                                                                              cur.R_col.get(), a.R, rres, bn, cg)));
         prof_end(ctx, prr);
         OCP_LAUNCH_CHECK();
     };
@@ -267,6 +329,7 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
         OCP_LAUNCH_CHECK();
     }
     // ---- up: prolongation + correction, post-smoothing
+    unsigned fin_nb = 0;
     auto up = [&](int l, auto bptr, auto outptr, bool dot) {
         using BT = std::remove_const_t<std::remove_pointer_t<decltype(bptr)>>;
         using OT = std::remove_pointer_t<decltype(outptr)>;
@@ -275,63 +338,62 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
         const auto a = arrays<T>(cur);
         const T *xc = reinterpret_cast<const T *>(nxt.vx.get());
         T *xp = reinterpret_cast<T *>(cur.vxp.get());
-        T *r1 = reinterpret_cast<T *>(cur.vr.get());
-        T *r0 = reinterpret_cast<T *>(cur.vr2.get());
+        T *x2 = reinterpret_cast<T *>(cur.vx2.get());
+        T *r0 = reinterpret_cast<T *>(cur.vr.get());
+        T *x1 = reinterpret_cast<T *>(cur.vx1.get());
         const T ca = (T)cur.cheb_a, c1 = (T)cur.cheb_c1, c2 = (T)cur.cheb_c2;
+        const T zero = T(0);
         const RowLaunch LP = row_launch(cur.n, cur.gP);
-        const RowLaunch LA = row_launch(cur.n, cur.gA);
         const int prp = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_PROLONG0) : -1;
         if (cur.deg == 2) {
             OCP_DISPATCH_G(cur.gP, (k_vc_prolong<G, T, BT, true><<<LP.blocks, kBlock, 0, s>>>(
-                                       cur.n, LP.iters, cur.P_rp.get(), cur.P_col.get(), a.P, a.d, bptr, r1, c1, c2,
-                                       xc, xp, cg)));
+                                       cur.n, LP.iters, cur.P_rp.get(), cur.P_col.get(), a.P, a.d, bptr, x2, ca, xc, xp,
+                                       cg)));
         } else {
             OCP_DISPATCH_G(cur.gP, (k_vc_prolong<G, T, BT, false><<<LP.blocks, kBlock, 0, s>>>(
                                        cur.n, LP.iters, cur.P_rp.get(), cur.P_col.get(), a.P, a.d, bptr, nullptr, ca,
-                                       zero, xc, xp, cg)));
+                                       xc, xp, cg)));
         }
         prof_end(ctx, prp);
         OCP_LAUNCH_CHECK();
-        int pro = -1;
         if (cur.deg == 2) {
-            // r0 = b - A xp, then z = xp + D^-1 (c1 r0 + c2 r1) with r1 = b - A (xp + a D^-1 r0)
+            // r0 = b - A xp and x1 = xp + a D^-1 r0; then r1 = b - A x1 and
+            // z = xp + D^-1 (c1 r0 + c2 r1)
             const int pra = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_POST0_A) : -1;
-            OCP_DISPATCH_G(cur.gA, (k_smooth<G, T, BT, T, T, true, false, false, 0, false><<<LA.blocks, kBlock, 0, s>>>(
-                                       cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, bptr, xp, nullptr, nullptr,
-                                       zero, zero, zero, zero, r0, cg, nullptr, nullptr)));
+            pass(l, SmoothOps<T, BT, T, false, kPostA, false>{a.d, bptr, xp, xp, nullptr, ca, c1, c2, r0, x1}, false);
             prof_end(ctx, pra);
-            OCP_LAUNCH_CHECK();
-            pro = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_POST0) : -1;
-            if (dot) {
-                OCP_DISPATCH_G(cur.gA, (k_smooth<G, T, BT, T, OT, true, true, false, 1, true><<<LA.blocks, kBlock, 0, s>>>(
-                                           cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, bptr, xp, r0, nullptr, ca,
-                                           zero, c1, c2, outptr, cg, part, cnt)));
-            } else {
-                OCP_DISPATCH_G(cur.gA, (k_smooth<G, T, BT, T, OT, true, true, false, 1, false><<<LA.blocks, kBlock, 0, s>>>(
-                                           cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, bptr, xp, r0, nullptr, ca,
-                                           zero, c1, c2, outptr, cg, nullptr, nullptr)));
-            }
+            const int pro = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_POST0) : -1;
+            if (dot)
+                fin_nb = pass(l, SmoothOps<T, BT, OT, false, kZ, true>{a.d, bptr, x1, xp, r0, ca, c1, c2, outptr,
+                                                                       nullptr},
+                              true);
+            else
+                pass(l, SmoothOps<T, BT, OT, false, kZ, false>{a.d, bptr, x1, xp, r0, ca, c1, c2, outptr, nullptr},
+                     false);
+            prof_end(ctx, pro);
         } else {
             // z = xp + a D^-1 (b - A xp)
-            pro = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_POST0) : -1;
-            if (dot) {
-                OCP_DISPATCH_G(cur.gA, (k_smooth<G, T, BT, T, OT, true, false, false, 1, true><<<LA.blocks, kBlock, 0, s>>>(
-                                           cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, bptr, xp, nullptr, nullptr,
-                                           zero, zero, zero, ca, outptr, cg, part, cnt)));
-            } else {
-                OCP_DISPATCH_G(cur.gA, (k_smooth<G, T, BT, T, OT, true, false, false, 1, false><<<LA.blocks, kBlock, 0, s>>>(
-                                           cur.n, LA.iters, cur.A_rp, cur.A_col, a.A, a.d, bptr, xp, nullptr, nullptr,
-                                           zero, zero, zero, ca, outptr, cg, nullptr, nullptr)));
-            }
+            const int pro = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_POST0) : -1;
+            if (dot)
+                fin_nb = pass(l, SmoothOps<T, BT, OT, false, kZ, true>{a.d, bptr, xp, xp, nullptr, ca, zero, ca, outptr,
+                                                                       nullptr},
+                              true);
+            else
+                pass(l, SmoothOps<T, BT, OT, false, kZ, false>{a.d, bptr, xp, xp, nullptr, ca, zero, ca, outptr,
+                                                               nullptr},
+                     false);
+            prof_end(ctx, pro);
         }
-        prof_end(ctx, pro);
-        OCP_LAUNCH_CHECK();
     };
     for (int l = L - 2; l >= 0; --l) {
         if (l == 0)
             up(0, r_in, z_out, cg != nullptr);
         else
             up(l, reinterpret_cast<const T *>(lv[l]->vb.get()), reinterpret_cast<T *>(lv[l]->vx.get()), false);
+    }
+    if (cg) {
+        k_vc_fin_rz<<<1, kBlock, 0, s>>>(fin_nb, part, cg);
+        OCP_LAUNCH_CHECK();
     }
 }
 

@@ -311,3 +311,18 @@ def test_assembled_matrix_is_bitwise_symmetric(P, ctx):
     D = (A - A.T).tocoo()
     print(f"    asymmetric entries {(A != A.T.tocsr()).nnz}, max |a_ij - a_ji| {abs(D.data).max() if D.nnz else 0.0}")
     assert (A != A.T.tocsr()).nnz == 0
+
+
+def test_spmv_ragged_sizes(P, ctx):
+    """The sliced fine-level SpMV on sizes whose row count is not a multiple
+    of the 64-row slice (and a single slice), jittered and not."""
+    import torch
+    for N, jit in ((2, 0.0), (3, 0.15), (5, 0.15), (9, 0.0)):
+        print(f"[spmv ragged] N={N} jitter={jit}", flush=True)
+        mesh = I.kuhn_mesh(N, jitter=jit, seed=N)
+        s, _ = _gpu_system(P, ctx, mesh, 0.3, I.single_sine())
+        o = O.assemble(mesh, 0.3, I.single_sine())
+        x = np.random.default_rng(N).standard_normal(o.n)
+        y = s.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
+        bound = 32 * 2.2e-16 * np.abs(o.val).max() * np.abs(x).max()
+        assert np.abs(y - O.spmv(o, x)).max() <= bound

@@ -8,7 +8,8 @@ as smoothed aggregation; this module states that construction plainly, one
 definition per function, so that the GPU setup can be compared with it:
 
   strength     j is a strong neighbour of i  iff  j != i, a_ij != 0 and
-               |a_ij| >= theta * sqrt(a_ii * a_jj)
+               |a_ij| >= theta * sqrt(a_ii * a_jj); for theta = 0 every
+               off-diagonal entry of the sparsity pattern is strong
   priority     p(i) = lowbias32(i XOR salt) >> 2, where lowbias32 is the
                published 32-bit integer hash  x ^= x>>16; x *= 0x7feb352d;
                x ^= x>>15; x *= 0x846ca68b; x ^= x>>16  (C. Wellons), and the
@@ -61,7 +62,9 @@ def strong_neighbours(A: sp.csr_matrix, theta: float):
         lo, hi = A.indptr[i], A.indptr[i + 1]
         nb = []
         for j, a in zip(A.indices[lo:hi], A.data[lo:hi]):
-            if j != i and a != 0.0 and abs(a) >= theta * np.sqrt(d[i] * d[j]):
+            if j == i:
+                continue
+            if theta == 0.0 or (a != 0.0 and abs(a) >= theta * np.sqrt(d[i] * d[j])):
                 nb.append(int(j))
         out.append(nb)
     return out

@@ -6,7 +6,9 @@
 // A_c = P^T A P recursively.  Here the same three ingredients are realised as
 // smoothed aggregation:
 //
-//   strength   j ~ i  if  |a_ij| >= theta * sqrt(a_ii a_jj)
+//   strength   j ~ i  if  |a_ij| >= theta * sqrt(a_ii a_jj), a_ij != 0;
+//              theta = 0 (the default) makes every off-diagonal entry of
+//              the pattern strong
 //   coarsening roots = a maximal distance-2 independent set of the strength
 //              graph, chosen greedily in the order of a fixed hash priority
 //              (the parallel rounds below select exactly the set the
@@ -23,6 +25,7 @@
 // entry in a fixed order.  The last level (n <= coarse_max) is inverted
 // densely with Gauss-Jordan elimination in one workgroup.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include "kernels.h"
@@ -90,6 +93,12 @@ __global__ void k_strength(int32_t n, const int32_t *__restrict__ rp, const int3
     }
 }
 
+// Strength flag of entry k (column j) of row i; with theta = 0 there is no
+// flag array and every off-diagonal entry of the pattern is strong.
+__device__ __forceinline__ bool is_strong(const uint8_t *__restrict__ strong, int k, int j, int i) {
+    return strong ? strong[k] != 0 : j != i;
+}
+
 // ------------------------------------------------------------------- MIS-2
 // Round of the distance-2 independent set, G lanes per row:
 //   m1[i] = max key over i and its strong neighbours
@@ -114,12 +123,13 @@ __global__ void __launch_bounds__(256) k_mis_m1(int32_t n, const int32_t *__rest
     const int i = (int)(t / G), lane = (int)(t % G);
     if (i >= n) return;
     uint64_t m = 0;
-    for (int k = rp[i] + lane; k < rp[i + 1]; k += G)
-        if (strong[k]) {
-            const int j = col[k];
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += G) {
+        const int j = col[k];
+        if (is_strong(strong, k, j, i)) {
             const uint64_t kj = mis_key(j, state[j], salt);
             m = kj > m ? kj : m;
         }
+    }
     m = group_max_u64<G>(m);
     if (lane == 0) {
         const uint64_t ki = mis_key(i, state[i], salt);
@@ -137,11 +147,13 @@ __global__ void __launch_bounds__(256) k_mis_m2(int32_t n, const int32_t *__rest
     if (i >= n) return;
     if (state[i] != 0) return;   // uniform over the group
     uint64_t m = 0;
-    for (int k = rp[i] + lane; k < rp[i + 1]; k += G)
-        if (strong[k]) {
-            const uint64_t v = m1[col[k]];
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += G) {
+        const int j = col[k];
+        if (is_strong(strong, k, j, i)) {
+            const uint64_t v = m1[j];
             m = v > m ? v : m;
         }
+    }
     m = group_max_u64<G>(m);
     bool still = false;
     if (lane == 0) {
@@ -179,9 +191,9 @@ __global__ void k_agg1(int32_t n, const int32_t *__restrict__ rp, const int32_t 
     }
     uint64_t best = 0;
     int bj = -1;
-    for (int k = rp[i]; k < rp[i + 1]; ++k)
-        if (strong[k]) {
-            const int j = col[k];
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = col[k];
+        if (is_strong(strong, k, j, i)) {
             if (state[j] == 1) {
                 const uint64_t kj = mis_key(j, 1, salt);
                 if (kj > best) {
@@ -190,6 +202,7 @@ __global__ void k_agg1(int32_t n, const int32_t *__restrict__ rp, const int32_t 
                 }
             }
         }
+    }
     agg[i] = bj >= 0 ? root_pos[bj] : -1;
     assigned[i] = bj >= 0 ? 2 : 0;
 }
@@ -203,9 +216,9 @@ __global__ void k_agg2(int32_t n, const int32_t *__restrict__ rp, const int32_t 
     if (assigned[i] != 0) return;
     uint64_t best = 0;
     int bj = -1;
-    for (int k = rp[i]; k < rp[i + 1]; ++k)
-        if (strong[k]) {
-            const int j = col[k];
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = col[k];
+        if (is_strong(strong, k, j, i)) {
             if (assigned[j] == 2) {
                 const uint64_t kj = mis_key(j, 2, salt);
                 if (kj > best) {
@@ -214,6 +227,7 @@ __global__ void k_agg2(int32_t n, const int32_t *__restrict__ rp, const int32_t 
                 }
             }
         }
+    }
     if (bj < 0) {
         atomicOr(flag, 16);
         return;
@@ -277,32 +291,34 @@ __global__ void k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp, const in
 }
 
 constexpr int kSpgemmClasses = 5;
-__constant__ int c_class_ub[kSpgemmClasses - 1] = {16, 64, 256, 1024};
+struct ClassBounds {
+    int lim[kSpgemmClasses - 1];   // class q holds keys <= lim[q]; the last class the rest
+};
 
-// Row lists per size class; one atomic per class per wavefront.
-__global__ void k_bin_rows(int32_t m, const int32_t *__restrict__ ub, int32_t *__restrict__ counts,
-                           int32_t *__restrict__ lists) {
+// Row lists per size class.  Positions are reserved with LDS atomics inside
+// the block and one global atomic per class per block.
+__global__ void __launch_bounds__(256) k_bin_rows(int32_t m, const int32_t *__restrict__ key, ClassBounds cb,
+                                                  int32_t *__restrict__ counts, int32_t *__restrict__ lists) {
+    __shared__ int lcnt[kSpgemmClasses], lbase[kSpgemmClasses];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    int c = kSpgemmClasses;
+    if (threadIdx.x < kSpgemmClasses) lcnt[threadIdx.x] = 0;
+    __syncthreads();
+    int c = 0, lpos = 0;
     if (i < m) {
-        const int u = ub[i];
+        const int u = key[i];
         c = kSpgemmClasses - 1;
         for (int q = 0; q < kSpgemmClasses - 1; ++q)
-            if (u <= c_class_ub[q]) {
+            if (u <= cb.lim[q]) {
                 c = q;
                 break;
             }
+        lpos = atomicAdd(&lcnt[c], 1);
     }
-    for (int q = 0; q < kSpgemmClasses; ++q) {
-        const unsigned long long mask = __ballot(c == q);
-        if (mask == 0ull) continue;
-        const int leader = __ffsll((long long)mask) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&counts[q], __popcll(mask));
-        base = __shfl(base, leader, 64);
-        if (c == q) lists[(int64_t)q * m + base + __popcll(mask & ((1ull << lane) - 1ull))] = i;
-    }
+    __syncthreads();
+    if (threadIdx.x < kSpgemmClasses && lcnt[threadIdx.x] > 0)
+        lbase[threadIdx.x] = atomicAdd(&counts[threadIdx.x], lcnt[threadIdx.x]);
+    __syncthreads();
+    if (i < m) lists[(int64_t)c * m + lbase[c] + lpos] = i;
 }
 
 template <int H>
@@ -328,7 +344,7 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
                                                    const int32_t *__restrict__ bcol, const double *__restrict__ bval,
                                                    const int32_t *__restrict__ crp, int32_t *__restrict__ cnt,
                                                    int32_t *__restrict__ ccol, double *__restrict__ cval,
-                                                   int32_t *flag) {
+                                                   int32_t *flag, int32_t *retry, int32_t *nretry) {
     constexpr int RPW = 64 / G;
     __shared__ int keys[RPW][H];
     __shared__ double vals[NUMERIC ? RPW : 1][NUMERIC ? H : 1];
@@ -361,7 +377,12 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
     if (!NUMERIC) {
         if (active && lane == 0) {
             cnt[i] = count[g];
-            if (count[g] > (3 * H) / 4) atomicOr(flag, 32);
+            if (count[g] > (3 * H) / 4) {
+                if (retry)
+                    retry[atomicAdd(nretry, 1)] = i;   // recount with a larger table
+                else
+                    atomicOr(flag, 32);
+            }
         }
         return;
     }
@@ -392,13 +413,104 @@ struct Csr {
 template <int G, int H, bool NUMERIC>
 static void launch_grp(ocp_ctx *ctx, const int32_t *rows, int32_t nrows, const int32_t *arp, const int32_t *acol,
                        const double *aval, const int32_t *brp, const int32_t *bcol, const double *bval,
-                       const int32_t *crp, int32_t *cnt, int32_t *ccol, double *cval) {
+                       const int32_t *crp, int32_t *cnt, int32_t *ccol, double *cval, int32_t *retry = nullptr,
+                       int32_t *nretry = nullptr) {
     if (nrows <= 0) return;
     constexpr int RPW = 64 / G;
     const unsigned blocks = (unsigned)((nrows + RPW - 1) / RPW);
     k_spgemm_grp<G, H, NUMERIC><<<blocks, 64, 0, ctx->stream>>>(rows, nrows, arp, acol, aval, brp, bcol, bval, crp,
-                                                                 cnt, ccol, cval, ctx->dev_flag);
+                                                                 cnt, ccol, cval, ctx->dev_flag, retry, nretry);
     OCP_LAUNCH_CHECK();
+}
+
+__global__ void k_row_len(int32_t m, const int32_t *__restrict__ rp, double *__restrict__ len) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) len[i] = (double)(rp[i + 1] - rp[i]);
+}
+
+static int csr_max_row(ocp_ctx *ctx, int32_t m, const int32_t *rp) {
+    DevBuf<double> len(ctx, (size_t)std::max(m, 1));
+    k_row_len<<<grid_for(m, 256), 256, 0, ctx->stream>>>(m, rp, len.get());
+    OCP_LAUNCH_CHECK();
+    return (int)reduce_max_abs(ctx, len.get(), m);
+}
+
+// C = A P_tent (one entry per row of P_tent: column agg[j], value pt[j]),
+// one thread per row with up to 16 distinct columns held in registers;
+// entries accumulate in the order of the A row and are sorted by a network.
+template <bool NUMERIC>
+__global__ void __launch_bounds__(256) k_ap_tent(int32_t m, const int32_t *__restrict__ arp,
+                                                 const int32_t *__restrict__ acol, const double *__restrict__ aval,
+                                                 const int32_t *__restrict__ agg, const double *__restrict__ pt,
+                                                 const int32_t *__restrict__ crp, int32_t *__restrict__ cnt,
+                                                 int32_t *__restrict__ ccol, double *__restrict__ cval,
+                                                 int32_t *flag) {
+    constexpr int S = 16;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int keys[S];
+    double acc[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        keys[q] = INT_MAX;
+        acc[q] = 0.0;
+    }
+    int nk = 0;
+    for (int k = arp[i]; k < arp[i + 1]; ++k) {
+        const int j = acol[k];
+        const int J = agg[j];
+        const double v = NUMERIC ? aval[k] * pt[j] : 0.0;
+        bool found = false;
+#pragma unroll
+        for (int q = 0; q < S; ++q)
+            if (keys[q] == J) {
+                acc[q] += v;
+                found = true;
+            }
+        if (!found) {
+            if (nk == S) {
+                atomicOr(flag, 32);
+                return;
+            }
+#pragma unroll
+            for (int q = 0; q < S; ++q)
+                if (q == nk) {
+                    keys[q] = J;
+                    acc[q] = v;
+                }
+            ++nk;
+        }
+    }
+    if (!NUMERIC) {
+        cnt[i] = nk;
+        return;
+    }
+    // bitonic sort of the 16 (key, value) pairs, unused keys are INT_MAX
+#pragma unroll
+    for (int kk = 2; kk <= S; kk <<= 1)
+#pragma unroll
+        for (int jj = kk >> 1; jj > 0; jj >>= 1)
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int l = q ^ jj;
+                if (l > q) {
+                    const bool up = (q & kk) == 0;
+                    const bool sw = up ? (keys[q] > keys[l]) : (keys[q] < keys[l]);
+                    const int tk = keys[q];
+                    const double tv = acc[q];
+                    keys[q] = sw ? keys[l] : keys[q];
+                    acc[q] = sw ? acc[l] : acc[q];
+                    keys[l] = sw ? tk : keys[l];
+                    acc[l] = sw ? tv : acc[l];
+                }
+            }
+    const int b = crp[i];
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+        if (q < nk) {
+            ccol[b + q] = keys[q];
+            cval[b + q] = acc[q];
+        }
 }
 
 template <bool NUMERIC>
@@ -422,14 +534,29 @@ static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, c
     DevBuf<int32_t> counts(ctx, 8);
     fill_zero_bytes(ctx, counts.get(), 32);
     DevBuf<int32_t> lists(ctx, (size_t)kSpgemmClasses * m);
-    k_bin_rows<<<grid_for(m, 256), 256, 0, s>>>(m, ub.get(), counts.get(), lists.get());
+    // symbolic: table sized by the product bound, large bounds first try 512
+    // slots and recount in 4096 slots when more than 384 columns show up
+    const ClassBounds sym{{16, 64, INT_MAX - 1, INT_MAX - 1}};
+    k_bin_rows<<<grid_for(m, 256), 256, 0, s>>>(m, ub.get(), sym, counts.get(), lists.get());
     OCP_LAUNCH_CHECK();
     int32_t hc[8];
     read_back(ctx, hc, counts.get(), 32);
     DevBuf<int32_t> cnt(ctx, (size_t)m + 1);
+    DevBuf<int32_t> retry(ctx, (size_t)std::max(hc[2], 1) + 1);
+    fill_zero_bytes(ctx, retry.get() + std::max(hc[2], 1), 4);
     fill_zero_bytes(ctx, ctx->dev_flag, 4);
-    spgemm_pass<false>(ctx, lists.get(), hc, m, arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(), nullptr,
-                       nullptr);
+    const int64_t M = m;
+    launch_grp<4, 32, false>(ctx, lists.get(), hc[0], arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(), nullptr,
+                             nullptr);
+    launch_grp<8, 128, false>(ctx, lists.get() + M, hc[1], arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
+                              nullptr, nullptr);
+    launch_grp<16, 512, false>(ctx, lists.get() + 2 * M, hc[2], arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
+                               nullptr, nullptr, retry.get(), retry.get() + std::max(hc[2], 1));
+    int32_t nretry = 0;
+    read_back(ctx, &nretry, retry.get() + std::max(hc[2], 1), 4);
+    if (nretry > 0)
+        launch_grp<64, 4096, false>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
+                                    nullptr, nullptr);
     int32_t fl = 0;
     read_back(ctx, &fl, ctx->dev_flag, 4);
     if (fl & 32) fail(OCP_ERR_UNSUPPORTED, "sparse product row with more than 3072 entries");
@@ -439,13 +566,38 @@ static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, c
     C.nnz = scan_exclusive(ctx, cnt.get(), C.rp.get(), m);
     C.col.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
     C.val.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
-    // the numeric pass sizes each row's table by its exact distinct count
+    // numeric: table sized by the exact distinct count
     fill_zero_bytes(ctx, counts.get(), 32);
-    k_bin_rows<<<grid_for(m, 256), 256, 0, s>>>(m, cnt.get(), counts.get(), lists.get());
+    const ClassBounds num{{16, 64, 256, 1024}};
+    k_bin_rows<<<grid_for(m, 256), 256, 0, s>>>(m, cnt.get(), num, counts.get(), lists.get());
     OCP_LAUNCH_CHECK();
     read_back(ctx, hc, counts.get(), 32);
     spgemm_pass<true>(ctx, lists.get(), hc, m, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr, C.col.get(),
                       C.val.get());
+}
+
+// C = A P_tent: the register kernel when every A row has at most 16 entries,
+// otherwise the general product with P_tent as a CSR matrix
+static void spgemm_ptent(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, const int32_t *acol,
+                         const double *aval, const int32_t *agg, const int32_t *trp, const double *pt, Csr &C) {
+    if (csr_max_row(ctx, m, arp) > 16) {
+        spgemm(ctx, m, ncols, arp, acol, aval, trp, agg, pt, C);
+        return;
+    }
+    DevBuf<int32_t> cnt(ctx, (size_t)m + 1);
+    fill_zero_bytes(ctx, ctx->dev_flag, 4);
+    k_ap_tent<false><<<grid_for(m, 256), 256, 0, ctx->stream>>>(m, arp, acol, aval, agg, pt, nullptr, cnt.get(),
+                                                                nullptr, nullptr, ctx->dev_flag);
+    OCP_LAUNCH_CHECK();
+    C.rows = m;
+    C.cols = ncols;
+    C.rp.reset(ctx, (size_t)m + 1);
+    C.nnz = scan_exclusive(ctx, cnt.get(), C.rp.get(), m);
+    C.col.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
+    C.val.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
+    k_ap_tent<true><<<grid_for(m, 256), 256, 0, ctx->stream>>>(m, arp, acol, aval, agg, pt, C.rp.get(), nullptr,
+                                                               C.col.get(), C.val.get(), ctx->dev_flag);
+    OCP_LAUNCH_CHECK();
 }
 
 // --------------------------------------------------------------- transpose
@@ -616,9 +768,12 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
         DevBuf<uint8_t> strong;
         if (!last) {
             // strength and distance-2 maximal independent set
-            strong.reset(ctx, (size_t)L.nnzA);
-            k_strength<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, L.A_val, diag.get(), pr.theta, strong.get());
-            OCP_LAUNCH_CHECK();
+            if (pr.theta > 0.0) {
+                strong.reset(ctx, (size_t)L.nnzA);
+                k_strength<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, L.A_val, diag.get(), pr.theta,
+                                                            strong.get());
+                OCP_LAUNCH_CHECK();
+            }
             DevBuf<int8_t> state(ctx, n);
             fill_zero_bytes(ctx, state.get(), (size_t)n);
             DevBuf<uint64_t> m1(ctx, n);
@@ -690,7 +845,7 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
         OCP_LAUNCH_CHECK();
         // smoothed prolongator P = (I - w D^-1 A) P_tent
         Csr P;
-        spgemm(ctx, n, nc, L.A_rp, L.A_col, L.A_val, trp.get(), tcol.get(), tval.get(), P);
+        spgemm_ptent(ctx, n, nc, L.A_rp, L.A_col, L.A_val, tcol.get(), trp.get(), tval.get(), P);
         const double w = pr.omega / L.lambda_max;
         k_smooth_p<<<grid_for(n, 256), 256, 0, s>>>(n, P.rp.get(), P.col.get(), P.val.get(), diag.get(), L.agg.get(),
                                                     tval.get(), w);

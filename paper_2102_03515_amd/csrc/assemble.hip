@@ -1,9 +1,9 @@
 // Finite element assembly of A = rho*K + M and f = (int ubar phi_i) into CSR
 // (Section 3, system (linsys) and the entries K_ij, M_ij, f_i defined there).
 //
-// Row-owned, atomic-free on values: every interior vertex owns its row; the
-// lanes of its group recompute the element entries of its incident
-// tetrahedra on the fly and sum them in a fixed order.  The result is
+// Row-owned, atomic-free on values: every interior vertex owns its row and
+// recomputes the element entries of its incident tetrahedra on the fly,
+// summing them in ascending tet id.  The result is
 // bitwise deterministic (and A bitwise symmetric).
 //
 //   1. per tet: index/degeneracy checks, incidence counts   (int atomics)
@@ -190,12 +190,13 @@ __global__ void k_dof_maps(const uint8_t *__restrict__ dirichlet, const int32_t 
 // pass 1: write the sorted list to col[row_ptr[i] ..] (only needed when some
 //         row exceeded kPadW)
 constexpr int kPadW = 32;
+template <int CAP>
 __global__ void __launch_bounds__(kAsmBlock) k_row_symbolic(
     int pass, int32_t n, const int32_t *__restrict__ vertex_of_dof, const int32_t *__restrict__ dof_of_vertex,
     const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc, const int4 *__restrict__ tets,
     int32_t *__restrict__ row_cnt, const int32_t *__restrict__ row_ptr, int32_t *__restrict__ col,
     int32_t *__restrict__ pad, int32_t *__restrict__ flag) {
-    __shared__ int32_t lst[kRowCap][kAsmBlock];
+    __shared__ int32_t lst[CAP][kAsmBlock];
     const int t = threadIdx.x;
     const int i = blockIdx.x * kAsmBlock + t;
     if (i >= n) return;
@@ -212,8 +213,8 @@ __global__ void __launch_bounds__(kAsmBlock) k_row_symbolic(
             int s = cnt - 1;
             while (s >= 0 && lst[s][t] > d) --s;
             if (s >= 0 && lst[s][t] == d) continue;
-            if (cnt == kRowCap) {
-                atomicOr(flag, 4);
+            if (cnt == CAP) {
+                atomicOr(flag, CAP == kRowCap ? 4 : 128);
                 return;
             }
             for (int u = cnt - 1; u > s; --u) lst[u + 1][t] = lst[u][t];
@@ -223,11 +224,8 @@ __global__ void __launch_bounds__(kAsmBlock) k_row_symbolic(
     }
     if (pass == 0) {
         row_cnt[i] = cnt;
-        if (cnt <= kPadW) {
+        if (pad)
             for (int s = 0; s < cnt; ++s) pad[(int64_t)i * kPadW + s] = lst[s][t];
-        } else {
-            atomicOr(flag, 128);
-        }
     } else {
         const int b = row_ptr[i];
         for (int s = 0; s < cnt; ++s) col[b + s] = lst[s][t];
@@ -248,7 +246,6 @@ __global__ void k_pad_to_csr(int32_t n, const int32_t *__restrict__ pad, const i
 struct TargetDev {
     int32_t kind;
     int32_t n_modes;
-    int32_t kmax_table;   // largest wave number handled by the recurrence table
     const int32_t *k;     // device [n_modes][3]
     const double *amp;    // device [n_modes]
     double offset;
@@ -256,18 +253,20 @@ struct TargetDev {
     const double *nodal;  // device [n_vertices]
 };
 
-// ubar(x) for sine modes.  sin(k pi x_d) for k <= kmax_table comes from the
+// ubar(x) for sine modes.  sin(k pi x_d) for k <= kSineTable comes from the
 // three-term recurrence s_{k+1} = 2 cos(pi x) s_k - s_{k-1}, seeded with
-// sinpi/cospi; larger wave numbers call sinpi directly.
+// sincospi, stored in a per-thread LDS table (stride = block size, so a
+// wavefront's reads of one entry are conflict-free); larger wave numbers
+// call sinpi directly.
 __device__ double eval_sine(const TargetDev &t, const double x[3], double *tab, int stride) {
-    const int K = t.kmax_table;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         double s, c;
         sincospi(x[d], &s, &c);
         double sm1 = 0.0, sk = s;
-        for (int k = 1; k <= K; ++k) {
-            tab[(d * kSineTable + (k - 1)) * stride] = sk;
+#pragma unroll
+        for (int k = 0; k < kSineTable; ++k) {
+            tab[(d * kSineTable + k) * stride] = sk;
             const double sn = 2.0 * c * sk - sm1;
             sm1 = sk;
             sk = sn;
@@ -279,14 +278,14 @@ __device__ double eval_sine(const TargetDev &t, const double x[3], double *tab, 
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const int k = t.k[3 * m + d];
-            prod *= (k <= K) ? tab[(d * kSineTable + (k - 1)) * stride] : sinpi((double)k * x[d]);
+            prod *= (k <= kSineTable) ? tab[(d * kSineTable + (k - 1)) * stride] : sinpi((double)k * x[d]);
         }
         u += prod;
     }
     return u;
 }
 
-constexpr int kLoadBlock = 128;
+constexpr int kLoadBlock = 64;
 __global__ void __launch_bounds__(kLoadBlock) k_tet_load(const int4 *__restrict__ tets, int64_t nt,
                                                          const double *__restrict__ xyz, TargetDev tg,
                                                          double4 *__restrict__ fe) {
@@ -310,7 +309,7 @@ __global__ void __launch_bounds__(kLoadBlock) k_tet_load(const int4 *__restrict_
     const double qb = 0.1381966011250105;   // (5 - sqrt5) / 20
     const int vv[4] = {tv.x, tv.y, tv.z, tv.w};
     double f[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
+#pragma unroll 1
     for (int q = 0; q < 4; ++q) {
         double x[3];
 #pragma unroll
@@ -341,12 +340,14 @@ __global__ void __launch_bounds__(kLoadBlock) k_tet_load(const int4 *__restrict_
 }
 
 // ---------------------------------------------------------- 6. numeric rows
-// G lanes per row.  Lane l takes the incident tets with id = l (mod G) in
-// ascending order and accumulates rho*K_e + M_e into register slots (one per
-// row entry, matched by column); the lanes' partial rows are then added in a
-// fixed butterfly order.  Entry (i,j) and entry (j,i) therefore sum the same
+// One thread per row: the incident tets are visited in ascending id and
+// rho*K_e + M_e is accumulated into register slots (one per row entry,
+// matched by column).  Entry (i,j) and entry (j,i) therefore sum the same
 // element terms in the same order: the assembled A is bitwise symmetric.
-constexpr int kNumG = 8;
+// (kNumG > 1 splits the tets of a row over lanes by id mod kNumG and adds the
+// lane sums in a fixed butterfly order, which keeps that property; one lane
+// per row measured fastest.)
+constexpr int kNumG = 1;
 template <int MAXS, bool KM>
 __global__ void __launch_bounds__(256) k_row_numeric(
     int32_t n, double rho, const int32_t *__restrict__ vertex_of_dof, const int32_t *__restrict__ dof_of_vertex,
@@ -501,9 +502,6 @@ static void upload_target(ocp_ctx *ctx, const ocp_target *t, TargetUpload &up) {
         up.amp.reset(ctx, (size_t)m);
         OCP_HIP(hipMemcpyAsync(up.k.get(), t->k, sizeof(int32_t) * 3 * m, hipMemcpyHostToDevice, ctx->stream));
         OCP_HIP(hipMemcpyAsync(up.amp.get(), t->amp, sizeof(double) * m, hipMemcpyHostToDevice, ctx->stream));
-        int kmax = 0;
-        for (int q = 0; q < 3 * m; ++q) kmax = t->k[q] > kmax ? t->k[q] : kmax;
-        up.dev.kmax_table = kmax < kSineTable ? kmax : kSineTable;
         up.dev.n_modes = m;
         up.dev.k = up.k.get();
         up.dev.amp = up.amp.get();
@@ -617,21 +615,32 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
     OCP_LAUNCH_CHECK();
     pos.release();
 
-    // 4. symbolic rows
+    // 4. symbolic rows: rows of up to kPadW entries in one pass into a padded
+    // buffer; if any row is longer, count and fill again with kRowCap slots
     DevBuf<int32_t> rcnt(ctx, (size_t)n + 1);
     DevBuf<int32_t> pad(ctx, (size_t)n * kPadW);
     fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
-    k_row_symbolic<<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
+    k_row_symbolic<kPadW><<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
         0, sys->n, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
         rcnt.get(), nullptr, nullptr, pad.get(), ctx->dev_flag);
     OCP_LAUNCH_CHECK();
     read_back(ctx, &fl, ctx->dev_flag, sizeof(fl));
-    if (fl & 4) fail(OCP_ERR_UNSUPPORTED, "an assembled row has more than 128 entries");
+    const bool long_rows = (fl & 128) != 0;
+    if (long_rows) {
+        pad.release();
+        fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
+        k_row_symbolic<kRowCap><<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
+            0, sys->n, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
+            rcnt.get(), nullptr, nullptr, nullptr, ctx->dev_flag);
+        OCP_LAUNCH_CHECK();
+        read_back(ctx, &fl, ctx->dev_flag, sizeof(fl));
+        if (fl & 4) fail(OCP_ERR_UNSUPPORTED, "an assembled row has more than 128 entries");
+    }
     sys->row_ptr.reset(ctx, (size_t)n + 1);
     sys->nnz = scan_exclusive(ctx, rcnt.get(), sys->row_ptr.get(), n);
     sys->col.reset(ctx, (size_t)sys->nnz);
-    if (fl & 128) {
-        k_row_symbolic<<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
+    if (long_rows) {
+        k_row_symbolic<kRowCap><<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
             1, sys->n, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
             nullptr, sys->row_ptr.get(), sys->col.get(), nullptr, ctx->dev_flag);
     } else {
@@ -640,7 +649,7 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
     }
     OCP_LAUNCH_CHECK();
     pad.release();
-    const int maxlen = (fl & 128) ? kRowCap : kPadW;
+    const int maxlen = long_rows ? kRowCap : kPadW;
     rcnt.release();
 
     // 5. element loads

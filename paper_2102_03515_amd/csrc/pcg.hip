@@ -13,7 +13,6 @@
 
 namespace ocp {
 
-constexpr int kSpmvLanes = 16;  // lanes per row of the fine-level SpMV (15-point rows)
 
 // ------------------------------------------------------------------ SpMV
 // y = A x on the sliced-ELL copy

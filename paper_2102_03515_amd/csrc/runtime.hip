@@ -163,8 +163,7 @@ int64_t scan_exclusive(ocp_ctx *ctx, const int32_t *in, int32_t *out, int64_t n)
 // -------------------------------------------------------------- reductions
 constexpr int kRedBlock = 256;
 
-__global__ void __launch_bounds__(kRedBlock) k_max_abs(const double *v, int64_t n, double *partials,
-                                                       unsigned *counter, double *out) {
+__global__ void __launch_bounds__(kRedBlock) k_max_abs(const double *v, int64_t n, double *partials) {
     double m = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kRedBlock)
@@ -177,16 +176,21 @@ __global__ void __launch_bounds__(kRedBlock) k_max_abs(const double *v, int64_t 
     if (threadIdx.x == 0) {
         for (int w = 1; w < kRedBlock / 64; ++w) m = fmax(m, ws[w]);
         partials[blockIdx.x] = m;
-        __threadfence();
-        unsigned t = atomicAdd(counter, 1u);
-        if (t == gridDim.x - 1) {
-            __threadfence();
-            double r = 0.0;
-            for (unsigned b = 0; b < gridDim.x; ++b)
-                r = fmax(r, __hip_atomic_load(&partials[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            *out = r;
-            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+    }
+}
+
+// one block: max of the partials (a max is exact in any order)
+__global__ void __launch_bounds__(kRedBlock) k_max_fin(const double *partials, unsigned nb, double *out) {
+    double m = 0.0;
+    for (unsigned b = threadIdx.x; b < nb; b += kRedBlock) m = fmax(m, partials[b]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    __shared__ double ws[kRedBlock / 64];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kRedBlock / 64; ++w) m = fmax(m, ws[w]);
+        *out = m;
     }
 }
 
@@ -209,8 +213,9 @@ static unsigned red_grid(int64_t n) {
 }
 
 double reduce_max_abs(ocp_ctx *ctx, const double *v, int64_t n) {
-    k_max_abs<<<red_grid(n), kRedBlock, 0, ctx->stream>>>(v, n, ctx->red_partials, ctx->red_counters,
-                                                          ctx->red_out);
+    const unsigned nb = red_grid(n);
+    k_max_abs<<<nb, kRedBlock, 0, ctx->stream>>>(v, n, ctx->red_partials);
+    k_max_fin<<<1, kRedBlock, 0, ctx->stream>>>(ctx->red_partials, nb, ctx->red_out);
     OCP_LAUNCH_CHECK();
     double r;
     read_back(ctx, &r, ctx->red_out, sizeof(r));

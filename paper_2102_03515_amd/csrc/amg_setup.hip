@@ -114,14 +114,19 @@ __device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
     return v;
 }
 
+// Rounds after the first only touch what can still change: m2 and the
+// marking pass skip decided nodes, and m1 is recomputed only for nodes marked
+// (need[i] == round) as the closed neighbourhood of an undecided node.
 template <int G>
 __global__ void __launch_bounds__(256) k_mis_m1(int32_t n, const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ col, const uint8_t *__restrict__ strong,
                                                 const int8_t *__restrict__ state, uint32_t salt,
+                                                const int32_t *__restrict__ need, int32_t round,
                                                 uint64_t *__restrict__ m1) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int i = (int)(t / G), lane = (int)(t % G);
     if (i >= n) return;
+    if (need && need[i] != round) return;   // uniform over the group
     uint64_t m = 0;
     for (int k = rp[i] + lane; k < rp[i + 1]; k += G) {
         const int j = col[k];
@@ -134,6 +139,23 @@ __global__ void __launch_bounds__(256) k_mis_m1(int32_t n, const int32_t *__rest
     if (lane == 0) {
         const uint64_t ki = mis_key(i, state[i], salt);
         m1[i] = ki > m ? ki : m;
+    }
+}
+
+// need[i] = need[j] = round for every undecided i and its strong neighbours j
+// (every writer stores the same value)
+template <int G>
+__global__ void __launch_bounds__(256) k_mis_mark(int32_t n, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ col, const uint8_t *__restrict__ strong,
+                                                  const int8_t *__restrict__ state, int32_t *__restrict__ need,
+                                                  int32_t round) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / G), lane = (int)(t % G);
+    if (i >= n || state[i] != 0) return;
+    if (lane == 0) need[i] = round;
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += G) {
+        const int j = col[k];
+        if (is_strong(strong, k, j, i)) need[j] = round;
     }
 }
 
@@ -777,32 +799,23 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
             DevBuf<int8_t> state(ctx, n);
             fill_zero_bytes(ctx, state.get(), (size_t)n);
             DevBuf<uint64_t> m1(ctx, n);
+            DevBuf<int32_t> need(ctx, n);
+            fill_zero_bytes(ctx, need.get(), sizeof(int32_t) * (size_t)n);
             const uint32_t salt = 0x9E3779B9u * (uint32_t)(lev + 1);
-            for (int round = 0;; ++round) {
+            constexpr int GM = 4;
+            const unsigned gb = grid_for((int64_t)n * GM, 256);
+            for (int round = 1;; ++round) {
                 if (round > 1000) fail(OCP_ERR_HIP, "independent-set rounds did not terminate");
-                fill_zero_bytes(ctx, ctx->dev_flag, 4);
-                const int gm = std::min(L.gA, 16);
-                const unsigned gb = grid_for((int64_t)n * gm, 256);
-                switch (gm) {
-                    case 4:
-                        k_mis_m1<4><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get());
-                        k_mis_m2<4><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get(),
-                                                       ctx->dev_flag);
-                        break;
-                    case 8:
-                        k_mis_m1<8><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get());
-                        k_mis_m2<8><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get(),
-                                                       ctx->dev_flag);
-                        break;
-                    default:
-                        k_mis_m1<16><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get());
-                        k_mis_m2<16><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt,
-                                                        m1.get(), ctx->dev_flag);
-                        break;
-                }
+                fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
+                if (round > 1)
+                    k_mis_mark<GM><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), need.get(), round);
+                k_mis_m1<GM><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt,
+                                                round > 1 ? need.get() : nullptr, round, m1.get());
+                k_mis_m2<GM><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get(),
+                                                ctx->dev_flag);
                 OCP_LAUNCH_CHECK();
                 int32_t und = 0;
-                read_back(ctx, &und, ctx->dev_flag, 4);
+                read_back(ctx, &und, ctx->dev_flag, sizeof(int32_t));
                 if (und == 0) break;
             }
             // aggregates

@@ -67,59 +67,114 @@ __device__ __forceinline__ void load_tet(const double *__restrict__ xyz, const i
 }
 
 // ------------------------------------------------------- 1. check + count
-__global__ void k_tet_check_count(const int4 *__restrict__ tets, int64_t nt,
-                                  const double *__restrict__ xyz, int32_t nv,
-                                  int32_t *__restrict__ inc_cnt, int32_t *__restrict__ flag) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nt) return;
-    const int4 tv = tets[e];
-    const int v[4] = {tv.x, tv.y, tv.z, tv.w};
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-        if (v[a] < 0 || v[a] >= nv) {
-            atomicOr(flag, 1);
-            return;
-        }
-    double p[4][3], g[4][3];
-    load_tet(xyz, tv, p);
-    double l2 = 0.0;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = a + 1; b < 4; ++b) {
-            double s = 0.0;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) s += (p[a][d] - p[b][d]) * (p[a][d] - p[b][d]);
-            l2 = fmax(l2, s);
-        }
-    double e3[3][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int r = 0; r < 3; ++r) e3[r][c] = p[c + 1][r] - p[0][r];
-    const double det = e3[0][0] * (e3[1][1] * e3[2][2] - e3[1][2] * e3[2][1]) -
-                       e3[0][1] * (e3[1][0] * e3[2][2] - e3[1][2] * e3[2][0]) +
-                       e3[0][2] * (e3[1][0] * e3[2][1] - e3[1][1] * e3[2][0]);
-    (void)g;
-    if (!(fabs(det) > 1e-12 * l2 * sqrt(l2))) {
-        atomicOr(flag, 2);
-        return;
+// The 4 x 256 vertex references of a block's tets are first combined in an
+// LDS hash table (consecutive tets share most vertices), so each distinct
+// vertex costs one global atomic per block instead of one per reference.
+constexpr int kIncBlock = 256;
+constexpr int kIncHash = 2048;
+
+__device__ __forceinline__ int inc_slot(int *keys, int v) {
+    int s = (int)(((uint32_t)v * 2654435761u) >> (32 - 11));
+    for (;;) {
+        const int prev = atomicCAS(&keys[s], -1, v);
+        if (prev == -1 || prev == v) return s;
+        s = (s + 1) & (kIncHash - 1);
     }
+}
+
+__global__ void __launch_bounds__(kIncBlock) k_tet_check_count(const int4 *__restrict__ tets, int64_t nt,
+                                                               const double *__restrict__ xyz, int32_t nv,
+                                                               int32_t *__restrict__ inc_cnt,
+                                                               int32_t *__restrict__ flag) {
+    __shared__ int keys[kIncHash];
+    __shared__ int cnt[kIncHash];
+    for (int q = threadIdx.x; q < kIncHash; q += kIncBlock) {
+        keys[q] = -1;
+        cnt[q] = 0;
+    }
+    __syncthreads();
+    const int64_t e = (int64_t)blockIdx.x * kIncBlock + threadIdx.x;
+    bool ok = e < nt;
+    int v[4] = {0, 0, 0, 0};
+    if (ok) {
+        const int4 tv = tets[e];
+        v[0] = tv.x;
+        v[1] = tv.y;
+        v[2] = tv.z;
+        v[3] = tv.w;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) atomicAdd(&inc_cnt[v[a]], 1);
+        for (int a = 0; a < 4; ++a)
+            if (v[a] < 0 || v[a] >= nv) ok = false;
+        if (!ok) {
+            atomicOr(flag, 1);
+        } else {
+            double p[4][3];
+            load_tet(xyz, tv, p);
+            double l2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = a + 1; b < 4; ++b) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) s += (p[a][d] - p[b][d]) * (p[a][d] - p[b][d]);
+                    l2 = fmax(l2, s);
+                }
+            double e3[3][3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int r = 0; r < 3; ++r) e3[r][c] = p[c + 1][r] - p[0][r];
+            const double det = e3[0][0] * (e3[1][1] * e3[2][2] - e3[1][2] * e3[2][1]) -
+                               e3[0][1] * (e3[1][0] * e3[2][2] - e3[1][2] * e3[2][0]) +
+                               e3[0][2] * (e3[1][0] * e3[2][1] - e3[1][1] * e3[2][0]);
+            if (!(fabs(det) > 1e-12 * l2 * sqrt(l2))) {
+                atomicOr(flag, 2);
+                ok = false;
+            }
+        }
+    }
+    if (ok) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) atomicAdd(&cnt[inc_slot(keys, v[a])], 1);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kIncHash; q += kIncBlock)
+        if (keys[q] >= 0) atomicAdd(&inc_cnt[keys[q]], cnt[q]);
 }
 
 // ------------------------------------------------------ 2. incidence lists
-__global__ void k_tet_fill(const int4 *__restrict__ tets, int64_t nt, const int32_t *__restrict__ inc_ptr,
-                           int32_t *__restrict__ fill, int32_t *__restrict__ inc) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nt) return;
-    const int4 tv = tets[e];
-    const int v[4] = {tv.x, tv.y, tv.z, tv.w};
+// Same LDS combining: one global atomic per distinct vertex reserves the
+// block's range in that vertex's list; references get local offsets.
+__global__ void __launch_bounds__(kIncBlock) k_tet_fill(const int4 *__restrict__ tets, int64_t nt,
+                                                        const int32_t *__restrict__ inc_ptr,
+                                                        int32_t *__restrict__ fill, int32_t *__restrict__ inc) {
+    __shared__ int keys[kIncHash];
+    __shared__ int cnt[kIncHash];
+    __shared__ int base[kIncHash];
+    for (int q = threadIdx.x; q < kIncHash; q += kIncBlock) {
+        keys[q] = -1;
+        cnt[q] = 0;
+    }
+    __syncthreads();
+    const int64_t e = (int64_t)blockIdx.x * kIncBlock + threadIdx.x;
+    int slot[4] = {0, 0, 0, 0}, pos[4] = {0, 0, 0, 0};
+    if (e < nt) {
+        const int4 tv = tets[e];
+        const int v[4] = {tv.x, tv.y, tv.z, tv.w};
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        int pos = atomicAdd(&fill[v[a]], 1);
-        inc[inc_ptr[v[a]] + pos] = (int32_t)e;
+        for (int a = 0; a < 4; ++a) {
+            slot[a] = inc_slot(keys, v[a]);
+            pos[a] = atomicAdd(&cnt[slot[a]], 1);
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kIncHash; q += kIncBlock)
+        if (keys[q] >= 0) base[q] = inc_ptr[keys[q]] + atomicAdd(&fill[keys[q]], cnt[q]);
+    __syncthreads();
+    if (e < nt) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) inc[base[slot[a]] + pos[a]] = (int32_t)e;
     }
 }
 
@@ -582,8 +637,8 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
     DevBuf<int32_t> cnt(ctx, (size_t)nv + 1);
     fill_zero_bytes(ctx, cnt.get(), sizeof(int32_t) * ((size_t)nv + 1));
     fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
-    k_tet_check_count<<<grid_for(nt, 256), 256, 0, ctx->stream>>>(tets, nt, mesh->xyz, nv, cnt.get(),
-                                                                  ctx->dev_flag);
+    k_tet_check_count<<<grid_for(nt, kIncBlock), kIncBlock, 0, ctx->stream>>>(tets, nt, mesh->xyz, nv, cnt.get(),
+                                                                              ctx->dev_flag);
     OCP_LAUNCH_CHECK();
     int32_t fl = 0;
     read_back(ctx, &fl, ctx->dev_flag, sizeof(fl));
@@ -595,8 +650,8 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
     const int64_t ninc = scan_exclusive(ctx, cnt.get(), sys->inc_ptr.get(), nv);
     sys->inc.reset(ctx, (size_t)ninc);
     fill_zero_bytes(ctx, cnt.get(), sizeof(int32_t) * (size_t)nv);
-    k_tet_fill<<<grid_for(nt, 256), 256, 0, ctx->stream>>>(tets, nt, sys->inc_ptr.get(), cnt.get(),
-                                                           sys->inc.get());
+    k_tet_fill<<<grid_for(nt, kIncBlock), kIncBlock, 0, ctx->stream>>>(tets, nt, sys->inc_ptr.get(), cnt.get(),
+                                                                       sys->inc.get());
     OCP_LAUNCH_CHECK();
     k_inc_sort<<<grid_for(nv, 64), 64, 0, ctx->stream>>>(sys->inc_ptr.get(), sys->inc.get(), nv);
     OCP_LAUNCH_CHECK();

@@ -384,16 +384,27 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
     wave_sync();
     if (active) {
         const int ke = arp[i + 1];
-        for (int k = arp[i]; k < ke; ++k) {
-            const int c = acol[k];
-            const double a = NUMERIC ? aval[k] : 0.0;
-            const int te = brp[c + 1];
-            for (int t = brp[c] + lane; t < te; t += G) {
-                if (!NUMERIC && *(volatile int *)&count[g] > (3 * H) / 4) break;
-                const int q = hash_insert<H>(keys[g], bcol[t], NUMERIC ? nullptr : &count[g]);
-                if (NUMERIC) vals[g][q] += a * bval[t];
+        for (int kb = arp[i]; kb < ke; kb += G) {
+            // lanes fetch the metadata of G consecutive A entries at once
+            double am = 0.0;
+            int tb = 0, tn = 0;
+            if (kb + lane < ke) {
+                const int c = acol[kb + lane];
+                if (NUMERIC) am = aval[kb + lane];
+                tb = brp[c];
+                tn = brp[c + 1];
             }
-            wave_sync();
+            const int cnt = ke - kb < G ? ke - kb : G;
+            for (int jj = 0; jj < cnt; ++jj) {
+                const int t0 = __shfl(tb, jj, G), t1 = __shfl(tn, jj, G);
+                const double a = NUMERIC ? __shfl(am, jj, G) : 0.0;
+                for (int t = t0 + lane; t < t1; t += G) {
+                    if (!NUMERIC && *(volatile int *)&count[g] > (3 * H) / 4) break;
+                    const int q = hash_insert<H>(keys[g], bcol[t], NUMERIC ? nullptr : &count[g]);
+                    if (NUMERIC) vals[g][q] += a * bval[t];
+                }
+                wave_sync();
+            }
         }
     }
     if (!NUMERIC) {

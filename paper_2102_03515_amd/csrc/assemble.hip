@@ -16,7 +16,7 @@
 #include <climits>
 #include <cmath>
 
-#include "common.h"
+#include "kernels.h"
 #include "system.h"
 
 namespace ocp {
@@ -298,55 +298,80 @@ __global__ void k_pad_to_csr(int32_t n, const int32_t *__restrict__ pad, const i
 }
 
 // --------------------------------------------------------- 5. element loads
+// One sine mode as the kernel reads it: 32 bytes, so that a batch of
+// kModeBatch modes is a few wide scalar loads issued together.
+struct SineMode {
+    int32_t k[3];
+    int32_t pad;
+    double amp;
+    double pad2;
+};
+constexpr int kModeBatch = 8;   // modes are padded on the host to a multiple (amp 0)
+
 struct TargetDev {
     int32_t kind;
-    int32_t n_modes;
-    const int32_t *k;     // device [n_modes][3]
-    const double *amp;    // device [n_modes]
+    int32_t n_modes;          // padded to a multiple of kModeBatch
+    const SineMode *modes;    // device [n_modes]
     double offset;
     double lo[3], hi[3];
-    const double *nodal;  // device [n_vertices]
+    const double *nodal;      // device [n_vertices]
 };
 
 // ubar(x) for sine modes.  sin(k pi x_d) for k <= kSineTable comes from the
 // three-term recurrence s_{k+1} = 2 cos(pi x) s_k - s_{k-1}, seeded with
-// sincospi, stored in a per-thread LDS table (stride = block size, so a
-// wavefront's reads of one entry are conflict-free); larger wave numbers
-// call sinpi directly.
-__device__ double eval_sine(const TargetDev &t, const double x[3], double *tab, int stride) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
+// sincospi and held in registers; a mode's wave numbers are the same for
+// every lane, so the tables are indexed with a uniform index.  With
+// TABLE_ONLY every wave number is known to be <= kSineTable; otherwise the
+// larger ones call sinpi.  The modes are added in their given order.
+template <bool TABLE_ONLY>
+__device__ double eval_sine(const TargetDev &t, const double x[3]) {
+    double t0[kSineTable], t1[kSineTable], t2[kSineTable];
+    auto fill = [&](double xd, double *tab) {
         double s, c;
-        sincospi(x[d], &s, &c);
+        sincospi(xd, &s, &c);
         double sm1 = 0.0, sk = s;
 #pragma unroll
         for (int k = 0; k < kSineTable; ++k) {
-            tab[(d * kSineTable + k) * stride] = sk;
+            tab[k] = sk;
             const double sn = 2.0 * c * sk - sm1;
             sm1 = sk;
             sk = sn;
         }
-    }
+    };
+    fill(x[0], t0);
+    fill(x[1], t1);
+    fill(x[2], t2);
+    auto factor = [&](int k, const double *tab, double xd) {
+        if (TABLE_ONLY) return tab[k - 1];
+        return k <= kSineTable ? tab[k - 1] : sinpi((double)k * xd);
+    };
     double u = t.offset;
-    for (int m = 0; m < t.n_modes; ++m) {
-        double prod = t.amp[m];
+    for (int m0 = 0; m0 < t.n_modes; m0 += kModeBatch) {
+        SineMode md[kModeBatch];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int k = t.k[3 * m + d];
-            prod *= (k <= kSineTable) ? tab[(d * kSineTable + (k - 1)) * stride] : sinpi((double)k * x[d]);
+        for (int j = 0; j < kModeBatch; ++j) md[j] = t.modes[m0 + j];
+#pragma unroll
+        for (int j = 0; j < kModeBatch; ++j) {
+            const double f0 = factor(md[j].k[0], t0, x[0]);
+            const double f1 = factor(md[j].k[1], t1, x[1]);
+            const double f2 = factor(md[j].k[2], t2, x[2]);
+            u += md[j].amp * f0 * f1 * f2;
         }
-        u += prod;
     }
     return u;
 }
 
-constexpr int kLoadBlock = 64;
+// One lane per quadrature point (4 lanes per tet); the 4 point contributions
+// are added in a fixed order across the lanes.
+constexpr int kLoadBlock = 128;
+template <bool TABLE_ONLY>
 __global__ void __launch_bounds__(kLoadBlock) k_tet_load(const int4 *__restrict__ tets, int64_t nt,
                                                          const double *__restrict__ xyz, TargetDev tg,
                                                          double4 *__restrict__ fe) {
-    __shared__ double tab[3 * kSineTable * kLoadBlock];
-    const int64_t e = (int64_t)blockIdx.x * kLoadBlock + threadIdx.x;
-    if (e >= nt) return;
+    const int64_t tid = (int64_t)blockIdx.x * kLoadBlock + threadIdx.x;
+    const int64_t e = tid >> 2;
+    const int q = (int)(tid & 3);
+    if (e >= nt) return;   // uniform over the 4 lanes of a tet
     const int4 tv = tets[e];
     double p[4][3];
     load_tet(xyz, tv, p);
@@ -359,39 +384,36 @@ __global__ void __launch_bounds__(kLoadBlock) k_tet_load(const int4 *__restrict_
                        e3[0][1] * (e3[1][0] * e3[2][2] - e3[1][2] * e3[2][0]) +
                        e3[0][2] * (e3[1][0] * e3[2][1] - e3[1][1] * e3[2][0]);
     const double w = fabs(det) / 6.0 / 4.0;  // |tau|/4 per quadrature point
-    // barycentric points (a,b,b,b) and permutations
+    // barycentric point q: (a,b,b,b) with a at position q
     const double qa = 0.5854101966249685;   // (5 + 3 sqrt5) / 20
     const double qb = 0.1381966011250105;   // (5 - sqrt5) / 20
-    const int vv[4] = {tv.x, tv.y, tv.z, tv.w};
-    double f[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-    for (int q = 0; q < 4; ++q) {
-        double x[3];
+    double x[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            double s = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double sum = 0.0;
 #pragma unroll
-            for (int a = 0; a < 4; ++a) s += (a == q ? qa : qb) * p[a][d];
-            x[d] = s;
-        }
-        double u;
-        if (tg.kind == OCP_TARGET_SINE_MODES) {
-            u = eval_sine(tg, x, tab + threadIdx.x, kLoadBlock);
-        } else if (tg.kind == OCP_TARGET_BOX) {
-            u = (x[0] > tg.lo[0] && x[0] < tg.hi[0] && x[1] > tg.lo[1] && x[1] < tg.hi[1] &&
-                 x[2] > tg.lo[2] && x[2] < tg.hi[2])
-                    ? 1.0
-                    : 0.0;
-        } else {
-            u = 0.0;
-#pragma unroll
-            for (int a = 0; a < 4; ++a) u += (a == q ? qa : qb) * tg.nodal[vv[a]];
-        }
-        const double wu = w * u;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) f[a] += wu * (a == q ? qa : qb);
+        for (int a = 0; a < 4; ++a) sum += (a == q ? qa : qb) * p[a][d];
+        x[d] = sum;
     }
-    fe[e] = make_double4(f[0], f[1], f[2], f[3]);
+    double u;
+    if (tg.kind == OCP_TARGET_SINE_MODES) {
+        u = eval_sine<TABLE_ONLY>(tg, x);
+    } else if (tg.kind == OCP_TARGET_BOX) {
+        u = (x[0] > tg.lo[0] && x[0] < tg.hi[0] && x[1] > tg.lo[1] && x[1] < tg.hi[1] && x[2] > tg.lo[2] &&
+             x[2] < tg.hi[2])
+                ? 1.0
+                : 0.0;
+    } else {
+        const int vv[4] = {tv.x, tv.y, tv.z, tv.w};
+        u = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) u += (a == q ? qa : qb) * tg.nodal[vv[a]];
+    }
+    const double wu = w * u;
+    double f[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) f[a] = dev::group_sum<4>(wu * (a == q ? qa : qb));
+    if (q == 0) fe[e] = make_double4(f[0], f[1], f[2], f[3]);
 }
 
 // ---------------------------------------------------------- 6. numeric rows
@@ -538,8 +560,8 @@ static void check_target(const ocp_target *t, int32_t nv) {
 
 // Upload the target description; the returned buffers must outlive the launch.
 struct TargetUpload {
-    DevBuf<int32_t> k;
-    DevBuf<double> amp;
+    DevBuf<SineMode> modes;
+    bool table_only = true;   // every wave number <= kSineTable
     TargetDev dev{};
 };
 
@@ -553,15 +575,38 @@ static void upload_target(ocp_ctx *ctx, const ocp_target *t, TargetUpload &up) {
     up.dev.nodal = t->nodal;
     if (t->kind == OCP_TARGET_SINE_MODES) {
         const int m = t->n_modes;
-        up.k.reset(ctx, (size_t)m * 3);
-        up.amp.reset(ctx, (size_t)m);
-        OCP_HIP(hipMemcpyAsync(up.k.get(), t->k, sizeof(int32_t) * 3 * m, hipMemcpyHostToDevice, ctx->stream));
-        OCP_HIP(hipMemcpyAsync(up.amp.get(), t->amp, sizeof(double) * m, hipMemcpyHostToDevice, ctx->stream));
-        up.dev.n_modes = m;
-        up.dev.k = up.k.get();
-        up.dev.amp = up.amp.get();
-        sync(ctx);  // the host arrays may be released after the call returns
+        const int mp = (m + kModeBatch - 1) / kModeBatch * kModeBatch;
+        std::vector<SineMode> md((size_t)mp);
+        for (int q = 0; q < mp; ++q) {
+            SineMode &o = md[q];
+            o.pad = 0;
+            o.pad2 = 0.0;
+            if (q < m) {
+                for (int d = 0; d < 3; ++d) {
+                    o.k[d] = t->k[3 * q + d];
+                    up.table_only = up.table_only && o.k[d] <= kSineTable;
+                }
+                o.amp = t->amp[q];
+            } else {   // padding: contributes amp * (...) = 0
+                o.k[0] = o.k[1] = o.k[2] = 1;
+                o.amp = 0.0;
+            }
+        }
+        up.modes.reset(ctx, (size_t)mp);
+        OCP_HIP(hipMemcpyAsync(up.modes.get(), md.data(), sizeof(SineMode) * mp, hipMemcpyHostToDevice, ctx->stream));
+        up.dev.n_modes = mp;
+        up.dev.modes = up.modes.get();
+        sync(ctx);  // the staging vector is released when this returns
     }
+}
+
+static void launch_tet_load(ocp_ctx *ctx, const TargetUpload &up, const int4 *tets, int64_t nt, const double *xyz,
+                            double4 *fe) {
+    if (up.table_only)
+        k_tet_load<true><<<grid_for(nt * 4, kLoadBlock), kLoadBlock, 0, ctx->stream>>>(tets, nt, xyz, up.dev, fe);
+    else
+        k_tet_load<false><<<grid_for(nt * 4, kLoadBlock), kLoadBlock, 0, ctx->stream>>>(tets, nt, xyz, up.dev, fe);
+    OCP_LAUNCH_CHECK();
 }
 
 static void compute_loads(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *mesh, const ocp_target *t,
@@ -570,9 +615,7 @@ static void compute_loads(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *m
     upload_target(ctx, t, up);
     DevBuf<double4> fe(ctx, (size_t)sys->nt);
     const int4 *tets = reinterpret_cast<const int4 *>(mesh->tets);
-    k_tet_load<<<grid_for(sys->nt, kLoadBlock), kLoadBlock, 0, ctx->stream>>>(tets, sys->nt, mesh->xyz, up.dev,
-                                                                              fe.get());
-    OCP_LAUNCH_CHECK();
+    launch_tet_load(ctx, up, tets, sys->nt, mesh->xyz, fe.get());
     // row sums of the element loads (reuse the numeric kernel's f output
     // through a dedicated pass that only accumulates f)
     extern void row_loads(ocp_ctx *, const ocp_system *, const double4 *, double *);
@@ -711,8 +754,7 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
     TargetUpload up;
     upload_target(ctx, t, up);
     DevBuf<double4> fe(ctx, (size_t)nt);
-    k_tet_load<<<grid_for(nt, kLoadBlock), kLoadBlock, 0, ctx->stream>>>(tets, nt, mesh->xyz, up.dev, fe.get());
-    OCP_LAUNCH_CHECK();
+    launch_tet_load(ctx, up, tets, nt, mesh->xyz, fe.get());
 
     // 6. numeric rows
     sys->val.reset(ctx, (size_t)sys->nnz);

@@ -33,6 +33,7 @@ def ctx(P):
 def _target(name):
     return {"sine111": I.single_sine(), "box": I.box_indicator(),
             "modes": I.random_sine_modes(1000, n_modes=64),
+            "modes_hi": I.random_sine_modes(1001, n_modes=13, kmax=20),
             "offset": I.single_sine(offset=1.0)}[name]
 
 
@@ -51,6 +52,9 @@ ASM_CASES = [
     ("cube12_jitter_box", 12, 0.15, 1e-2, "box"),
     ("cube9_jitter_modes64", 9, 0.15, 1e-6, "modes"),
     ("cube7_offset", 7, 0.0, 1.0, "offset"),
+    # 13 modes (not a multiple of the kernel's mode batch), wave numbers up to
+    # 20 (beyond the recurrence table: the direct sinpi branch)
+    ("cube9_jitter_modes13_k20", 9, 0.15, 1e-3, "modes_hi"),
 ]
 
 

@@ -124,6 +124,13 @@ int fe_set_rho(ocp_ctx *ctx, ocp_system *sys, double rho);
 int fe_load(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *mesh, const ocp_target *target,
             double *f_dev);
 
+/* Load vectors of k targets on the same mesh in one block: F (device
+ * [n_dofs][k], row-major, caller-owned) receives F[i*k + j] = int ubar_j phi_i
+ * for target j (the same rule as fe_assemble).  This is the right-hand side
+ * block of pcg_solve_multi.  Errors as fe_load; INVALID_ARG if k < 1. */
+int fe_load_multi(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *mesh, int32_t k,
+                  const ocp_target *targets, double *F);
+
 /* Read-only view of an assembled system (device pointers owned by `sys`). */
 typedef struct {
     int32_t n_vertices;
@@ -224,6 +231,24 @@ typedef struct {
 int pcg_solve(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, const double *f,
               double *u, double rtol, int32_t maxit, int32_t flags, ocp_solve_info *info);
 
+/* Block PCG for k right-hand sides that share A and the hierarchy (the PCG
+ * of Section 5 run as k independent recurrences in one pass over the
+ * matrix per iteration).  Every column has its own alpha, beta and stop
+ * test; a column that has converged, broken down or reached maxit is frozen
+ * while the others continue.  The V-cycle is the one of pcg_solve (same
+ * coefficients, the hierarchy's precision); CG is double.
+ *   k      1..64 columns
+ *   F      device [n_dofs][k] row-major (entry (i,j) at i*k + j), or NULL:
+ *          every column solves with the system's f
+ *   U      device [n_vertices][k] output, caller-owned; Dirichlet rows 0
+ *   infos  host [k] per-column results (may be NULL)
+ * Blocks until every column has stopped.  Returns the worst column's status:
+ * OCP_ERR_BREAKDOWN if any column broke down, else OCP_MAXIT if any column
+ * reached the cap, else 0; or another error (then no column result). */
+int pcg_solve_multi(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, int32_t k,
+                    const double *F, double *U, double rtol, int32_t maxit, int32_t flags,
+                    ocp_solve_info *infos);
+
 /* ------------------------------------------------------- kernel timing */
 #define OCP_KERNEL_CG_SPMV 0      /* q = A p with p.q, FP64 CSR (the CG iteration's SpMV) */
 #define OCP_KERNEL_VC_PRE0 1      /* fine-level first smoothing step fused with the residual */
@@ -232,10 +257,11 @@ int pcg_solve(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, const
 #define OCP_KERNEL_VC_PROLONG0 4  /* fine-level prolongation D^-1 (...) + P e */
 #define OCP_KERNEL_VC_PRE0_B 5    /* fine-level second pre-smoothing pass (degree 2) */
 #define OCP_KERNEL_VC_POST0_A 6   /* fine-level first post-smoothing residual (degree 2) */
+#define OCP_KERNEL_BLK_SPMM 7     /* Q = A P with per-column p.q, FP64 CSR (pcg_solve_multi) */
 
 /* Live timing of selected kernels with HIP events on the context stream.
  * ocp_profile_enable(ctx, 1) clears the counters and brackets every launch of
- * the kernels above inside pcg_solve with an event pair; launches of the
+ * the kernels above inside pcg_solve (pcg_solve_multi for BLK_SPMM) with an event pair; launches of the
  * solve's final iteration (which may return early after convergence) are not
  * counted.  ocp_profile_read returns the number of counted launches and their
  * summed duration in milliseconds. */

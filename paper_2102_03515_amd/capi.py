@@ -90,6 +90,8 @@ _SIGS = {
     "ocp_system_destroy": (None, [C.c_void_p]),
     "fe_set_rho": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double]),
     "fe_load": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(_Mesh), C.POINTER(_Target), C.c_void_p]),
+    "fe_load_multi": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(_Mesh), C.c_int32, C.POINTER(_Target),
+                                C.c_void_p]),
     "ocp_system_get_view": (C.c_int, [C.c_void_p, C.POINTER(_SystemView)]),
     "ocp_spmv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "amg_default_params": (None, [C.POINTER(_AmgParams)]),
@@ -99,12 +101,14 @@ _SIGS = {
     "amg_vcycle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pcg_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                             C.c_int32, C.c_int32, C.POINTER(SolveInfo)]),
+    "pcg_solve_multi": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                  C.c_double, C.c_int32, C.c_int32, C.POINTER(SolveInfo)]),
     "ocp_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "ocp_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
 }
 
 (KERNEL_CG_SPMV, KERNEL_VC_PRE0, KERNEL_VC_POST0, KERNEL_VC_RESTRICT0, KERNEL_VC_PROLONG0, KERNEL_VC_PRE0_B,
- KERNEL_VC_POST0_A) = range(7)
+ KERNEL_VC_POST0_A, KERNEL_BLK_SPMM) = range(8)
 
 _lib = None
 
@@ -352,6 +356,18 @@ class System:
         self.ctx.check(lib().fe_load(self.ctx.handle, self.handle, C.byref(m), C.byref(t), _ptr(out)))
         return out
 
+    def load_multi(self, targets, out=None):
+        """Load vectors of several targets as one row-major block [n][k]."""
+        torch = _torch()
+        k = len(targets)
+        if out is None:
+            out = torch.empty((self.n, k), dtype=torch.float64, device="cuda")
+        keep = []
+        arr = (_Target * k)(*[target_struct(t, keep) for t in targets])
+        m = self.mesh.struct()
+        self.ctx.check(lib().fe_load_multi(self.ctx.handle, self.handle, C.byref(m), k, arr, _ptr(out)))
+        return out
+
     def close(self):
         if getattr(self, "handle", None):
             lib().ocp_system_destroy(self.handle)
@@ -454,3 +470,25 @@ def pcg_solve(ctx: Context, system: System, hierarchy: Optional[Hierarchy] = Non
     ok = (OK,) if raise_on_maxit else (OK, MAXIT)
     ctx.check(rc, ok=ok)
     return u, info, rc
+
+
+def pcg_solve_multi(ctx: Context, system: System, hierarchy: Optional[Hierarchy], F, k: Optional[int] = None,
+                    U=None, rtol: float = 1e-8, maxit: int = 500, stop: int = STOP_L2):
+    """Block PCG over the k columns of F (device [n][k] row-major, or None for
+    k copies of the system's f).  Returns (U [n_vertices][k], [SolveInfo]*k,
+    status)."""
+    torch = _torch()
+    if F is not None:
+        if F.dim() != 2 or not F.is_contiguous() or F.dtype != torch.float64:
+            raise ValueError("F must be a contiguous float64 [n][k] tensor")
+        k = F.shape[1]
+    if k is None:
+        raise ValueError("k is needed when F is None")
+    nv = system.view().n_vertices
+    if U is None:
+        U = torch.empty((nv, k), dtype=torch.float64, device="cuda")
+    infos = (SolveInfo * k)()
+    rc = lib().pcg_solve_multi(ctx.handle, system.handle, hierarchy.handle if hierarchy is not None else None,
+                               int(k), _ptr(F), _ptr(U), float(rtol), int(maxit), int(stop), infos)
+    ctx.check(rc, ok=(OK, MAXIT))
+    return U, list(infos), rc

@@ -610,7 +610,7 @@ static void launch_tet_load(ocp_ctx *ctx, const TargetUpload &up, const int4 *te
 }
 
 static void compute_loads(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *mesh, const ocp_target *t,
-                          double *f_out) {
+                          double *f_out, int64_t ld = 1) {
     TargetUpload up;
     upload_target(ctx, t, up);
     DevBuf<double4> fe(ctx, (size_t)sys->nt);
@@ -618,8 +618,8 @@ static void compute_loads(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *m
     launch_tet_load(ctx, up, tets, sys->nt, mesh->xyz, fe.get());
     // row sums of the element loads (reuse the numeric kernel's f output
     // through a dedicated pass that only accumulates f)
-    extern void row_loads(ocp_ctx *, const ocp_system *, const double4 *, double *);
-    row_loads(ctx, sys, fe.get(), f_out);
+    extern void row_loads(ocp_ctx *, const ocp_system *, const double4 *, double *, int64_t);
+    row_loads(ctx, sys, fe.get(), f_out, ld);
     sync(ctx);
 }
 
@@ -627,7 +627,8 @@ __global__ void __launch_bounds__(kAsmBlock) k_row_loads(int32_t n, const int32_
                                                          const int32_t *__restrict__ inc_ptr,
                                                          const int32_t *__restrict__ inc,
                                                          const int4 *__restrict__ tets,
-                                                         const double4 *__restrict__ fe, double *__restrict__ f) {
+                                                         const double4 *__restrict__ fe, double *__restrict__ f,
+                                                         int64_t ld) {
     const int i = blockIdx.x * kAsmBlock + threadIdx.x;
     if (i >= n) return;
     const int vi = vertex_of_dof[i];
@@ -638,13 +639,14 @@ __global__ void __launch_bounds__(kAsmBlock) k_row_loads(int32_t n, const int32_
         const double4 fv = fe[e];
         fi += (tv.x == vi) ? fv.x : (tv.y == vi) ? fv.y : (tv.z == vi) ? fv.z : fv.w;
     }
-    f[i] = fi;
+    f[(int64_t)i * ld] = fi;
 }
 
-void row_loads(ocp_ctx *ctx, const ocp_system *sys, const double4 *fe, double *f) {
+// f[i * ld] = sum over the tets of row i of their element load at its vertex
+void row_loads(ocp_ctx *ctx, const ocp_system *sys, const double4 *fe, double *f, int64_t ld) {
     k_row_loads<<<grid_for(sys->n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
         sys->n, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(),
-        reinterpret_cast<const int4 *>(sys->tets_ref), fe, f);
+        reinterpret_cast<const int4 *>(sys->tets_ref), fe, f, ld);
     OCP_LAUNCH_CHECK();
 }
 
@@ -832,6 +834,19 @@ extern "C" int fe_load(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *mesh
             fail(OCP_ERR_INVALID_ARG, "mesh differs from the one the system was assembled on");
         check_target(target, mesh->n_vertices);
         compute_loads(ctx, sys, mesh, target, f_dev);
+    });
+}
+
+extern "C" int fe_load_multi(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *mesh, int32_t k,
+                             const ocp_target *targets, double *F) {
+    if (!ctx) return OCP_ERR_INVALID_ARG;
+    return run_guarded(ctx, [&] {
+        if (!sys || !mesh || !targets || !F) fail(OCP_ERR_INVALID_ARG, "system, mesh, targets and F must not be NULL");
+        if (k < 1) fail(OCP_ERR_INVALID_ARG, "k must be >= 1");
+        if (mesh->n_vertices != sys->nv || mesh->n_tets != sys->nt || mesh->tets != sys->tets_ref)
+            fail(OCP_ERR_INVALID_ARG, "mesh differs from the one the system was assembled on");
+        for (int j = 0; j < k; ++j) check_target(&targets[j], mesh->n_vertices);
+        for (int j = 0; j < k; ++j) compute_loads(ctx, sys, mesh, &targets[j], F + j, k);
     });
 }
 

@@ -1,0 +1,838 @@
+// Block (multi right-hand side) PCG: k independent CG recurrences that share
+// one matrix and one AMG hierarchy (Section 5's PCG with one V-cycle as
+// preconditioner, applied to k load vectors at once).
+//
+// Vectors of the block are stored row-major, entry (i, j) at i*k + j, so that
+// the k values of a row are contiguous.  A row is handled by a group of KB
+// lanes (KB = 8/16/32/64 >= k), lane j owning column j: every matrix entry is
+// loaded once per group (the same address in all its lanes, a broadcast) and
+// multiplies k gathered values that sit next to each other in memory.  The
+// matrix stream is therefore read once per k right-hand sides; the vector
+// streams are what scale with k.
+//
+// Every column has its own alpha, beta, gamma and stop flag on the device.  A
+// column that has converged (or broken down, or hit the cap) is frozen: its
+// lanes skip all further work, so its vectors keep their final values.  The
+// V-cycle is the same polynomial-smoother cycle as the single-vector one,
+// with identical coefficients, in the hierarchy's precision; the CG
+// recurrences, dot products and the final residual are double.
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+#include <vector>
+
+#include "kernels.h"
+#include "system.h"
+
+namespace ocp {
+
+constexpr int kMaxCols = 64;
+constexpr int kBlkMaxBlocks = 4096;
+constexpr int kFinBlock = 1024;
+
+// Per-column CG scalars of the block solve (device).
+struct CgBlock {
+    double ff[kMaxCols];      // f_j . f_j
+    double tol2[kMaxCols];    // rtol^2 * (f.f or r0.z0)
+    double gamma[kMaxCols];   // r.z of the current iterate
+    double gamma0[kMaxCols];  // r0.z0
+    double alpha[kMaxCols], beta[kMaxCols];
+    double pq[kMaxCols];      // p.Ap
+    double rr[kMaxCols];      // r.r
+    int32_t cflag[kMaxCols];  // 0 running, 1 converged, 2 breakdown, 3 iteration cap
+    int32_t citer[kMaxCols];  // iterations taken by column j
+    int32_t flag;             // 1 once no column runs
+    int32_t iter;             // block iterations
+    int32_t k, stop_mode, maxit, pad;
+};
+
+struct BlkLaunch {
+    unsigned blocks;
+    int iters;
+};
+
+inline BlkLaunch blk_launch(int64_t n, int KB) {
+    const int64_t rpp = kBlock / KB;
+    int64_t iters = (n + rpp * kBlkMaxBlocks - 1) / (rpp * kBlkMaxBlocks);
+    if (iters < 1) iters = 1;
+    int64_t b = (n + rpp * iters - 1) / (rpp * iters);
+    return {(unsigned)(b < 1 ? 1 : b), (int)iters};
+}
+
+static int lanes_for_cols(int k) {
+    int g = 8;
+    while (g < k) g <<= 1;
+    return g;
+}
+
+#define OCP_DISPATCH_KB(kb, ...)                                        \
+    switch (kb) {                                                       \
+        case 8: { constexpr int KB = 8; __VA_ARGS__; } break;           \
+        case 16: { constexpr int KB = 16; __VA_ARGS__; } break;         \
+        case 32: { constexpr int KB = 32; __VA_ARGS__; } break;         \
+        default: { constexpr int KB = 64; __VA_ARGS__; } break;         \
+    }
+
+// Row loop of a block kernel: lane j of row group grp; `on` is false for
+// padding lanes and frozen columns.
+#define OCP_BLK_BEGIN(KB)                                                 \
+    constexpr int RPP = kBlock / KB;                                      \
+    const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);          \
+    const int j = threadIdx.x % KB, grp = threadIdx.x / KB;              \
+    const bool on = j < k && (cgb == nullptr || cgb->cflag[j] == 0);     \
+    const int base = (int)tile * RPP * iters;                            \
+    for (int it = 0; it < iters; ++it) {                                 \
+        const int row = base + it * RPP + grp;                           \
+        if (on && row < n) {                                             \
+            const size_t e = (size_t)row * k + j;
+#define OCP_BLK_END() \
+    }                 \
+    }
+
+namespace dev {
+// Per-column block sums in a fixed order: partials[j * nbs + block].
+template <int KB>
+__device__ __forceinline__ void blk_store_partial(double acc, double *partials, int nbs, int k) {
+    constexpr int RPP = kBlock / KB;
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < (unsigned)k) {
+        double s = 0.0;
+#pragma unroll
+        for (int g = 0; g < RPP; ++g) s += red[g * KB + threadIdx.x];
+        partials[(size_t)threadIdx.x * nbs + blockIdx.x] = s;
+    }
+}
+
+// Sum of the nb block partials of column j by one wavefront (fixed order).
+__device__ __forceinline__ double col_sum(const double *partials, int nbs, unsigned nb, int j) {
+    double s = 0.0;
+    for (unsigned b = threadIdx.x & 63; b < nb; b += 64) s += partials[(size_t)j * nbs + b];
+    return wave_sum(s);
+}
+
+// flag = 1 once every column has stopped (one block, after a column update).
+__device__ __forceinline__ void blk_update_flag(CgBlock *cgb) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int any = 0;
+        for (int j = 0; j < cgb->k; ++j) any |= (cgb->cflag[j] == 0);
+        cgb->flag = any ? 0 : 1;
+    }
+}
+}  // namespace dev
+
+#define OCP_FIN_COLUMNS(kk) for (int j = (int)(threadIdx.x >> 6); j < (kk); j += kFinBlock / 64)
+
+// ------------------------------------------------------------ V-cycle passes
+enum { kBR = 0, kBX2 = 1, kBPostA = 2, kBZ = 3 };
+
+// One pass over a level matrix for every column: r = b - A x with x either a
+// stored block (GDB false) or the first smoothing step a D^-1 b rebuilt on
+// the fly (GDB true); the epilogue per MODE matches the single-vector pass.
+template <typename T, typename BT, typename OT, bool GDB, int MODE>
+struct BlkOps {
+    const T *d;
+    const BT *b;
+    const T *g;
+    const T *xp;
+    const T *u;
+    T a, c1, c2;
+    OT *out1;
+    T *out2;
+    int k;
+    __device__ __forceinline__ T gather(int c, int j) const {
+        const size_t ec = (size_t)c * k + j;
+        if (GDB) return a * d[c] * (T)b[ec];
+        return g[ec];
+    }
+    __device__ __forceinline__ double finish(int i, size_t e, T s) const {
+        const BT bi = b[e];
+        const T r = (T)bi - s;
+        if (MODE == kBR) {
+            out1[e] = (OT)r;
+        } else if (MODE == kBX2) {
+            out1[e] = (OT)(d[i] * (c1 * (T)bi + c2 * r));
+        } else if (MODE == kBPostA) {
+            out1[e] = (OT)r;
+            out2[e] = xp[e] + a * d[i] * r;
+        } else {
+            T w = c2 * r;
+            if (u) w += c1 * u[e];
+            const T z = xp[e] + d[i] * w;
+            out1[e] = (OT)z;
+            return (double)bi * (double)z;
+        }
+        return 0.0;
+    }
+};
+
+template <int KB, typename T, typename BT, typename OT, bool GDB, int MODE, bool DOT>
+__global__ void __launch_bounds__(kBlock) k_blk_smooth(int32_t n, int k, int iters, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                       BlkOps<T, BT, OT, GDB, MODE> ops, const CgBlock *cgb,
+                                                       double *partials, int nbs) {
+    if (cgb && cgb->flag) return;
+    double acc = 0.0;
+    OCP_BLK_BEGIN(KB)
+    const int pe = rp[row + 1];
+    T s = T(0);
+#pragma unroll 4
+    for (int p = rp[row]; p < pe; ++p) s += val[p] * ops.gather(col[p], j);
+    const double c = ops.finish(row, e, s);
+    if (DOT) acc += c;
+    OCP_BLK_END()
+    if (DOT) dev::blk_store_partial<KB>(acc, partials, nbs, k);
+}
+
+// y = M x for every column (restriction with R = P^T)
+template <int KB, typename T>
+__global__ void __launch_bounds__(kBlock) k_blk_spmv(int32_t n, int k, int iters, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                     const T *__restrict__ x, T *__restrict__ y, const CgBlock *cgb) {
+    if (cgb && cgb->flag) return;
+    OCP_BLK_BEGIN(KB)
+    const int pe = rp[row + 1];
+    T s = T(0);
+#pragma unroll 4
+    for (int p = rp[row]; p < pe; ++p) s += val[p] * x[(size_t)col[p] * k + j];
+    y[e] = s;
+    OCP_BLK_END()
+}
+
+// xp = base + P xc, base = the stored pre-smoothed block (HX) or a d .* b
+template <int KB, typename T, typename BT, bool HX>
+__global__ void __launch_bounds__(kBlock) k_blk_prolong(int32_t n, int k, int iters, const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                        const T *__restrict__ d, const BT *__restrict__ b,
+                                                        const T *__restrict__ xs, T a, const T *__restrict__ xc,
+                                                        T *__restrict__ xp, const CgBlock *cgb) {
+    if (cgb && cgb->flag) return;
+    OCP_BLK_BEGIN(KB)
+    const int pe = rp[row + 1];
+    T s = T(0);
+#pragma unroll 4
+    for (int p = rp[row]; p < pe; ++p) s += val[p] * xc[(size_t)col[p] * k + j];
+    xp[e] = (HX ? xs[e] : a * d[row] * (T)b[e]) + s;
+    OCP_BLK_END()
+}
+
+// x = Ainv b on the last level (dense inverse, row-major n x n)
+template <int KB, typename T, typename BT, typename ZT>
+__global__ void __launch_bounds__(kBlock) k_blk_dense(int32_t n, int k, int iters, const T *__restrict__ inv,
+                                                      const BT *__restrict__ b, ZT *__restrict__ x,
+                                                      const CgBlock *cgb) {
+    if (cgb && cgb->flag) return;
+    OCP_BLK_BEGIN(KB)
+    const T *ir = inv + (size_t)row * n;
+    T s = T(0);
+    for (int c = 0; c < n; ++c) s += ir[c] * (T)b[(size_t)c * k + j];
+    x[e] = (ZT)s;
+    OCP_BLK_END()
+}
+
+// x = d .* b (last level without a dense inverse)
+template <int KB, typename T, typename BT, typename ZT>
+__global__ void __launch_bounds__(kBlock) k_blk_diag(int32_t n, int k, int iters, const T *__restrict__ d,
+                                                     const BT *__restrict__ b, ZT *__restrict__ x,
+                                                     const CgBlock *cgb) {
+    if (cgb && cgb->flag) return;
+    OCP_BLK_BEGIN(KB)
+    x[e] = (ZT)(d[row] * (T)b[e]);
+    OCP_BLK_END()
+}
+
+// r.z per column (single-level hierarchy)
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_blk_rz(int32_t n, int k, int iters, const double *__restrict__ r,
+                                                   const double *__restrict__ z, const CgBlock *cgb, double *partials,
+                                                   int nbs) {
+    if (cgb && cgb->flag) return;
+    double acc = 0.0;
+    OCP_BLK_BEGIN(KB)
+    acc += r[e] * z[e];
+    OCP_BLK_END()
+    dev::blk_store_partial<KB>(acc, partials, nbs, k);
+}
+
+// ------------------------------------------------------------- CG kernels
+// X = 0, R = F, P = 0 and f.f per column; F column j of row i sits at
+// F[i * fs_row + j * fs_col] (fs_col = 0: the same vector for every column).
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_blk_init(int32_t n, int k, int iters, const double *__restrict__ F,
+                                                     int64_t fs_row, int fs_col, double *__restrict__ X,
+                                                     double *__restrict__ R, double *__restrict__ P,
+                                                     double *partials, int nbs) {
+    const CgBlock *cgb = nullptr;
+    double acc = 0.0;
+    OCP_BLK_BEGIN(KB)
+    const double fi = F[(size_t)row * fs_row + (size_t)j * fs_col];
+    X[e] = 0.0;
+    R[e] = fi;
+    P[e] = 0.0;
+    acc += fi * fi;
+    OCP_BLK_END()
+    dev::blk_store_partial<KB>(acc, partials, nbs, k);
+}
+
+// Q = A P (FP64 CSR) and p.q per column
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_blk_spmm_pq(int32_t n, int k, int iters, const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ col,
+                                                        const double *__restrict__ val, const double *__restrict__ P,
+                                                        double *__restrict__ Q, const CgBlock *cgb, double *partials,
+                                                        int nbs) {
+    if (cgb->flag) return;
+    double acc = 0.0;
+    OCP_BLK_BEGIN(KB)
+    const int pe = rp[row + 1];
+    double s = 0.0;
+#pragma unroll 4
+    for (int p = rp[row]; p < pe; ++p) s += val[p] * P[(size_t)col[p] * k + j];
+    Q[e] = s;
+    acc += P[e] * s;
+    OCP_BLK_END()
+    dev::blk_store_partial<KB>(acc, partials, nbs, k);
+}
+
+// F - A X per column, squared norm (true residual at exit; every column)
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_blk_resid2(int32_t n, int k, int iters, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col,
+                                                       const double *__restrict__ val, const double *__restrict__ X,
+                                                       const double *__restrict__ F, int64_t fs_row, int fs_col,
+                                                       double *partials, int nbs) {
+    const CgBlock *cgb = nullptr;
+    double acc = 0.0;
+    OCP_BLK_BEGIN(KB)
+    const int pe = rp[row + 1];
+    double s = 0.0;
+    for (int p = rp[row]; p < pe; ++p) s += val[p] * X[(size_t)col[p] * k + j];
+    (void)e;
+    const double r = F[(size_t)row * fs_row + (size_t)j * fs_col] - s;
+    acc += r * r;
+    OCP_BLK_END()
+    dev::blk_store_partial<KB>(acc, partials, nbs, k);
+}
+
+// X += alpha P, R -= alpha Q, r.r per column; with JAC also Z = dinv R and r.z
+template <int KB, bool JAC>
+__global__ void __launch_bounds__(kBlock) k_blk_update(int32_t n, int k, int iters, double *__restrict__ X,
+                                                       double *__restrict__ R, const double *__restrict__ P,
+                                                       const double *__restrict__ Q, const double *__restrict__ dinv,
+                                                       double *__restrict__ Z, const CgBlock *cgb, double *partials,
+                                                       double *partials2, int nbs) {
+    if (cgb->flag) return;
+    double rr = 0.0, rz = 0.0;
+    OCP_BLK_BEGIN(KB)
+    const double a = cgb->alpha[j];
+    X[e] += a * P[e];
+    const double r = R[e] - a * Q[e];
+    R[e] = r;
+    rr += r * r;
+    if (JAC) {
+        const double z = dinv[row] * r;
+        Z[e] = z;
+        rz += r * z;
+    }
+    OCP_BLK_END()
+    dev::blk_store_partial<KB>(rr, partials, nbs, k);
+    if (JAC) {
+        __syncthreads();
+        dev::blk_store_partial<KB>(rz, partials2, nbs, k);
+    }
+}
+
+// Z = dinv R and r.z (Jacobi preconditioner at the start)
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_blk_jacobi(int32_t n, int k, int iters, const double *__restrict__ R,
+                                                       const double *__restrict__ dinv, double *__restrict__ Z,
+                                                       const CgBlock *cgb, double *partials, int nbs) {
+    if (cgb->flag) return;
+    double rz = 0.0;
+    OCP_BLK_BEGIN(KB)
+    const double z = dinv[row] * R[e];
+    Z[e] = z;
+    rz += R[e] * z;
+    OCP_BLK_END()
+    dev::blk_store_partial<KB>(rz, partials, nbs, k);
+}
+
+// P = Z + beta P
+template <int KB>
+__global__ void __launch_bounds__(kBlock) k_blk_pupdate(int32_t n, int k, int iters, double *__restrict__ P,
+                                                        const double *__restrict__ Z, const CgBlock *cgb) {
+    if (cgb->flag) return;
+    OCP_BLK_BEGIN(KB)
+    P[e] = Z[e] + cgb->beta[j] * P[e];
+    OCP_BLK_END()
+}
+
+// U[v][j] = X[dof(v)][j], 0 on Gamma
+__global__ void k_blk_scatter(int32_t nv, int k, const int32_t *__restrict__ dof_of_vertex,
+                              const double *__restrict__ X, double *__restrict__ U) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nv * k) return;
+    const int v = (int)(t / k), j = (int)(t % k);
+    const int d = dof_of_vertex[v];
+    U[t] = d >= 0 ? X[(size_t)d * k + j] : 0.0;
+}
+
+// ------------------------------------------------- per-column finalize kernels
+__global__ void __launch_bounds__(kFinBlock) k_blk_fin_init(unsigned nb, const double *partials, int nbs,
+                                                            CgBlock *cgb, int k, double rtol, int mode, int maxit) {
+    OCP_FIN_COLUMNS(k) {
+        const double tot = dev::col_sum(partials, nbs, nb, j);
+        if ((threadIdx.x & 63) == 0) {
+            cgb->ff[j] = tot;
+            cgb->rr[j] = tot;
+            cgb->tol2[j] = (mode == OCP_STOP_L2) ? rtol * rtol * tot : rtol * rtol;
+            cgb->gamma[j] = 1.0;
+            cgb->gamma0[j] = 0.0;
+            cgb->alpha[j] = 0.0;
+            cgb->beta[j] = 0.0;
+            cgb->pq[j] = 0.0;
+            cgb->citer[j] = 0;
+            cgb->cflag[j] = (tot == 0.0) ? 1 : (isfinite(tot) ? 0 : 2);
+        }
+    }
+    if (threadIdx.x == 0) {
+        cgb->k = k;
+        cgb->iter = 0;
+        cgb->stop_mode = mode;
+        cgb->maxit = maxit;
+    }
+    dev::blk_update_flag(cgb);
+}
+
+// after the preconditioner: beta = rz / gamma, gamma = rz; breakdown and the
+// preconditioned stop test, per running column
+__global__ void __launch_bounds__(kFinBlock) k_blk_fin_rz(unsigned nb, const double *partials, int nbs, CgBlock *cgb) {
+    if (cgb->flag) return;
+    const int k = cgb->k;
+    OCP_FIN_COLUMNS(k) {
+        if (cgb->cflag[j] != 0) continue;
+        const double rz = dev::col_sum(partials, nbs, nb, j);
+        if ((threadIdx.x & 63) == 0) {
+            const int it = cgb->citer[j];
+            if (it == 0) cgb->gamma0[j] = rz;
+            if (!(rz > 0.0) || !isfinite(rz)) {
+                cgb->cflag[j] = (rz == 0.0 && cgb->rr[j] == 0.0) ? 1 : 2;
+                cgb->beta[j] = 0.0;
+            } else {
+                cgb->beta[j] = (it == 0) ? 0.0 : rz / cgb->gamma[j];
+                cgb->gamma[j] = rz;
+                if (cgb->stop_mode == OCP_STOP_PRECOND) {
+                    if (it == 0) cgb->tol2[j] *= rz;   // tol2 held rtol^2 until now
+                    else if (rz <= cgb->tol2[j]) cgb->cflag[j] = 1;
+                }
+            }
+        }
+    }
+    dev::blk_update_flag(cgb);
+}
+
+// alpha = gamma / p.q per running column
+__global__ void __launch_bounds__(kFinBlock) k_blk_fin_alpha(unsigned nb, const double *partials, int nbs,
+                                                             CgBlock *cgb) {
+    if (cgb->flag) return;
+    const int k = cgb->k;
+    OCP_FIN_COLUMNS(k) {
+        if (cgb->cflag[j] != 0) continue;
+        const double pq = dev::col_sum(partials, nbs, nb, j);
+        if ((threadIdx.x & 63) == 0) {
+            cgb->pq[j] = pq;
+            if (!(pq > 0.0) || !isfinite(pq)) {
+                cgb->cflag[j] = 2;
+                cgb->alpha[j] = 0.0;
+            } else {
+                cgb->alpha[j] = cgb->gamma[j] / pq;
+            }
+        }
+    }
+    dev::blk_update_flag(cgb);
+}
+
+// r.r after the update: L2 stop test, breakdown, iteration cap; with JAC the
+// Jacobi r.z follows as in k_blk_fin_rz
+template <bool JAC>
+__global__ void __launch_bounds__(kFinBlock) k_blk_fin_update(unsigned nb, const double *partials,
+                                                              const double *partials2, int nbs, CgBlock *cgb) {
+    if (cgb->flag) return;
+    const int k = cgb->k;
+    OCP_FIN_COLUMNS(k) {
+        if (cgb->cflag[j] != 0) continue;
+        const double rr = dev::col_sum(partials, nbs, nb, j);
+        const double rz = JAC ? dev::col_sum(partials2, nbs, nb, j) : 0.0;
+        if ((threadIdx.x & 63) == 0) {
+            cgb->rr[j] = rr;
+            const int it = cgb->citer[j] + 1;
+            cgb->citer[j] = it;
+            if (cgb->stop_mode == OCP_STOP_L2 && rr <= cgb->tol2[j]) {
+                cgb->cflag[j] = 1;
+            } else if (!isfinite(rr)) {
+                cgb->cflag[j] = 2;
+            } else {
+                if (JAC) {
+                    if (!(rz > 0.0) || !isfinite(rz)) {
+                        cgb->cflag[j] = (rz == 0.0 && rr == 0.0) ? 1 : 2;
+                        cgb->beta[j] = 0.0;
+                    } else {
+                        cgb->beta[j] = rz / cgb->gamma[j];
+                        cgb->gamma[j] = rz;
+                        if (cgb->stop_mode == OCP_STOP_PRECOND && rz <= cgb->tol2[j]) cgb->cflag[j] = 1;
+                    }
+                }
+                if (cgb->cflag[j] == 0 && it >= cgb->maxit) cgb->cflag[j] = 3;
+            }
+        }
+    }
+    if (threadIdx.x == 0) cgb->iter += 1;
+    dev::blk_update_flag(cgb);
+}
+
+// ---------------------------------------------------------------- V-cycle
+// Work blocks of one level in the hierarchy's precision, [n_l][k] each.
+struct BlkLevelWork {
+    DevBuf<char> vb, vr, vx, vxp, vx1, vx2;
+};
+
+template <typename T>
+struct BlkArrays {
+    const T *A, *P, *R, *d, *inv;
+};
+template <typename T>
+static BlkArrays<T> blk_arrays(const Level &L);
+template <>
+BlkArrays<double> blk_arrays<double>(const Level &L) {
+    return {L.A_val, L.P_val.get(), L.R_val.get(), L.dinv.get(), L.dense_inv.get()};
+}
+template <>
+BlkArrays<float> blk_arrays<float>(const Level &L) {
+    return {L.A_val32.get(), L.P_val32.get(), L.R_val32.get(), L.dinv32.get(), L.dense_inv32.get()};
+}
+
+struct BlkCtx {
+    int k, KB;
+    double *part;   // [k][nbs] partials of the final r.z
+    int nbs;
+    CgBlock *cgb;
+    std::vector<BlkLevelWork> *work;
+};
+
+// Z = B R for the k columns.  Returns the number of blocks whose r.z
+// partials the last pass stored (0 if cgb is null).
+template <int KB, typename T>
+static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *R, double *Z, const BlkCtx &bc) {
+    const auto &lv = h->levels;
+    const int L = (int)lv.size();
+    const int k = bc.k;
+    hipStream_t s = ctx->stream;
+    CgBlock *cgb = bc.cgb;
+    auto &W = *bc.work;
+    auto lvec = [&](int l, DevBuf<char> BlkLevelWork::*m) { return reinterpret_cast<T *>((W[l].*m).get()); };
+
+    if (L == 1) {
+        const Level &l0 = *lv[0];
+        const auto a = blk_arrays<T>(l0);
+        const BlkLaunch LB = blk_launch(l0.n, KB);
+        if (a.inv)
+            k_blk_dense<KB, T, double, double><<<LB.blocks, kBlock, 0, s>>>(l0.n, k, LB.iters, a.inv, R, Z, cgb);
+        else
+            k_blk_diag<KB, T, double, double><<<LB.blocks, kBlock, 0, s>>>(l0.n, k, LB.iters, a.d, R, Z, cgb);
+        OCP_LAUNCH_CHECK();
+        if (!cgb) return 0;
+        k_blk_rz<KB><<<LB.blocks, kBlock, 0, s>>>(l0.n, k, LB.iters, R, Z, cgb, bc.part, bc.nbs);
+        OCP_LAUNCH_CHECK();
+        return LB.blocks;
+    }
+
+    // ---- down
+    for (int l = 0; l < L - 1; ++l) {
+        const Level &cur = *lv[l];
+        const Level &nxt = *lv[l + 1];
+        const auto a = blk_arrays<T>(cur);
+        const BlkLaunch LB = blk_launch(cur.n, KB);
+        T *rres = lvec(l, &BlkLevelWork::vr);
+        T *x2 = lvec(l, &BlkLevelWork::vx2);
+        const T ca = (T)cur.cheb_a, c1 = (T)cur.cheb_c1, c2 = (T)cur.cheb_c2;
+        auto run_down = [&](auto bptr) {
+            using BT = std::remove_const_t<std::remove_pointer_t<decltype(bptr)>>;
+            if (cur.deg == 2) {
+                k_blk_smooth<KB, T, BT, T, true, kBX2, false><<<LB.blocks, kBlock, 0, s>>>(
+                    cur.n, k, LB.iters, cur.A_rp, cur.A_col, a.A,
+                    BlkOps<T, BT, T, true, kBX2>{a.d, bptr, nullptr, nullptr, nullptr, ca, c1, c2, x2, nullptr, k},
+                    cgb, nullptr, 0);
+                k_blk_smooth<KB, T, BT, T, false, kBR, false><<<LB.blocks, kBlock, 0, s>>>(
+                    cur.n, k, LB.iters, cur.A_rp, cur.A_col, a.A,
+                    BlkOps<T, BT, T, false, kBR>{a.d, bptr, x2, nullptr, nullptr, ca, c1, c2, rres, nullptr, k}, cgb,
+                    nullptr, 0);
+            } else {
+                k_blk_smooth<KB, T, BT, T, true, kBR, false><<<LB.blocks, kBlock, 0, s>>>(
+                    cur.n, k, LB.iters, cur.A_rp, cur.A_col, a.A,
+                    BlkOps<T, BT, T, true, kBR>{a.d, bptr, nullptr, nullptr, nullptr, ca, c1, c2, rres, nullptr, k},
+                    cgb, nullptr, 0);
+            }
+            OCP_LAUNCH_CHECK();
+        };
+        if (l == 0)
+            run_down(R);
+        else
+            run_down(static_cast<const T *>(lvec(l, &BlkLevelWork::vb)));
+        const BlkLaunch LR = blk_launch(nxt.n, KB);
+        k_blk_spmv<KB, T><<<LR.blocks, kBlock, 0, s>>>(nxt.n, k, LR.iters, cur.R_rp.get(), cur.R_col.get(), a.R, rres,
+                                                       lvec(l + 1, &BlkLevelWork::vb), cgb);
+        OCP_LAUNCH_CHECK();
+    }
+    // ---- coarsest
+    {
+        const Level &cl = *lv[L - 1];
+        const auto a = blk_arrays<T>(cl);
+        const BlkLaunch LB = blk_launch(cl.n, KB);
+        const T *b = lvec(L - 1, &BlkLevelWork::vb);
+        T *x = lvec(L - 1, &BlkLevelWork::vx);
+        if (a.inv)
+            k_blk_dense<KB, T, T, T><<<LB.blocks, kBlock, 0, s>>>(cl.n, k, LB.iters, a.inv, b, x, cgb);
+        else
+            k_blk_diag<KB, T, T, T><<<LB.blocks, kBlock, 0, s>>>(cl.n, k, LB.iters, a.d, b, x, cgb);
+        OCP_LAUNCH_CHECK();
+    }
+    // ---- up
+    unsigned fin_nb = 0;
+    for (int l = L - 2; l >= 0; --l) {
+        const Level &cur = *lv[l];
+        const auto a = blk_arrays<T>(cur);
+        const BlkLaunch LB = blk_launch(cur.n, KB);
+        const T *xc = lvec(l + 1, &BlkLevelWork::vx);
+        T *xp = lvec(l, &BlkLevelWork::vxp);
+        T *x2 = lvec(l, &BlkLevelWork::vx2);
+        T *r0 = lvec(l, &BlkLevelWork::vr);
+        T *x1 = lvec(l, &BlkLevelWork::vx1);
+        const T ca = (T)cur.cheb_a, c1 = (T)cur.cheb_c1, c2 = (T)cur.cheb_c2;
+        const T zero = T(0);
+        auto run_up = [&](auto bptr, auto outptr, auto dot_tag) {
+            using BT = std::remove_const_t<std::remove_pointer_t<decltype(bptr)>>;
+            using OT = std::remove_pointer_t<decltype(outptr)>;
+            constexpr bool DOT = decltype(dot_tag)::value;
+            if (cur.deg == 2)
+                k_blk_prolong<KB, T, BT, true><<<LB.blocks, kBlock, 0, s>>>(cur.n, k, LB.iters, cur.P_rp.get(),
+                                                                          cur.P_col.get(), a.P, a.d, bptr, x2, ca,
+                                                                          xc, xp, cgb);
+            else
+                k_blk_prolong<KB, T, BT, false><<<LB.blocks, kBlock, 0, s>>>(cur.n, k, LB.iters, cur.P_rp.get(),
+                                                                           cur.P_col.get(), a.P, a.d, bptr, nullptr,
+                                                                           ca, xc, xp, cgb);
+            OCP_LAUNCH_CHECK();
+            if (cur.deg == 2) {
+                k_blk_smooth<KB, T, BT, T, false, kBPostA, false><<<LB.blocks, kBlock, 0, s>>>(
+                    cur.n, k, LB.iters, cur.A_rp, cur.A_col, a.A,
+                    BlkOps<T, BT, T, false, kBPostA>{a.d, bptr, xp, xp, nullptr, ca, c1, c2, r0, x1, k}, cgb, nullptr,
+                    0);
+                k_blk_smooth<KB, T, BT, OT, false, kBZ, DOT><<<LB.blocks, kBlock, 0, s>>>(
+                    cur.n, k, LB.iters, cur.A_rp, cur.A_col, a.A,
+                    BlkOps<T, BT, OT, false, kBZ>{a.d, bptr, x1, xp, r0, ca, c1, c2, outptr, nullptr, k}, cgb,
+                    DOT ? bc.part : nullptr, bc.nbs);
+            } else {
+                k_blk_smooth<KB, T, BT, OT, false, kBZ, DOT><<<LB.blocks, kBlock, 0, s>>>(
+                    cur.n, k, LB.iters, cur.A_rp, cur.A_col, a.A,
+                    BlkOps<T, BT, OT, false, kBZ>{a.d, bptr, xp, xp, nullptr, ca, zero, ca, outptr, nullptr, k}, cgb,
+                    DOT ? bc.part : nullptr, bc.nbs);
+            }
+            OCP_LAUNCH_CHECK();
+            if (DOT) fin_nb = LB.blocks;
+        };
+        if (l == 0) {
+            if (cgb)
+                run_up(R, Z, std::true_type{});
+            else
+                run_up(R, Z, std::false_type{});
+        } else {
+            run_up(static_cast<const T *>(lvec(l, &BlkLevelWork::vb)), lvec(l, &BlkLevelWork::vx), std::false_type{});
+        }
+    }
+    return fin_nb;
+}
+
+template <typename T>
+static unsigned vcycle_block(ocp_ctx *ctx, const ocp_hierarchy *h, const double *R, double *Z, const BlkCtx &bc) {
+    unsigned nb = 0;
+    OCP_DISPATCH_KB(bc.KB, (nb = vcycle_block_t<KB, T>(ctx, h, R, Z, bc)));
+    return nb;
+}
+
+static void alloc_block_work(ocp_ctx *ctx, const ocp_hierarchy *h, int k, std::vector<BlkLevelWork> &W) {
+    const size_t vs = h->params.precision == OCP_PREC_MIXED ? sizeof(float) : sizeof(double);
+    const int L = (int)h->levels.size();
+    W.resize(L);
+    for (int l = 0; l < L; ++l) {
+        const size_t bytes = (size_t)h->levels[l]->n * k * vs;
+        const bool inner = l < L - 1;
+        if (l > 0) W[l].vb.reset(ctx, bytes);
+        if (l > 0) W[l].vx.reset(ctx, bytes);
+        if (inner) {
+            W[l].vr.reset(ctx, bytes);
+            W[l].vxp.reset(ctx, bytes);
+            W[l].vx1.reset(ctx, bytes);
+            W[l].vx2.reset(ctx, bytes);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ driver
+static int worst_status(const std::vector<int> &st) {
+    int w = OCP_OK;
+    for (int s : st) {
+        if (s == OCP_ERR_BREAKDOWN) return OCP_ERR_BREAKDOWN;
+        if (s == OCP_MAXIT) w = OCP_MAXIT;
+    }
+    return w;
+}
+
+static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, int k, const double *F, double *U,
+                        double rtol, int32_t maxit, int32_t flags, ocp_solve_info *infos, int *status) {
+    const int32_t n = sys->n;
+    const int KB = lanes_for_cols(k);
+    const int64_t fs_row = F ? k : 1;
+    const int fs_col = F ? 1 : 0;
+    const double *Fp = F ? F : sys->f.get();
+    const size_t nk = (size_t)n * k;
+    DevBuf<double> X(ctx, nk), R(ctx, nk), P(ctx, nk), Q(ctx, nk), Z(ctx, nk);
+    const BlkLaunch LB = blk_launch(n, KB);
+    const int nbs = (int)LB.blocks;
+    DevBuf<double> part0(ctx, (size_t)k * nbs), part1(ctx, (size_t)k * nbs), part2(ctx, (size_t)k * nbs);
+    DevBuf<CgBlock> cgbuf(ctx, 1);
+    CgBlock *cgb = cgbuf.get();
+    const double *dinv = h ? nullptr : system_dinv(ctx, sys);
+    const int mode = (flags & OCP_STOP_PRECOND) ? OCP_STOP_PRECOND : OCP_STOP_L2;
+    std::vector<BlkLevelWork> work;
+    if (h) alloc_block_work(ctx, h, k, work);
+    const bool mixed = h && h->params.precision == OCP_PREC_MIXED;
+    BlkCtx bc{k, KB, part1.get(), nbs, cgb, &work};
+    hipStream_t s = ctx->stream;
+
+    auto precond = [&](void) {
+        if (h) {
+            const unsigned nb = mixed ? vcycle_block<float>(ctx, h, R.get(), Z.get(), bc)
+                                      : vcycle_block<double>(ctx, h, R.get(), Z.get(), bc);
+            k_blk_fin_rz<<<1, kFinBlock, 0, s>>>(nb, part1.get(), nbs, cgb);
+        } else {
+            OCP_DISPATCH_KB(KB, (k_blk_jacobi<KB><<<LB.blocks, kBlock, 0, s>>>(n, k, LB.iters, R.get(), dinv, Z.get(),
+                                                                            cgb, part1.get(), nbs)));
+            k_blk_fin_rz<<<1, kFinBlock, 0, s>>>(LB.blocks, part1.get(), nbs, cgb);
+        }
+        OCP_LAUNCH_CHECK();
+    };
+    auto pupdate = [&](void) {
+        OCP_DISPATCH_KB(KB, (k_blk_pupdate<KB><<<LB.blocks, kBlock, 0, s>>>(n, k, LB.iters, P.get(), Z.get(), cgb)));
+        OCP_LAUNCH_CHECK();
+    };
+
+    ctx->prof_iter = -1;
+    OCP_HIP(hipEventRecord(ctx->ev0, s));
+    OCP_DISPATCH_KB(KB, (k_blk_init<KB><<<LB.blocks, kBlock, 0, s>>>(n, k, LB.iters, Fp, fs_row, fs_col, X.get(),
+                                                                      R.get(), P.get(), part0.get(), nbs)));
+    k_blk_fin_init<<<1, kFinBlock, 0, s>>>(LB.blocks, part0.get(), nbs, cgb, k, rtol, mode, maxit);
+    OCP_LAUNCH_CHECK();
+    precond();
+    pupdate();
+
+    struct {
+        int32_t flag, iter;
+    } hs{0, 0};
+    int chunk = 2;
+    ctx->prof_iter = 0;
+    for (;;) {
+        read_back(ctx, &hs, &cgb->flag, sizeof(hs));
+        if (hs.flag != 0) break;
+        for (int c = 0; c < chunk; ++c) {
+            const int pr = prof_begin(ctx, OCP_KERNEL_BLK_SPMM);
+            OCP_DISPATCH_KB(KB, (k_blk_spmm_pq<KB><<<LB.blocks, kBlock, 0, s>>>(
+                                    n, k, LB.iters, sys->row_ptr.get(), sys->col.get(), sys->val.get(), P.get(),
+                                    Q.get(), cgb, part0.get(), nbs)));
+            prof_end(ctx, pr);
+            k_blk_fin_alpha<<<1, kFinBlock, 0, s>>>(LB.blocks, part0.get(), nbs, cgb);
+            if (h) {
+                OCP_DISPATCH_KB(KB, (k_blk_update<KB, false><<<LB.blocks, kBlock, 0, s>>>(
+                                        n, k, LB.iters, X.get(), R.get(), P.get(), Q.get(), nullptr, nullptr, cgb,
+                                        part0.get(), nullptr, nbs)));
+                k_blk_fin_update<false><<<1, kFinBlock, 0, s>>>(LB.blocks, part0.get(), nullptr, nbs, cgb);
+                OCP_LAUNCH_CHECK();
+                precond();
+            } else {
+                OCP_DISPATCH_KB(KB, (k_blk_update<KB, true><<<LB.blocks, kBlock, 0, s>>>(
+                                        n, k, LB.iters, X.get(), R.get(), P.get(), Q.get(), dinv, Z.get(), cgb,
+                                        part0.get(), part2.get(), nbs)));
+                k_blk_fin_update<true><<<1, kFinBlock, 0, s>>>(LB.blocks, part0.get(), part2.get(), nbs, cgb);
+                OCP_LAUNCH_CHECK();
+            }
+            pupdate();
+            ++ctx->prof_iter;
+        }
+        if (chunk < 8) chunk *= 2;
+    }
+    OCP_HIP(hipEventRecord(ctx->ev1, s));
+
+    // true residuals in double, then U on all vertices
+    OCP_DISPATCH_KB(KB, (k_blk_resid2<KB><<<LB.blocks, kBlock, 0, s>>>(n, k, LB.iters, sys->row_ptr.get(),
+                                                                        sys->col.get(), sys->val.get(), X.get(), Fp,
+                                                                        fs_row, fs_col, part2.get(), nbs)));
+    OCP_LAUNCH_CHECK();
+    k_blk_scatter<<<grid_for((int64_t)sys->nv * k, 256), 256, 0, s>>>(sys->nv, k, sys->dof_of_vertex.get(), X.get(),
+                                                                       U);
+    OCP_LAUNCH_CHECK();
+    // per-column residual partials and scalars to the host (summed there in
+    // block order)
+    std::vector<double> res_part((size_t)k * nbs);
+    OCP_HIP(hipMemcpyAsync(res_part.data(), part2.get(), sizeof(double) * k * nbs, hipMemcpyDeviceToHost, s));
+    CgBlock hcg;
+    OCP_HIP(hipMemcpyAsync(&hcg, cgb, sizeof(CgBlock), hipMemcpyDeviceToHost, s));
+    sync(ctx);
+    float ms = 0.f;
+    OCP_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    prof_resolve(ctx, hs.iter - 1);
+
+    std::vector<int> st((size_t)k);
+    for (int j = 0; j < k; ++j) {
+        double res2 = 0.0;
+        for (int b = 0; b < nbs; ++b) res2 += res_part[(size_t)j * nbs + b];
+        const int cf = hcg.cflag[j];
+        st[j] = cf == 2 ? OCP_ERR_BREAKDOWN : cf == 3 ? OCP_MAXIT : OCP_OK;
+        if (infos) {
+            ocp_solve_info &in = infos[j];
+            in.iterations = hcg.citer[j];
+            in.status = st[j];
+            in.rel_res_l2 = hcg.ff[j] > 0 ? std::sqrt(hcg.rr[j] / hcg.ff[j]) : 0.0;
+            in.rel_res_precond = hcg.gamma0[j] > 0 ? std::sqrt(hcg.gamma[j] / hcg.gamma0[j]) : 0.0;
+            in.true_rel_res = hcg.ff[j] > 0 ? std::sqrt(res2 / hcg.ff[j]) : 0.0;
+            in.solve_ms = ms;
+        }
+    }
+    *status = worst_status(st);
+}
+
+}  // namespace ocp
+
+using namespace ocp;
+
+extern "C" int pcg_solve_multi(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, int32_t k,
+                               const double *F, double *U, double rtol, int32_t maxit, int32_t flags,
+                               ocp_solve_info *infos) {
+    if (!ctx) return OCP_ERR_INVALID_ARG;
+    int status = OCP_OK;
+    int rc = run_guarded(ctx, [&] {
+        if (!sys || !U) fail(OCP_ERR_INVALID_ARG, "system and U must not be NULL");
+        if (k < 1 || k > kMaxCols) fail(OCP_ERR_INVALID_ARG, "k must lie in 1..64");
+        if (!(rtol > 0.0) || !std::isfinite(rtol)) fail(OCP_ERR_INVALID_ARG, "rtol must be positive");
+        if (maxit < 1) fail(OCP_ERR_INVALID_ARG, "maxit must be >= 1");
+        if (h && h->sys != sys) fail(OCP_ERR_INVALID_ARG, "hierarchy belongs to another system");
+        solve_multi(ctx, const_cast<ocp_system *>(sys), h, k, F, U, rtol, maxit, flags, infos, &status);
+    });
+    if (rc != OCP_OK) {
+        if (infos)
+            for (int j = 0; j < std::max(0, std::min<int>(k, kMaxCols)); ++j) infos[j].status = rc;
+        return rc;
+    }
+    if (status == OCP_ERR_BREAKDOWN) ctx->last_error = "CG breakdown in at least one column";
+    return status;
+}

@@ -1,0 +1,168 @@
+"""GPU parity of the block (multi right-hand side) PCG, through the C interface.
+
+Bars: the load block equals k single load vectors bit for bit (the same
+kernels write it) and matches the oracle's loads; with an FP64 hierarchy at a
+tight tolerance every column is within 1e-10 relative error of the oracle's
+own solve of that target; in mixed precision every column reaches the 1e-8
+relative residual (recomputed in double) and its error against the FP64
+oracle is reported; frozen and zero columns leave the other columns' results
+unchanged.
+"""
+import numpy as np
+import pytest
+
+import ocp_inputs as I
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2102_03515_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    return P.Context()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _targets(k, base=2000, n_modes=8):
+    return [I.random_sine_modes(base + j, n_modes=n_modes) for j in range(k)]
+
+
+def test_load_multi_matches_single_loads_and_oracle(P, ctx):
+    import torch
+    print("[load_multi] cube10 jitter, 5 targets", flush=True)
+    mesh = I.kuhn_mesh(10, jitter=0.15, seed=21)
+    targets = [I.single_sine(), I.box_indicator(), I.random_sine_modes(5, n_modes=13, kmax=20),
+               I.single_sine(offset=1.0), I.random_sine_modes(6)]
+    dm = P.upload_mesh(mesh)
+    s = P.fe_assemble(ctx, dm, 1e-2, targets[0])
+    F = s.load_multi(targets)
+    assert F.shape == (s.n, len(targets))
+    for j, t in enumerate(targets):
+        fj = s.load(t)
+        assert torch.equal(F[:, j].contiguous(), fj), j
+        o = O.assemble(mesh, 1e-2, t)
+        np.testing.assert_allclose(F[:, j].cpu().numpy(), o.f, rtol=0, atol=1e-13 * np.abs(o.f).max())
+
+
+@pytest.mark.parametrize("k,N", [(1, 10), (3, 14), (9, 14), (32, 12), (64, 8)])
+def test_multi_fp64_matches_oracle(P, ctx, k, N):
+    print(f"[multi fp64] cube{N} jitter k={k}", flush=True)
+    rho = 1.0 / N ** 2
+    mesh = I.kuhn_mesh(N, jitter=0.15, seed=23)
+    targets = _targets(k)
+    dm = P.upload_mesh(mesh)
+    s = P.fe_assemble(ctx, dm, rho, targets[0])
+    h = P.amg_setup(ctx, s, coarse_max=32)
+    F = s.load_multi(targets)
+    U, infos, rc = P.pcg_solve_multi(ctx, s, h, F, rtol=1e-13, maxit=500)
+    assert rc == 0, [i.as_dict() for i in infos]
+    Uh = U.cpu().numpy()
+    its = []
+    for j, t in enumerate(targets):
+        x, o, _, _ = O.solve(mesh, rho, t, rtol=1e-14)
+        uo = O.to_vertices(o, x, mesh.n_vertices)
+        err = _rel(Uh[:, j], uo)
+        assert err < 1e-10, (j, err)
+        assert infos[j].status == 0 and infos[j].true_rel_res < 1e-12, infos[j].as_dict()
+        its.append(infos[j].iterations)
+    # the recurrences are the single-vector ones: iteration counts agree
+    for j in (0, k - 1):
+        _, info1, rc1 = P.pcg_solve(ctx, s, h, f=F[:, j].contiguous(), rtol=1e-13, maxit=500)
+        assert rc1 == 0 and abs(info1.iterations - its[j]) <= 1, (info1.iterations, its[j])
+    print(f"    levels={h.n_levels} iterations per column {min(its)}..{max(its)}")
+
+
+def test_multi_mixed_k32_reaches_tolerance(P, ctx):
+    print("[multi mixed] cube20 k=32", flush=True)
+    N, k = 20, 32
+    rho = 1.0 / N ** 2
+    mesh = I.kuhn_mesh(N)
+    targets = _targets(k, base=2000, n_modes=64)
+    dm = P.upload_mesh(mesh)
+    s = P.fe_assemble(ctx, dm, rho, targets[0])
+    h = P.amg_setup(ctx, s, precision=P.capi.PREC_MIXED, coarse_max=64)
+    F = s.load_multi(targets)
+    U, infos, rc = P.pcg_solve_multi(ctx, s, h, F, rtol=1e-8, maxit=500)
+    assert rc == 0
+    Uh = U.cpu().numpy()
+    errs = []
+    for j in range(0, k, 5):
+        assert infos[j].true_rel_res <= 1.0001e-8, infos[j].as_dict()
+        x, o, _, _ = O.solve(mesh, rho, targets[j], rtol=1e-14)
+        errs.append(_rel(Uh[:, j], O.to_vertices(o, x, mesh.n_vertices)))
+    assert all(i.true_rel_res <= 1.0001e-8 for i in infos)
+    print(f"    its {min(i.iterations for i in infos)}..{max(i.iterations for i in infos)} "
+          f"max err vs fp64 oracle {max(errs):.2e}")
+    assert max(errs) < 1e-6
+
+
+def test_frozen_and_zero_columns(P, ctx):
+    import torch
+    print("[multi frozen] cube12 k=4 with a zero column", flush=True)
+    N = 12
+    mesh = I.kuhn_mesh(N, jitter=0.15, seed=29)
+    dm = P.upload_mesh(mesh)
+    s = P.fe_assemble(ctx, dm, 1e-3, I.single_sine())
+    h = P.amg_setup(ctx, s, coarse_max=32)
+    F1 = s.load_multi([I.random_sine_modes(7), I.single_sine(), I.box_indicator(), I.random_sine_modes(8)])
+    F1[:, 1] = 0.0
+    F1[:, 3] *= 1e-3
+    U, infos, rc = P.pcg_solve_multi(ctx, s, h, F1.contiguous(), rtol=1e-12, maxit=500)
+    assert rc == 0
+    assert infos[1].iterations == 0 and float(U[:, 1].abs().max()) == 0.0
+    for j in (0, 2, 3):
+        u1, info1, rc1 = P.pcg_solve(ctx, s, h, f=F1[:, j].contiguous(), rtol=1e-12, maxit=500)
+        assert rc1 == 0
+        d = _rel(U[:, j].cpu().numpy(), u1.cpu().numpy())
+        assert d < 1e-9, (j, d)
+    # the same columns alone give the same result (frozen columns do not
+    # disturb the others)
+    U2, infos2, _ = P.pcg_solve_multi(ctx, s, h, F1[:, [0, 2]].contiguous(), rtol=1e-12, maxit=500)
+    assert torch.equal(U2[:, 0], U[:, 0]) or _rel(U2[:, 0].cpu().numpy(), U[:, 0].cpu().numpy()) < 1e-12
+
+
+def test_multi_jacobi_and_default_rhs(P, ctx):
+    print("[multi jacobi] cube8 k=3; F=None k=2", flush=True)
+    mesh = I.kuhn_mesh(8, jitter=0.15, seed=31)
+    targets = _targets(3)
+    dm = P.upload_mesh(mesh)
+    s = P.fe_assemble(ctx, dm, 1e-2, targets[0])
+    F = s.load_multi(targets)
+    U, infos, rc = P.pcg_solve_multi(ctx, s, None, F, rtol=1e-13, maxit=5000)
+    assert rc == 0
+    for j, t in enumerate(targets):
+        x, o, _, _ = O.solve(mesh, 1e-2, t, rtol=1e-14)
+        assert _rel(U[:, j].cpu().numpy(), O.to_vertices(o, x, mesh.n_vertices)) < 1e-10
+    h = P.amg_setup(ctx, s, coarse_max=32)
+    U0, infos0, rc0 = P.pcg_solve_multi(ctx, s, h, None, k=2, rtol=1e-13)
+    u1, _, _ = P.pcg_solve(ctx, s, h, rtol=1e-13)
+    for j in range(2):
+        assert _rel(U0[:, j].cpu().numpy(), u1.cpu().numpy()) < 1e-10
+
+
+def test_multi_error_paths(P, ctx):
+    import torch
+    print("[multi errors]", flush=True)
+    mesh = I.kuhn_mesh(4)
+    dm = P.upload_mesh(mesh)
+    s = P.fe_assemble(ctx, dm, 1.0, I.single_sine())
+    for k in (0, 65):
+        with pytest.raises(P.OcpError) as ei:
+            P.pcg_solve_multi(ctx, s, None, None, k=k)
+        assert ei.value.code == P.capi.ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        P.pcg_solve_multi(ctx, s, None, torch.zeros((s.n, 2), dtype=torch.float32, device="cuda"))
+    with pytest.raises(P.OcpError):
+        P.pcg_solve_multi(ctx, s, None, torch.zeros((s.n, 2), dtype=torch.float64, device="cuda"), rtol=0.0)

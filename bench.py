@@ -61,6 +61,76 @@ KERNEL_NAMES = {0: "cg_spmv_pq (FP64 CSR SpMV + p.q)", 1: "vc_pre_smooth_1 (leve
 MATRIX_KERNELS = (0, 1, 2, 5, 6)
 
 
+def block_bench(P, capi, reps: int = 3, N: int = 128, k: int = 32):
+    """Many targets on one mesh: 127^3 unknowns, rho = h^2, k sine-mode
+    targets (seeds 2000..2000+k-1) solved as one block PCG (FP32 hierarchy,
+    FP64 CG) against k sequential single-vector solves with an FP64
+    hierarchy, and k sequential mixed-precision solves, all to 1e-8.
+    Assembly and setup are outside the timed solves (one matrix and one
+    hierarchy serve all targets)."""
+    import torch
+    import ocp_inputs as I
+    mesh = I.kuhn_mesh(N)
+    targets = [I.random_sine_modes(2000 + j) for j in range(k)]
+    dm = P.upload_mesh(mesh)
+    del mesh
+    ctx = P.Context()
+    s = P.fe_assemble(ctx, dm, 1.0 / N ** 2, targets[0])
+    hm = P.amg_setup(ctx, s, precision=capi.PREC_MIXED)
+    hd = P.amg_setup(ctx, s, precision=capi.PREC_FP64)
+    F = s.load_multi(targets)
+    cols = [F[:, j].contiguous() for j in range(k)]
+    n, nnz = s.n, s.nnz
+    P.pcg_solve_multi(ctx, s, hm, F, rtol=1e-8)          # warm-up
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        U, infos, rc = P.pcg_solve_multi(ctx, s, hm, F, rtol=1e-8)
+        if rc != 0:
+            raise RuntimeError(f"block solve status {rc}")
+    torch.cuda.synchronize()
+    t_block = (time.perf_counter() - t0) / reps
+    launches, tot_ms = ctx.kernel_timing(capi.KERNEL_BLK_SPMM)
+    ctx.profile(False)
+
+    def seq(h):
+        P.pcg_solve(ctx, s, h, f=cols[0], rtol=1e-8)     # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        its = []
+        for j in range(k):
+            _, info, rc = P.pcg_solve(ctx, s, h, f=cols[j], rtol=1e-8)
+            if rc != 0:
+                raise RuntimeError(f"sequential solve status {rc}")
+            its.append(info.iterations)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, its
+
+    t_seq64, its64 = seq(hd)
+    t_seqm, itsm = seq(hm)
+    avg_ms = tot_ms / max(launches, 1)
+    alg = 12.0 * nnz + 4.0 * (n + 1) + 16.0 * k * n
+    out = {"workload": f"cube{N}_block{k}", "unknowns": n, "nnz": nnz, "k": k,
+           "block_mixed_ms": 1e3 * t_block, "block_dof_per_s": k * n / t_block,
+           "block_iterations": [int(i.iterations) for i in infos],
+           "max_true_rel_res": max(i.true_rel_res for i in infos),
+           "sequential_fp64_ms": 1e3 * t_seq64, "sequential_fp64_dof_per_s": k * n / t_seq64,
+           "sequential_fp64_iterations": its64,
+           "sequential_mixed_ms": 1e3 * t_seqm, "sequential_mixed_dof_per_s": k * n / t_seqm,
+           "speedup_vs_sequential_fp64": t_seq64 / t_block,
+           "spmm_roofline": {"bound": "hbm", "kernel": "blk_spmm_pq (FP64 CSR SpMM + per-column p.q)",
+                             "achieved": alg / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None,
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": alg / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if avg_ms > 0 else None,
+                             "alg_bytes": alg, "launches": launches, "avg_us": 1e3 * avg_ms}}
+    hm.close()
+    hd.close()
+    s.close()
+    ctx.close()
+    return out
+
+
 def cpu_baseline(target_seed: int, N_sample: int = 64):
     """The oracle (own assembly + Jacobi-PCG to 1e-8) on a smaller mesh of
     the same family: N_sample^3 cubes, rho = h^2, the same 64 modes."""
@@ -86,6 +156,7 @@ def main():
     ap.add_argument("--workload", default="cube256_modes64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-hierarchy comparison step")
+    ap.add_argument("--no-block", action="store_true", help="skip the 32-target block solve at 127^3")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this solver is measured per GPU "
@@ -175,6 +246,12 @@ def main():
                 "setup_ms": m64["setup_ms"], "true_rel_res": m64["true_rel_res"]}
         print(f"[bench] fp64 step: {json.dumps(m64)}", file=sys.stderr, flush=True)
 
+    block = None
+    if not args.no_block:
+        print("[bench] block solve (32 targets, 127^3) ...", file=sys.stderr, flush=True)
+        block = block_bench(P, capi)
+        print(f"[bench] block: {json.dumps(block)}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline and isinstance(tspec, tuple):
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
@@ -205,6 +282,7 @@ def main():
                      "solve": solve_ms},
         "solve_only_dof_per_s": n / (solve_ms * 1e-3),
         "fp64": fp64,
+        "block32": block,
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

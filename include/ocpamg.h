@@ -242,9 +242,15 @@ int pcg_solve(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, const
  *          every column solves with the system's f
  *   U      device [n_vertices][k] output, caller-owned; Dirichlet rows 0
  *   infos  host [k] per-column results (may be NULL)
+ *   flags  OCP_STOP_L2 or OCP_STOP_PRECOND, optionally | OCP_BLOCK_TILE(kb)
+ * The block kernels cut the k columns into panels of kb columns (8, 16, 32
+ * or 64); unless forced with OCP_BLOCK_TILE the width is chosen by timing
+ * the candidates on the first solve of each (system or hierarchy, k) and
+ * then kept, so repeated solves run the same kernels and give the same bits.
  * Blocks until every column has stopped.  Returns the worst column's status:
  * OCP_ERR_BREAKDOWN if any column broke down, else OCP_MAXIT if any column
  * reached the cap, else 0; or another error (then no column result). */
+#define OCP_BLOCK_TILE(kb) ((int32_t)(kb) << 8)
 int pcg_solve_multi(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, int32_t k,
                     const double *F, double *U, double rtol, int32_t maxit, int32_t flags,
                     ocp_solve_info *infos);

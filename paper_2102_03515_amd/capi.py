@@ -473,10 +473,11 @@ def pcg_solve(ctx: Context, system: System, hierarchy: Optional[Hierarchy] = Non
 
 
 def pcg_solve_multi(ctx: Context, system: System, hierarchy: Optional[Hierarchy], F, k: Optional[int] = None,
-                    U=None, rtol: float = 1e-8, maxit: int = 500, stop: int = STOP_L2):
+                    U=None, rtol: float = 1e-8, maxit: int = 500, stop: int = STOP_L2, tile: int = 0):
     """Block PCG over the k columns of F (device [n][k] row-major, or None for
-    k copies of the system's f).  Returns (U [n_vertices][k], [SolveInfo]*k,
-    status)."""
+    k copies of the system's f).  tile forces the column-panel width of the
+    block kernels (8/16/32/64; 0 = chosen by timing).  Returns
+    (U [n_vertices][k], [SolveInfo]*k, status)."""
     torch = _torch()
     if F is not None:
         if F.dim() != 2 or not F.is_contiguous() or F.dtype != torch.float64:
@@ -489,6 +490,7 @@ def pcg_solve_multi(ctx: Context, system: System, hierarchy: Optional[Hierarchy]
         U = torch.empty((nv, k), dtype=torch.float64, device="cuda")
     infos = (SolveInfo * k)()
     rc = lib().pcg_solve_multi(ctx.handle, system.handle, hierarchy.handle if hierarchy is not None else None,
-                               int(k), _ptr(F), _ptr(U), float(rtol), int(maxit), int(stop), infos)
+                               int(k), _ptr(F), _ptr(U), float(rtol), int(maxit), int(stop) | (int(tile) << 8),
+                               infos)
     ctx.check(rc, ok=(OK, MAXIT))
     return U, list(infos), rc

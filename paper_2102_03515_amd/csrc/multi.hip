@@ -46,17 +46,29 @@ struct CgBlock {
     int32_t k, stop_mode, maxit, pad;
 };
 
+// Tiling of a block launch: the k columns are cut into panels of KB columns
+// (lane j of a row group owns column panel*KB + j) and the rows into tiles
+// of RPP*iters consecutive rows.  Blocks run panel-major, so the gathered
+// working set of a panel is KB/k of a full row block: with k = 32 double
+// columns a full row is 256 bytes and one mesh plane of rows would no longer
+// fit an XCD's L2.  Partial sums are indexed by (column, tile).
+struct BlkT {
+    int iters;        // row passes per block
+    unsigned tiles;   // row tiles per panel
+};
 struct BlkLaunch {
-    unsigned blocks;
-    int iters;
+    BlkT t;
+    unsigned blocks;  // tiles * panels
 };
 
-inline BlkLaunch blk_launch(int64_t n, int KB) {
+inline BlkLaunch blk_launch(int64_t n, int KB, int k) {
     const int64_t rpp = kBlock / KB;
     int64_t iters = (n + rpp * kBlkMaxBlocks - 1) / (rpp * kBlkMaxBlocks);
     if (iters < 1) iters = 1;
     int64_t b = (n + rpp * iters - 1) / (rpp * iters);
-    return {(unsigned)(b < 1 ? 1 : b), (int)iters};
+    if (b < 1) b = 1;
+    const int panels = (k + KB - 1) / KB;
+    return {{(int)iters, (unsigned)b}, (unsigned)b * (unsigned)panels};
 }
 
 static int lanes_for_cols(int k) {
@@ -75,12 +87,19 @@ static int lanes_for_cols(int k) {
 
 // Row loop of a block kernel: lane j of row group grp; `on` is false for
 // padding lanes and frozen columns.
-#define OCP_BLK_BEGIN(KB)                                                 \
+#define OCP_BLK_TILE(KB)                                                  \
     constexpr int RPP = kBlock / KB;                                      \
-    const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);          \
-    const int j = threadIdx.x % KB, grp = threadIdx.x / KB;              \
+    const unsigned gtile = dev::xcd_tile(blockIdx.x, gridDim.x);         \
+    const int panel = (int)(gtile / bt.tiles);                            \
+    const unsigned tile = gtile % bt.tiles;                               \
+    const int iters = bt.iters;                                           \
+    const int lane = (int)(threadIdx.x % KB);                             \
+    const int j = panel * KB + lane;                                      \
+    const int grp = threadIdx.x / KB;                                     \
     const bool on = j < k && (cgb == nullptr || cgb->cflag[j] == 0);     \
-    const int base = (int)tile * RPP * iters;                            \
+    const int base = (int)tile * RPP * iters;
+#define OCP_BLK_BEGIN(KB)                                                 \
+    OCP_BLK_TILE(KB)                                                      \
     for (int it = 0; it < iters; ++it) {                                 \
         const int row = base + it * RPP + grp;                           \
         if (on && row < n) {                                             \
@@ -89,19 +108,139 @@ static int lanes_for_cols(int k) {
     }                 \
     }
 
+// Lane roles of a block matrix kernel that streams its rows with blk_rows.
+#define OCP_BLKGRP(KB) OCP_BLK_TILE(KB)
+
 namespace dev {
+constexpr int kBlkChunk = 16;
+
+// sum_q val_q * sf(col_q) * xf(col_q) over the entries [rb, re) of one row,
+// for the column of the calling lane in a KB-lane group.  The group loads up to KB entries at a time
+// (lane q takes entry q, non-temporal: the matrix is streamed once) and
+// broadcasts them with shuffles; each lane then issues up to kBlkChunk
+// independent gathers of its own column before it consumes any, so a row of
+// the fine level costs two memory round trips instead of one per entry.
+// sf scales an entry's value by a per-column factor (loaded once per entry
+// by its owner lane); xf(c) is lane j's gathered value of column c.
+template <int KB, typename T, typename XF, typename SF>
+__device__ __forceinline__ T blk_row(int rb, int re, int lane, bool on, const int32_t *__restrict__ col,
+                                     const T *__restrict__ val, XF xf, SF sf) {
+    constexpr int CH = KB < kBlkChunk ? KB : kBlkChunk;
+    T s = T(0);
+    for (int b0 = rb; b0 < re; b0 += KB) {
+        const int cnt = re - b0 < KB ? re - b0 : KB;
+        int mc = 0;
+        T mv = T(0);
+        if (lane < cnt) {
+            mc = ldnt(col + b0 + lane);
+            mv = ldnt(val + b0 + lane) * sf(mc);
+        }
+        for (int q0 = 0; q0 < cnt; q0 += CH) {
+            T a[CH], g[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int q = q0 + u;   // < KB: CH divides KB and q0 < cnt <= KB
+                const int c = __shfl(mc, q, KB);
+                a[u] = __shfl(mv, q, KB);
+                g[u] = (on && q < cnt) ? xf(c) : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) s += a[u] * g[u];
+        }
+    }
+    return s;
+}
+
+// Streams the rows of one KB-lane group (rows base + grp + it*RPP, it <
+// iters) as a software pipeline: while the gathers of the current row are in
+// flight, the first KB entries of the next row, the row range of the one
+// after, and the current row's epilogue operands (ld) are already loaded, so
+// a row costs about one memory round trip instead of four.  fin(row, s, pre)
+// consumes the row product s = sum_q val_q xf(col_q); rows longer than KB
+// finish with blk_row.  Uniform per group: every lane of the group runs the
+// same rows (lanes with `on` false load entries but skip gathers).
+template <int KB, typename T, typename XF, typename LD, typename FIN>
+__device__ __forceinline__ void blk_rows(int n, int iters, int base, int grp, int lane, bool on,
+                                         const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                         const T *__restrict__ val, XF xf, LD ld, FIN fin) {
+    constexpr int RPP = kBlock / KB;
+    constexpr int CH = KB < kBlkChunk ? KB : kBlkChunk;
+    int row = base + grp;
+    if (iters <= 0 || row >= n) return;
+    int rb = rp[row], re = rp[row + 1];
+    int mc = 0;
+    T mv = T(0);
+    if (lane < re - rb) {
+        mc = ldnt(col + rb + lane);
+        mv = ldnt(val + rb + lane);
+    }
+    int nrow = row + RPP;
+    bool hn = iters > 1 && nrow < n;
+    int nb = 0, ne = 0;
+    if (hn) {
+        nb = rp[nrow];
+        ne = rp[nrow + 1];
+    }
+    for (int it = 0;;) {
+        // prefetch: entries of the next row, range of the row after it
+        int mc2 = 0;
+        T mv2 = T(0);
+        if (hn && lane < ne - nb) {
+            mc2 = ldnt(col + nb + lane);
+            mv2 = ldnt(val + nb + lane);
+        }
+        const int nnrow = nrow + RPP;
+        const bool hnn = hn && it + 2 < iters && nnrow < n;
+        int nnb = 0, nne = 0;
+        if (hnn) {
+            nnb = rp[nnrow];
+            nne = rp[nnrow + 1];
+        }
+        const auto pre = ld(row);
+        const int cnt = re - rb < KB ? re - rb : KB;
+        T s = T(0);
+        for (int q0 = 0; q0 < cnt; q0 += CH) {
+            T a[CH], g[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int q = q0 + u;   // < KB: CH divides KB and q0 < cnt <= KB
+                const int c = __shfl(mc, q, KB);
+                a[u] = __shfl(mv, q, KB);
+                g[u] = (on && q < cnt) ? xf(c) : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) s += a[u] * g[u];
+        }
+        if (re - rb > KB) s += blk_row<KB>(rb + KB, re, lane, on, col, val, xf, [](int) { return T(1); });
+        fin(row, s, pre);
+        if (!hn) break;
+        ++it;
+        row = nrow;
+        rb = nb;
+        re = ne;
+        mc = mc2;
+        mv = mv2;
+        nrow = nnrow;
+        hn = hnn;
+        nb = nnb;
+        ne = nne;
+    }
+}
+
 // Per-column block sums in a fixed order: partials[j * nbs + block].
 template <int KB>
-__device__ __forceinline__ void blk_store_partial(double acc, double *partials, int nbs, int k) {
+__device__ __forceinline__ void blk_store_partial(double acc, double *partials, int nbs, int k, int panel,
+                                                  unsigned tile) {
     constexpr int RPP = kBlock / KB;
     __shared__ double red[kBlock];
     red[threadIdx.x] = acc;
     __syncthreads();
-    if (threadIdx.x < (unsigned)k) {
+    const int c = panel * KB + (int)threadIdx.x;
+    if (threadIdx.x < (unsigned)KB && c < k) {
         double s = 0.0;
 #pragma unroll
         for (int g = 0; g < RPP; ++g) s += red[g * KB + threadIdx.x];
-        partials[(size_t)threadIdx.x * nbs + blockIdx.x] = s;
+        partials[(size_t)c * nbs + tile] = s;
     }
 }
 
@@ -142,25 +281,42 @@ struct BlkOps {
     OT *out1;
     T *out2;
     int k;
+    // gathered value of column c for lane j: the first smoothing step
+    // a d_c b_c rebuilt on the fly (GDB) or the stored block
     __device__ __forceinline__ T gather(int c, int j) const {
         const size_t ec = (size_t)c * k + j;
         if (GDB) return a * d[c] * (T)b[ec];
         return g[ec];
     }
-    __device__ __forceinline__ double finish(int i, size_t e, T s) const {
-        const BT bi = b[e];
+    // epilogue operands of row i, loaded before the row's gathers
+    struct Pre {
+        BT bi;
+        T di, xpi, ui;
+    };
+    __device__ __forceinline__ Pre load(int i, size_t e) const {
+        Pre p{};
+        p.bi = b[e];
+        if (MODE != kBR) p.di = d[i];
+        if (MODE == kBZ) {
+            p.xpi = xp[e];
+            if (u) p.ui = u[e];
+        }
+        return p;
+    }
+    __device__ __forceinline__ double finish(int i, size_t e, T s, const Pre &p) const {
+        const BT bi = p.bi;
         const T r = (T)bi - s;
         if (MODE == kBR) {
             out1[e] = (OT)r;
         } else if (MODE == kBX2) {
-            out1[e] = (OT)(d[i] * (c1 * (T)bi + c2 * r));
+            out1[e] = (OT)(p.di * (c1 * (T)bi + c2 * r));
         } else if (MODE == kBPostA) {
             out1[e] = (OT)r;
-            out2[e] = xp[e] + a * d[i] * r;
+            out2[e] = xp[e] + a * p.di * r;
         } else {
             T w = c2 * r;
-            if (u) w += c1 * u[e];
-            const T z = xp[e] + d[i] * w;
+            if (u) w += c1 * p.ui;
+            const T z = p.xpi + p.di * w;
             out1[e] = (OT)z;
             return (double)bi * (double)z;
         }
@@ -169,58 +325,64 @@ struct BlkOps {
 };
 
 template <int KB, typename T, typename BT, typename OT, bool GDB, int MODE, bool DOT>
-__global__ void __launch_bounds__(kBlock) k_blk_smooth(int32_t n, int k, int iters, const int32_t *__restrict__ rp,
+__global__ void __launch_bounds__(kBlock) k_blk_smooth(int32_t n, int k, BlkT bt, const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ col, const T *__restrict__ val,
                                                        BlkOps<T, BT, OT, GDB, MODE> ops, const CgBlock *cgb,
                                                        double *partials, int nbs) {
     if (cgb && cgb->flag) return;
     double acc = 0.0;
-    OCP_BLK_BEGIN(KB)
-    const int pe = rp[row + 1];
-    T s = T(0);
-#pragma unroll 4
-    for (int p = rp[row]; p < pe; ++p) s += val[p] * ops.gather(col[p], j);
-    const double c = ops.finish(row, e, s);
-    if (DOT) acc += c;
-    OCP_BLK_END()
-    if (DOT) dev::blk_store_partial<KB>(acc, partials, nbs, k);
+    using Pre = typename BlkOps<T, BT, OT, GDB, MODE>::Pre;
+    OCP_BLKGRP(KB)
+    dev::blk_rows<KB>(
+        n, iters, base, grp, lane, on, rp, col, val, [&](int c) { return ops.gather(c, j); },
+        [&](int row) { return on ? ops.load(row, (size_t)row * k + j) : Pre{}; },
+        [&](int row, T s, const Pre &pre) {
+            if (on) {
+                const double c = ops.finish(row, (size_t)row * k + j, s, pre);
+                if (DOT) acc += c;
+            }
+        });
+    if (DOT) dev::blk_store_partial<KB>(acc, partials, nbs, k, panel, tile);
 }
 
 // y = M x for every column (restriction with R = P^T)
 template <int KB, typename T>
-__global__ void __launch_bounds__(kBlock) k_blk_spmv(int32_t n, int k, int iters, const int32_t *__restrict__ rp,
+__global__ void __launch_bounds__(kBlock) k_blk_spmv(int32_t n, int k, BlkT bt, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ col, const T *__restrict__ val,
                                                      const T *__restrict__ x, T *__restrict__ y, const CgBlock *cgb) {
     if (cgb && cgb->flag) return;
-    OCP_BLK_BEGIN(KB)
-    const int pe = rp[row + 1];
-    T s = T(0);
-#pragma unroll 4
-    for (int p = rp[row]; p < pe; ++p) s += val[p] * x[(size_t)col[p] * k + j];
-    y[e] = s;
-    OCP_BLK_END()
+    OCP_BLKGRP(KB)
+    dev::blk_rows<KB>(
+        n, iters, base, grp, lane, on, rp, col, val, [&](int c) { return x[(size_t)c * k + j]; },
+        [](int) { return 0; },
+        [&](int row, T s, int) {
+            if (on) y[(size_t)row * k + j] = s;
+        });
 }
 
 // xp = base + P xc, base = the stored pre-smoothed block (HX) or a d .* b
 template <int KB, typename T, typename BT, bool HX>
-__global__ void __launch_bounds__(kBlock) k_blk_prolong(int32_t n, int k, int iters, const int32_t *__restrict__ rp,
+__global__ void __launch_bounds__(kBlock) k_blk_prolong(int32_t n, int k, BlkT bt, const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ col, const T *__restrict__ val,
                                                         const T *__restrict__ d, const BT *__restrict__ b,
                                                         const T *__restrict__ xs, T a, const T *__restrict__ xc,
                                                         T *__restrict__ xp, const CgBlock *cgb) {
     if (cgb && cgb->flag) return;
-    OCP_BLK_BEGIN(KB)
-    const int pe = rp[row + 1];
-    T s = T(0);
-#pragma unroll 4
-    for (int p = rp[row]; p < pe; ++p) s += val[p] * xc[(size_t)col[p] * k + j];
-    xp[e] = (HX ? xs[e] : a * d[row] * (T)b[e]) + s;
-    OCP_BLK_END()
+    OCP_BLKGRP(KB)
+    dev::blk_rows<KB>(
+        n, iters, base, grp, lane, on, rp, col, val, [&](int c) { return xc[(size_t)c * k + j]; },
+        [&](int row) {
+            const size_t e = (size_t)row * k + j;
+            return on ? (HX ? xs[e] : a * d[row] * (T)b[e]) : T(0);
+        },
+        [&](int row, T s, T base_v) {
+            if (on) xp[(size_t)row * k + j] = base_v + s;
+        });
 }
 
 // x = Ainv b on the last level (dense inverse, row-major n x n)
 template <int KB, typename T, typename BT, typename ZT>
-__global__ void __launch_bounds__(kBlock) k_blk_dense(int32_t n, int k, int iters, const T *__restrict__ inv,
+__global__ void __launch_bounds__(kBlock) k_blk_dense(int32_t n, int k, BlkT bt, const T *__restrict__ inv,
                                                       const BT *__restrict__ b, ZT *__restrict__ x,
                                                       const CgBlock *cgb) {
     if (cgb && cgb->flag) return;
@@ -234,7 +396,7 @@ __global__ void __launch_bounds__(kBlock) k_blk_dense(int32_t n, int k, int iter
 
 // x = d .* b (last level without a dense inverse)
 template <int KB, typename T, typename BT, typename ZT>
-__global__ void __launch_bounds__(kBlock) k_blk_diag(int32_t n, int k, int iters, const T *__restrict__ d,
+__global__ void __launch_bounds__(kBlock) k_blk_diag(int32_t n, int k, BlkT bt, const T *__restrict__ d,
                                                      const BT *__restrict__ b, ZT *__restrict__ x,
                                                      const CgBlock *cgb) {
     if (cgb && cgb->flag) return;
@@ -245,7 +407,7 @@ __global__ void __launch_bounds__(kBlock) k_blk_diag(int32_t n, int k, int iters
 
 // r.z per column (single-level hierarchy)
 template <int KB>
-__global__ void __launch_bounds__(kBlock) k_blk_rz(int32_t n, int k, int iters, const double *__restrict__ r,
+__global__ void __launch_bounds__(kBlock) k_blk_rz(int32_t n, int k, BlkT bt, const double *__restrict__ r,
                                                    const double *__restrict__ z, const CgBlock *cgb, double *partials,
                                                    int nbs) {
     if (cgb && cgb->flag) return;
@@ -253,17 +415,30 @@ __global__ void __launch_bounds__(kBlock) k_blk_rz(int32_t n, int k, int iters, 
     OCP_BLK_BEGIN(KB)
     acc += r[e] * z[e];
     OCP_BLK_END()
-    dev::blk_store_partial<KB>(acc, partials, nbs, k);
+    dev::blk_store_partial<KB>(acc, partials, nbs, k, panel, tile);
 }
 
 // ------------------------------------------------------------- CG kernels
+// The V-cycle's first smoothing step from zero, y = a D^-1 r, in the
+// hierarchy's precision: written by the kernels that produce r, so the first
+// pass of the cycle gathers this block instead of rebuilding it from r and
+// d for every matrix entry.  y == nullptr: not wanted.
+template <typename YT>
+struct FirstStep {
+    YT *y;
+    const YT *d;
+    YT a;
+    __device__ __forceinline__ void put(size_t e, int row, double r) const {
+        if (y) y[e] = a * d[row] * (YT)r;
+    }
+};
 // X = 0, R = F, P = 0 and f.f per column; F column j of row i sits at
 // F[i * fs_row + j * fs_col] (fs_col = 0: the same vector for every column).
-template <int KB>
-__global__ void __launch_bounds__(kBlock) k_blk_init(int32_t n, int k, int iters, const double *__restrict__ F,
+template <int KB, typename YT>
+__global__ void __launch_bounds__(kBlock) k_blk_init(int32_t n, int k, BlkT bt, const double *__restrict__ F,
                                                      int64_t fs_row, int fs_col, double *__restrict__ X,
                                                      double *__restrict__ R, double *__restrict__ P,
-                                                     double *partials, int nbs) {
+                                                     FirstStep<YT> first, double *partials, int nbs) {
     const CgBlock *cgb = nullptr;
     double acc = 0.0;
     OCP_BLK_BEGIN(KB)
@@ -271,58 +446,65 @@ __global__ void __launch_bounds__(kBlock) k_blk_init(int32_t n, int k, int iters
     X[e] = 0.0;
     R[e] = fi;
     P[e] = 0.0;
+    first.put(e, row, fi);
     acc += fi * fi;
     OCP_BLK_END()
-    dev::blk_store_partial<KB>(acc, partials, nbs, k);
+    dev::blk_store_partial<KB>(acc, partials, nbs, k, panel, tile);
 }
 
 // Q = A P (FP64 CSR) and p.q per column
 template <int KB>
-__global__ void __launch_bounds__(kBlock) k_blk_spmm_pq(int32_t n, int k, int iters, const int32_t *__restrict__ rp,
+__global__ void __launch_bounds__(kBlock) k_blk_spmm_pq(int32_t n, int k, BlkT bt, const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ col,
                                                         const double *__restrict__ val, const double *__restrict__ P,
                                                         double *__restrict__ Q, const CgBlock *cgb, double *partials,
                                                         int nbs) {
     if (cgb->flag) return;
     double acc = 0.0;
-    OCP_BLK_BEGIN(KB)
-    const int pe = rp[row + 1];
-    double s = 0.0;
-#pragma unroll 4
-    for (int p = rp[row]; p < pe; ++p) s += val[p] * P[(size_t)col[p] * k + j];
-    Q[e] = s;
-    acc += P[e] * s;
-    OCP_BLK_END()
-    dev::blk_store_partial<KB>(acc, partials, nbs, k);
+    OCP_BLKGRP(KB)
+    dev::blk_rows<KB>(
+        n, iters, base, grp, lane, on, rp, col, val, [&](int c) { return P[(size_t)c * k + j]; },
+        [&](int row) { return on ? P[(size_t)row * k + j] : 0.0; },
+        [&](int row, double s, double pi) {
+            if (on) {
+                Q[(size_t)row * k + j] = s;
+                acc += pi * s;
+            }
+        });
+    dev::blk_store_partial<KB>(acc, partials, nbs, k, panel, tile);
 }
 
 // F - A X per column, squared norm (true residual at exit; every column)
 template <int KB>
-__global__ void __launch_bounds__(kBlock) k_blk_resid2(int32_t n, int k, int iters, const int32_t *__restrict__ rp,
+__global__ void __launch_bounds__(kBlock) k_blk_resid2(int32_t n, int k, BlkT bt, const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ col,
                                                        const double *__restrict__ val, const double *__restrict__ X,
                                                        const double *__restrict__ F, int64_t fs_row, int fs_col,
                                                        double *partials, int nbs) {
     const CgBlock *cgb = nullptr;
     double acc = 0.0;
-    OCP_BLK_BEGIN(KB)
-    const int pe = rp[row + 1];
-    double s = 0.0;
-    for (int p = rp[row]; p < pe; ++p) s += val[p] * X[(size_t)col[p] * k + j];
-    (void)e;
-    const double r = F[(size_t)row * fs_row + (size_t)j * fs_col] - s;
-    acc += r * r;
-    OCP_BLK_END()
-    dev::blk_store_partial<KB>(acc, partials, nbs, k);
+    OCP_BLKGRP(KB)
+    dev::blk_rows<KB>(
+        n, iters, base, grp, lane, on, rp, col, val, [&](int c) { return X[(size_t)c * k + j]; },
+        [&](int row) { return on ? F[(size_t)row * fs_row + (size_t)j * fs_col] : 0.0; },
+        [&](int row, double s, double fi) {
+            (void)row;
+            if (on) {
+                const double r = fi - s;
+                acc += r * r;
+            }
+        });
+    dev::blk_store_partial<KB>(acc, partials, nbs, k, panel, tile);
 }
 
 // X += alpha P, R -= alpha Q, r.r per column; with JAC also Z = dinv R and r.z
-template <int KB, bool JAC>
-__global__ void __launch_bounds__(kBlock) k_blk_update(int32_t n, int k, int iters, double *__restrict__ X,
+template <int KB, bool JAC, typename YT>
+__global__ void __launch_bounds__(kBlock) k_blk_update(int32_t n, int k, BlkT bt, double *__restrict__ X,
                                                        double *__restrict__ R, const double *__restrict__ P,
                                                        const double *__restrict__ Q, const double *__restrict__ dinv,
-                                                       double *__restrict__ Z, const CgBlock *cgb, double *partials,
-                                                       double *partials2, int nbs) {
+                                                       double *__restrict__ Z, FirstStep<YT> first,
+                                                       const CgBlock *cgb, double *partials, double *partials2,
+                                                       int nbs) {
     if (cgb->flag) return;
     double rr = 0.0, rz = 0.0;
     OCP_BLK_BEGIN(KB)
@@ -330,6 +512,7 @@ __global__ void __launch_bounds__(kBlock) k_blk_update(int32_t n, int k, int ite
     X[e] += a * P[e];
     const double r = R[e] - a * Q[e];
     R[e] = r;
+    first.put(e, row, r);
     rr += r * r;
     if (JAC) {
         const double z = dinv[row] * r;
@@ -337,16 +520,16 @@ __global__ void __launch_bounds__(kBlock) k_blk_update(int32_t n, int k, int ite
         rz += r * z;
     }
     OCP_BLK_END()
-    dev::blk_store_partial<KB>(rr, partials, nbs, k);
+    dev::blk_store_partial<KB>(rr, partials, nbs, k, panel, tile);
     if (JAC) {
         __syncthreads();
-        dev::blk_store_partial<KB>(rz, partials2, nbs, k);
+        dev::blk_store_partial<KB>(rz, partials2, nbs, k, panel, tile);
     }
 }
 
 // Z = dinv R and r.z (Jacobi preconditioner at the start)
 template <int KB>
-__global__ void __launch_bounds__(kBlock) k_blk_jacobi(int32_t n, int k, int iters, const double *__restrict__ R,
+__global__ void __launch_bounds__(kBlock) k_blk_jacobi(int32_t n, int k, BlkT bt, const double *__restrict__ R,
                                                        const double *__restrict__ dinv, double *__restrict__ Z,
                                                        const CgBlock *cgb, double *partials, int nbs) {
     if (cgb->flag) return;
@@ -356,12 +539,12 @@ __global__ void __launch_bounds__(kBlock) k_blk_jacobi(int32_t n, int k, int ite
     Z[e] = z;
     rz += R[e] * z;
     OCP_BLK_END()
-    dev::blk_store_partial<KB>(rz, partials, nbs, k);
+    dev::blk_store_partial<KB>(rz, partials, nbs, k, panel, tile);
 }
 
 // P = Z + beta P
 template <int KB>
-__global__ void __launch_bounds__(kBlock) k_blk_pupdate(int32_t n, int k, int iters, double *__restrict__ P,
+__global__ void __launch_bounds__(kBlock) k_blk_pupdate(int32_t n, int k, BlkT bt, double *__restrict__ P,
                                                         const double *__restrict__ Z, const CgBlock *cgb) {
     if (cgb->flag) return;
     OCP_BLK_BEGIN(KB)
@@ -514,7 +697,8 @@ BlkArrays<float> blk_arrays<float>(const Level &L) {
 }
 
 struct BlkCtx {
-    int k, KB;
+    int k;
+    const void *y0;  // level-0 first smoothing step of R ([n][k], hierarchy precision) or null
     double *part;   // [k][nbs] partials of the final r.z
     int nbs;
     CgBlock *cgb;
@@ -536,16 +720,16 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
     if (L == 1) {
         const Level &l0 = *lv[0];
         const auto a = blk_arrays<T>(l0);
-        const BlkLaunch LB = blk_launch(l0.n, KB);
+        const BlkLaunch LB = blk_launch(l0.n, KB, k);
         if (a.inv)
-            k_blk_dense<KB, T, double, double><<<LB.blocks, kBlock, 0, s>>>(l0.n, k, LB.iters, a.inv, R, Z, cgb);
+            k_blk_dense<KB, T, double, double><<<LB.blocks, kBlock, 0, s>>>(l0.n, k, LB.t, a.inv, R, Z, cgb);
         else
-            k_blk_diag<KB, T, double, double><<<LB.blocks, kBlock, 0, s>>>(l0.n, k, LB.iters, a.d, R, Z, cgb);
+            k_blk_diag<KB, T, double, double><<<LB.blocks, kBlock, 0, s>>>(l0.n, k, LB.t, a.d, R, Z, cgb);
         OCP_LAUNCH_CHECK();
         if (!cgb) return 0;
-        k_blk_rz<KB><<<LB.blocks, kBlock, 0, s>>>(l0.n, k, LB.iters, R, Z, cgb, bc.part, bc.nbs);
+        k_blk_rz<KB><<<LB.blocks, kBlock, 0, s>>>(l0.n, k, LB.t, R, Z, cgb, bc.part, bc.nbs);
         OCP_LAUNCH_CHECK();
-        return LB.blocks;
+        return LB.t.tiles;
     }
 
     // ---- down
@@ -553,24 +737,41 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
         const Level &cur = *lv[l];
         const Level &nxt = *lv[l + 1];
         const auto a = blk_arrays<T>(cur);
-        const BlkLaunch LB = blk_launch(cur.n, KB);
+        const BlkLaunch LB = blk_launch(cur.n, KB, k);
         T *rres = lvec(l, &BlkLevelWork::vr);
         T *x2 = lvec(l, &BlkLevelWork::vx2);
         const T ca = (T)cur.cheb_a, c1 = (T)cur.cheb_c1, c2 = (T)cur.cheb_c2;
         auto run_down = [&](auto bptr) {
             using BT = std::remove_const_t<std::remove_pointer_t<decltype(bptr)>>;
-            if (cur.deg == 2) {
+            const T *y0 = l == 0 ? static_cast<const T *>(bc.y0) : nullptr;
+            if (y0) {   // the first step is stored: plain passes gathering it
+                if (cur.deg == 2) {
+                    k_blk_smooth<KB, T, BT, T, false, kBX2, false><<<LB.blocks, kBlock, 0, s>>>(
+                        cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
+                        BlkOps<T, BT, T, false, kBX2>{a.d, bptr, y0, nullptr, nullptr, ca, c1, c2, x2, nullptr, k},
+                        cgb, nullptr, 0);
+                    k_blk_smooth<KB, T, BT, T, false, kBR, false><<<LB.blocks, kBlock, 0, s>>>(
+                        cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
+                        BlkOps<T, BT, T, false, kBR>{a.d, bptr, x2, nullptr, nullptr, ca, c1, c2, rres, nullptr, k},
+                        cgb, nullptr, 0);
+                } else {
+                    k_blk_smooth<KB, T, BT, T, false, kBR, false><<<LB.blocks, kBlock, 0, s>>>(
+                        cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
+                        BlkOps<T, BT, T, false, kBR>{a.d, bptr, y0, nullptr, nullptr, ca, c1, c2, rres, nullptr, k},
+                        cgb, nullptr, 0);
+                }
+            } else if (cur.deg == 2) {
                 k_blk_smooth<KB, T, BT, T, true, kBX2, false><<<LB.blocks, kBlock, 0, s>>>(
-                    cur.n, k, LB.iters, cur.A_rp, cur.A_col, a.A,
+                    cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
                     BlkOps<T, BT, T, true, kBX2>{a.d, bptr, nullptr, nullptr, nullptr, ca, c1, c2, x2, nullptr, k},
                     cgb, nullptr, 0);
                 k_blk_smooth<KB, T, BT, T, false, kBR, false><<<LB.blocks, kBlock, 0, s>>>(
-                    cur.n, k, LB.iters, cur.A_rp, cur.A_col, a.A,
+                    cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
                     BlkOps<T, BT, T, false, kBR>{a.d, bptr, x2, nullptr, nullptr, ca, c1, c2, rres, nullptr, k}, cgb,
                     nullptr, 0);
             } else {
                 k_blk_smooth<KB, T, BT, T, true, kBR, false><<<LB.blocks, kBlock, 0, s>>>(
-                    cur.n, k, LB.iters, cur.A_rp, cur.A_col, a.A,
+                    cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
                     BlkOps<T, BT, T, true, kBR>{a.d, bptr, nullptr, nullptr, nullptr, ca, c1, c2, rres, nullptr, k},
                     cgb, nullptr, 0);
             }
@@ -580,8 +781,8 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
             run_down(R);
         else
             run_down(static_cast<const T *>(lvec(l, &BlkLevelWork::vb)));
-        const BlkLaunch LR = blk_launch(nxt.n, KB);
-        k_blk_spmv<KB, T><<<LR.blocks, kBlock, 0, s>>>(nxt.n, k, LR.iters, cur.R_rp.get(), cur.R_col.get(), a.R, rres,
+        const BlkLaunch LR = blk_launch(nxt.n, KB, k);
+        k_blk_spmv<KB, T><<<LR.blocks, kBlock, 0, s>>>(nxt.n, k, LR.t, cur.R_rp.get(), cur.R_col.get(), a.R, rres,
                                                        lvec(l + 1, &BlkLevelWork::vb), cgb);
         OCP_LAUNCH_CHECK();
     }
@@ -589,13 +790,13 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
     {
         const Level &cl = *lv[L - 1];
         const auto a = blk_arrays<T>(cl);
-        const BlkLaunch LB = blk_launch(cl.n, KB);
+        const BlkLaunch LB = blk_launch(cl.n, KB, k);
         const T *b = lvec(L - 1, &BlkLevelWork::vb);
         T *x = lvec(L - 1, &BlkLevelWork::vx);
         if (a.inv)
-            k_blk_dense<KB, T, T, T><<<LB.blocks, kBlock, 0, s>>>(cl.n, k, LB.iters, a.inv, b, x, cgb);
+            k_blk_dense<KB, T, T, T><<<LB.blocks, kBlock, 0, s>>>(cl.n, k, LB.t, a.inv, b, x, cgb);
         else
-            k_blk_diag<KB, T, T, T><<<LB.blocks, kBlock, 0, s>>>(cl.n, k, LB.iters, a.d, b, x, cgb);
+            k_blk_diag<KB, T, T, T><<<LB.blocks, kBlock, 0, s>>>(cl.n, k, LB.t, a.d, b, x, cgb);
         OCP_LAUNCH_CHECK();
     }
     // ---- up
@@ -603,7 +804,7 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
     for (int l = L - 2; l >= 0; --l) {
         const Level &cur = *lv[l];
         const auto a = blk_arrays<T>(cur);
-        const BlkLaunch LB = blk_launch(cur.n, KB);
+        const BlkLaunch LB = blk_launch(cur.n, KB, k);
         const T *xc = lvec(l + 1, &BlkLevelWork::vx);
         T *xp = lvec(l, &BlkLevelWork::vxp);
         T *x2 = lvec(l, &BlkLevelWork::vx2);
@@ -616,31 +817,31 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
             using OT = std::remove_pointer_t<decltype(outptr)>;
             constexpr bool DOT = decltype(dot_tag)::value;
             if (cur.deg == 2)
-                k_blk_prolong<KB, T, BT, true><<<LB.blocks, kBlock, 0, s>>>(cur.n, k, LB.iters, cur.P_rp.get(),
+                k_blk_prolong<KB, T, BT, true><<<LB.blocks, kBlock, 0, s>>>(cur.n, k, LB.t, cur.P_rp.get(),
                                                                           cur.P_col.get(), a.P, a.d, bptr, x2, ca,
                                                                           xc, xp, cgb);
             else
-                k_blk_prolong<KB, T, BT, false><<<LB.blocks, kBlock, 0, s>>>(cur.n, k, LB.iters, cur.P_rp.get(),
+                k_blk_prolong<KB, T, BT, false><<<LB.blocks, kBlock, 0, s>>>(cur.n, k, LB.t, cur.P_rp.get(),
                                                                            cur.P_col.get(), a.P, a.d, bptr, nullptr,
                                                                            ca, xc, xp, cgb);
             OCP_LAUNCH_CHECK();
             if (cur.deg == 2) {
                 k_blk_smooth<KB, T, BT, T, false, kBPostA, false><<<LB.blocks, kBlock, 0, s>>>(
-                    cur.n, k, LB.iters, cur.A_rp, cur.A_col, a.A,
+                    cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
                     BlkOps<T, BT, T, false, kBPostA>{a.d, bptr, xp, xp, nullptr, ca, c1, c2, r0, x1, k}, cgb, nullptr,
                     0);
                 k_blk_smooth<KB, T, BT, OT, false, kBZ, DOT><<<LB.blocks, kBlock, 0, s>>>(
-                    cur.n, k, LB.iters, cur.A_rp, cur.A_col, a.A,
+                    cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
                     BlkOps<T, BT, OT, false, kBZ>{a.d, bptr, x1, xp, r0, ca, c1, c2, outptr, nullptr, k}, cgb,
                     DOT ? bc.part : nullptr, bc.nbs);
             } else {
                 k_blk_smooth<KB, T, BT, OT, false, kBZ, DOT><<<LB.blocks, kBlock, 0, s>>>(
-                    cur.n, k, LB.iters, cur.A_rp, cur.A_col, a.A,
+                    cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
                     BlkOps<T, BT, OT, false, kBZ>{a.d, bptr, xp, xp, nullptr, ca, zero, ca, outptr, nullptr, k}, cgb,
                     DOT ? bc.part : nullptr, bc.nbs);
             }
             OCP_LAUNCH_CHECK();
-            if (DOT) fin_nb = LB.blocks;
+            if (DOT) fin_nb = LB.t.tiles;
         };
         if (l == 0) {
             if (cgb)
@@ -655,9 +856,10 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
 }
 
 template <typename T>
-static unsigned vcycle_block(ocp_ctx *ctx, const ocp_hierarchy *h, const double *R, double *Z, const BlkCtx &bc) {
+static unsigned vcycle_block(ocp_ctx *ctx, const ocp_hierarchy *h, const double *R, double *Z, const BlkCtx &bc,
+                             int kb) {
     unsigned nb = 0;
-    OCP_DISPATCH_KB(bc.KB, (nb = vcycle_block_t<KB, T>(ctx, h, R, Z, bc)));
+    OCP_DISPATCH_KB(kb, (nb = vcycle_block_t<KB, T>(ctx, h, R, Z, bc)));
     return nb;
 }
 
@@ -689,17 +891,54 @@ static int worst_status(const std::vector<int> &st) {
     return w;
 }
 
+// Panel width of the block kernels: forced by the flags, else the fastest of
+// the candidates KB = 8, 16, 32, 64 (KB <= the single-panel width), timed
+// once per system (SpMM) or hierarchy (V-cycle) and k, then kept, so that
+// repeated solves take the same kernels and give the same bits.
+static int forced_kb(int32_t flags, int kb_max) {
+    const int f = (flags >> 8) & 0xff;
+    if (f == 0) return 0;
+    if (f != 8 && f != 16 && f != 32 && f != 64) fail(OCP_ERR_INVALID_ARG, "block tile must be 8, 16, 32 or 64");
+    return f < kb_max ? f : kb_max;
+}
+
+template <typename F>
+static int tune_kb(ocp_ctx *ctx, int kb_max, F launch) {
+    hipEvent_t e0, e1;
+    OCP_HIP(hipEventCreate(&e0));
+    OCP_HIP(hipEventCreate(&e1));
+    int best = kb_max;
+    float best_ms = 0.f;
+    for (int kb = 8; kb <= kb_max; kb <<= 1) {
+        launch(kb);   // first launch of the variant (code load, caches)
+        OCP_HIP(hipEventRecord(e0, ctx->stream));
+        launch(kb);
+        OCP_HIP(hipEventRecord(e1, ctx->stream));
+        OCP_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        OCP_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (kb == 8 || ms < best_ms) {
+            best_ms = ms;
+            best = kb;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
+}
+
 static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, int k, const double *F, double *U,
                         double rtol, int32_t maxit, int32_t flags, ocp_solve_info *infos, int *status) {
     const int32_t n = sys->n;
-    const int KB = lanes_for_cols(k);
+    const int KB0 = lanes_for_cols(k);   // one panel: elementwise CG kernels
     const int64_t fs_row = F ? k : 1;
     const int fs_col = F ? 1 : 0;
     const double *Fp = F ? F : sys->f.get();
     const size_t nk = (size_t)n * k;
+    const int forced = forced_kb(flags, KB0);
     DevBuf<double> X(ctx, nk), R(ctx, nk), P(ctx, nk), Q(ctx, nk), Z(ctx, nk);
-    const BlkLaunch LB = blk_launch(n, KB);
-    const int nbs = (int)LB.blocks;
+    const BlkLaunch LB = blk_launch(n, KB0, k);
+    const int nbs = kBlkMaxBlocks;
     DevBuf<double> part0(ctx, (size_t)k * nbs), part1(ctx, (size_t)k * nbs), part2(ctx, (size_t)k * nbs);
     DevBuf<CgBlock> cgbuf(ctx, 1);
     CgBlock *cgb = cgbuf.get();
@@ -708,81 +947,160 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
     std::vector<BlkLevelWork> work;
     if (h) alloc_block_work(ctx, h, k, work);
     const bool mixed = h && h->params.precision == OCP_PREC_MIXED;
-    BlkCtx bc{k, KB, part1.get(), nbs, cgb, &work};
+    // level-0 first smoothing step of R, written by the kernels producing R
+    DevBuf<char> y0buf;
+    const bool want_y0 = h && h->levels.size() > 1;
+    FirstStep<float> fs32{nullptr, nullptr, 0.f};
+    FirstStep<double> fs64{nullptr, nullptr, 0.0};
+    if (want_y0) {
+        const Level &l0 = *h->levels[0];
+        y0buf.reset(ctx, nk * (mixed ? sizeof(float) : sizeof(double)));
+        if (mixed)
+            fs32 = {reinterpret_cast<float *>(y0buf.get()), l0.dinv32.get(), (float)l0.cheb_a};
+        else
+            fs64 = {reinterpret_cast<double *>(y0buf.get()), l0.dinv.get(), l0.cheb_a};
+    }
+    BlkCtx bc{k, want_y0 ? y0buf.get() : nullptr, part1.get(), nbs, cgb, &work};
     hipStream_t s = ctx->stream;
+    const int32_t *rp = sys->row_ptr.get(), *ci = sys->col.get();
+    const double *av = sys->val.get();
+    int kb_vc = KB0;
+    if (h) {
+        int &cached = const_cast<ocp_hierarchy *>(h)->blk_kb_vc[k];
+        kb_vc = forced ? forced : (cached ? cached : KB0);
+    }
+    int kb_mm = forced ? forced : (sys->blk_kb_spmm[k] ? sys->blk_kb_spmm[k] : KB0);
 
     auto precond = [&](void) {
         if (h) {
-            const unsigned nb = mixed ? vcycle_block<float>(ctx, h, R.get(), Z.get(), bc)
-                                      : vcycle_block<double>(ctx, h, R.get(), Z.get(), bc);
+            const unsigned nb = mixed ? vcycle_block<float>(ctx, h, R.get(), Z.get(), bc, kb_vc)
+                                      : vcycle_block<double>(ctx, h, R.get(), Z.get(), bc, kb_vc);
             k_blk_fin_rz<<<1, kFinBlock, 0, s>>>(nb, part1.get(), nbs, cgb);
         } else {
-            OCP_DISPATCH_KB(KB, (k_blk_jacobi<KB><<<LB.blocks, kBlock, 0, s>>>(n, k, LB.iters, R.get(), dinv, Z.get(),
-                                                                            cgb, part1.get(), nbs)));
-            k_blk_fin_rz<<<1, kFinBlock, 0, s>>>(LB.blocks, part1.get(), nbs, cgb);
+            OCP_DISPATCH_KB(KB0, (k_blk_jacobi<KB><<<LB.blocks, kBlock, 0, s>>>(n, k, LB.t, R.get(), dinv, Z.get(),
+                                                                             cgb, part1.get(), nbs)));
+            k_blk_fin_rz<<<1, kFinBlock, 0, s>>>(LB.t.tiles, part1.get(), nbs, cgb);
         }
         OCP_LAUNCH_CHECK();
     };
     auto pupdate = [&](void) {
-        OCP_DISPATCH_KB(KB, (k_blk_pupdate<KB><<<LB.blocks, kBlock, 0, s>>>(n, k, LB.iters, P.get(), Z.get(), cgb)));
+        OCP_DISPATCH_KB(KB0, (k_blk_pupdate<KB><<<LB.blocks, kBlock, 0, s>>>(n, k, LB.t, P.get(), Z.get(), cgb)));
         OCP_LAUNCH_CHECK();
+    };
+    auto spmm = [&](int kb) {
+        const BlkLaunch LS = blk_launch(n, kb, k);
+        OCP_DISPATCH_KB(kb, (k_blk_spmm_pq<KB><<<LS.blocks, kBlock, 0, s>>>(n, k, LS.t, rp, ci, av, P.get(), Q.get(),
+                                                                         cgb, part0.get(), nbs)));
+        OCP_LAUNCH_CHECK();
+        return LS.t.tiles;
     };
 
     ctx->prof_iter = -1;
     OCP_HIP(hipEventRecord(ctx->ev0, s));
-    OCP_DISPATCH_KB(KB, (k_blk_init<KB><<<LB.blocks, kBlock, 0, s>>>(n, k, LB.iters, Fp, fs_row, fs_col, X.get(),
-                                                                      R.get(), P.get(), part0.get(), nbs)));
-    k_blk_fin_init<<<1, kFinBlock, 0, s>>>(LB.blocks, part0.get(), nbs, cgb, k, rtol, mode, maxit);
+    if (mixed) {
+        OCP_DISPATCH_KB(KB0, (k_blk_init<KB, float><<<LB.blocks, kBlock, 0, s>>>(
+                                 n, k, LB.t, Fp, fs_row, fs_col, X.get(), R.get(), P.get(), fs32, part0.get(), nbs)));
+    } else {
+        OCP_DISPATCH_KB(KB0, (k_blk_init<KB, double><<<LB.blocks, kBlock, 0, s>>>(
+                                 n, k, LB.t, Fp, fs_row, fs_col, X.get(), R.get(), P.get(), fs64, part0.get(), nbs)));
+    }
+    k_blk_fin_init<<<1, kFinBlock, 0, s>>>(LB.t.tiles, part0.get(), nbs, cgb, k, rtol, mode, maxit);
     OCP_LAUNCH_CHECK();
-    precond();
-    pupdate();
 
     struct {
         int32_t flag, iter;
     } hs{0, 0};
+    read_back(ctx, &hs, &cgb->flag, sizeof(hs));
+    // first solve of this shape: time the panel widths on the live data before
+    // the first V-cycle (the outputs of these launches are overwritten before
+    // they are read), so that every solve of the shape uses the same kernels
+    if (!forced && hs.flag == 0) {
+        if (!sys->blk_kb_spmm[k]) sys->blk_kb_spmm[k] = tune_kb(ctx, KB0, spmm);
+        kb_mm = sys->blk_kb_spmm[k];
+        if (h && !h->blk_kb_vc[k]) {
+            const Level &l0 = *h->levels[0];
+            int &cached = const_cast<ocp_hierarchy *>(h)->blk_kb_vc[k];
+            if (h->levels.size() > 1) {
+                cached = tune_kb(ctx, KB0, [&](int kb) {
+                    OCP_DISPATCH_KB(kb, ({
+                        const BlkLaunch LV = blk_launch(l0.n, KB, k);
+                        if (mixed) {
+                            float *x2 = reinterpret_cast<float *>(work[0].vx2.get());
+                            float *rr = reinterpret_cast<float *>(work[0].vr.get());
+                            k_blk_smooth<KB, float, double, float, false, kBR, false><<<LV.blocks, kBlock, 0, s>>>(
+                                l0.n, k, LV.t, l0.A_rp, l0.A_col, l0.A_val32.get(),
+                                BlkOps<float, double, float, false, kBR>{l0.dinv32.get(), R.get(), x2, nullptr,
+                                                                        nullptr, 0.f, 0.f, 0.f, rr, nullptr, k},
+                                cgb, nullptr, 0);
+                        } else {
+                            double *x2 = reinterpret_cast<double *>(work[0].vx2.get());
+                            double *rr = reinterpret_cast<double *>(work[0].vr.get());
+                            k_blk_smooth<KB, double, double, double, false, kBR, false><<<LV.blocks, kBlock, 0, s>>>(
+                                l0.n, k, LV.t, l0.A_rp, l0.A_col, l0.A_val,
+                                BlkOps<double, double, double, false, kBR>{l0.dinv.get(), R.get(), x2, nullptr,
+                                                                           nullptr, 0.0, 0.0, 0.0, rr, nullptr, k},
+                                cgb, nullptr, 0);
+                        }
+                    }));
+                    OCP_LAUNCH_CHECK();
+                });
+            } else {
+                cached = KB0;
+            }
+        }
+        if (h) kb_vc = h->blk_kb_vc[k];
+    }
+    precond();
+    pupdate();
+    read_back(ctx, &hs, &cgb->flag, sizeof(hs));
+
     int chunk = 2;
     ctx->prof_iter = 0;
     for (;;) {
-        read_back(ctx, &hs, &cgb->flag, sizeof(hs));
         if (hs.flag != 0) break;
         for (int c = 0; c < chunk; ++c) {
             const int pr = prof_begin(ctx, OCP_KERNEL_BLK_SPMM);
-            OCP_DISPATCH_KB(KB, (k_blk_spmm_pq<KB><<<LB.blocks, kBlock, 0, s>>>(
-                                    n, k, LB.iters, sys->row_ptr.get(), sys->col.get(), sys->val.get(), P.get(),
-                                    Q.get(), cgb, part0.get(), nbs)));
+            const unsigned nbm = spmm(kb_mm);
             prof_end(ctx, pr);
-            k_blk_fin_alpha<<<1, kFinBlock, 0, s>>>(LB.blocks, part0.get(), nbs, cgb);
+            k_blk_fin_alpha<<<1, kFinBlock, 0, s>>>(nbm, part0.get(), nbs, cgb);
             if (h) {
-                OCP_DISPATCH_KB(KB, (k_blk_update<KB, false><<<LB.blocks, kBlock, 0, s>>>(
-                                        n, k, LB.iters, X.get(), R.get(), P.get(), Q.get(), nullptr, nullptr, cgb,
-                                        part0.get(), nullptr, nbs)));
-                k_blk_fin_update<false><<<1, kFinBlock, 0, s>>>(LB.blocks, part0.get(), nullptr, nbs, cgb);
+                if (mixed) {
+                    OCP_DISPATCH_KB(KB0, (k_blk_update<KB, false, float><<<LB.blocks, kBlock, 0, s>>>(
+                                             n, k, LB.t, X.get(), R.get(), P.get(), Q.get(), nullptr, nullptr, fs32,
+                                             cgb, part0.get(), nullptr, nbs)));
+                } else {
+                    OCP_DISPATCH_KB(KB0, (k_blk_update<KB, false, double><<<LB.blocks, kBlock, 0, s>>>(
+                                             n, k, LB.t, X.get(), R.get(), P.get(), Q.get(), nullptr, nullptr, fs64,
+                                             cgb, part0.get(), nullptr, nbs)));
+                }
+                k_blk_fin_update<false><<<1, kFinBlock, 0, s>>>(LB.t.tiles, part0.get(), nullptr, nbs, cgb);
                 OCP_LAUNCH_CHECK();
                 precond();
             } else {
-                OCP_DISPATCH_KB(KB, (k_blk_update<KB, true><<<LB.blocks, kBlock, 0, s>>>(
-                                        n, k, LB.iters, X.get(), R.get(), P.get(), Q.get(), dinv, Z.get(), cgb,
-                                        part0.get(), part2.get(), nbs)));
-                k_blk_fin_update<true><<<1, kFinBlock, 0, s>>>(LB.blocks, part0.get(), part2.get(), nbs, cgb);
+                OCP_DISPATCH_KB(KB0, (k_blk_update<KB, true, float><<<LB.blocks, kBlock, 0, s>>>(
+                                         n, k, LB.t, X.get(), R.get(), P.get(), Q.get(), dinv, Z.get(), fs32, cgb,
+                                         part0.get(), part2.get(), nbs)));
+                k_blk_fin_update<true><<<1, kFinBlock, 0, s>>>(LB.t.tiles, part0.get(), part2.get(), nbs, cgb);
                 OCP_LAUNCH_CHECK();
             }
             pupdate();
             ++ctx->prof_iter;
         }
         if (chunk < 8) chunk *= 2;
+        read_back(ctx, &hs, &cgb->flag, sizeof(hs));
     }
     OCP_HIP(hipEventRecord(ctx->ev1, s));
 
     // true residuals in double, then U on all vertices
-    OCP_DISPATCH_KB(KB, (k_blk_resid2<KB><<<LB.blocks, kBlock, 0, s>>>(n, k, LB.iters, sys->row_ptr.get(),
-                                                                        sys->col.get(), sys->val.get(), X.get(), Fp,
-                                                                        fs_row, fs_col, part2.get(), nbs)));
+    const BlkLaunch LR = blk_launch(n, kb_mm, k);
+    OCP_DISPATCH_KB(kb_mm, (k_blk_resid2<KB><<<LR.blocks, kBlock, 0, s>>>(n, k, LR.t, rp, ci, av, X.get(), Fp,
+                                                                           fs_row, fs_col, part2.get(), nbs)));
     OCP_LAUNCH_CHECK();
     k_blk_scatter<<<grid_for((int64_t)sys->nv * k, 256), 256, 0, s>>>(sys->nv, k, sys->dof_of_vertex.get(), X.get(),
                                                                        U);
     OCP_LAUNCH_CHECK();
     // per-column residual partials and scalars to the host (summed there in
-    // block order)
+    // tile order)
     std::vector<double> res_part((size_t)k * nbs);
     OCP_HIP(hipMemcpyAsync(res_part.data(), part2.get(), sizeof(double) * k * nbs, hipMemcpyDeviceToHost, s));
     CgBlock hcg;
@@ -795,7 +1113,7 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
     std::vector<int> st((size_t)k);
     for (int j = 0; j < k; ++j) {
         double res2 = 0.0;
-        for (int b = 0; b < nbs; ++b) res2 += res_part[(size_t)j * nbs + b];
+        for (unsigned b = 0; b < LR.t.tiles; ++b) res2 += res_part[(size_t)j * nbs + b];
         const int cf = hcg.cflag[j];
         st[j] = cf == 2 ? OCP_ERR_BREAKDOWN : cf == 3 ? OCP_MAXIT : OCP_OK;
         if (infos) {

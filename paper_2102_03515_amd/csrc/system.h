@@ -35,6 +35,7 @@ struct ocp_system {
     // derived data, rebuilt on demand and dropped when the values change
     ocp::DevBuf<double> dinv;   // 1 / a_ii
     ocp::Sell sell;             // sliced-ELL copy of A for the solve phase
+    int blk_kb_spmm[65] = {};   // block SpMM panel width chosen per column count k (0: not yet)
     void invalidate_derived() {
         dinv.release();
         sell = ocp::Sell();
@@ -77,6 +78,7 @@ struct ocp_hierarchy {
     const ocp_system *sys = nullptr;
     ocp_amg_params params{};
     std::vector<std::unique_ptr<ocp::Level>> levels;
+    int blk_kb_vc[65] = {};     // block V-cycle panel width chosen per column count k (0: not yet)
 };
 
 namespace ocp {

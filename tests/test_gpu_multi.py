@@ -84,6 +84,34 @@ def test_multi_fp64_matches_oracle(P, ctx, k, N):
     print(f"    levels={h.n_levels} iterations per column {min(its)}..{max(its)}")
 
 
+def test_panel_widths_agree_and_repeat(P, ctx):
+    """Every column-panel width gives the oracle's solution; the width chosen
+    by timing is kept, so a repeated solve returns the same bits."""
+    import torch
+    print("[multi tiles] cube12 jitter k=32 tiles 8/16/32 + autotuned twice", flush=True)
+    N, k = 12, 32
+    rho = 1.0 / N ** 2
+    mesh = I.kuhn_mesh(N, jitter=0.15, seed=37)
+    targets = _targets(k, base=3000)
+    dm = P.upload_mesh(mesh)
+    s = P.fe_assemble(ctx, dm, rho, targets[0])
+    h = P.amg_setup(ctx, s, coarse_max=32)
+    F = s.load_multi(targets)
+    ref = []
+    for j in range(0, k, 3):
+        x, o, _, _ = O.solve(mesh, rho, targets[j], rtol=1e-14)
+        ref.append((j, O.to_vertices(o, x, mesh.n_vertices)))
+    for tile in (8, 16, 32):
+        U, infos, rc = P.pcg_solve_multi(ctx, s, h, F, rtol=1e-13, maxit=500, tile=tile)
+        assert rc == 0
+        Uh = U.cpu().numpy()
+        for j, uo in ref:
+            assert _rel(Uh[:, j], uo) < 1e-10, (tile, j)
+    U1, _, _ = P.pcg_solve_multi(ctx, s, h, F, rtol=1e-13, maxit=500)
+    U2, _, _ = P.pcg_solve_multi(ctx, s, h, F, rtol=1e-13, maxit=500)
+    assert torch.equal(U1, U2)
+
+
 def test_multi_mixed_k32_reaches_tolerance(P, ctx):
     print("[multi mixed] cube20 k=32", flush=True)
     N, k = 20, 32
@@ -166,3 +194,6 @@ def test_multi_error_paths(P, ctx):
         P.pcg_solve_multi(ctx, s, None, torch.zeros((s.n, 2), dtype=torch.float32, device="cuda"))
     with pytest.raises(P.OcpError):
         P.pcg_solve_multi(ctx, s, None, torch.zeros((s.n, 2), dtype=torch.float64, device="cuda"), rtol=0.0)
+    with pytest.raises(P.OcpError) as ei:
+        P.pcg_solve_multi(ctx, s, None, None, k=2, tile=12)
+    assert ei.value.code == P.capi.ERR_INVALID_ARG

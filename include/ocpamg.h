@@ -118,6 +118,13 @@ void ocp_system_destroy(ocp_system *sys);
 /* Replace rho: A = rho*K + M (needs OCP_KEEP_KM at assembly). */
 int fe_set_rho(ocp_ctx *ctx, ocp_system *sys, double rho);
 
+/* A new system on the same mesh with A = rho*K + M, from the K and M values
+ * that `base` stored (base assembled with OCP_KEEP_KM): the pattern, maps
+ * and f are copied, no element is recomputed.  The result has no K/M of its
+ * own and is freed by ocp_system_destroy; the mesh must stay alive as for
+ * base.  Errors: INVALID_ARG (NULL, rho <= 0, base without K/M), OOM, HIP. */
+int fe_derive(ocp_ctx *ctx, const ocp_system *base, double rho, ocp_system **out);
+
 /* Load vector of another target on the same mesh: f_dev (device [n_dofs],
  * caller-owned) receives f_i = int ubar phi_i.  The mesh given at assembly
  * must still be alive. */
@@ -254,6 +261,31 @@ int pcg_solve(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, const
 int pcg_solve_multi(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, int32_t k,
                     const double *F, double *U, double rtol, int32_t maxit, int32_t flags,
                     ocp_solve_info *infos);
+
+/* Step interface of pcg_solve for callers that interleave several solves
+ * (the serving loop): the same iteration, enqueued in pieces without
+ * blocking.  A context runs one such solve at a time, and while it is
+ * active every other call on that context is refused (INVALID_ARG); use one
+ * context (stream) per concurrent solve.  The hierarchy and system are only
+ * read, so several contexts may solve with the same ones at once.
+ *   pcg_begin    enqueues u = 0, r = f, the first V-cycle; *out owns the
+ *                work vectors.  Arguments as pcg_solve.
+ *   pcg_advance  enqueues `iters` more iterations (those after the stop
+ *                return at once on the device) and a copy of the scalars.
+ *   pcg_poll     does not block: 2 while the last advance is still on the
+ *                GPU (info untouched), 1 when it has finished and the stop
+ *                test has not fired (advance again), 0 once the solve has
+ *                stopped (info->status holds 0, OCP_MAXIT or BREAKDOWN), <0
+ *                on a runtime error.  true_rel_res and solve_ms are 0 here.
+ *   pcg_end      recomputes the true residual, writes u (device
+ *                [n_vertices]), fills info, frees the handle; returns the
+ *                status as pcg_solve (OCP_MAXIT if ended before the stop). */
+typedef struct ocp_solve_handle ocp_solve_handle;
+int pcg_begin(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, const double *f, double rtol,
+              int32_t maxit, int32_t flags, ocp_solve_handle **out);
+int pcg_advance(ocp_solve_handle *hd, int32_t iters);
+int pcg_poll(ocp_solve_handle *hd, ocp_solve_info *info);
+int pcg_end(ocp_solve_handle *hd, double *u, ocp_solve_info *info);
 
 /* ------------------------------------------------------- kernel timing */
 #define OCP_KERNEL_CG_SPMV 0      /* q = A p with p.q, FP64 CSR (the CG iteration's SpMV) */

@@ -89,6 +89,7 @@ _SIGS = {
                               C.POINTER(C.c_void_p)]),
     "ocp_system_destroy": (None, [C.c_void_p]),
     "fe_set_rho": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double]),
+    "fe_derive": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.POINTER(C.c_void_p)]),
     "fe_load": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(_Mesh), C.POINTER(_Target), C.c_void_p]),
     "fe_load_multi": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(_Mesh), C.c_int32, C.POINTER(_Target),
                                 C.c_void_p]),
@@ -103,6 +104,11 @@ _SIGS = {
                             C.c_int32, C.c_int32, C.POINTER(SolveInfo)]),
     "pcg_solve_multi": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                   C.c_double, C.c_int32, C.c_int32, C.POINTER(SolveInfo)]),
+    "pcg_begin": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32,
+                            C.POINTER(C.c_void_p)]),
+    "pcg_advance": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pcg_poll": (C.c_int, [C.c_void_p, C.POINTER(SolveInfo)]),
+    "pcg_end": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SolveInfo)]),
     "ocp_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "ocp_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
 }
@@ -346,14 +352,17 @@ class System:
     def set_rho(self, rho: float):
         self.ctx.check(lib().fe_set_rho(self.ctx.handle, self.handle, float(rho)))
 
-    def load(self, target, out=None):
+    def load(self, target, out=None, ctx: Optional["Context"] = None):
+        """Load vector of a target; runs on `ctx` (default: the creating
+        context)."""
         torch = _torch()
+        ctx = ctx or self.ctx
         if out is None:
             out = torch.empty(self.n, dtype=torch.float64, device="cuda")
         keep = []
         t = target_struct(target, keep)
         m = self.mesh.struct()
-        self.ctx.check(lib().fe_load(self.ctx.handle, self.handle, C.byref(m), C.byref(t), _ptr(out)))
+        ctx.check(lib().fe_load(ctx.handle, self.handle, C.byref(m), C.byref(t), _ptr(out)))
         return out
 
     def load_multi(self, targets, out=None):
@@ -387,6 +396,14 @@ def fe_assemble(ctx: Context, mesh: DeviceMesh, rho: float, target, flags: int =
     h = C.c_void_p()
     ctx.check(lib().fe_assemble(ctx.handle, C.byref(m), float(rho), C.byref(t), int(flags), C.byref(h)))
     return System(ctx, h, mesh)
+
+
+def fe_derive(ctx: Context, base: System, rho: float) -> System:
+    """System with A = rho*K + M from base's stored K and M (base assembled
+    with KEEP_KM); pattern, maps and f are copied."""
+    h = C.c_void_p()
+    ctx.check(lib().fe_derive(ctx.handle, base.handle, float(rho), C.byref(h)))
+    return System(ctx, h, base.mesh)
 
 
 # -------------------------------------------------------------- hierarchy
@@ -494,3 +511,40 @@ def pcg_solve_multi(ctx: Context, system: System, hierarchy: Optional[Hierarchy]
                                infos)
     ctx.check(rc, ok=(OK, MAXIT))
     return U, list(infos), rc
+
+
+class SolveHandle:
+    """A PCG solve driven in steps (pcg_begin / advance / poll / end)."""
+
+    def __init__(self, ctx: Context, handle, system: System, u):
+        self.ctx, self.handle, self.system, self.u = ctx, handle, system, u
+
+    def advance(self, iters: int):
+        self.ctx.check(lib().pcg_advance(self.handle, int(iters)))
+
+    def poll(self):
+        """(state, SolveInfo): 0 stopped, 1 ready for more iterations, 2 the
+        last advance is still running."""
+        info = SolveInfo()
+        rc = lib().pcg_poll(self.handle, C.byref(info))
+        if rc < 0:
+            self.ctx.check(rc)
+        return rc, info
+
+    def end(self):
+        info = SolveInfo()
+        rc = lib().pcg_end(self.handle, _ptr(self.u), C.byref(info))
+        self.handle = None
+        self.ctx.check(rc, ok=(OK, MAXIT))
+        return self.u, info, rc
+
+
+def pcg_begin(ctx: Context, system: System, hierarchy: Optional[Hierarchy] = None, f=None, u=None,
+              rtol: float = 1e-8, maxit: int = 500, stop: int = STOP_L2) -> SolveHandle:
+    torch = _torch()
+    if u is None:
+        u = torch.empty(system.view().n_vertices, dtype=torch.float64, device="cuda")
+    h = C.c_void_p()
+    ctx.check(lib().pcg_begin(ctx.handle, system.handle, hierarchy.handle if hierarchy is not None else None,
+                              _ptr(f), float(rtol), int(maxit), int(stop), C.byref(h)))
+    return SolveHandle(ctx, h, system, u)

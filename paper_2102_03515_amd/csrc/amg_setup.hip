@@ -907,7 +907,6 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
 
     // precision copies and work vectors
     const bool mixed = pr.precision == OCP_PREC_MIXED;
-    const size_t es = mixed ? sizeof(float) : sizeof(double);
     for (size_t l = 0; l < h->levels.size(); ++l) {
         Level &L = *h->levels[l];
         if (mixed) {
@@ -917,16 +916,6 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
             if (L.P_val.get()) to_float(ctx, L.P_val.get(), L.P_val32, L.nnzP);
             if (L.R_val.get()) to_float(ctx, L.R_val.get(), L.R_val32, L.nnzP);
             if (L.dense_inv.get()) to_float(ctx, L.dense_inv.get(), L.dense_inv32, (int64_t)L.n * L.n);
-        }
-        L.vr.reset(ctx, es * L.n);
-        L.vxp.reset(ctx, es * L.n);
-        if (L.deg == 2) {
-            L.vx1.reset(ctx, es * L.n);
-            L.vx2.reset(ctx, es * L.n);
-        }
-        if (l > 0) {
-            L.vb.reset(ctx, es * L.n);
-            L.vx.reset(ctx, es * L.n);
         }
     }
     sync(ctx);

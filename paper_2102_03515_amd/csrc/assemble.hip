@@ -16,6 +16,8 @@
 #include <climits>
 #include <cmath>
 
+#include <type_traits>
+
 #include "kernels.h"
 #include "system.h"
 
@@ -808,6 +810,52 @@ extern "C" int fe_assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const
 }
 
 extern "C" void ocp_system_destroy(ocp_system *sys) { delete sys; }
+
+extern "C" int fe_derive(ocp_ctx *ctx, const ocp_system *base, double rho, ocp_system **out) {
+    if (!ctx) return OCP_ERR_INVALID_ARG;
+    if (out) *out = nullptr;
+    ocp_system *sys = nullptr;
+    int rc = run_guarded(ctx, [&] {
+        if (!base || !out) fail(OCP_ERR_INVALID_ARG, "base and out must not be NULL");
+        if (!(rho > 0.0) || !std::isfinite(rho)) fail(OCP_ERR_INVALID_ARG, "rho must be positive and finite");
+        if (!base->valK.get()) fail(OCP_ERR_INVALID_ARG, "base system was assembled without OCP_KEEP_KM");
+        sys = new ocp_system();
+        sys->ctx = ctx;
+        sys->nv = base->nv;
+        sys->n = base->n;
+        sys->nt = base->nt;
+        sys->nnz = base->nnz;
+        sys->rho = rho;
+        sys->max_row_len = base->max_row_len;
+        sys->tets_ref = base->tets_ref;
+        auto dup = [&](auto &dst, const auto &src) {
+            using T = std::remove_pointer_t<decltype(src.get())>;
+            dst.reset(ctx, src.size());
+            if (src.size())
+                OCP_HIP(hipMemcpyAsync(dst.get(), src.get(), sizeof(T) * src.size(), hipMemcpyDeviceToDevice,
+                                       ctx->stream));
+        };
+        dup(sys->inc_ptr, base->inc_ptr);
+        dup(sys->inc, base->inc);
+        dup(sys->dof_of_vertex, base->dof_of_vertex);
+        dup(sys->vertex_of_dof, base->vertex_of_dof);
+        dup(sys->row_ptr, base->row_ptr);
+        dup(sys->col, base->col);
+        dup(sys->f, base->f);
+        sys->val.reset(ctx, (size_t)sys->nnz);
+        k_set_rho<<<grid_for(sys->nnz, 256), 256, 0, ctx->stream>>>(sys->nnz, rho, base->valK.get(),
+                                                                    base->valM.get(), sys->val.get());
+        OCP_LAUNCH_CHECK();
+        system_sell(ctx, sys);
+        sync(ctx);
+    });
+    if (rc != OCP_OK) {
+        delete sys;
+        return rc;
+    }
+    *out = sys;
+    return OCP_OK;
+}
 
 extern "C" int fe_set_rho(ocp_ctx *ctx, ocp_system *sys, double rho) {
     if (!ctx) return OCP_ERR_INVALID_ARG;

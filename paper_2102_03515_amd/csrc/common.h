@@ -70,6 +70,7 @@ struct ocp_ctx {
     ocp::CgScalars *cg = nullptr;       // device scalars
     void *pinned = nullptr;             // small pinned host staging buffer (4 KiB)
     int32_t *dev_flag = nullptr;        // general device error/overflow flag
+    bool active_solve = false;          // a step-API solve holds the CG scalars
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // live kernel timing (ocp_profile_enable): event pairs around selected
     // launches, resolved after each solve
@@ -153,7 +154,10 @@ void prof_end(ocp_ctx *ctx, int rec);
 void prof_resolve(ocp_ctx *ctx, int valid_iters);
 
 // Run f, turning internal errors into a status code and ctx->last_error.
+// Refused while a step-API solve (pcg_begin .. pcg_end) holds the context.
 int run_guarded(ocp_ctx *ctx, const std::function<void()> &f);
+// The same without that check, for the step API's own calls.
+int run_step(ocp_ctx *ctx, const std::function<void()> &f);
 
 }  // namespace ocp
 

@@ -676,10 +676,7 @@ __global__ void __launch_bounds__(kFinBlock) k_blk_fin_update(unsigned nb, const
 }
 
 // ---------------------------------------------------------------- V-cycle
-// Work blocks of one level in the hierarchy's precision, [n_l][k] each.
-struct BlkLevelWork {
-    DevBuf<char> vb, vr, vx, vxp, vx1, vx2;
-};
+using BlkLevelWork = VcWork::Lvl;   // work blocks of one level, [n_l][k] each
 
 template <typename T>
 struct BlkArrays {
@@ -863,24 +860,6 @@ static unsigned vcycle_block(ocp_ctx *ctx, const ocp_hierarchy *h, const double 
     return nb;
 }
 
-static void alloc_block_work(ocp_ctx *ctx, const ocp_hierarchy *h, int k, std::vector<BlkLevelWork> &W) {
-    const size_t vs = h->params.precision == OCP_PREC_MIXED ? sizeof(float) : sizeof(double);
-    const int L = (int)h->levels.size();
-    W.resize(L);
-    for (int l = 0; l < L; ++l) {
-        const size_t bytes = (size_t)h->levels[l]->n * k * vs;
-        const bool inner = l < L - 1;
-        if (l > 0) W[l].vb.reset(ctx, bytes);
-        if (l > 0) W[l].vx.reset(ctx, bytes);
-        if (inner) {
-            W[l].vr.reset(ctx, bytes);
-            W[l].vxp.reset(ctx, bytes);
-            W[l].vx1.reset(ctx, bytes);
-            W[l].vx2.reset(ctx, bytes);
-        }
-    }
-}
-
 // ------------------------------------------------------------------ driver
 static int worst_status(const std::vector<int> &st) {
     int w = OCP_OK;
@@ -944,8 +923,9 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
     CgBlock *cgb = cgbuf.get();
     const double *dinv = h ? nullptr : system_dinv(ctx, sys);
     const int mode = (flags & OCP_STOP_PRECOND) ? OCP_STOP_PRECOND : OCP_STOP_L2;
-    std::vector<BlkLevelWork> work;
-    if (h) alloc_block_work(ctx, h, k, work);
+    VcWork vwork;
+    if (h) vc_work_alloc(ctx, h, vwork, k);
+    std::vector<BlkLevelWork> &work = vwork.lv;
     const bool mixed = h && h->params.precision == OCP_PREC_MIXED;
     // level-0 first smoothing step of R, written by the kernels producing R
     DevBuf<char> y0buf;

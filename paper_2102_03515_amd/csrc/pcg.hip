@@ -247,85 +247,127 @@ const double *system_dinv(ocp_ctx *ctx, ocp_system *sys) {
     return sys->dinv.get();
 }
 
-static void solve(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, const double *f_in, double *u,
-                  double rtol, int32_t maxit, int32_t flags, ocp_solve_info *info, int *status) {
+// One PCG solve in progress: its vectors and launch shapes.  The scalars
+// live in the context (ctx->cg), so a context runs one solve at a time.
+struct SolveState {
+    ocp_ctx *ctx = nullptr;
+    ocp_system *sys = nullptr;
+    const ocp_hierarchy *h = nullptr;
+    const double *f = nullptr;
+    const double *dinv = nullptr;
+    DevBuf<double> x, r, p, q, z;
+    VcWork vw;           // V-cycle work vectors of this solve
+    int mode = OCP_STOP_L2;
+    int32_t maxit = 0;
+    double rtol = 0.0;
+    int host_iter = 0;   // iterations enqueued (host count)
+};
+
+// Allocate and enqueue x = 0, r = f, the first preconditioner application
+// and p = z (no host synchronization).
+static void solve_begin(SolveState &S, ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, const double *f_in,
+                        double rtol, int32_t maxit, int32_t flags) {
+    S.ctx = ctx;
+    S.sys = sys;
+    S.h = h;
+    S.rtol = rtol;
+    S.maxit = maxit;
     const int32_t n = sys->n;
-    const double *f = f_in ? f_in : sys->f.get();
-    DevBuf<double> x(ctx, n), r(ctx, n), p(ctx, n), q(ctx, n), z(ctx, n);
-    const double *dinv = h ? nullptr : system_dinv(ctx, sys);
-    const int mode = (flags & OCP_STOP_PRECOND) ? OCP_STOP_PRECOND : OCP_STOP_L2;
+    S.f = f_in ? f_in : sys->f.get();
+    S.x.reset(ctx, n);
+    S.r.reset(ctx, n);
+    S.p.reset(ctx, n);
+    S.q.reset(ctx, n);
+    S.z.reset(ctx, n);
+    S.dinv = h ? nullptr : system_dinv(ctx, sys);
+    if (h) vc_work_alloc(ctx, h, S.vw);
+    S.mode = (flags & OCP_STOP_PRECOND) ? OCP_STOP_PRECOND : OCP_STOP_L2;
     CgScalars *cg = ctx->cg;
     double *part0 = ctx->red_partials;
     double *part1 = ctx->red_partials + kRedBlocks;
-    double *part2 = ctx->red_partials + 2 * kRedBlocks;
-    const Sell &A = system_sell(ctx, sys);
-    const SellLaunch LS = sell_launch(A.nslices);
+    system_sell(ctx, sys);
     const RowLaunch LV = vec_launch(n);
-    const unsigned gp = grid_for(n, kBlock);
-
     ctx->prof_iter = -1;   // the initial preconditioner application
     OCP_HIP(hipEventRecord(ctx->ev0, ctx->stream));
-    k_cg_init<<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, f, x.get(), r.get(), p.get(), part0);
-    k_fin_init<<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part0, cg, rtol, mode, maxit);
+    k_cg_init<<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, S.f, S.x.get(), S.r.get(), S.p.get(), part0);
+    k_fin_init<<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part0, cg, rtol, S.mode, maxit);
     OCP_LAUNCH_CHECK();
     if (h) {
-        vcycle_enqueue(ctx, h, r.get(), z.get(), cg);
+        vcycle_enqueue(ctx, h, S.r.get(), S.z.get(), cg, S.vw);
     } else {
-        k_cg_jacobi<<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, r.get(), dinv, z.get(), cg, part1);
+        k_cg_jacobi<<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, S.r.get(), S.dinv, S.z.get(), cg, part1);
         k_fin_rz<<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part1, cg);
     }
     OCP_LAUNCH_CHECK();
-    k_cg_pupdate<<<gp, kBlock, 0, ctx->stream>>>(n, p.get(), z.get(), cg);
+    k_cg_pupdate<<<grid_for(n, kBlock), kBlock, 0, ctx->stream>>>(n, S.p.get(), S.z.get(), cg);
     OCP_LAUNCH_CHECK();
-
-    CgScalars hs{};
-    int chunk = 2;
     ctx->prof_iter = 0;
-    for (;;) {
-        read_back(ctx, &hs, cg, sizeof(hs));
-        if (hs.flag != 0) break;
-        for (int k = 0; k < chunk; ++k) {
-            const int pr = prof_begin(ctx, OCP_KERNEL_CG_SPMV);
-            k_cg_spmv_pq_sell<<<LS.blocks, kBlock, 0, ctx->stream>>>(n, A.nslices, LS.slices_per_block, A.sp.get(),
-                                                                     A.sw.get(), A.col.get(), A.val.get(), p.get(),
-                                                                     q.get(), cg, part0);
-            prof_end(ctx, pr);
-            k_fin_alpha<<<1, kBlock, 0, ctx->stream>>>(LS.blocks, part0, cg);
-            if (h) {
-                k_cg_update<false><<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, x.get(), r.get(), p.get(),
-                                                                          q.get(), nullptr, nullptr, cg, part1);
-                k_fin_update<false><<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part1, cg);
-                vcycle_enqueue(ctx, h, r.get(), z.get(), cg);
-            } else {
-                k_cg_update<true><<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, x.get(), r.get(), p.get(),
-                                                                         q.get(), dinv, z.get(), cg, part1);
-                k_fin_update<true><<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part1, cg);
-            }
-            k_cg_pupdate<<<gp, kBlock, 0, ctx->stream>>>(n, p.get(), z.get(), cg);
-            ++ctx->prof_iter;
-        }
-        OCP_LAUNCH_CHECK();
-        if (chunk < 8) chunk *= 2;
-    }
-    OCP_HIP(hipEventRecord(ctx->ev1, ctx->stream));
+}
 
-    // true residual in double, then u on all vertices
+// Enqueue `iters` PCG iterations; kernels of iterations after the stop
+// return at once on the device flag.
+static void solve_iterate(SolveState &S, int iters) {
+    ocp_ctx *ctx = S.ctx;
+    const int32_t n = S.sys->n;
+    CgScalars *cg = ctx->cg;
+    double *part0 = ctx->red_partials;
+    double *part1 = ctx->red_partials + kRedBlocks;
+    const Sell &A = system_sell(ctx, S.sys);
+    const SellLaunch LS = sell_launch(A.nslices);
+    const RowLaunch LV = vec_launch(n);
+    const unsigned gp = grid_for(n, kBlock);
+    for (int k = 0; k < iters; ++k) {
+        const int pr = prof_begin(ctx, OCP_KERNEL_CG_SPMV);
+        k_cg_spmv_pq_sell<<<LS.blocks, kBlock, 0, ctx->stream>>>(n, A.nslices, LS.slices_per_block, A.sp.get(),
+                                                                 A.sw.get(), A.col.get(), A.val.get(), S.p.get(),
+                                                                 S.q.get(), cg, part0);
+        prof_end(ctx, pr);
+        k_fin_alpha<<<1, kBlock, 0, ctx->stream>>>(LS.blocks, part0, cg);
+        if (S.h) {
+            k_cg_update<false><<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, S.x.get(), S.r.get(), S.p.get(),
+                                                                      S.q.get(), nullptr, nullptr, cg, part1);
+            k_fin_update<false><<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part1, cg);
+            vcycle_enqueue(ctx, S.h, S.r.get(), S.z.get(), cg, S.vw);
+        } else {
+            k_cg_update<true><<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, S.x.get(), S.r.get(), S.p.get(),
+                                                                     S.q.get(), S.dinv, S.z.get(), cg, part1);
+            k_fin_update<true><<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part1, cg);
+        }
+        k_cg_pupdate<<<gp, kBlock, 0, ctx->stream>>>(n, S.p.get(), S.z.get(), cg);
+        ++ctx->prof_iter;
+        ++S.host_iter;
+    }
+    OCP_LAUNCH_CHECK();
+}
+
+// After the stop: true residual in double, u on all vertices, the info
+// record; synchronizes the context stream.
+static int solve_finish(SolveState &S, double *u, ocp_solve_info *info) {
+    ocp_ctx *ctx = S.ctx;
+    ocp_system *sys = S.sys;
+    const int32_t n = sys->n;
+    double *part2 = ctx->red_partials + 2 * kRedBlocks;
+    const Sell &A = system_sell(ctx, sys);
+    const SellLaunch LS = sell_launch(A.nslices);
+    OCP_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     k_resid2_sell<<<LS.blocks, kBlock, 0, ctx->stream>>>(n, A.nslices, LS.slices_per_block, A.sp.get(), A.sw.get(),
-                                                         A.col.get(), A.val.get(), x.get(), f, part2);
+                                                         A.col.get(), A.val.get(), S.x.get(), S.f, part2);
     k_fin_store<<<1, kBlock, 0, ctx->stream>>>(LS.blocks, part2, ctx->red_out + 1);
     OCP_LAUNCH_CHECK();
-    k_scatter<<<grid_for(sys->nv, 256), 256, 0, ctx->stream>>>(sys->nv, sys->dof_of_vertex.get(), x.get(), u);
+    k_scatter<<<grid_for(sys->nv, 256), 256, 0, ctx->stream>>>(sys->nv, sys->dof_of_vertex.get(), S.x.get(), u);
     OCP_LAUNCH_CHECK();
+    CgScalars hs{};
+    read_back(ctx, &hs, ctx->cg, sizeof(hs));
     double res2 = 0.0;
     read_back(ctx, &res2, ctx->red_out + 1, sizeof(res2));
     float ms = 0.f;
     OCP_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     // every kernel of host iterations 0 .. iter-2 did its full work
     prof_resolve(ctx, hs.iter - 1);
-
     int st = OCP_OK;
     if (hs.flag == 2) st = OCP_ERR_BREAKDOWN;
     else if (hs.flag == 3) st = OCP_MAXIT;
+    else if (hs.flag == 0) st = OCP_MAXIT;   // ended by the caller before the stop
     if (info) {
         info->iterations = hs.iter;
         info->status = st;
@@ -334,7 +376,22 @@ static void solve(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, const d
         info->true_rel_res = hs.ff > 0 ? std::sqrt(res2 / hs.ff) : 0.0;
         info->solve_ms = ms;
     }
-    *status = st;
+    return st;
+}
+
+static void solve(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, const double *f_in, double *u,
+                  double rtol, int32_t maxit, int32_t flags, ocp_solve_info *info, int *status) {
+    SolveState S;
+    solve_begin(S, ctx, sys, h, f_in, rtol, maxit, flags);
+    CgScalars hs{};
+    int chunk = 2;
+    for (;;) {
+        read_back(ctx, &hs, ctx->cg, sizeof(hs));
+        if (hs.flag != 0) break;
+        solve_iterate(S, chunk);
+        if (chunk < 8) chunk *= 2;
+    }
+    *status = solve_finish(S, u, info);
 }
 
 }  // namespace ocp
@@ -370,4 +427,89 @@ extern "C" int pcg_solve(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarch
     }
     if (status == OCP_ERR_BREAKDOWN) ctx->last_error = "CG breakdown (p^T A p <= 0, r^T z <= 0 or non-finite)";
     return status;
+}
+
+// ------------------------------------------------------------ step API
+struct ocp_solve_handle {
+    ocp::SolveState S;
+    hipEvent_t ev_poll = nullptr;   // recorded after the scalar copy of the last advance
+    bool polled_copy = false;
+};
+
+extern "C" int pcg_begin(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, const double *f, double rtol,
+                         int32_t maxit, int32_t flags, ocp_solve_handle **out) {
+    if (!ctx) return OCP_ERR_INVALID_ARG;
+    return run_guarded(ctx, [&] {
+        if (!out) fail(OCP_ERR_INVALID_ARG, "out must not be NULL");
+        *out = nullptr;
+        if (!sys) fail(OCP_ERR_INVALID_ARG, "system must not be NULL");
+        if (!(rtol > 0.0) || !std::isfinite(rtol)) fail(OCP_ERR_INVALID_ARG, "rtol must be positive");
+        if (maxit < 1) fail(OCP_ERR_INVALID_ARG, "maxit must be >= 1");
+        if (h && h->sys != sys) fail(OCP_ERR_INVALID_ARG, "hierarchy belongs to another system");
+        if (ctx->active_solve) fail(OCP_ERR_INVALID_ARG, "the context already runs a solve (one per context)");
+        auto *hd = new ocp_solve_handle();
+        try {
+            OCP_HIP(hipEventCreateWithFlags(&hd->ev_poll, hipEventDisableTiming));
+            solve_begin(hd->S, ctx, const_cast<ocp_system *>(sys), h, f, rtol, maxit, flags);
+        } catch (...) {
+            if (hd->ev_poll) (void)hipEventDestroy(hd->ev_poll);
+            delete hd;
+            throw;
+        }
+        ctx->active_solve = true;
+        *out = hd;
+    });
+}
+
+extern "C" int pcg_advance(ocp_solve_handle *hd, int32_t iters) {
+    if (!hd || !hd->S.ctx) return OCP_ERR_INVALID_ARG;
+    ocp_ctx *ctx = hd->S.ctx;
+    return run_step(ctx, [&] {
+        if (iters < 1) fail(OCP_ERR_INVALID_ARG, "iters must be >= 1");
+        solve_iterate(hd->S, iters);
+        // scalars to the pinned staging buffer, then a marker to poll
+        OCP_HIP(hipMemcpyAsync(ctx->pinned, ctx->cg, sizeof(CgScalars), hipMemcpyDeviceToHost, ctx->stream));
+        OCP_HIP(hipEventRecord(hd->ev_poll, ctx->stream));
+        hd->polled_copy = true;
+    });
+}
+
+extern "C" int pcg_poll(ocp_solve_handle *hd, ocp_solve_info *info) {
+    if (!hd || !hd->S.ctx) return OCP_ERR_INVALID_ARG;
+    ocp_ctx *ctx = hd->S.ctx;
+    if (!hd->polled_copy) return 1;   // nothing advanced yet
+    const hipError_t q = hipEventQuery(hd->ev_poll);
+    if (q == hipErrorNotReady) return 2;
+    if (q != hipSuccess) {
+        ctx->last_error = std::string("hipEventQuery: ") + hipGetErrorString(q);
+        return OCP_ERR_HIP;
+    }
+    CgScalars hs;
+    std::memcpy(&hs, ctx->pinned, sizeof(hs));
+    if (info) {
+        info->iterations = hs.iter;
+        info->status = hs.flag == 0 ? 1 : hs.flag == 1 ? OCP_OK : hs.flag == 2 ? OCP_ERR_BREAKDOWN : OCP_MAXIT;
+        info->rel_res_l2 = hs.ff > 0 ? std::sqrt(hs.rr / hs.ff) : 0.0;
+        info->rel_res_precond = hs.gamma0 > 0 ? std::sqrt(hs.gamma / hs.gamma0) : 0.0;
+        info->true_rel_res = 0.0;
+        info->solve_ms = 0.0;
+    }
+    return hs.flag == 0 ? 1 : 0;
+}
+
+extern "C" int pcg_end(ocp_solve_handle *hd, double *u, ocp_solve_info *info) {
+    if (!hd || !hd->S.ctx) return OCP_ERR_INVALID_ARG;
+    ocp_ctx *ctx = hd->S.ctx;
+    int st = OCP_OK;
+    int rc = run_step(ctx, [&] {
+        if (!u) fail(OCP_ERR_INVALID_ARG, "u must not be NULL");
+        st = solve_finish(hd->S, u, info);
+    });
+    (void)hipStreamSynchronize(ctx->stream);
+    if (hd->ev_poll) (void)hipEventDestroy(hd->ev_poll);
+    ctx->active_solve = false;
+    delete hd;
+    if (rc != OCP_OK) return rc;
+    if (st == OCP_ERR_BREAKDOWN) ctx->last_error = "CG breakdown (p^T A p <= 0, r^T z <= 0 or non-finite)";
+    return st;
 }

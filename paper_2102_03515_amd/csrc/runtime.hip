@@ -374,5 +374,12 @@ extern "C" const char *ocp_last_error(const ocp_ctx *ctx) {
 
 // exported to the other translation units
 namespace ocp {
-int run_guarded(ocp_ctx *ctx, const std::function<void()> &f) { return guarded(ctx, f); }
+int run_guarded(ocp_ctx *ctx, const std::function<void()> &f) {
+    if (ctx && ctx->active_solve) {
+        ctx->last_error = "a solve started with pcg_begin is active on this context (end it first)";
+        return OCP_ERR_INVALID_ARG;
+    }
+    return guarded(ctx, f);
+}
+int run_step(ocp_ctx *ctx, const std::function<void()> &f) { return guarded(ctx, f); }
 }  // namespace ocp

@@ -61,8 +61,6 @@ struct Level {
     DevBuf<float> A_val32, P_val32, R_val32, dinv32, dense_inv32;
     // level 0: values of the system's sliced-ELL copy in the hierarchy's precision
     DevBuf<float> sell_val32;
-    // V-cycle work vectors in the hierarchy's precision (bytes)
-    DevBuf<char> vb, vr, vx, vxp, vx1, vx2;
     double lambda_max = 0.0;   // Gershgorin bound of D^-1 A
     // polynomial smoother: first step x = a D^-1 r; degree 2 adds
     // x = D^-1 (c1 r0 + c2 r1) with r1 the residual after the first step
@@ -82,10 +80,21 @@ struct ocp_hierarchy {
 };
 
 namespace ocp {
+// V-cycle work vectors of one solve, per level, in the hierarchy's precision
+// (k columns for the block solve).  They belong to the solve, not to the
+// hierarchy, so one hierarchy serves concurrent solves on several streams.
+struct VcWork {
+    struct Lvl {
+        DevBuf<char> vb, vr, vx, vxp, vx1, vx2;
+    };
+    std::vector<Lvl> lv;
+};
+void vc_work_alloc(ocp_ctx *ctx, const ocp_hierarchy *h, VcWork &w, int k = 1);
+
 // Enqueue z = B r (one V-cycle).  If cg != nullptr the level-0 post-smoother
 // also forms r.z and updates the CG scalars (through a one-block finalize
 // kernel), and every kernel returns at once when cg->flag is set.
-void vcycle_enqueue(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r, double *z, CgScalars *cg);
+void vcycle_enqueue(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r, double *z, CgScalars *cg, VcWork &w);
 // Lanes per row for a matrix with the given average row length.
 int level_lanes(int64_t nnz, int64_t rows);
 // Build 1/a_ii of the system if missing.

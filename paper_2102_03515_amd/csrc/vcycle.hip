@@ -230,7 +230,8 @@ static int lanes_for(int64_t nnz, int64_t rows) {
 }
 
 template <typename T>
-static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, double *z_out, CgScalars *cg) {
+static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, double *z_out, CgScalars *cg,
+                     VcWork &W) {
     const auto &lv = h->levels;
     const int L = (int)lv.size();
     hipStream_t s = ctx->stream;
@@ -282,8 +283,8 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
         const Level &cur = *lv[l];
         const Level &nxt = *lv[l + 1];
         const auto a = arrays<T>(cur);
-        T *rres = reinterpret_cast<T *>(cur.vr.get());
-        T *x2 = reinterpret_cast<T *>(cur.vx2.get());
+        T *rres = reinterpret_cast<T *>(W.lv[l].vr.get());
+        T *x2 = reinterpret_cast<T *>(W.lv[l].vx2.get());
         const T ca = (T)cur.cheb_a, c1 = (T)cur.cheb_c1, c2 = (T)cur.cheb_c2;
         if (cur.deg == 2) {
             // x2 = D^-1 (c1 b + c2 r1), r1 = b - A (a D^-1 b); then r2 = b - A x2
@@ -302,7 +303,7 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
                  false);
             prof_end(ctx, pr);
         }
-        T *bn = reinterpret_cast<T *>(nxt.vb.get());
+        T *bn = reinterpret_cast<T *>(W.lv[l + 1].vb.get());
         const RowLaunch LR = row_launch(nxt.n, cur.gR);
         const int prr = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_RESTRICT0) : -1;
         OCP_DISPATCH_G(cur.gR, (k_vc_spmv<G, T><<<LR.blocks, kBlock, 0, s>>>(nxt.n, LR.iters, cur.R_rp.get(),
@@ -314,14 +315,14 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
         if (l == 0)
             down(0, r_in);
         else
-            down(l, reinterpret_cast<const T *>(lv[l]->vb.get()));
+            down(l, reinterpret_cast<const T *>(W.lv[l].vb.get()));
     }
     // ---- coarsest
     {
         const Level &cl = *lv[L - 1];
         const auto a = arrays<T>(cl);
-        const T *b = reinterpret_cast<const T *>(cl.vb.get());
-        T *x = reinterpret_cast<T *>(cl.vx.get());
+        const T *b = reinterpret_cast<const T *>(W.lv[L - 1].vb.get());
+        T *x = reinterpret_cast<T *>(W.lv[L - 1].vx.get());
         if (a.inv)
             k_vc_dense<T, T, T><<<grid_for(cl.n, kBlock / 64), kBlock, 0, s>>>(cl.n, a.inv, b, x, cg);
         else
@@ -334,13 +335,12 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
         using BT = std::remove_const_t<std::remove_pointer_t<decltype(bptr)>>;
         using OT = std::remove_pointer_t<decltype(outptr)>;
         const Level &cur = *lv[l];
-        const Level &nxt = *lv[l + 1];
         const auto a = arrays<T>(cur);
-        const T *xc = reinterpret_cast<const T *>(nxt.vx.get());
-        T *xp = reinterpret_cast<T *>(cur.vxp.get());
-        T *x2 = reinterpret_cast<T *>(cur.vx2.get());
-        T *r0 = reinterpret_cast<T *>(cur.vr.get());
-        T *x1 = reinterpret_cast<T *>(cur.vx1.get());
+        const T *xc = reinterpret_cast<const T *>(W.lv[l + 1].vx.get());
+        T *xp = reinterpret_cast<T *>(W.lv[l].vxp.get());
+        T *x2 = reinterpret_cast<T *>(W.lv[l].vx2.get());
+        T *r0 = reinterpret_cast<T *>(W.lv[l].vr.get());
+        T *x1 = reinterpret_cast<T *>(W.lv[l].vx1.get());
         const T ca = (T)cur.cheb_a, c1 = (T)cur.cheb_c1, c2 = (T)cur.cheb_c2;
         const T zero = T(0);
         const RowLaunch LP = row_launch(cur.n, cur.gP);
@@ -389,7 +389,7 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
         if (l == 0)
             up(0, r_in, z_out, cg != nullptr);
         else
-            up(l, reinterpret_cast<const T *>(lv[l]->vb.get()), reinterpret_cast<T *>(lv[l]->vx.get()), false);
+            up(l, reinterpret_cast<const T *>(W.lv[l].vb.get()), reinterpret_cast<T *>(W.lv[l].vx.get()), false);
     }
     if (cg) {
         k_vc_fin_rz<<<1, kBlock, 0, s>>>(fin_nb, part, cg);
@@ -397,11 +397,31 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
     }
 }
 
-void vcycle_enqueue(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r, double *z, CgScalars *cg) {
+void vcycle_enqueue(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r, double *z, CgScalars *cg, VcWork &w) {
     if (h->params.precision == OCP_PREC_MIXED)
-        vcycle_t<float>(ctx, h, r, z, cg);
+        vcycle_t<float>(ctx, h, r, z, cg, w);
     else
-        vcycle_t<double>(ctx, h, r, z, cg);
+        vcycle_t<double>(ctx, h, r, z, cg, w);
+}
+
+void vc_work_alloc(ocp_ctx *ctx, const ocp_hierarchy *h, VcWork &w, int k) {
+    const size_t vs = h->params.precision == OCP_PREC_MIXED ? sizeof(float) : sizeof(double);
+    const int L = (int)h->levels.size();
+    w.lv.clear();
+    w.lv.resize(L);
+    for (int l = 0; l < L; ++l) {
+        const size_t bytes = (size_t)h->levels[l]->n * k * vs;
+        if (l > 0) {
+            w.lv[l].vb.reset(ctx, bytes);
+            w.lv[l].vx.reset(ctx, bytes);
+        }
+        if (l < L - 1) {
+            w.lv[l].vr.reset(ctx, bytes);
+            w.lv[l].vxp.reset(ctx, bytes);
+            w.lv[l].vx1.reset(ctx, bytes);
+            w.lv[l].vx2.reset(ctx, bytes);
+        }
+    }
 }
 
 int level_lanes(int64_t nnz, int64_t rows) { return lanes_for(nnz, rows); }
@@ -414,6 +434,9 @@ extern "C" int amg_vcycle(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r,
     if (!ctx) return OCP_ERR_INVALID_ARG;
     return run_guarded(ctx, [&] {
         if (!h || !r || !z) fail(OCP_ERR_INVALID_ARG, "hierarchy, r and z must not be NULL");
-        vcycle_enqueue(ctx, h, r, z, nullptr);
+        VcWork w;
+        vc_work_alloc(ctx, h, w);
+        vcycle_enqueue(ctx, h, r, z, nullptr, w);
+        sync(ctx);   // the work vectors are released on return
     });
 }

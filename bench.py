@@ -131,6 +131,82 @@ def block_bench(P, capi, reps: int = 3, N: int = 128, k: int = 32):
     return out
 
 
+def packed_bench(P, capi, m: int = 32, N: int = 32, reps: int = 3):
+    """m small solves on the N^3 mesh (the smallest serving size): each its
+    own rho = 10^U(-8,-2) (seed 5000), target (seeds 5001..) and FP32
+    hierarchy, solved to 1e-8 once as one packed batch (one graph launch per
+    iteration for all) and once as m pcg_solve calls in a row.  Systems and
+    hierarchies are built before the timing."""
+    import numpy as np
+    import torch
+    import ocp_inputs as I
+    ctx = P.Context(stream=torch.cuda.Stream())
+    mesh = I.kuhn_mesh(N)
+    dm = P.upload_mesh(mesh)
+    base = P.fe_assemble(ctx, dm, 1.0 / N ** 2, I.single_sine(), capi.KEEP_KM)
+    rng = np.random.default_rng(5000)
+    rhos = [float(10.0 ** rng.uniform(-8.0, -2.0)) for _ in range(m)]
+    systems = [P.fe_derive(ctx, base, r) for r in rhos]
+    hs = [P.amg_setup(ctx, s, precision=capi.PREC_MIXED) for s in systems]
+    fs = [s.load(I.random_sine_modes(5001 + j)) for j, s in enumerate(systems)]
+    us = [torch.empty(s.view().n_vertices, dtype=torch.float64, device="cuda") for s in systems]
+    P.pcg_solve_batch(ctx, systems, hs, fs, us, rtol=1e-8)          # warm-up
+    for s, h, f, u in zip(systems, hs, fs, us):
+        P.pcg_solve(ctx, s, h, f=f, u=u, rtol=1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, infos, rc = P.pcg_solve_batch(ctx, systems, hs, fs, us, rtol=1e-8)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for s, h, f, u in zip(systems, hs, fs, us):
+            P.pcg_solve(ctx, s, h, f=f, u=u, rtol=1e-8)
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / reps
+    n = systems[0].n
+    out = {"workload": f"packed{m}_cube{N}", "solves": m, "unknowns_each": n,
+           "batch_ms": 1e3 * t_batch, "sequential_ms": 1e3 * t_seq, "speedup": t_seq / t_batch,
+           "batch_dof_per_s": m * n / t_batch, "sequential_dof_per_s": m * n / t_seq,
+           "iterations": [min(i.iterations for i in infos), max(i.iterations for i in infos)],
+           "max_true_rel_res": max(i.true_rel_res for i in infos)}
+    for h in hs:
+        h.close()
+    for s in systems:
+        s.close()
+    base.close()
+    ctx.close()
+    return out
+
+
+def serve_bench(P, capi, n_requests: int = 400, rate: float = 200.0, slots: int = 8):
+    """Poisson stream of solve requests (mean `rate` per second, seed 3000):
+    N uniform in {32, 48, 64, 96, 128, 160}, rho = h^2 with probability 1/2
+    else 10^U(-8,-2), a sine-mode target per request; each solved to 1e-8.
+    The meshes and K/M systems of the six sizes are built before the stream
+    starts (server start-up); hierarchies are built on demand and cached per
+    (N, rho, precision).  Latency = completion time - arrival time."""
+    import ocp_inputs as I
+    from paper_2102_03515_amd import serve
+    reqs = I.serving_requests(n_requests, rate=rate, seed=3000)
+    srv = serve.Server(slots=slots, precision=capi.PREC_MIXED)
+    t0 = time.perf_counter()
+    srv.warm(I.SERVE_SIZES)
+    warm_s = time.perf_counter() - t0
+    out = {"workload": f"serve_poisson{int(rate)}", "requests": n_requests, "rate_per_s": rate, "slots": slots,
+           "sizes": list(I.SERVE_SIZES), "startup_s": warm_s}
+    for name, prec in (("mixed", capi.PREC_MIXED), ("fp64", capi.PREC_FP64)):
+        srv.precision = prec
+        before = dict(srv.stats)
+        res, makespan = srv.run(reqs, realtime=True)
+        out[name] = serve.summarize(res, makespan)
+        out[name]["hierarchy_builds"] = srv.stats["misses"] - before["misses"]
+        print(f"[bench] serve {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
+    srv.close()
+    return out
+
+
 def cpu_baseline(target_seed: int, N_sample: int = 64):
     """The oracle (own assembly + Jacobi-PCG to 1e-8) on a smaller mesh of
     the same family: N_sample^3 cubes, rho = h^2, the same 64 modes."""
@@ -157,6 +233,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-hierarchy comparison step")
     ap.add_argument("--no-block", action="store_true", help="skip the 32-target block solve at 127^3")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served request stream")
+    ap.add_argument("--no-packed", action="store_true", help="skip the packed batch of small solves")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this solver is measured per GPU "
@@ -252,6 +330,17 @@ def main():
         block = block_bench(P, capi)
         print(f"[bench] block: {json.dumps(block)}", file=sys.stderr, flush=True)
 
+    packed = None
+    if not args.no_packed:
+        print("[bench] packed batch of 32 small solves ...", file=sys.stderr, flush=True)
+        packed = [packed_bench(P, capi, m=m) for m in (32, 256)]
+        print(f"[bench] packed: {json.dumps(packed)}", file=sys.stderr, flush=True)
+
+    served = None
+    if not args.no_serve:
+        print("[bench] serving stream (400 requests, 200/s) ...", file=sys.stderr, flush=True)
+        served = serve_bench(P, capi)
+
     cpu = None
     if not args.no_cpu_baseline and isinstance(tspec, tuple):
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
@@ -283,6 +372,8 @@ def main():
         "solve_only_dof_per_s": n / (solve_ms * 1e-3),
         "fp64": fp64,
         "block32": block,
+        "packed_small": packed,
+        "serve": served,
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

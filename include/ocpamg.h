@@ -262,6 +262,29 @@ int pcg_solve_multi(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h,
                     const double *F, double *U, double rtol, int32_t maxit, int32_t flags,
                     ocp_solve_info *infos);
 
+/* Many independent solves packed together (each one the PCG of pcg_solve
+ * on its own system, hierarchy and right-hand side).  Problems of at most
+ * 2^18 unknowns run in one persistent launch, one workgroup per solve doing
+ * the whole iteration (every V-cycle pass, the stop test) on the device:
+ * some thirty kernel dispatches per iteration per problem, each only
+ * microseconds of work at these sizes, become one dispatch for the batch.
+ * Their results equal pcg_solve's to rounding (dot products are summed in
+ * another order), bit for bit from one batch call to the next.  Larger
+ * problems (or all, with OCP_BATCH_GRAPH) are packed into one HIP graph that
+ * holds one iteration of every solve and is replayed until all have
+ * stopped; those give the same bits as pcg_solve alone.
+ *   m             1..4096 solves
+ *   systems[m]    systems (may repeat); hierarchies[m] or NULL (Jacobi), an
+ *                 entry may be NULL; f[m] device right-hand sides or NULL
+ *                 (system f), an entry may be NULL; u[m] device outputs
+ *                 [n_vertices of system i]
+ *   infos         host [m] or NULL; solve_ms is the whole batch's time
+ * Returns the worst status (BREAKDOWN, then MAXIT) or an error. */
+#define OCP_BATCH_GRAPH (1 << 16) /* pcg_solve_batch: use the graph path for every solve */
+int pcg_solve_batch(ocp_ctx *ctx, int32_t m, const ocp_system *const *systems,
+                    const ocp_hierarchy *const *hierarchies, const double *const *f, double *const *u,
+                    double rtol, int32_t maxit, int32_t flags, ocp_solve_info *infos);
+
 /* Step interface of pcg_solve for callers that interleave several solves
  * (the serving loop): the same iteration, enqueued in pieces without
  * blocking.  A context runs one such solve at a time, and while it is

@@ -104,6 +104,9 @@ _SIGS = {
                             C.c_int32, C.c_int32, C.POINTER(SolveInfo)]),
     "pcg_solve_multi": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                   C.c_double, C.c_int32, C.c_int32, C.POINTER(SolveInfo)]),
+    "pcg_solve_batch": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                  C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_double, C.c_int32, C.c_int32,
+                                  C.POINTER(SolveInfo)]),
     "pcg_begin": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32,
                             C.POINTER(C.c_void_p)]),
     "pcg_advance": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -548,3 +551,28 @@ def pcg_begin(ctx: Context, system: System, hierarchy: Optional[Hierarchy] = Non
     ctx.check(lib().pcg_begin(ctx.handle, system.handle, hierarchy.handle if hierarchy is not None else None,
                               _ptr(f), float(rtol), int(maxit), int(stop), C.byref(h)))
     return SolveHandle(ctx, h, system, u)
+
+
+BATCH_GRAPH = 1 << 16
+
+
+def pcg_solve_batch(ctx: Context, systems, hierarchies=None, fs=None, us=None, rtol: float = 1e-8,
+                    maxit: int = 500, stop: int = STOP_L2, graph: bool = False):
+    """Many independent solves packed together: small ones in one persistent
+    launch (one workgroup per solve), the others (or all, with graph=True)
+    in one graph launch per iteration.  Returns ([u_i], [SolveInfo_i],
+    worst status)."""
+    torch = _torch()
+    m = len(systems)
+    if us is None:
+        us = [torch.empty(s.view().n_vertices, dtype=torch.float64, device="cuda") for s in systems]
+    arr = lambda xs: (C.c_void_p * m)(*[None if x is None else C.c_void_p(x) for x in xs])
+    sys_a = arr([s.handle.value for s in systems])
+    h_a = arr([None if h is None else h.handle.value for h in hierarchies]) if hierarchies is not None else None
+    f_a = arr([_ptr(f) for f in fs]) if fs is not None else None
+    u_a = arr([_ptr(u) for u in us])
+    infos = (SolveInfo * m)()
+    flags = int(stop) | (BATCH_GRAPH if graph else 0)
+    rc = lib().pcg_solve_batch(ctx.handle, m, sys_a, h_a, f_a, u_a, float(rtol), int(maxit), flags, infos)
+    ctx.check(rc, ok=(OK, MAXIT))
+    return us, list(infos), rc

@@ -714,30 +714,38 @@ __global__ void k_csr_to_dense(int32_t n, const int32_t *__restrict__ rp, const 
     for (int k = rp[i]; k < rp[i + 1]; ++k) D[(int64_t)i * n + col[k]] = val[k];
 }
 
-// In-place Gauss-Jordan inversion of an SPD matrix (no pivoting needed), one
-// workgroup.  Step k: save column k and the scaled row k, then update all
-// other entries.
-__global__ void __launch_bounds__(1024) k_gauss_jordan(int32_t n, double *__restrict__ D) {
-    __shared__ double colk[kDenseMax];
-    __shared__ double rowk[kDenseMax];
+// Gauss-Jordan inversion of an SPD matrix (no pivoting needed), one launch
+// per elimination step k over the whole n x n matrix, reading the previous
+// step's matrix A and writing B (two buffers, so no block overwrites the
+// pivot row or column that another block still reads):
+//   B[k][k] = 1/a_kk,  B[k][j] = a_kj / a_kk,  B[i][k] = -a_ik / a_kk,
+//   B[i][j] = a_ij - a_ik (a_kj / a_kk).
+__global__ void __launch_bounds__(256) k_gj_step(int32_t n, int32_t k, const double *__restrict__ A,
+                                                 double *__restrict__ B) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)n * n) return;
+    const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+    const double p = 1.0 / A[(int64_t)k * n + k];
+    const double rkj = A[(int64_t)k * n + j] * p;
+    double v;
+    if (i == k)
+        v = (j == k) ? p : rkj;
+    else
+        v = (j == k) ? -A[(int64_t)i * n + k] * p : A[e] - A[(int64_t)i * n + k] * rkj;
+    B[e] = v;
+}
+
+static void dense_inverse(ocp_ctx *ctx, int32_t n, double *D) {
+    DevBuf<double> tmp(ctx, (size_t)n * n);
+    double *a = D, *b = tmp.get();
+    const unsigned g = grid_for((int64_t)n * n, 256);
     for (int k = 0; k < n; ++k) {
-        const double p = 1.0 / D[(int64_t)k * n + k];
-        for (int t = threadIdx.x; t < n; t += blockDim.x) {
-            colk[t] = D[(int64_t)t * n + k];
-            rowk[t] = D[(int64_t)k * n + t] * p;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-            const int i = e / n, j = e - i * n;
-            double v;
-            if (i == k)
-                v = (j == k) ? p : rowk[j];
-            else
-                v = (j == k) ? -colk[i] * p : D[e] - colk[i] * rowk[j];
-            D[e] = v;
-        }
-        __syncthreads();
+        k_gj_step<<<g, 256, 0, ctx->stream>>>(n, k, a, b);
+        std::swap(a, b);
     }
+    OCP_LAUNCH_CHECK();
+    if (a != D) OCP_HIP(hipMemcpyAsync(D, a, sizeof(double) * n * n, hipMemcpyDeviceToDevice, ctx->stream));
+    sync(ctx);   // tmp is released on return
 }
 
 __global__ void k_to_float(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
@@ -853,8 +861,8 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
                 L.dense_inv.reset(ctx, (size_t)n * n);
                 fill_zero_bytes(ctx, L.dense_inv.get(), sizeof(double) * (size_t)n * n);
                 k_csr_to_dense<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, L.A_val, L.dense_inv.get());
-                k_gauss_jordan<<<1, 1024, 0, s>>>(n, L.dense_inv.get());
                 OCP_LAUNCH_CHECK();
+                dense_inverse(ctx, n, L.dense_inv.get());
             }
             break;
         }

@@ -6,7 +6,9 @@
 // fixed order and updates them, so an iteration is a chain of kernels with no
 // host round trip.  The host enqueues a few iterations at a time and then
 // reads the flag; kernels enqueued after convergence return immediately.
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "kernels.h"
 #include "system.h"
@@ -247,8 +249,9 @@ const double *system_dinv(ocp_ctx *ctx, ocp_system *sys) {
     return sys->dinv.get();
 }
 
-// One PCG solve in progress: its vectors and launch shapes.  The scalars
-// live in the context (ctx->cg), so a context runs one solve at a time.
+// One PCG solve in progress: its vectors, its device scalars and its
+// reduction partials (its own, so several solves can be enqueued on one
+// stream, as the packed batch does).
 struct SolveState {
     ocp_ctx *ctx = nullptr;
     ocp_system *sys = nullptr;
@@ -257,6 +260,10 @@ struct SolveState {
     const double *dinv = nullptr;
     DevBuf<double> x, r, p, q, z;
     VcWork vw;           // V-cycle work vectors of this solve
+    DevBuf<CgScalars> cgbuf;
+    DevBuf<double> partbuf;   // [4][kRedBlocks]: p.q, r.r / r.z, residual, V-cycle r.z
+    CgScalars *cg = nullptr;
+    double *part = nullptr;
     int mode = OCP_STOP_L2;
     int32_t maxit = 0;
     double rtol = 0.0;
@@ -280,11 +287,18 @@ static void solve_begin(SolveState &S, ocp_ctx *ctx, ocp_system *sys, const ocp_
     S.q.reset(ctx, n);
     S.z.reset(ctx, n);
     S.dinv = h ? nullptr : system_dinv(ctx, sys);
-    if (h) vc_work_alloc(ctx, h, S.vw);
+    S.cgbuf.reset(ctx, 1);
+    S.partbuf.reset(ctx, (size_t)4 * kRedBlocks);
+    S.cg = S.cgbuf.get();
+    S.part = S.partbuf.get();
+    if (h) {
+        vc_work_alloc(ctx, h, S.vw);
+        S.vw.part = S.part + 3 * kRedBlocks;
+    }
     S.mode = (flags & OCP_STOP_PRECOND) ? OCP_STOP_PRECOND : OCP_STOP_L2;
-    CgScalars *cg = ctx->cg;
-    double *part0 = ctx->red_partials;
-    double *part1 = ctx->red_partials + kRedBlocks;
+    CgScalars *cg = S.cg;
+    double *part0 = S.part;
+    double *part1 = S.part + kRedBlocks;
     system_sell(ctx, sys);
     const RowLaunch LV = vec_launch(n);
     ctx->prof_iter = -1;   // the initial preconditioner application
@@ -309,9 +323,9 @@ static void solve_begin(SolveState &S, ocp_ctx *ctx, ocp_system *sys, const ocp_
 static void solve_iterate(SolveState &S, int iters) {
     ocp_ctx *ctx = S.ctx;
     const int32_t n = S.sys->n;
-    CgScalars *cg = ctx->cg;
-    double *part0 = ctx->red_partials;
-    double *part1 = ctx->red_partials + kRedBlocks;
+    CgScalars *cg = S.cg;
+    double *part0 = S.part;
+    double *part1 = S.part + kRedBlocks;
     const Sell &A = system_sell(ctx, S.sys);
     const SellLaunch LS = sell_launch(A.nslices);
     const RowLaunch LV = vec_launch(n);
@@ -346,20 +360,20 @@ static int solve_finish(SolveState &S, double *u, ocp_solve_info *info) {
     ocp_ctx *ctx = S.ctx;
     ocp_system *sys = S.sys;
     const int32_t n = sys->n;
-    double *part2 = ctx->red_partials + 2 * kRedBlocks;
+    double *part2 = S.part + 2 * kRedBlocks;
     const Sell &A = system_sell(ctx, sys);
     const SellLaunch LS = sell_launch(A.nslices);
     OCP_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     k_resid2_sell<<<LS.blocks, kBlock, 0, ctx->stream>>>(n, A.nslices, LS.slices_per_block, A.sp.get(), A.sw.get(),
                                                          A.col.get(), A.val.get(), S.x.get(), S.f, part2);
-    k_fin_store<<<1, kBlock, 0, ctx->stream>>>(LS.blocks, part2, ctx->red_out + 1);
+    k_fin_store<<<1, kBlock, 0, ctx->stream>>>(LS.blocks, part2, part2 + kRedBlocks - 1);
     OCP_LAUNCH_CHECK();
     k_scatter<<<grid_for(sys->nv, 256), 256, 0, ctx->stream>>>(sys->nv, sys->dof_of_vertex.get(), S.x.get(), u);
     OCP_LAUNCH_CHECK();
     CgScalars hs{};
-    read_back(ctx, &hs, ctx->cg, sizeof(hs));
+    read_back(ctx, &hs, S.cg, sizeof(hs));
     double res2 = 0.0;
-    read_back(ctx, &res2, ctx->red_out + 1, sizeof(res2));
+    read_back(ctx, &res2, part2 + kRedBlocks - 1, sizeof(res2));
     float ms = 0.f;
     OCP_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     // every kernel of host iterations 0 .. iter-2 did its full work
@@ -386,7 +400,7 @@ static void solve(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, const d
     CgScalars hs{};
     int chunk = 2;
     for (;;) {
-        read_back(ctx, &hs, ctx->cg, sizeof(hs));
+        read_back(ctx, &hs, S.cg, sizeof(hs));
         if (hs.flag != 0) break;
         solve_iterate(S, chunk);
         if (chunk < 8) chunk *= 2;
@@ -394,9 +408,201 @@ static void solve(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, const d
     *status = solve_finish(S, u, info);
 }
 
+// ------------------------------------------------------------ packed batch
+constexpr int kBatchBranches = 8;   // parallel chains of a packed batch graph
+
+bool small_eligible(const ocp_system *sys, const ocp_hierarchy *h);
+void small_batch(ocp_ctx *ctx, const std::vector<int> &idx, const ocp_system *const *systems,
+                 const ocp_hierarchy *const *hs, const double *const *fs, double *const *us, double rtol,
+                 int32_t maxit, int mode, ocp_solve_info *infos, std::vector<int> &st);
+
+// Number of solves of a batch still running (one thread: m is small).
+__global__ void k_batch_running(int32_t m, CgScalars *const *cgs, int32_t *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int c = 0;
+    for (int i = 0; i < m; ++i) c += cgs[i]->flag == 0;
+    *out = c;
+}
+
+// m independent solves packed into one graph launch per iteration: the first
+// steps are enqueued normally, then one iteration of every solve (and the
+// running count) is captured into a HIP graph that is replayed until all
+// have stopped.  Each solve runs exactly the kernels of pcg_solve on its own
+// vectors and scalars, so its result is the same bits as alone.
+static void solve_batch(ocp_ctx *ctx, int m, const ocp_system *const *systems, const ocp_hierarchy *const *hs,
+                        const double *const *fs, double *const *us, double rtol, int32_t maxit, int32_t flags,
+                        ocp_solve_info *infos, int *status) {
+    // the null stream cannot be captured: run the batch on a private stream
+    // (default priority), ordered after the context's work by a sync
+    struct StreamSwap {
+        ocp_ctx *ctx;
+        hipStream_t user, own = nullptr;
+        explicit StreamSwap(ocp_ctx *c) : ctx(c), user(c->stream) {
+            if (user == nullptr) {
+                OCP_HIP(hipStreamSynchronize(user));
+                OCP_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+                ctx->stream = own;
+            }
+        }
+        ~StreamSwap() {
+            if (own) {
+                (void)hipStreamSynchronize(own);
+                ctx->stream = user;
+                (void)hipStreamDestroy(own);
+            }
+        }
+    } swap(ctx);
+    std::vector<SolveState> S((size_t)m);
+    for (int i = 0; i < m; ++i)
+        solve_begin(S[i], ctx, const_cast<ocp_system *>(systems[i]), hs ? hs[i] : nullptr, fs ? fs[i] : nullptr,
+                    rtol, maxit, flags);
+    std::vector<CgScalars *> hcg((size_t)m);
+    for (int i = 0; i < m; ++i) hcg[i] = S[i].cg;
+    DevBuf<CgScalars *> dcg(ctx, (size_t)m);
+    DevBuf<int32_t> running(ctx, 1);
+    OCP_HIP(hipMemcpyAsync(dcg.get(), hcg.data(), sizeof(CgScalars *) * m, hipMemcpyHostToDevice, ctx->stream));
+    sync(ctx);
+
+    // the solves are independent: each is captured on one of B forked branch
+    // streams, so one replay of the graph holds B parallel chains that the
+    // GPU can run side by side
+    const int B = std::min(m, kBatchBranches);
+    std::vector<hipStream_t> br((size_t)B, nullptr);
+    std::vector<hipEvent_t> ev((size_t)B, nullptr);
+    struct Cleanup {
+        std::vector<hipStream_t> &br;
+        std::vector<hipEvent_t> &ev;
+        ~Cleanup() {
+            for (size_t b = 1; b < br.size(); ++b)
+                if (br[b]) (void)hipStreamDestroy(br[b]);
+            for (auto e : ev)
+                if (e) (void)hipEventDestroy(e);
+        }
+    } cleanup{br, ev};
+    hipStream_t main = ctx->stream;
+    br[0] = main;
+    for (int b = 0; b < B; ++b) {
+        if (b > 0) OCP_HIP(hipStreamCreateWithFlags(&br[b], hipStreamNonBlocking));
+        OCP_HIP(hipEventCreateWithFlags(&ev[b], hipEventDisableTiming));
+    }
+    const bool prof = ctx->profile;
+    ctx->profile = false;   // no event timing inside the captured graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    OCP_HIP(hipStreamBeginCapture(main, hipStreamCaptureModeThreadLocal));
+    try {
+        OCP_HIP(hipEventRecord(ev[0], main));
+        for (int b = 1; b < B; ++b) OCP_HIP(hipStreamWaitEvent(br[b], ev[0], 0));
+        for (int i = 0; i < m; ++i) {
+            ctx->stream = br[i % B];
+            solve_iterate(S[i], 1);
+        }
+        ctx->stream = main;
+        for (int b = 1; b < B; ++b) {
+            OCP_HIP(hipEventRecord(ev[b], br[b]));
+            OCP_HIP(hipStreamWaitEvent(main, ev[b], 0));
+        }
+        k_batch_running<<<1, 64, 0, main>>>(m, dcg.get(), running.get());
+        OCP_LAUNCH_CHECK();
+    } catch (...) {
+        ctx->stream = main;
+        hipGraph_t g2 = nullptr;
+        (void)hipStreamEndCapture(main, &g2);
+        if (g2) (void)hipGraphDestroy(g2);
+        ctx->profile = prof;
+        throw;
+    }
+    ctx->profile = prof;
+    OCP_HIP(hipStreamEndCapture(main, &graph));
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        fail(OCP_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    }
+    int32_t left = m;
+    int chunk = 2, replays = 0;
+    while (left > 0 && replays <= maxit) {
+        for (int c = 0; c < chunk; ++c) OCP_HIP(hipGraphLaunch(exec, ctx->stream));
+        replays += chunk;
+        if (chunk < 8) chunk *= 2;
+        read_back(ctx, &left, running.get(), sizeof(left));
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    std::vector<int> st((size_t)m);
+    for (int i = 0; i < m; ++i) st[i] = solve_finish(S[i], us[i], infos ? &infos[i] : nullptr);
+    int w = OCP_OK;
+    for (int x : st) {
+        if (x == OCP_ERR_BREAKDOWN) w = OCP_ERR_BREAKDOWN;
+        else if (x == OCP_MAXIT && w == OCP_OK) w = OCP_MAXIT;
+    }
+    *status = w;
+}
+
 }  // namespace ocp
 
 using namespace ocp;
+
+extern "C" int pcg_solve_batch(ocp_ctx *ctx, int32_t m, const ocp_system *const *systems,
+                               const ocp_hierarchy *const *hierarchies, const double *const *f, double *const *u,
+                               double rtol, int32_t maxit, int32_t flags, ocp_solve_info *infos) {
+    if (!ctx) return OCP_ERR_INVALID_ARG;
+    int status = OCP_OK;
+    int rc = run_guarded(ctx, [&] {
+        if (m < 1 || m > 4096) fail(OCP_ERR_INVALID_ARG, "m must lie in 1..4096");
+        if (!systems || !u) fail(OCP_ERR_INVALID_ARG, "systems and u must not be NULL");
+        if (!(rtol > 0.0) || !std::isfinite(rtol)) fail(OCP_ERR_INVALID_ARG, "rtol must be positive");
+        if (maxit < 1) fail(OCP_ERR_INVALID_ARG, "maxit must be >= 1");
+        for (int i = 0; i < m; ++i) {
+            if (!systems[i] || !u[i]) fail(OCP_ERR_INVALID_ARG, "a system or u entry is NULL");
+            if (hierarchies && hierarchies[i] && hierarchies[i]->sys != systems[i])
+                fail(OCP_ERR_INVALID_ARG, "hierarchy belongs to another system");
+        }
+        // small problems: one workgroup each in one persistent launch; the
+        // rest: packed into one graph launch per iteration
+        std::vector<int> small, big;
+        for (int i = 0; i < m; ++i) {
+            const ocp_hierarchy *h = hierarchies ? hierarchies[i] : nullptr;
+            ((flags & OCP_BATCH_GRAPH) || !small_eligible(systems[i], h) ? big : small).push_back(i);
+        }
+        std::vector<int> st((size_t)m, OCP_OK);
+        if (!big.empty()) {
+            std::vector<const ocp_system *> bs;
+            std::vector<const ocp_hierarchy *> bh;
+            std::vector<const double *> bf;
+            std::vector<double *> bu;
+            std::vector<ocp_solve_info> bi(big.size());
+            for (int i : big) {
+                bs.push_back(systems[i]);
+                bh.push_back(hierarchies ? hierarchies[i] : nullptr);
+                bf.push_back(f ? f[i] : nullptr);
+                bu.push_back(u[i]);
+            }
+            int bst = OCP_OK;
+            solve_batch(ctx, (int)big.size(), bs.data(), bh.data(), bf.data(), bu.data(), rtol, maxit, flags,
+                        bi.data(), &bst);
+            for (size_t t = 0; t < big.size(); ++t) {
+                st[big[t]] = bi[t].status;
+                if (infos) infos[big[t]] = bi[t];
+            }
+        }
+        if (!small.empty()) {
+            const int mode = (flags & OCP_STOP_PRECOND) ? OCP_STOP_PRECOND : OCP_STOP_L2;
+            small_batch(ctx, small, systems, hierarchies, f, u, rtol, maxit, mode, infos, st);
+        }
+        for (int x : st) {
+            if (x == OCP_ERR_BREAKDOWN) status = OCP_ERR_BREAKDOWN;
+            else if (x == OCP_MAXIT && status == OCP_OK) status = OCP_MAXIT;
+        }
+    });
+    if (rc != OCP_OK) {
+        if (infos)
+            for (int i = 0; i < std::max(0, std::min<int>(m, 4096)); ++i) infos[i].status = rc;
+        return rc;
+    }
+    if (status == OCP_ERR_BREAKDOWN) ctx->last_error = "CG breakdown in at least one solve";
+    return status;
+}
 
 extern "C" int ocp_spmv(ocp_ctx *ctx, const ocp_system *sys, const double *x, double *y) {
     if (!ctx) return OCP_ERR_INVALID_ARG;
@@ -468,7 +674,7 @@ extern "C" int pcg_advance(ocp_solve_handle *hd, int32_t iters) {
         if (iters < 1) fail(OCP_ERR_INVALID_ARG, "iters must be >= 1");
         solve_iterate(hd->S, iters);
         // scalars to the pinned staging buffer, then a marker to poll
-        OCP_HIP(hipMemcpyAsync(ctx->pinned, ctx->cg, sizeof(CgScalars), hipMemcpyDeviceToHost, ctx->stream));
+        OCP_HIP(hipMemcpyAsync(ctx->pinned, hd->S.cg, sizeof(CgScalars), hipMemcpyDeviceToHost, ctx->stream));
         OCP_HIP(hipEventRecord(hd->ev_poll, ctx->stream));
         hd->polled_copy = true;
     });

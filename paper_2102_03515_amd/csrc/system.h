@@ -88,6 +88,7 @@ struct VcWork {
         DevBuf<char> vb, vr, vx, vxp, vx1, vx2;
     };
     std::vector<Lvl> lv;
+    double *part = nullptr;   // partials of the fine-level r.z (null: the context's)
 };
 void vc_work_alloc(ocp_ctx *ctx, const ocp_hierarchy *h, VcWork &w, int k = 1);
 

@@ -235,7 +235,7 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
     const auto &lv = h->levels;
     const int L = (int)lv.size();
     hipStream_t s = ctx->stream;
-    double *part = ctx->red_partials + 3 * kRedBlocks;
+    double *part = W.part ? W.part : ctx->red_partials + 3 * kRedBlocks;
     const Sell &S = system_sell(ctx, h->sys);
     const T *sval = sell_values<T>(h, S);
     const SellLaunch LSL = sell_launch(S.nslices);

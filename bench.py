@@ -55,6 +55,21 @@ def kernel_bytes(kernel: int, n: int, nnz: int, mixed: bool) -> float:
     raise ValueError(kernel)
 
 
+# HBM bytes per launch of the fine-level kernels from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE) of `bench.py --calibrate-copy`, each scaled
+# by what the same counter reads for the 1 GiB elementwise copy of that run.
+# Only kernels measured as they stand are listed (None otherwise).
+MEASURED_TRAFFIC = {
+    # k_cg_spmv_pq_sell at 255^3: FETCH 1,584,305 KiB x 1.99993 + WRITE 129,827 KiB x 0.99998
+    # per full dispatch (profiles/pmc_traffic_cg_spmv_cube256_modes64.md)
+    0: 3377481367,
+}
+
+
+def traffic_bytes(kernel: int):
+    return MEASURED_TRAFFIC.get(kernel)
+
+
 KERNEL_NAMES = {0: "cg_spmv_pq (FP64 CSR SpMV + p.q)", 1: "vc_pre_smooth_1 (level 0)",
                 2: "vc_post_smooth_final_rz (level 0)", 3: "vc_restrict (level 0)",
                 4: "vc_prolong (level 0)", 5: "vc_pre_smooth_2 (level 0)", 6: "vc_post_residual (level 0)"}
@@ -235,6 +250,11 @@ def main():
     ap.add_argument("--no-block", action="store_true", help="skip the 32-target block solve at 127^3")
     ap.add_argument("--no-serve", action="store_true", help="skip the served request stream")
     ap.add_argument("--no-packed", action="store_true", help="skip the packed batch of small solves")
+    ap.add_argument("--skip-main", action="store_true",
+                    help="skip the headline steps (profiling one of the other sections)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain elementwise copy of 1 GiB (reads 1 GiB, writes 1 GiB): the "
+                         "reference dispatch for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this solver is measured per GPU "
@@ -246,83 +266,116 @@ def main():
     import paper_2102_03515_amd as P
     from paper_2102_03515_amd import capi
 
-    wl = WORKLOADS[args.workload]
-    N, rho = wl["N"], wl["rho"]
-    print(f"[bench] workload={args.workload} N={N} rho={rho:.3e} steps={args.steps} warmup={args.warmup}",
-          file=sys.stderr, flush=True)
-    mesh = I.kuhn_mesh(N, jitter=wl["jitter"], seed=wl["seed"])
-    tspec = wl["target"]
-    target = I.make_target(tspec) if tspec != "modes" else None
-    if isinstance(tspec, tuple):
-        target = I.random_sine_modes(tspec[1])
-    dmesh = P.upload_mesh(mesh)
-    del mesh
-    torch.cuda.synchronize()
-    ctx = P.Context()
+    if args.calibrate_copy:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        del x, y
+        print("[bench] calibration copy of 1 GiB done", file=sys.stderr, flush=True)
 
-    def step(precision):
+    def headline():
+        wl = WORKLOADS[args.workload]
+        N, rho = wl["N"], wl["rho"]
+        print(f"[bench] workload={args.workload} N={N} rho={rho:.3e} steps={args.steps} warmup={args.warmup}",
+              file=sys.stderr, flush=True)
+        mesh = I.kuhn_mesh(N, jitter=wl["jitter"], seed=wl["seed"])
+        tspec = wl["target"]
+        target = I.make_target(tspec) if tspec != "modes" else None
+        if isinstance(tspec, tuple):
+            target = I.random_sine_modes(tspec[1])
+        dmesh = P.upload_mesh(mesh)
+        del mesh
+        torch.cuda.synchronize()
+        ctx = P.Context()
+
+        def step(precision):
+            t0 = time.perf_counter()
+            s = P.fe_assemble(ctx, dmesh, rho, target)
+            t1 = time.perf_counter()
+            h = P.amg_setup(ctx, s, precision=precision)
+            t2 = time.perf_counter()
+            u, info, rc = P.pcg_solve(ctx, s, h, rtol=1e-8, maxit=500)
+            t3 = time.perf_counter()
+            if rc != 0:
+                raise RuntimeError(f"solve did not converge: status {rc} {info.as_dict()}")
+            meta = {"n": s.n, "nnz": s.nnz, "levels": h.n_levels, "nnz_P0": int(h.level(0).nnz_P),
+                    "iterations": info.iterations, "true_rel_res": info.true_rel_res,
+                    "assemble_ms": 1e3 * (t1 - t0), "setup_ms": 1e3 * (t2 - t1), "solve_ms": 1e3 * (t3 - t2),
+                    "solve_gpu_ms": info.solve_ms}
+            h.close()
+            s.close()
+            del u
+            return meta
+
+        for w in range(args.warmup):
+            m = step(capi.PREC_MIXED)
+            print(f"[bench] warmup {w}: {json.dumps(m)}", file=sys.stderr, flush=True)
+
+        ctx.profile(True)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s = P.fe_assemble(ctx, dmesh, rho, target)
+        metas = []
+        for k in range(args.steps):
+            metas.append(step(capi.PREC_MIXED))
+            print(f"[bench] step {k}: {json.dumps(metas[-1])}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
         t1 = time.perf_counter()
-        h = P.amg_setup(ctx, s, precision=precision)
-        t2 = time.perf_counter()
-        u, info, rc = P.pcg_solve(ctx, s, h, rtol=1e-8, maxit=500)
-        t3 = time.perf_counter()
-        if rc != 0:
-            raise RuntimeError(f"solve did not converge: status {rc} {info.as_dict()}")
-        meta = {"n": s.n, "nnz": s.nnz, "levels": h.n_levels, "nnz_P0": int(h.level(0).nnz_P),
-                "iterations": info.iterations, "true_rel_res": info.true_rel_res,
-                "assemble_ms": 1e3 * (t1 - t0), "setup_ms": 1e3 * (t2 - t1), "solve_ms": 1e3 * (t3 - t2),
-                "solve_gpu_ms": info.solve_ms}
-        h.close()
-        s.close()
-        del u
-        return meta
+        n, nnz = metas[0]["n"], metas[0]["nnz"]
+        ms_per_step = 1e3 * (t1 - t0) / args.steps
+        value = n * args.steps / (t1 - t0)
 
-    for w in range(args.warmup):
-        m = step(capi.PREC_MIXED)
-        print(f"[bench] warmup {w}: {json.dumps(m)}", file=sys.stderr, flush=True)
+        # dominant kernel of the timed region, live event timings
+        timings = {k: ctx.kernel_timing(k) for k in range(7)}
+        dom = max(MATRIX_KERNELS, key=lambda k: timings[k][1])
+        launches, tot_ms = timings[dom]
+        avg_ms = tot_ms / max(launches, 1)
+        alg = kernel_bytes(dom, n, nnz, mixed=(dom != 0))
+        achieved = alg / (avg_ms * 1e-3) / 1e9
+        kernels = {KERNEL_NAMES[k]: {"launches": timings[k][0],
+                                     "avg_us": 1e3 * timings[k][1] / max(timings[k][0], 1)}
+                   for k in range(7)}
+        for k in MATRIX_KERNELS:
+            b = kernel_bytes(k, n, nnz, mixed=(k != 0))
+            t = timings[k][1] / max(timings[k][0], 1)
+            kernels[KERNEL_NAMES[k]]["alg_bytes"] = b
+            kernels[KERNEL_NAMES[k]]["alg_GBps"] = b / (t * 1e-3) / 1e9 if t > 0 else None
 
-    ctx.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    metas = []
-    for k in range(args.steps):
-        metas.append(step(capi.PREC_MIXED))
-        print(f"[bench] step {k}: {json.dumps(metas[-1])}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    n, nnz = metas[0]["n"], metas[0]["nnz"]
-    ms_per_step = 1e3 * (t1 - t0) / args.steps
-    value = n * args.steps / (t1 - t0)
+        fp64 = None
+        if not args.no_fp64:
+            ctx.profile(False)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            m64 = step(capi.PREC_FP64)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            fp64 = {"dof_per_s": n / (tb - ta), "iterations": m64["iterations"], "solve_ms": m64["solve_ms"],
+                    "setup_ms": m64["setup_ms"], "true_rel_res": m64["true_rel_res"]}
+            print(f"[bench] fp64 step: {json.dumps(m64)}", file=sys.stderr, flush=True)
+        solve_ms = sum(m["solve_ms"] for m in metas) / len(metas)
+        return {
+            "value": value, "ms_per_step": ms_per_step,
+            "config": {"workload": args.workload, "cubes_per_edge": N, "unknowns": n, "nnz": nnz,
+                       "rho": rho, "rtol": 1e-8, "stop": "||r||2/||f||2", "precision": "mixed",
+                       "parallelism": "single GPU"},
+            "iterations": metas[-1]["iterations"],
+            "true_rel_res": metas[-1]["true_rel_res"],
+            "levels": metas[-1]["levels"],
+            "phase_ms": {"assemble": sum(m["assemble_ms"] for m in metas) / len(metas),
+                         "setup": sum(m["setup_ms"] for m in metas) / len(metas),
+                         "solve": solve_ms},
+            "solve_only_dof_per_s": n / (solve_ms * 1e-3),
+            "fp64": fp64,
+            "kernels": kernels,
+            "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": traffic_bytes(dom), "launches": launches, "avg_us": 1e3 * avg_ms},
+        }
 
-    # dominant kernel of the timed region, live event timings
-    timings = {k: ctx.kernel_timing(k) for k in range(7)}
-    dom = max(MATRIX_KERNELS, key=lambda k: timings[k][1])
-    launches, tot_ms = timings[dom]
-    avg_ms = tot_ms / max(launches, 1)
-    alg = kernel_bytes(dom, n, nnz, mixed=(dom != 0))
-    achieved = alg / (avg_ms * 1e-3) / 1e9
-    kernels = {KERNEL_NAMES[k]: {"launches": timings[k][0],
-                                 "avg_us": 1e3 * timings[k][1] / max(timings[k][0], 1)}
-               for k in range(7)}
-    for k in MATRIX_KERNELS:
-        b = kernel_bytes(k, n, nnz, mixed=(k != 0))
-        t = timings[k][1] / max(timings[k][0], 1)
-        kernels[KERNEL_NAMES[k]]["alg_bytes"] = b
-        kernels[KERNEL_NAMES[k]]["alg_GBps"] = b / (t * 1e-3) / 1e9 if t > 0 else None
-
-    fp64 = None
-    if not args.no_fp64:
-        ctx.profile(False)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        m64 = step(capi.PREC_FP64)
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        fp64 = {"dof_per_s": n / (tb - ta), "iterations": m64["iterations"], "solve_ms": m64["solve_ms"],
-                "setup_ms": m64["setup_ms"], "true_rel_res": m64["true_rel_res"]}
-        print(f"[bench] fp64 step: {json.dumps(m64)}", file=sys.stderr, flush=True)
+    head = {"value": None, "ms_per_step": None, "config": {"workload": args.workload}} if args.skip_main \
+        else headline()
+    wl = WORKLOADS[args.workload]
+    tspec = wl["target"]
 
     block = None
     if not args.no_block:
@@ -346,40 +399,22 @@ def main():
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         cpu = cpu_baseline(tspec[1])
 
-    solve_ms = sum(m["solve_ms"] for m in metas) / len(metas)
     out = {
         "metric": "AMG-PCG DOF/s to 1e-8 rel. residual (assemble + AMG setup + PCG solve)",
-        "value": value,
+        "value": head["value"],
         "unit": "DOF/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64 CG / f32 V-cycle",
         "data": "synthetic (seeded Kuhn mesh and sine-mode target)",
-        "config": {"workload": args.workload, "cubes_per_edge": N, "unknowns": n, "nnz": nnz,
-                   "rho": rho, "rtol": 1e-8, "stop": "||r||2/||f||2", "precision": "mixed",
-                   "parallelism": "single GPU"},
-        "iterations": metas[-1]["iterations"],
-        "true_rel_res": metas[-1]["true_rel_res"],
-        "levels": metas[-1]["levels"],
-        "phase_ms": {"assemble": sum(m["assemble_ms"] for m in metas) / len(metas),
-                     "setup": sum(m["setup_ms"] for m in metas) / len(metas),
-                     "solve": solve_ms},
-        "solve_only_dof_per_s": n / (solve_ms * 1e-3),
-        "fp64": fp64,
-        "block32": block,
-        "packed_small": packed,
-        "serve": served,
-        "kernels": kernels,
-        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "launches": launches, "avg_us": 1e3 * avg_ms},
-        "cpu_baseline": cpu,
     }
+    out.update({k: v for k, v in head.items() if k not in ("value", "ms_per_step")})
+    out.update({"block32": block, "packed_small": packed, "serve": served, "cpu_baseline": cpu})
     print(json.dumps(out), flush=True)
 
 

@@ -69,12 +69,31 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
     return s;
 }
 
+// sum_k val[k] xf(col[k]) over row i, in entry order; the column indices,
+// values and gathers of 8 entries are issued before any is used, so a
+// thread keeps 8 gathers in flight (one workgroup per problem has few waves
+// to hide memory latency with).
 template <typename VT, typename XF>
 __device__ __forceinline__ VT csr_row(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                       const VT *__restrict__ val, int i, XF xf) {
+    constexpr int U = 8;
     VT s = VT(0);
+    int k = rp[i];
     const int e = rp[i + 1];
-    for (int k = rp[i]; k < e; ++k) s += val[k] * xf(col[k]);
+    for (; k + U <= e; k += U) {
+        int c[U];
+        VT v[U], g[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = col[k + u];
+            v[u] = val[k + u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) g[u] = xf(c[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += v[u] * g[u];
+    }
+    for (; k < e; ++k) s += val[k] * xf(col[k]);
     return s;
 }
 }  // namespace dev

@@ -635,7 +635,27 @@ __global__ void __launch_bounds__(kAsmBlock) k_row_loads(int32_t n, const int32_
     if (i >= n) return;
     const int vi = vertex_of_dof[i];
     double fi = 0.0;
-    for (int q = inc_ptr[vi]; q < inc_ptr[vi + 1]; ++q) {
+    int q = inc_ptr[vi];
+    const int qe = inc_ptr[vi + 1];
+    // eight incident tets at a time: their ids, vertex lists and element
+    // loads are all requested before any is used (the sum keeps list order)
+    constexpr int U = 8;
+    for (; q + U <= qe; q += U) {
+        int e[U];
+        int4 tv[U];
+        double4 fv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) e[u] = inc[q + u];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            tv[u] = tets[e[u]];
+            fv[u] = fe[e[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            fi += (tv[u].x == vi) ? fv[u].x : (tv[u].y == vi) ? fv[u].y : (tv[u].z == vi) ? fv[u].z : fv[u].w;
+    }
+    for (; q < qe; ++q) {
         const int e = inc[q];
         const int4 tv = tets[e];
         const double4 fv = fe[e];

@@ -229,7 +229,12 @@ typedef struct {
 
 /* Preconditioned CG from u = 0 (Section 5: PCG, one V(1,1)-cycle per
  * iteration as preconditioner; tolerance 1e-8 in the paper).
- *   h      hierarchy from amg_setup, or NULL for Jacobi preconditioning
+ *   h      hierarchy from amg_setup, or NULL for Jacobi preconditioning.  It may
+ *          belong to another system on the same mesh with the same pattern
+ *          (another rho): the V-cycle is then the one built for that
+ *          system, still a fixed SPD preconditioner, while CG and the stop
+ *          test use this system (the serving loop shares hierarchies across
+ *          nearby rho this way)
  *   f      device [n_dofs] right-hand side, or NULL for the system's f
  *   u      device [n_vertices] output, caller-owned; Dirichlet entries set 0
  *   rtol   > 0;  maxit >= 1;  flags: OCP_STOP_L2 or OCP_STOP_PRECOND

@@ -1123,7 +1123,7 @@ extern "C" int pcg_solve_multi(ocp_ctx *ctx, const ocp_system *sys, const ocp_hi
         if (k < 1 || k > kMaxCols) fail(OCP_ERR_INVALID_ARG, "k must lie in 1..64");
         if (!(rtol > 0.0) || !std::isfinite(rtol)) fail(OCP_ERR_INVALID_ARG, "rtol must be positive");
         if (maxit < 1) fail(OCP_ERR_INVALID_ARG, "maxit must be >= 1");
-        if (h && h->sys != sys) fail(OCP_ERR_INVALID_ARG, "hierarchy belongs to another system");
+        if (h && !hierarchy_fits(h, sys)) fail(OCP_ERR_INVALID_ARG, "hierarchy is for a system on another mesh or pattern");
         solve_multi(ctx, const_cast<ocp_system *>(sys), h, k, F, U, rtol, maxit, flags, infos, &status);
     });
     if (rc != OCP_OK) {

@@ -232,6 +232,13 @@ __global__ void k_diag_inv(int32_t n, const int32_t *__restrict__ rp, const int3
 }
 
 // --------------------------------------------------------------- host side
+bool hierarchy_fits(const ocp_hierarchy *h, const ocp_system *sys) {
+    const ocp_system *o = h->sys;
+    if (o == sys) return true;
+    return o && sys && o->nv == sys->nv && o->n == sys->n && o->nt == sys->nt && o->nnz == sys->nnz &&
+           o->tets_ref == sys->tets_ref;
+}
+
 const Sell &system_sell(ocp_ctx *ctx, const ocp_system *csys) {
     ocp_system *sys = const_cast<ocp_system *>(csys);
     if (!sys->sell.col.get())
@@ -555,8 +562,8 @@ extern "C" int pcg_solve_batch(ocp_ctx *ctx, int32_t m, const ocp_system *const 
         if (maxit < 1) fail(OCP_ERR_INVALID_ARG, "maxit must be >= 1");
         for (int i = 0; i < m; ++i) {
             if (!systems[i] || !u[i]) fail(OCP_ERR_INVALID_ARG, "a system or u entry is NULL");
-            if (hierarchies && hierarchies[i] && hierarchies[i]->sys != systems[i])
-                fail(OCP_ERR_INVALID_ARG, "hierarchy belongs to another system");
+            if (hierarchies && hierarchies[i] && !hierarchy_fits(hierarchies[i], systems[i]))
+                fail(OCP_ERR_INVALID_ARG, "hierarchy is for a system on another mesh or pattern");
         }
         // small problems: one workgroup each in one persistent launch; the
         // rest: packed into one graph launch per iteration
@@ -624,7 +631,7 @@ extern "C" int pcg_solve(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarch
         if (!sys || !u) fail(OCP_ERR_INVALID_ARG, "system and u must not be NULL");
         if (!(rtol > 0.0) || !std::isfinite(rtol)) fail(OCP_ERR_INVALID_ARG, "rtol must be positive");
         if (maxit < 1) fail(OCP_ERR_INVALID_ARG, "maxit must be >= 1");
-        if (h && h->sys != sys) fail(OCP_ERR_INVALID_ARG, "hierarchy belongs to another system");
+        if (h && !hierarchy_fits(h, sys)) fail(OCP_ERR_INVALID_ARG, "hierarchy is for a system on another mesh or pattern");
         solve(ctx, const_cast<ocp_system *>(sys), h, f, u, rtol, maxit, flags, info, &status);
     });
     if (rc != OCP_OK) {
@@ -651,7 +658,7 @@ extern "C" int pcg_begin(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarch
         if (!sys) fail(OCP_ERR_INVALID_ARG, "system must not be NULL");
         if (!(rtol > 0.0) || !std::isfinite(rtol)) fail(OCP_ERR_INVALID_ARG, "rtol must be positive");
         if (maxit < 1) fail(OCP_ERR_INVALID_ARG, "maxit must be >= 1");
-        if (h && h->sys != sys) fail(OCP_ERR_INVALID_ARG, "hierarchy belongs to another system");
+        if (h && !hierarchy_fits(h, sys)) fail(OCP_ERR_INVALID_ARG, "hierarchy is for a system on another mesh or pattern");
         if (ctx->active_solve) fail(OCP_ERR_INVALID_ARG, "the context already runs a solve (one per context)");
         auto *hd = new ocp_solve_handle();
         try {

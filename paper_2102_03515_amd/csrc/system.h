@@ -100,6 +100,10 @@ void vcycle_enqueue(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r, doubl
 int level_lanes(int64_t nnz, int64_t rows);
 // Build 1/a_ii of the system if missing.
 const double *system_dinv(ocp_ctx *ctx, ocp_system *sys);
+// A hierarchy may precondition its own system or any system on the same
+// mesh with the same sparsity pattern (another rho): the V-cycle then
+// applies the operator built for the hierarchy's system.
+bool hierarchy_fits(const ocp_hierarchy *h, const ocp_system *sys);
 // Build the sliced-ELL copy of the system's matrix if missing.
 const Sell &system_sell(ocp_ctx *ctx, const ocp_system *sys);
 }  // namespace ocp

@@ -4,9 +4,16 @@ sizes and values of rho, with continuous batching on one GPU.
 Each request (N, rho, target) asks for the discrete solution of
 (rho K + M) u = f on the N^3-cube Kuhn mesh, f the load vector of its target.
 The server keeps on the device, per mesh size N, the mesh and one system
-assembled with its K and M values; per (N, rho, precision) a system derived
-from them (A = rho K + M, no re-assembly) and its AMG hierarchy, in an LRU
-cache.  Requests are admitted as solve slots free up and as the estimated
+assembled with its K and M values, from which every request's system is
+derived (A = rho K + M, no re-assembly).  AMG hierarchies are cached in an
+LRU per (N, rho key, precision).  The rho key is rho itself for rho = h^2
+(the paper's choice, shared by many requests) and, with `rho_bucket`, the
+centre 10^(b w) of the bucket of width w decades that holds log10(rho)
+otherwise: the hierarchy is built once at that centre and preconditions
+every request of the bucket (CG and the stop test use the request's exact
+system; the preconditioner is a fixed SPD operator either way).  Because the
+key does not depend on which request came first, a result does not depend
+on the mix it was served in.  rho_bucket=None keys hierarchies by exact rho.  Requests are admitted as solve slots free up and as the estimated
 HBM footprint of what they need fits the budget (idle cache entries are
 evicted first); every slot runs its solves on its own stream, so the work of
 requests that arrived while others were on the GPU overlaps on the device.
@@ -50,7 +57,7 @@ def footprint(N: int, precision: int) -> Dict[str, int]:
     hier = 8 * n + (vs + 4) * nnz + 40 * n * (1 + vs // 4) + 2 * (12 * nnz) // 10
     entry = pattern + 8 * nnz + sell + hier
     solve = 5 * 8 * n + 8 * nv + 8 * n + 6 * vs * n
-    return {"mesh": mesh, "base": base, "entry": entry, "solve": solve}
+    return {"mesh": mesh, "base": base, "entry": entry, "hier": hier, "solve": solve}
 
 
 @dataclass
@@ -88,13 +95,15 @@ class Server:
     """Continuous-batching solve server on the current GPU."""
 
     def __init__(self, slots: int = 8, precision: int = capi.PREC_MIXED, rtol: float = 1e-8, maxit: int = 500,
-                 hbm_budget: Optional[int] = None, keep_solutions: bool = False, amg_kw: Optional[dict] = None):
+                 hbm_budget: Optional[int] = None, keep_solutions: bool = False, amg_kw: Optional[dict] = None,
+                 rho_bucket: Optional[float] = 0.25):
         import torch
         self.torch = torch
         self.slots = slots
         self.precision = precision
         self.rtol, self.maxit = rtol, maxit
         self.keep = keep_solutions
+        self.rho_bucket = rho_bucket
         self.amg_kw = dict(amg_kw or {})
         if hbm_budget is None:
             free, _total = torch.cuda.mem_get_info()
@@ -155,16 +164,28 @@ class Server:
                     e.system.close()
         return self.reserved + need <= self.budget
 
+    def rho_key(self, N: int, rho: float) -> float:
+        """rho at which the hierarchy serving (N, rho) is built."""
+        if self.rho_bucket is None or rho == 1.0 / (N * N):
+            return rho
+        import math
+        b = round(math.log10(rho) / self.rho_bucket)
+        return 10.0 ** (b * self.rho_bucket)
+
     def _admit(self, req) -> Tuple[_Entry, bool, int]:
         """Reserve what the request needs (blocking until it fits); returns
         the cache entry (possibly still being built), whether it was a hit,
-        and the bytes reserved for the solve itself."""
+        and the bytes reserved for the solve itself (its vectors, and its own
+        derived system when the hierarchy was built at another rho)."""
         fp = footprint(req.N, self.precision)
-        key = (req.N, req.rho, self.precision)
+        rk = self.rho_key(req.N, req.rho)
+        key = (req.N, rk, self.precision)
+        own = rk != req.rho
+        solve_need = fp["solve"] + (fp["entry"] - fp["hier"] if own else 0)
         with self.lock:
             while True:
                 e = self.entries.get(key)
-                need = fp["solve"]
+                need = solve_need
                 if e is None:
                     need += fp["entry"]
                 if req.N not in self.base_reserved:
@@ -187,10 +208,10 @@ class Server:
                 self.base_reserved.add(req.N)
                 self.reserved += fp["base"] + fp["mesh"]   # kept for the server's lifetime
             self.reserved += e.bytes if not hit else 0
-            self.reserved += fp["solve"]
+            self.reserved += solve_need
             self.running += 1
             e.users += 1
-            return e, hit, fp["solve"]
+            return e, hit, solve_need
 
     def _release(self, e: _Entry, solve_bytes: int):
         with self.lock:
@@ -217,7 +238,7 @@ class Server:
     def _build(self, e: _Entry, req, ctx):
         try:
             base = self._mesh_and_base(req.N, ctx)
-            s = capi.fe_derive(ctx, base, req.rho)
+            s = capi.fe_derive(ctx, base, self.rho_key(req.N, req.rho))
             h = capi.amg_setup(ctx, s, precision=self.precision, **self.amg_kw)
             e.system, e.hierarchy = s, h
         except BaseException as exc:   # recorded for the waiting requests
@@ -237,10 +258,17 @@ class Server:
             e.ready.wait()
             if e.error is not None:
                 raise e.error
+            own = None
             with torch.cuda.stream(self.streams[slot]):
-                f = e.system.load(I.random_sine_modes(req.target_seed), ctx=ctx)
-                u, info, rc = capi.pcg_solve(ctx, e.system, e.hierarchy, f=f, rtol=self.rtol, maxit=self.maxit)
-            res = Result(rid=req.rid, N=req.N, rho=req.rho, n=e.system.n, t_arrival=req.t_arrival,
+                if self.rho_key(req.N, req.rho) != req.rho:
+                    own = capi.fe_derive(ctx, self.bases[req.N], req.rho)
+                system = own if own is not None else e.system
+                n_sys = system.n
+                f = system.load(I.random_sine_modes(req.target_seed), ctx=ctx)
+                u, info, rc = capi.pcg_solve(ctx, system, e.hierarchy, f=f, rtol=self.rtol, maxit=self.maxit)
+                if own is not None:
+                    own.close()
+            res = Result(rid=req.rid, N=req.N, rho=req.rho, n=n_sys, t_arrival=req.t_arrival,
                          t_start=t_start, t_done=time.perf_counter(), iterations=info.iterations,
                          true_rel_res=info.true_rel_res, status=rc, cache_hit=hit, slot=slot,
                          u=u if self.keep else None)

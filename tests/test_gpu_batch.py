@@ -98,7 +98,8 @@ def test_batch_on_a_private_stream_and_errors(P):
     for graph in (False, True):
         us, infos, rc = P.pcg_solve_batch(ctx, [s, s], [h, h], None, rtol=1e-9, graph=graph)
         assert rc == 0 and torch.equal(us[0], us[1])
-    other = P.fe_assemble(ctx, dm, 1.0, I.single_sine())
+    dm5 = P.upload_mesh(I.kuhn_mesh(5))
+    other = P.fe_assemble(ctx, dm5, 1.0, I.single_sine())   # another mesh: the hierarchy does not fit
     with pytest.raises(P.OcpError) as ei:
         P.pcg_solve_batch(ctx, [s, other], [h, h], None)
     assert ei.value.code == P.capi.ERR_INVALID_ARG

@@ -95,6 +95,27 @@ def test_fe_derive_matches_oracle_assembly(P):
         P.fe_derive(ctx, d, 1.0)     # a derived system keeps no K and M
 
 
+def test_hierarchy_of_a_nearby_rho_preconditions(P):
+    print("[compatible hierarchy] cube10 jitter: hierarchy at rho 1e-3 for rho 1.5e-3", flush=True)
+    ctx = P.Context()
+    mesh = I.kuhn_mesh(10, jitter=0.15, seed=55)
+    dm = P.upload_mesh(mesh)
+    base = P.fe_assemble(ctx, dm, 1e-3, I.single_sine(), P.capi.KEEP_KM)
+    s1 = P.fe_derive(ctx, base, 1e-3)
+    s2 = P.fe_derive(ctx, base, 1.5e-3)
+    h1 = P.amg_setup(ctx, s1, coarse_max=32)
+    target = I.random_sine_modes(12)
+    u, info, rc = P.pcg_solve(ctx, s2, h1, f=s2.load(target), rtol=1e-12)
+    assert rc == 0 and info.true_rel_res <= 1.0001e-11, info.as_dict()
+    x, o, _, _ = O.solve(mesh, 1.5e-3, target, rtol=1e-14)
+    assert _rel(u.cpu().numpy(), O.to_vertices(o, x, mesh.n_vertices)) < 1e-9
+    dm8 = P.upload_mesh(I.kuhn_mesh(8))
+    s3 = P.fe_assemble(ctx, dm8, 1e-3, I.single_sine())
+    with pytest.raises(P.OcpError) as ei:
+        P.pcg_solve(ctx, s3, h1)
+    assert ei.value.code == P.capi.ERR_INVALID_ARG
+
+
 def _requests():
     reqs = []
     specs = [(8, None), (10, 1e-3), (12, None), (8, 1e-5), (10, None), (12, 1e-3), (8, None), (10, 1e-3),
@@ -137,11 +158,12 @@ def test_server_admission_under_a_small_budget(P):
     fp = serve.footprint(10, P.capi.PREC_MIXED)
     budget = fp["base"] + fp["mesh"] + int(1.5 * (fp["entry"] + fp["solve"]))
     small = serve.Server(slots=3, precision=P.capi.PREC_MIXED, hbm_budget=budget, keep_solutions=True,
-                         amg_kw={"coarse_max": 32})
+                         amg_kw={"coarse_max": 32}, rho_bucket=None)
     res, _ = small.run(reqs, realtime=False)
     st = dict(small.stats)
     small.close()
-    big = serve.Server(slots=3, precision=P.capi.PREC_MIXED, keep_solutions=True, amg_kw={"coarse_max": 32})
+    big = serve.Server(slots=3, precision=P.capi.PREC_MIXED, keep_solutions=True, amg_kw={"coarse_max": 32},
+                       rho_bucket=None)
     ref, _ = big.run(reqs, realtime=False)
     big.close()
     assert st["evictions"] >= 4 and st["admission_waits"] >= 1, st

@@ -60,7 +60,25 @@ __global__ void k_level_diag(int32_t n, const int32_t *__restrict__ rp, const in
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double d = 0.0, s = 0.0;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    int k = rp[i];
+    const int e = rp[i + 1];
+    // eight entries' loads in flight before any is used (same summation order)
+    constexpr int U = 8;
+    for (; k + U <= e; k += U) {
+        double v[U];
+        int c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            v[u] = val[k + u];
+            c[u] = col[k + u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s += fabs(v[u]);
+            if (c[u] == i) d = v[u];
+        }
+    }
+    for (; k < e; ++k) {
         const double v = val[k];
         s += fabs(v);
         if (col[k] == i) d = v;

@@ -34,10 +34,29 @@ __global__ void k_sell_fill(int32_t n, int64_t nslices, const int32_t *__restric
     const int b = row < n ? rp[row] : 0;
     const int len = row < n ? rp[row + 1] - b : 0;
     const int64_t base = sp[s] + lane;
-    for (int j = 0; j < sw[s]; ++j) {
-        const bool in = j < len;
-        if (scol) scol[base + (int64_t)j * kSellC] = in ? col[b + j] : (row < n ? row : 0);
-        sval[base + (int64_t)j * kSellC] = in ? val[b + j] : VT(0);
+    const int w = sw[s];
+    // eight entries of the row are read before they are written (the reads
+    // of a lane are scattered across rows; the writes of a wavefront are
+    // consecutive)
+    constexpr int U = 8;
+    for (int j0 = 0; j0 < w; j0 += U) {
+        int c[U];
+        VT v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u;
+            const bool in = j < len;
+            c[u] = (in && scol) ? col[b + j] : (row < n ? row : 0);
+            v[u] = in ? val[b + j] : VT(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u;
+            if (j < w) {
+                if (scol) scol[base + (int64_t)j * kSellC] = c[u];
+                sval[base + (int64_t)j * kSellC] = v[u];
+            }
+        }
     }
 }
 

@@ -195,7 +195,7 @@ def packed_bench(P, capi, m: int = 32, N: int = 32, reps: int = 3):
     return out
 
 
-def serve_bench(P, capi, n_requests: int = 400, rate: float = 200.0, slots: int = 8):
+def serve_bench(P, capi, n_requests: int = 400, rate: float = 200.0, slots: int = 16, rho_bucket: float = 0.5):
     """Poisson stream of solve requests (mean `rate` per second, seed 3000):
     N uniform in {32, 48, 64, 96, 128, 160}, rho = h^2 with probability 1/2
     else 10^U(-8,-2), a sine-mode target per request; each solved to 1e-8.
@@ -205,11 +205,12 @@ def serve_bench(P, capi, n_requests: int = 400, rate: float = 200.0, slots: int 
     import ocp_inputs as I
     from paper_2102_03515_amd import serve
     reqs = I.serving_requests(n_requests, rate=rate, seed=3000)
-    srv = serve.Server(slots=slots, precision=capi.PREC_MIXED)
+    srv = serve.Server(slots=slots, precision=capi.PREC_MIXED, rho_bucket=rho_bucket)
     t0 = time.perf_counter()
     srv.warm(I.SERVE_SIZES)
     warm_s = time.perf_counter() - t0
     out = {"workload": f"serve_poisson{int(rate)}", "requests": n_requests, "rate_per_s": rate, "slots": slots,
+           "rho_bucket_decades": rho_bucket,
            "sizes": list(I.SERVE_SIZES), "startup_s": warm_s}
     for name, prec in (("mixed", capi.PREC_MIXED), ("fp64", capi.PREC_FP64)):
         srv.precision = prec

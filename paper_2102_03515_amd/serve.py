@@ -94,9 +94,9 @@ class _Entry:
 class Server:
     """Continuous-batching solve server on the current GPU."""
 
-    def __init__(self, slots: int = 8, precision: int = capi.PREC_MIXED, rtol: float = 1e-8, maxit: int = 500,
+    def __init__(self, slots: int = 16, precision: int = capi.PREC_MIXED, rtol: float = 1e-8, maxit: int = 500,
                  hbm_budget: Optional[int] = None, keep_solutions: bool = False, amg_kw: Optional[dict] = None,
-                 rho_bucket: Optional[float] = 0.25):
+                 rho_bucket: Optional[float] = 0.5):
         import torch
         self.torch = torch
         self.slots = slots
@@ -106,8 +106,11 @@ class Server:
         self.rho_bucket = rho_bucket
         self.amg_kw = dict(amg_kw or {})
         if hbm_budget is None:
+            # free device memory plus what torch's caching allocator holds
+            # without using it (the library allocates through that cache)
             free, _total = torch.cuda.mem_get_info()
-            hbm_budget = int(0.8 * free)
+            cached = torch.cuda.memory_reserved() - torch.cuda.memory_allocated()
+            hbm_budget = int(0.8 * (free + cached))
         self.budget = hbm_budget
         self.lock = threading.Condition()
         self.meshes: Dict[int, Tuple[object, object]] = {}        # N -> (host mesh, device mesh)
@@ -147,12 +150,14 @@ class Server:
             raise RuntimeError(f"building the N={N} mesh and K/M system failed")
         return self.bases[N]
 
-    def _evict_idle(self, need: int) -> bool:
-        """Drop idle cache entries, oldest first, until `need` more bytes fit
-        (called with the lock held)."""
+    def _evict_idle(self, need: int, protect) -> bool:
+        """Drop idle cache entries other than `protect`, oldest first, until
+        `need` more bytes fit (called with the lock held)."""
         for key in list(self.entries.keys()):
             if self.reserved + need <= self.budget:
                 break
+            if key == protect:
+                continue
             e = self.entries[key]
             if e.users == 0 and e.ready.is_set():
                 del self.entries[key]
@@ -190,7 +195,8 @@ class Server:
                     need += fp["entry"]
                 if req.N not in self.base_reserved:
                     need += fp["base"] + fp["mesh"]
-                if self.reserved + need <= self.budget or self._evict_idle(need):
+                # the entry this request uses is never the one evicted for it
+                if self.reserved + need <= self.budget or self._evict_idle(need, key):
                     break
                 if self.running == 0:
                     raise MemoryError(f"request N={req.N} needs {need} bytes, budget {self.budget}")

@@ -330,3 +330,30 @@ def test_spmv_ragged_sizes(P, ctx):
         y = s.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
         bound = 32 * 2.2e-16 * np.abs(o.val).max() * np.abs(x).max()
         assert np.abs(y - O.spmv(o, x)).max() <= bound
+
+
+def test_iterations_robust_in_h_and_rho(P, ctx):
+    """The paper's claim for the solver: iteration counts that do not grow
+    with 1/h (at rho = h^2) and stay bounded over the range of rho (Section 5,
+    Table 4).  With this build's smoothed aggregation the counts at 1e-8 stay
+    within a narrow band."""
+    print("[robustness] N 16..96 at rho = h^2; rho 1e-8..1 at N = 48", flush=True)
+    its_h = []
+    for N in (16, 32, 64, 96):
+        mesh = I.kuhn_mesh(N)
+        s, _ = _gpu_system(P, ctx, mesh, 1.0 / N ** 2, I.random_sine_modes(1000))
+        h = P.amg_setup(ctx, s, precision=P.capi.PREC_MIXED)
+        _, info, rc = P.pcg_solve(ctx, s, h, rtol=1e-8)
+        assert rc == 0 and info.true_rel_res <= 1.0001e-8
+        its_h.append(info.iterations)
+    its_r = []
+    mesh = I.kuhn_mesh(48, jitter=0.15, seed=5)
+    for rho in (1e-8, 1e-6, 1e-4, 1e-2, 1.0):
+        s, _ = _gpu_system(P, ctx, mesh, rho, I.box_indicator())
+        h = P.amg_setup(ctx, s, precision=P.capi.PREC_MIXED)
+        _, info, rc = P.pcg_solve(ctx, s, h, rtol=1e-8)
+        assert rc == 0 and info.true_rel_res <= 1.0001e-8
+        its_r.append(info.iterations)
+    print(f"    iterations vs N (rho=h^2): {its_h}; vs rho at N=48: {its_r}")
+    assert max(its_h) <= 12 and max(its_h) - min(its_h) <= 4
+    assert max(its_r) <= 40

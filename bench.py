@@ -223,21 +223,32 @@ def serve_bench(P, capi, n_requests: int = 400, rate: float = 200.0, slots: int 
     return out
 
 
-def cpu_baseline(target_seed: int, N_sample: int = 64):
-    """The oracle (own assembly + Jacobi-PCG to 1e-8) on a smaller mesh of
-    the same family: N_sample^3 cubes, rho = h^2, the same 64 modes."""
+def cpu_baseline(target_seed: int, N_sample: int = 64, N_single: int = 32):
+    """The oracle (own assembly + Jacobi-PCG to 1e-8) on smaller meshes of
+    the same family: N_sample^3 cubes on all host threads and N_single^3
+    cubes on one thread, rho = h^2, the same 64 modes."""
     import ocp_inputs as I
     import oracle as O
-    mesh = I.kuhn_mesh(N_sample)
-    tgt = I.random_sine_modes(target_seed)
-    rho = 1.0 / N_sample ** 2
-    t0 = time.perf_counter()
-    s = O.assemble(mesh, rho, tgt)
-    x, it, rr = O.pcg(s, rtol=1e-8, maxit=100000)
-    dt = time.perf_counter() - t0
-    return {"value": s.n / dt, "unit": "DOF/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"Kuhn mesh {N_sample}^3 cubes ({s.n} unknowns), rho=h^2, the same 64 sine modes; "
-                      f"oracle assembly + Jacobi-PCG to 1e-8 ({it} iterations) in {dt:.2f} s"}
+
+    def run(N):
+        mesh = I.kuhn_mesh(N)
+        tgt = I.random_sine_modes(target_seed)
+        t0 = time.perf_counter()
+        s = O.assemble(mesh, 1.0 / N ** 2, tgt)
+        x, it, rr = O.pcg(s, rtol=1e-8, maxit=100000)
+        return s.n, it, time.perf_counter() - t0
+
+    n, it, dt = run(N_sample)
+    cores = O.num_threads()
+    O.set_threads(1)
+    n1, it1, dt1 = run(N_single)
+    O.set_threads(cores)
+    return {"value": n / dt, "unit": "DOF/s", "cores": cores, "kind": "oracle",
+            "sample": f"Kuhn mesh {N_sample}^3 cubes ({n} unknowns), rho=h^2, the same 64 sine modes; "
+                      f"oracle assembly + Jacobi-PCG to 1e-8 ({it} iterations) in {dt:.2f} s on {cores} threads",
+            "single_thread": {"value": n1 / dt1, "unit": "DOF/s", "cores": 1,
+                              "sample": f"Kuhn mesh {N_single}^3 cubes ({n1} unknowns), {it1} iterations, "
+                                        f"{dt1:.2f} s"}}
 
 
 def main():

@@ -84,6 +84,8 @@ def lib():
         L.orc_element.argtypes = [dp, ip, C.POINTER(_Target), dp, dp, dp, dp]
         L.orc_element.restype = C.c_int
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
         _lib_handle = L
     return _lib_handle
 
@@ -243,6 +245,11 @@ def element(pts: np.ndarray, target):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    lib().orc_set_threads(int(n))
 
 
 def solve(mesh, rho: float, target, rtol: float = 1e-14, maxit: int = 100000):

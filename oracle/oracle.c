@@ -436,6 +436,16 @@ done:
     return it;
 }
 
+/* Threads used by the parallel loops from now on (n >= 1). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

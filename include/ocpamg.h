@@ -217,6 +217,9 @@ int amg_vcycle(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r, double *z)
 /* ---------------------------------------------------------------- solve */
 #define OCP_STOP_L2 0      /* stop when ||r_k||_2 <= rtol ||f||_2 (default) */
 #define OCP_STOP_PRECOND 1 /* stop when sqrt(r_k^T z_k) <= rtol sqrt(r_0^T z_0) */
+#define OCP_FLEXIBLE 2     /* flexible (Polak-Ribiere) beta = r'.(z' - z) / (r.z), for a preconditioner
+                              symmetric only to rounding (FP32 V-cycle); pcg_solve and the step API
+                              with a hierarchy; ignored by the batch and block solves */
 
 typedef struct {
     int32_t iterations;
@@ -237,7 +240,7 @@ typedef struct {
  *          nearby rho this way)
  *   f      device [n_dofs] right-hand side, or NULL for the system's f
  *   u      device [n_vertices] output, caller-owned; Dirichlet entries set 0
- *   rtol   > 0;  maxit >= 1;  flags: OCP_STOP_L2 or OCP_STOP_PRECOND
+ *   rtol   > 0;  maxit >= 1;  flags: OCP_STOP_L2 or OCP_STOP_PRECOND, | OCP_FLEXIBLE
  * Blocks until converged or capped.  Returns 0 (converged), OCP_MAXIT (u holds
  * the last iterate), OCP_ERR_BREAKDOWN, or another error. */
 int pcg_solve(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, const double *f,

@@ -24,6 +24,7 @@ KEEP_KM = 1
 PREC_FP64, PREC_MIXED = 0, 1
 SMOOTH_L1JACOBI, SMOOTH_CHEBYSHEV = 0, 1
 STOP_L2, STOP_PRECOND = 0, 1
+FLEXIBLE = 2
 TARGET_SINE, TARGET_BOX, TARGET_NODAL = 0, 1, 2
 
 
@@ -478,15 +479,18 @@ def amg_setup(ctx: Context, system: System, precision: int = PREC_FP64, **kw) ->
 
 # ------------------------------------------------------------------ solve
 def pcg_solve(ctx: Context, system: System, hierarchy: Optional[Hierarchy] = None, f=None, u=None,
-              rtol: float = 1e-8, maxit: int = 500, stop: int = STOP_L2, raise_on_maxit: bool = False):
-    """Returns (u on all vertices, SolveInfo, status)."""
+              rtol: float = 1e-8, maxit: int = 500, stop: int = STOP_L2, raise_on_maxit: bool = False,
+              flexible: bool = False):
+    """Returns (u on all vertices, SolveInfo, status).  flexible: the
+    Polak-Ribiere beta (for an FP32 V-cycle)."""
     torch = _torch()
     nv = system.view().n_vertices
     if u is None:
         u = torch.empty(nv, dtype=torch.float64, device="cuda")
     info = SolveInfo()
+    flags = int(stop) | (FLEXIBLE if flexible else 0)
     rc = lib().pcg_solve(ctx.handle, system.handle, hierarchy.handle if hierarchy is not None else None,
-                         _ptr(f), _ptr(u), float(rtol), int(maxit), int(stop), C.byref(info))
+                         _ptr(f), _ptr(u), float(rtol), int(maxit), flags, C.byref(info))
     ok = (OK,) if raise_on_maxit else (OK, MAXIT)
     ctx.check(rc, ok=ok)
     return u, info, rc

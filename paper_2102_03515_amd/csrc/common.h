@@ -48,6 +48,7 @@ struct CgScalars {
     double pq;        // p.Aq
     double rr;        // r.r
     double rz_new;    // r.z after the preconditioner
+    double gamma_prev; // r.z of the previous iterate (flexible beta)
     int32_t flag;     // 0 running, 1 converged, 2 breakdown
     int32_t iter;     // completed iterations
     int32_t stop_mode;

@@ -152,6 +152,7 @@ __device__ __forceinline__ void cg_after_precond(CgScalars *cg, double rz) {
         return;
     }
     cg->beta = (cg->iter == 0) ? 0.0 : rz / cg->gamma;
+    cg->gamma_prev = cg->gamma;
     cg->gamma = rz;
     cg->rz_new = rz;
     if (cg->stop_mode == OCP_STOP_PRECOND) {

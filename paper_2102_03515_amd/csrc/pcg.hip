@@ -145,6 +145,30 @@ __global__ void __launch_bounds__(kBlock) k_cg_pupdate(int32_t n, double *__rest
     if (i < n) p[i] = z[i] + beta * p[i];
 }
 
+// Flexible (Polak-Ribiere) beta = r'.(z' - z) / (r.z): the partials of
+// r'.z with the previous z, then beta -= r'.z / gamma_prev.  Used when the
+// preconditioner is applied in lower precision and so is symmetric only to
+// rounding.
+__global__ void __launch_bounds__(kBlock) k_cg_rzold(int32_t n, int iters, const double *__restrict__ r,
+                                                     const double *__restrict__ zold, const CgScalars *cg,
+                                                     double *partials) {
+    if (cg->flag) return;
+    const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
+    const int base = (int)tile * kBlock * iters;
+    double s = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        const int i = base + it * kBlock + threadIdx.x;
+        if (i < n) s += r[i] * zold[i];
+    }
+    dev::store_partial(dev::block_sum<kBlock>(s), partials);
+}
+
+__global__ void __launch_bounds__(kBlock) k_fin_flex(unsigned nb, const double *partials, CgScalars *cg) {
+    if (cg->flag) return;
+    const double tot = dev::sum_partials<kBlock>(partials, nb);
+    if (threadIdx.x == 0 && cg->iter > 0) cg->beta -= tot / cg->gamma_prev;
+}
+
 // x = 0, r = f, p = 0, f.f and the initial scalars
 __global__ void __launch_bounds__(kBlock) k_cg_init(int32_t n, int iters, const double *__restrict__ f,
                                                     double *__restrict__ x, double *__restrict__ r,
@@ -179,6 +203,7 @@ __global__ void __launch_bounds__(kBlock) k_fin_init(unsigned nb, const double *
         cg->beta = 0.0;
         cg->pq = 0.0;
         cg->rz_new = 0.0;
+        cg->gamma_prev = 1.0;
         cg->iter = 0;
         cg->stop_mode = mode;
         cg->maxit = maxit;
@@ -265,7 +290,9 @@ struct SolveState {
     const ocp_hierarchy *h = nullptr;
     const double *f = nullptr;
     const double *dinv = nullptr;
-    DevBuf<double> x, r, p, q, z;
+    DevBuf<double> x, r, p, q, z, z2;
+    bool flexible = false;   // Polak-Ribiere beta with the previous z (AMG only)
+    int zsel = 0;            // which of z / z2 receives the next preconditioned residual
     VcWork vw;           // V-cycle work vectors of this solve
     DevBuf<CgScalars> cgbuf;
     DevBuf<double> partbuf;   // [4][kRedBlocks]: p.q, r.r / r.z, residual, V-cycle r.z
@@ -293,6 +320,9 @@ static void solve_begin(SolveState &S, ocp_ctx *ctx, ocp_system *sys, const ocp_
     S.p.reset(ctx, n);
     S.q.reset(ctx, n);
     S.z.reset(ctx, n);
+    S.flexible = h && (flags & OCP_FLEXIBLE);
+    if (S.flexible) S.z2.reset(ctx, n);
+    S.zsel = 0;
     S.dinv = h ? nullptr : system_dinv(ctx, sys);
     S.cgbuf.reset(ctx, 1);
     S.partbuf.reset(ctx, (size_t)4 * kRedBlocks);
@@ -322,6 +352,7 @@ static void solve_begin(SolveState &S, ocp_ctx *ctx, ocp_system *sys, const ocp_
     OCP_LAUNCH_CHECK();
     k_cg_pupdate<<<grid_for(n, kBlock), kBlock, 0, ctx->stream>>>(n, S.p.get(), S.z.get(), cg);
     OCP_LAUNCH_CHECK();
+    S.zsel = 1;   // flexible: the next preconditioned residual goes to z2
     ctx->prof_iter = 0;
 }
 
@@ -344,17 +375,28 @@ static void solve_iterate(SolveState &S, int iters) {
                                                                  S.q.get(), cg, part0);
         prof_end(ctx, pr);
         k_fin_alpha<<<1, kBlock, 0, ctx->stream>>>(LS.blocks, part0, cg);
+        double *znew = S.z.get();
         if (S.h) {
             k_cg_update<false><<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, S.x.get(), S.r.get(), S.p.get(),
                                                                       S.q.get(), nullptr, nullptr, cg, part1);
             k_fin_update<false><<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part1, cg);
-            vcycle_enqueue(ctx, S.h, S.r.get(), S.z.get(), cg, S.vw);
+            if (S.flexible) {
+                znew = S.zsel ? S.z2.get() : S.z.get();
+                const double *zold = S.zsel ? S.z.get() : S.z2.get();
+                vcycle_enqueue(ctx, S.h, S.r.get(), znew, cg, S.vw);
+                double *part2 = S.part + 2 * kRedBlocks;
+                k_cg_rzold<<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, S.r.get(), zold, cg, part2);
+                k_fin_flex<<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part2, cg);
+                S.zsel ^= 1;
+            } else {
+                vcycle_enqueue(ctx, S.h, S.r.get(), znew, cg, S.vw);
+            }
         } else {
             k_cg_update<true><<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, S.x.get(), S.r.get(), S.p.get(),
                                                                      S.q.get(), S.dinv, S.z.get(), cg, part1);
             k_fin_update<true><<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part1, cg);
         }
-        k_cg_pupdate<<<gp, kBlock, 0, ctx->stream>>>(n, S.p.get(), S.z.get(), cg);
+        k_cg_pupdate<<<gp, kBlock, 0, ctx->stream>>>(n, S.p.get(), znew, cg);
         ++ctx->prof_iter;
         ++S.host_iter;
     }
@@ -462,7 +504,7 @@ static void solve_batch(ocp_ctx *ctx, int m, const ocp_system *const *systems, c
     std::vector<SolveState> S((size_t)m);
     for (int i = 0; i < m; ++i)
         solve_begin(S[i], ctx, const_cast<ocp_system *>(systems[i]), hs ? hs[i] : nullptr, fs ? fs[i] : nullptr,
-                    rtol, maxit, flags);
+                    rtol, maxit, flags & ~OCP_FLEXIBLE);   // a captured iteration has fixed buffers
     std::vector<CgScalars *> hcg((size_t)m);
     for (int i = 0; i < m; ++i) hcg[i] = S[i].cg;
     DevBuf<CgScalars *> dcg(ctx, (size_t)m);

@@ -357,3 +357,35 @@ def test_iterations_robust_in_h_and_rho(P, ctx):
     print(f"    iterations vs N (rho=h^2): {its_h}; vs rho at N=48: {its_r}")
     assert max(its_h) <= 12 and max(its_h) - min(its_h) <= 4
     assert max(its_r) <= 40
+
+
+def test_flexible_beta(P, ctx):
+    """Flexible (Polak-Ribiere) beta: with an FP64 hierarchy (symmetric to
+    rounding) it tracks the standard recurrence; with the FP32 V-cycle it
+    reaches the same tolerance; both match the oracle."""
+    print("[flexible] cube20 jitter, fp64 and mixed hierarchy", flush=True)
+    mesh = I.kuhn_mesh(20, jitter=0.15, seed=19)
+    target = I.random_sine_modes(1000, n_modes=16)
+    s, _ = _gpu_system(P, ctx, mesh, 1.0 / 400, target)
+    x, o, _, _ = O.solve(mesh, 1.0 / 400, target, rtol=1e-14)
+    uo = O.to_vertices(o, x, mesh.n_vertices)
+    for prec in (P.capi.PREC_FP64, P.capi.PREC_MIXED):
+        h = P.amg_setup(ctx, s, precision=prec, coarse_max=32)
+        u0, i0, r0 = P.pcg_solve(ctx, s, h, rtol=1e-12)
+        u1, i1, r1 = P.pcg_solve(ctx, s, h, rtol=1e-12, flexible=True)
+        assert r0 == 0 and r1 == 0
+        assert abs(i1.iterations - i0.iterations) <= 1, (i0.iterations, i1.iterations)
+        assert i1.true_rel_res <= 1e-11
+        assert _rel(u1.cpu().numpy(), uo) < 1e-9
+        # the step interface runs the same flexible iteration
+        hd = P.pcg_begin(ctx, s, h, rtol=1e-12, stop=P.capi.STOP_L2 | P.capi.FLEXIBLE)
+        while True:
+            st, _ = hd.poll()
+            if st == 0:
+                break
+            if st == 1:
+                hd.advance(3)
+        u2, i2, _ = hd.end()
+        assert i2.iterations == i1.iterations
+        import torch
+        assert torch.equal(u2, u1)

@@ -331,7 +331,8 @@ int pcg_end(ocp_solve_handle *hd, double *u, ocp_solve_info *info);
 /* Live timing of selected kernels with HIP events on the context stream.
  * ocp_profile_enable(ctx, 1) clears the counters and brackets every launch of
  * the kernels above inside pcg_solve (pcg_solve_multi for BLK_SPMM) with an event pair; launches of the
- * solve's final iteration (which may return early after convergence) are not
+ * solve's final iteration (which may return early after convergence) and of
+ * the initial preconditioner application (before iteration 1) are not
  * counted.  ocp_profile_read returns the number of counted launches and their
  * summed duration in milliseconds. */
 int ocp_profile_enable(ocp_ctx *ctx, int32_t on);

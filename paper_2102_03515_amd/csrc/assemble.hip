@@ -313,38 +313,75 @@ constexpr int kModeBatch = 8;   // modes are padded on the host to a multiple (a
 struct TargetDev {
     int32_t kind;
     int32_t n_modes;          // padded to a multiple of kModeBatch
-    const SineMode *modes;    // device [n_modes]
+    const SineMode *modes;    // device [n_modes] (targets with a wave number > kSineTable)
+    // targets whose wave numbers are all <= kSineTable: the amplitudes
+    // summed by wave vector, dense[(k1-1) T^2 + (k2-1) T + (k3-1)] with
+    // T = kSineTable, and bit (k1-1) T + (k2-1) of `pairs` set when some mode
+    // has that (k1, k2)
+    const double *dense;
+    uint64_t pairs;
     double offset;
     double lo[3], hi[3];
     const double *nodal;      // device [n_vertices]
 };
+static_assert(kSineTable * kSineTable <= 64, "pairs mask holds kSineTable^2 bits");
 
-// ubar(x) for sine modes.  sin(k pi x_d) for k <= kSineTable comes from the
-// three-term recurrence s_{k+1} = 2 cos(pi x) s_k - s_{k-1}, seeded with
-// sincospi and held in registers; a mode's wave numbers are the same for
-// every lane, so the tables are indexed with a uniform index.  With
-// TABLE_ONLY every wave number is known to be <= kSineTable; otherwise the
-// larger ones call sinpi.  The modes are added in their given order.
-template <bool TABLE_ONLY>
+// sin(k pi x_d) for k = 1..kSineTable from the three-term recurrence
+// s_{k+1} = 2 cos(pi x) s_k - s_{k-1}, seeded with sincospi.
+__device__ __forceinline__ void sine_table(double xd, double (&tab)[kSineTable]) {
+    double s, c;
+    sincospi(xd, &s, &c);
+    double sm1 = 0.0, sk = s;
+#pragma unroll
+    for (int k = 0; k < kSineTable; ++k) {
+        tab[k] = sk;
+        const double sn = 2.0 * c * sk - sm1;
+        sm1 = sk;
+        sk = sn;
+    }
+}
+
+// ubar(x) for sine modes with every wave number <= kSineTable, as the
+// separable contraction
+//   ubar = offset + sum_k1 s1[k1] sum_k2 s2[k2] sum_k3 A[k1,k2,k3] s3[k3]
+// over the dense amplitude array A: every table index is a compile-time
+// constant (no indexed register moves), A comes in through wide scalar
+// loads, and (k1, k2) pairs that no mode uses are skipped by a uniform
+// branch.  Amplitudes of equal wave vectors are summed on the host.
+__device__ double eval_sine_dense(const TargetDev &t, const double x[3]) {
+    double t0[kSineTable], t1[kSineTable], t2[kSineTable];
+    sine_table(x[0], t0);
+    sine_table(x[1], t1);
+    sine_table(x[2], t2);
+    double u = t.offset;
+#pragma unroll
+    for (int a = 0; a < kSineTable; ++a) {
+        double ua = 0.0;
+#pragma unroll
+        for (int b = 0; b < kSineTable; ++b) {
+            if ((t.pairs >> (a * kSineTable + b)) & 1) {
+                const double *c = t.dense + (a * kSineTable + b) * kSineTable;
+                double w = 0.0;
+#pragma unroll
+                for (int k = 0; k < kSineTable; ++k) w += c[k] * t2[k];
+                ua += t1[b] * w;
+            }
+        }
+        u += t0[a] * ua;
+    }
+    return u;
+}
+
+// ubar(x) for sine modes in general: wave numbers <= kSineTable read the
+// recurrence tables (a mode's wave numbers are the same for every lane, so
+// the index is uniform), larger ones call sinpi.  The modes are added in
+// their given order.
 __device__ double eval_sine(const TargetDev &t, const double x[3]) {
     double t0[kSineTable], t1[kSineTable], t2[kSineTable];
-    auto fill = [&](double xd, double *tab) {
-        double s, c;
-        sincospi(xd, &s, &c);
-        double sm1 = 0.0, sk = s;
-#pragma unroll
-        for (int k = 0; k < kSineTable; ++k) {
-            tab[k] = sk;
-            const double sn = 2.0 * c * sk - sm1;
-            sm1 = sk;
-            sk = sn;
-        }
-    };
-    fill(x[0], t0);
-    fill(x[1], t1);
-    fill(x[2], t2);
+    sine_table(x[0], t0);
+    sine_table(x[1], t1);
+    sine_table(x[2], t2);
     auto factor = [&](int k, const double *tab, double xd) {
-        if (TABLE_ONLY) return tab[k - 1];
         return k <= kSineTable ? tab[k - 1] : sinpi((double)k * xd);
     };
     double u = t.offset;
@@ -399,7 +436,7 @@ __global__ void __launch_bounds__(kLoadBlock) k_tet_load(const int4 *__restrict_
     }
     double u;
     if (tg.kind == OCP_TARGET_SINE_MODES) {
-        u = eval_sine<TABLE_ONLY>(tg, x);
+        u = TABLE_ONLY ? eval_sine_dense(tg, x) : eval_sine(tg, x);
     } else if (tg.kind == OCP_TARGET_BOX) {
         u = (x[0] > tg.lo[0] && x[0] < tg.hi[0] && x[1] > tg.lo[1] && x[1] < tg.hi[1] && x[2] > tg.lo[2] &&
              x[2] < tg.hi[2])
@@ -563,6 +600,7 @@ static void check_target(const ocp_target *t, int32_t nv) {
 // Upload the target description; the returned buffers must outlive the launch.
 struct TargetUpload {
     DevBuf<SineMode> modes;
+    DevBuf<double> dense;
     bool table_only = true;   // every wave number <= kSineTable
     TargetDev dev{};
 };
@@ -577,6 +615,26 @@ static void upload_target(ocp_ctx *ctx, const ocp_target *t, TargetUpload &up) {
     up.dev.nodal = t->nodal;
     if (t->kind == OCP_TARGET_SINE_MODES) {
         const int m = t->n_modes;
+        for (int q = 0; q < 3 * m; ++q) up.table_only = up.table_only && t->k[q] <= kSineTable;
+        if (up.table_only) {
+            constexpr int T = kSineTable;
+            std::vector<double> a((size_t)T * T * T, 0.0);
+            uint64_t pairs = 0;
+            for (int q = 0; q < m; ++q) {
+                const int k1 = t->k[3 * q] - 1, k2 = t->k[3 * q + 1] - 1, k3 = t->k[3 * q + 2] - 1;
+                a[((size_t)k1 * T + k2) * T + k3] += t->amp[q];
+                pairs |= uint64_t(1) << (k1 * T + k2);
+            }
+            up.dense.reset(ctx, a.size());
+            OCP_HIP(hipMemcpyAsync(up.dense.get(), a.data(), sizeof(double) * a.size(), hipMemcpyHostToDevice,
+                                   ctx->stream));
+            up.dev.dense = up.dense.get();
+            up.dev.pairs = pairs;
+            up.dev.n_modes = 0;
+            up.dev.modes = nullptr;
+            sync(ctx);  // the staging vector is released when this returns
+            return;
+        }
         const int mp = (m + kModeBatch - 1) / kModeBatch * kModeBatch;
         std::vector<SineMode> md((size_t)mp);
         for (int q = 0; q < mp; ++q) {
@@ -584,10 +642,7 @@ static void upload_target(ocp_ctx *ctx, const ocp_target *t, TargetUpload &up) {
             o.pad = 0;
             o.pad2 = 0.0;
             if (q < m) {
-                for (int d = 0; d < 3; ++d) {
-                    o.k[d] = t->k[3 * q + d];
-                    up.table_only = up.table_only && o.k[d] <= kSineTable;
-                }
+                for (int d = 0; d < 3; ++d) o.k[d] = t->k[3 * q + d];
                 o.amp = t->amp[q];
             } else {   // padding: contributes amp * (...) = 0
                 o.k[0] = o.k[1] = o.k[2] = 1;

@@ -141,6 +141,24 @@ __device__ __forceinline__ double sum_partials(const double *partials, unsigned 
     return block_sum<BLOCK>(s);
 }
 
+}  // namespace dev
+
+// The V-cycle's first smoothing step from zero, y = a D^-1 r, in the
+// hierarchy's precision: written by the kernels that produce r, so that the
+// first pass of the cycle gathers this vector (4 bytes per entry in mixed
+// precision) instead of rebuilding a d_j r_j from r and d for every matrix
+// entry.  y == nullptr: not wanted.
+template <typename YT>
+struct FirstStep {
+    YT *y;
+    const YT *d;
+    YT a;
+    __device__ __forceinline__ void put(size_t e, int row, double r) const {
+        if (y) y[e] = a * d[row] * (YT)r;
+    }
+};
+
+namespace dev {
 // After r.z of the new preconditioned residual is known (thread 0 of the
 // last block): beta = rz / gamma, gamma = rz; first call records gamma0; the
 // preconditioned stop test and the breakdown test live here.

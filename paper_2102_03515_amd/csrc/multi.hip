@@ -419,19 +419,6 @@ __global__ void __launch_bounds__(kBlock) k_blk_rz(int32_t n, int k, BlkT bt, co
 }
 
 // ------------------------------------------------------------- CG kernels
-// The V-cycle's first smoothing step from zero, y = a D^-1 r, in the
-// hierarchy's precision: written by the kernels that produce r, so the first
-// pass of the cycle gathers this block instead of rebuilding it from r and
-// d for every matrix entry.  y == nullptr: not wanted.
-template <typename YT>
-struct FirstStep {
-    YT *y;
-    const YT *d;
-    YT a;
-    __device__ __forceinline__ void put(size_t e, int row, double r) const {
-        if (y) y[e] = a * d[row] * (YT)r;
-    }
-};
 // X = 0, R = F, P = 0 and f.f per column; F column j of row i sits at
 // F[i * fs_row + j * fs_col] (fs_col = 0: the same vector for every column).
 template <int KB, typename YT>

@@ -87,11 +87,12 @@ __global__ void __launch_bounds__(kBlock) k_fin_store(unsigned nb, const double 
 }
 
 // x += alpha p, r -= alpha q, r.r; with JAC also z = dinv r and r.z.
-template <bool JAC>
+template <bool JAC, typename YT>
 __global__ void __launch_bounds__(kBlock) k_cg_update(int32_t n, int iters, double *__restrict__ x,
                                                       double *__restrict__ r, const double *__restrict__ p,
                                                       const double *__restrict__ q, const double *__restrict__ dinv,
-                                                      double *__restrict__ z, CgScalars *cg, double *partials) {
+                                                      double *__restrict__ z, FirstStep<YT> first, CgScalars *cg,
+                                                      double *partials) {
     if (cg->flag) return;
     const double alpha = cg->alpha;
     const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
@@ -103,6 +104,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int32_t n, int iters, doub
             x[i] += alpha * p[i];
             const double ri = r[i] - alpha * q[i];
             r[i] = ri;
+            first.put(i, i, ri);
             rr += ri * ri;
             if (JAC) {
                 const double zi = dinv[i] * ri;
@@ -170,9 +172,10 @@ __global__ void __launch_bounds__(kBlock) k_fin_flex(unsigned nb, const double *
 }
 
 // x = 0, r = f, p = 0, f.f and the initial scalars
+template <typename YT>
 __global__ void __launch_bounds__(kBlock) k_cg_init(int32_t n, int iters, const double *__restrict__ f,
                                                     double *__restrict__ x, double *__restrict__ r,
-                                                    double *__restrict__ p, double *partials) {
+                                                    double *__restrict__ p, FirstStep<YT> first, double *partials) {
     const unsigned tile = dev::xcd_tile(blockIdx.x, gridDim.x);
     const int base = (int)tile * kBlock * iters;
     double ff = 0.0;
@@ -183,6 +186,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(int32_t n, int iters, const 
             x[i] = 0.0;
             r[i] = fi;
             p[i] = 0.0;
+            first.put(i, i, fi);
             ff += fi * fi;
         }
     }
@@ -291,6 +295,7 @@ struct SolveState {
     const double *f = nullptr;
     const double *dinv = nullptr;
     DevBuf<double> x, r, p, q, z, z2;
+    DevBuf<char> y0;         // level 0's first smoothing step of r (hierarchies of 2+ levels)
     bool flexible = false;   // Polak-Ribiere beta with the previous z (AMG only)
     int zsel = 0;            // which of z / z2 receives the next preconditioned residual
     VcWork vw;           // V-cycle work vectors of this solve
@@ -303,6 +308,21 @@ struct SolveState {
     double rtol = 0.0;
     int host_iter = 0;   // iterations enqueued (host count)
 };
+
+// Call fn with the FirstStep that the kernels producing r fill for the
+// V-cycle (y = a D0^-1 r in the hierarchy's precision), or an empty one.
+template <typename Fn>
+static void with_first_step(const SolveState &S, Fn &&fn) {
+    if (!S.y0.get()) {
+        fn(FirstStep<float>{nullptr, nullptr, 0.f});
+        return;
+    }
+    const Level &l0 = *S.h->levels[0];
+    if (S.h->params.precision == OCP_PREC_MIXED)
+        fn(FirstStep<float>{reinterpret_cast<float *>(S.y0.get()), l0.dinv32.get(), (float)l0.cheb_a});
+    else
+        fn(FirstStep<double>{reinterpret_cast<double *>(S.y0.get()), l0.dinv.get(), l0.cheb_a});
+}
 
 // Allocate and enqueue x = 0, r = f, the first preconditioner application
 // and p = z (no host synchronization).
@@ -331,6 +351,11 @@ static void solve_begin(SolveState &S, ocp_ctx *ctx, ocp_system *sys, const ocp_
     if (h) {
         vc_work_alloc(ctx, h, S.vw);
         S.vw.part = S.part + 3 * kRedBlocks;
+        if (h->levels.size() > 1) {
+            const size_t vs = h->params.precision == OCP_PREC_MIXED ? sizeof(float) : sizeof(double);
+            S.y0.reset(ctx, (size_t)n * vs);
+            S.vw.y0 = S.y0.get();
+        }
     }
     S.mode = (flags & OCP_STOP_PRECOND) ? OCP_STOP_PRECOND : OCP_STOP_L2;
     CgScalars *cg = S.cg;
@@ -340,7 +365,10 @@ static void solve_begin(SolveState &S, ocp_ctx *ctx, ocp_system *sys, const ocp_
     const RowLaunch LV = vec_launch(n);
     ctx->prof_iter = -1;   // the initial preconditioner application
     OCP_HIP(hipEventRecord(ctx->ev0, ctx->stream));
-    k_cg_init<<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, S.f, S.x.get(), S.r.get(), S.p.get(), part0);
+    with_first_step(S, [&](auto fs) {
+        k_cg_init<<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, S.f, S.x.get(), S.r.get(), S.p.get(), fs,
+                                                         part0);
+    });
     k_fin_init<<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part0, cg, rtol, S.mode, maxit);
     OCP_LAUNCH_CHECK();
     if (h) {
@@ -377,8 +405,10 @@ static void solve_iterate(SolveState &S, int iters) {
         k_fin_alpha<<<1, kBlock, 0, ctx->stream>>>(LS.blocks, part0, cg);
         double *znew = S.z.get();
         if (S.h) {
-            k_cg_update<false><<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, S.x.get(), S.r.get(), S.p.get(),
-                                                                      S.q.get(), nullptr, nullptr, cg, part1);
+            with_first_step(S, [&](auto fs) {
+                k_cg_update<false><<<LV.blocks, kBlock, 0, ctx->stream>>>(
+                    n, LV.iters, S.x.get(), S.r.get(), S.p.get(), S.q.get(), nullptr, nullptr, fs, cg, part1);
+            });
             k_fin_update<false><<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part1, cg);
             if (S.flexible) {
                 znew = S.zsel ? S.z2.get() : S.z.get();
@@ -393,7 +423,8 @@ static void solve_iterate(SolveState &S, int iters) {
             }
         } else {
             k_cg_update<true><<<LV.blocks, kBlock, 0, ctx->stream>>>(n, LV.iters, S.x.get(), S.r.get(), S.p.get(),
-                                                                     S.q.get(), S.dinv, S.z.get(), cg, part1);
+                                                                     S.q.get(), S.dinv, S.z.get(),
+                                                                     FirstStep<float>{nullptr, nullptr, 0.f}, cg, part1);
             k_fin_update<true><<<1, kBlock, 0, ctx->stream>>>(LV.blocks, part1, cg);
         }
         k_cg_pupdate<<<gp, kBlock, 0, ctx->stream>>>(n, S.p.get(), znew, cg);

@@ -260,7 +260,10 @@ void prof_resolve(ocp_ctx *ctx, int valid_iters) {
     if (ctx->prof_recs.empty()) return;
     OCP_HIP(hipStreamSynchronize(ctx->stream));
     for (auto &r : ctx->prof_recs) {
-        if (r.iter < valid_iters && r.kernel >= 0 && r.kernel < 8) {
+        // iteration launches only: the initial application (iter -1) follows
+        // the solve's allocations and its first event pair has been seen to
+        // read several ms above the kernel's own duration in a trace
+        if (r.iter >= 0 && r.iter < valid_iters && r.kernel >= 0 && r.kernel < 8) {
             float ms = 0.f;
             OCP_HIP(hipEventElapsedTime(&ms, r.a, r.b));
             ctx->prof_ms[r.kernel] += ms;

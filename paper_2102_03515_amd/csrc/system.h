@@ -89,6 +89,9 @@ struct VcWork {
     };
     std::vector<Lvl> lv;
     double *part = nullptr;   // partials of the fine-level r.z (null: the context's)
+    // Level 0's first pre-smoothing step a D^-1 r, written beside r by the
+    // kernel that produced r (hierarchy precision); null: rebuilt from r.
+    const void *y0 = nullptr;
 };
 void vc_work_alloc(ocp_ctx *ctx, const ocp_hierarchy *h, VcWork &w, int k = 1);
 

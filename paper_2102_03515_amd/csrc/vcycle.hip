@@ -286,11 +286,19 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
         T *rres = reinterpret_cast<T *>(W.lv[l].vr.get());
         T *x2 = reinterpret_cast<T *>(W.lv[l].vx2.get());
         const T ca = (T)cur.cheb_a, c1 = (T)cur.cheb_c1, c2 = (T)cur.cheb_c2;
+        // the first step from zero, a D^-1 b, as stored by b's producer
+        const T *y0 = l == 0 ? static_cast<const T *>(W.y0) : nullptr;
         if (cur.deg == 2) {
             // x2 = D^-1 (c1 b + c2 r1), r1 = b - A (a D^-1 b); then r2 = b - A x2
             const int pr = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_PRE0) : -1;
-            pass(l, SmoothOps<T, BT, T, true, kX2, false>{a.d, bptr, nullptr, nullptr, nullptr, ca, c1, c2, x2, nullptr},
-                 false);
+            if (y0)
+                pass(l, SmoothOps<T, BT, T, false, kX2, false>{a.d, bptr, y0, nullptr, nullptr, ca, c1, c2, x2,
+                                                               nullptr},
+                     false);
+            else
+                pass(l, SmoothOps<T, BT, T, true, kX2, false>{a.d, bptr, nullptr, nullptr, nullptr, ca, c1, c2, x2,
+                                                              nullptr},
+                     false);
             prof_end(ctx, pr);
             const int pr2 = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_PRE0_B) : -1;
             pass(l, SmoothOps<T, BT, T, false, kR, false>{a.d, bptr, x2, nullptr, nullptr, ca, c1, c2, rres, nullptr},
@@ -299,8 +307,14 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
         } else {
             // r1 = b - A (a D^-1 b)
             const int pr = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_PRE0) : -1;
-            pass(l, SmoothOps<T, BT, T, true, kR, false>{a.d, bptr, nullptr, nullptr, nullptr, ca, c1, c2, rres, nullptr},
-                 false);
+            if (y0)
+                pass(l, SmoothOps<T, BT, T, false, kR, false>{a.d, bptr, y0, nullptr, nullptr, ca, c1, c2, rres,
+                                                              nullptr},
+                     false);
+            else
+                pass(l, SmoothOps<T, BT, T, true, kR, false>{a.d, bptr, nullptr, nullptr, nullptr, ca, c1, c2, rres,
+                                                             nullptr},
+                     false);
             prof_end(ctx, pr);
         }
         T *bn = reinterpret_cast<T *>(W.lv[l + 1].vb.get());

@@ -1,16 +1,17 @@
 // Finite element assembly of A = rho*K + M and f = (int ubar phi_i) into CSR
 // (Section 3, system (linsys) and the entries K_ij, M_ij, f_i defined there).
 //
-// Row-owned, atomic-free on values: every interior vertex owns its row and
-// recomputes the element entries of its incident tetrahedra on the fly,
-// summing them in ascending tet id.  The result is
-// bitwise deterministic (and A bitwise symmetric).
+// Row-owned, atomic-free on values: every tet writes one element record
+// (its vertex dofs, element matrix and element loads), and every interior
+// vertex owns its row and sums the records of its incident tetrahedra in
+// ascending tet id.  The result is bitwise deterministic (and A bitwise
+// symmetric).
 //
 //   1. per tet: index/degeneracy checks, incidence counts   (int atomics)
 //   2. scan -> incidence pointers; fill; sort each list      (vertex -> tets)
 //   3. dof numbering of interior vertices (scan)
-//   4. symbolic rows: sorted union of the interior vertices of incident tets
-//   5. per tet: load contributions fe[4] by the 4-point degree-2 rule
+//   4. per tet: element record; loads by the 4-point degree-2 rule
+//   5. symbolic rows: sorted union of the interior vertices of incident tets
 //   6. numeric rows: sum rho*K_e + M_e (and fe) over incident tets
 #include <cfloat>
 #include <climits>
@@ -147,7 +148,9 @@ __global__ void __launch_bounds__(kIncBlock) k_tet_check_count(const int4 *__res
 
 // ------------------------------------------------------ 2. incidence lists
 // Same LDS combining: one global atomic per distinct vertex reserves the
-// block's range in that vertex's list; references get local offsets.
+// block's range in that vertex's list; references get local offsets.  An
+// entry is the code (e << 2) | a: tet e, in which the vertex is local vertex
+// a (fits in int32: at most 2^29 tets).  Codes sort like tet ids.
 __global__ void __launch_bounds__(kIncBlock) k_tet_fill(const int4 *__restrict__ tets, int64_t nt,
                                                         const int32_t *__restrict__ inc_ptr,
                                                         int32_t *__restrict__ fill, int32_t *__restrict__ inc) {
@@ -176,11 +179,11 @@ __global__ void __launch_bounds__(kIncBlock) k_tet_fill(const int4 *__restrict__
     __syncthreads();
     if (e < nt) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) inc[base[slot[a]] + pos[a]] = (int32_t)e;
+        for (int a = 0; a < 4; ++a) inc[base[slot[a]] + pos[a]] = (int32_t)((e << 2) | a);
     }
 }
 
-// Sort each vertex's list of incident tets ascending: a 32-wide sorting
+// Sort each vertex's list of incidence codes ascending: a 32-wide sorting
 // network in registers for the common case, insertion sort otherwise.
 __global__ void k_inc_sort(const int32_t *__restrict__ inc_ptr, int32_t *__restrict__ inc, int32_t nv) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -241,7 +244,7 @@ __global__ void k_dof_maps(const uint8_t *__restrict__ dirichlet, const int32_t 
     }
 }
 
-// ---------------------------------------------------- 4. symbolic rows
+// ---------------------------------------------------- 5. symbolic rows
 // pass 0: row_cnt[i] = number of distinct interior neighbours (incl. i); rows
 //         of at most kPadW entries are also written, sorted, to pad[i][.]
 // pass 1: write the sorted list to col[row_ptr[i] ..] (only needed when some
@@ -249,34 +252,44 @@ __global__ void k_dof_maps(const uint8_t *__restrict__ dirichlet, const int32_t 
 constexpr int kPadW = 32;
 template <int CAP>
 __global__ void __launch_bounds__(kAsmBlock) k_row_symbolic(
-    int pass, int32_t n, const int32_t *__restrict__ vertex_of_dof, const int32_t *__restrict__ dof_of_vertex,
-    const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc, const int4 *__restrict__ tets,
-    int32_t *__restrict__ row_cnt, const int32_t *__restrict__ row_ptr, int32_t *__restrict__ col,
-    int32_t *__restrict__ pad, int32_t *__restrict__ flag) {
+    int pass, int32_t n, const int32_t *__restrict__ vertex_of_dof, const int32_t *__restrict__ inc_ptr,
+    const int32_t *__restrict__ inc, const int4 *__restrict__ tdof, int32_t *__restrict__ row_cnt,
+    const int32_t *__restrict__ row_ptr, int32_t *__restrict__ col, int32_t *__restrict__ pad,
+    int32_t *__restrict__ flag) {
     __shared__ int32_t lst[CAP][kAsmBlock];
     const int t = threadIdx.x;
-    const int i = blockIdx.x * kAsmBlock + t;
+    const int lb = xcd_block((unsigned)((n + kAsmBlock - 1) / kAsmBlock));
+    if (lb < 0) return;
+    const int i = lb * kAsmBlock + t;
     if (i >= n) return;
     const int vi = vertex_of_dof[i];
     int cnt = 0;
-    for (int q = inc_ptr[vi]; q < inc_ptr[vi + 1]; ++q) {
-        const int4 tv = tets[inc[q]];
-        const int vv[4] = {tv.x, tv.y, tv.z, tv.w};
+    const int qe = inc_ptr[vi + 1];
+    // the dof quadruples of U incident tets are requested before any is used
+    constexpr int U = 8;
+    for (int q0 = inc_ptr[vi]; q0 < qe; q0 += U) {
+        int4 td[U];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int d = dof_of_vertex[vv[a]];
-            if (d < 0) continue;
-            // insert d into the sorted list lst[0..cnt)
-            int s = cnt - 1;
-            while (s >= 0 && lst[s][t] > d) --s;
-            if (s >= 0 && lst[s][t] == d) continue;
-            if (cnt == CAP) {
-                atomicOr(flag, CAP == kRowCap ? 4 : 128);
-                return;
+        for (int u = 0; u < U; ++u) td[u] = q0 + u < qe ? tdof[inc[q0 + u] >> 2] : make_int4(-1, -1, -1, -1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int dd[4] = {td[u].x, td[u].y, td[u].z, td[u].w};
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int d = dd[a];
+                if (d < 0) continue;
+                // insert d into the sorted list lst[0..cnt)
+                int s = cnt - 1;
+                while (s >= 0 && lst[s][t] > d) --s;
+                if (s >= 0 && lst[s][t] == d) continue;
+                if (cnt == CAP) {
+                    atomicOr(flag, CAP == kRowCap ? 4 : 128);
+                    return;
+                }
+                for (int w = cnt - 1; w > s; --w) lst[w + 1][t] = lst[w][t];
+                lst[s + 1][t] = d;
+                ++cnt;
             }
-            for (int u = cnt - 1; u > s; --u) lst[u + 1][t] = lst[u][t];
-            lst[s + 1][t] = d;
-            ++cnt;
         }
     }
     if (pass == 0) {
@@ -299,7 +312,7 @@ __global__ void k_pad_to_csr(int32_t n, const int32_t *__restrict__ pad, const i
     if (s < row_ptr[i + 1] - b) col[b + s] = pad[t];
 }
 
-// --------------------------------------------------------- 5. element loads
+// --------------------------------------------- 4. element loads and records
 // One sine mode as the kernel reads it: 32 bytes, so that a batch of
 // kModeBatch modes is a few wide scalar loads issued together.
 struct SineMode {
@@ -400,14 +413,64 @@ __device__ double eval_sine(const TargetDev &t, const double x[3]) {
     return u;
 }
 
+// Element records, one 128-byte line per tet:
+//   ints 0..3      dof numbers of the 4 vertices (-1 on the boundary)
+//   doubles 2..11  the 10 distinct entries (a <= b, packed row by row) of the
+//                  symmetric element matrix rho K_e + M_e, or of K_e alone
+//                  when K and M are kept apart (then |tau| goes to vol[e])
+//   doubles 12..15 the element loads
+// with K_e[a][b] = |tau| grad phi_a . grad phi_b and M_e[a][b] =
+// |tau|/20 (1 + delta_ab).  Every entry is computed once, so the element
+// matrix is exactly symmetric.
+constexpr int kRecD = 16;   // doubles per record
+constexpr int kRecVal = 2, kRecFe = 12;
+__device__ __forceinline__ int sym_index(int a, int b) {   // packed (min, max) position
+    const int i = a < b ? a : b, j = a < b ? b : a;
+    return i * 4 - (i * (i - 1)) / 2 + (j - i);
+}
+
+// the 10 record values of one tet and |tau|
+template <bool KM>
+__device__ __forceinline__ void elem_values(const double p[4][3], double rho, double v[10], double &vol) {
+#pragma clang fp contract(off)
+    double g[4][3];
+    const double det = tet_gradients(p, g);
+    vol = fabs(det) / 6.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a; b < 4; ++b) {
+            const double kab = vol * (g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2]);
+            const double mab = vol / 20.0 * (b == a ? 2.0 : 1.0);
+            v[sym_index(a, b)] = KM ? kab : rho * kab + mab;
+        }
+}
+
+__device__ __forceinline__ double ints_as_double(int lo, int hi) {
+    return __longlong_as_double((long long)(uint32_t)lo | ((long long)(uint32_t)hi << 32));
+}
+
 // One lane per quadrature point (4 lanes per tet); the 4 point contributions
-// are added in a fixed order across the lanes.
+// are added in a fixed order across the lanes.  REC = 0: the element loads go
+// to fe[e].  REC = 1 (rho K + M) or 2 (K, with |tau| to vol[e]): the whole
+// element record is written, lane q storing its doubles 4q .. 4q+3 (so a
+// wavefront's store covers 16 consecutive records), and the vertex dofs also
+// go to tdof[e].
 constexpr int kLoadBlock = 128;
-template <bool TABLE_ONLY>
+struct RecOut {
+    const int32_t *dof_of_vertex;
+    double rho;
+    double *rec;
+    double *vol;
+    int4 *tdof;
+};
+template <bool TABLE_ONLY, int REC>
 __global__ void __launch_bounds__(kLoadBlock) k_tet_load(const int4 *__restrict__ tets, int64_t nt,
                                                          const double *__restrict__ xyz, TargetDev tg,
-                                                         double4 *__restrict__ fe) {
-    const int64_t tid = (int64_t)blockIdx.x * kLoadBlock + threadIdx.x;
+                                                         double4 *__restrict__ fe, RecOut ro) {
+    const int lb = xcd_block((unsigned)((nt * 4 + kLoadBlock - 1) / kLoadBlock));
+    if (lb < 0) return;
+    const int64_t tid = (int64_t)lb * kLoadBlock + threadIdx.x;
     const int64_t e = tid >> 2;
     const int q = (int)(tid & 3);
     if (e >= nt) return;   // uniform over the 4 lanes of a tet
@@ -452,31 +515,45 @@ __global__ void __launch_bounds__(kLoadBlock) k_tet_load(const int4 *__restrict_
     double f[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) f[a] = dev::group_sum<4>(wu * (a == q ? qa : qb));
-    if (q == 0) fe[e] = make_double4(f[0], f[1], f[2], f[3]);
+    if (REC == 0) {
+        if (q == 0) fe[e] = make_double4(f[0], f[1], f[2], f[3]);
+        return;
+    }
+    double v[10], vol;
+    elem_values<REC == 2>(p, ro.rho, v, vol);
+    double4 out;
+    if (q == 0) {
+        const int4 d = make_int4(ro.dof_of_vertex[tv.x], ro.dof_of_vertex[tv.y], ro.dof_of_vertex[tv.z],
+                                 ro.dof_of_vertex[tv.w]);
+        ro.tdof[e] = d;
+        if (REC == 2) ro.vol[e] = vol;
+        out = make_double4(ints_as_double(d.x, d.y), ints_as_double(d.z, d.w), v[0], v[1]);
+    } else if (q == 1) {
+        out = make_double4(v[2], v[3], v[4], v[5]);
+    } else if (q == 2) {
+        out = make_double4(v[6], v[7], v[8], v[9]);
+    } else {
+        out = make_double4(f[0], f[1], f[2], f[3]);
+    }
+    reinterpret_cast<double4 *>(ro.rec)[4 * e + q] = out;
 }
 
 // ---------------------------------------------------------- 6. numeric rows
-// One thread per row: the incident tets are visited in ascending id and
-// rho*K_e + M_e is accumulated into register slots (one per row entry,
-// matched by column).  Entry (i,j) and entry (j,i) therefore sum the same
-// element terms in the same order: the assembled A is bitwise symmetric.
-// (kNumG > 1 splits the tets of a row over lanes by id mod kNumG and adds the
-// lane sums in a fixed butterfly order, which keeps that property; one lane
-// per row measured fastest.)
-constexpr int kNumG = 1;
+// One thread per row: the incident tets are visited in ascending id and the
+// element values are accumulated into register slots (one per row entry,
+// matched by column).  Entry (i,j) and entry (j,i) therefore add the same
+// element values in the same order: the assembled A is bitwise symmetric.
+// The records of U incident tets are requested before any is used.
 template <int MAXS, bool KM>
 __global__ void __launch_bounds__(256) k_row_numeric(
-    int32_t n, double rho, const int32_t *__restrict__ vertex_of_dof, const int32_t *__restrict__ dof_of_vertex,
-    const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc, const int4 *__restrict__ tets,
-    const double *__restrict__ xyz, const double4 *__restrict__ fe, const int32_t *__restrict__ row_ptr,
-    const int32_t *__restrict__ col, double *__restrict__ val, double *__restrict__ valK,
-    double *__restrict__ valM, double *__restrict__ f) {
-    // No FMA contraction here: the unrolled copies of the element-entry
-    // expression for different local indices must round identically, so that
-    // entry (i,j) and entry (j,i) get the same bits.
+    int32_t n, double rho, const int32_t *__restrict__ vertex_of_dof, const int32_t *__restrict__ inc_ptr,
+    const int32_t *__restrict__ inc, const double *__restrict__ rec, const double *__restrict__ vol_in,
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col, double *__restrict__ val,
+    double *__restrict__ valK, double *__restrict__ valM, double *__restrict__ f) {
 #pragma clang fp contract(off)
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = (int)(tid / kNumG), lane = (int)(tid % kNumG);
+    const int lb = xcd_block((unsigned)((n + 255) / 256));
+    if (lb < 0) return;
+    const int i = lb * 256 + (int)threadIdx.x;
     if (i >= n) return;
     const int vi = vertex_of_dof[i];
     const int rb = row_ptr[i], len = row_ptr[i + 1] - rb;
@@ -493,76 +570,78 @@ __global__ void __launch_bounds__(256) k_row_numeric(
     }
     double fi = 0.0;
     const int qe = inc_ptr[vi + 1];
-    for (int q = inc_ptr[vi]; q < qe; ++q) {
-        const int e = inc[q];
-        if ((e % kNumG) != lane) continue;
-        const int4 tv = tets[e];
-        const int vv[4] = {tv.x, tv.y, tv.z, tv.w};
-        double p[4][3], g[4][3];
-        load_tet(xyz, tv, p);
-        const double det = tet_gradients(p, g);
-        const double vol = fabs(det) / 6.0;
-        int a = 0;
+    constexpr int U = 4;
+    for (int q0 = inc_ptr[vi]; q0 < qe; q0 += U) {
+        int code[U];
+        int4 td[U];
+        double kr[U][4], vol[U], fa[U];
 #pragma unroll
-        for (int c = 1; c < 4; ++c)
-            if (vv[c] == vi) a = c;
-        const double4 fv = fe[e];
-        fi += (a == 0) ? fv.x : (a == 1) ? fv.y : (a == 2) ? fv.z : fv.w;
-        double ga[3];
+        for (int u = 0; u < U; ++u) code[u] = q0 + u < qe ? inc[q0 + u] : -1;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) ga[d] = (a == 0) ? g[0][d] : (a == 1) ? g[1][d] : (a == 2) ? g[2][d] : g[3][d];
+        for (int u = 0; u < U; ++u) {
+            if (code[u] < 0) continue;
+            const int64_t e = code[u] >> 2;
+            const int a = code[u] & 3;
+            const double *r = rec + kRecD * e;
+            td[u] = *reinterpret_cast<const int4 *>(r);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int j = dof_of_vertex[vv[b]];
-            if (j < 0) continue;
-            const double kab = vol * (ga[0] * g[b][0] + ga[1] * g[b][1] + ga[2] * g[b][2]);
-            const double mab = vol / 20.0 * (b == a ? 2.0 : 1.0);
-            const double v = rho * kab + mab;
-#pragma unroll
-            for (int s2 = 0; s2 < MAXS; ++s2)
-                if (cols[s2] == j) {
-                    acc[s2] += v;
-                    if (KM) {
-                        aK[s2] += kab;
-                        aM[s2] += mab;
-                    }
-                }
+            for (int b = 0; b < 4; ++b) kr[u][b] = r[kRecVal + sym_index(a, b)];
+            fa[u] = r[kRecFe + a];
+            if (KM) vol[u] = vol_in[e];
         }
-    }
-    fi = dev::group_sum<kNumG>(fi);
 #pragma unroll
-    for (int q = 0; q < MAXS; ++q) {
-        acc[q] = dev::group_sum<kNumG>(acc[q]);
-        if (KM) {
-            aK[q] = dev::group_sum<kNumG>(aK[q]);
-            aM[q] = dev::group_sum<kNumG>(aM[q]);
+        for (int u = 0; u < U; ++u) {
+            if (code[u] < 0) continue;
+            const int a = code[u] & 3;
+            fi += fa[u];
+            const int dd[4] = {td[u].x, td[u].y, td[u].z, td[u].w};
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int j = dd[b];
+                if (j < 0) continue;
+                double v, kab = 0.0, mab = 0.0;
+                if (KM) {
+                    kab = kr[u][b];
+                    mab = vol[u] / 20.0 * (b == a ? 2.0 : 1.0);
+                    v = rho * kab + mab;
+                } else {
+                    v = kr[u][b];
+                }
+#pragma unroll
+                for (int s2 = 0; s2 < MAXS; ++s2)
+                    if (cols[s2] == j) {
+                        acc[s2] += v;
+                        if (KM) {
+                            aK[s2] += kab;
+                            aM[s2] += mab;
+                        }
+                    }
+            }
         }
     }
 #pragma unroll
     for (int q = 0; q < MAXS; ++q)
-        if (q < len && (q % kNumG) == lane) {
+        if (q < len) {
             val[rb + q] = acc[q];
             if (KM) {
                 valK[rb + q] = aK[q];
                 valM[rb + q] = aM[q];
             }
         }
-    if (lane == 0) f[i] = fi;
+    f[i] = fi;
 }
 
 template <int MAXS>
-static void launch_numeric(ocp_ctx *ctx, ocp_system *sys, double rho, const int4 *tets, const double *xyz,
-                           const double4 *fe) {
-    const unsigned g = grid_for((int64_t)sys->n * kNumG, 256);
+static void launch_numeric(ocp_ctx *ctx, ocp_system *sys, double rho, const double *rec, const double *vol) {
+    const unsigned g = xcd_grid(grid_for(sys->n, 256));
     if (sys->valK.get())
         k_row_numeric<MAXS, true><<<g, 256, 0, ctx->stream>>>(
-            sys->n, rho, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
-            xyz, fe, sys->row_ptr.get(), sys->col.get(), sys->val.get(), sys->valK.get(), sys->valM.get(),
-            sys->f.get());
+            sys->n, rho, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(), rec, vol, sys->row_ptr.get(),
+            sys->col.get(), sys->val.get(), sys->valK.get(), sys->valM.get(), sys->f.get());
     else
         k_row_numeric<MAXS, false><<<g, 256, 0, ctx->stream>>>(
-            sys->n, rho, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
-            xyz, fe, sys->row_ptr.get(), sys->col.get(), sys->val.get(), nullptr, nullptr, sys->f.get());
+            sys->n, rho, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(), rec, nullptr,
+            sys->row_ptr.get(), sys->col.get(), sys->val.get(), nullptr, nullptr, sys->f.get());
     OCP_LAUNCH_CHECK();
 }
 
@@ -657,12 +736,25 @@ static void upload_target(ocp_ctx *ctx, const ocp_target *t, TargetUpload &up) {
     }
 }
 
+// element loads of every tet to fe[e]; with rec set (RecOut::rec), the
+// element records instead (REC 1, or 2 with ro.vol for separate K and M)
 static void launch_tet_load(ocp_ctx *ctx, const TargetUpload &up, const int4 *tets, int64_t nt, const double *xyz,
-                            double4 *fe) {
+                            double4 *fe, const RecOut &ro = RecOut{}) {
+    const unsigned g = xcd_grid(grid_for(nt * 4, kLoadBlock));
+    const int rec = ro.rec ? (ro.vol ? 2 : 1) : 0;
+    auto go = [&](auto table_only) {
+        constexpr bool TO = decltype(table_only)::value;
+        if (rec == 0)
+            k_tet_load<TO, 0><<<g, kLoadBlock, 0, ctx->stream>>>(tets, nt, xyz, up.dev, fe, ro);
+        else if (rec == 1)
+            k_tet_load<TO, 1><<<g, kLoadBlock, 0, ctx->stream>>>(tets, nt, xyz, up.dev, fe, ro);
+        else
+            k_tet_load<TO, 2><<<g, kLoadBlock, 0, ctx->stream>>>(tets, nt, xyz, up.dev, fe, ro);
+    };
     if (up.table_only)
-        k_tet_load<true><<<grid_for(nt * 4, kLoadBlock), kLoadBlock, 0, ctx->stream>>>(tets, nt, xyz, up.dev, fe);
+        go(std::true_type{});
     else
-        k_tet_load<false><<<grid_for(nt * 4, kLoadBlock), kLoadBlock, 0, ctx->stream>>>(tets, nt, xyz, up.dev, fe);
+        go(std::false_type{});
     OCP_LAUNCH_CHECK();
 }
 
@@ -683,8 +775,7 @@ static void compute_loads(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *m
 __global__ void __launch_bounds__(kAsmBlock) k_row_loads(int32_t n, const int32_t *__restrict__ vertex_of_dof,
                                                          const int32_t *__restrict__ inc_ptr,
                                                          const int32_t *__restrict__ inc,
-                                                         const int4 *__restrict__ tets,
-                                                         const double4 *__restrict__ fe, double *__restrict__ f,
+                                                         const double *__restrict__ fe, double *__restrict__ f,
                                                          int64_t ld) {
     const int i = blockIdx.x * kAsmBlock + threadIdx.x;
     if (i >= n) return;
@@ -692,29 +783,23 @@ __global__ void __launch_bounds__(kAsmBlock) k_row_loads(int32_t n, const int32_
     double fi = 0.0;
     int q = inc_ptr[vi];
     const int qe = inc_ptr[vi + 1];
-    // eight incident tets at a time: their ids, vertex lists and element
-    // loads are all requested before any is used (the sum keeps list order)
+    // eight incident tets at a time: their codes, then their element loads
+    // at this vertex, are all requested before any is used (the sum keeps
+    // list order)
     constexpr int U = 8;
     for (; q + U <= qe; q += U) {
-        int e[U];
-        int4 tv[U];
-        double4 fv[U];
+        int code[U];
+        double fv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) e[u] = inc[q + u];
+        for (int u = 0; u < U; ++u) code[u] = inc[q + u];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            tv[u] = tets[e[u]];
-            fv[u] = fe[e[u]];
-        }
+        for (int u = 0; u < U; ++u) fv[u] = fe[4 * (int64_t)(code[u] >> 2) + (code[u] & 3)];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            fi += (tv[u].x == vi) ? fv[u].x : (tv[u].y == vi) ? fv[u].y : (tv[u].z == vi) ? fv[u].z : fv[u].w;
+        for (int u = 0; u < U; ++u) fi += fv[u];
     }
     for (; q < qe; ++q) {
-        const int e = inc[q];
-        const int4 tv = tets[e];
-        const double4 fv = fe[e];
-        fi += (tv.x == vi) ? fv.x : (tv.y == vi) ? fv.y : (tv.z == vi) ? fv.z : fv.w;
+        const int code = inc[q];
+        fi += fe[4 * (int64_t)(code >> 2) + (code & 3)];
     }
     f[(int64_t)i * ld] = fi;
 }
@@ -722,8 +807,8 @@ __global__ void __launch_bounds__(kAsmBlock) k_row_loads(int32_t n, const int32_
 // f[i * ld] = sum over the tets of row i of their element load at its vertex
 void row_loads(ocp_ctx *ctx, const ocp_system *sys, const double4 *fe, double *f, int64_t ld) {
     k_row_loads<<<grid_for(sys->n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
-        sys->n, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(),
-        reinterpret_cast<const int4 *>(sys->tets_ref), fe, f, ld);
+        sys->n, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(), reinterpret_cast<const double *>(fe),
+        f, ld);
     OCP_LAUNCH_CHECK();
 }
 
@@ -792,23 +877,37 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
     OCP_LAUNCH_CHECK();
     pos.release();
 
-    // 4. symbolic rows: rows of up to kPadW entries in one pass into a padded
+    // 4. element records (dofs, element matrix, element loads) and vertex
+    // dofs, one pass over the tets
+    const bool km = (flags & OCP_KEEP_KM) != 0;
+    DevBuf<double> rec(ctx, (size_t)kRecD * nt);
+    DevBuf<double> vol;
+    if (km) vol.reset(ctx, (size_t)nt);
+    DevBuf<int4> tdof(ctx, (size_t)nt);
+    {
+        TargetUpload up;
+        upload_target(ctx, t, up);
+        launch_tet_load(ctx, up, tets, nt, mesh->xyz, nullptr,
+                        RecOut{sys->dof_of_vertex.get(), rho, rec.get(), vol.get(), tdof.get()});
+    }
+
+    // 5. symbolic rows: rows of up to kPadW entries in one pass into a padded
     // buffer; if any row is longer, count and fill again with kRowCap slots
     DevBuf<int32_t> rcnt(ctx, (size_t)n + 1);
     DevBuf<int32_t> pad(ctx, (size_t)n * kPadW);
     fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
-    k_row_symbolic<kPadW><<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
-        0, sys->n, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
-        rcnt.get(), nullptr, nullptr, pad.get(), ctx->dev_flag);
+    k_row_symbolic<kPadW><<<xcd_grid(grid_for(n, kAsmBlock)), kAsmBlock, 0, ctx->stream>>>(
+        0, sys->n, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(), tdof.get(), rcnt.get(), nullptr,
+        nullptr, pad.get(), ctx->dev_flag);
     OCP_LAUNCH_CHECK();
     read_back(ctx, &fl, ctx->dev_flag, sizeof(fl));
     const bool long_rows = (fl & 128) != 0;
     if (long_rows) {
         pad.release();
         fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
-        k_row_symbolic<kRowCap><<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
-            0, sys->n, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
-            rcnt.get(), nullptr, nullptr, nullptr, ctx->dev_flag);
+        k_row_symbolic<kRowCap><<<xcd_grid(grid_for(n, kAsmBlock)), kAsmBlock, 0, ctx->stream>>>(
+            0, sys->n, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(), tdof.get(), rcnt.get(), nullptr,
+            nullptr, nullptr, ctx->dev_flag);
         OCP_LAUNCH_CHECK();
         read_back(ctx, &fl, ctx->dev_flag, sizeof(fl));
         if (fl & 4) fail(OCP_ERR_UNSUPPORTED, "an assembled row has more than 128 entries");
@@ -817,9 +916,9 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
     sys->nnz = scan_exclusive(ctx, rcnt.get(), sys->row_ptr.get(), n);
     sys->col.reset(ctx, (size_t)sys->nnz);
     if (long_rows) {
-        k_row_symbolic<kRowCap><<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
-            1, sys->n, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
-            nullptr, sys->row_ptr.get(), sys->col.get(), nullptr, ctx->dev_flag);
+        k_row_symbolic<kRowCap><<<xcd_grid(grid_for(n, kAsmBlock)), kAsmBlock, 0, ctx->stream>>>(
+            1, sys->n, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(), tdof.get(), nullptr,
+            sys->row_ptr.get(), sys->col.get(), nullptr, ctx->dev_flag);
     } else {
         k_pad_to_csr<<<grid_for((int64_t)n * kPadW, 256), 256, 0, ctx->stream>>>(sys->n, pad.get(),
                                                                                   sys->row_ptr.get(), sys->col.get());
@@ -829,27 +928,23 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
     const int maxlen = long_rows ? kRowCap : kPadW;
     rcnt.release();
 
-    // 5. element loads
-    TargetUpload up;
-    upload_target(ctx, t, up);
-    DevBuf<double4> fe(ctx, (size_t)nt);
-    launch_tet_load(ctx, up, tets, nt, mesh->xyz, fe.get());
+    tdof.release();
 
     // 6. numeric rows
     sys->val.reset(ctx, (size_t)sys->nnz);
     sys->f.reset(ctx, (size_t)n);
-    if (flags & OCP_KEEP_KM) {
+    if (km) {
         sys->valK.reset(ctx, (size_t)sys->nnz);
         sys->valM.reset(ctx, (size_t)sys->nnz);
     }
     if (maxlen <= 16 || max_row_len(ctx, sys) <= 16)
-        launch_numeric<16>(ctx, sys, rho, tets, mesh->xyz, fe.get());
+        launch_numeric<16>(ctx, sys, rho, rec.get(), vol.get());
     else if (max_row_len(ctx, sys) <= 32)
-        launch_numeric<32>(ctx, sys, rho, tets, mesh->xyz, fe.get());
+        launch_numeric<32>(ctx, sys, rho, rec.get(), vol.get());
     else if (max_row_len(ctx, sys) <= 64)
-        launch_numeric<64>(ctx, sys, rho, tets, mesh->xyz, fe.get());
+        launch_numeric<64>(ctx, sys, rho, rec.get(), vol.get());
     else
-        launch_numeric<128>(ctx, sys, rho, tets, mesh->xyz, fe.get());
+        launch_numeric<128>(ctx, sys, rho, rec.get(), vol.get());
     OCP_LAUNCH_CHECK();
     // sliced-ELL copy for the solve phase
     system_sell(ctx, sys);

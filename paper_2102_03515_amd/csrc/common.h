@@ -138,20 +138,6 @@ inline unsigned grid_for(int64_t n, int threads) {
     return (unsigned)(g < 1 ? 1 : g);
 }
 
-// Workgroups are handed to the chip's 8 XCDs in turn (workgroup b to XCD
-// b mod 8) and every XCD has its own L2.  A kernel whose neighbouring rows
-// gather the same data launches xcd_grid(nb) workgroups and works on logical
-// block xcd_block(nb): XCD x then runs logical blocks x*per .. x*per+per-1 in
-// order (per = grid / 8), so rows that share gathered data share an L2.
-// xcd_block returns -1 for the padding workgroups.
-constexpr unsigned kXcds = 8;
-inline unsigned xcd_grid(unsigned nb) { return (nb + kXcds - 1) / kXcds * kXcds; }
-__device__ __forceinline__ int xcd_block(unsigned nb) {
-    const unsigned per = gridDim.x / kXcds;
-    const unsigned l = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
-    return l < nb ? (int)l : -1;
-}
-
 // --------------------------------------------------------------- primitives
 // Exclusive prefix sum of n int32 counts into out[0..n] (out[n] = total).
 // Returns the total (synchronizes).

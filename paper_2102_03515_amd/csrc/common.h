@@ -35,7 +35,7 @@ struct Error {
 
 // Number of partial-sum slots a grid reduction may use (fixed grid size for
 // the reduction kernels, so their summation order never depends on the GPU).
-constexpr int kRedBlocks = 16384;
+constexpr int kRedBlocks = 32768;
 constexpr int kRedSlots = 8;  // independent reductions that may be in flight
 
 // Device-resident scalars of one CG solve (one per context).

@@ -136,9 +136,15 @@ __device__ __forceinline__ void store_partial2(double2 v, double *partials) {
 // valid in thread 0).
 template <int BLOCK>
 __device__ __forceinline__ double sum_partials(const double *partials, unsigned nb, int stride = 1, int off = 0) {
-    double s = 0.0;
-    for (unsigned b = threadIdx.x; b < nb; b += BLOCK) s += partials[(size_t)b * stride + off];
-    return block_sum<BLOCK>(s);
+    // four independent loads in flight per thread
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    unsigned b = threadIdx.x;
+    for (; b + 3 * BLOCK < nb; b += 4 * BLOCK) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s[u] += partials[(size_t)(b + u * BLOCK) * stride + off];
+    }
+    for (; b < nb; b += BLOCK) s[0] += partials[(size_t)b * stride + off];
+    return block_sum<BLOCK>((s[0] + s[1]) + (s[2] + s[3]));
 }
 
 }  // namespace dev
@@ -192,6 +198,7 @@ __device__ __forceinline__ void cg_after_precond(CgScalars *cg, double rz) {
 // issues the loads of a whole chunk of its row before consuming them.
 namespace ocp {
 
+constexpr int kFinBlock = 1024;   // one-block finalize kernels over the partials of a SELL pass
 constexpr int kSellC = 64;
 constexpr int kSellChunk = 16;
 
@@ -200,9 +207,12 @@ struct SellLaunch {
     int slices_per_block;   // multiple of kBlock / kSellC
 };
 
+// One slice per wavefront while the grid stays within the partial slots of
+// a reduction (kRedBlocks - 1 blocks; the last slot may hold the total):
+// short per-wave work keeps the most independent loads in flight.
 inline SellLaunch sell_launch(int64_t nslices) {
     constexpr int WPB = kBlock / kSellC;
-    const int64_t max_blocks = kMaxPartials / 2;
+    const int64_t max_blocks = kRedBlocks - 1;
     int64_t spb = (nslices + max_blocks - 1) / max_blocks;
     spb = ((spb + WPB - 1) / WPB) * WPB;
     if (spb < WPB) spb = WPB;

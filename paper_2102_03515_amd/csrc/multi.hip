@@ -28,7 +28,6 @@ namespace ocp {
 
 constexpr int kMaxCols = 64;
 constexpr int kBlkMaxBlocks = 4096;
-constexpr int kFinBlock = 1024;
 
 // Per-column CG scalars of the block solve (device).
 struct CgBlock {

@@ -50,9 +50,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_spmv_pq_sell(int32_t n, int64_t n
 }
 
 // alpha = gamma / (p.q) from the partials of k_cg_spmv_pq_sell
-__global__ void __launch_bounds__(kBlock) k_fin_alpha(unsigned nb, const double *partials, CgScalars *cg) {
+__global__ void __launch_bounds__(kFinBlock) k_fin_alpha(unsigned nb, const double *partials, CgScalars *cg) {
     if (cg->flag) return;
-    const double tot = dev::sum_partials<kBlock>(partials, nb);
+    const double tot = dev::sum_partials<kFinBlock>(partials, nb);
     if (threadIdx.x == 0) {
         cg->pq = tot;
         if (!(tot > 0.0) || !isfinite(tot)) {
@@ -81,8 +81,8 @@ __global__ void __launch_bounds__(kBlock) k_resid2_sell(int32_t n, int64_t nslic
     dev::store_partial(acc, partials);
 }
 
-__global__ void __launch_bounds__(kBlock) k_fin_store(unsigned nb, const double *partials, double *out) {
-    const double tot = dev::sum_partials<kBlock>(partials, nb);
+__global__ void __launch_bounds__(kFinBlock) k_fin_store(unsigned nb, const double *partials, double *out) {
+    const double tot = dev::sum_partials<kFinBlock>(partials, nb);
     if (threadIdx.x == 0) *out = tot;
 }
 
@@ -402,7 +402,7 @@ static void solve_iterate(SolveState &S, int iters) {
                                                                  A.sw.get(), A.col.get(), A.val.get(), S.p.get(),
                                                                  S.q.get(), cg, part0);
         prof_end(ctx, pr);
-        k_fin_alpha<<<1, kBlock, 0, ctx->stream>>>(LS.blocks, part0, cg);
+        k_fin_alpha<<<1, kFinBlock, 0, ctx->stream>>>(LS.blocks, part0, cg);
         double *znew = S.z.get();
         if (S.h) {
             with_first_step(S, [&](auto fs) {
@@ -446,7 +446,7 @@ static int solve_finish(SolveState &S, double *u, ocp_solve_info *info) {
     OCP_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     k_resid2_sell<<<LS.blocks, kBlock, 0, ctx->stream>>>(n, A.nslices, LS.slices_per_block, A.sp.get(), A.sw.get(),
                                                          A.col.get(), A.val.get(), S.x.get(), S.f, part2);
-    k_fin_store<<<1, kBlock, 0, ctx->stream>>>(LS.blocks, part2, part2 + kRedBlocks - 1);
+    k_fin_store<<<1, kFinBlock, 0, ctx->stream>>>(LS.blocks, part2, part2 + kRedBlocks - 1);
     OCP_LAUNCH_CHECK();
     k_scatter<<<grid_for(sys->nv, 256), 256, 0, ctx->stream>>>(sys->nv, sys->dof_of_vertex.get(), S.x.get(), u);
     OCP_LAUNCH_CHECK();

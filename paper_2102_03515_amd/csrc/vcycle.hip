@@ -188,9 +188,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_rz(int32_t n, int iters, const do
     dev::store_partial(dev::block_sum<kBlock>(acc), partials);
 }
 
-__global__ void __launch_bounds__(kBlock) k_vc_fin_rz(unsigned nb, const double *partials, CgScalars *cg) {
+__global__ void __launch_bounds__(kFinBlock) k_vc_fin_rz(unsigned nb, const double *partials, CgScalars *cg) {
     if (cg->flag) return;
-    const double tot = dev::sum_partials<kBlock>(partials, nb);
+    const double tot = dev::sum_partials<kFinBlock>(partials, nb);
     if (threadIdx.x == 0) dev::cg_after_precond(cg, tot);
 }
 
@@ -251,7 +251,7 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
         if (cg) {
             const RowLaunch LV = vec_launch(l0.n);
             k_cg_rz<<<LV.blocks, kBlock, 0, s>>>(l0.n, LV.iters, r_in, z_out, cg, part);
-            k_vc_fin_rz<<<1, kBlock, 0, s>>>(LV.blocks, part, cg);
+            k_vc_fin_rz<<<1, kFinBlock, 0, s>>>(LV.blocks, part, cg);
             OCP_LAUNCH_CHECK();
         }
         return;
@@ -406,7 +406,7 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
             up(l, reinterpret_cast<const T *>(W.lv[l].vb.get()), reinterpret_cast<T *>(W.lv[l].vx.get()), false);
     }
     if (cg) {
-        k_vc_fin_rz<<<1, kBlock, 0, s>>>(fin_nb, part, cg);
+        k_vc_fin_rz<<<1, kFinBlock, 0, s>>>(fin_nb, part, cg);
         OCP_LAUNCH_CHECK();
     }
 }

@@ -150,6 +150,8 @@ typedef struct {
     const double *f;            /* device [n_dofs] */
     const int32_t *dof_of_vertex; /* device [n_vertices], -1 on Gamma */
     const int32_t *vertex_of_dof; /* device [n_dofs] */
+    int32_t sell_coded;         /* 1: the solve-phase sliced-ELL copy reads 4-bit column codes
+                                   (every 64-row slice has <= 16 distinct col - row offsets) */
 } ocp_system_view;
 int ocp_system_get_view(const ocp_system *sys, ocp_system_view *view);
 

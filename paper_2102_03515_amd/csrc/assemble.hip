@@ -1075,5 +1075,6 @@ extern "C" int ocp_system_get_view(const ocp_system *sys, ocp_system_view *v) {
     v->f = sys->f.get();
     v->dof_of_vertex = sys->dof_of_vertex.get();
     v->vertex_of_dof = sys->vertex_of_dof.get();
+    v->sell_coded = sys->sell.code.get() ? 1 : 0;
     return OCP_OK;
 }

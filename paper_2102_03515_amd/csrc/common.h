@@ -133,6 +133,15 @@ struct DevBuf {
 void read_back(ocp_ctx *ctx, void *host, const void *dev, size_t bytes);
 void sync(ocp_ctx *ctx);
 
+// Column source of a sliced-ELL pass: plain columns, or (code != nullptr)
+// 4-bit codes into the slice's dictionary of column offsets.
+struct SellCols {
+    const int32_t *col;
+    const uint32_t *code;
+    const int32_t *cp;
+    const int32_t *dict;
+};
+
 inline unsigned grid_for(int64_t n, int threads) {
     int64_t g = (n + threads - 1) / threads;
     return (unsigned)(g < 1 ? 1 : g);

@@ -200,6 +200,7 @@ namespace ocp {
 
 constexpr int kFinBlock = 1024;   // one-block finalize kernels over the partials of a SELL pass
 constexpr int kSellC = 64;
+constexpr int kSellDict = 16;     // column offsets per slice that 4-bit codes can name
 constexpr int kSellChunk = 16;
 
 struct SellLaunch {
@@ -244,6 +245,38 @@ __device__ __forceinline__ VT sell_row(const int32_t *__restrict__ col, const VT
 #pragma unroll
         for (int j = 0; j < kSellChunk; ++j)
             if (j0 + j < w) acc += v[j] * xf(c[j]);
+    }
+    return acc;
+}
+
+// sell_row over either column source; the coded form adds the same terms in
+// the same order (the same result bits) and reads half a byte per entry
+// instead of four.  w is uniform over the wavefront, so every lane takes
+// part in each shuffle.
+template <typename VT, typename XF>
+__device__ __forceinline__ VT sell_row_c(const SellCols &C, int64_t slice, int row, int n,
+                                         const VT *__restrict__ val, int64_t base, int w, XF xf) {
+    if (!C.code) return sell_row(C.col, val, base, w, xf);
+    const int lane = threadIdx.x & 63;
+    const int rr = row < n ? row : 0;   // lanes past the last row hold offset 0 from row 0
+    const int dl = C.dict[slice * kSellDict + (lane & (kSellDict - 1))];
+    const int64_t cb = C.cp[slice] + lane;
+    VT acc = VT(0);
+    for (int j0 = 0; j0 < w; j0 += kSellChunk) {
+        uint32_t cw[kSellChunk / 8];
+        VT v[kSellChunk];
+#pragma unroll
+        for (int q = 0; q < kSellChunk / 8; ++q)
+            if (j0 + 8 * q < w) cw[q] = ldnt(C.code + cb + (int64_t)(j0 / 8 + q) * kSellC);
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j)
+            if (j0 + j < w) v[j] = ldnt(val + base + (int64_t)(j0 + j) * kSellC);
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j)
+            if (j0 + j < w) {
+                const int c = (int)((cw[j >> 3] >> (4 * (j & 7))) & 15u);
+                acc += v[j] * xf(rr + __shfl(dl, c, 64));
+            }
     }
     return acc;
 }

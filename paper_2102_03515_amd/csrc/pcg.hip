@@ -19,11 +19,11 @@ namespace ocp {
 // ------------------------------------------------------------------ SpMV
 // y = A x on the sliced-ELL copy
 __global__ void __launch_bounds__(kBlock) k_spmv_sell(int32_t n, int64_t nslices, int spb, const int32_t *__restrict__ sp,
-                                                      const int32_t *__restrict__ sw, const int32_t *__restrict__ col,
+                                                      const int32_t *__restrict__ sw, SellCols col,
                                                       const double *__restrict__ val, const double *__restrict__ x,
                                                       double *__restrict__ y) {
     OCP_SELL_BEGIN(nslices, spb)
-    const double s = dev::sell_row(col, val, base, w, [&](int c) { return x[c]; });
+    const double s = dev::sell_row_c(col, slice, row, n, val, base, w, [&](int c) { return x[c]; });
     if (row < n) y[row] = s;
     OCP_SELL_END()
 }
@@ -31,15 +31,14 @@ __global__ void __launch_bounds__(kBlock) k_spmv_sell(int32_t n, int64_t nslices
 // q = A p and alpha = gamma / (p.q), sliced-ELL fine matrix
 __global__ void __launch_bounds__(kBlock) k_cg_spmv_pq_sell(int32_t n, int64_t nslices, int spb,
                                                             const int32_t *__restrict__ sp,
-                                                            const int32_t *__restrict__ sw,
-                                                            const int32_t *__restrict__ col,
+                                                            const int32_t *__restrict__ sw, SellCols col,
                                                             const double *__restrict__ val,
                                                             const double *__restrict__ p, double *__restrict__ q,
                                                             CgScalars *cg, double *partials) {
     if (cg->flag) return;
     double acc = 0.0;
     OCP_SELL_BEGIN(nslices, spb)
-    const double s = dev::sell_row(col, val, base, w, [&](int c) { return p[c]; });
+    const double s = dev::sell_row_c(col, slice, row, n, val, base, w, [&](int c) { return p[c]; });
     if (row < n) {
         q[row] = s;
         acc += s * p[row];
@@ -66,12 +65,12 @@ __global__ void __launch_bounds__(kFinBlock) k_fin_alpha(unsigned nb, const doub
 
 // sum_i (f_i - (A x)_i)^2 on the sliced-ELL copy
 __global__ void __launch_bounds__(kBlock) k_resid2_sell(int32_t n, int64_t nslices, int spb, const int32_t *__restrict__ sp,
-                                                        const int32_t *__restrict__ sw, const int32_t *__restrict__ col,
+                                                        const int32_t *__restrict__ sw, SellCols col,
                                                         const double *__restrict__ val, const double *__restrict__ x,
                                                         const double *__restrict__ f, double *partials) {
     double acc = 0.0;
     OCP_SELL_BEGIN(nslices, spb)
-    const double s = dev::sell_row(col, val, base, w, [&](int c) { return x[c]; });
+    const double s = dev::sell_row_c(col, slice, row, n, val, base, w, [&](int c) { return x[c]; });
     if (row < n) {
         const double d = f[row] - s;
         acc += d * d;
@@ -399,7 +398,7 @@ static void solve_iterate(SolveState &S, int iters) {
     for (int k = 0; k < iters; ++k) {
         const int pr = prof_begin(ctx, OCP_KERNEL_CG_SPMV);
         k_cg_spmv_pq_sell<<<LS.blocks, kBlock, 0, ctx->stream>>>(n, A.nslices, LS.slices_per_block, A.sp.get(),
-                                                                 A.sw.get(), A.col.get(), A.val.get(), S.p.get(),
+                                                                 A.sw.get(), sell_cols(A), A.val.get(), S.p.get(),
                                                                  S.q.get(), cg, part0);
         prof_end(ctx, pr);
         k_fin_alpha<<<1, kFinBlock, 0, ctx->stream>>>(LS.blocks, part0, cg);
@@ -445,7 +444,7 @@ static int solve_finish(SolveState &S, double *u, ocp_solve_info *info) {
     const SellLaunch LS = sell_launch(A.nslices);
     OCP_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     k_resid2_sell<<<LS.blocks, kBlock, 0, ctx->stream>>>(n, A.nslices, LS.slices_per_block, A.sp.get(), A.sw.get(),
-                                                         A.col.get(), A.val.get(), S.x.get(), S.f, part2);
+                                                         sell_cols(A), A.val.get(), S.x.get(), S.f, part2);
     k_fin_store<<<1, kFinBlock, 0, ctx->stream>>>(LS.blocks, part2, part2 + kRedBlocks - 1);
     OCP_LAUNCH_CHECK();
     k_scatter<<<grid_for(sys->nv, 256), 256, 0, ctx->stream>>>(sys->nv, sys->dof_of_vertex.get(), S.x.get(), u);
@@ -691,7 +690,7 @@ extern "C" int ocp_spmv(ocp_ctx *ctx, const ocp_system *sys, const double *x, do
         const Sell &A = system_sell(ctx, sys);
         const SellLaunch L = sell_launch(A.nslices);
         k_spmv_sell<<<L.blocks, kBlock, 0, ctx->stream>>>(sys->n, A.nslices, L.slices_per_block, A.sp.get(),
-                                                          A.sw.get(), A.col.get(), A.val.get(), x, y);
+                                                          A.sw.get(), sell_cols(A), A.val.get(), x, y);
         OCP_LAUNCH_CHECK();
     });
 }

@@ -1,4 +1,7 @@
 // Conversion of the fine-level CSR matrix to sliced ELLPACK (64-row slices).
+#include <algorithm>
+#include <climits>
+
 #include "kernels.h"
 #include "system.h"
 
@@ -60,6 +63,84 @@ __global__ void k_sell_fill(int32_t n, int64_t nslices, const int32_t *__restric
     }
 }
 
+// Column codes, one wavefront per slice.  The slice's distinct offsets
+// col - row are found smallest first (a wavefront minimum over the entries
+// not yet named, repeated), so the dictionary is ascending; more than
+// kSellDict of them sets *overflow and leaves the slice uncoded.  MAXW bounds
+// the slice width held in registers.
+template <int MAXW>
+__device__ __forceinline__ void sell_code_slice(int64_t s, int w, int rr, int lane, int64_t base,
+                                                const int32_t *__restrict__ scol, const int32_t *__restrict__ cp,
+                                                uint32_t *__restrict__ code, int32_t *__restrict__ dict,
+                                                int32_t *overflow) {
+    int d[MAXW];
+    uint32_t done = 0;   // entries already named
+#pragma unroll
+    for (int j = 0; j < MAXW; ++j) d[j] = j < w ? scol[base + (int64_t)j * kSellC] - rr : 0;
+    int nd = 0, mine = 0;
+    for (;;) {
+        int m = INT_MAX;
+#pragma unroll
+        for (int j = 0; j < MAXW; ++j)
+            if (j < w && !((done >> j) & 1u) && d[j] < m) m = d[j];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int v = __shfl_xor(m, o, 64);
+            m = v < m ? v : m;
+        }
+        if (m == INT_MAX) break;   // every entry named
+        if (nd == kSellDict) {
+            if (lane == 0) atomicOr(overflow, 1);
+            return;
+        }
+        if (lane == nd) mine = m;
+#pragma unroll
+        for (int j = 0; j < MAXW; ++j)
+            if (j < w && !((done >> j) & 1u) && d[j] == m) {
+                done |= 1u << j;
+                d[j] = nd;   // the entry's code from here on
+            }
+        ++nd;
+    }
+    if (lane < kSellDict) dict[s * kSellDict + lane] = lane < nd ? mine : 0;
+    const int64_t cb = cp[s] + lane;
+#pragma unroll
+    for (int q = 0; q < (MAXW + 7) / 8; ++q) {
+        if (q * 8 >= w) break;
+        uint32_t word = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = q * 8 + u;
+            if (j < w) word |= (uint32_t)d[j] << (4 * u);
+        }
+        code[cb + (int64_t)q * kSellC] = word;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_sell_code(int32_t n, int64_t nslices, const int32_t *__restrict__ sp,
+                                                   const int32_t *__restrict__ sw, const int32_t *__restrict__ scol,
+                                                   const int32_t *__restrict__ cp, uint32_t *__restrict__ code,
+                                                   int32_t *__restrict__ dict, int32_t *overflow) {
+    const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSellC;
+    const int lane = threadIdx.x & 63;
+    if (s >= nslices) return;   // uniform over the wavefront
+    const int w = sw[s];
+    const int row = (int)(s * kSellC) + lane;
+    const int rr = row < n ? row : 0;
+    const int64_t base = sp[s] + lane;
+    if (w <= 16)
+        sell_code_slice<16>(s, w, rr, lane, base, scol, cp, code, dict, overflow);
+    else if (w <= 32)
+        sell_code_slice<32>(s, w, rr, lane, base, scol, cp, code, dict, overflow);
+    else if (lane == 0)
+        atomicOr(overflow, 1);   // wider slices stay uncoded
+}
+
+__global__ void k_sell_code_words(int64_t nslices, const int32_t *__restrict__ sw, int32_t *__restrict__ words) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nslices) words[s] = (sw[s] + 7) / 8 * kSellC;
+}
+
 // Build the slice structure and column array (values follow with sell_values).
 void sell_build(ocp_ctx *ctx, Sell &S, int32_t n, const int32_t *rp, const int32_t *col, const double *val) {
     S.n = n;
@@ -77,6 +158,25 @@ void sell_build(ocp_ctx *ctx, Sell &S, int32_t n, const int32_t *rp, const int32
     k_sell_fill<double><<<grid_for((int64_t)S.nslices * kSellC, 256), 256, 0, ctx->stream>>>(
         n, S.nslices, rp, col, val, S.sp.get(), S.sw.get(), S.col.get(), S.val.get());
     OCP_LAUNCH_CHECK();
+    // column codes (kept only if every slice fits the dictionary)
+    DevBuf<int32_t> words(ctx, (size_t)S.nslices + 1);
+    k_sell_code_words<<<grid_for(S.nslices, 256), 256, 0, ctx->stream>>>(S.nslices, S.sw.get(), words.get());
+    OCP_LAUNCH_CHECK();
+    S.cp.reset(ctx, (size_t)S.nslices + 1);
+    const int64_t nwords = scan_exclusive(ctx, words.get(), S.cp.get(), S.nslices);
+    S.code.reset(ctx, (size_t)std::max<int64_t>(nwords, 1));
+    S.dict.reset(ctx, (size_t)S.nslices * kSellDict);
+    fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
+    k_sell_code<<<grid_for((int64_t)S.nslices * kSellC, 256), 256, 0, ctx->stream>>>(
+        n, S.nslices, S.sp.get(), S.sw.get(), S.col.get(), S.cp.get(), S.code.get(), S.dict.get(), ctx->dev_flag);
+    OCP_LAUNCH_CHECK();
+    int32_t over = 0;
+    read_back(ctx, &over, ctx->dev_flag, sizeof(over));
+    if (over) {
+        S.code.release();
+        S.cp.release();
+        S.dict.release();
+    }
 }
 
 // Single-precision values of an existing slice structure.

@@ -14,8 +14,16 @@ struct Sell {
     DevBuf<int32_t> sw;    // [nslices]   slice width
     DevBuf<int32_t> col;   // [nnz_padded]
     DevBuf<double> val;    // [nnz_padded]
+    // Column codes, kept when every slice's column offsets (col - row) take
+    // at most kSellDict distinct values: entry j of lane l of slice s has
+    // column row + dict[s][c], c the 4-bit code j % 8 of dword
+    // code[cp[s] + (j / 8) * 64 + l]; dict[s] is ascending.  Empty otherwise.
+    DevBuf<uint32_t> code;   // [cp[nslices]]
+    DevBuf<int32_t> cp;      // [nslices+1] dword offset of each slice
+    DevBuf<int32_t> dict;    // [nslices][kSellDict]
 };
 void sell_build(ocp_ctx *ctx, Sell &S, int32_t n, const int32_t *rp, const int32_t *col, const double *val);
+inline SellCols sell_cols(const Sell &S) { return SellCols{S.col.get(), S.code.get(), S.cp.get(), S.dict.get()}; }
 void sell_values32(ocp_ctx *ctx, const Sell &S, const int32_t *rp, const float *val32, DevBuf<float> &out);
 }  // namespace ocp
 

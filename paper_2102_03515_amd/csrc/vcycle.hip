@@ -112,13 +112,13 @@ __global__ void __launch_bounds__(kBlock) k_smooth(int32_t n, int iters, const i
 template <typename T, typename BT, typename OT, bool GDB, int MODE, bool DOT>
 __global__ void __launch_bounds__(kBlock) k_smooth_sell(int32_t n, int64_t nslices, int spb,
                                                         const int32_t *__restrict__ sp, const int32_t *__restrict__ sw,
-                                                        const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                        SellCols col, const T *__restrict__ val,
                                                         SmoothOps<T, BT, OT, GDB, MODE, DOT> ops, CgScalars *cg,
                                                         double *partials) {
     if (cg && cg->flag) return;
     double acc = 0.0;
     OCP_SELL_BEGIN(nslices, spb)
-    const T s = dev::sell_row(col, val, base, w, [&](int c) { return ops.gather(c); });
+    const T s = dev::sell_row_c(col, slice, row, n, val, base, w, [&](int c) { return ops.gather(c); });
     if (row < n) acc += ops.finish(row, s);
     OCP_SELL_END()
     if (DOT) dev::store_partial(dev::block_sum<kBlock>(acc), partials);
@@ -265,7 +265,7 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
         if (l == 0) {
             nb = LSL.blocks;
             k_smooth_sell<<<LSL.blocks, kBlock, 0, s>>>(S.n, S.nslices, LSL.slices_per_block, S.sp.get(), S.sw.get(),
-                                                         S.col.get(), sval, ops, cg, dot ? part : nullptr);
+                                                         sell_cols(S), sval, ops, cg, dot ? part : nullptr);
         } else {
             const auto a = arrays<T>(cur);
             const RowLaunch LA = row_launch(cur.n, cur.gA);

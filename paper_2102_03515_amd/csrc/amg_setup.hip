@@ -147,11 +147,26 @@ __global__ void __launch_bounds__(256) k_mis_m1(int32_t n, const int32_t *__rest
     if (i >= n) return;
     if (need && need[i] != round) return;   // uniform over the group
     uint64_t m = 0;
-    for (int k = rp[i] + lane; k < rp[i + 1]; k += G) {
-        const int j = col[k];
-        if (is_strong(strong, k, j, i)) {
-            const uint64_t kj = mis_key(j, state[j], salt);
-            m = kj > m ? kj : m;
+    const int ke = rp[i + 1];
+    // U of this lane's entries at a time: columns, then their states, all
+    // requested before any is used
+    constexpr int U = 4;
+    for (int k0 = rp[i] + lane; k0 < ke; k0 += U * G) {
+        int j[U];
+        int8_t st[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * G < ke) j[u] = col[k0 + u * G];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * G < ke) st[u] = state[j[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * G;
+            if (k < ke && is_strong(strong, k, j[u], i)) {
+                const uint64_t kj = mis_key(j[u], st[u], salt);
+                m = kj > m ? kj : m;
+            }
         }
     }
     m = group_max_u64<G>(m);
@@ -188,11 +203,21 @@ __global__ void __launch_bounds__(256) k_mis_m2(int32_t n, const int32_t *__rest
     if (i >= n) return;
     if (state[i] != 0) return;   // uniform over the group
     uint64_t m = 0;
-    for (int k = rp[i] + lane; k < rp[i + 1]; k += G) {
-        const int j = col[k];
-        if (is_strong(strong, k, j, i)) {
-            const uint64_t v = m1[j];
-            m = v > m ? v : m;
+    const int ke = rp[i + 1];
+    constexpr int U = 4;   // as in k_mis_m1
+    for (int k0 = rp[i] + lane; k0 < ke; k0 += U * G) {
+        int j[U];
+        uint64_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * G < ke) j[u] = col[k0 + u * G];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * G < ke) v[u] = m1[j[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * G;
+            if (k < ke && is_strong(strong, k, j[u], i)) m = v[u] > m ? v[u] : m;
         }
     }
     m = group_max_u64<G>(m);
@@ -232,14 +257,25 @@ __global__ void k_agg1(int32_t n, const int32_t *__restrict__ rp, const int32_t 
     }
     uint64_t best = 0;
     int bj = -1;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
-        const int j = col[k];
-        if (is_strong(strong, k, j, i)) {
-            if (state[j] == 1) {
-                const uint64_t kj = mis_key(j, 1, salt);
+    const int ke = rp[i + 1];
+    constexpr int U = 8;   // columns, then their states, requested together
+    for (int k0 = rp[i]; k0 < ke; k0 += U) {
+        int j[U];
+        int8_t st[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u < ke) j[u] = col[k0 + u];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u < ke) st[u] = state[j[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u;
+            if (k < ke && is_strong(strong, k, j[u], i) && st[u] == 1) {
+                const uint64_t kj = mis_key(j[u], 1, salt);
                 if (kj > best) {
                     best = kj;
-                    bj = j;
+                    bj = j[u];
                 }
             }
         }
@@ -325,9 +361,22 @@ __global__ void k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp, const in
     const int i = (int)dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= m) return;
     int64_t s = 0;
-    for (int k = arp[i]; k < arp[i + 1]; ++k) {
-        const int c = acol[k];
-        s += brp[c + 1] - brp[c];
+    const int ke = arp[i + 1];
+    constexpr int U = 8;   // columns, then their row extents, requested together
+    for (int k0 = arp[i]; k0 < ke; k0 += U) {
+        int c[U], b0[U], b1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u < ke) c[u] = acol[k0 + u];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u < ke) {
+                b0[u] = brp[c[u]];
+                b1[u] = brp[c[u] + 1];
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u < ke) s += b1[u] - b0[u];
     }
     ub[i] = (int32_t)(s > INT32_MAX ? INT32_MAX : s);
 }
@@ -509,29 +558,50 @@ __global__ void __launch_bounds__(256) k_ap_tent(int32_t m, const int32_t *__res
         acc[q] = 0.0;
     }
     int nk = 0;
-    for (int k = arp[i]; k < arp[i + 1]; ++k) {
-        const int j = acol[k];
-        const int J = agg[j];
-        const double v = NUMERIC ? aval[k] * pt[j] : 0.0;
-        bool found = false;
+    const int ke = arp[i + 1];
+    // U entries at a time: their columns, then the aggregates and tentative
+    // values of those columns, are requested before any is used (entries are
+    // still taken in row order)
+    constexpr int U = 8;
+    for (int k0 = arp[i]; k0 < ke; k0 += U) {
+        int j[U], J[U];
+        double av[U], pv[U];
 #pragma unroll
-        for (int q = 0; q < S; ++q)
-            if (keys[q] == J) {
-                acc[q] += v;
-                found = true;
+        for (int u = 0; u < U; ++u)
+            if (k0 + u < ke) {
+                j[u] = acol[k0 + u];
+                if (NUMERIC) av[u] = aval[k0 + u];
             }
-        if (!found) {
-            if (nk == S) {
-                atomicOr(flag, 32);
-                return;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u < ke) {
+                J[u] = agg[j[u]];
+                if (NUMERIC) pv[u] = pt[j[u]];
             }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (k0 + u >= ke) break;
+            const double v = NUMERIC ? av[u] * pv[u] : 0.0;
+            bool found = false;
 #pragma unroll
             for (int q = 0; q < S; ++q)
-                if (q == nk) {
-                    keys[q] = J;
-                    acc[q] = v;
+                if (keys[q] == J[u]) {
+                    acc[q] += v;
+                    found = true;
                 }
-            ++nk;
+            if (!found) {
+                if (nk == S) {
+                    atomicOr(flag, 32);
+                    return;
+                }
+#pragma unroll
+                for (int q = 0; q < S; ++q)
+                    if (q == nk) {
+                        keys[q] = J[u];
+                        acc[q] = v;
+                    }
+                ++nk;
+            }
         }
     }
     if (!NUMERIC) {

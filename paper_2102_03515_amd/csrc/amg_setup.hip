@@ -437,6 +437,7 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
                                                    int32_t *__restrict__ ccol, double *__restrict__ cval,
                                                    int32_t *flag, int32_t *retry, int32_t *nretry) {
     constexpr int RPW = 64 / G;
+    constexpr int MB = G <= 16 ? 16 / G : 0;   // B entries per lane and A entry fetched ahead
     __shared__ int keys[RPW][H];
     __shared__ double vals[NUMERIC ? RPW : 1][NUMERIC ? H : 1];
     __shared__ int list[NUMERIC ? RPW : 1][NUMERIC ? H : 1];
@@ -464,15 +465,54 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
                 tn = brp[c + 1];
             }
             const int cnt = ke - kb < G ? ke - kb : G;
-            for (int jj = 0; jj < cnt; ++jj) {
-                const int t0 = __shfl(tb, jj, G), t1 = __shfl(tn, jj, G);
-                const double a = NUMERIC ? __shfl(am, jj, G) : 0.0;
-                for (int t = t0 + lane; t < t1; t += G) {
-                    if (!NUMERIC && *(volatile int *)&count[g] > (3 * H) / 4) break;
-                    const int q = hash_insert<H>(keys[g], bcol[t], NUMERIC ? nullptr : &count[g]);
-                    if (NUMERIC) vals[g][q] += a * bval[t];
+            if constexpr (MB > 0) {
+                // the first MB of this lane's entries of each of the G B rows
+                // are requested before any is inserted; longer rows continue
+                // in the loop below.  Insertion order is unchanged.
+                int bc[G][MB];
+                double bv[NUMERIC ? G : 1][MB];
+#pragma unroll
+                for (int jj = 0; jj < G; ++jj) {
+                    const int t0 = __shfl(tb, jj, G), t1 = __shfl(tn, jj, G);
+#pragma unroll
+                    for (int m = 0; m < MB; ++m) {
+                        const int t = t0 + lane + m * G;
+                        if (jj < cnt && t < t1) {
+                            bc[jj][m] = bcol[t];
+                            if (NUMERIC) bv[jj][m] = bval[t];
+                        }
+                    }
                 }
-                wave_sync();
+#pragma unroll
+                for (int jj = 0; jj < G; ++jj) {
+                    if (jj >= cnt) break;
+                    const int t0 = __shfl(tb, jj, G), t1 = __shfl(tn, jj, G);
+                    const double a = NUMERIC ? __shfl(am, jj, G) : 0.0;
+#pragma unroll
+                    for (int m = 0; m < MB; ++m) {
+                        if (t0 + lane + m * G >= t1) break;
+                        if (!NUMERIC && *(volatile int *)&count[g] > (3 * H) / 4) break;
+                        const int q = hash_insert<H>(keys[g], bc[jj][m], NUMERIC ? nullptr : &count[g]);
+                        if (NUMERIC) vals[g][q] += a * bv[NUMERIC ? jj : 0][m];
+                    }
+                    for (int t = t0 + lane + MB * G; t < t1; t += G) {
+                        if (!NUMERIC && *(volatile int *)&count[g] > (3 * H) / 4) break;
+                        const int q = hash_insert<H>(keys[g], bcol[t], NUMERIC ? nullptr : &count[g]);
+                        if (NUMERIC) vals[g][q] += a * bval[t];
+                    }
+                    wave_sync();
+                }
+            } else {
+                for (int jj = 0; jj < cnt; ++jj) {
+                    const int t0 = __shfl(tb, jj, G), t1 = __shfl(tn, jj, G);
+                    const double a = NUMERIC ? __shfl(am, jj, G) : 0.0;
+                    for (int t = t0 + lane; t < t1; t += G) {
+                        if (!NUMERIC && *(volatile int *)&count[g] > (3 * H) / 4) break;
+                        const int q = hash_insert<H>(keys[g], bcol[t], NUMERIC ? nullptr : &count[g]);
+                        if (NUMERIC) vals[g][q] += a * bval[t];
+                    }
+                    wave_sync();
+                }
             }
         }
     }

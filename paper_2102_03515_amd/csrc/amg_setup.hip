@@ -176,28 +176,14 @@ __global__ void __launch_bounds__(256) k_mis_m1(int32_t n, const int32_t *__rest
     }
 }
 
-// need[i] = need[j] = round for every undecided i and its strong neighbours j
-// (every writer stores the same value)
-template <int G>
-__global__ void __launch_bounds__(256) k_mis_mark(int32_t n, const int32_t *__restrict__ rp,
-                                                  const int32_t *__restrict__ col, const uint8_t *__restrict__ strong,
-                                                  const int8_t *__restrict__ state, int32_t *__restrict__ need,
-                                                  int32_t round) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = (int)(t / G), lane = (int)(t % G);
-    if (i >= n || state[i] != 0) return;
-    if (lane == 0) need[i] = round;
-    for (int k = rp[i] + lane; k < rp[i + 1]; k += G) {
-        const int j = col[k];
-        if (is_strong(strong, k, j, i)) need[j] = round;
-    }
-}
-
+// A node that stays undecided marks itself and its strong neighbours with
+// need = round + 1: the nodes whose m1 the next round recomputes.
 template <int G>
 __global__ void __launch_bounds__(256) k_mis_m2(int32_t n, const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ col, const uint8_t *__restrict__ strong,
                                                 int8_t *__restrict__ state, uint32_t salt,
-                                                const uint64_t *__restrict__ m1, int32_t *undecided) {
+                                                const uint64_t *__restrict__ m1, int32_t *__restrict__ need,
+                                                int32_t round, int32_t *undecided) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int i = (int)(t / G), lane = (int)(t % G);
     if (i >= n) return;
@@ -221,16 +207,24 @@ __global__ void __launch_bounds__(256) k_mis_m2(int32_t n, const int32_t *__rest
         }
     }
     m = group_max_u64<G>(m);
-    bool still = false;
+    const uint64_t mi = m1[i];
+    m = mi > m ? mi : m;
+    // every lane of the group holds the same m
+    const bool joins = m == mis_key(i, 0, salt);
+    const bool leaves = !joins && (m >> 62) == 3u;
+    const bool still = !joins && !leaves && lane == 0;
     if (lane == 0) {
-        const uint64_t mi = m1[i];
-        m = mi > m ? mi : m;
-        if (m == mis_key(i, 0, salt))
+        if (joins)
             state[i] = 1;
-        else if ((m >> 62) == 3u)
+        else if (leaves)
             state[i] = 2;
-        else
-            still = true;
+    }
+    if (!joins && !leaves) {
+        if (lane == 0) need[i] = round + 1;
+        for (int k = rp[i] + lane; k < ke; k += G) {
+            const int j = col[k];
+            if (is_strong(strong, k, j, i)) need[j] = round + 1;
+        }
     }
     // "some node is still undecided": every writer stores the same value, so
     // one plain store per wavefront suffices (no contended atomic)
@@ -764,22 +758,99 @@ static void spgemm_ptent(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *
 }
 
 // --------------------------------------------------------------- transpose
-__global__ void k_count_cols(int64_t nnz, const int32_t *__restrict__ col, int32_t *__restrict__ cnt) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < nnz) atomicAdd(&cnt[col[k]], 1);
+// Column counts and the scatter of the transpose, 256 rows per block.  When
+// the block's rows hold at most kTHash/2 entries and none more than kTRow,
+// the block first combines its entries per column in an LDS hash table, so
+// one global atomic per distinct column and block reserves the space (rows of
+// an aggregation operator share few columns); otherwise every entry takes
+// its own global atomic.  The order inside a transposed row is fixed by the
+// sort that follows.
+constexpr int kTHash = 4096;
+constexpr int kTRow = 16;
+
+__device__ __forceinline__ int t_slot(int *keys, int v) {
+    int s = (int)(((uint32_t)v * 2654435761u) >> (32 - 12));
+    for (;;) {
+        const int prev = atomicCAS(&keys[s], -1, v);
+        if (prev == -1 || prev == v) return s;
+        s = (s + 1) & (kTHash - 1);
+    }
 }
 
-__global__ void k_fill_t(int32_t m, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                         const double *__restrict__ val, const int32_t *__restrict__ trp, int32_t *__restrict__ fill,
-                         int32_t *__restrict__ tcol, double *__restrict__ tval) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
-        const int j = col[k];
-        const int pos = trp[j] + atomicAdd(&fill[j], 1);
-        tcol[pos] = i;
-        tval[pos] = val[k];
+__device__ __forceinline__ bool t_combine(int32_t m, const int32_t *__restrict__ rp, int r0) {
+    const int r1 = r0 + 256 < m ? r0 + 256 : m;
+    const int i = r0 + (int)threadIdx.x;
+    const bool longrow = i < m && rp[i + 1] - rp[i] > kTRow;
+    return !__syncthreads_or(longrow) && rp[r1] - rp[r0] <= kTHash / 2;
+}
+
+__global__ void __launch_bounds__(256) k_count_cols(int32_t m, const int32_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ col, int32_t *__restrict__ cnt) {
+    __shared__ int keys[kTHash];
+    __shared__ int c[kTHash];
+    const int r0 = blockIdx.x * 256;
+    const bool combine = t_combine(m, rp, r0);   // uniform over the block
+    const int i = r0 + (int)threadIdx.x;
+    if (combine) {
+        for (int q = threadIdx.x; q < kTHash; q += 256) {
+            keys[q] = -1;
+            c[q] = 0;
+        }
+        __syncthreads();
+        if (i < m)
+            for (int k = rp[i]; k < rp[i + 1]; ++k) atomicAdd(&c[t_slot(keys, col[k])], 1);
+        __syncthreads();
+        for (int q = threadIdx.x; q < kTHash; q += 256)
+            if (keys[q] >= 0) atomicAdd(&cnt[keys[q]], c[q]);
+    } else if (i < m) {
+        for (int k = rp[i]; k < rp[i + 1]; ++k) atomicAdd(&cnt[col[k]], 1);
     }
+}
+
+__global__ void __launch_bounds__(256) k_fill_t(int32_t m, const int32_t *__restrict__ rp,
+                                                const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                const int32_t *__restrict__ trp, int32_t *__restrict__ fill,
+                                                int32_t *__restrict__ tcol, double *__restrict__ tval) {
+    __shared__ int keys[kTHash];
+    __shared__ int c[kTHash];
+    __shared__ int base[kTHash];
+    const int r0 = blockIdx.x * 256;
+    const bool combine = t_combine(m, rp, r0);   // uniform over the block
+    const int i = r0 + (int)threadIdx.x;
+    if (!combine) {
+        if (i < m)
+            for (int k = rp[i]; k < rp[i + 1]; ++k) {
+                const int j = col[k];
+                const int pos = trp[j] + atomicAdd(&fill[j], 1);
+                tcol[pos] = i;
+                tval[pos] = val[k];
+            }
+        return;
+    }
+    for (int q = threadIdx.x; q < kTHash; q += 256) {
+        keys[q] = -1;
+        c[q] = 0;
+    }
+    __syncthreads();
+    int slot[kTRow], pos[kTRow];
+    const int kb = i < m ? rp[i] : 0, len = i < m ? rp[i + 1] - kb : 0;
+#pragma unroll
+    for (int u = 0; u < kTRow; ++u)
+        if (u < len) {
+            slot[u] = t_slot(keys, col[kb + u]);
+            pos[u] = atomicAdd(&c[slot[u]], 1);
+        }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kTHash; q += 256)
+        if (keys[q] >= 0) base[q] = trp[keys[q]] + atomicAdd(&fill[keys[q]], c[q]);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kTRow; ++u)
+        if (u < len) {
+            const int p = base[slot[u]] + pos[u];
+            tcol[p] = i;
+            tval[p] = val[kb + u];
+        }
 }
 
 constexpr int kSortCap = 2048;
@@ -816,7 +887,7 @@ static void transpose(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t nnz, const
     hipStream_t s = ctx->stream;
     DevBuf<int32_t> cnt(ctx, (size_t)ncols + 1);
     fill_zero_bytes(ctx, cnt.get(), sizeof(int32_t) * ((size_t)ncols + 1));
-    k_count_cols<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, col, cnt.get());
+    k_count_cols<<<grid_for(m, 256), 256, 0, s>>>(m, rp, col, cnt.get());
     OCP_LAUNCH_CHECK();
     T.rows = ncols;
     T.cols = m;
@@ -956,12 +1027,10 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
             for (int round = 1;; ++round) {
                 if (round > 1000) fail(OCP_ERR_HIP, "independent-set rounds did not terminate");
                 fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
-                if (round > 1)
-                    k_mis_mark<GM><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), need.get(), round);
                 k_mis_m1<GM><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt,
                                                 round > 1 ? need.get() : nullptr, round, m1.get());
                 k_mis_m2<GM><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get(),
-                                                ctx->dev_flag);
+                                                need.get(), round, ctx->dev_flag);
                 OCP_LAUNCH_CHECK();
                 int32_t und = 0;
                 read_back(ctx, &und, ctx->dev_flag, sizeof(int32_t));

@@ -35,23 +35,32 @@ WORKLOADS = {
 }
 
 
-def kernel_bytes(kernel: int, n: int, nnz: int, mixed: bool) -> float:
-    """Algorithmic HBM bytes of one launch of a fine-level kernel: every matrix
-    entry (4-byte column + value) read once, the row pointers once, and every
-    vector read or written once (a gathered vector counts once).  CG vectors
-    are double; V-cycle values and vectors are float in mixed precision."""
+def kernel_bytes(kernel: int, n: int, entries: int, coded: bool, mixed: bool) -> float:
+    """Algorithmic HBM bytes of one launch of a fine-level kernel on the
+    sliced-ELL matrix as stored: every stored entry read once (its value and
+    either a 4-bit column code or a 4-byte column), the per-slice metadata
+    once (width and offset; with codes also the code offset and the 16-entry
+    offset table), and every vector read or written once (a gathered vector
+    counts once).  CG vectors are double; V-cycle values and vectors are float
+    in mixed precision."""
     vs = 4 if mixed else 8
-    mat = (4 + vs) * nnz + 4.0 * (n + 1)
+    slices = (n + 63) // 64
+    col_b = 0.5 if coded else 4.0
+    meta = (8.0 + (68.0 if coded else 0.0)) * slices
+
+    def mat(v):
+        return (v + col_b) * entries + meta
+
     if kernel == 0:    # q = A p, p.q: 8-byte values, p gathered, q written
-        return 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n
-    if kernel == 1:    # x2 = D^-1 (c1 b + c2 r1), r1 = b - A (a D^-1 b): b(8) d x2
-        return mat + 8.0 * n + 2.0 * vs * n
+        return mat(8) + 16.0 * n
+    if kernel == 1:    # x2 = D^-1 (c1 b + c2 r1), r1 = b - A y0: y0 (gathered), b(8), d, x2
+        return mat(vs) + 8.0 * n + 3.0 * vs * n
     if kernel == 5:    # r2 = b - A x2: x2 b(8) r2
-        return mat + 8.0 * n + 2.0 * vs * n
+        return mat(vs) + 8.0 * n + 2.0 * vs * n
     if kernel == 6:    # r0 = b - A xp, x1 = xp + a D^-1 r0: xp b(8) d r0 x1
-        return mat + 8.0 * n + 4.0 * vs * n
+        return mat(vs) + 8.0 * n + 4.0 * vs * n
     if kernel == 2:    # r1 = b - A x1, z = xp + D^-1 (c1 r0 + c2 r1), b.z: x1 b(8) xp r0 d z(8)
-        return mat + 16.0 * n + 4.0 * vs * n
+        return mat(vs) + 16.0 * n + 4.0 * vs * n
     raise ValueError(kernel)
 
 
@@ -60,9 +69,6 @@ def kernel_bytes(kernel: int, n: int, nnz: int, mixed: bool) -> float:
 # by what the same counter reads for the 1 GiB elementwise copy of that run.
 # Only kernels measured as they stand are listed (None otherwise).
 MEASURED_TRAFFIC = {
-    # k_cg_spmv_pq_sell at 255^3: FETCH 1,584,305 KiB x 1.99993 + WRITE 129,827 KiB x 0.99998
-    # per full dispatch (profiles/pmc_traffic_cg_spmv_cube256_modes64.md)
-    0: 3377481367,
 }
 
 
@@ -311,7 +317,8 @@ def main():
             t3 = time.perf_counter()
             if rc != 0:
                 raise RuntimeError(f"solve did not converge: status {rc} {info.as_dict()}")
-            meta = {"n": s.n, "nnz": s.nnz, "levels": h.n_levels, "nnz_P0": int(h.level(0).nnz_P),
+            meta = {"n": s.n, "nnz": s.nnz, "sell_entries": s.sell_entries, "sell_coded": s.sell_coded,
+                    "levels": h.n_levels, "nnz_P0": int(h.level(0).nnz_P),
                     "iterations": info.iterations, "true_rel_res": info.true_rel_res,
                     "assemble_ms": 1e3 * (t1 - t0), "setup_ms": 1e3 * (t2 - t1), "solve_ms": 1e3 * (t3 - t2),
                     "solve_gpu_ms": info.solve_ms}
@@ -334,6 +341,7 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         n, nnz = metas[0]["n"], metas[0]["nnz"]
+        entries, coded = metas[0]["sell_entries"], metas[0]["sell_coded"]
         ms_per_step = 1e3 * (t1 - t0) / args.steps
         value = n * args.steps / (t1 - t0)
 
@@ -342,13 +350,13 @@ def main():
         dom = max(MATRIX_KERNELS, key=lambda k: timings[k][1])
         launches, tot_ms = timings[dom]
         avg_ms = tot_ms / max(launches, 1)
-        alg = kernel_bytes(dom, n, nnz, mixed=(dom != 0))
+        alg = kernel_bytes(dom, n, entries, coded, mixed=(dom != 0))
         achieved = alg / (avg_ms * 1e-3) / 1e9
         kernels = {KERNEL_NAMES[k]: {"launches": timings[k][0],
                                      "avg_us": 1e3 * timings[k][1] / max(timings[k][0], 1)}
                    for k in range(7)}
         for k in MATRIX_KERNELS:
-            b = kernel_bytes(k, n, nnz, mixed=(k != 0))
+            b = kernel_bytes(k, n, entries, coded, mixed=(k != 0))
             t = timings[k][1] / max(timings[k][0], 1)
             kernels[KERNEL_NAMES[k]]["alg_bytes"] = b
             kernels[KERNEL_NAMES[k]]["alg_GBps"] = b / (t * 1e-3) / 1e9 if t > 0 else None
@@ -368,6 +376,7 @@ def main():
         return {
             "value": value, "ms_per_step": ms_per_step,
             "config": {"workload": args.workload, "cubes_per_edge": N, "unknowns": n, "nnz": nnz,
+                       "sell_entries": entries, "sell_column_codes": coded,
                        "rho": rho, "rtol": 1e-8, "stop": "||r||2/||f||2", "precision": "mixed",
                        "parallelism": "single GPU"},
             "iterations": metas[-1]["iterations"],

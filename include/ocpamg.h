@@ -152,6 +152,8 @@ typedef struct {
     const int32_t *vertex_of_dof; /* device [n_dofs] */
     int32_t sell_coded;         /* 1: the solve-phase sliced-ELL copy reads 4-bit column codes
                                    (every 64-row slice has <= 16 distinct col - row offsets) */
+    int64_t sell_entries;       /* stored entries of that copy (64-row slices padded to their
+                                   longest row) */
 } ocp_system_view;
 int ocp_system_get_view(const ocp_system *sys, ocp_system_view *view);
 

@@ -50,7 +50,7 @@ class _SystemView(C.Structure):
     _fields_ = [("n_vertices", C.c_int32), ("n_dofs", C.c_int32), ("nnz", C.c_int64),
                 ("rho", C.c_double), ("row_ptr", C.c_void_p), ("col", C.c_void_p),
                 ("val", C.c_void_p), ("f", C.c_void_p), ("dof_of_vertex", C.c_void_p),
-                ("vertex_of_dof", C.c_void_p), ("sell_coded", C.c_int32)]
+                ("vertex_of_dof", C.c_void_p), ("sell_coded", C.c_int32), ("sell_entries", C.c_int64)]
 
 
 class _AmgParams(C.Structure):
@@ -332,6 +332,11 @@ class System:
     def sell_coded(self) -> bool:
         """True when the solve-phase sliced-ELL matrix reads 4-bit column codes."""
         return bool(self.view().sell_coded)
+
+    @property
+    def sell_entries(self) -> int:
+        """Stored entries of the solve-phase sliced-ELL matrix (slices padded)."""
+        return int(self.view().sell_entries)
 
     def csr(self):
         """(row_ptr, col, val) as torch tensors viewing the library's arrays."""

@@ -1076,5 +1076,6 @@ extern "C" int ocp_system_get_view(const ocp_system *sys, ocp_system_view *v) {
     v->dof_of_vertex = sys->dof_of_vertex.get();
     v->vertex_of_dof = sys->vertex_of_dof.get();
     v->sell_coded = sys->sell.code.get() ? 1 : 0;
+    v->sell_entries = sys->sell.nnz_padded;
     return OCP_OK;
 }

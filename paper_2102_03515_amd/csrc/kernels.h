@@ -202,6 +202,7 @@ constexpr int kFinBlock = 1024;   // one-block finalize kernels over the partial
 constexpr int kSellC = 64;
 constexpr int kSellDict = 16;     // column offsets per slice that 4-bit codes can name
 constexpr int kSellChunk = 16;
+static_assert(kSellChunk == 16, "the coded row reads two code words per chunk");
 
 struct SellLaunch {
     unsigned blocks;
@@ -228,23 +229,29 @@ inline SellLaunch sell_launch(int64_t nslices) {
 namespace dev {
 
 // sum_j val * xf(col) over the row held by this lane of slice (base = its
-// offset); w is the slice width (uniform over the wavefront)
+// offset); w is the slice width (uniform over the wavefront).  A chunk's
+// loads and gathers are all issued before its first product: entries past w
+// re-read entry w-1 (cached, in bounds) and are left out of the sum, which
+// adds the products in entry order.
 template <typename VT, typename XF>
 __device__ __forceinline__ VT sell_row(const int32_t *__restrict__ col, const VT *__restrict__ val, int64_t base,
                                        int w, XF xf) {
+    w = __builtin_amdgcn_readfirstlane(w);
     VT acc = VT(0);
     for (int j0 = 0; j0 < w; j0 += kSellChunk) {
         int c[kSellChunk];
-        VT v[kSellChunk];
+        VT v[kSellChunk], x[kSellChunk];
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j) {
+            const int jj = j0 + j < w ? j0 + j : w - 1;
+            c[j] = ldnt(col + base + (int64_t)jj * kSellC);
+            v[j] = ldnt(val + base + (int64_t)jj * kSellC);
+        }
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j) x[j] = xf(c[j]);
 #pragma unroll
         for (int j = 0; j < kSellChunk; ++j)
-            if (j0 + j < w) {
-                c[j] = ldnt(col + base + (int64_t)(j0 + j) * kSellC);
-                v[j] = ldnt(val + base + (int64_t)(j0 + j) * kSellC);
-            }
-#pragma unroll
-        for (int j = 0; j < kSellChunk; ++j)
-            if (j0 + j < w) acc += v[j] * xf(c[j]);
+            if (j0 + j < w) acc += v[j] * x[j];
     }
     return acc;
 }
@@ -257,6 +264,7 @@ template <typename VT, typename XF>
 __device__ __forceinline__ VT sell_row_c(const SellCols &C, int64_t slice, int row, int n,
                                          const VT *__restrict__ val, int64_t base, int w, XF xf) {
     if (!C.code) return sell_row(C.col, val, base, w, xf);
+    w = __builtin_amdgcn_readfirstlane(w);
     const int lane = threadIdx.x & 63;
     const int rr = row < n ? row : 0;   // lanes past the last row hold offset 0 from row 0
     const int dl = C.dict[slice * kSellDict + (lane & (kSellDict - 1))];
@@ -264,19 +272,29 @@ __device__ __forceinline__ VT sell_row_c(const SellCols &C, int64_t slice, int r
     VT acc = VT(0);
     for (int j0 = 0; j0 < w; j0 += kSellChunk) {
         uint32_t cw[kSellChunk / 8];
-        VT v[kSellChunk];
+        VT v[kSellChunk], x[kSellChunk];
 #pragma unroll
-        for (int q = 0; q < kSellChunk / 8; ++q)
-            if (j0 + 8 * q < w) cw[q] = ldnt(C.code + cb + (int64_t)(j0 / 8 + q) * kSellC);
+        for (int q = 0; q < kSellChunk / 8; ++q) {
+            const int qq = j0 + 8 * q < w ? j0 / 8 + q : (w - 1) / 8;
+            cw[q] = ldnt(C.code + cb + (int64_t)qq * kSellC);
+        }
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j) {
+            const int jj = j0 + j < w ? j0 + j : w - 1;
+            v[j] = ldnt(val + base + (int64_t)jj * kSellC);
+        }
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j) {
+            // entry j of the chunk, or past w entry w-1, which lies in this
+            // (last) chunk
+            const int jj = j0 + j < w ? j : w - 1 - j0;
+            const uint32_t word = (jj >> 3) ? cw[1] : cw[0];
+            const int c = (int)((word >> (4 * (jj & 7))) & 15u);
+            x[j] = xf(rr + __shfl(dl, c, 64));
+        }
 #pragma unroll
         for (int j = 0; j < kSellChunk; ++j)
-            if (j0 + j < w) v[j] = ldnt(val + base + (int64_t)(j0 + j) * kSellC);
-#pragma unroll
-        for (int j = 0; j < kSellChunk; ++j)
-            if (j0 + j < w) {
-                const int c = (int)((cw[j >> 3] >> (4 * (j & 7))) & 15u);
-                acc += v[j] * xf(rr + __shfl(dl, c, 64));
-            }
+            if (j0 + j < w) acc += v[j] * x[j];
     }
     return acc;
 }

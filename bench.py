@@ -69,6 +69,10 @@ def kernel_bytes(kernel: int, n: int, entries: int, coded: bool, mixed: bool) ->
 # by what the same counter reads for the 1 GiB elementwise copy of that run.
 # Only kernels measured as they stand are listed (None otherwise).
 MEASURED_TRAFFIC = {
+    # k_cg_spmv_pq_sell at 255^3 (coded sliced-ELL): FETCH 1,111,040.3 KiB x 1.99993
+    # + WRITE 130,557.5 KiB x 0.99997 per full dispatch
+    # (profiles/pmc_traffic_cg_spmv_cube256_modes64.md)
+    0: 2409016550,
 }
 
 

@@ -118,6 +118,57 @@ __device__ __forceinline__ bool is_strong(const uint8_t *__restrict__ strong, in
     return strong ? strong[k] != 0 : j != i;
 }
 
+// The same on the system's sliced-ELL copy (level 0): one wavefront per 64-row
+// slice, coalesced loads.  Entries are taken in row order and the padding
+// (value 0) only adds zeros, so the results are the CSR kernel's bits; the
+// diagonal is the entry in column row with a nonzero value (padding sits in
+// column row with value 0).
+__global__ void __launch_bounds__(kBlock) k_level_diag_sell(int32_t n, int64_t nslices, int spb,
+                                                            const int32_t *__restrict__ sp,
+                                                            const int32_t *__restrict__ sw, SellCols cols,
+                                                            const double *__restrict__ val, double *__restrict__ diag,
+                                                            double *__restrict__ dl1, double *__restrict__ gersh,
+                                                            int32_t *flag) {
+    OCP_SELL_BEGIN(nslices, spb)
+    const int ww = __builtin_amdgcn_readfirstlane(w);
+    const int rr = row < n ? row : 0;
+    const int dl = cols.code ? cols.dict[slice * kSellDict + (lane & (kSellDict - 1))] : 0;
+    const int64_t cb = cols.code ? cols.cp[slice] + lane : 0;
+    double d = 0.0, sum = 0.0;
+    for (int j0 = 0; j0 < ww; j0 += kSellChunk) {
+        double v[kSellChunk];
+        int c[kSellChunk];
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j) {
+            const int jj = j0 + j < ww ? j0 + j : ww - 1;
+            v[j] = val[base + (int64_t)jj * kSellC];
+            if (cols.code) {
+                const uint32_t word = cols.code[cb + (int64_t)(jj >> 3) * kSellC];
+                c[j] = rr + __shfl(dl, (int)((word >> (4 * (jj & 7))) & 15u), 64);
+            } else {
+                c[j] = cols.col[base + (int64_t)jj * kSellC];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j)
+            if (j0 + j < ww) {
+                sum += fabs(v[j]);
+                if (c[j] == row && v[j] != 0.0) d = v[j];
+            }
+    }
+    if (row < n) {
+        if (!(d > 0.0) || !isfinite(sum)) {
+            atomicOr(flag, 8);
+            d = 1.0;
+            sum = 1.0;
+        }
+        diag[row] = d;
+        dl1[row] = 1.0 / sum;
+        gersh[row] = sum / d;
+    }
+    OCP_SELL_END()
+}
+
 // ------------------------------------------------------------------- MIS-2
 // Round of the distance-2 independent set, G lanes per row:
 //   m1[i] = max key over i and its strong neighbours
@@ -439,7 +490,7 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int r = blockIdx.x * RPW + g;
     const bool active = r < nrows;
-    const int i = active ? rows[r] : 0;
+    const int i = active ? (rows ? rows[r] : r) : 0;   // rows == nullptr: every row, in order
     for (int q = lane; q < H; q += G) {
         keys[g][q] = -1;
         if (NUMERIC) vals[g][q] = 0.0;
@@ -723,9 +774,15 @@ static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, c
     C.nnz = scan_exclusive(ctx, cnt.get(), C.rp.get(), m);
     C.col.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
     C.val.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
-    // numeric: table sized by the exact distinct count
-    fill_zero_bytes(ctx, counts.get(), 32);
+    // numeric: table sized by the exact distinct count; when every row fits
+    // the smallest table no binning is needed
     const ClassBounds num{{16, 64, 256, 1024}};
+    if (csr_max_row(ctx, m, C.rp.get()) <= num.lim[0]) {
+        launch_grp<4, 32, true>(ctx, nullptr, m, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr, C.col.get(),
+                                C.val.get());
+        return;
+    }
+    fill_zero_bytes(ctx, counts.get(), 32);
     k_bin_rows<<<grid_for(m, 256), 256, 0, s>>>(m, cnt.get(), num, counts.get(), lists.get());
     OCP_LAUNCH_CHECK();
     read_back(ctx, hc, counts.get(), 32);
@@ -854,6 +911,39 @@ __global__ void __launch_bounds__(256) k_fill_t(int32_t m, const int32_t *__rest
 }
 
 constexpr int kSortCap = 2048;
+constexpr int kSortWave = 256;   // rows up to this length are sorted by one wavefront
+
+// Sort each row of at most kSortWave entries by column, one wavefront per
+// row (4 per block), rank sort in the wavefront's LDS slice.  Longer rows are
+// left to k_sort_rows (flag bit 1 of *longrows).
+__global__ void __launch_bounds__(256) k_sort_rows_wave(int32_t m, const int32_t *__restrict__ rp,
+                                                        int32_t *__restrict__ col, double *__restrict__ val,
+                                                        int32_t *longrows) {
+    __shared__ int keys[4][kSortWave];
+    __shared__ double vals[4][kSortWave];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + wv;
+    if (i >= m) return;   // uniform over the wavefront
+    const int b = rp[i], len = rp[i + 1] - b;
+    if (len > kSortWave) {
+        if (lane == 0) atomicOr(longrows, 1);
+        return;
+    }
+    for (int e = lane; e < len; e += 64) {
+        keys[wv][e] = col[b + e];
+        vals[wv][e] = val[b + e];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int e = lane; e < len; e += 64) {
+        const int ke = keys[wv][e];
+        int rank = 0;
+        for (int f = 0; f < len; ++f) rank += keys[wv][f] < ke;
+        col[b + rank] = ke;
+        val[b + rank] = vals[wv][e];
+    }
+}
 
 // Sort each row by column (keys unique within a row): rank sort in LDS.
 __global__ void __launch_bounds__(256) k_sort_rows(int32_t m, const int32_t *__restrict__ rp, int32_t *__restrict__ col,
@@ -862,6 +952,7 @@ __global__ void __launch_bounds__(256) k_sort_rows(int32_t m, const int32_t *__r
     __shared__ double vals[kSortCap];
     for (int i = blockIdx.x; i < m; i += gridDim.x) {
         const int b = rp[i], len = rp[i + 1] - b;
+        if (len <= kSortWave) continue;   // sorted by k_sort_rows_wave
         if (len > kSortCap) {
             if (threadIdx.x == 0) atomicOr(flag, 64);
             continue;
@@ -899,12 +990,19 @@ static void transpose(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t nnz, const
     k_fill_t<<<grid_for(m, 256), 256, 0, s>>>(m, rp, col, val, T.rp.get(), cnt.get(), T.col.get(), T.val.get());
     OCP_LAUNCH_CHECK();
     fill_zero_bytes(ctx, ctx->dev_flag, 4);
-    k_sort_rows<<<(unsigned)std::min<int64_t>(std::max<int32_t>(ncols, 1), 65536), 256, 0, s>>>(
-        ncols, T.rp.get(), T.col.get(), T.val.get(), ctx->dev_flag);
+    k_sort_rows_wave<<<(unsigned)((std::max<int32_t>(ncols, 1) + 3) / 4), 256, 0, s>>>(ncols, T.rp.get(), T.col.get(),
+                                                                                  T.val.get(), ctx->dev_flag);
     OCP_LAUNCH_CHECK();
     int32_t fl = 0;
     read_back(ctx, &fl, ctx->dev_flag, 4);
-    if (fl & 64) fail(OCP_ERR_UNSUPPORTED, "transpose row with more than 2048 entries");
+    if (fl & 1) {   // some rows are longer than a wavefront's slice: sort those by blocks
+        fill_zero_bytes(ctx, ctx->dev_flag, 4);
+        k_sort_rows<<<(unsigned)std::min<int64_t>(std::max<int32_t>(ncols, 1), 65536), 256, 0, s>>>(
+            ncols, T.rp.get(), T.col.get(), T.val.get(), ctx->dev_flag);
+        OCP_LAUNCH_CHECK();
+        read_back(ctx, &fl, ctx->dev_flag, 4);
+        if (fl & 64) fail(OCP_ERR_UNSUPPORTED, "transpose row with more than 2048 entries");
+    }
 }
 
 // ------------------------------------------------------------ dense inverse
@@ -980,8 +1078,16 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
         L.gA = level_lanes(L.nnzA, n);
         DevBuf<double> diag(ctx, n), gersh(ctx, n), dl1(ctx, n);
         fill_zero_bytes(ctx, ctx->dev_flag, 4);
-        k_level_diag<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, L.A_val, diag.get(), dl1.get(),
-                                                      gersh.get(), ctx->dev_flag);
+        if (lev == 0 && sys->sell.col.get() && sys->sell.n == n) {
+            const Sell &S = sys->sell;
+            const SellLaunch LS = sell_launch(S.nslices);
+            k_level_diag_sell<<<LS.blocks, kBlock, 0, s>>>(n, S.nslices, LS.slices_per_block, S.sp.get(),
+                                                            S.sw.get(), sell_cols(S), S.val.get(), diag.get(),
+                                                            dl1.get(), gersh.get(), ctx->dev_flag);
+        } else {
+            k_level_diag<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, L.A_val, diag.get(), dl1.get(),
+                                                          gersh.get(), ctx->dev_flag);
+        }
         OCP_LAUNCH_CHECK();
         int32_t fl = 0;
         read_back(ctx, &fl, ctx->dev_flag, 4);

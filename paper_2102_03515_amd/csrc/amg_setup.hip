@@ -433,28 +433,63 @@ struct ClassBounds {
 
 // Row lists per size class.  Positions are reserved with LDS atomics inside
 // the block and one global atomic per class per block.
+constexpr int kBinChunks = 16;   // 256-row chunks per block of the binning pass
+
+__device__ __forceinline__ int bin_class(int u, const ClassBounds &cb) {
+    int c = kSpgemmClasses - 1;
+    for (int q = 0; q < kSpgemmClasses - 1; ++q)
+        if (u <= cb.lim[q]) {
+            c = q;
+            break;
+        }
+    return c;
+}
+
+// Each block bins kBinChunks chunks of 256 rows: positions inside a
+// wavefront come from ballots, the block's per-class offsets from a prefix
+// over its (chunk, wavefront) counts, and one global atomic per class and
+// block reserves the block's range (one atomic per 256 rows serialized on
+// the few class counters).
 __global__ void __launch_bounds__(256) k_bin_rows(int32_t m, const int32_t *__restrict__ key, ClassBounds cb,
                                                   int32_t *__restrict__ counts, int32_t *__restrict__ lists) {
-    __shared__ int lcnt[kSpgemmClasses], lbase[kSpgemmClasses];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (threadIdx.x < kSpgemmClasses) lcnt[threadIdx.x] = 0;
-    __syncthreads();
-    int c = 0, lpos = 0;
-    if (i < m) {
-        const int u = key[i];
-        c = kSpgemmClasses - 1;
-        for (int q = 0; q < kSpgemmClasses - 1; ++q)
-            if (u <= cb.lim[q]) {
-                c = q;
-                break;
-            }
-        lpos = atomicAdd(&lcnt[c], 1);
+    __shared__ int wcnt[kBinChunks][4][kSpgemmClasses], lbase[kSpgemmClasses];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * kBinChunks * 256;
+    for (int ch = 0; ch < kBinChunks; ++ch) {
+        const int64_t i = r0 + ch * 256 + threadIdx.x;
+        const bool valid = i < m;
+        const int c = valid ? bin_class(key[i], cb) : -1;
+#pragma unroll
+        for (int q = 0; q < kSpgemmClasses; ++q) {
+            const unsigned long long mask = __ballot(c == q);
+            if (lane == 0) wcnt[ch][wv][q] = __popcll(mask);
+        }
     }
     __syncthreads();
-    if (threadIdx.x < kSpgemmClasses && lcnt[threadIdx.x] > 0)
-        lbase[threadIdx.x] = atomicAdd(&counts[threadIdx.x], lcnt[threadIdx.x]);
+    if (threadIdx.x < kSpgemmClasses) {
+        const int q = threadIdx.x;
+        int tot = 0;
+        for (int ch = 0; ch < kBinChunks; ++ch)
+            for (int w = 0; w < 4; ++w) {
+                const int t = wcnt[ch][w][q];
+                wcnt[ch][w][q] = tot;
+                tot += t;
+            }
+        if (tot > 0) lbase[q] = atomicAdd(&counts[q], tot);
+    }
     __syncthreads();
-    if (i < m) lists[(int64_t)c * m + lbase[c] + lpos] = i;
+    for (int ch = 0; ch < kBinChunks; ++ch) {
+        const int64_t i = r0 + ch * 256 + threadIdx.x;
+        const bool valid = i < m;
+        const int c = valid ? bin_class(key[i], cb) : -1;
+        int lpos = 0;
+#pragma unroll
+        for (int q = 0; q < kSpgemmClasses; ++q) {
+            const unsigned long long mask = __ballot(c == q);
+            if (c == q) lpos = __popcll(mask & ((1ull << lane) - 1ull));
+        }
+        if (valid) lists[(int64_t)c * m + lbase[c] + wcnt[ch][wv][c] + lpos] = (int32_t)i;
+    }
 }
 
 template <int H>
@@ -745,7 +780,7 @@ static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, c
     // symbolic: table sized by the product bound, large bounds first try 512
     // slots and recount in 4096 slots when more than 384 columns show up
     const ClassBounds sym{{16, 64, INT_MAX - 1, INT_MAX - 1}};
-    k_bin_rows<<<grid_for(m, 256), 256, 0, s>>>(m, ub.get(), sym, counts.get(), lists.get());
+    k_bin_rows<<<grid_for(m, 256 * kBinChunks), 256, 0, s>>>(m, ub.get(), sym, counts.get(), lists.get());
     OCP_LAUNCH_CHECK();
     int32_t hc[8];
     read_back(ctx, hc, counts.get(), 32);
@@ -783,7 +818,7 @@ static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, c
         return;
     }
     fill_zero_bytes(ctx, counts.get(), 32);
-    k_bin_rows<<<grid_for(m, 256), 256, 0, s>>>(m, cnt.get(), num, counts.get(), lists.get());
+    k_bin_rows<<<grid_for(m, 256 * kBinChunks), 256, 0, s>>>(m, cnt.get(), num, counts.get(), lists.get());
     OCP_LAUNCH_CHECK();
     read_back(ctx, hc, counts.get(), 32);
     spgemm_pass<true>(ctx, lists.get(), hc, m, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr, C.col.get(),

@@ -1253,6 +1253,12 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
         h->levels.push_back(std::move(nxt));
     }
 
+    // sliced-ELL copies of the larger coarse operators (their smoothing
+    // passes then stream 64-row slices instead of one wide row group per row)
+    for (size_t l = 1; l < h->levels.size(); ++l) {
+        Level &L = *h->levels[l];
+        if (L.n >= kSellMinRows && !L.dense_inv.get()) sell_build(ctx, L.sell, L.n, L.A_rp, L.A_col, L.A_val);
+    }
     // precision copies and work vectors
     const bool mixed = pr.precision == OCP_PREC_MIXED;
     for (size_t l = 0; l < h->levels.size(); ++l) {
@@ -1260,6 +1266,7 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
         if (mixed) {
             to_float(ctx, L.A_val, L.A_val32, L.nnzA);
             if (l == 0) sell_values32(ctx, system_sell(ctx, sys), L.A_rp, L.A_val32.get(), L.sell_val32);
+            if (l > 0 && L.sell.col.get()) sell_values32(ctx, L.sell, L.A_rp, L.A_val32.get(), L.sell_val32);
             to_float(ctx, L.dinv.get(), L.dinv32, L.n);
             if (L.P_val.get()) to_float(ctx, L.P_val.get(), L.P_val32, L.nnzP);
             if (L.R_val.get()) to_float(ctx, L.R_val.get(), L.R_val32, L.nnzP);

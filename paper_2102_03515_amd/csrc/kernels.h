@@ -221,6 +221,7 @@ namespace ocp {
 constexpr int kFinBlock = 1024;   // one-block finalize kernels over the partials of a SELL pass
 constexpr int kSellC = 64;
 constexpr int kSellDict = 16;     // column offsets per slice that 4-bit codes can name
+constexpr int kSellMinRows = 1 << 16;   // coarse levels from this size get a sliced-ELL copy
 constexpr int kSellChunk = 16;
 static_assert(kSellChunk == 16, "the coded row reads two code words per chunk");
 

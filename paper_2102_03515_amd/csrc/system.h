@@ -68,7 +68,10 @@ struct Level {
     // single-precision copies (mixed precision)
     DevBuf<float> A_val32, P_val32, R_val32, dinv32, dense_inv32;
     // level 0: values of the system's sliced-ELL copy in the hierarchy's precision
+    // (FP32 hierarchies); levels >= 1 with at least kSellMinRows rows: a
+    // sliced-ELL copy of their own A (FP64 values, and the FP32 copy)
     DevBuf<float> sell_val32;
+    Sell sell;
     double lambda_max = 0.0;   // Gershgorin bound of D^-1 A
     // polynomial smoother: first step x = a D^-1 r; degree 2 adds
     // x = D^-1 (c1 r0 + c2 r1) with r1 the residual after the first step

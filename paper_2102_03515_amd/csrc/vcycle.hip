@@ -200,15 +200,19 @@ struct LevelArrays {
     const T *A, *P, *R, *d, *inv;
 };
 
+// values of a level's sliced-ELL copy (level 0: the system's) in the
+// hierarchy's precision
 template <typename T>
-static const T *sell_values(const ocp_hierarchy *h, const Sell &S);
+static const T *sell_values(const Level &L, const Sell &S);
 template <>
-const double *sell_values<double>(const ocp_hierarchy *h, const Sell &S) {
+const double *sell_values<double>(const Level &L, const Sell &S) {
+    (void)L;
     return S.val.get();
 }
 template <>
-const float *sell_values<float>(const ocp_hierarchy *h, const Sell &S) {
-    return h->levels[0]->sell_val32.get();
+const float *sell_values<float>(const Level &L, const Sell &S) {
+    (void)S;
+    return L.sell_val32.get();
 }
 
 template <typename T>
@@ -237,7 +241,7 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
     hipStream_t s = ctx->stream;
     double *part = W.part ? W.part : ctx->red_partials + 3 * kRedBlocks;
     const Sell &S = system_sell(ctx, h->sys);
-    const T *sval = sell_values<T>(h, S);
+    const T *sval = sell_values<T>(*lv[0], S);
     const SellLaunch LSL = sell_launch(S.nslices);
 
     if (L == 1) {
@@ -266,6 +270,13 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
             nb = LSL.blocks;
             k_smooth_sell<<<LSL.blocks, kBlock, 0, s>>>(S.n, S.nslices, LSL.slices_per_block, S.sp.get(), S.sw.get(),
                                                          sell_cols(S), sval, ops, cg, dot ? part : nullptr);
+        } else if (cur.sell.col.get()) {
+            const Sell &C = cur.sell;
+            const SellLaunch LC = sell_launch(C.nslices);
+            nb = LC.blocks;
+            k_smooth_sell<<<LC.blocks, kBlock, 0, s>>>(C.n, C.nslices, LC.slices_per_block, C.sp.get(), C.sw.get(),
+                                                        sell_cols(C), sell_values<T>(cur, C), ops, cg,
+                                                        dot ? part : nullptr);
         } else {
             const auto a = arrays<T>(cur);
             const RowLaunch LA = row_launch(cur.n, cur.gA);

@@ -52,9 +52,11 @@ def footprint(N: int, precision: int) -> Dict[str, int]:
     vs = 4 if precision == capi.PREC_MIXED else 8
     mesh = 24 * nv + 16 * nt + nv
     pattern = 4 * (n + 1) + 4 * nnz + 8 * n + 4 * nv + 4 * n + 4 * (nv + 1) + 16 * nt
-    sell = 12 * nnz + 8 * n
+    sell = 13 * nnz + 8 * n                      # values, columns, 4-bit codes and offset tables
     base = pattern + 3 * 8 * nnz + sell
     hier = 8 * n + (vs + 4) * nnz + 40 * n * (1 + vs // 4) + 2 * (12 * nnz) // 10
+    if n // 27 >= 1 << 16:                       # level 1 gets a sliced-ELL copy (~nnz/4 entries)
+        hier += (12 + vs) * nnz // 4
     entry = pattern + 8 * nnz + sell + hier
     solve = 5 * 8 * n + 8 * nv + 8 * n + 6 * vs * n
     return {"mesh": mesh, "base": base, "entry": entry, "hier": hier, "solve": solve}

@@ -524,8 +524,9 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
     __shared__ int count[RPW];
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int r = blockIdx.x * RPW + g;
-    const bool active = r < nrows;
-    const int i = active ? (rows ? rows[r] : r) : 0;   // rows == nullptr: every row, in order
+    const int i = r < nrows ? (rows ? rows[r] : r) : 0;   // rows == nullptr: every row, in order
+    // a numeric pass over every row leaves rows past half its table to another launch
+    const bool active = r < nrows && !(NUMERIC && !rows && crp[i + 1] - crp[i] > H / 2);
     for (int q = lane; q < H; q += G) {
         keys[g][q] = -1;
         if (NUMERIC) vals[g][q] = 0.0;
@@ -657,6 +658,29 @@ static int csr_max_row(ocp_ctx *ctx, int32_t m, const int32_t *rp) {
     return (int)reduce_max_abs(ctx, len.get(), m);
 }
 
+// bitonic sort of 16 (key, value) register pairs by key; unused keys are INT_MAX
+__device__ __forceinline__ void sort_slots(int (&keys)[16], double (&acc)[16]) {
+    constexpr int S = 16;
+#pragma unroll
+    for (int kk = 2; kk <= S; kk <<= 1)
+#pragma unroll
+        for (int jj = kk >> 1; jj > 0; jj >>= 1)
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int l = q ^ jj;
+                if (l > q) {
+                    const bool up = (q & kk) == 0;
+                    const bool sw = up ? (keys[q] > keys[l]) : (keys[q] < keys[l]);
+                    const int tk = keys[q];
+                    const double tv = acc[q];
+                    keys[q] = sw ? keys[l] : keys[q];
+                    acc[q] = sw ? acc[l] : acc[q];
+                    keys[l] = sw ? tk : keys[l];
+                    acc[l] = sw ? tv : acc[l];
+                }
+            }
+}
+
 // C = A P_tent (one entry per row of P_tent: column agg[j], value pt[j]),
 // one thread per row with up to 16 distinct columns held in registers;
 // entries accumulate in the order of the A row and are sorted by a network.
@@ -728,25 +752,7 @@ __global__ void __launch_bounds__(256) k_ap_tent(int32_t m, const int32_t *__res
         cnt[i] = nk;
         return;
     }
-    // bitonic sort of the 16 (key, value) pairs, unused keys are INT_MAX
-#pragma unroll
-    for (int kk = 2; kk <= S; kk <<= 1)
-#pragma unroll
-        for (int jj = kk >> 1; jj > 0; jj >>= 1)
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                const int l = q ^ jj;
-                if (l > q) {
-                    const bool up = (q & kk) == 0;
-                    const bool sw = up ? (keys[q] > keys[l]) : (keys[q] < keys[l]);
-                    const int tk = keys[q];
-                    const double tv = acc[q];
-                    keys[q] = sw ? keys[l] : keys[q];
-                    acc[q] = sw ? acc[l] : acc[q];
-                    keys[l] = sw ? tk : keys[l];
-                    acc[l] = sw ? tv : acc[l];
-                }
-            }
+    sort_slots(keys, acc);
     const int b = crp[i];
 #pragma unroll
     for (int q = 0; q < S; ++q)
@@ -754,6 +760,67 @@ __global__ void __launch_bounds__(256) k_ap_tent(int32_t m, const int32_t *__res
             ccol[b + q] = keys[q];
             cval[b + q] = acc[q];
         }
+}
+
+// Distinct columns of each row of C = A B while they number at most 16: one
+// thread per row holding the columns in registers.  The B rows of U
+// consecutive A entries, and the first MB entries of each, are requested
+// before any is compared.  A row that reaches a 17th column is listed in
+// over[] (counted in *nover) and left to the hash product.
+template <int U, int MB>
+__global__ void __launch_bounds__(256) k_ab_count(int32_t m, const int32_t *__restrict__ arp,
+                                                  const int32_t *__restrict__ acol, const int32_t *__restrict__ brp,
+                                                  const int32_t *__restrict__ bcol, int32_t *__restrict__ cnt,
+                                                  int32_t *__restrict__ over, int32_t *nover) {
+    constexpr int S = 16;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int keys[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) keys[q] = INT_MAX;
+    int nk = 0;
+    // false when the row would need a 17th slot
+    auto add = [&](int key) {
+        bool found = false;
+#pragma unroll
+        for (int q = 0; q < S; ++q) found |= keys[q] == key;
+        if (found) return true;
+        if (nk == S) return false;
+#pragma unroll
+        for (int q = 0; q < S; ++q)
+            if (q == nk) keys[q] = key;
+        ++nk;
+        return true;
+    };
+    const int ke = arp[i + 1];
+    for (int k0 = arp[i]; k0 < ke; k0 += U) {
+        int j[U], tb[U], te[U], bc[U][MB];
+#pragma unroll
+        for (int u = 0; u < U; ++u) j[u] = k0 + u < ke ? acol[k0 + u] : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            tb[u] = j[u] >= 0 ? brp[j[u]] : 0;
+            te[u] = j[u] >= 0 ? brp[j[u] + 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < MB; ++q)
+                if (tb[u] + q < te[u]) bc[u][q] = bcol[tb[u] + q];
+        bool ok = true;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int q = 0; q < MB; ++q)
+                if (ok && tb[u] + q < te[u]) ok = add(bc[u][q]);
+            for (int t = tb[u] + MB; ok && t < te[u]; ++t) ok = add(bcol[t]);
+        }
+        if (!ok) {
+            over[atomicAdd(nover, 1)] = i;
+            return;
+        }
+    }
+    cnt[i] = nk;
 }
 
 template <bool NUMERIC>
@@ -823,6 +890,57 @@ static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, c
     read_back(ctx, hc, counts.get(), 32);
     spgemm_pass<true>(ctx, lists.get(), hc, m, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr, C.col.get(),
                       C.val.get());
+}
+
+// C = A B when nearly every row of C has at most 16 columns: rows are counted
+// in registers, formed by the 32-slot hash pass over every row, and the few
+// longer rows are counted and formed in larger tables
+static void spgemm_small_rows(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, const int32_t *acol,
+                              const double *aval, const int32_t *brp, const int32_t *bcol, const double *bval,
+                              Csr &C) {
+    hipStream_t s = ctx->stream;
+    DevBuf<int32_t> cnt(ctx, (size_t)m + 1);
+    DevBuf<int32_t> over(ctx, (size_t)m + 1);   // over[m]: number of listed rows
+    fill_zero_bytes(ctx, over.get() + m, 4);
+    k_ab_count<4, 4><<<grid_for(m, 256), 256, 0, s>>>(m, arp, acol, brp, bcol, cnt.get(), over.get(), over.get() + m);
+    OCP_LAUNCH_CHECK();
+    int32_t nover = 0;
+    read_back(ctx, &nover, over.get() + m, 4);
+    // rows past 16 columns: counted in 512 slots, recounted in 4096 slots
+    // when more than 384 columns show up
+    int32_t nlong = 0;
+    DevBuf<int32_t> retry(ctx, (size_t)std::max(nover, 1) + 1);
+    if (nover > 0) {
+        fill_zero_bytes(ctx, retry.get() + std::max(nover, 1), 4);
+        fill_zero_bytes(ctx, ctx->dev_flag, 4);
+        launch_grp<16, 512, false>(ctx, over.get(), nover, arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
+                                   nullptr, nullptr, retry.get(), retry.get() + std::max(nover, 1));
+        read_back(ctx, &nlong, retry.get() + std::max(nover, 1), 4);
+        if (nlong > 0)
+            launch_grp<64, 4096, false>(ctx, retry.get(), nlong, arp, acol, aval, brp, bcol, bval, nullptr,
+                                        cnt.get(), nullptr, nullptr);
+        int32_t fl = 0;
+        read_back(ctx, &fl, ctx->dev_flag, 4);
+        if (fl & 32) fail(OCP_ERR_UNSUPPORTED, "sparse product row with more than 3072 entries");
+    }
+    C.rows = m;
+    C.cols = ncols;
+    C.rp.reset(ctx, (size_t)m + 1);
+    C.nnz = scan_exclusive(ctx, cnt.get(), C.rp.get(), m);
+    C.col.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
+    C.val.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
+    // rows of at most 16 columns (the pass skips the others)
+    launch_grp<4, 32, true>(ctx, nullptr, m, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr, C.col.get(),
+                            C.val.get());
+    if (nover == 0) return;
+    // every listed row holds at most 384 columns unless some were recounted,
+    // then all of them go through the 4096-slot table
+    if (nlong == 0)
+        launch_grp<16, 512, true>(ctx, over.get(), nover, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr,
+                                  C.col.get(), C.val.get());
+    else
+        launch_grp<64, 4096, true>(ctx, over.get(), nover, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr,
+                                   C.col.get(), C.val.get());
 }
 
 // C = A P_tent: the register kernel when every A row has at most 16 entries,
@@ -1226,7 +1344,12 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
         Csr R;
         transpose(ctx, n, nc, P.nnz, P.rp.get(), P.col.get(), P.val.get(), R);
         Csr AP, Ac;
-        spgemm(ctx, n, nc, L.A_rp, L.A_col, L.A_val, P.rp.get(), P.col.get(), P.val.get(), AP);
+        // rows of A P are counted in registers when A's rows are short on
+        // average (a thread per row walks its A row serially)
+        if (L.nnzA <= 16 * (int64_t)n)
+            spgemm_small_rows(ctx, n, nc, L.A_rp, L.A_col, L.A_val, P.rp.get(), P.col.get(), P.val.get(), AP);
+        else
+            spgemm(ctx, n, nc, L.A_rp, L.A_col, L.A_val, P.rp.get(), P.col.get(), P.val.get(), AP);
         spgemm(ctx, nc, nc, R.rp.get(), R.col.get(), R.val.get(), AP.rp.get(), AP.col.get(), AP.val.get(), Ac);
         sync(ctx);
 

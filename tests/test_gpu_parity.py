@@ -248,6 +248,35 @@ def test_hierarchy_matches_oracle_definitions(P, ctx, theta, N, jit):
         np.testing.assert_allclose(Ainv @ Ad, np.eye(last["n"]), atol=1e-10)
 
 
+@pytest.mark.gpu
+def test_galerkin_products_with_rows_past_16_columns(P, ctx):
+    """A_c = P^T A P on every level against the definition on the GPU's own A
+    and P, for a strength threshold under which thousands of level-0 rows of
+    A P have more than 16 columns (short A rows: those rows are counted in
+    registers, found too long, and formed in the larger hash tables)."""
+    import scipy.sparse as sp
+    N, theta = 24, 0.08
+    print(f"[amg setup] cube{N} theta={theta} long product rows", flush=True)
+    mesh = I.kuhn_mesh(N)
+    s, _ = _gpu_system(P, ctx, mesh, 1.0 / N ** 2, I.single_sine())
+    h = P.amg_setup(ctx, s, coarse_max=32, theta=theta)
+    for lev in range(h.n_levels - 1):
+        g = h.level_arrays(lev)
+        n, nc = g["n"], g["nc"]
+        Pg = sp.csr_matrix((g["P"][2].cpu().numpy(), g["P"][1].cpu().numpy(), g["P"][0].cpu().numpy()),
+                           shape=(n, nc))
+        Ag = sp.csr_matrix((g["A"][2].cpu().numpy(), g["A"][1].cpu().numpy(), g["A"][0].cpu().numpy()),
+                           shape=(n, n))
+        if lev == 0:
+            assert Ag.nnz <= 16 * n
+            assert (np.diff((Ag @ Pg).tocsr().indptr) > 16).sum() > 1000
+        nxt = h.level_arrays(lev + 1)
+        Ac = sp.csr_matrix((nxt["A"][2].cpu().numpy(), nxt["A"][1].cpu().numpy(), nxt["A"][0].cpu().numpy()),
+                           shape=(nc, nc))
+        Adef = (Pg.T @ Ag @ Pg).tocsr()
+        assert abs(Adef - Ac).max() <= 1e-13 * abs(Adef).max()
+
+
 def test_solve_is_deterministic(P, ctx):
     print("[determinism] cube18 jitter box", flush=True)
     mesh = I.kuhn_mesh(18, jitter=0.15, seed=21)

@@ -506,9 +506,25 @@ __device__ __forceinline__ int hash_insert(int *keys, int key, int *count) {
     }
 }
 
+// hash_insert that gives up (returns -1) after probing every slot once
+template <int H>
+__device__ __forceinline__ int hash_insert_bounded(int *keys, int key) {
+    int s = (int)(((uint32_t)key * 2654435761u) >> (32 - __builtin_ctz(H)));
+    for (int p = 0; p < H; ++p) {
+        const int prev = atomicCAS(&keys[s], -1, key);
+        if (prev == -1 || prev == key) return s;
+        s = (s + 1) & (H - 1);
+    }
+    return -1;
+}
+
 // NUMERIC = false: cnt[i] = number of distinct columns of C row i.
-// NUMERIC = true : write C row i (columns ascending) at crp[i].
-template <int G, int H, bool NUMERIC>
+// NUMERIC = true, W = 0: write C row i (columns ascending) at crp[i].
+// NUMERIC = true, W > 0: write the row at ccol/cval + r W, r its position in
+//   rows, and its length at cnt[i]; a row with more than W columns, or one
+//   that fills the table (it then stops after the current B row), is listed
+//   in retry[] (counted in *nretry) and written nowhere.
+template <int G, int H, bool NUMERIC, int W = 0>
 __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ rows, int32_t nrows,
                                                    const int32_t *__restrict__ arp, const int32_t *__restrict__ acol,
                                                    const double *__restrict__ aval, const int32_t *__restrict__ brp,
@@ -518,10 +534,13 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
                                                    int32_t *flag, int32_t *retry, int32_t *nretry) {
     constexpr int RPW = 64 / G;
     constexpr int MB = G <= 16 ? 16 / G : 0;   // B entries per lane and A entry fetched ahead
+    static_assert(W <= H, "a padded row fits its table");
+    constexpr int LIM = (3 * H) / 4;   // symbolic: count past which the row is retried
     __shared__ int keys[RPW][H];
     __shared__ double vals[NUMERIC ? RPW : 1][NUMERIC ? H : 1];
     __shared__ int list[NUMERIC ? RPW : 1][NUMERIC ? H : 1];
     __shared__ int count[RPW];
+    __shared__ int full[RPW];
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int r = blockIdx.x * RPW + g;
     const int i = r < nrows ? (rows ? rows[r] : r) : 0;   // rows == nullptr: every row, in order
@@ -531,11 +550,35 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
         keys[g][q] = -1;
         if (NUMERIC) vals[g][q] = 0.0;
     }
-    if (lane == 0) count[g] = 0;
+    if (lane == 0) {
+        count[g] = 0;
+        full[g] = 0;
+    }
     wave_sync();
+    // one product into the table: symbolic passes count new columns, padded
+    // passes flag a full table, the others rely on a table sized for the row
+    auto put = [&](int key, double v) {
+        if (!NUMERIC) {
+            // the count is checked before every insert, so the table never fills
+            if (*(volatile int *)&count[g] <= LIM) hash_insert<H>(keys[g], key, &count[g]);
+        } else if (W > 0) {
+            const int q = hash_insert_bounded<H>(keys[g], key);
+            if (q < 0)
+                full[g] = 1;
+            else
+                vals[g][q] += v;
+        } else {
+            vals[g][hash_insert<H>(keys[g], key, nullptr)] += v;
+        }
+    };
+    // after each B row: the group stops once its row is known to be retried
+    auto stop = [&]() {
+        return (!NUMERIC && *(volatile int *)&count[g] > LIM) || (W > 0 && *(volatile int *)&full[g] != 0);
+    };
     if (active) {
         const int ke = arp[i + 1];
-        for (int kb = arp[i]; kb < ke; kb += G) {
+        bool done = false;
+        for (int kb = arp[i]; kb < ke && !done; kb += G) {
             // lanes fetch the metadata of G consecutive A entries at once
             double am = 0.0;
             int tb = 0, tn = 0;
@@ -566,33 +609,25 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
                 }
 #pragma unroll
                 for (int jj = 0; jj < G; ++jj) {
-                    if (jj >= cnt) break;
+                    if (jj >= cnt || done) break;
                     const int t0 = __shfl(tb, jj, G), t1 = __shfl(tn, jj, G);
                     const double a = NUMERIC ? __shfl(am, jj, G) : 0.0;
 #pragma unroll
                     for (int m = 0; m < MB; ++m) {
                         if (t0 + lane + m * G >= t1) break;
-                        if (!NUMERIC && *(volatile int *)&count[g] > (3 * H) / 4) break;
-                        const int q = hash_insert<H>(keys[g], bc[jj][m], NUMERIC ? nullptr : &count[g]);
-                        if (NUMERIC) vals[g][q] += a * bv[NUMERIC ? jj : 0][m];
+                        put(bc[jj][m], NUMERIC ? a * bv[NUMERIC ? jj : 0][m] : 0.0);
                     }
-                    for (int t = t0 + lane + MB * G; t < t1; t += G) {
-                        if (!NUMERIC && *(volatile int *)&count[g] > (3 * H) / 4) break;
-                        const int q = hash_insert<H>(keys[g], bcol[t], NUMERIC ? nullptr : &count[g]);
-                        if (NUMERIC) vals[g][q] += a * bval[t];
-                    }
+                    for (int t = t0 + lane + MB * G; t < t1; t += G) put(bcol[t], NUMERIC ? a * bval[t] : 0.0);
                     wave_sync();
+                    done = stop();
                 }
             } else {
-                for (int jj = 0; jj < cnt; ++jj) {
+                for (int jj = 0; jj < cnt && !done; ++jj) {
                     const int t0 = __shfl(tb, jj, G), t1 = __shfl(tn, jj, G);
                     const double a = NUMERIC ? __shfl(am, jj, G) : 0.0;
-                    for (int t = t0 + lane; t < t1; t += G) {
-                        if (!NUMERIC && *(volatile int *)&count[g] > (3 * H) / 4) break;
-                        const int q = hash_insert<H>(keys[g], bcol[t], NUMERIC ? nullptr : &count[g]);
-                        if (NUMERIC) vals[g][q] += a * bval[t];
-                    }
+                    for (int t = t0 + lane; t < t1; t += G) put(bcol[t], NUMERIC ? a * bval[t] : 0.0);
                     wave_sync();
+                    done = stop();
                 }
             }
         }
@@ -615,7 +650,12 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
     wave_sync();
     if (!active) return;
     const int nc = count[g];
-    const int base = crp[i];
+    if (W > 0 && (full[g] != 0 || nc > W)) {
+        if (lane == 0) retry[atomicAdd(nretry, 1)] = i;
+        return;
+    }
+    const int64_t base = W > 0 ? (int64_t)r * W : crp[i];
+    if (W > 0 && lane == 0) cnt[i] = nc;
     for (int e = lane; e < nc; e += G) {
         const int se = list[g][e];
         const int kk = keys[g][se];
@@ -633,7 +673,7 @@ struct Csr {
     DevBuf<double> val;
 };
 
-template <int G, int H, bool NUMERIC>
+template <int G, int H, bool NUMERIC, int W = 0>
 static void launch_grp(ocp_ctx *ctx, const int32_t *rows, int32_t nrows, const int32_t *arp, const int32_t *acol,
                        const double *aval, const int32_t *brp, const int32_t *bcol, const double *bval,
                        const int32_t *crp, int32_t *cnt, int32_t *ccol, double *cval, int32_t *retry = nullptr,
@@ -641,8 +681,8 @@ static void launch_grp(ocp_ctx *ctx, const int32_t *rows, int32_t nrows, const i
     if (nrows <= 0) return;
     constexpr int RPW = 64 / G;
     const unsigned blocks = (unsigned)((nrows + RPW - 1) / RPW);
-    k_spgemm_grp<G, H, NUMERIC><<<blocks, 64, 0, ctx->stream>>>(rows, nrows, arp, acol, aval, brp, bcol, bval, crp,
-                                                                 cnt, ccol, cval, ctx->dev_flag, retry, nretry);
+    k_spgemm_grp<G, H, NUMERIC, W><<<blocks, 64, 0, ctx->stream>>>(rows, nrows, arp, acol, aval, brp, bcol, bval, crp,
+                                                                    cnt, ccol, cval, ctx->dev_flag, retry, nretry);
     OCP_LAUNCH_CHECK();
 }
 
@@ -823,18 +863,36 @@ __global__ void __launch_bounds__(256) k_ab_count(int32_t m, const int32_t *__re
     cnt[i] = nk;
 }
 
-template <bool NUMERIC>
-static void spgemm_pass(ocp_ctx *ctx, const int32_t *lists, const int32_t *hc, int32_t m, const int32_t *arp,
-                        const int32_t *acol, const double *aval, const int32_t *brp, const int32_t *bcol,
-                        const double *bval, const int32_t *crp, int32_t *cnt, int32_t *ccol, double *cval) {
-    const int64_t M = m;
-    launch_grp<4, 32, NUMERIC>(ctx, lists, hc[0], arp, acol, aval, brp, bcol, bval, crp, cnt, ccol, cval);
-    launch_grp<8, 128, NUMERIC>(ctx, lists + M, hc[1], arp, acol, aval, brp, bcol, bval, crp, cnt, ccol, cval);
-    launch_grp<16, 512, NUMERIC>(ctx, lists + 2 * M, hc[2], arp, acol, aval, brp, bcol, bval, crp, cnt, ccol, cval);
-    launch_grp<64, 2048, NUMERIC>(ctx, lists + 3 * M, hc[3], arp, acol, aval, brp, bcol, bval, crp, cnt, ccol, cval);
-    launch_grp<64, 4096, NUMERIC>(ctx, lists + 4 * M, hc[4], arp, acol, aval, brp, bcol, bval, crp, cnt, ccol, cval);
+// Rows formed in padded slots (row r of a class list at pcol/pval + r W)
+// copied to their CSR positions, one wavefront per row; rows longer than W
+// were formed in the CSR directly.
+__global__ void __launch_bounds__(256) k_pad_copy(const int32_t *__restrict__ rows, int32_t nrows, int W,
+                                                  const int32_t *__restrict__ pcol, const double *__restrict__ pval,
+                                                  const int32_t *__restrict__ crp, int32_t *__restrict__ ccol,
+                                                  double *__restrict__ cval) {
+    const int r = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    if (r >= nrows) return;
+    const int i = rows[r];
+    const int b = crp[i], len = crp[i + 1] - b;
+    if (len > W) return;
+    const int64_t p = (int64_t)r * W;
+    for (int e = lane; e < len; e += 64) {
+        ccol[b + e] = pcol[p + e];
+        cval[b + e] = pval[p + e];
+    }
 }
 
+// C = A B by hash tables in LDS.  Rows are binned by their product bound
+// (the sum of the B row lengths over the A row) and formed in one numeric
+// pass that writes each row, columns ascending, into a padded slot of its
+// class and records its length: bound <= 16 in 32 slots by 4 lanes, <= 64 in
+// 64 slots by 4 lanes (rows past 48 columns retried), larger bounds in 128
+// slots by 8 lanes (past 96 columns retried), or, when fewer than
+// kWideRows rows have such bounds, in 512 slots by a whole wavefront (past
+// 384 columns retried).  Retried rows are counted in 512 slots (4096 past
+// 384 columns) and formed in the CSR directly, after the scan of the lengths.
+constexpr int kWideRows = 16384;
 static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, const int32_t *acol, const double *aval,
                    const int32_t *brp, const int32_t *bcol, const double *bval, Csr &C) {
     hipStream_t s = ctx->stream;
@@ -844,52 +902,71 @@ static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, c
     DevBuf<int32_t> counts(ctx, 8);
     fill_zero_bytes(ctx, counts.get(), 32);
     DevBuf<int32_t> lists(ctx, (size_t)kSpgemmClasses * m);
-    // symbolic: table sized by the product bound, large bounds first try 512
-    // slots and recount in 4096 slots when more than 384 columns show up
-    const ClassBounds sym{{16, 64, INT_MAX - 1, INT_MAX - 1}};
-    k_bin_rows<<<grid_for(m, 256 * kBinChunks), 256, 0, s>>>(m, ub.get(), sym, counts.get(), lists.get());
+    const ClassBounds cls{{16, 64, INT_MAX - 1, INT_MAX - 1}};
+    k_bin_rows<<<grid_for(m, 256 * kBinChunks), 256, 0, s>>>(m, ub.get(), cls, counts.get(), lists.get());
     OCP_LAUNCH_CHECK();
     int32_t hc[8];
     read_back(ctx, hc, counts.get(), 32);
-    DevBuf<int32_t> cnt(ctx, (size_t)m + 1);
-    DevBuf<int32_t> retry(ctx, (size_t)std::max(hc[2], 1) + 1);
-    fill_zero_bytes(ctx, retry.get() + std::max(hc[2], 1), 4);
-    fill_zero_bytes(ctx, ctx->dev_flag, 4);
     const int64_t M = m;
-    launch_grp<4, 32, false>(ctx, lists.get(), hc[0], arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(), nullptr,
-                             nullptr);
-    launch_grp<8, 128, false>(ctx, lists.get() + M, hc[1], arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
-                              nullptr, nullptr);
-    launch_grp<16, 512, false>(ctx, lists.get() + 2 * M, hc[2], arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
-                               nullptr, nullptr, retry.get(), retry.get() + std::max(hc[2], 1));
+    const bool wide = hc[2] < kWideRows;
+    const int32_t W[3] = {16, 48, wide ? 384 : 96};   // padded widths of the three classes
+    int64_t off[4] = {0, 0, 0, 0};
+    for (int c = 0; c < 3; ++c) off[c + 1] = off[c] + (int64_t)hc[c] * W[c];
+    DevBuf<int32_t> pcol(ctx, (size_t)std::max<int64_t>(off[3], 1));
+    DevBuf<double> pval(ctx, (size_t)std::max<int64_t>(off[3], 1));
+    DevBuf<int32_t> cnt(ctx, (size_t)m + 1);
+    DevBuf<int32_t> retry(ctx, (size_t)m + 1);   // retry[m]: number of listed rows
+    fill_zero_bytes(ctx, retry.get() + m, 4);
+    int32_t *nr = retry.get() + m;
+    launch_grp<4, 32, true, 16>(ctx, lists.get(), hc[0], arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
+                                pcol.get(), pval.get(), retry.get(), nr);
+    launch_grp<4, 64, true, 48>(ctx, lists.get() + M, hc[1], arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
+                                pcol.get() + off[1], pval.get() + off[1], retry.get(), nr);
+    if (wide)
+        launch_grp<64, 512, true, 384>(ctx, lists.get() + 2 * M, hc[2], arp, acol, aval, brp, bcol, bval, nullptr,
+                                       cnt.get(), pcol.get() + off[2], pval.get() + off[2], retry.get(), nr);
+    else
+        launch_grp<8, 128, true, 96>(ctx, lists.get() + 2 * M, hc[2], arp, acol, aval, brp, bcol, bval, nullptr,
+                                     cnt.get(), pcol.get() + off[2], pval.get() + off[2], retry.get(), nr);
     int32_t nretry = 0;
-    read_back(ctx, &nretry, retry.get() + std::max(hc[2], 1), 4);
-    if (nretry > 0)
-        launch_grp<64, 4096, false>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
-                                    nullptr, nullptr);
-    int32_t fl = 0;
-    read_back(ctx, &fl, ctx->dev_flag, 4);
-    if (fl & 32) fail(OCP_ERR_UNSUPPORTED, "sparse product row with more than 3072 entries");
+    read_back(ctx, &nretry, nr, 4);
+    int32_t nlong = 0;
+    DevBuf<int32_t> retry2(ctx, (size_t)std::max(nretry, 1) + 1);
+    if (nretry > 0) {
+        fill_zero_bytes(ctx, retry2.get() + std::max(nretry, 1), 4);
+        fill_zero_bytes(ctx, ctx->dev_flag, 4);
+        launch_grp<16, 512, false>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
+                                   nullptr, nullptr, retry2.get(), retry2.get() + std::max(nretry, 1));
+        read_back(ctx, &nlong, retry2.get() + std::max(nretry, 1), 4);
+        if (nlong > 0)
+            launch_grp<64, 4096, false>(ctx, retry2.get(), nlong, arp, acol, aval, brp, bcol, bval, nullptr,
+                                        cnt.get(), nullptr, nullptr);
+        int32_t fl = 0;
+        read_back(ctx, &fl, ctx->dev_flag, 4);
+        if (fl & 32) fail(OCP_ERR_UNSUPPORTED, "sparse product row with more than 3072 entries");
+    }
     C.rows = m;
     C.cols = ncols;
     C.rp.reset(ctx, (size_t)m + 1);
     C.nnz = scan_exclusive(ctx, cnt.get(), C.rp.get(), m);
     C.col.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
     C.val.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
-    // numeric: table sized by the exact distinct count; when every row fits
-    // the smallest table no binning is needed
-    const ClassBounds num{{16, 64, 256, 1024}};
-    if (csr_max_row(ctx, m, C.rp.get()) <= num.lim[0]) {
-        launch_grp<4, 32, true>(ctx, nullptr, m, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr, C.col.get(),
-                                C.val.get());
-        return;
+    for (int c = 0; c < 3; ++c) {
+        if (hc[c] <= 0) continue;
+        k_pad_copy<<<(unsigned)((hc[c] + 3) / 4), 256, 0, s>>>(lists.get() + c * M, hc[c], W[c], pcol.get() + off[c],
+                                                               pval.get() + off[c], C.rp.get(), C.col.get(),
+                                                               C.val.get());
+        OCP_LAUNCH_CHECK();
     }
-    fill_zero_bytes(ctx, counts.get(), 32);
-    k_bin_rows<<<grid_for(m, 256 * kBinChunks), 256, 0, s>>>(m, cnt.get(), num, counts.get(), lists.get());
-    OCP_LAUNCH_CHECK();
-    read_back(ctx, hc, counts.get(), 32);
-    spgemm_pass<true>(ctx, lists.get(), hc, m, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr, C.col.get(),
-                      C.val.get());
+    if (nretry == 0) return;
+    // every listed row holds at most 384 columns unless some were recounted,
+    // then all of them go through the 4096-slot table
+    if (nlong == 0)
+        launch_grp<16, 512, true>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr,
+                                  C.col.get(), C.val.get());
+    else
+        launch_grp<64, 4096, true>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr,
+                                   C.col.get(), C.val.get());
 }
 
 // C = A B when nearly every row of C has at most 16 columns: rows are counted

@@ -544,8 +544,8 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
     const int g = threadIdx.x / G, lane = threadIdx.x % G;
     const int r = blockIdx.x * RPW + g;
     const int i = r < nrows ? (rows ? rows[r] : r) : 0;   // rows == nullptr: every row, in order
-    // a numeric pass over every row leaves rows past half its table to another launch
-    const bool active = r < nrows && !(NUMERIC && !rows && crp[i + 1] - crp[i] > H / 2);
+    // a CSR numeric pass over every row leaves rows past half its table to another launch
+    const bool active = r < nrows && !(NUMERIC && W == 0 && !rows && crp[i + 1] - crp[i] > H / 2);
     for (int q = lane; q < H; q += G) {
         keys[g][q] = -1;
         if (NUMERIC) vals[g][q] = 0.0;
@@ -802,82 +802,22 @@ __global__ void __launch_bounds__(256) k_ap_tent(int32_t m, const int32_t *__res
         }
 }
 
-// Distinct columns of each row of C = A B while they number at most 16: one
-// thread per row holding the columns in registers.  The B rows of U
-// consecutive A entries, and the first MB entries of each, are requested
-// before any is compared.  A row that reaches a 17th column is listed in
-// over[] (counted in *nover) and left to the hash product.
-template <int U, int MB>
-__global__ void __launch_bounds__(256) k_ab_count(int32_t m, const int32_t *__restrict__ arp,
-                                                  const int32_t *__restrict__ acol, const int32_t *__restrict__ brp,
-                                                  const int32_t *__restrict__ bcol, int32_t *__restrict__ cnt,
-                                                  int32_t *__restrict__ over, int32_t *nover) {
-    constexpr int S = 16;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    int keys[S];
-#pragma unroll
-    for (int q = 0; q < S; ++q) keys[q] = INT_MAX;
-    int nk = 0;
-    // false when the row would need a 17th slot
-    auto add = [&](int key) {
-        bool found = false;
-#pragma unroll
-        for (int q = 0; q < S; ++q) found |= keys[q] == key;
-        if (found) return true;
-        if (nk == S) return false;
-#pragma unroll
-        for (int q = 0; q < S; ++q)
-            if (q == nk) keys[q] = key;
-        ++nk;
-        return true;
-    };
-    const int ke = arp[i + 1];
-    for (int k0 = arp[i]; k0 < ke; k0 += U) {
-        int j[U], tb[U], te[U], bc[U][MB];
-#pragma unroll
-        for (int u = 0; u < U; ++u) j[u] = k0 + u < ke ? acol[k0 + u] : -1;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            tb[u] = j[u] >= 0 ? brp[j[u]] : 0;
-            te[u] = j[u] >= 0 ? brp[j[u] + 1] : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int q = 0; q < MB; ++q)
-                if (tb[u] + q < te[u]) bc[u][q] = bcol[tb[u] + q];
-        bool ok = true;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-#pragma unroll
-            for (int q = 0; q < MB; ++q)
-                if (ok && tb[u] + q < te[u]) ok = add(bc[u][q]);
-            for (int t = tb[u] + MB; ok && t < te[u]; ++t) ok = add(bcol[t]);
-        }
-        if (!ok) {
-            over[atomicAdd(nover, 1)] = i;
-            return;
-        }
-    }
-    cnt[i] = nk;
-}
-
 // Rows formed in padded slots (row r of a class list at pcol/pval + r W)
-// copied to their CSR positions, one wavefront per row; rows longer than W
-// were formed in the CSR directly.
+// copied to their CSR positions, L lanes per row; rows longer than W were
+// formed in the CSR directly.
+template <int L>
 __global__ void __launch_bounds__(256) k_pad_copy(const int32_t *__restrict__ rows, int32_t nrows, int W,
                                                   const int32_t *__restrict__ pcol, const double *__restrict__ pval,
                                                   const int32_t *__restrict__ crp, int32_t *__restrict__ ccol,
                                                   double *__restrict__ cval) {
-    const int r = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-    const int lane = (int)(threadIdx.x & 63);
+    const int r = blockIdx.x * (256 / L) + (int)(threadIdx.x / L);
+    const int lane = (int)(threadIdx.x % L);
     if (r >= nrows) return;
-    const int i = rows[r];
+    const int i = rows ? rows[r] : r;   // rows == nullptr: every row, in order
     const int b = crp[i], len = crp[i + 1] - b;
     if (len > W) return;
     const int64_t p = (int64_t)r * W;
-    for (int e = lane; e < len; e += 64) {
+    for (int e = lane; e < len; e += L) {
         ccol[b + e] = pcol[p + e];
         cval[b + e] = pval[p + e];
     }
@@ -953,9 +893,14 @@ static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, c
     C.val.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
     for (int c = 0; c < 3; ++c) {
         if (hc[c] <= 0) continue;
-        k_pad_copy<<<(unsigned)((hc[c] + 3) / 4), 256, 0, s>>>(lists.get() + c * M, hc[c], W[c], pcol.get() + off[c],
-                                                               pval.get() + off[c], C.rp.get(), C.col.get(),
-                                                               C.val.get());
+        if (W[c] <= 16)
+            k_pad_copy<16><<<(unsigned)((hc[c] + 15) / 16), 256, 0, s>>>(lists.get() + c * M, hc[c], W[c],
+                                                                         pcol.get() + off[c], pval.get() + off[c],
+                                                                         C.rp.get(), C.col.get(), C.val.get());
+        else
+            k_pad_copy<64><<<(unsigned)((hc[c] + 3) / 4), 256, 0, s>>>(lists.get() + c * M, hc[c], W[c],
+                                                                       pcol.get() + off[c], pval.get() + off[c],
+                                                                       C.rp.get(), C.col.get(), C.val.get());
         OCP_LAUNCH_CHECK();
     }
     if (nretry == 0) return;
@@ -969,32 +914,36 @@ static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, c
                                    C.col.get(), C.val.get());
 }
 
-// C = A B when nearly every row of C has at most 16 columns: rows are counted
-// in registers, formed by the 32-slot hash pass over every row, and the few
-// longer rows are counted and formed in larger tables
+// C = A B when nearly every row of C has at most 16 columns: every row is
+// formed in a 32-slot table by 4 lanes and written to a 16-wide padded slot;
+// the few longer rows are counted and formed in larger tables
 static void spgemm_small_rows(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, const int32_t *acol,
                               const double *aval, const int32_t *brp, const int32_t *bcol, const double *bval,
                               Csr &C) {
+    constexpr int W = 16;
     hipStream_t s = ctx->stream;
+    const size_t pn = (size_t)std::max<int64_t>((int64_t)m * W, 1);
+    DevBuf<int32_t> pcol(ctx, pn);
+    DevBuf<double> pval(ctx, pn);
     DevBuf<int32_t> cnt(ctx, (size_t)m + 1);
-    DevBuf<int32_t> over(ctx, (size_t)m + 1);   // over[m]: number of listed rows
-    fill_zero_bytes(ctx, over.get() + m, 4);
-    k_ab_count<4, 4><<<grid_for(m, 256), 256, 0, s>>>(m, arp, acol, brp, bcol, cnt.get(), over.get(), over.get() + m);
-    OCP_LAUNCH_CHECK();
-    int32_t nover = 0;
-    read_back(ctx, &nover, over.get() + m, 4);
+    DevBuf<int32_t> retry(ctx, (size_t)m + 1);   // retry[m]: number of listed rows
+    fill_zero_bytes(ctx, retry.get() + m, 4);
+    launch_grp<4, 32, true, W>(ctx, nullptr, m, arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(), pcol.get(),
+                               pval.get(), retry.get(), retry.get() + m);
+    int32_t nretry = 0;
+    read_back(ctx, &nretry, retry.get() + m, 4);
     // rows past 16 columns: counted in 512 slots, recounted in 4096 slots
     // when more than 384 columns show up
     int32_t nlong = 0;
-    DevBuf<int32_t> retry(ctx, (size_t)std::max(nover, 1) + 1);
-    if (nover > 0) {
-        fill_zero_bytes(ctx, retry.get() + std::max(nover, 1), 4);
+    DevBuf<int32_t> retry2(ctx, (size_t)std::max(nretry, 1) + 1);
+    if (nretry > 0) {
+        fill_zero_bytes(ctx, retry2.get() + std::max(nretry, 1), 4);
         fill_zero_bytes(ctx, ctx->dev_flag, 4);
-        launch_grp<16, 512, false>(ctx, over.get(), nover, arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
-                                   nullptr, nullptr, retry.get(), retry.get() + std::max(nover, 1));
-        read_back(ctx, &nlong, retry.get() + std::max(nover, 1), 4);
+        launch_grp<16, 512, false>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
+                                   nullptr, nullptr, retry2.get(), retry2.get() + std::max(nretry, 1));
+        read_back(ctx, &nlong, retry2.get() + std::max(nretry, 1), 4);
         if (nlong > 0)
-            launch_grp<64, 4096, false>(ctx, retry.get(), nlong, arp, acol, aval, brp, bcol, bval, nullptr,
+            launch_grp<64, 4096, false>(ctx, retry2.get(), nlong, arp, acol, aval, brp, bcol, bval, nullptr,
                                         cnt.get(), nullptr, nullptr);
         int32_t fl = 0;
         read_back(ctx, &fl, ctx->dev_flag, 4);
@@ -1006,17 +955,17 @@ static void spgemm_small_rows(ocp_ctx *ctx, int32_t m, int32_t ncols, const int3
     C.nnz = scan_exclusive(ctx, cnt.get(), C.rp.get(), m);
     C.col.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
     C.val.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
-    // rows of at most 16 columns (the pass skips the others)
-    launch_grp<4, 32, true>(ctx, nullptr, m, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr, C.col.get(),
-                            C.val.get());
-    if (nover == 0) return;
+    k_pad_copy<W><<<(unsigned)((m + 255 / W) / (256 / W)), 256, 0, s>>>(nullptr, m, W, pcol.get(), pval.get(),
+                                                                        C.rp.get(), C.col.get(), C.val.get());
+    OCP_LAUNCH_CHECK();
+    if (nretry == 0) return;
     // every listed row holds at most 384 columns unless some were recounted,
     // then all of them go through the 4096-slot table
     if (nlong == 0)
-        launch_grp<16, 512, true>(ctx, over.get(), nover, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr,
+        launch_grp<16, 512, true>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr,
                                   C.col.get(), C.val.get());
     else
-        launch_grp<64, 4096, true>(ctx, over.get(), nover, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr,
+        launch_grp<64, 4096, true>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr,
                                    C.col.get(), C.val.get());
 }
 

@@ -426,6 +426,37 @@ __global__ void k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp, const in
     ub[i] = (int32_t)(s > INT32_MAX ? INT32_MAX : s);
 }
 
+// the same bound with G lanes per row, for long A rows
+template <int G>
+__global__ void __launch_bounds__(256) k_spgemm_ub_grp(int32_t m, const int32_t *__restrict__ arp,
+                                                       const int32_t *__restrict__ acol,
+                                                       const int32_t *__restrict__ brp, int32_t *__restrict__ ub) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int i = (int)(t / G), lane = (int)(t % G);
+    if (i >= m) return;   // uniform over the group
+    int64_t s = 0;
+    const int ke = arp[i + 1];
+    constexpr int U = 2;   // columns, then their row extents, requested together
+    for (int k0 = arp[i] + lane; k0 < ke; k0 += U * G) {
+        int c[U], b0[U], b1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * G < ke) c[u] = acol[k0 + u * G];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * G < ke) {
+                b0[u] = brp[c[u]];
+                b1[u] = brp[c[u] + 1];
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * G < ke) s += b1[u] - b0[u];
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+    if (lane == 0) ub[i] = (int32_t)(s > INT32_MAX ? INT32_MAX : s);
+}
+
 constexpr int kSpgemmClasses = 5;
 struct ClassBounds {
     int lim[kSpgemmClasses - 1];   // class q holds keys <= lim[q]; the last class the rest
@@ -833,11 +864,14 @@ __global__ void __launch_bounds__(256) k_pad_copy(const int32_t *__restrict__ ro
 // 384 columns retried).  Retried rows are counted in 512 slots (4096 past
 // 384 columns) and formed in the CSR directly, after the scan of the lengths.
 constexpr int kWideRows = 16384;
-static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, const int32_t *acol, const double *aval,
-                   const int32_t *brp, const int32_t *bcol, const double *bval, Csr &C) {
+static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t annz, const int32_t *arp, const int32_t *acol,
+                   const double *aval, const int32_t *brp, const int32_t *bcol, const double *bval, Csr &C) {
     hipStream_t s = ctx->stream;
     DevBuf<int32_t> ub(ctx, (size_t)m + 1);
-    k_spgemm_ub<<<grid_for(m, 256), 256, 0, s>>>(m, arp, acol, brp, ub.get());
+    if (annz >= 32 * (int64_t)m)   // long A rows: 16 lanes per row
+        k_spgemm_ub_grp<16><<<grid_for((int64_t)m * 16, 256), 256, 0, s>>>(m, arp, acol, brp, ub.get());
+    else
+        k_spgemm_ub<<<grid_for(m, 256), 256, 0, s>>>(m, arp, acol, brp, ub.get());
     OCP_LAUNCH_CHECK();
     DevBuf<int32_t> counts(ctx, 8);
     fill_zero_bytes(ctx, counts.get(), 32);
@@ -971,10 +1005,11 @@ static void spgemm_small_rows(ocp_ctx *ctx, int32_t m, int32_t ncols, const int3
 
 // C = A P_tent: the register kernel when every A row has at most 16 entries,
 // otherwise the general product with P_tent as a CSR matrix
-static void spgemm_ptent(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, const int32_t *acol,
-                         const double *aval, const int32_t *agg, const int32_t *trp, const double *pt, Csr &C) {
+static void spgemm_ptent(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t annz, const int32_t *arp,
+                         const int32_t *acol, const double *aval, const int32_t *agg, const int32_t *trp,
+                         const double *pt, Csr &C) {
     if (csr_max_row(ctx, m, arp) > 16) {
-        spgemm(ctx, m, ncols, arp, acol, aval, trp, agg, pt, C);
+        spgemm(ctx, m, ncols, annz, arp, acol, aval, trp, agg, pt, C);
         return;
     }
     DevBuf<int32_t> cnt(ctx, (size_t)m + 1);
@@ -1361,7 +1396,7 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
         OCP_LAUNCH_CHECK();
         // smoothed prolongator P = (I - w D^-1 A) P_tent
         Csr P;
-        spgemm_ptent(ctx, n, nc, L.A_rp, L.A_col, L.A_val, tcol.get(), trp.get(), tval.get(), P);
+        spgemm_ptent(ctx, n, nc, L.nnzA, L.A_rp, L.A_col, L.A_val, tcol.get(), trp.get(), tval.get(), P);
         const double w = pr.omega / L.lambda_max;
         k_smooth_p<<<grid_for(n, 256), 256, 0, s>>>(n, P.rp.get(), P.col.get(), P.val.get(), diag.get(), L.agg.get(),
                                                     tval.get(), w);
@@ -1375,8 +1410,9 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
         if (L.nnzA <= 16 * (int64_t)n)
             spgemm_small_rows(ctx, n, nc, L.A_rp, L.A_col, L.A_val, P.rp.get(), P.col.get(), P.val.get(), AP);
         else
-            spgemm(ctx, n, nc, L.A_rp, L.A_col, L.A_val, P.rp.get(), P.col.get(), P.val.get(), AP);
-        spgemm(ctx, nc, nc, R.rp.get(), R.col.get(), R.val.get(), AP.rp.get(), AP.col.get(), AP.val.get(), Ac);
+            spgemm(ctx, n, nc, L.nnzA, L.A_rp, L.A_col, L.A_val, P.rp.get(), P.col.get(), P.val.get(), AP);
+        spgemm(ctx, nc, nc, P.nnz, R.rp.get(), R.col.get(), R.val.get(), AP.rp.get(), AP.col.get(), AP.val.get(),
+               Ac);
         sync(ctx);
 
         L.nc = nc;

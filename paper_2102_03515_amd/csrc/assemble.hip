@@ -540,16 +540,36 @@ __global__ void __launch_bounds__(kLoadBlock) k_tet_load(const int4 *__restrict_
 // element values are accumulated into register slots (one per row entry,
 // matched by column).  Entry (i,j) and entry (j,i) therefore add the same
 // element values in the same order: the assembled A is bitwise symmetric.
-// The records of U incident tets are requested before any is used.
+// The records of U incident tets are requested before any is used.  A
+// wavefront holds the 64 rows of one slice of the sliced-ELL copy, so with
+// its layout given (sc) the rows are also stored there, padding included
+// (column = row, value 0), by consecutive stores.
+struct SellOut {
+    int64_t nslices = 0;
+    const int32_t *sp = nullptr, *sw = nullptr;
+    int32_t *col = nullptr;
+    double *val = nullptr;
+};
 template <int MAXS, bool KM>
 __global__ void __launch_bounds__(256) k_row_numeric(
     int32_t n, double rho, const int32_t *__restrict__ vertex_of_dof, const int32_t *__restrict__ inc_ptr,
     const int32_t *__restrict__ inc, const double *__restrict__ rec, const double *__restrict__ vol_in,
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col, double *__restrict__ val,
-    double *__restrict__ valK, double *__restrict__ valM, double *__restrict__ f) {
+    double *__restrict__ valK, double *__restrict__ valM, double *__restrict__ f, SellOut sc) {
 #pragma clang fp contract(off)
     const int i = blockIdx.x * 256 + (int)threadIdx.x;
-    if (i >= n) return;
+    if (i >= n) {
+        // padding rows of the last slice
+        const int64_t s = i / kSellC;
+        if (!sc.val || s >= sc.nslices) return;
+        const int w = sc.sw[s];
+        const int64_t base = sc.sp[s] + (threadIdx.x & (kSellC - 1));
+        for (int q = 0; q < w; ++q) {
+            sc.col[base + (int64_t)q * kSellC] = 0;
+            sc.val[base + (int64_t)q * kSellC] = 0.0;
+        }
+        return;
+    }
     const int vi = vertex_of_dof[i];
     const int rb = row_ptr[i], len = row_ptr[i + 1] - rb;
     int cols[MAXS];
@@ -624,19 +644,31 @@ __global__ void __launch_bounds__(256) k_row_numeric(
             }
         }
     f[i] = fi;
+    if (sc.val) {
+        const int64_t s = i / kSellC;
+        const int w = sc.sw[s];   // the slice's longest row: at most MAXS
+        const int64_t base = sc.sp[s] + (threadIdx.x & (kSellC - 1));
+#pragma unroll
+        for (int q = 0; q < MAXS; ++q)
+            if (q < w) {
+                sc.col[base + (int64_t)q * kSellC] = q < len ? cols[q] : i;
+                sc.val[base + (int64_t)q * kSellC] = q < len ? acc[q] : 0.0;
+            }
+    }
 }
 
 template <int MAXS>
-static void launch_numeric(ocp_ctx *ctx, ocp_system *sys, double rho, const double *rec, const double *vol) {
+static void launch_numeric(ocp_ctx *ctx, ocp_system *sys, double rho, const double *rec, const double *vol,
+                           const SellOut &sc) {
     const unsigned g = grid_for(sys->n, 256);
     if (sys->valK.get())
         k_row_numeric<MAXS, true><<<g, 256, 0, ctx->stream>>>(
             sys->n, rho, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(), rec, vol, sys->row_ptr.get(),
-            sys->col.get(), sys->val.get(), sys->valK.get(), sys->valM.get(), sys->f.get());
+            sys->col.get(), sys->val.get(), sys->valK.get(), sys->valM.get(), sys->f.get(), sc);
     else
         k_row_numeric<MAXS, false><<<g, 256, 0, ctx->stream>>>(
             sys->n, rho, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(), rec, nullptr,
-            sys->row_ptr.get(), sys->col.get(), sys->val.get(), nullptr, nullptr, sys->f.get());
+            sys->row_ptr.get(), sys->col.get(), sys->val.get(), nullptr, nullptr, sys->f.get(), sc);
     OCP_LAUNCH_CHECK();
 }
 
@@ -932,17 +964,24 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
         sys->valK.reset(ctx, (size_t)sys->nnz);
         sys->valM.reset(ctx, (size_t)sys->nnz);
     }
+    // the rows go to the CSR and to the sliced-ELL copy for the solve phase
+    sell_layout(ctx, sys->sell, n, sys->row_ptr.get());
+    SellOut sc;
+    sc.nslices = sys->sell.nslices;
+    sc.sp = sys->sell.sp.get();
+    sc.sw = sys->sell.sw.get();
+    sc.col = sys->sell.col.get();
+    sc.val = sys->sell.val.get();
     if (maxlen <= 16 || max_row_len(ctx, sys) <= 16)
-        launch_numeric<16>(ctx, sys, rho, rec.get(), vol.get());
+        launch_numeric<16>(ctx, sys, rho, rec.get(), vol.get(), sc);
     else if (max_row_len(ctx, sys) <= 32)
-        launch_numeric<32>(ctx, sys, rho, rec.get(), vol.get());
+        launch_numeric<32>(ctx, sys, rho, rec.get(), vol.get(), sc);
     else if (max_row_len(ctx, sys) <= 64)
-        launch_numeric<64>(ctx, sys, rho, rec.get(), vol.get());
+        launch_numeric<64>(ctx, sys, rho, rec.get(), vol.get(), sc);
     else
-        launch_numeric<128>(ctx, sys, rho, rec.get(), vol.get());
+        launch_numeric<128>(ctx, sys, rho, rec.get(), vol.get(), sc);
     OCP_LAUNCH_CHECK();
-    // sliced-ELL copy for the solve phase
-    system_sell(ctx, sys);
+    sell_codes(ctx, sys->sell);
     sync(ctx);
 }
 

@@ -141,8 +141,9 @@ __global__ void k_sell_code_words(int64_t nslices, const int32_t *__restrict__ s
     if (s < nslices) words[s] = (sw[s] + 7) / 8 * kSellC;
 }
 
-// Build the slice structure and column array (values follow with sell_values).
-void sell_build(ocp_ctx *ctx, Sell &S, int32_t n, const int32_t *rp, const int32_t *col, const double *val) {
+// Slice widths and offsets of the CSR matrix, with the column and value
+// arrays allocated (filled by sell_build or by the caller).
+void sell_layout(ocp_ctx *ctx, Sell &S, int32_t n, const int32_t *rp) {
     S.n = n;
     S.nslices = (n + kSellC - 1) / kSellC;
     DevBuf<int32_t> w64(ctx, (size_t)S.nslices + 1);
@@ -155,10 +156,11 @@ void sell_build(ocp_ctx *ctx, Sell &S, int32_t n, const int32_t *rp, const int32
     S.nnz_padded = scan_exclusive(ctx, w64.get(), S.sp.get(), S.nslices);
     S.col.reset(ctx, (size_t)S.nnz_padded);
     S.val.reset(ctx, (size_t)S.nnz_padded);
-    k_sell_fill<double><<<grid_for((int64_t)S.nslices * kSellC, 256), 256, 0, ctx->stream>>>(
-        n, S.nslices, rp, col, val, S.sp.get(), S.sw.get(), S.col.get(), S.val.get());
-    OCP_LAUNCH_CHECK();
-    // column codes (kept only if every slice fits the dictionary)
+}
+
+// Column codes of filled slices (kept only if every slice fits the dictionary).
+void sell_codes(ocp_ctx *ctx, Sell &S) {
+    const int32_t n = S.n;
     DevBuf<int32_t> words(ctx, (size_t)S.nslices + 1);
     k_sell_code_words<<<grid_for(S.nslices, 256), 256, 0, ctx->stream>>>(S.nslices, S.sw.get(), words.get());
     OCP_LAUNCH_CHECK();
@@ -177,6 +179,15 @@ void sell_build(ocp_ctx *ctx, Sell &S, int32_t n, const int32_t *rp, const int32
         S.cp.release();
         S.dict.release();
     }
+}
+
+// The whole sliced-ELL copy of a CSR matrix: layout, columns and values, codes.
+void sell_build(ocp_ctx *ctx, Sell &S, int32_t n, const int32_t *rp, const int32_t *col, const double *val) {
+    sell_layout(ctx, S, n, rp);
+    k_sell_fill<double><<<grid_for((int64_t)S.nslices * kSellC, 256), 256, 0, ctx->stream>>>(
+        n, S.nslices, rp, col, val, S.sp.get(), S.sw.get(), S.col.get(), S.val.get());
+    OCP_LAUNCH_CHECK();
+    sell_codes(ctx, S);
 }
 
 // Single-precision values of an existing slice structure.

@@ -1425,6 +1425,7 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
         L.R_val = std::move(R.val);
         L.gP = level_lanes(L.nnzP, n);
         L.gR = level_lanes(L.nnzP, nc);
+        L.maxP = csr_max_row(ctx, n, L.P_rp.get());
 
         auto nxt = std::make_unique<Level>();
         nxt->n = nc;

@@ -80,6 +80,7 @@ struct Level {
     int deg = 1;
     double cheb_a = 1.0, cheb_c1 = 0.0, cheb_c2 = 0.0;
     int gA = 16, gP = 4, gR = 64;  // lanes per row of the A, P and R kernels
+    int maxP = 0;                  // longest row of P
 };
 
 }  // namespace ocp

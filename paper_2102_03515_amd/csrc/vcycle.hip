@@ -151,6 +151,45 @@ __global__ void __launch_bounds__(kBlock) k_vc_prolong(int32_t n, int iters, con
     OCP_ROWS_END()
 }
 
+// The same for P with short rows (at most kStreamRow entries): 256 rows per
+// block; the block's entries are read once, consecutively, their products
+// staged in LDS, and each row is summed in entry order by its own thread.
+constexpr int kStreamRow = 16;
+template <typename T, typename BT, bool HX>
+__global__ void __launch_bounds__(kBlock) k_vc_prolong_stream(int32_t n, const int32_t *__restrict__ rp,
+                                                              const int32_t *__restrict__ col,
+                                                              const T *__restrict__ val, const T *__restrict__ d,
+                                                              const BT *__restrict__ b, const T *__restrict__ xs, T a,
+                                                              const T *__restrict__ xc, T *__restrict__ xp,
+                                                              const CgScalars *cg) {
+    if (cg && cg->flag) return;
+    __shared__ T prod[kBlock * kStreamRow];
+    const int r0 = blockIdx.x * kBlock;
+    const int r1 = r0 + kBlock < n ? r0 + kBlock : n;
+    const int e0 = rp[r0], e1 = rp[r1];
+    constexpr int U = 4;   // entries per thread and step, all requested first
+    for (int k0 = e0 + (int)threadIdx.x; k0 < e1; k0 += U * kBlock) {
+        int c[U];
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * kBlock < e1 ? k0 + u * kBlock : e1 - 1;
+            c[u] = dev::ldnt(col + k);
+            v[u] = dev::ldnt(val + k);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * kBlock < e1) prod[k0 + u * kBlock - e0] = v[u] * xc[c[u]];
+    }
+    __syncthreads();
+    const int row = r0 + (int)threadIdx.x;
+    if (row >= n) return;
+    const int kb = rp[row] - e0, ke = rp[row + 1] - e0;
+    T s = T(0);
+    for (int k = kb; k < ke; ++k) s += prod[k];
+    xp[row] = (HX ? xs[row] : a * d[row] * (T)b[row]) + s;
+}
+
 // x = Ainv b on the last level (dense, one wavefront per row)
 template <typename T, typename BT, typename ZT>
 __global__ void __launch_bounds__(kBlock) k_vc_dense(int32_t n, const T *__restrict__ inv, const BT *__restrict__ b,
@@ -370,7 +409,15 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
         const T zero = T(0);
         const RowLaunch LP = row_launch(cur.n, cur.gP);
         const int prp = (cg && l == 0) ? prof_begin(ctx, OCP_KERNEL_VC_PROLONG0) : -1;
-        if (cur.deg == 2) {
+        if (cur.maxP <= kStreamRow) {
+            const unsigned nb = (unsigned)((cur.n + kBlock - 1) / kBlock);
+            if (cur.deg == 2)
+                k_vc_prolong_stream<T, BT, true><<<nb, kBlock, 0, s>>>(cur.n, cur.P_rp.get(), cur.P_col.get(), a.P,
+                                                                       a.d, bptr, x2, ca, xc, xp, cg);
+            else
+                k_vc_prolong_stream<T, BT, false><<<nb, kBlock, 0, s>>>(cur.n, cur.P_rp.get(), cur.P_col.get(), a.P,
+                                                                        a.d, bptr, nullptr, ca, xc, xp, cg);
+        } else if (cur.deg == 2) {
             OCP_DISPATCH_G(cur.gP, (k_vc_prolong<G, T, BT, true><<<LP.blocks, kBlock, 0, s>>>(
                                        cur.n, LP.iters, cur.P_rp.get(), cur.P_col.get(), a.P, a.d, bptr, x2, ca, xc, xp,
                                        cg)));

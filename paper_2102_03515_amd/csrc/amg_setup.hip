@@ -400,8 +400,11 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// B rows are CSR (blen == nullptr: row c spans brp[c] .. brp[c+1]) or given
+// by start and length (row c spans brp[c] .. brp[c] + blen[c]).
 __global__ void k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp, const int32_t *__restrict__ acol,
-                            const int32_t *__restrict__ brp, int32_t *__restrict__ ub) {
+                            const int32_t *__restrict__ brp, const int32_t *__restrict__ blen,
+                            int32_t *__restrict__ ub) {
     // XCD x takes a contiguous run of blocks (measured faster here)
     const int i = (int)dev::xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= m) return;
@@ -417,7 +420,7 @@ __global__ void k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp, const in
         for (int u = 0; u < U; ++u)
             if (k0 + u < ke) {
                 b0[u] = brp[c[u]];
-                b1[u] = brp[c[u] + 1];
+                b1[u] = blen ? b0[u] + blen[c[u]] : brp[c[u] + 1];
             }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -430,7 +433,8 @@ __global__ void k_spgemm_ub(int32_t m, const int32_t *__restrict__ arp, const in
 template <int G>
 __global__ void __launch_bounds__(256) k_spgemm_ub_grp(int32_t m, const int32_t *__restrict__ arp,
                                                        const int32_t *__restrict__ acol,
-                                                       const int32_t *__restrict__ brp, int32_t *__restrict__ ub) {
+                                                       const int32_t *__restrict__ brp,
+                                                       const int32_t *__restrict__ blen, int32_t *__restrict__ ub) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int i = (int)(t / G), lane = (int)(t % G);
     if (i >= m) return;   // uniform over the group
@@ -446,7 +450,7 @@ __global__ void __launch_bounds__(256) k_spgemm_ub_grp(int32_t m, const int32_t 
         for (int u = 0; u < U; ++u)
             if (k0 + u * G < ke) {
                 b0[u] = brp[c[u]];
-                b1[u] = brp[c[u] + 1];
+                b1[u] = blen ? b0[u] + blen[c[u]] : brp[c[u] + 1];
             }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -549,6 +553,7 @@ __device__ __forceinline__ int hash_insert_bounded(int *keys, int key) {
     return -1;
 }
 
+// B rows as in k_spgemm_ub (CSR, or start and length).
 // NUMERIC = false: cnt[i] = number of distinct columns of C row i.
 // NUMERIC = true, W = 0: write C row i (columns ascending) at crp[i].
 // NUMERIC = true, W > 0: write the row at ccol/cval + r W, r its position in
@@ -559,6 +564,7 @@ template <int G, int H, bool NUMERIC, int W = 0>
 __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ rows, int32_t nrows,
                                                    const int32_t *__restrict__ arp, const int32_t *__restrict__ acol,
                                                    const double *__restrict__ aval, const int32_t *__restrict__ brp,
+                                                   const int32_t *__restrict__ blen,
                                                    const int32_t *__restrict__ bcol, const double *__restrict__ bval,
                                                    const int32_t *__restrict__ crp, int32_t *__restrict__ cnt,
                                                    int32_t *__restrict__ ccol, double *__restrict__ cval,
@@ -617,7 +623,7 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
                 const int c = acol[kb + lane];
                 if (NUMERIC) am = aval[kb + lane];
                 tb = brp[c];
-                tn = brp[c + 1];
+                tn = blen ? tb + blen[c] : brp[c + 1];
             }
             const int cnt = ke - kb < G ? ke - kb : G;
             if constexpr (MB > 0) {
@@ -708,12 +714,13 @@ template <int G, int H, bool NUMERIC, int W = 0>
 static void launch_grp(ocp_ctx *ctx, const int32_t *rows, int32_t nrows, const int32_t *arp, const int32_t *acol,
                        const double *aval, const int32_t *brp, const int32_t *bcol, const double *bval,
                        const int32_t *crp, int32_t *cnt, int32_t *ccol, double *cval, int32_t *retry = nullptr,
-                       int32_t *nretry = nullptr) {
+                       int32_t *nretry = nullptr, const int32_t *blen = nullptr) {
     if (nrows <= 0) return;
     constexpr int RPW = 64 / G;
     const unsigned blocks = (unsigned)((nrows + RPW - 1) / RPW);
-    k_spgemm_grp<G, H, NUMERIC, W><<<blocks, 64, 0, ctx->stream>>>(rows, nrows, arp, acol, aval, brp, bcol, bval, crp,
-                                                                    cnt, ccol, cval, ctx->dev_flag, retry, nretry);
+    k_spgemm_grp<G, H, NUMERIC, W><<<blocks, 64, 0, ctx->stream>>>(rows, nrows, arp, acol, aval, brp, blen, bcol, bval,
+                                                                    crp, cnt, ccol, cval, ctx->dev_flag, retry,
+                                                                    nretry);
     OCP_LAUNCH_CHECK();
 }
 
@@ -865,13 +872,14 @@ __global__ void __launch_bounds__(256) k_pad_copy(const int32_t *__restrict__ ro
 // 384 columns) and formed in the CSR directly, after the scan of the lengths.
 constexpr int kWideRows = 16384;
 static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t annz, const int32_t *arp, const int32_t *acol,
-                   const double *aval, const int32_t *brp, const int32_t *bcol, const double *bval, Csr &C) {
+                   const double *aval, const int32_t *brp, const int32_t *bcol, const double *bval, Csr &C,
+                   const int32_t *blen = nullptr) {
     hipStream_t s = ctx->stream;
     DevBuf<int32_t> ub(ctx, (size_t)m + 1);
     if (annz >= 32 * (int64_t)m)   // long A rows: 16 lanes per row
-        k_spgemm_ub_grp<16><<<grid_for((int64_t)m * 16, 256), 256, 0, s>>>(m, arp, acol, brp, ub.get());
+        k_spgemm_ub_grp<16><<<grid_for((int64_t)m * 16, 256), 256, 0, s>>>(m, arp, acol, brp, blen, ub.get());
     else
-        k_spgemm_ub<<<grid_for(m, 256), 256, 0, s>>>(m, arp, acol, brp, ub.get());
+        k_spgemm_ub<<<grid_for(m, 256), 256, 0, s>>>(m, arp, acol, brp, blen, ub.get());
     OCP_LAUNCH_CHECK();
     DevBuf<int32_t> counts(ctx, 8);
     fill_zero_bytes(ctx, counts.get(), 32);
@@ -893,15 +901,15 @@ static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t annz, const i
     fill_zero_bytes(ctx, retry.get() + m, 4);
     int32_t *nr = retry.get() + m;
     launch_grp<4, 32, true, 16>(ctx, lists.get(), hc[0], arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
-                                pcol.get(), pval.get(), retry.get(), nr);
+                                pcol.get(), pval.get(), retry.get(), nr, blen);
     launch_grp<4, 64, true, 48>(ctx, lists.get() + M, hc[1], arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
-                                pcol.get() + off[1], pval.get() + off[1], retry.get(), nr);
+                                pcol.get() + off[1], pval.get() + off[1], retry.get(), nr, blen);
     if (wide)
         launch_grp<64, 512, true, 384>(ctx, lists.get() + 2 * M, hc[2], arp, acol, aval, brp, bcol, bval, nullptr,
-                                       cnt.get(), pcol.get() + off[2], pval.get() + off[2], retry.get(), nr);
+                                       cnt.get(), pcol.get() + off[2], pval.get() + off[2], retry.get(), nr, blen);
     else
         launch_grp<8, 128, true, 96>(ctx, lists.get() + 2 * M, hc[2], arp, acol, aval, brp, bcol, bval, nullptr,
-                                     cnt.get(), pcol.get() + off[2], pval.get() + off[2], retry.get(), nr);
+                                     cnt.get(), pcol.get() + off[2], pval.get() + off[2], retry.get(), nr, blen);
     int32_t nretry = 0;
     read_back(ctx, &nretry, nr, 4);
     int32_t nlong = 0;
@@ -910,11 +918,11 @@ static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t annz, const i
         fill_zero_bytes(ctx, retry2.get() + std::max(nretry, 1), 4);
         fill_zero_bytes(ctx, ctx->dev_flag, 4);
         launch_grp<16, 512, false>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
-                                   nullptr, nullptr, retry2.get(), retry2.get() + std::max(nretry, 1));
+                                   nullptr, nullptr, retry2.get(), retry2.get() + std::max(nretry, 1), blen);
         read_back(ctx, &nlong, retry2.get() + std::max(nretry, 1), 4);
         if (nlong > 0)
             launch_grp<64, 4096, false>(ctx, retry2.get(), nlong, arp, acol, aval, brp, bcol, bval, nullptr,
-                                        cnt.get(), nullptr, nullptr);
+                                        cnt.get(), nullptr, nullptr, nullptr, nullptr, blen);
         int32_t fl = 0;
         read_back(ctx, &fl, ctx->dev_flag, 4);
         if (fl & 32) fail(OCP_ERR_UNSUPPORTED, "sparse product row with more than 3072 entries");
@@ -942,65 +950,101 @@ static void spgemm(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t annz, const i
     // then all of them go through the 4096-slot table
     if (nlong == 0)
         launch_grp<16, 512, true>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr,
-                                  C.col.get(), C.val.get());
+                                  C.col.get(), C.val.get(), nullptr, nullptr, blen);
     else
         launch_grp<64, 4096, true>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr,
-                                   C.col.get(), C.val.get());
+                                   C.col.get(), C.val.get(), nullptr, nullptr, blen);
 }
 
-// C = A B when nearly every row of C has at most 16 columns: every row is
-// formed in a 32-slot table by 4 lanes and written to a 16-wide padded slot;
-// the few longer rows are counted and formed in larger tables
-static void spgemm_small_rows(ocp_ctx *ctx, int32_t m, int32_t ncols, const int32_t *arp, const int32_t *acol,
-                              const double *aval, const int32_t *brp, const int32_t *bcol, const double *bval,
-                              Csr &C) {
+// A product kept in padded form for use as the B operand of a following
+// product: row i spans col/val[start[i] .. start[i] + len[i]).
+struct PadCsr {
+    DevBuf<int32_t> start, len, col;
+    DevBuf<double> val;
+};
+
+__global__ void k_pad_starts(int32_t m, int W, int32_t *__restrict__ start) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) start[i] = i * W;
+}
+
+__global__ void k_gather_len(int32_t nr, const int32_t *__restrict__ rows, const int32_t *__restrict__ len,
+                             int32_t *__restrict__ out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nr) out[r] = len[rows[r]];
+}
+
+__global__ void k_set_starts(int32_t nr, const int32_t *__restrict__ rows, const int32_t *__restrict__ off,
+                             int32_t base, int32_t *__restrict__ start) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nr) start[rows[r]] = base + off[r];
+}
+
+// C = A B when nearly every row of C has at most 16 columns, left in padded
+// form: every row is formed in a 32-slot table by 4 lanes into its 16-wide
+// slot; the few longer rows are counted and formed in larger tables into a
+// region after the slots (m entries are reserved for them; a larger need
+// moves the slots to a bigger buffer first).
+static void spgemm_small_rows(ocp_ctx *ctx, int32_t m, const int32_t *arp, const int32_t *acol, const double *aval,
+                              const int32_t *brp, const int32_t *bcol, const double *bval, PadCsr &C) {
     constexpr int W = 16;
     hipStream_t s = ctx->stream;
-    const size_t pn = (size_t)std::max<int64_t>((int64_t)m * W, 1);
-    DevBuf<int32_t> pcol(ctx, pn);
-    DevBuf<double> pval(ctx, pn);
-    DevBuf<int32_t> cnt(ctx, (size_t)m + 1);
+    const int64_t slots = (int64_t)m * W;
+    if (slots + m > INT32_MAX) fail(OCP_ERR_UNSUPPORTED, "padded product too large");
+    int64_t cap = slots + std::max<int64_t>(m, 1);
+    C.col.reset(ctx, (size_t)cap);
+    C.val.reset(ctx, (size_t)cap);
+    C.len.reset(ctx, (size_t)m + 1);
+    C.start.reset(ctx, (size_t)m + 1);
+    k_pad_starts<<<grid_for(m, 256), 256, 0, s>>>(m, W, C.start.get());
+    OCP_LAUNCH_CHECK();
     DevBuf<int32_t> retry(ctx, (size_t)m + 1);   // retry[m]: number of listed rows
     fill_zero_bytes(ctx, retry.get() + m, 4);
-    launch_grp<4, 32, true, W>(ctx, nullptr, m, arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(), pcol.get(),
-                               pval.get(), retry.get(), retry.get() + m);
+    launch_grp<4, 32, true, W>(ctx, nullptr, m, arp, acol, aval, brp, bcol, bval, nullptr, C.len.get(), C.col.get(),
+                               C.val.get(), retry.get(), retry.get() + m);
     int32_t nretry = 0;
     read_back(ctx, &nretry, retry.get() + m, 4);
+    if (nretry == 0) return;
     // rows past 16 columns: counted in 512 slots, recounted in 4096 slots
     // when more than 384 columns show up
     int32_t nlong = 0;
-    DevBuf<int32_t> retry2(ctx, (size_t)std::max(nretry, 1) + 1);
-    if (nretry > 0) {
-        fill_zero_bytes(ctx, retry2.get() + std::max(nretry, 1), 4);
-        fill_zero_bytes(ctx, ctx->dev_flag, 4);
-        launch_grp<16, 512, false>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, nullptr, cnt.get(),
-                                   nullptr, nullptr, retry2.get(), retry2.get() + std::max(nretry, 1));
-        read_back(ctx, &nlong, retry2.get() + std::max(nretry, 1), 4);
-        if (nlong > 0)
-            launch_grp<64, 4096, false>(ctx, retry2.get(), nlong, arp, acol, aval, brp, bcol, bval, nullptr,
-                                        cnt.get(), nullptr, nullptr);
-        int32_t fl = 0;
-        read_back(ctx, &fl, ctx->dev_flag, 4);
-        if (fl & 32) fail(OCP_ERR_UNSUPPORTED, "sparse product row with more than 3072 entries");
-    }
-    C.rows = m;
-    C.cols = ncols;
-    C.rp.reset(ctx, (size_t)m + 1);
-    C.nnz = scan_exclusive(ctx, cnt.get(), C.rp.get(), m);
-    C.col.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
-    C.val.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
-    k_pad_copy<W><<<(unsigned)((m + 255 / W) / (256 / W)), 256, 0, s>>>(nullptr, m, W, pcol.get(), pval.get(),
-                                                                        C.rp.get(), C.col.get(), C.val.get());
+    DevBuf<int32_t> retry2(ctx, (size_t)nretry + 1);
+    fill_zero_bytes(ctx, retry2.get() + nretry, 4);
+    fill_zero_bytes(ctx, ctx->dev_flag, 4);
+    launch_grp<16, 512, false>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, nullptr, C.len.get(),
+                               nullptr, nullptr, retry2.get(), retry2.get() + nretry);
+    read_back(ctx, &nlong, retry2.get() + nretry, 4);
+    if (nlong > 0)
+        launch_grp<64, 4096, false>(ctx, retry2.get(), nlong, arp, acol, aval, brp, bcol, bval, nullptr, C.len.get(),
+                                    nullptr, nullptr);
+    int32_t fl = 0;
+    read_back(ctx, &fl, ctx->dev_flag, 4);
+    if (fl & 32) fail(OCP_ERR_UNSUPPORTED, "sparse product row with more than 3072 entries");
+    // the listed rows go after the slots, in list order
+    DevBuf<int32_t> lens(ctx, (size_t)nretry + 1), off(ctx, (size_t)nretry + 1);
+    k_gather_len<<<grid_for(nretry, 256), 256, 0, s>>>(nretry, retry.get(), C.len.get(), lens.get());
     OCP_LAUNCH_CHECK();
-    if (nretry == 0) return;
+    const int64_t extra = scan_exclusive(ctx, lens.get(), off.get(), nretry);
+    if (slots + extra > INT32_MAX) fail(OCP_ERR_UNSUPPORTED, "padded product too large");
+    if (slots + extra > cap) {
+        DevBuf<int32_t> col2(ctx, (size_t)(slots + extra));
+        DevBuf<double> val2(ctx, (size_t)(slots + extra));
+        OCP_HIP(hipMemcpyAsync(col2.get(), C.col.get(), sizeof(int32_t) * (size_t)slots, hipMemcpyDeviceToDevice, s));
+        OCP_HIP(hipMemcpyAsync(val2.get(), C.val.get(), sizeof(double) * (size_t)slots, hipMemcpyDeviceToDevice, s));
+        C.col = std::move(col2);
+        C.val = std::move(val2);
+    }
+    k_set_starts<<<grid_for(nretry, 256), 256, 0, s>>>(nretry, retry.get(), off.get(), (int32_t)slots,
+                                                        C.start.get());
+    OCP_LAUNCH_CHECK();
     // every listed row holds at most 384 columns unless some were recounted,
     // then all of them go through the 4096-slot table
     if (nlong == 0)
-        launch_grp<16, 512, true>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr,
+        launch_grp<16, 512, true>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, C.start.get(), nullptr,
                                   C.col.get(), C.val.get());
     else
-        launch_grp<64, 4096, true>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, C.rp.get(), nullptr,
-                                   C.col.get(), C.val.get());
+        launch_grp<64, 4096, true>(ctx, retry.get(), nretry, arp, acol, aval, brp, bcol, bval, C.start.get(),
+                                   nullptr, C.col.get(), C.val.get());
 }
 
 // C = A P_tent: the register kernel when every A row has at most 16 entries,
@@ -1404,15 +1448,20 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
         // restriction and Galerkin product
         Csr R;
         transpose(ctx, n, nc, P.nnz, P.rp.get(), P.col.get(), P.val.get(), R);
-        Csr AP, Ac;
-        // rows of A P are counted in registers when A's rows are short on
-        // average (a thread per row walks its A row serially)
-        if (L.nnzA <= 16 * (int64_t)n)
-            spgemm_small_rows(ctx, n, nc, L.A_rp, L.A_col, L.A_val, P.rp.get(), P.col.get(), P.val.get(), AP);
-        else
+        Csr Ac;
+        // A P in padded 16-wide rows when A's rows are short on average
+        // (their products rarely pass 16 columns), else in CSR
+        if (L.nnzA <= 16 * (int64_t)n) {
+            PadCsr AP;
+            spgemm_small_rows(ctx, n, L.A_rp, L.A_col, L.A_val, P.rp.get(), P.col.get(), P.val.get(), AP);
+            spgemm(ctx, nc, nc, P.nnz, R.rp.get(), R.col.get(), R.val.get(), AP.start.get(), AP.col.get(),
+                   AP.val.get(), Ac, AP.len.get());
+        } else {
+            Csr AP;
             spgemm(ctx, n, nc, L.nnzA, L.A_rp, L.A_col, L.A_val, P.rp.get(), P.col.get(), P.val.get(), AP);
-        spgemm(ctx, nc, nc, P.nnz, R.rp.get(), R.col.get(), R.val.get(), AP.rp.get(), AP.col.get(), AP.val.get(),
-               Ac);
+            spgemm(ctx, nc, nc, P.nnz, R.rp.get(), R.col.get(), R.val.get(), AP.rp.get(), AP.col.get(),
+                   AP.val.get(), Ac);
+        }
         sync(ctx);
 
         L.nc = nc;

@@ -301,14 +301,15 @@ __global__ void __launch_bounds__(kAsmBlock) k_row_symbolic(
     }
 }
 
-// copy the padded sorted lists into CSR
+// copy the padded sorted lists into CSR, kPadLanes lanes per row
+constexpr int kPadLanes = 16;
 __global__ void k_pad_to_csr(int32_t n, const int32_t *__restrict__ pad, const int32_t *__restrict__ row_ptr,
                              int32_t *__restrict__ col) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = (int)(t / kPadW), s = (int)(t % kPadW);
+    const int i = (int)(t / kPadLanes), s0 = (int)(t % kPadLanes);
     if (i >= n) return;
-    const int b = row_ptr[i];
-    if (s < row_ptr[i + 1] - b) col[b + s] = pad[t];
+    const int b = row_ptr[i], len = row_ptr[i + 1] - b;
+    for (int s = s0; s < len; s += kPadLanes) col[b + s] = pad[(int64_t)i * kPadW + s];
 }
 
 // --------------------------------------------- 4. element loads and records
@@ -544,11 +545,16 @@ __global__ void __launch_bounds__(kLoadBlock) k_tet_load(const int4 *__restrict_
 // wavefront holds the 64 rows of one slice of the sliced-ELL copy, so with
 // its layout given (sc) the rows are also stored there, padding included
 // (column = row, value 0), by consecutive stores.
+// With code given, the wavefront also builds its slice's column codes (rows
+// of at most 32 entries).
 struct SellOut {
     int64_t nslices = 0;
     const int32_t *sp = nullptr, *sw = nullptr;
     int32_t *col = nullptr;
     double *val = nullptr;
+    const int32_t *cp = nullptr;
+    uint32_t *code = nullptr;
+    int32_t *dict = nullptr, *over = nullptr;
 };
 template <int MAXS, bool KM>
 __global__ void __launch_bounds__(256) k_row_numeric(
@@ -558,31 +564,27 @@ __global__ void __launch_bounds__(256) k_row_numeric(
     double *__restrict__ valK, double *__restrict__ valM, double *__restrict__ f, SellOut sc) {
 #pragma clang fp contract(off)
     const int i = blockIdx.x * 256 + (int)threadIdx.x;
-    if (i >= n) {
-        // padding rows of the last slice
-        const int64_t s = i / kSellC;
-        if (!sc.val || s >= sc.nslices) return;
-        const int w = sc.sw[s];
-        const int64_t base = sc.sp[s] + (threadIdx.x & (kSellC - 1));
-        for (int q = 0; q < w; ++q) {
-            sc.col[base + (int64_t)q * kSellC] = 0;
-            sc.val[base + (int64_t)q * kSellC] = 0.0;
-        }
-        return;
-    }
-    const int vi = vertex_of_dof[i];
-    const int rb = row_ptr[i], len = row_ptr[i + 1] - rb;
+    const bool valid = i < n;   // the last slice also holds padding rows
+    const int64_t s = i / kSellC;
+    if (!valid && (!sc.val || s >= sc.nslices)) return;
+    int len = 0;
     int cols[MAXS];
     double acc[MAXS], aK[KM ? MAXS : 1], aM[KM ? MAXS : 1];
 #pragma unroll
     for (int q = 0; q < MAXS; ++q) {
-        cols[q] = q < len ? col[rb + q] : -1;
+        cols[q] = -1;
         acc[q] = 0.0;
         if (KM) {
             aK[q] = 0.0;
             aM[q] = 0.0;
         }
     }
+    if (valid) {
+    const int vi = vertex_of_dof[i];
+    const int rb = row_ptr[i];
+    len = row_ptr[i + 1] - rb;
+#pragma unroll
+    for (int q = 0; q < MAXS; ++q) cols[q] = q < len ? col[rb + q] : -1;
     double fi = 0.0;
     const int qe = inc_ptr[vi + 1];
     constexpr int U = 4;
@@ -644,16 +646,26 @@ __global__ void __launch_bounds__(256) k_row_numeric(
             }
         }
     f[i] = fi;
+    }
     if (sc.val) {
-        const int64_t s = i / kSellC;
         const int w = sc.sw[s];   // the slice's longest row: at most MAXS
         const int64_t base = sc.sp[s] + (threadIdx.x & (kSellC - 1));
+        // padding: column = the row (0 past the last row), value 0
+        const int pad = valid ? i : 0;
 #pragma unroll
         for (int q = 0; q < MAXS; ++q)
             if (q < w) {
-                sc.col[base + (int64_t)q * kSellC] = q < len ? cols[q] : i;
+                sc.col[base + (int64_t)q * kSellC] = q < len ? cols[q] : pad;
                 sc.val[base + (int64_t)q * kSellC] = q < len ? acc[q] : 0.0;
             }
+        if constexpr (MAXS <= 32) {
+            if (sc.code) {   // every lane of the slice's wavefront is here
+                int d[MAXS];
+#pragma unroll
+                for (int q = 0; q < MAXS; ++q) d[q] = q < w ? (q < len ? cols[q] : pad) - pad : 0;
+                dev::sell_code_regs<MAXS>(s, w, (int)(threadIdx.x & 63), d, sc.cp, sc.code, sc.dict, sc.over);
+            }
+        }
     }
 }
 
@@ -947,8 +959,8 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
             1, sys->n, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(), tdof.get(), nullptr,
             sys->row_ptr.get(), sys->col.get(), nullptr, ctx->dev_flag);
     } else {
-        k_pad_to_csr<<<grid_for((int64_t)n * kPadW, 256), 256, 0, ctx->stream>>>(sys->n, pad.get(),
-                                                                                  sys->row_ptr.get(), sys->col.get());
+        k_pad_to_csr<<<grid_for((int64_t)n * kPadLanes, 256), 256, 0, ctx->stream>>>(
+            sys->n, pad.get(), sys->row_ptr.get(), sys->col.get());
     }
     OCP_LAUNCH_CHECK();
     pad.release();
@@ -972,16 +984,28 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
     sc.sw = sys->sell.sw.get();
     sc.col = sys->sell.col.get();
     sc.val = sys->sell.val.get();
-    if (maxlen <= 16 || max_row_len(ctx, sys) <= 16)
+    const int ml = maxlen <= 16 ? 16 : max_row_len(ctx, sys);
+    const int ms = ml <= 16 ? 16 : ml <= 32 ? 32 : ml <= 64 ? 64 : 128;
+    if (ms <= 32) {   // column codes built by the same wavefronts
+        sell_code_layout(ctx, sys->sell);
+        sc.cp = sys->sell.cp.get();
+        sc.code = sys->sell.code.get();
+        sc.dict = sys->sell.dict.get();
+        sc.over = ctx->dev_flag;
+    }
+    if (ms == 16)
         launch_numeric<16>(ctx, sys, rho, rec.get(), vol.get(), sc);
-    else if (max_row_len(ctx, sys) <= 32)
+    else if (ms == 32)
         launch_numeric<32>(ctx, sys, rho, rec.get(), vol.get(), sc);
-    else if (max_row_len(ctx, sys) <= 64)
+    else if (ms == 64)
         launch_numeric<64>(ctx, sys, rho, rec.get(), vol.get(), sc);
     else
         launch_numeric<128>(ctx, sys, rho, rec.get(), vol.get(), sc);
     OCP_LAUNCH_CHECK();
-    sell_codes(ctx, sys->sell);
+    if (ms <= 32)
+        sell_code_finish(ctx, sys->sell);
+    else
+        sell_codes(ctx, sys->sell);
     sync(ctx);
 }
 

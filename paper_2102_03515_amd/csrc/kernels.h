@@ -10,6 +10,7 @@
 // the single-use matrix stream does not evict the reused x-vector from cache.
 #pragma once
 
+#include <climits>
 #include "common.h"
 
 namespace ocp {
@@ -221,6 +222,59 @@ namespace ocp {
 constexpr int kFinBlock = 1024;   // one-block finalize kernels over the partials of a SELL pass
 constexpr int kSellC = 64;
 constexpr int kSellDict = 16;     // column offsets per slice that 4-bit codes can name
+namespace dev {
+// Column codes of one slice from its entries' offsets d[j] = col - row (j <
+// w, the slice width; every lane of the wavefront takes part).  The distinct
+// offsets are found smallest first (a wavefront minimum over the entries not
+// yet named, repeated), so the dictionary is ascending; more than kSellDict
+// of them sets *overflow and leaves the slice uncoded.  d is overwritten with
+// the codes.
+template <int MAXW>
+__device__ __forceinline__ void sell_code_regs(int64_t s, int w, int lane, int (&d)[MAXW],
+                                               const int32_t *__restrict__ cp, uint32_t *__restrict__ code,
+                                               int32_t *__restrict__ dict, int32_t *overflow) {
+    uint32_t done = 0;   // entries already named
+    int nd = 0, mine = 0;
+    for (;;) {
+        int m = INT_MAX;
+#pragma unroll
+        for (int j = 0; j < MAXW; ++j)
+            if (j < w && !((done >> j) & 1u) && d[j] < m) m = d[j];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int v = __shfl_xor(m, o, 64);
+            m = v < m ? v : m;
+        }
+        if (m == INT_MAX) break;   // every entry named
+        if (nd == kSellDict) {
+            if (lane == 0) atomicOr(overflow, 1);
+            return;
+        }
+        if (lane == nd) mine = m;
+#pragma unroll
+        for (int j = 0; j < MAXW; ++j)
+            if (j < w && !((done >> j) & 1u) && d[j] == m) {
+                done |= 1u << j;
+                d[j] = nd;   // the entry's code from here on
+            }
+        ++nd;
+    }
+    if (lane < kSellDict) dict[s * kSellDict + lane] = lane < nd ? mine : 0;
+    const int64_t cb = cp[s] + lane;
+#pragma unroll
+    for (int q = 0; q < (MAXW + 7) / 8; ++q) {
+        if (q * 8 >= w) break;
+        uint32_t word = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = q * 8 + u;
+            if (j < w) word |= (uint32_t)d[j] << (4 * u);
+        }
+        code[cb + (int64_t)q * kSellC] = word;
+    }
+}
+}  // namespace dev
+
 constexpr int kSellMinRows = 1 << 16;   // coarse levels from this size get a sliced-ELL copy
 constexpr int kSellChunk = 16;
 static_assert(kSellChunk == 16, "the coded row reads two code words per chunk");

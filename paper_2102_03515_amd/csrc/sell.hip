@@ -63,58 +63,17 @@ __global__ void k_sell_fill(int32_t n, int64_t nslices, const int32_t *__restric
     }
 }
 
-// Column codes, one wavefront per slice.  The slice's distinct offsets
-// col - row are found smallest first (a wavefront minimum over the entries
-// not yet named, repeated), so the dictionary is ascending; more than
-// kSellDict of them sets *overflow and leaves the slice uncoded.  MAXW bounds
-// the slice width held in registers.
+// Column codes, one wavefront per slice (sell_code_regs): the entries'
+// offsets col - row are read back from the slice's columns.
 template <int MAXW>
 __device__ __forceinline__ void sell_code_slice(int64_t s, int w, int rr, int lane, int64_t base,
                                                 const int32_t *__restrict__ scol, const int32_t *__restrict__ cp,
                                                 uint32_t *__restrict__ code, int32_t *__restrict__ dict,
                                                 int32_t *overflow) {
     int d[MAXW];
-    uint32_t done = 0;   // entries already named
 #pragma unroll
     for (int j = 0; j < MAXW; ++j) d[j] = j < w ? scol[base + (int64_t)j * kSellC] - rr : 0;
-    int nd = 0, mine = 0;
-    for (;;) {
-        int m = INT_MAX;
-#pragma unroll
-        for (int j = 0; j < MAXW; ++j)
-            if (j < w && !((done >> j) & 1u) && d[j] < m) m = d[j];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const int v = __shfl_xor(m, o, 64);
-            m = v < m ? v : m;
-        }
-        if (m == INT_MAX) break;   // every entry named
-        if (nd == kSellDict) {
-            if (lane == 0) atomicOr(overflow, 1);
-            return;
-        }
-        if (lane == nd) mine = m;
-#pragma unroll
-        for (int j = 0; j < MAXW; ++j)
-            if (j < w && !((done >> j) & 1u) && d[j] == m) {
-                done |= 1u << j;
-                d[j] = nd;   // the entry's code from here on
-            }
-        ++nd;
-    }
-    if (lane < kSellDict) dict[s * kSellDict + lane] = lane < nd ? mine : 0;
-    const int64_t cb = cp[s] + lane;
-#pragma unroll
-    for (int q = 0; q < (MAXW + 7) / 8; ++q) {
-        if (q * 8 >= w) break;
-        uint32_t word = 0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int j = q * 8 + u;
-            if (j < w) word |= (uint32_t)d[j] << (4 * u);
-        }
-        code[cb + (int64_t)q * kSellC] = word;
-    }
+    dev::sell_code_regs<MAXW>(s, w, lane, d, cp, code, dict, overflow);
 }
 
 __global__ void __launch_bounds__(256) k_sell_code(int32_t n, int64_t nslices, const int32_t *__restrict__ sp,
@@ -158,9 +117,9 @@ void sell_layout(ocp_ctx *ctx, Sell &S, int32_t n, const int32_t *rp) {
     S.val.reset(ctx, (size_t)S.nnz_padded);
 }
 
-// Column codes of filled slices (kept only if every slice fits the dictionary).
-void sell_codes(ocp_ctx *ctx, Sell &S) {
-    const int32_t n = S.n;
+// Code words, offsets and dictionaries of a slice layout, allocated, with
+// the overflow flag cleared (the codes themselves follow).
+void sell_code_layout(ocp_ctx *ctx, Sell &S) {
     DevBuf<int32_t> words(ctx, (size_t)S.nslices + 1);
     k_sell_code_words<<<grid_for(S.nslices, 256), 256, 0, ctx->stream>>>(S.nslices, S.sw.get(), words.get());
     OCP_LAUNCH_CHECK();
@@ -169,9 +128,10 @@ void sell_codes(ocp_ctx *ctx, Sell &S) {
     S.code.reset(ctx, (size_t)std::max<int64_t>(nwords, 1));
     S.dict.reset(ctx, (size_t)S.nslices * kSellDict);
     fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
-    k_sell_code<<<grid_for((int64_t)S.nslices * kSellC, 256), 256, 0, ctx->stream>>>(
-        n, S.nslices, S.sp.get(), S.sw.get(), S.col.get(), S.cp.get(), S.code.get(), S.dict.get(), ctx->dev_flag);
-    OCP_LAUNCH_CHECK();
+}
+
+// Codes are kept only if every slice fitted the dictionary.
+void sell_code_finish(ocp_ctx *ctx, Sell &S) {
     int32_t over = 0;
     read_back(ctx, &over, ctx->dev_flag, sizeof(over));
     if (over) {
@@ -179,6 +139,15 @@ void sell_codes(ocp_ctx *ctx, Sell &S) {
         S.cp.release();
         S.dict.release();
     }
+}
+
+// Column codes of filled slices.
+void sell_codes(ocp_ctx *ctx, Sell &S) {
+    sell_code_layout(ctx, S);
+    k_sell_code<<<grid_for((int64_t)S.nslices * kSellC, 256), 256, 0, ctx->stream>>>(
+        S.n, S.nslices, S.sp.get(), S.sw.get(), S.col.get(), S.cp.get(), S.code.get(), S.dict.get(), ctx->dev_flag);
+    OCP_LAUNCH_CHECK();
+    sell_code_finish(ctx, S);
 }
 
 // The whole sliced-ELL copy of a CSR matrix: layout, columns and values, codes.

@@ -25,6 +25,8 @@ struct Sell {
 void sell_build(ocp_ctx *ctx, Sell &S, int32_t n, const int32_t *rp, const int32_t *col, const double *val);
 void sell_layout(ocp_ctx *ctx, Sell &S, int32_t n, const int32_t *rp);
 void sell_codes(ocp_ctx *ctx, Sell &S);
+void sell_code_layout(ocp_ctx *ctx, Sell &S);
+void sell_code_finish(ocp_ctx *ctx, Sell &S);
 inline SellCols sell_cols(const Sell &S) { return SellCols{S.col.get(), S.code.get(), S.cp.get(), S.dict.get()}; }
 void sell_values32(ocp_ctx *ctx, const Sell &S, const int32_t *rp, const float *val32, DevBuf<float> &out);
 }  // namespace ocp

@@ -184,9 +184,10 @@ __device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
     return v;
 }
 
-// Rounds after the first only touch what can still change: m2 and the
-// marking pass skip decided nodes, and m1 is recomputed only for nodes marked
-// (need[i] == round) as the closed neighbourhood of an undecided node.
+// Rounds only touch what can still change: m2 skips decided nodes, and from
+// round kMisMarkFrom + 1 on m1 is recomputed only for nodes marked (need[i]
+// == round) as the closed neighbourhood of an undecided node.
+constexpr int kMisMarkFrom = 5;   // first round whose m2 marks
 template <int G>
 __global__ void __launch_bounds__(256) k_mis_m1(int32_t n, const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ col, const uint8_t *__restrict__ strong,
@@ -270,7 +271,7 @@ __global__ void __launch_bounds__(256) k_mis_m2(int32_t n, const int32_t *__rest
         else if (leaves)
             state[i] = 2;
     }
-    if (!joins && !leaves) {
+    if (!joins && !leaves && need) {
         if (lane == 0) need[i] = round + 1;
         for (int k = rp[i] + lane; k < ke; k += G) {
             const int j = col[k];
@@ -1391,10 +1392,13 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
             for (int round = 1;; ++round) {
                 if (round > 1000) fail(OCP_ERR_HIP, "independent-set rounds did not terminate");
                 fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
+                // the first rounds leave most nodes undecided: marking their
+                // neighbourhoods would cost more than the m1 work it skips,
+                // so m1 takes every node until the marks start
                 k_mis_m1<GM><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt,
-                                                round > 1 ? need.get() : nullptr, round, m1.get());
+                                                round > kMisMarkFrom ? need.get() : nullptr, round, m1.get());
                 k_mis_m2<GM><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get(),
-                                                need.get(), round, ctx->dev_flag);
+                                                round >= kMisMarkFrom ? need.get() : nullptr, round, ctx->dev_flag);
                 OCP_LAUNCH_CHECK();
                 int32_t und = 0;
                 read_back(ctx, &und, ctx->dev_flag, sizeof(int32_t));

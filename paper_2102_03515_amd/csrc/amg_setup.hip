@@ -574,7 +574,7 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
     constexpr int MB = G <= 16 ? 16 / G : 0;   // B entries per lane and A entry fetched ahead
     static_assert(W <= H, "a padded row fits its table");
     constexpr int LIM = (3 * H) / 4;   // symbolic: count past which the row is retried
-    __shared__ int keys[RPW][H];
+    __shared__ __align__(16) int keys[RPW][H];
     __shared__ double vals[NUMERIC ? RPW : 1][NUMERIC ? H : 1];
     __shared__ int list[NUMERIC ? RPW : 1][NUMERIC ? H : 1];
     __shared__ int count[RPW];
@@ -682,7 +682,8 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
         }
         return;
     }
-    // compact the occupied slots, rank them by column, write the row
+    // compact the occupied slots (spreading them over the lanes), rank each
+    // by column, write the row
     for (int q = lane; q < H; q += G)
         if (keys[g][q] >= 0) list[g][atomicAdd(&count[g], 1)] = q;
     wave_sync();
@@ -698,7 +699,19 @@ __global__ void __launch_bounds__(64) k_spgemm_grp(const int32_t *__restrict__ r
         const int se = list[g][e];
         const int kk = keys[g][se];
         int rank = 0;
-        for (int f = 0; f < nc; ++f) rank += keys[g][list[g][f]] < kk;
+        if constexpr (H <= 512) {
+            // against the whole table, four slots per read; an empty slot
+            // (-1) is the largest unsigned value and never counts
+            const uint4 *kt = reinterpret_cast<const uint4 *>(&keys[g][0]);
+            const uint32_t ku = (uint32_t)kk;
+#pragma unroll 8
+            for (int f = 0; f < H / 4; ++f) {
+                const uint4 v = kt[f];
+                rank += (int)(v.x < ku) + (int)(v.y < ku) + (int)(v.z < ku) + (int)(v.w < ku);
+            }
+        } else {
+            for (int f = 0; f < nc; ++f) rank += keys[g][list[g][f]] < kk;
+        }
         ccol[base + rank] = kk;
         cval[base + rank] = vals[g][se];
     }

@@ -750,29 +750,6 @@ static int csr_max_row(ocp_ctx *ctx, int32_t m, const int32_t *rp) {
     return (int)reduce_max_abs(ctx, len.get(), m);
 }
 
-// bitonic sort of 16 (key, value) register pairs by key; unused keys are INT_MAX
-__device__ __forceinline__ void sort_slots(int (&keys)[16], double (&acc)[16]) {
-    constexpr int S = 16;
-#pragma unroll
-    for (int kk = 2; kk <= S; kk <<= 1)
-#pragma unroll
-        for (int jj = kk >> 1; jj > 0; jj >>= 1)
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                const int l = q ^ jj;
-                if (l > q) {
-                    const bool up = (q & kk) == 0;
-                    const bool sw = up ? (keys[q] > keys[l]) : (keys[q] < keys[l]);
-                    const int tk = keys[q];
-                    const double tv = acc[q];
-                    keys[q] = sw ? keys[l] : keys[q];
-                    acc[q] = sw ? acc[l] : acc[q];
-                    keys[l] = sw ? tk : keys[l];
-                    acc[l] = sw ? tv : acc[l];
-                }
-            }
-}
-
 // C = A P_tent (one entry per row of P_tent: column agg[j], value pt[j]),
 // one thread per row with up to 16 distinct columns held in registers;
 // entries accumulate in the order of the A row and are sorted by a network.
@@ -844,7 +821,7 @@ __global__ void __launch_bounds__(256) k_ap_tent(int32_t m, const int32_t *__res
         cnt[i] = nk;
         return;
     }
-    sort_slots(keys, acc);
+    dev::sort_slots(keys, acc);
     const int b = crp[i];
 #pragma unroll
     for (int q = 0; q < S; ++q)

@@ -556,6 +556,32 @@ struct SellOut {
     uint32_t *code = nullptr;
     int32_t *dict = nullptr, *over = nullptr;
 };
+// Row i (lane i % 64 of slice s's wavefront) stored in the sliced-ELL copy,
+// padding included (column = the row, 0 past the last row; value 0), and,
+// with sc.code given, the slice's column codes built by the wavefront (every
+// lane of it must be here).
+template <int MAXS>
+__device__ __forceinline__ void sell_store_row(const SellOut &sc, int64_t s, bool valid, int i, int len,
+                                               const int (&cols)[MAXS], const double (&acc)[MAXS]) {
+    const int w = sc.sw[s];   // the slice's longest row: at most MAXS
+    const int64_t base = sc.sp[s] + (threadIdx.x & (kSellC - 1));
+    const int pad = valid ? i : 0;
+#pragma unroll
+    for (int q = 0; q < MAXS; ++q)
+        if (q < w) {
+            sc.col[base + (int64_t)q * kSellC] = q < len ? cols[q] : pad;
+            sc.val[base + (int64_t)q * kSellC] = q < len ? acc[q] : 0.0;
+        }
+    if constexpr (MAXS <= 32) {
+        if (sc.code) {
+            int d[MAXS];
+#pragma unroll
+            for (int q = 0; q < MAXS; ++q) d[q] = q < w ? (q < len ? cols[q] : pad) - pad : 0;
+            dev::sell_code_regs<MAXS>(s, w, (int)(threadIdx.x & 63), d, sc.cp, sc.code, sc.dict, sc.over);
+        }
+    }
+}
+
 template <int MAXS, bool KM>
 __global__ void __launch_bounds__(256) k_row_numeric(
     int32_t n, double rho, const int32_t *__restrict__ vertex_of_dof, const int32_t *__restrict__ inc_ptr,
@@ -647,26 +673,151 @@ __global__ void __launch_bounds__(256) k_row_numeric(
         }
     f[i] = fi;
     }
-    if (sc.val) {
-        const int w = sc.sw[s];   // the slice's longest row: at most MAXS
-        const int64_t base = sc.sp[s] + (threadIdx.x & (kSellC - 1));
-        // padding: column = the row (0 past the last row), value 0
-        const int pad = valid ? i : 0;
+    if (sc.val) sell_store_row<MAXS>(sc, s, valid, i, len, cols, acc);
+}
+
+// Rows with at most kFuseW entries in one pass over their incident tets:
+// a column gets a register slot at its first appearance (the dofs come with
+// each element record) and values are accumulated as in k_row_numeric (same
+// order, so the same bits); the row is then sorted by column and written to
+// its kFuseW-wide padded slot with its length.  A longer row sets bit 64 of
+// *flag (the caller then assembles in separate symbolic and numeric passes).
+constexpr int kFuseW = 16;
+__global__ void __launch_bounds__(256) k_row_fused(int32_t n, const int32_t *__restrict__ vertex_of_dof,
+                                                   const int32_t *__restrict__ inc_ptr,
+                                                   const int32_t *__restrict__ inc, const double *__restrict__ rec,
+                                                   int32_t *__restrict__ rlen, int32_t *__restrict__ pcol,
+                                                   double *__restrict__ pval, double *__restrict__ f,
+                                                   int32_t *flag) {
+#pragma clang fp contract(off)
+    constexpr int S = kFuseW;
+    const int i = blockIdx.x * 256 + (int)threadIdx.x;
+    if (i >= n) return;
+    const int vi = vertex_of_dof[i];
+    int keys[S];
+    double acc[S];
 #pragma unroll
-        for (int q = 0; q < MAXS; ++q)
-            if (q < w) {
-                sc.col[base + (int64_t)q * kSellC] = q < len ? cols[q] : pad;
-                sc.val[base + (int64_t)q * kSellC] = q < len ? acc[q] : 0.0;
-            }
-        if constexpr (MAXS <= 32) {
-            if (sc.code) {   // every lane of the slice's wavefront is here
-                int d[MAXS];
+    for (int q = 0; q < S; ++q) {
+        keys[q] = INT_MAX;
+        acc[q] = 0.0;
+    }
+    int nk = 0;
+    double fi = 0.0;
+    const int qe = inc_ptr[vi + 1];
+    constexpr int U = 4;   // records of U incident tets requested together
+    for (int q0 = inc_ptr[vi]; q0 < qe; q0 += U) {
+        int code[U];
+        int4 td[U];
+        double kr[U][4], fa[U];
 #pragma unroll
-                for (int q = 0; q < MAXS; ++q) d[q] = q < w ? (q < len ? cols[q] : pad) - pad : 0;
-                dev::sell_code_regs<MAXS>(s, w, (int)(threadIdx.x & 63), d, sc.cp, sc.code, sc.dict, sc.over);
+        for (int u = 0; u < U; ++u) code[u] = q0 + u < qe ? inc[q0 + u] : -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (code[u] < 0) continue;
+            const int64_t e = code[u] >> 2;
+            const int a = code[u] & 3;
+            const double *r = rec + kRecD * e;
+            td[u] = *reinterpret_cast<const int4 *>(r);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) kr[u][b] = r[kRecVal + sym_index(a, b)];
+            fa[u] = r[kRecFe + a];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (code[u] < 0) continue;
+            fi += fa[u];
+            const int dd[4] = {td[u].x, td[u].y, td[u].z, td[u].w};
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int j = dd[b];
+                if (j < 0) continue;
+                const double v = kr[u][b];
+                bool found = false;
+#pragma unroll
+                for (int s2 = 0; s2 < S; ++s2)
+                    if (keys[s2] == j) {
+                        acc[s2] += v;
+                        found = true;
+                    }
+                if (found) continue;
+                if (nk == S) {
+                    atomicOr(flag, 64);
+                    return;
+                }
+#pragma unroll
+                for (int s2 = 0; s2 < S; ++s2)
+                    if (s2 == nk) {
+                        keys[s2] = j;
+                        acc[s2] = 0.0 + v;   // as the first add onto a zero slot
+                    }
+                ++nk;
             }
         }
     }
+    dev::sort_slots(keys, acc);
+    const int64_t p = (int64_t)i * S;
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+        if (q < nk) {
+            pcol[p + q] = keys[q];
+            pval[p + q] = acc[q];
+        }
+    rlen[i] = nk;
+    f[i] = fi;
+}
+
+// The padded rows of k_row_fused copied to the CSR and to the sliced-ELL
+// copy (with its column codes), one thread per row, a wavefront per slice.
+__global__ void __launch_bounds__(256) k_row_finish(int32_t n, const int32_t *__restrict__ pcol,
+                                                    const double *__restrict__ pval,
+                                                    const int32_t *__restrict__ row_ptr, int32_t *__restrict__ col,
+                                                    double *__restrict__ val, SellOut sc) {
+    constexpr int S = kFuseW;
+    const int i = blockIdx.x * 256 + (int)threadIdx.x;
+    const bool valid = i < n;
+    const int64_t s = i / kSellC;
+    if (!valid && s >= sc.nslices) return;
+    int len = 0, cols[S];
+    double acc[S];
+    if (valid) {
+        const int rb = row_ptr[i];
+        len = row_ptr[i + 1] - rb;
+        // the whole padded row in 16-byte loads (slots past len are read
+        // and dropped: the padded arrays hold n full rows)
+        const int64_t p = (int64_t)i * S;
+        const int4 *c4 = reinterpret_cast<const int4 *>(pcol + p);
+        const double2 *v2 = reinterpret_cast<const double2 *>(pval + p);
+        int4 cc[S / 4];
+        double2 vv[S / 2];
+#pragma unroll
+        for (int k = 0; k < S / 4; ++k) cc[k] = c4[k];
+#pragma unroll
+        for (int k = 0; k < S / 2; ++k) vv[k] = v2[k];
+#pragma unroll
+        for (int k = 0; k < S / 4; ++k) {
+            const int c[4] = {cc[k].x, cc[k].y, cc[k].z, cc[k].w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) cols[4 * k + u] = 4 * k + u < len ? c[u] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < S / 2; ++k) {
+            acc[2 * k] = 2 * k < len ? vv[k].x : 0.0;
+            acc[2 * k + 1] = 2 * k + 1 < len ? vv[k].y : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < S; ++q)
+            if (q < len) {
+                col[rb + q] = cols[q];
+                val[rb + q] = acc[q];
+            }
+    } else {
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            cols[q] = -1;
+            acc[q] = 0.0;
+        }
+    }
+    sell_store_row<S>(sc, s, valid, i, len, cols, acc);
 }
 
 template <int MAXS>
@@ -930,82 +1081,124 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
                         RecOut{sys->dof_of_vertex.get(), rho, rec.get(), vol.get(), tdof.get()});
     }
 
-    // 5. symbolic rows: rows of up to kPadW entries in one pass into a padded
-    // buffer; if any row is longer, count and fill again with kRowCap slots
-    DevBuf<int32_t> rcnt(ctx, (size_t)n + 1);
-    DevBuf<int32_t> pad(ctx, (size_t)n * kPadW);
-    fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
-    k_row_symbolic<kPadW><<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
-        0, sys->n, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(), tdof.get(), rcnt.get(), nullptr,
-        nullptr, pad.get(), ctx->dev_flag);
-    OCP_LAUNCH_CHECK();
-    read_back(ctx, &fl, ctx->dev_flag, sizeof(fl));
-    const bool long_rows = (fl & 128) != 0;
-    if (long_rows) {
-        pad.release();
+    // 5-6. rows.  With K and M not kept apart, rows of at most kFuseW entries
+    // are assembled in one pass (columns found while the values are summed);
+    // otherwise, or if a row is longer, symbolic rows then numeric rows.
+    bool fused = false;
+    if (!km) {
+        DevBuf<int32_t> rlen(ctx, (size_t)n + 1);
+        DevBuf<int32_t> pcol(ctx, (size_t)n * kFuseW);
+        DevBuf<double> pval(ctx, (size_t)n * kFuseW);
+        sys->f.reset(ctx, (size_t)n);
         fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
-        k_row_symbolic<kRowCap><<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
-            0, sys->n, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(), tdof.get(), rcnt.get(), nullptr,
-            nullptr, nullptr, ctx->dev_flag);
+        k_row_fused<<<grid_for(n, 256), 256, 0, ctx->stream>>>(n, sys->vertex_of_dof.get(), sys->inc_ptr.get(),
+                                                              sys->inc.get(), rec.get(), rlen.get(), pcol.get(),
+                                                              pval.get(), sys->f.get(), ctx->dev_flag);
         OCP_LAUNCH_CHECK();
         read_back(ctx, &fl, ctx->dev_flag, sizeof(fl));
-        if (fl & 4) fail(OCP_ERR_UNSUPPORTED, "an assembled row has more than 128 entries");
+        if (!(fl & 64)) {
+            fused = true;
+            tdof.release();
+            sys->row_ptr.reset(ctx, (size_t)n + 1);
+            sys->nnz = scan_exclusive(ctx, rlen.get(), sys->row_ptr.get(), n);
+            sys->col.reset(ctx, (size_t)sys->nnz);
+            sys->val.reset(ctx, (size_t)sys->nnz);
+            sell_layout(ctx, sys->sell, n, sys->row_ptr.get());
+            sell_code_layout(ctx, sys->sell);
+            SellOut sc;
+            sc.nslices = sys->sell.nslices;
+            sc.sp = sys->sell.sp.get();
+            sc.sw = sys->sell.sw.get();
+            sc.col = sys->sell.col.get();
+            sc.val = sys->sell.val.get();
+            sc.cp = sys->sell.cp.get();
+            sc.code = sys->sell.code.get();
+            sc.dict = sys->sell.dict.get();
+            sc.over = ctx->dev_flag;
+            k_row_finish<<<grid_for(n, 256), 256, 0, ctx->stream>>>(n, pcol.get(), pval.get(), sys->row_ptr.get(),
+                                                                   sys->col.get(), sys->val.get(), sc);
+            OCP_LAUNCH_CHECK();
+            sell_code_finish(ctx, sys->sell);
+        }
     }
-    sys->row_ptr.reset(ctx, (size_t)n + 1);
-    sys->nnz = scan_exclusive(ctx, rcnt.get(), sys->row_ptr.get(), n);
-    sys->col.reset(ctx, (size_t)sys->nnz);
-    if (long_rows) {
-        k_row_symbolic<kRowCap><<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
-            1, sys->n, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(), tdof.get(), nullptr,
-            sys->row_ptr.get(), sys->col.get(), nullptr, ctx->dev_flag);
-    } else {
-        k_pad_to_csr<<<grid_for((int64_t)n * kPadLanes, 256), 256, 0, ctx->stream>>>(
-            sys->n, pad.get(), sys->row_ptr.get(), sys->col.get());
-    }
-    OCP_LAUNCH_CHECK();
-    pad.release();
-    const int maxlen = long_rows ? kRowCap : kPadW;
-    rcnt.release();
+    if (!fused) {
+        // 5. symbolic rows: rows of up to kPadW entries in one pass into a padded
+        // buffer; if any row is longer, count and fill again with kRowCap slots
+        DevBuf<int32_t> rcnt(ctx, (size_t)n + 1);
+        DevBuf<int32_t> pad(ctx, (size_t)n * kPadW);
+        fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
+        k_row_symbolic<kPadW><<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
+            0, sys->n, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(), tdof.get(), rcnt.get(), nullptr,
+            nullptr, pad.get(), ctx->dev_flag);
+        OCP_LAUNCH_CHECK();
+        read_back(ctx, &fl, ctx->dev_flag, sizeof(fl));
+        const bool long_rows = (fl & 128) != 0;
+        if (long_rows) {
+            pad.release();
+            fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
+            k_row_symbolic<kRowCap><<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
+                0, sys->n, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(), tdof.get(), rcnt.get(), nullptr,
+                nullptr, nullptr, ctx->dev_flag);
+            OCP_LAUNCH_CHECK();
+            read_back(ctx, &fl, ctx->dev_flag, sizeof(fl));
+            if (fl & 4) fail(OCP_ERR_UNSUPPORTED, "an assembled row has more than 128 entries");
+        }
+        sys->row_ptr.reset(ctx, (size_t)n + 1);
+        sys->nnz = scan_exclusive(ctx, rcnt.get(), sys->row_ptr.get(), n);
+        sys->col.reset(ctx, (size_t)sys->nnz);
+        if (long_rows) {
+            k_row_symbolic<kRowCap><<<grid_for(n, kAsmBlock), kAsmBlock, 0, ctx->stream>>>(
+                1, sys->n, sys->vertex_of_dof.get(), sys->inc_ptr.get(), sys->inc.get(), tdof.get(), nullptr,
+                sys->row_ptr.get(), sys->col.get(), nullptr, ctx->dev_flag);
+        } else {
+            k_pad_to_csr<<<grid_for((int64_t)n * kPadLanes, 256), 256, 0, ctx->stream>>>(
+                sys->n, pad.get(), sys->row_ptr.get(), sys->col.get());
+        }
+        OCP_LAUNCH_CHECK();
+        pad.release();
+        const int maxlen = long_rows ? kRowCap : kPadW;
+        rcnt.release();
 
-    tdof.release();
+        tdof.release();
 
-    // 6. numeric rows
-    sys->val.reset(ctx, (size_t)sys->nnz);
-    sys->f.reset(ctx, (size_t)n);
-    if (km) {
-        sys->valK.reset(ctx, (size_t)sys->nnz);
-        sys->valM.reset(ctx, (size_t)sys->nnz);
+        // 6. numeric rows
+        sys->val.reset(ctx, (size_t)sys->nnz);
+        sys->f.reset(ctx, (size_t)n);
+        if (km) {
+            sys->valK.reset(ctx, (size_t)sys->nnz);
+            sys->valM.reset(ctx, (size_t)sys->nnz);
+        }
+        // the rows go to the CSR and to the sliced-ELL copy for the solve phase
+        sell_layout(ctx, sys->sell, n, sys->row_ptr.get());
+        SellOut sc;
+        sc.nslices = sys->sell.nslices;
+        sc.sp = sys->sell.sp.get();
+        sc.sw = sys->sell.sw.get();
+        sc.col = sys->sell.col.get();
+        sc.val = sys->sell.val.get();
+        const int ml = maxlen <= 16 ? 16 : max_row_len(ctx, sys);
+        const int ms = ml <= 16 ? 16 : ml <= 32 ? 32 : ml <= 64 ? 64 : 128;
+        if (ms <= 32) {   // column codes built by the same wavefronts
+            sell_code_layout(ctx, sys->sell);
+            sc.cp = sys->sell.cp.get();
+            sc.code = sys->sell.code.get();
+            sc.dict = sys->sell.dict.get();
+            sc.over = ctx->dev_flag;
+        }
+        if (ms == 16)
+            launch_numeric<16>(ctx, sys, rho, rec.get(), vol.get(), sc);
+        else if (ms == 32)
+            launch_numeric<32>(ctx, sys, rho, rec.get(), vol.get(), sc);
+        else if (ms == 64)
+            launch_numeric<64>(ctx, sys, rho, rec.get(), vol.get(), sc);
+        else
+            launch_numeric<128>(ctx, sys, rho, rec.get(), vol.get(), sc);
+        OCP_LAUNCH_CHECK();
+        if (ms <= 32)
+            sell_code_finish(ctx, sys->sell);
+        else
+            sell_codes(ctx, sys->sell);
     }
-    // the rows go to the CSR and to the sliced-ELL copy for the solve phase
-    sell_layout(ctx, sys->sell, n, sys->row_ptr.get());
-    SellOut sc;
-    sc.nslices = sys->sell.nslices;
-    sc.sp = sys->sell.sp.get();
-    sc.sw = sys->sell.sw.get();
-    sc.col = sys->sell.col.get();
-    sc.val = sys->sell.val.get();
-    const int ml = maxlen <= 16 ? 16 : max_row_len(ctx, sys);
-    const int ms = ml <= 16 ? 16 : ml <= 32 ? 32 : ml <= 64 ? 64 : 128;
-    if (ms <= 32) {   // column codes built by the same wavefronts
-        sell_code_layout(ctx, sys->sell);
-        sc.cp = sys->sell.cp.get();
-        sc.code = sys->sell.code.get();
-        sc.dict = sys->sell.dict.get();
-        sc.over = ctx->dev_flag;
-    }
-    if (ms == 16)
-        launch_numeric<16>(ctx, sys, rho, rec.get(), vol.get(), sc);
-    else if (ms == 32)
-        launch_numeric<32>(ctx, sys, rho, rec.get(), vol.get(), sc);
-    else if (ms == 64)
-        launch_numeric<64>(ctx, sys, rho, rec.get(), vol.get(), sc);
-    else
-        launch_numeric<128>(ctx, sys, rho, rec.get(), vol.get(), sc);
-    OCP_LAUNCH_CHECK();
-    if (ms <= 32)
-        sell_code_finish(ctx, sys->sell);
-    else
-        sell_codes(ctx, sys->sell);
     sync(ctx);
 }
 

@@ -275,6 +275,31 @@ __device__ __forceinline__ void sell_code_regs(int64_t s, int w, int lane, int (
 }
 }  // namespace dev
 
+namespace dev {
+// bitonic sort of 16 (key, value) register pairs by key; unused keys are INT_MAX
+__device__ __forceinline__ void sort_slots(int (&keys)[16], double (&acc)[16]) {
+    constexpr int S = 16;
+#pragma unroll
+    for (int kk = 2; kk <= S; kk <<= 1)
+#pragma unroll
+        for (int jj = kk >> 1; jj > 0; jj >>= 1)
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int l = q ^ jj;
+                if (l > q) {
+                    const bool up = (q & kk) == 0;
+                    const bool sw = up ? (keys[q] > keys[l]) : (keys[q] < keys[l]);
+                    const int tk = keys[q];
+                    const double tv = acc[q];
+                    keys[q] = sw ? keys[l] : keys[q];
+                    acc[q] = sw ? acc[l] : acc[q];
+                    keys[l] = sw ? tk : keys[l];
+                    acc[l] = sw ? tv : acc[l];
+                }
+            }
+}
+}  // namespace dev
+
 constexpr int kSellMinRows = 1 << 16;   // coarse levels from this size get a sliced-ELL copy
 constexpr int kSellChunk = 16;
 static_assert(kSellChunk == 16, "the coded row reads two code words per chunk");

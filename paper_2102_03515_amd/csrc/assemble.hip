@@ -768,19 +768,30 @@ __global__ void __launch_bounds__(256) k_row_fused(int32_t n, const int32_t *__r
 
 // The padded rows of k_row_fused copied to the CSR and to the sliced-ELL
 // copy (with its column codes), one thread per row, a wavefront per slice.
+// A wavefront's 64 rows are consecutive in the CSR: they are staged in LDS
+// (columns, then values, through one buffer) and stored consecutively.
+__device__ __forceinline__ void lds_wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 __global__ void __launch_bounds__(256) k_row_finish(int32_t n, const int32_t *__restrict__ pcol,
                                                     const double *__restrict__ pval,
                                                     const int32_t *__restrict__ row_ptr, int32_t *__restrict__ col,
                                                     double *__restrict__ val, SellOut sc) {
     constexpr int S = kFuseW;
+    __shared__ double stage[256 / kSellC][kSellC * S];
     const int i = blockIdx.x * 256 + (int)threadIdx.x;
     const bool valid = i < n;
     const int64_t s = i / kSellC;
-    if (!valid && s >= sc.nslices) return;
-    int len = 0, cols[S];
+    if (!valid && s >= sc.nslices) return;   // whole wavefronts past the last slice
+    const int lane = (int)(threadIdx.x & (kSellC - 1)), wv = (int)(threadIdx.x / kSellC);
+    const int i0 = i - lane;
+    const int e0 = row_ptr[i0], e1 = row_ptr[i0 + kSellC < n ? i0 + kSellC : n];
+    int len = 0, rb = 0, cols[S];
     double acc[S];
     if (valid) {
-        const int rb = row_ptr[i];
+        rb = row_ptr[i];
         len = row_ptr[i + 1] - rb;
         // the whole padded row in 16-byte loads (slots past len are read
         // and dropped: the padded arrays hold n full rows)
@@ -804,12 +815,6 @@ __global__ void __launch_bounds__(256) k_row_finish(int32_t n, const int32_t *__
             acc[2 * k] = 2 * k < len ? vv[k].x : 0.0;
             acc[2 * k + 1] = 2 * k + 1 < len ? vv[k].y : 0.0;
         }
-#pragma unroll
-        for (int q = 0; q < S; ++q)
-            if (q < len) {
-                col[rb + q] = cols[q];
-                val[rb + q] = acc[q];
-            }
     } else {
 #pragma unroll
         for (int q = 0; q < S; ++q) {
@@ -817,6 +822,19 @@ __global__ void __launch_bounds__(256) k_row_finish(int32_t n, const int32_t *__
             acc[q] = 0.0;
         }
     }
+    // CSR: columns, then values, staged per wavefront and stored consecutively
+    int *sc32 = reinterpret_cast<int *>(&stage[wv][0]);
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+        if (q < len) sc32[rb - e0 + q] = cols[q];
+    lds_wave_fence();
+    for (int t = lane; t < e1 - e0; t += kSellC) col[e0 + t] = sc32[t];
+    lds_wave_fence();
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+        if (q < len) stage[wv][rb - e0 + q] = acc[q];
+    lds_wave_fence();
+    for (int t = lane; t < e1 - e0; t += kSellC) val[e0 + t] = stage[wv][t];
     sell_store_row<S>(sc, s, valid, i, len, cols, acc);
 }
 

@@ -755,13 +755,14 @@ __global__ void __launch_bounds__(256) k_row_fused(int32_t n, const int32_t *__r
         }
     }
     dev::sort_slots(keys, acc);
+    // the whole slot in 16-byte stores (unused slots: INT_MAX, 0)
     const int64_t p = (int64_t)i * S;
+    int4 *c4 = reinterpret_cast<int4 *>(pcol + p);
+    double2 *v2 = reinterpret_cast<double2 *>(pval + p);
 #pragma unroll
-    for (int q = 0; q < S; ++q)
-        if (q < nk) {
-            pcol[p + q] = keys[q];
-            pval[p + q] = acc[q];
-        }
+    for (int k = 0; k < S / 4; ++k) c4[k] = make_int4(keys[4 * k], keys[4 * k + 1], keys[4 * k + 2], keys[4 * k + 3]);
+#pragma unroll
+    for (int k = 0; k < S / 2; ++k) v2[k] = make_double2(acc[2 * k], acc[2 * k + 1]);
     rlen[i] = nk;
     f[i] = fi;
 }

@@ -359,9 +359,20 @@ __global__ void k_agg2(int32_t n, const int32_t *__restrict__ rp, const int32_t 
     assigned[i] = 3;
 }
 
+// Aggregate sizes.  Neighbouring nodes often share an aggregate: within a
+// wavefront each run of equal aggregates adds its length with one atomic
+// (lanes past n hold -1, so a run never extends past the last node).
 __global__ void k_agg_sizes(int32_t n, const int32_t *__restrict__ agg, int32_t *__restrict__ size) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicAdd(&size[agg[i]], 1);
+    const int lane = (int)(threadIdx.x & 63);
+    const int a = i < n ? agg[i] : -1;
+    const int prev = __shfl_up(a, 1, 64);
+    const bool head = lane == 0 || prev != a;
+    const unsigned long long heads = __ballot(head);
+    if (!head || i >= n) return;
+    const unsigned long long above = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
+    const int next = above ? __ffsll((long long)above) - 1 : 64;
+    atomicAdd(&size[a], next - lane);
 }
 
 __global__ void k_ptent(int32_t n, const int32_t *__restrict__ agg, const int32_t *__restrict__ size,

@@ -339,14 +339,25 @@ __global__ void k_agg2(int32_t n, const int32_t *__restrict__ rp, const int32_t 
     if (assigned[i] != 0) return;
     uint64_t best = 0;
     int bj = -1;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
-        const int j = col[k];
-        if (is_strong(strong, k, j, i)) {
-            if (assigned[j] == 2) {
-                const uint64_t kj = mis_key(j, 2, salt);
+    const int ke = rp[i + 1];
+    constexpr int U = 8;   // columns, then their states, requested together
+    for (int k0 = rp[i]; k0 < ke; k0 += U) {
+        int j[U];
+        int8_t st[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u < ke) j[u] = col[k0 + u];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u < ke) st[u] = assigned[j[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u;
+            if (k < ke && is_strong(strong, k, j[u], i) && st[u] == 2) {
+                const uint64_t kj = mis_key(j[u], 2, salt);
                 if (kj > best) {
                     best = kj;
-                    bj = j;
+                    bj = j[u];
                 }
             }
         }

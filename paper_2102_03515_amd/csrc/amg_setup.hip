@@ -781,7 +781,7 @@ __global__ void __launch_bounds__(256) k_ap_tent(int32_t m, const int32_t *__res
                                                  const int32_t *__restrict__ agg, const double *__restrict__ pt,
                                                  const int32_t *__restrict__ crp, int32_t *__restrict__ cnt,
                                                  int32_t *__restrict__ ccol, double *__restrict__ cval,
-                                                 int32_t *flag) {
+                                                 int32_t *flag, const double *__restrict__ diag, double w) {
     constexpr int S = 16;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
@@ -845,11 +845,16 @@ __global__ void __launch_bounds__(256) k_ap_tent(int32_t m, const int32_t *__res
     }
     dev::sort_slots(keys, acc);
     const int b = crp[i];
+    // with diag given, the row of the smoothed prolongator
+    // P = P_tent - w D^-1 (A P_tent), as k_smooth_p forms it
+    const double sw = diag ? w / diag[i] : 0.0;
+    const int ai = agg[i];
+    const double pti = pt[i];
 #pragma unroll
     for (int q = 0; q < S; ++q)
         if (q < nk) {
             ccol[b + q] = keys[q];
-            cval[b + q] = acc[q];
+            cval[b + q] = diag ? (keys[q] == ai ? pti : 0.0) - sw * acc[q] : acc[q];
         }
 }
 
@@ -1062,17 +1067,20 @@ static void spgemm_small_rows(ocp_ctx *ctx, int32_t m, const int32_t *arp, const
 
 // C = A P_tent: the register kernel when every A row has at most 16 entries,
 // otherwise the general product with P_tent as a CSR matrix
-static void spgemm_ptent(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t annz, const int32_t *arp,
+// With diag given, the register kernel writes the smoothed prolongator
+// P = P_tent - w D^-1 (A P_tent) directly; returns whether it did (else C
+// holds A P_tent).
+static bool spgemm_ptent(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t annz, const int32_t *arp,
                          const int32_t *acol, const double *aval, const int32_t *agg, const int32_t *trp,
-                         const double *pt, Csr &C) {
+                         const double *pt, Csr &C, const double *diag, double w) {
     if (csr_max_row(ctx, m, arp) > 16) {
         spgemm(ctx, m, ncols, annz, arp, acol, aval, trp, agg, pt, C);
-        return;
+        return false;
     }
     DevBuf<int32_t> cnt(ctx, (size_t)m + 1);
     fill_zero_bytes(ctx, ctx->dev_flag, 4);
     k_ap_tent<false><<<grid_for(m, 256), 256, 0, ctx->stream>>>(m, arp, acol, aval, agg, pt, nullptr, cnt.get(),
-                                                                nullptr, nullptr, ctx->dev_flag);
+                                                                nullptr, nullptr, ctx->dev_flag, nullptr, 0.0);
     OCP_LAUNCH_CHECK();
     C.rows = m;
     C.cols = ncols;
@@ -1081,8 +1089,9 @@ static void spgemm_ptent(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t annz, c
     C.col.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
     C.val.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
     k_ap_tent<true><<<grid_for(m, 256), 256, 0, ctx->stream>>>(m, arp, acol, aval, agg, pt, C.rp.get(), nullptr,
-                                                               C.col.get(), C.val.get(), ctx->dev_flag);
+                                                               C.col.get(), C.val.get(), ctx->dev_flag, diag, w);
     OCP_LAUNCH_CHECK();
+    return diag != nullptr;
 }
 
 // --------------------------------------------------------------- transpose
@@ -1456,10 +1465,11 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
         OCP_LAUNCH_CHECK();
         // smoothed prolongator P = (I - w D^-1 A) P_tent
         Csr P;
-        spgemm_ptent(ctx, n, nc, L.nnzA, L.A_rp, L.A_col, L.A_val, tcol.get(), trp.get(), tval.get(), P);
         const double w = pr.omega / L.lambda_max;
-        k_smooth_p<<<grid_for(n, 256), 256, 0, s>>>(n, P.rp.get(), P.col.get(), P.val.get(), diag.get(), L.agg.get(),
-                                                    tval.get(), w);
+        if (!spgemm_ptent(ctx, n, nc, L.nnzA, L.A_rp, L.A_col, L.A_val, tcol.get(), trp.get(), tval.get(), P,
+                          diag.get(), w))
+            k_smooth_p<<<grid_for(n, 256), 256, 0, s>>>(n, P.rp.get(), P.col.get(), P.val.get(), diag.get(),
+                                                        L.agg.get(), tval.get(), w);
         OCP_LAUNCH_CHECK();
         // restriction and Galerkin product
         Csr R;

@@ -184,11 +184,12 @@ __device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
     return v;
 }
 
+// FIRST: every node undecided (the first round), no states read.
 // Rounds only touch what can still change: m2 skips decided nodes, and from
 // round kMisMarkFrom + 1 on m1 is recomputed only for nodes marked (need[i]
 // == round) as the closed neighbourhood of an undecided node.
 constexpr int kMisMarkFrom = 5;   // first round whose m2 marks
-template <int G>
+template <int G, bool FIRST>
 __global__ void __launch_bounds__(256) k_mis_m1(int32_t n, const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ col, const uint8_t *__restrict__ strong,
                                                 const int8_t *__restrict__ state, uint32_t salt,
@@ -211,7 +212,7 @@ __global__ void __launch_bounds__(256) k_mis_m1(int32_t n, const int32_t *__rest
             if (k0 + u * G < ke) j[u] = col[k0 + u * G];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (k0 + u * G < ke) st[u] = state[j[u]];
+            if (k0 + u * G < ke) st[u] = FIRST ? (int8_t)0 : state[j[u]];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = k0 + u * G;
@@ -223,7 +224,7 @@ __global__ void __launch_bounds__(256) k_mis_m1(int32_t n, const int32_t *__rest
     }
     m = group_max_u64<G>(m);
     if (lane == 0) {
-        const uint64_t ki = mis_key(i, state[i], salt);
+        const uint64_t ki = mis_key(i, FIRST ? (int8_t)0 : state[i], salt);
         m1[i] = ki > m ? ki : m;
     }
 }
@@ -1416,8 +1417,14 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
                 // the first rounds leave most nodes undecided: marking their
                 // neighbourhoods would cost more than the m1 work it skips,
                 // so m1 takes every node until the marks start
-                k_mis_m1<GM><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt,
-                                                round > kMisMarkFrom ? need.get() : nullptr, round, m1.get());
+                // round 1: every node undecided, no states to gather
+                if (round == 1)
+                    k_mis_m1<GM, true><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, nullptr,
+                                                          round, m1.get());
+                else
+                    k_mis_m1<GM, false><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt,
+                                                           round > kMisMarkFrom ? need.get() : nullptr, round,
+                                                           m1.get());
                 k_mis_m2<GM><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get(),
                                                 round >= kMisMarkFrom ? need.get() : nullptr, round, ctx->dev_flag);
                 OCP_LAUNCH_CHECK();

@@ -1,6 +1,8 @@
 """Smoothed-aggregation hierarchy written out from its definitions -- TEST INFRASTRUCTURE.
 
-Section 4.1 of the paper builds its AMG from three ingredients: a greedy
+Only the test suite may import this module; the product package never does.
+
+Section 3.1 of the paper builds its AMG from three ingredients: a greedy
 colouring of the matrix graph that picks coarse dofs and marks their
 neighbours, an interpolation P from the coarse dofs, and the Galerkin coarse
 operator A_c = P^T A P, applied recursively.  The GPU library realises these
@@ -24,10 +26,16 @@ definition per function, so that the GPU setup can be compared with it:
   lambda       max_i sum_j |a_ij| / a_ii   (Gershgorin bound of D^-1 A)
   P            (I - (omega/lambda) D^-1 A) P_tent
   A_c          P^T A P
+  pattern      P and A_c keep every structural entry of the product (an
+               entry some product term reaches), also one whose terms cancel
+               to 0.0: the sparsity pattern of the next level, and with
+               theta = 0 its strength, depend on the patterns only
   levels       stop at n <= coarse_max, at max_levels, or where the
                aggregation leaves more than half of the nodes
-The sparse products use scipy.sparse (a library primitive).  Only for small
-problems: the loops are plain Python.
+The paper fixes none of the parameters (strength threshold, stopping rule,
+coarsest size); the defaults here are this build's choices, and the tests
+pass them explicitly.  The sparse products use scipy.sparse (a library
+primitive).  Only for small problems: the loops are plain Python.
 """
 from __future__ import annotations
 
@@ -126,11 +134,49 @@ def gershgorin(A: sp.csr_matrix) -> float:
     return float(np.max(np.asarray(abs(A).sum(axis=1)).ravel() / d))
 
 
+def _ones(M: sp.csr_matrix) -> sp.csr_matrix:
+    """The sparsity pattern of M (every stored entry) with value 1."""
+    M = M.tocsr()
+    return sp.csr_matrix((np.ones(M.indices.size), M.indices.copy(), M.indptr.copy()), shape=M.shape)
+
+
+def structural_product(*mats) -> sp.csr_matrix:
+    """M1 M2 ... with the structural pattern of the product: scipy drops
+    entries whose sum is exactly 0.0, so the pattern comes from the product
+    of the 0/1 patterns (positive terms cannot cancel) and the values from
+    the ordinary product, entries missing there being explicit zeros."""
+    V = mats[0]
+    S = _ones(mats[0])
+    for M in mats[1:]:
+        V = V @ M
+        S = S @ _ones(M)
+    V = V.tocsr()
+    S = S.tocsr()
+    S.sort_indices()
+    V.sort_indices()
+    ncol = S.shape[1]
+    srow = np.repeat(np.arange(S.shape[0], dtype=np.int64), np.diff(S.indptr))
+    vrow = np.repeat(np.arange(V.shape[0], dtype=np.int64), np.diff(V.indptr))
+    skey = srow * ncol + S.indices
+    vkey = vrow * ncol + V.indices
+    pos = np.searchsorted(skey, vkey)
+    assert np.all(skey[pos] == vkey), "a value entry outside the structural pattern"
+    data = np.zeros(skey.size)
+    data[pos] = V.data
+    return sp.csr_matrix((data, S.indices.copy(), S.indptr.copy()), shape=S.shape)
+
+
 def smoothed_prolongator(A: sp.csr_matrix, Pt: sp.csr_matrix, omega: float) -> sp.csr_matrix:
+    """(I - (omega/lambda) D^-1 A) P_tent on A's pattern (its diagonal is
+    stored: A is SPD)."""
+    A = A.tocsr()
     lam = gershgorin(A)
-    Dinv = sp.diags(1.0 / A.diagonal())
-    S = sp.identity(A.shape[0], format="csr") - (omega / lam) * (Dinv @ A)
-    return (S @ Pt).tocsr()
+    d = A.diagonal()
+    rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    vals = -(omega / lam) * A.data / d[rows]
+    vals = vals + (A.indices == rows)
+    S = sp.csr_matrix((vals, A.indices.copy(), A.indptr.copy()), shape=A.shape)
+    return structural_product(S, Pt)
 
 
 def build_hierarchy(A: sp.csr_matrix, theta: float = 0.0, omega: float = 4.0 / 3.0,
@@ -153,7 +199,7 @@ def build_hierarchy(A: sp.csr_matrix, theta: float = 0.0, omega: float = 4.0 / 3
         Pt = tentative_prolongator(agg, nc)
         P = smoothed_prolongator(A, Pt, omega)
         levels.append({"A": A, "agg": agg, "nc": nc, "P": P})
-        A = (P.T @ (A @ P)).tocsr()
+        A = structural_product(P.T.tocsr(), A, P)
     return levels
 
 

@@ -3,17 +3,17 @@
  * reduced optimality equation of elliptic optimal control with energy
  * regularization, on one MI355X (gfx950).
  *
- * The problem (Section 1, eq. (6)): find u with  -rho*Lap(u) + u = ubar  in
+ * The problem (Section 1, eq. (5)): find u with  -rho*Lap(u) + u = ubar  in
  * Omega and u = 0 on Gamma, for a regularization parameter rho > 0 and a
  * target ubar in L2(Omega).  Its Galerkin discretization with continuous
- * piecewise-linear elements on a tetrahedral mesh (Section 2, discrete
- * variational problem; Section 3, system (linsys)) is the sparse SPD system
+ * piecewise-linear elements on a tetrahedral mesh (Section 2: the discrete
+ * variational problem and system (linsys)) is the sparse SPD system
  *
  *     (rho*K + M) u = f,   K_ij = int grad(phi_j).grad(phi_i),
  *                          M_ij = int phi_j phi_i,   f_i = int ubar phi_i,
  *
- * over the interior vertices.  It is solved by preconditioned CG (Section 5)
- * with an algebraic multigrid V(1,1)-cycle as preconditioner (Section 4.1).
+ * over the interior vertices.  It is solved by preconditioned CG (Section 4)
+ * with an algebraic multigrid V(1,1)-cycle as preconditioner (Section 3.1).
  *
  * Conventions for every entry point below:
  *   - Every function returns an int status: 0 success, negative on error
@@ -25,7 +25,14 @@
  *     size or a status computed on the GPU synchronize that stream.
  *   - Library-owned device memory comes from the allocator given to
  *     ocp_ctx_create (or hipMalloc/hipFree when none is given).
- *   - A context is used by one host thread at a time.
+ *   - A context is used by one host thread at a time.  Solves only read
+ *     systems and hierarchies (each solve owns its vectors, scalars and
+ *     reduction partials; data a first solve derives, such as the Jacobi
+ *     diagonal or a block panel width, is published under a lock or by
+ *     compare-and-swap once complete), so several contexts on several
+ *     streams may solve with the same system and hierarchy at once.
+ *     Calls that change a system (fe_set_rho) or free it must not overlap
+ *     solves that use it.
  */
 #ifndef OCPAMG_H
 #define OCPAMG_H
@@ -102,7 +109,7 @@ typedef struct {
 /* -------------------------------------------------------------- assembly */
 #define OCP_KEEP_KM 1 /* keep K and M values separately so fe_set_rho can re-weight */
 
-/* Assemble A = rho*K + M and f (Section 3, system (linsys)) on the interior
+/* Assemble A = rho*K + M and f (Section 2, system (linsys)) on the interior
  * vertices of `mesh` into CSR on the device.  Element matrices are exact; f
  * uses the 4-point degree-2 rule on each tetrahedron.  The assembly is
  * row-owned (one owner per row, no atomics on values) and bitwise
@@ -115,7 +122,12 @@ int fe_assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_target
                 int32_t flags, ocp_system **out);
 void ocp_system_destroy(ocp_system *sys);
 
-/* Replace rho: A = rho*K + M (needs OCP_KEEP_KM at assembly). */
+/* Replace rho: A = rho*K + M (needs OCP_KEEP_KM at assembly).  The system's
+ * values change in place, so no solve may use it while this runs.  Every
+ * hierarchy built on this system before the call is stale afterwards (its
+ * smoother diagonal, eigenvalue bound and coarse operators belong to the old
+ * matrix): the solves and amg_vcycle refuse it with INVALID_ARG until it is
+ * rebuilt with amg_setup. */
 int fe_set_rho(ocp_ctx *ctx, ocp_system *sys, double rho);
 
 /* A new system on the same mesh with A = rho*K + M, from the K and M values
@@ -125,18 +137,18 @@ int fe_set_rho(ocp_ctx *ctx, ocp_system *sys, double rho);
  * base.  Errors: INVALID_ARG (NULL, rho <= 0, base without K/M), OOM, HIP. */
 int fe_derive(ocp_ctx *ctx, const ocp_system *base, double rho, ocp_system **out);
 
-/* Load vector of another target on the same mesh: f_dev (device [n_dofs],
- * caller-owned) receives f_i = int ubar phi_i.  The mesh given at assembly
- * must still be alive. */
-int fe_load(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *mesh, const ocp_target *target,
-            double *f_dev);
+/* Load vector of another target on the system's mesh (Section 2: f_i =
+ * int ubar phi_i, by the rule of fe_assemble): f_dev (device [n_dofs],
+ * caller-owned) receives it.  The system borrows the mesh given to
+ * fe_assemble (for fe_derive: the base's), whose device arrays must still be
+ * alive.  Errors: INVALID_ARG (NULL, bad target), OOM, HIP. */
+int fe_load(ocp_ctx *ctx, const ocp_system *sys, const ocp_target *target, double *f_dev);
 
 /* Load vectors of k targets on the same mesh in one block: F (device
  * [n_dofs][k], row-major, caller-owned) receives F[i*k + j] = int ubar_j phi_i
  * for target j (the same rule as fe_assemble).  This is the right-hand side
  * block of pcg_solve_multi.  Errors as fe_load; INVALID_ARG if k < 1. */
-int fe_load_multi(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *mesh, int32_t k,
-                  const ocp_target *targets, double *F);
+int fe_load_multi(ocp_ctx *ctx, const ocp_system *sys, int32_t k, const ocp_target *targets, double *F);
 
 /* Read-only view of an assembled system (device pointers owned by `sys`). */
 typedef struct {
@@ -183,7 +195,7 @@ typedef struct {
  * coarse_max 512, 10 levels, theta 0, omega 4/3). */
 void amg_default_params(ocp_amg_params *p);
 
-/* Build a smoothed-aggregation hierarchy for the system's A (Section 4.1:
+/* Build a smoothed-aggregation hierarchy for the system's A (Section 3.1:
  * coarse spaces from a coarsening of the matrix graph, interpolation P, and
  * Galerkin coarse operators A_c = P^T A P, applied recursively).  NULL params
  * means defaults.  The hierarchy must not outlive `sys`.
@@ -213,7 +225,7 @@ typedef struct {
 } ocp_level_view;
 int ocp_hierarchy_get_level(const ocp_hierarchy *h, int32_t level, ocp_level_view *view);
 
-/* z = B r: one V-cycle with zero initial guess (Section 4.1, two-grid
+/* z = B r: one V-cycle with zero initial guess (Section 3.1, two-grid
  * operator applied recursively), the same polynomial smoother before and
  * after the coarse correction so that B is symmetric.  r, z: device [n_dofs]. */
 int amg_vcycle(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r, double *z);
@@ -231,10 +243,11 @@ typedef struct {
     double rel_res_l2;      /* ||r_k|| / ||f|| of the CG recurrence */
     double rel_res_precond; /* sqrt(r_k^T z_k / r_0^T z_0) */
     double true_rel_res;    /* ||f - A u|| / ||f|| recomputed in double at exit */
+    double setup_ms;        /* wall time amg_setup took to build the hierarchy used (0: Jacobi) */
     double solve_ms;        /* GPU time of the solve (events on the context stream) */
 } ocp_solve_info;
 
-/* Preconditioned CG from u = 0 (Section 5: PCG, one V(1,1)-cycle per
+/* Preconditioned CG from u = 0 (Section 4: PCG, one V(1,1)-cycle per
  * iteration as preconditioner; tolerance 1e-8 in the paper).
  *   h      hierarchy from amg_setup, or NULL for Jacobi preconditioning.  It may
  *          belong to another system on the same mesh with the same pattern
@@ -251,7 +264,7 @@ int pcg_solve(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, const
               double *u, double rtol, int32_t maxit, int32_t flags, ocp_solve_info *info);
 
 /* Block PCG for k right-hand sides that share A and the hierarchy (the PCG
- * of Section 5 run as k independent recurrences in one pass over the
+ * of Section 4 run as k independent recurrences in one pass over the
  * matrix per iteration).  Every column has its own alpha, beta and stop
  * test; a column that has converged, broken down or reached maxit is frozen
  * while the others continue.  The V-cycle is the one of pcg_solve (same

@@ -1,9 +1,9 @@
 """Seeded synthetic inputs for the reduced optimal-control equation.
 
 This module produces *inputs only*: the tetrahedral mesh of the unit cube
-Omega = (0,1)^3 used in the paper's experiments (Section 5), the homogeneous
+Omega = (0,1)^3 used in the paper's experiments (Section 4), the homogeneous
 Dirichlet boundary marker, and descriptors of the target functions ubar
-(Sections 5.1 and 5.2).  It holds none of the method's arithmetic: no element
+(Sections 4.1 and 4.2).  It holds none of the method's arithmetic: no element
 matrices, no quadrature, no target evaluation, no solver.  Both the CPU
 oracle and the GPU library consume what is produced here.
 
@@ -135,7 +135,7 @@ class Nodal:
 
 
 def single_sine(offset: float = 0.0) -> SineModes:
-    """ubar = offset + sin(pi x) sin(pi y) sin(pi z) (Sections 5.1 and 5.3)."""
+    """ubar = offset + sin(pi x) sin(pi y) sin(pi z) (Sections 4.1 and 4.3)."""
     return SineModes(k=np.array([[1, 1, 1]], dtype=np.int32),
                      amp=np.array([1.0]), offset=float(offset))
 
@@ -149,7 +149,7 @@ def random_sine_modes(seed: int, n_modes: int = 64, kmax: int = 8) -> SineModes:
 
 
 def box_indicator() -> BoxIndicator:
-    """Discontinuous target of Section 5.2: 1 on (0.25, 0.75)^3."""
+    """Discontinuous target of Section 4.2: 1 on (0.25, 0.75)^3."""
     return BoxIndicator()
 
 
@@ -158,7 +158,7 @@ def box_indicator() -> BoxIndicator:
 # --------------------------------------------------------------------------
 
 WORKLOADS = {
-    # 16^3 cubes, rho = h^2, the eigenfunction target of Section 5.1
+    # 16^3 cubes, rho = h^2, the eigenfunction target of Section 4.1
     "cube16_sine111": dict(N=16, jitter=0.0, seed=None, rhos=[1.0 / 256], target="sine111"),
     # 128^3 cubes, jittered interior, three rho values, discontinuous target
     "cube128_jitter_box": dict(N=128, jitter=0.15, seed=1, rhos=[1e-6, 1.0 / 16384, 1e-2],

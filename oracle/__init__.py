@@ -1,4 +1,4 @@
-"""CPU oracle for the P1 system (rho*K + M) u = f of eq. (6) -- TEST INFRASTRUCTURE.
+"""CPU oracle for the P1 system (rho*K + M) u = f of eq. (5) -- TEST INFRASTRUCTURE.
 
 This package is the plain, slow, double-precision reference against which the
 GPU library is checked.  Only the test suite, ``__graft_entry__.smoke()`` and
@@ -10,12 +10,12 @@ descriptors, no method arithmetic).
 Contents
   * ``oracle.c``  (this package's C part, built with gcc + OpenMP):
     element matrices and load by the 4-point rule, row-by-row assembly of
-    A = rho*K + M and f on the interior vertices (Section 3, system (linsys)),
+    A = rho*K + M and f on the interior vertices (Section 2, system (linsys)),
     sampled rows, CSR SpMV and Jacobi-PCG from x0 = 0.
   * ``dense.py``: numpy element-by-element dense assembly and a Cholesky solve
     for tiny meshes.
   * ``norms.py``: L2 / H1 errors against the closed-form solutions of
-    Section 5.1 and its sine-mode superpositions.
+    Section 4.1 and its sine-mode superpositions.
   * ``amg.py``: the smoothed-aggregation hierarchy written out from its
     definitions (aggregation, tentative and smoothed prolongators, Galerkin
     coarse operators) for the parity checks of the GPU setup.

@@ -1,6 +1,6 @@
 """Dense numpy assembly and Cholesky solve for tiny meshes -- TEST INFRASTRUCTURE.
 
-An element-by-element restatement of system (linsys) of Section 3,
+An element-by-element restatement of system (linsys) of Section 2,
 independent of ``oracle.c``: per tetrahedron the barycentric gradients come
 from ``numpy.linalg.inv`` of the edge matrix, K_e = |tau| G G^T, M_e is the
 exact integral of lambda_a lambda_b (|tau|/20 (1 + delta_ab)), and f_e uses the

@@ -4,7 +4,7 @@ For a target that is a finite sum of Dirichlet eigenfunctions of the unit cube,
 ubar = sum_m a_m prod_d sin(k_{m,d} pi x_d), equation (6) is solved mode by
 mode: u_rho = sum_m a_m / (1 + rho pi^2 |k_m|^2) prod_d sin(k_{m,d} pi x_d).
 With a single mode k = (1,1,1) this is the manufactured solution of
-Section 5.1.  The errors ||u_rho - u_rho,h||_L2 and ||grad(u_rho - u_rho,h)||_L2
+Section 4.1.  The errors ||u_rho - u_rho,h||_L2 and ||grad(u_rho - u_rho,h)||_L2
 of Tables 1 and 2 are integrated element by element with a conical-product
 (collapsed Gauss-Jacobi) rule built from ``scipy.special.roots_jacobi``.
 """
@@ -35,7 +35,7 @@ def conical_rule(n: int = 4):
 
 
 def closed_form(target, rho: float):
-    """Callables u(x) and grad u(x) of the exact solution of eq. (6)."""
+    """Callables u(x) and grad u(x) of the exact solution of eq. (5)."""
     if target.kind != "sine" or float(target.offset) != 0.0:
         raise ValueError("closed form needs a homogeneous sine-mode target")
     ks = np.asarray(target.k, dtype=np.float64)

@@ -1,13 +1,13 @@
 /*
  * CPU oracle for the P1 finite element system of the reduced optimality
- * equation  -rho*Lap(u) + u = ubar  in Omega, u = 0 on Gamma  (eq. (6)).
+ * equation  -rho*Lap(u) + u = ubar  in Omega, u = 0 on Gamma  (eq. (5)).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference the GPU
  * library is checked against.  Only the test suite, the smoke check and the
  * benchmark's CPU-baseline leg may load it; the product never does.  It shares
  * no code, header or table with the GPU library.
  *
- * What it computes (Section 3, system (linsys) and the matrix entries that
+ * What it computes (Section 2, system (linsys) and the matrix entries that
  * follow it):
  *     A = rho*K + M,   K_ij = int grad(phi_j).grad(phi_i),
  *     M_ij = int phi_j phi_i,   f_i = int ubar phi_i,
@@ -19,7 +19,7 @@
  * (a,b,b,b) and permutations, a = (5+3 sqrt5)/20, b = (5-sqrt5)/20, weights
  * |tau|/4 each (the paper does not state its quadrature).
  *
- * The solver is Jacobi-preconditioned CG from x0 = 0 (Section 5 uses PCG;
+ * The solver is Jacobi-preconditioned CG from x0 = 0 (Section 4 uses PCG;
  * with an SPD matrix every preconditioner reaches the same discrete solution).
  */
 #include <math.h>

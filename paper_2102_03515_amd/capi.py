@@ -71,7 +71,7 @@ class _LevelView(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("status", C.c_int32), ("rel_res_l2", C.c_double),
                 ("rel_res_precond", C.c_double), ("true_rel_res", C.c_double),
-                ("solve_ms", C.c_double)]
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -91,9 +91,8 @@ _SIGS = {
     "ocp_system_destroy": (None, [C.c_void_p]),
     "fe_set_rho": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double]),
     "fe_derive": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.POINTER(C.c_void_p)]),
-    "fe_load": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(_Mesh), C.POINTER(_Target), C.c_void_p]),
-    "fe_load_multi": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(_Mesh), C.c_int32, C.POINTER(_Target),
-                                C.c_void_p]),
+    "fe_load": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(_Target), C.c_void_p]),
+    "fe_load_multi": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(_Target), C.c_void_p]),
     "ocp_system_get_view": (C.c_int, [C.c_void_p, C.POINTER(_SystemView)]),
     "ocp_spmv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "amg_default_params": (None, [C.POINTER(_AmgParams)]),
@@ -313,7 +312,7 @@ class System:
     def __init__(self, ctx: Context, handle, mesh: DeviceMesh):
         self.ctx = ctx
         self.handle = handle
-        self.mesh = mesh   # keeps the device mesh alive (fe_load reads it)
+        self.mesh = mesh   # keeps the device mesh alive (the system borrows it; fe_load reads it)
 
     def view(self) -> _SystemView:
         v = _SystemView()
@@ -375,20 +374,20 @@ class System:
             out = torch.empty(self.n, dtype=torch.float64, device="cuda")
         keep = []
         t = target_struct(target, keep)
-        m = self.mesh.struct()
-        ctx.check(lib().fe_load(ctx.handle, self.handle, C.byref(m), C.byref(t), _ptr(out)))
+        ctx.check(lib().fe_load(ctx.handle, self.handle, C.byref(t), _ptr(out)))
         return out
 
-    def load_multi(self, targets, out=None):
-        """Load vectors of several targets as one row-major block [n][k]."""
+    def load_multi(self, targets, out=None, ctx: Optional["Context"] = None):
+        """Load vectors of several targets as one row-major block [n][k];
+        runs on `ctx` (default: the creating context)."""
         torch = _torch()
+        ctx = ctx or self.ctx
         k = len(targets)
         if out is None:
             out = torch.empty((self.n, k), dtype=torch.float64, device="cuda")
         keep = []
         arr = (_Target * k)(*[target_struct(t, keep) for t in targets])
-        m = self.mesh.struct()
-        self.ctx.check(lib().fe_load_multi(self.ctx.handle, self.handle, C.byref(m), k, arr, _ptr(out)))
+        ctx.check(lib().fe_load_multi(ctx.handle, self.handle, k, arr, _ptr(out)))
         return out
 
     def close(self):

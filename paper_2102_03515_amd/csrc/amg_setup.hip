@@ -1,6 +1,6 @@
 // Smoothed-aggregation AMG setup on the GPU.
 //
-// Section 4.1 builds the coarse space from a greedy colouring of the matrix
+// Section 3.1 builds the coarse space from a greedy colouring of the matrix
 // graph (pick an unmarked dof as coarse, mark its neighbours fine, repeat),
 // interpolates by averaging, and forms Galerkin coarse operators
 // A_c = P^T A P recursively.  Here the same three ingredients are realised as
@@ -25,6 +25,7 @@
 // entry in a fixed order.  The last level (n <= coarse_max) is inverted
 // densely with Gauss-Jordan elimination in one workgroup.
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 
@@ -1566,9 +1567,11 @@ extern "C" int amg_setup(ocp_ctx *ctx, const ocp_system *sys, const ocp_amg_para
     ocp_hierarchy *h = nullptr;
     int rc = run_guarded(ctx, [&] {
         if (!sys || !out) fail(OCP_ERR_INVALID_ARG, "system and out must not be NULL");
+        const auto t0 = std::chrono::steady_clock::now();
         h = new ocp_hierarchy();
         h->ctx = ctx;
         h->sys = sys;
+        h->sys_generation = sys->generation.load(std::memory_order_acquire);
         if (params)
             h->params = *params;
         else
@@ -1584,7 +1587,8 @@ extern "C" int amg_setup(ocp_ctx *ctx, const ocp_system *sys, const ocp_amg_para
         if (p.coarse_max < 1 || p.coarse_max > kDenseMax) fail(OCP_ERR_INVALID_ARG, "coarse_max must be in 1..2048");
         if (p.max_levels < 1 || p.max_levels > 16) fail(OCP_ERR_INVALID_ARG, "max_levels must be in 1..16");
         if (!(p.theta >= 0.0) || !(p.omega > 0.0)) fail(OCP_ERR_INVALID_ARG, "theta >= 0 and omega > 0 required");
-        setup(ctx, sys, h);
+        setup(ctx, sys, h);   // ends with a stream synchronization
+        h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     });
     if (rc != OCP_OK) {
         delete h;

@@ -1,5 +1,5 @@
 // Finite element assembly of A = rho*K + M and f = (int ubar phi_i) into CSR
-// (Section 3, system (linsys) and the entries K_ij, M_ij, f_i defined there).
+// (Section 2, system (linsys) and the entries K_ij, M_ij, f_i defined there).
 //
 // Row-owned, atomic-free on values: every tet writes one element record
 // (its vertex dofs, element matrix and element loads), and every interior
@@ -1045,6 +1045,7 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
     sys->nt = nt;
     sys->rho = rho;
     sys->tets_ref = mesh->tets;
+    sys->mesh = *mesh;
     const int4 *tets = reinterpret_cast<const int4 *>(mesh->tets);
     if (reinterpret_cast<uintptr_t>(mesh->tets) % 16 != 0)
         fail(OCP_ERR_INVALID_ARG, "tets must be 16-byte aligned");
@@ -1268,6 +1269,7 @@ extern "C" int fe_derive(ocp_ctx *ctx, const ocp_system *base, double rho, ocp_s
         sys->rho = rho;
         sys->max_row_len = base->max_row_len;
         sys->tets_ref = base->tets_ref;
+        sys->mesh = base->mesh;
         auto dup = [&](auto &dst, const auto &src) {
             using T = std::remove_pointer_t<decltype(src.get())>;
             dst.reset(ctx, src.size());
@@ -1286,7 +1288,7 @@ extern "C" int fe_derive(ocp_ctx *ctx, const ocp_system *base, double rho, ocp_s
         k_set_rho<<<grid_for(sys->nnz, 256), 256, 0, ctx->stream>>>(sys->nnz, rho, base->valK.get(),
                                                                     base->valM.get(), sys->val.get());
         OCP_LAUNCH_CHECK();
-        system_sell(ctx, sys);
+        sell_build(ctx, sys->sell, sys->n, sys->row_ptr.get(), sys->col.get(), sys->val.get());
         sync(ctx);
     });
     if (rc != OCP_OK) {
@@ -1307,34 +1309,36 @@ extern "C" int fe_set_rho(ocp_ctx *ctx, ocp_system *sys, double rho) {
                                                                     sys->val.get());
         OCP_LAUNCH_CHECK();
         sys->rho = rho;
-        sys->invalidate_derived();
-        system_sell(ctx, sys);
+        // derived data of the old values: dropped and rebuilt (no solve may
+        // use the system meanwhile); hierarchies built on it become stale
+        {
+            std::lock_guard<std::mutex> lock(sys->derived_mu);
+            sys->dinv_ready.store(false, std::memory_order_release);
+            sys->dinv.release();
+        }
+        sys->sell = Sell();
+        sell_build(ctx, sys->sell, sys->n, sys->row_ptr.get(), sys->col.get(), sys->val.get());
+        sys->generation.fetch_add(1, std::memory_order_acq_rel);
         sync(ctx);
     });
 }
 
-extern "C" int fe_load(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *mesh, const ocp_target *target,
-                       double *f_dev) {
+extern "C" int fe_load(ocp_ctx *ctx, const ocp_system *sys, const ocp_target *target, double *f_dev) {
     if (!ctx) return OCP_ERR_INVALID_ARG;
     return run_guarded(ctx, [&] {
-        if (!sys || !mesh || !f_dev) fail(OCP_ERR_INVALID_ARG, "system, mesh and f must not be NULL");
-        if (mesh->n_vertices != sys->nv || mesh->n_tets != sys->nt || mesh->tets != sys->tets_ref)
-            fail(OCP_ERR_INVALID_ARG, "mesh differs from the one the system was assembled on");
-        check_target(target, mesh->n_vertices);
-        compute_loads(ctx, sys, mesh, target, f_dev);
+        if (!sys || !f_dev) fail(OCP_ERR_INVALID_ARG, "system and f must not be NULL");
+        check_target(target, sys->nv);
+        compute_loads(ctx, sys, &sys->mesh, target, f_dev);
     });
 }
 
-extern "C" int fe_load_multi(ocp_ctx *ctx, const ocp_system *sys, const ocp_mesh *mesh, int32_t k,
-                             const ocp_target *targets, double *F) {
+extern "C" int fe_load_multi(ocp_ctx *ctx, const ocp_system *sys, int32_t k, const ocp_target *targets, double *F) {
     if (!ctx) return OCP_ERR_INVALID_ARG;
     return run_guarded(ctx, [&] {
-        if (!sys || !mesh || !targets || !F) fail(OCP_ERR_INVALID_ARG, "system, mesh, targets and F must not be NULL");
+        if (!sys || !targets || !F) fail(OCP_ERR_INVALID_ARG, "system, targets and F must not be NULL");
         if (k < 1) fail(OCP_ERR_INVALID_ARG, "k must be >= 1");
-        if (mesh->n_vertices != sys->nv || mesh->n_tets != sys->nt || mesh->tets != sys->tets_ref)
-            fail(OCP_ERR_INVALID_ARG, "mesh differs from the one the system was assembled on");
-        for (int j = 0; j < k; ++j) check_target(&targets[j], mesh->n_vertices);
-        for (int j = 0; j < k; ++j) compute_loads(ctx, sys, mesh, &targets[j], F + j, k);
+        for (int j = 0; j < k; ++j) check_target(&targets[j], sys->nv);
+        for (int j = 0; j < k; ++j) compute_loads(ctx, sys, &sys->mesh, &targets[j], F + j, k);
     });
 }
 

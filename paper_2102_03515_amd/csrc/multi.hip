@@ -1,5 +1,5 @@
 // Block (multi right-hand side) PCG: k independent CG recurrences that share
-// one matrix and one AMG hierarchy (Section 5's PCG with one V-cycle as
+// one matrix and one AMG hierarchy (Section 4's PCG with one V-cycle as
 // preconditioner, applied to k load vectors at once).
 //
 // Vectors of the block are stored row-major, entry (i, j) at i*k + j, so that
@@ -930,12 +930,24 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
     hipStream_t s = ctx->stream;
     const int32_t *rp = sys->row_ptr.get(), *ci = sys->col.get();
     const double *av = sys->val.get();
+    // panel widths chosen earlier for this (system or hierarchy, k); the
+    // first solve of a shape times the candidates below and publishes its
+    // choice by compare-and-swap, so concurrent first solves agree on the
+    // first published width and every later solve takes it
+    std::atomic<int> &kb_mm_slot = const_cast<ocp_system *>(sys)->blk_kb_spmm[k];
+    std::atomic<int> *kb_vc_slot = h ? &const_cast<ocp_hierarchy *>(h)->blk_kb_vc[k] : nullptr;
+    auto publish = [](std::atomic<int> &slot, int kb) {
+        int expected = 0;
+        slot.compare_exchange_strong(expected, kb, std::memory_order_acq_rel);
+        return slot.load(std::memory_order_acquire);
+    };
     int kb_vc = KB0;
     if (h) {
-        int &cached = const_cast<ocp_hierarchy *>(h)->blk_kb_vc[k];
+        const int cached = kb_vc_slot->load(std::memory_order_acquire);
         kb_vc = forced ? forced : (cached ? cached : KB0);
     }
-    int kb_mm = forced ? forced : (sys->blk_kb_spmm[k] ? sys->blk_kb_spmm[k] : KB0);
+    const int cached_mm = kb_mm_slot.load(std::memory_order_acquire);
+    int kb_mm = forced ? forced : (cached_mm ? cached_mm : KB0);
 
     auto precond = [&](void) {
         if (h) {
@@ -981,13 +993,12 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
     // the first V-cycle (the outputs of these launches are overwritten before
     // they are read), so that every solve of the shape uses the same kernels
     if (!forced && hs.flag == 0) {
-        if (!sys->blk_kb_spmm[k]) sys->blk_kb_spmm[k] = tune_kb(ctx, KB0, spmm);
-        kb_mm = sys->blk_kb_spmm[k];
-        if (h && !h->blk_kb_vc[k]) {
+        if (!kb_mm_slot.load(std::memory_order_acquire)) publish(kb_mm_slot, tune_kb(ctx, KB0, spmm));
+        kb_mm = kb_mm_slot.load(std::memory_order_acquire);
+        if (h && !kb_vc_slot->load(std::memory_order_acquire)) {
             const Level &l0 = *h->levels[0];
-            int &cached = const_cast<ocp_hierarchy *>(h)->blk_kb_vc[k];
             if (h->levels.size() > 1) {
-                cached = tune_kb(ctx, KB0, [&](int kb) {
+                publish(*kb_vc_slot, tune_kb(ctx, KB0, [&](int kb) {
                     OCP_DISPATCH_KB(kb, ({
                         const BlkLaunch LV = blk_launch(l0.n, KB, k);
                         if (mixed) {
@@ -1009,12 +1020,12 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
                         }
                     }));
                     OCP_LAUNCH_CHECK();
-                });
+                }));
             } else {
-                cached = KB0;
+                publish(*kb_vc_slot, KB0);
             }
         }
-        if (h) kb_vc = h->blk_kb_vc[k];
+        if (h) kb_vc = kb_vc_slot->load(std::memory_order_acquire);
     }
     precond();
     pupdate();
@@ -1089,6 +1100,7 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
             in.rel_res_l2 = hcg.ff[j] > 0 ? std::sqrt(hcg.rr[j] / hcg.ff[j]) : 0.0;
             in.rel_res_precond = hcg.gamma0[j] > 0 ? std::sqrt(hcg.gamma[j] / hcg.gamma0[j]) : 0.0;
             in.true_rel_res = hcg.ff[j] > 0 ? std::sqrt(res2 / hcg.ff[j]) : 0.0;
+            in.setup_ms = h ? h->setup_ms : 0.0;
             in.solve_ms = ms;
         }
     }
@@ -1109,7 +1121,7 @@ extern "C" int pcg_solve_multi(ocp_ctx *ctx, const ocp_system *sys, const ocp_hi
         if (k < 1 || k > kMaxCols) fail(OCP_ERR_INVALID_ARG, "k must lie in 1..64");
         if (!(rtol > 0.0) || !std::isfinite(rtol)) fail(OCP_ERR_INVALID_ARG, "rtol must be positive");
         if (maxit < 1) fail(OCP_ERR_INVALID_ARG, "maxit must be >= 1");
-        if (h && !hierarchy_fits(h, sys)) fail(OCP_ERR_INVALID_ARG, "hierarchy is for a system on another mesh or pattern");
+        check_hierarchy(h, sys);
         solve_multi(ctx, const_cast<ocp_system *>(sys), h, k, F, U, rtol, maxit, flags, infos, &status);
     });
     if (rc != OCP_OK) {

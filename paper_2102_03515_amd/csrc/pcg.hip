@@ -1,4 +1,4 @@
-// Preconditioned conjugate gradients for A u = f (Section 5: PCG with the
+// Preconditioned conjugate gradients for A u = f (Section 4: PCG with the
 // AMG V-cycle as preconditioner, stopped at a relative residual tolerance).
 //
 // All scalars (alpha, beta, gamma, residual norms, the stop flag) live on the
@@ -267,19 +267,33 @@ bool hierarchy_fits(const ocp_hierarchy *h, const ocp_system *sys) {
            o->tets_ref == sys->tets_ref;
 }
 
-const Sell &system_sell(ocp_ctx *ctx, const ocp_system *csys) {
-    ocp_system *sys = const_cast<ocp_system *>(csys);
-    if (!sys->sell.col.get())
-        sell_build(ctx, sys->sell, sys->n, sys->row_ptr.get(), sys->col.get(), sys->val.get());
+void check_hierarchy(const ocp_hierarchy *h, const ocp_system *sys) {
+    if (!h) return;
+    if (!hierarchy_fits(h, sys)) fail(OCP_ERR_INVALID_ARG, "hierarchy is for a system on another mesh or pattern");
+    if (h->sys->generation.load(std::memory_order_acquire) != h->sys_generation)
+        fail(OCP_ERR_INVALID_ARG, "hierarchy is stale: fe_set_rho changed its system after amg_setup; rebuild it");
+}
+
+const Sell &system_sell(ocp_ctx *, const ocp_system *sys) {
+    if (!sys->sell.val.get()) fail(OCP_ERR_INVALID_ARG, "system has no solve-phase matrix copy");
     return sys->sell;
 }
 
-const double *system_dinv(ocp_ctx *ctx, ocp_system *sys) {
-    if (!sys->dinv.get()) {
-        sys->dinv.reset(ctx, (size_t)sys->n);
-        k_diag_inv<<<grid_for(sys->n, 256), 256, 0, ctx->stream>>>(sys->n, sys->row_ptr.get(), sys->col.get(),
-                                                                   sys->val.get(), sys->dinv.get());
-        OCP_LAUNCH_CHECK();
+const double *system_dinv(ocp_ctx *ctx, const ocp_system *csys) {
+    ocp_system *sys = const_cast<ocp_system *>(csys);   // derived data only, under the system's lock
+    if (!sys->dinv_ready.load(std::memory_order_acquire)) {
+        std::lock_guard<std::mutex> lock(sys->derived_mu);
+        if (!sys->dinv_ready.load(std::memory_order_relaxed)) {
+            // allocated through the system's own context (it lives as long as
+            // the system), filled on the caller's stream and waited for before
+            // any other context may see it
+            sys->dinv.reset(sys->ctx, (size_t)sys->n);
+            k_diag_inv<<<grid_for(sys->n, 256), 256, 0, ctx->stream>>>(sys->n, sys->row_ptr.get(), sys->col.get(),
+                                                                       sys->val.get(), sys->dinv.get());
+            OCP_LAUNCH_CHECK();
+            sync(ctx);
+            sys->dinv_ready.store(true, std::memory_order_release);
+        }
     }
     return sys->dinv.get();
 }
@@ -467,6 +481,7 @@ static int solve_finish(SolveState &S, double *u, ocp_solve_info *info) {
         info->rel_res_l2 = hs.ff > 0 ? std::sqrt(hs.rr / hs.ff) : 0.0;
         info->rel_res_precond = hs.gamma0 > 0 ? std::sqrt(hs.gamma / hs.gamma0) : 0.0;
         info->true_rel_res = hs.ff > 0 ? std::sqrt(res2 / hs.ff) : 0.0;
+        info->setup_ms = S.h ? S.h->setup_ms : 0.0;
         info->solve_ms = ms;
     }
     return st;
@@ -634,8 +649,7 @@ extern "C" int pcg_solve_batch(ocp_ctx *ctx, int32_t m, const ocp_system *const 
         if (maxit < 1) fail(OCP_ERR_INVALID_ARG, "maxit must be >= 1");
         for (int i = 0; i < m; ++i) {
             if (!systems[i] || !u[i]) fail(OCP_ERR_INVALID_ARG, "a system or u entry is NULL");
-            if (hierarchies && hierarchies[i] && !hierarchy_fits(hierarchies[i], systems[i]))
-                fail(OCP_ERR_INVALID_ARG, "hierarchy is for a system on another mesh or pattern");
+            if (hierarchies) check_hierarchy(hierarchies[i], systems[i]);
         }
         // small problems: one workgroup each in one persistent launch; the
         // rest: packed into one graph launch per iteration
@@ -703,7 +717,7 @@ extern "C" int pcg_solve(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarch
         if (!sys || !u) fail(OCP_ERR_INVALID_ARG, "system and u must not be NULL");
         if (!(rtol > 0.0) || !std::isfinite(rtol)) fail(OCP_ERR_INVALID_ARG, "rtol must be positive");
         if (maxit < 1) fail(OCP_ERR_INVALID_ARG, "maxit must be >= 1");
-        if (h && !hierarchy_fits(h, sys)) fail(OCP_ERR_INVALID_ARG, "hierarchy is for a system on another mesh or pattern");
+        check_hierarchy(h, sys);
         solve(ctx, const_cast<ocp_system *>(sys), h, f, u, rtol, maxit, flags, info, &status);
     });
     if (rc != OCP_OK) {
@@ -730,7 +744,7 @@ extern "C" int pcg_begin(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarch
         if (!sys) fail(OCP_ERR_INVALID_ARG, "system must not be NULL");
         if (!(rtol > 0.0) || !std::isfinite(rtol)) fail(OCP_ERR_INVALID_ARG, "rtol must be positive");
         if (maxit < 1) fail(OCP_ERR_INVALID_ARG, "maxit must be >= 1");
-        if (h && !hierarchy_fits(h, sys)) fail(OCP_ERR_INVALID_ARG, "hierarchy is for a system on another mesh or pattern");
+        check_hierarchy(h, sys);
         if (ctx->active_solve) fail(OCP_ERR_INVALID_ARG, "the context already runs a solve (one per context)");
         auto *hd = new ocp_solve_handle();
         try {
@@ -777,6 +791,7 @@ extern "C" int pcg_poll(ocp_solve_handle *hd, ocp_solve_info *info) {
         info->rel_res_l2 = hs.ff > 0 ? std::sqrt(hs.rr / hs.ff) : 0.0;
         info->rel_res_precond = hs.gamma0 > 0 ? std::sqrt(hs.gamma / hs.gamma0) : 0.0;
         info->true_rel_res = 0.0;
+        info->setup_ms = hd->S.h ? hd->S.h->setup_ms : 0.0;
         info->solve_ms = 0.0;
     }
     return hs.flag == 0 ? 1 : 0;

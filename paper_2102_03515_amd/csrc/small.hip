@@ -1,5 +1,5 @@
 // Persistent kernel for many small solves: one workgroup runs one whole
-// PCG solve (Section 5's PCG with the V(1,1)-cycle preconditioner of Section
+// PCG solve (Section 4's PCG with the V(1,1)-cycle preconditioner of Section
 // 4.1), every phase a loop of the workgroup's 1024 threads over the rows
 // separated by barriers, the scalars in LDS, the stop test on the device.
 // A batch of m small problems is one launch of m workgroups, where the
@@ -424,6 +424,7 @@ static void run_small(ocp_ctx *ctx, const std::vector<int> &idx, const ocp_syste
             in.rel_res_l2 = o.ff > 0 ? std::sqrt(o.rr / o.ff) : 0.0;
             in.rel_res_precond = o.gamma0 > 0 ? std::sqrt(o.gamma / o.gamma0) : 0.0;
             in.true_rel_res = o.ff > 0 ? std::sqrt(o.res2 / o.ff) : 0.0;
+            in.setup_ms = (hs && hs[idx[t]]) ? hs[idx[t]]->setup_ms : 0.0;
             in.solve_ms = 0.0;
         }
     }

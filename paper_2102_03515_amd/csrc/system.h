@@ -2,6 +2,9 @@
 // assembled system and the AMG hierarchy.
 #pragma once
 
+#include <atomic>
+#include <mutex>
+
 #include "common.h"
 
 namespace ocp {
@@ -38,20 +41,28 @@ struct ocp_system {
     int64_t nt = 0;           // tetrahedra
     int64_t nnz = 0;
     double rho = 0.0;
-    int max_row_len = -1;     // longest assembled row (computed on demand)
+    int max_row_len = -1;     // longest assembled row (computed during assembly)
     const int32_t *tets_ref = nullptr;  // mesh tets the system was assembled from (borrowed)
+    ocp_mesh mesh{};          // that mesh (device pointers, borrowed): later load vectors read it
+    // incremented by fe_set_rho: hierarchies built before a change of the
+    // values are refused by the solves (their diagonal, bounds and coarse
+    // operators belong to the old matrix)
+    std::atomic<uint64_t> generation{0};
     ocp::DevBuf<int32_t> inc_ptr, inc;  // vertex -> incident tets, ascending
     ocp::DevBuf<int32_t> dof_of_vertex, vertex_of_dof;
     ocp::DevBuf<int32_t> row_ptr, col;
     ocp::DevBuf<double> val, valK, valM, f;
-    // derived data, rebuilt on demand and dropped when the values change
+    // Derived data.  The sliced-ELL copy is built with the values (fe_assemble,
+    // fe_derive, fe_set_rho).  1/a_ii is built by the first Jacobi solve under
+    // `derived_mu` and published only after its kernel has finished, so
+    // concurrent solves on other contexts never read it half-filled; the block
+    // SpMM panel widths are set once by compare-and-swap.  Solves otherwise
+    // only read the system.
+    std::mutex derived_mu;
+    std::atomic<bool> dinv_ready{false};
     ocp::DevBuf<double> dinv;   // 1 / a_ii
     ocp::Sell sell;             // sliced-ELL copy of A for the solve phase
-    int blk_kb_spmm[65] = {};   // block SpMM panel width chosen per column count k (0: not yet)
-    void invalidate_derived() {
-        dinv.release();
-        sell = ocp::Sell();
-    }
+    std::atomic<int> blk_kb_spmm[65] = {};   // block SpMM panel width chosen per column count k (0: not yet)
 };
 
 namespace ocp {
@@ -90,9 +101,13 @@ struct Level {
 struct ocp_hierarchy {
     ocp_ctx *ctx = nullptr;
     const ocp_system *sys = nullptr;
+    uint64_t sys_generation = 0;   // sys->generation when the hierarchy was built
+    double setup_ms = 0.0;         // wall time of amg_setup
     ocp_amg_params params{};
     std::vector<std::unique_ptr<ocp::Level>> levels;
-    int blk_kb_vc[65] = {};     // block V-cycle panel width chosen per column count k (0: not yet)
+    // block V-cycle panel width chosen per column count k (0: not yet), set
+    // once by compare-and-swap so that every later solve uses the same kernels
+    std::atomic<int> blk_kb_vc[65] = {};
 };
 
 namespace ocp {
@@ -117,12 +132,15 @@ void vc_work_alloc(ocp_ctx *ctx, const ocp_hierarchy *h, VcWork &w, int k = 1);
 void vcycle_enqueue(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r, double *z, CgScalars *cg, VcWork &w);
 // Lanes per row for a matrix with the given average row length.
 int level_lanes(int64_t nnz, int64_t rows);
-// Build 1/a_ii of the system if missing.
-const double *system_dinv(ocp_ctx *ctx, ocp_system *sys);
+// 1/a_ii of the system, built (and waited for) by the first caller.
+const double *system_dinv(ocp_ctx *ctx, const ocp_system *sys);
 // A hierarchy may precondition its own system or any system on the same
 // mesh with the same sparsity pattern (another rho): the V-cycle then
 // applies the operator built for the hierarchy's system.
 bool hierarchy_fits(const ocp_hierarchy *h, const ocp_system *sys);
-// Build the sliced-ELL copy of the system's matrix if missing.
+// Fail with INVALID_ARG if h cannot precondition sys: another pattern, or
+// its own system's values changed (fe_set_rho) after it was built.
+void check_hierarchy(const ocp_hierarchy *h, const ocp_system *sys);
+// The sliced-ELL copy of the system's matrix (built with the values).
 const Sell &system_sell(ocp_ctx *ctx, const ocp_system *sys);
 }  // namespace ocp

@@ -1,5 +1,5 @@
 // Application of the AMG preconditioner B: one V(1,1)-cycle with zero
-// initial guess (Section 4.1: pre-smoothing, restriction with P^T, recursive
+// initial guess (Section 3.1: pre-smoothing, restriction with P^T, recursive
 // coarse correction with zero start, prolongation with P, post-smoothing).
 //
 // The smoother is a polynomial in D^-1 A: Chebyshev of degree 1 or 2 on
@@ -506,6 +506,7 @@ extern "C" int amg_vcycle(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r,
     if (!ctx) return OCP_ERR_INVALID_ARG;
     return run_guarded(ctx, [&] {
         if (!h || !r || !z) fail(OCP_ERR_INVALID_ARG, "hierarchy, r and z must not be NULL");
+        check_hierarchy(h, h->sys);
         VcWork w;
         vc_work_alloc(ctx, h, w);
         vcycle_enqueue(ctx, h, r, z, nullptr, w);

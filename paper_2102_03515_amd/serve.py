@@ -262,7 +262,8 @@ class Server:
         t_start = time.perf_counter()
         try:
             if not hit:
-                self._build(e, req, ctx)
+                with torch.cuda.stream(self.streams[slot]):
+                    self._build(e, req, ctx)
             e.ready.wait()
             if e.error is not None:
                 raise e.error

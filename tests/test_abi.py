@@ -61,7 +61,7 @@ def test_struct_layouts():
     import ctypes
     assert ctypes.sizeof(capi._Mesh) == 4 + 4 + 3 * 8
     assert ctypes.sizeof(capi._Target) == 4 + 4 + 8 + 8 + 8 + 48 + 8
-    assert ctypes.sizeof(capi.SolveInfo) == 8 + 4 * 8
+    assert ctypes.sizeof(capi.SolveInfo) == 8 + 5 * 8
     assert ctypes.sizeof(capi._AmgParams) == 5 * 4 + 4 + 3 * 8
 
 
@@ -72,3 +72,35 @@ def test_package_has_no_cpu_fallback():
         if fn.endswith(".py"):
             src = open(os.path.join(pkg, fn)).read()
             assert "import oracle" not in src and "from oracle" not in src, fn
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    that gcc gives the header's struct (compiled here from the header)."""
+    import ctypes
+    import shutil
+    import subprocess
+    capi = _lib_or_skip()
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    pairs = [("ocp_mesh", capi._Mesh), ("ocp_target", capi._Target), ("ocp_system_view", capi._SystemView),
+             ("ocp_amg_params", capi._AmgParams), ("ocp_level_view", capi._LevelView),
+             ("ocp_solve_info", capi.SolveInfo)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ocpamg.h"', "int main(void) {"]
+    for cname, cls in pairs:
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        a, b, v = line.split()
+        got[(a, b)] = int(v)
+    for cname, cls in pairs:
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)

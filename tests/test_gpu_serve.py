@@ -78,6 +78,63 @@ def test_step_api_matches_blocking_solve(P):
     assert torch.equal(ua, ua2) and torch.equal(ub, ub2)
 
 
+def test_concurrent_first_solves_on_a_fresh_system(P):
+    """Two host threads, each with its own context and stream, start the
+    first Jacobi-PCG solves on one freshly assembled system at the same time
+    (the Jacobi diagonal is built by whichever comes first and published only
+    when complete), then the first block solves of one shape (whose panel
+    width is timed and published once).  Every result matches the oracle, and
+    the two threads' results are the same bits."""
+    import threading
+    import torch
+    print("[concurrent first solves] cube14 Jacobi + block k=8 on two threads", flush=True)
+    N, rho = 14, 1e-2
+    mesh = I.kuhn_mesh(N, jitter=0.15, seed=61)
+    target = I.random_sine_modes(61)
+    ctx0 = P.Context()
+    dm = P.upload_mesh(mesh)
+    s = P.fe_assemble(ctx0, dm, rho, target)
+    h = P.amg_setup(ctx0, s, coarse_max=32)
+    torch.cuda.synchronize()
+    ctxs = [P.Context(stream=torch.cuda.Stream()) for _ in range(2)]
+    targets = [I.random_sine_modes(70 + j) for j in range(8)]
+    with torch.cuda.stream(ctxs[0].stream):
+        F = s.load_multi(targets, ctx=ctxs[0])
+    ctxs[0].stream.synchronize()
+    out = [None, None]
+    errors = []
+    barrier = threading.Barrier(2)
+
+    def run(i):
+        try:
+            with torch.cuda.stream(ctxs[i].stream):
+                barrier.wait()
+                u, info, rc = P.pcg_solve(ctxs[i], s, None, rtol=1e-13, maxit=5000)
+                barrier.wait()
+                U, infos, rcm = P.pcg_solve_multi(ctxs[i], s, h, F, rtol=1e-12, maxit=200)
+                ctxs[i].stream.synchronize()
+            out[i] = (u.cpu(), rc, U.cpu(), rcm)
+        except BaseException as exc:
+            errors.append(exc)
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    assert out[0][1] == out[1][1] == 0 and out[0][3] == out[1][3] == 0
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][2], out[1][2])
+    x, o, it, rr = O.solve(mesh, rho, target, rtol=1e-14)
+    uo = O.to_vertices(o, x, mesh.n_vertices)
+    assert _rel(out[0][0].numpy(), uo) < 1e-10
+    for j in (0, 7):
+        xj, oj, _, _ = O.solve(mesh, rho, targets[j], rtol=1e-14)
+        uj = O.to_vertices(oj, xj, mesh.n_vertices)
+        assert _rel(out[0][2][:, j].numpy(), uj) < 1e-9
+
+
 def test_fe_derive_matches_oracle_assembly(P):
     print("[fe_derive] cube10 jitter rho 1e-3 -> 0.37", flush=True)
     ctx = P.Context()

@@ -2,7 +2,7 @@
 
 Each test ties an oracle function to something other than itself: exact
 integrals, textbook stencils, invariants, a library Cholesky solve, the
-closed-form solution of Section 5.1 and the rates of Tables 1-3.
+closed-form solution of Section 4.1 and the rates of Tables 1-3.
 """
 import numpy as np
 import pytest
@@ -229,7 +229,7 @@ def _errors(N, rho, tgt):
 
 def test_closed_form_solution_single_mode():
     """At the vertices of a fine mesh the discrete solution approaches
-    u_rho = ubar / (1 + 3 pi^2 rho) (Section 5.1)."""
+    u_rho = ubar / (1 + 3 pi^2 rho) (Section 4.1)."""
     rho = 1e-2
     errs = []
     for N in (12, 24):

@@ -64,6 +64,59 @@ def kernel_bytes(kernel: int, n: int, entries: int, coded: bool, mixed: bool) ->
     raise ValueError(kernel)
 
 
+def csr_bytes(kernel: int, n: int, nnz: int, mixed: bool) -> float:
+    """Algorithmic HBM bytes of one launch as the method defines them, on the
+    CSR matrix (a value and a 4-byte column per nonzero, 4(n+1) bytes of row
+    pointers) with the vectors of kernel_bytes: for the CG SpMV
+    12 nnz + 4(n+1) + 16 n.  The kernels read the sliced-ELL copy with 4-bit
+    column codes instead, which moves fewer bytes (kernel_bytes)."""
+    vs = 4 if mixed else 8
+
+    def mat(v):
+        return (v + 4.0) * nnz + 4.0 * (n + 1)
+
+    if kernel == 0:
+        return mat(8) + 16.0 * n
+    if kernel == 1:
+        return mat(vs) + 8.0 * n + 3.0 * vs * n
+    if kernel == 5:
+        return mat(vs) + 8.0 * n + 2.0 * vs * n
+    if kernel == 6:
+        return mat(vs) + 8.0 * n + 4.0 * vs * n
+    if kernel == 2:
+        return mat(vs) + 16.0 * n + 4.0 * vs * n
+    raise ValueError(kernel)
+
+
+def kappa_bound(system, dmesh):
+    """Upper bound of the condition number of A (diagnostic, outside the timed
+    region): lambda_max <= the largest absolute row sum, lambda_min >= the
+    smallest volume of the tetrahedra around an interior vertex over 20 (each
+    element mass matrix is at least |tau|/20 times the identity on its
+    vertices; rho K is positive semidefinite)."""
+    import torch
+    rp, col, val = system.csr()
+    n = rp.numel() - 1
+    rows = torch.repeat_interleave(torch.arange(n, device=val.device), (rp[1:] - rp[:-1]).long())
+    lmax = float(torch.zeros(n, dtype=torch.float64, device=val.device).index_add_(0, rows, val.abs()).max())
+    del rows, rp, col, val
+    xyz, tets = dmesh.xyz, dmesh.tets.long()
+    patch = torch.zeros(xyz.shape[0], dtype=torch.float64, device=xyz.device)
+    for s in range(0, tets.shape[0], 1 << 24):
+        t = tets[s:s + (1 << 24)]
+        p = xyz[t]                                   # [m,4,3]
+        e = p[:, 1:, :] - p[:, :1, :]                # rows: edge vectors from vertex 0
+        det = (e[:, 0, 0] * (e[:, 1, 1] * e[:, 2, 2] - e[:, 1, 2] * e[:, 2, 1])
+               - e[:, 0, 1] * (e[:, 1, 0] * e[:, 2, 2] - e[:, 1, 2] * e[:, 2, 0])
+               + e[:, 0, 2] * (e[:, 1, 0] * e[:, 2, 1] - e[:, 1, 1] * e[:, 2, 0]))
+        vol = det.abs() / 6.0
+        for a in range(4):
+            patch.index_add_(0, t[:, a], vol)
+    interior = dmesh.dirichlet == 0
+    lmin = float(patch[interior].min()) / 20.0
+    return lmax / lmin
+
+
 # HBM bytes per launch of the fine-level kernels from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE) of `bench.py --calibrate-copy`, each scaled
 # by what the same counter reads for the 1 GiB elementwise copy of that run.
@@ -205,7 +258,7 @@ def packed_bench(P, capi, m: int = 32, N: int = 32, reps: int = 3):
     return out
 
 
-def serve_bench(P, capi, n_requests: int = 400, rate: float = 200.0, slots: int = 16, rho_bucket: float = 0.5):
+def serve_bench(P, capi, n_requests: int = 10000, rate: float = 200.0, slots: int = 16, rho_bucket: float = 0.5):
     """Poisson stream of solve requests (mean `rate` per second, seed 3000):
     N uniform in {32, 48, 64, 96, 128, 160}, rho = h^2 with probability 1/2
     else 10^U(-8,-2), a sine-mode target per request; each solved to 1e-8.
@@ -272,6 +325,8 @@ def main():
     ap.add_argument("--no-block", action="store_true", help="skip the 32-target block solve at 127^3")
     ap.add_argument("--no-serve", action="store_true", help="skip the served request stream")
     ap.add_argument("--no-packed", action="store_true", help="skip the packed batch of small solves")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests of the served Poisson stream per precision (200/s: 10,000 take 50 s)")
     ap.add_argument("--skip-main", action="store_true",
                     help="skip the headline steps (profiling one of the other sections)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -354,16 +409,28 @@ def main():
         dom = max(MATRIX_KERNELS, key=lambda k: timings[k][1])
         launches, tot_ms = timings[dom]
         avg_ms = tot_ms / max(launches, 1)
-        alg = kernel_bytes(dom, n, entries, coded, mixed=(dom != 0))
+        stored = kernel_bytes(dom, n, entries, coded, mixed=(dom != 0))
+        alg = csr_bytes(dom, n, nnz, mixed=(dom != 0))
         achieved = alg / (avg_ms * 1e-3) / 1e9
+        achieved_stored = stored / (avg_ms * 1e-3) / 1e9
         kernels = {KERNEL_NAMES[k]: {"launches": timings[k][0],
                                      "avg_us": 1e3 * timings[k][1] / max(timings[k][0], 1)}
                    for k in range(7)}
         for k in MATRIX_KERNELS:
-            b = kernel_bytes(k, n, entries, coded, mixed=(k != 0))
+            b = csr_bytes(k, n, nnz, mixed=(k != 0))
+            bs = kernel_bytes(k, n, entries, coded, mixed=(k != 0))
             t = timings[k][1] / max(timings[k][0], 1)
             kernels[KERNEL_NAMES[k]]["alg_bytes"] = b
             kernels[KERNEL_NAMES[k]]["alg_GBps"] = b / (t * 1e-3) / 1e9 if t > 0 else None
+            kernels[KERNEL_NAMES[k]]["stored_bytes"] = bs
+            kernels[KERNEL_NAMES[k]]["stored_GBps"] = bs / (t * 1e-3) / 1e9 if t > 0 else None
+
+        # error against the exact discrete solution (the FP64 oracle's to its
+        # 1e-14 stop): ||u - A^-1 f|| / ||A^-1 f|| <= kappa(A) ||f - A u|| / ||f||
+        s_b = P.fe_assemble(ctx, dmesh, rho, target)
+        kap = kappa_bound(s_b, dmesh)
+        s_b.close()
+        torch.cuda.empty_cache()
 
         fp64 = None
         if not args.no_fp64:
@@ -374,7 +441,8 @@ def main():
             torch.cuda.synchronize()
             tb = time.perf_counter()
             fp64 = {"dof_per_s": n / (tb - ta), "iterations": m64["iterations"], "solve_ms": m64["solve_ms"],
-                    "setup_ms": m64["setup_ms"], "true_rel_res": m64["true_rel_res"]}
+                    "setup_ms": m64["setup_ms"], "true_rel_res": m64["true_rel_res"],
+                    "error_bound": kap * m64["true_rel_res"]}
             print(f"[bench] fp64 step: {json.dumps(m64)}", file=sys.stderr, flush=True)
         solve_ms = sum(m["solve_ms"] for m in metas) / len(metas)
         return {
@@ -390,11 +458,18 @@ def main():
                          "setup": sum(m["setup_ms"] for m in metas) / len(metas),
                          "solve": solve_ms},
             "solve_only_dof_per_s": n / (solve_ms * 1e-3),
+            "error_vs_fp64_oracle": {
+                "bound": kap * metas[-1]["true_rel_res"] + kap * 1e-14, "kappa_bound": kap,
+                "kind": "rigorous bound, not a measurement: ||u - u_oracle||/||u_oracle|| <= kappa(A) "
+                        "(true_rel_res + 1e-14) with kappa(A) <= max row sum of |A| / (min vertex-patch volume / 20)"},
             "fp64": fp64,
             "kernels": kernels,
             "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": traffic_bytes(dom), "launches": launches, "avg_us": 1e3 * avg_ms},
+                         "traffic": traffic_bytes(dom), "launches": launches, "avg_us": 1e3 * avg_ms,
+                         "alg_bytes": alg, "alg_bytes_def": "12 nnz + 4(n+1) + 16 n (CSR, FP64)",
+                         "stored_bytes": stored, "achieved_stored": achieved_stored,
+                         "frac_stored": achieved_stored / HBM_PEAK_GBS},
         }
 
     head = {"value": None, "ms_per_step": None, "config": {"workload": args.workload}} if args.skip_main \
@@ -416,8 +491,9 @@ def main():
 
     served = None
     if not args.no_serve:
-        print("[bench] serving stream (400 requests, 200/s) ...", file=sys.stderr, flush=True)
-        served = serve_bench(P, capi)
+        print(f"[bench] serving stream ({args.serve_requests} requests per precision, 200/s) ...", file=sys.stderr,
+              flush=True)
+        served = serve_bench(P, capi, n_requests=args.serve_requests)
 
     cpu = None
     if not args.no_cpu_baseline and isinstance(tspec, tuple):

@@ -180,6 +180,21 @@ int ocp_spmv(ocp_ctx *ctx, const ocp_system *sys, const double *x, double *y);
 #define OCP_SMOOTH_L1JACOBI 0
 #define OCP_SMOOTH_CHEBYSHEV 1
 
+/* The AMG method of the hierarchy:
+ *   OCP_AMG_AGGREGATION  smoothed aggregation (default): distance-2
+ *       independent-set aggregates, smoothed prolongator, polynomial
+ *       (Chebyshev or L1-Jacobi) smoother; this build's design for the GPU.
+ *   OCP_AMG_REDBLACK     the method of Section 3.1: red-black colouring
+ *       coarsening (an unmarked dof turns black = coarse, its unmarked
+ *       neighbours red = fine, until every dof is marked; visited here in a
+ *       fixed hash order of the dofs), interpolation of a fine dof by the
+ *       average of its coarse neighbours, Galerkin A_c = P^T A P, and one
+ *       symmetric Gauss-Seidel sweep (forward before, backward after the
+ *       coarse correction), the dofs swept colour by colour in a colouring of
+ *       A's graph.  smoother, degree, omega and cheb_ratio are ignored. */
+#define OCP_AMG_AGGREGATION 0
+#define OCP_AMG_REDBLACK 1
+
 typedef struct {
     int32_t precision;   /* OCP_PREC_* */
     int32_t smoother;    /* OCP_SMOOTH_* */
@@ -189,10 +204,11 @@ typedef struct {
     double theta;        /* strength threshold: |a_ij| >= theta sqrt(a_ii a_jj) */
     double omega;        /* prolongator smoothing: omega/lambda_max(D^-1 A), 4/3 default */
     double cheb_ratio;   /* Chebyshev interval [lambda/cheb_ratio, lambda], lambda = Gershgorin bound */
+    int32_t method;      /* OCP_AMG_AGGREGATION (default) or OCP_AMG_REDBLACK */
 } ocp_amg_params;
 
-/* Fill `p` with the defaults (FP64, Chebyshev degree 2 on [lambda/10, lambda],
- * coarse_max 512, 10 levels, theta 0, omega 4/3). */
+/* Fill `p` with the defaults (smoothed aggregation, FP64, Chebyshev degree 2
+ * on [lambda/10, lambda], coarse_max 512, 10 levels, theta 0, omega 4/3). */
 void amg_default_params(ocp_amg_params *p);
 
 /* Build a smoothed-aggregation hierarchy for the system's A (Section 3.1:
@@ -334,6 +350,34 @@ int pcg_begin(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, const
 int pcg_advance(ocp_solve_handle *hd, int32_t iters);
 int pcg_poll(ocp_solve_handle *hd, ocp_solve_info *info);
 int pcg_end(ocp_solve_handle *hd, double *u, ocp_solve_info *info);
+
+/* ------------------------------------------- control, adjoint, errors */
+/* Adjoint and control from a computed state (Section 1: the gradient
+ * equation (4) gives p = -rho u; the state equation (2) with the reduced
+ * equation (5) gives z = -Lap u = (ubar - u) / rho), at every vertex of the
+ * system's mesh: p[v] = -rho u[v], z[v] = (ubar(x_v) - u[v]) / rho, with
+ * ubar evaluated at the vertex (its nodal value for a NODAL target; on the
+ * box faces an indicator is 0), rho the system's.
+ *   u      device [n_vertices] state (as written by pcg_solve)
+ *   p, z   device [n_vertices] outputs, caller-owned; either may be NULL
+ * The system's mesh must still be alive.  Errors: INVALID_ARG (NULL system
+ * or u, bad target when z is asked for), OOM, HIP. */
+int fe_recover(ocp_ctx *ctx, const ocp_system *sys, const ocp_target *target, const double *u, double *p,
+               double *z);
+
+/* Errors of a P1 state u (device [n_vertices]) measured in Section 4.1
+ * (Tables 1-3), integrated element by element over the system's mesh with
+ * a degree-7 rule (125 points per tetrahedron):
+ *   out[0] = ||u_rho - u||_L2,  out[1] = ||grad(u_rho - u)||_L2, where u_rho
+ *            is the exact solution of eq. (5) for a target made of Dirichlet
+ *            eigenfunctions: a SINE_MODES target with offset 0 gives
+ *            u_rho = sum_m amp[m] / (1 + rho pi^2 |k_m|^2) prod_d sin(k_md pi x_d);
+ *            NaN for any other target (no closed form)
+ *   out[2] = ||ubar - u||_L2 (the distance to the target; a NODAL target is
+ *            its P1 interpolant)
+ * out is host memory [3].  Synchronizes the stream.  Errors: INVALID_ARG,
+ * OOM, HIP. */
+int fe_error_norms(ocp_ctx *ctx, const ocp_system *sys, const ocp_target *target, const double *u, double *out);
 
 /* ------------------------------------------------------- kernel timing */
 #define OCP_KERNEL_CG_SPMV 0      /* q = A p with p.q, FP64 CSR (the CG iteration's SpMV) */

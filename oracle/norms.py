@@ -103,3 +103,54 @@ def target_error_l2(mesh, u_vertices: np.ndarray, target, n_quad: int = 4,
         diff = eval_target(target, xq) - u_vertices[t] @ lam.T
         e2 += float(np.sum(det[:, None] * w[None, :] * diff ** 2))
     return float(np.sqrt(e2))
+
+
+def control_and_adjoint(mesh, u_vertices: np.ndarray, target, rho: float, nodal_target=None):
+    """Adjoint p = -rho u (gradient equation (4), Section 1) and control
+    z = (ubar - u) / rho (state equation (2) with the reduced equation (5)),
+    both at the vertices of the mesh from the nodal state u.  ubar is taken at
+    the vertices (its values there for a P1 target)."""
+    from .dense import eval_target
+    u = np.asarray(u_vertices, dtype=np.float64)
+    ub = np.asarray(nodal_target, dtype=np.float64) if nodal_target is not None else eval_target(target, mesh.xyz)
+    return -rho * u, (ub - u) / rho
+
+
+def closed_form_control(target, rho: float):
+    """z_rho(x) = (ubar - u_rho)/rho of a homogeneous sine-mode target: mode m
+    contributes a_m pi^2 |k_m|^2 / (1 + rho pi^2 |k_m|^2) prod_d sin(k_md pi x_d)
+    (-Lap of the mode-by-mode state)."""
+    ks = np.asarray(target.k, dtype=np.float64)
+    amps = np.asarray(target.amp, dtype=np.float64)
+    lam = np.pi ** 2 * (ks ** 2).sum(axis=1)
+    coef = amps * lam / (1.0 + rho * lam)
+
+    def z(p):
+        out = np.zeros(p.shape[:-1])
+        for k, c in zip(ks, coef):
+            out = out + c * np.prod(np.sin(k * np.pi * p), axis=-1)
+        return out
+
+    return z
+
+
+def box_series_coefficient(k: int, lo: float = 0.25, hi: float = 0.75) -> float:
+    """b_k = 2 int_lo^hi sin(k pi x) dx = (2/(k pi)) (cos(k pi lo) - cos(k pi hi)):
+    the sine-series coefficient of the indicator of (lo, hi) on (0, 1)."""
+    return 2.0 / (k * np.pi) * (np.cos(k * np.pi * lo) - np.cos(k * np.pi * hi))
+
+
+def box_indicator_state_on_grid(N: int, rho: float, K: int = 63, lo: float = 0.25, hi: float = 0.75):
+    """u_rho of eq. (5) for the box indicator target, truncated to wave
+    numbers <= K in every direction, at the lattice points (i/N, j/N, k/N):
+    u_rho = sum_k b_k1 b_k2 b_k3 / (1 + rho pi^2 |k|^2) prod_d sin(k_d pi x_d)
+    (the target's sine series solved mode by mode).  Returns [N+1]^3 indexed
+    [i, j, k] with x = i/N.  A truncation-limited reference (loose for small
+    rho, where u_rho approaches the discontinuous target)."""
+    ks = np.arange(1, K + 1)
+    b = box_series_coefficient(ks, lo, hi)
+    k2 = ks[:, None, None] ** 2 + ks[None, :, None] ** 2 + ks[None, None, :] ** 2
+    C = b[:, None, None] * b[None, :, None] * b[None, None, :] / (1.0 + rho * np.pi ** 2 * k2)
+    x = np.arange(N + 1) / N
+    S = np.sin(np.pi * ks[:, None] * x[None, :])       # [K, N+1]
+    return np.einsum("abc,ai,bj,ck->ijk", C, S, S, S, optimize=True)

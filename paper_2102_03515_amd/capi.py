@@ -23,6 +23,7 @@ ERR_INVALID_ARG, ERR_BAD_MESH, ERR_OOM, ERR_BREAKDOWN, ERR_HIP, ERR_UNSUPPORTED 
 KEEP_KM = 1
 PREC_FP64, PREC_MIXED = 0, 1
 SMOOTH_L1JACOBI, SMOOTH_CHEBYSHEV = 0, 1
+AMG_AGGREGATION, AMG_REDBLACK = 0, 1
 STOP_L2, STOP_PRECOND = 0, 1
 FLEXIBLE = 2
 TARGET_SINE, TARGET_BOX, TARGET_NODAL = 0, 1, 2
@@ -56,7 +57,7 @@ class _SystemView(C.Structure):
 class _AmgParams(C.Structure):
     _fields_ = [("precision", C.c_int32), ("smoother", C.c_int32), ("degree", C.c_int32),
                 ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("theta", C.c_double),
-                ("omega", C.c_double), ("cheb_ratio", C.c_double)]
+                ("omega", C.c_double), ("cheb_ratio", C.c_double), ("method", C.c_int32)]
 
 
 class _LevelView(C.Structure):
@@ -112,6 +113,9 @@ _SIGS = {
     "pcg_advance": (C.c_int, [C.c_void_p, C.c_int32]),
     "pcg_poll": (C.c_int, [C.c_void_p, C.POINTER(SolveInfo)]),
     "pcg_end": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SolveInfo)]),
+    "fe_recover": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(_Target), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fe_error_norms": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(_Target), C.c_void_p,
+                                 C.POINTER(C.c_double)]),
     "ocp_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "ocp_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
 }
@@ -389,6 +393,29 @@ class System:
         arr = (_Target * k)(*[target_struct(t, keep) for t in targets])
         ctx.check(lib().fe_load_multi(ctx.handle, self.handle, k, arr, _ptr(out)))
         return out
+
+    def recover(self, target, u, ctx: Optional["Context"] = None):
+        """(p, z) on all vertices: adjoint -rho u and control (ubar - u)/rho
+        from the state u (device [n_vertices])."""
+        torch = _torch()
+        ctx = ctx or self.ctx
+        nv = self.view().n_vertices
+        p = torch.empty(nv, dtype=torch.float64, device="cuda")
+        z = torch.empty(nv, dtype=torch.float64, device="cuda")
+        keep = []
+        t = target_struct(target, keep)
+        ctx.check(lib().fe_recover(ctx.handle, self.handle, C.byref(t), _ptr(u), _ptr(p), _ptr(z)))
+        return p, z
+
+    def error_norms(self, target, u, ctx: Optional["Context"] = None):
+        """(||u_rho - u||_L2, ||grad(u_rho - u)||_L2, ||ubar - u||_L2); the
+        first two are NaN for targets without a closed-form solution."""
+        ctx = ctx or self.ctx
+        keep = []
+        t = target_struct(target, keep)
+        out = (C.c_double * 3)()
+        ctx.check(lib().fe_error_norms(ctx.handle, self.handle, C.byref(t), _ptr(u), out))
+        return float(out[0]), float(out[1]), float(out[2])
 
     def close(self):
         if getattr(self, "handle", None):

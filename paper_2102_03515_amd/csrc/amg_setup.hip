@@ -190,15 +190,18 @@ __device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
 // round kMisMarkFrom + 1 on m1 is recomputed only for nodes marked (need[i]
 // == round) as the closed neighbourhood of an undecided node.
 constexpr int kMisMarkFrom = 5;   // first round whose m2 marks
+constexpr int kMisMaxRounds = 1024;
 template <int G, bool FIRST>
 __global__ void __launch_bounds__(256) k_mis_m1(int32_t n, const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ col, const uint8_t *__restrict__ strong,
                                                 const int8_t *__restrict__ state, uint32_t salt,
                                                 const int32_t *__restrict__ need, int32_t round,
+                                                const int32_t *__restrict__ prev_undecided,
                                                 uint64_t *__restrict__ m1) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int i = (int)(t / G), lane = (int)(t % G);
     if (i >= n) return;
+    if (prev_undecided && *prev_undecided == 0) return;   // every node decided in an earlier round
     if (need && need[i] != round) return;   // uniform over the group
     uint64_t m = 0;
     const int ke = rp[i + 1];
@@ -237,10 +240,12 @@ __global__ void __launch_bounds__(256) k_mis_m2(int32_t n, const int32_t *__rest
                                                 const int32_t *__restrict__ col, const uint8_t *__restrict__ strong,
                                                 int8_t *__restrict__ state, uint32_t salt,
                                                 const uint64_t *__restrict__ m1, int32_t *__restrict__ need,
-                                                int32_t round, int32_t *undecided) {
+                                                int32_t round, const int32_t *__restrict__ prev_undecided,
+                                                int32_t *undecided) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int i = (int)(t / G), lane = (int)(t % G);
     if (i >= n) return;
+    if (prev_undecided && *prev_undecided == 0) return;   // every node decided in an earlier round
     if (state[i] != 0) return;   // uniform over the group
     uint64_t m = 0;
     const int ke = rp[i + 1];
@@ -1343,6 +1348,374 @@ static void to_float(ocp_ctx *ctx, const double *a, DevBuf<float> &b, int64_t n)
 }
 
 // ------------------------------------------------------------------- setup
+// ------------------------------------------------------ red-black method
+// Section 3.1: red-black colouring coarsening.  Sequentially: pick an
+// unmarked dof, mark it black (coarse) and its unmarked neighbours red
+// (fine), until every dof is marked.  With the dofs picked in decreasing
+// order of a fixed key (the hash priority of the aggregation, ties by index)
+// the result is the independent set that parallel rounds produce: in a round
+// an undecided dof whose key exceeds every undecided neighbour's turns
+// coarse (k_rb_pick), and then every undecided neighbour of a new coarse dof
+// turns fine (k_rb_mark).  The pick is written to its own array so that no
+// dof reads a state another dof of the same round changes.
+__device__ __forceinline__ uint64_t rb_key(int i, uint32_t salt) {
+    return ((uint64_t)(mix32((uint32_t)i ^ salt) >> 2) << 32) | (uint32_t)i;
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_rb_pick(int32_t n, const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ col, const uint8_t *__restrict__ strong,
+                                                 const int8_t *__restrict__ state, uint32_t salt, int32_t round,
+                                                 const int32_t *__restrict__ prev_undecided, int32_t *__restrict__ pick) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / G), lane = (int)(t % G);
+    if (i >= n) return;
+    if (prev_undecided && *prev_undecided == 0) return;
+    if (state[i] != 0) return;   // uniform over the group
+    const uint64_t ki = rb_key(i, salt);
+    int beaten = 0;
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += G) {
+        const int j = col[k];
+        if (is_strong(strong, k, j, i) && state[j] == 0 && rb_key(j, salt) > ki) beaten = 1;
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) beaten |= __shfl_xor(beaten, o, G);
+    if (lane == 0 && !beaten) pick[i] = round;
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_rb_mark(int32_t n, const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ col, const uint8_t *__restrict__ strong,
+                                                 int8_t *__restrict__ state, const int32_t *__restrict__ pick,
+                                                 int32_t round, const int32_t *__restrict__ prev_undecided,
+                                                 int32_t *undecided) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / G), lane = (int)(t % G);
+    if (i >= n) return;
+    if (prev_undecided && *prev_undecided == 0) return;
+    if (state[i] != 0) return;   // uniform over the group
+    const bool black = pick[i] == round;
+    int red = 0;
+    if (!black)
+        for (int k = rp[i] + lane; k < rp[i + 1]; k += G) {
+            const int j = col[k];
+            if (is_strong(strong, k, j, i) && pick[j] == round) red = 1;
+        }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) red |= __shfl_xor(red, o, G);
+    if (lane == 0) {
+        if (black)
+            state[i] = 1;
+        else if (red)
+            state[i] = 2;
+    }
+    const bool still = lane == 0 && !black && !red;
+    const unsigned long long any = __ballot(still);
+    if (any != 0ull && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)any) - 1)) *undecided = 1;
+}
+
+// Interpolation by averaging (Section 3.1): a coarse dof keeps its value
+// (P[i, c(i)] = 1); a fine dof takes the mean of its coarse strong
+// neighbours (P[i, c(j)] = 1 / #coarse neighbours).  cidx[j] = coarse number
+// of a coarse dof (ascending in j, so each row's columns are sorted).
+__global__ void k_rb_p_len(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                           const uint8_t *__restrict__ strong, const int8_t *__restrict__ state,
+                           int32_t *__restrict__ len, int32_t *flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = 0;
+    if (state[i] == 1) {
+        c = 1;
+    } else {
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+            const int j = col[k];
+            if (is_strong(strong, k, j, i) && state[j] == 1) ++c;
+        }
+        if (c == 0) atomicOr(flag, 32);   // a fine dof without a coarse neighbour (not maximal)
+    }
+    len[i] = c;
+}
+
+__global__ void k_rb_p_fill(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                            const uint8_t *__restrict__ strong, const int8_t *__restrict__ state,
+                            const int32_t *__restrict__ cidx, const int32_t *__restrict__ prp,
+                            int32_t *__restrict__ pcol, double *__restrict__ pval, int32_t *__restrict__ agg) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int o = prp[i];
+    if (state[i] == 1) {
+        pcol[o] = cidx[i];
+        pval[o] = 1.0;
+        agg[i] = cidx[i];
+        return;
+    }
+    agg[i] = -1;
+    const double w = 1.0 / (double)(prp[i + 1] - o);
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = col[k];
+        if (is_strong(strong, k, j, i) && state[j] == 1) {
+            pcol[o] = cidx[j];
+            pval[o] = w;
+            ++o;
+        }
+    }
+}
+
+// Colouring of a level's graph (every off-diagonal entry couples) for the
+// Gauss-Seidel sweeps: colour c is the independent set that round c picks
+// among the uncoloured rows, each joining when its key exceeds every
+// uncoloured neighbour's.
+template <int G>
+__global__ void __launch_bounds__(256) k_col_pick(int32_t n, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ col, const int32_t *__restrict__ color,
+                                                  uint32_t salt, int32_t round,
+                                                  const int32_t *__restrict__ prev_uncoloured,
+                                                  int32_t *__restrict__ pick) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / G), lane = (int)(t % G);
+    if (i >= n) return;
+    if (prev_uncoloured && *prev_uncoloured == 0) return;
+    if (color[i] >= 0) return;
+    const uint64_t ki = rb_key(i, salt);
+    int beaten = 0;
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += G) {
+        const int j = col[k];
+        if (j != i && color[j] < 0 && rb_key(j, salt) > ki) beaten = 1;
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) beaten |= __shfl_xor(beaten, o, G);
+    if (lane == 0 && !beaten) pick[i] = round;
+}
+
+__global__ void k_col_mark(int32_t n, int32_t *__restrict__ color, const int32_t *__restrict__ pick, int32_t round,
+                           const int32_t *__restrict__ prev_uncoloured, int32_t *uncoloured) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (prev_uncoloured && *prev_uncoloured == 0) return;
+    if (color[i] >= 0) return;
+    bool still = true;
+    if (pick[i] == round) {
+        color[i] = round;
+        still = false;
+    }
+    const unsigned long long any = __ballot(still);
+    if (any != 0ull && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)any) - 1)) *uncoloured = 1;
+}
+
+__global__ void k_fill_i32(int64_t n, int32_t v, int32_t *__restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// rows grouped by colour, ascending within a colour: per tile of kColTile
+// rows its count of each colour (cnt[c * ntiles + tile]); after a scan of
+// cnt the tiles place their rows in order
+constexpr int kColTile = 64;
+__global__ void k_col_count(int32_t n, int32_t ncolors, const int32_t *__restrict__ color, int32_t ntiles,
+                            int32_t *__restrict__ cnt) {
+    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile >= ntiles) return;
+    const int r0 = tile * kColTile, r1 = r0 + kColTile < n ? r0 + kColTile : n;
+    for (int c = 0; c < ncolors; ++c) cnt[(int64_t)c * ntiles + tile] = 0;
+    for (int i = r0; i < r1; ++i) ++cnt[(int64_t)color[i] * ntiles + tile];
+}
+
+__global__ void k_col_scatter(int32_t n, const int32_t *__restrict__ color, int32_t ntiles,
+                              int32_t *__restrict__ off, int32_t *__restrict__ rows) {
+    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile >= ntiles) return;
+    const int r0 = tile * kColTile, r1 = r0 + kColTile < n ? r0 + kColTile : n;
+    for (int i = r0; i < r1; ++i) rows[off[(int64_t)color[i] * ntiles + tile]++] = i;
+}
+
+__global__ void k_col_starts(int32_t ncolors, int32_t ntiles, const int32_t *__restrict__ off,
+                             int32_t *__restrict__ starts) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncolors) starts[c] = off[(int64_t)c * ntiles];
+}
+
+constexpr int kMaxColors = 1000;   // colour offsets come back through the 4 KiB staging buffer
+
+// Colour level L's graph and group its rows by colour.
+static void colour_level(ocp_ctx *ctx, Level &L, uint32_t salt) {
+    hipStream_t s = ctx->stream;
+    const int32_t n = L.n;
+    DevBuf<int32_t> color(ctx, (size_t)n), pick(ctx, (size_t)n), unc(ctx, (size_t)kMaxColors + 1);
+    k_fill_i32<<<grid_for(n, 256), 256, 0, s>>>(n, -1, color.get());
+    k_fill_i32<<<grid_for(n, 256), 256, 0, s>>>(n, -1, pick.get());
+    fill_zero_bytes(ctx, unc.get(), sizeof(int32_t) * ((size_t)kMaxColors + 1));
+    constexpr int G = 4;
+    const unsigned gb = grid_for((int64_t)n * G, 256);
+    // unc[c + 1] = 1 when rows are still uncoloured after round c
+    int ncol = -1, batch = 4;
+    for (int c = 0; ncol < 0;) {
+        const int last = std::min(c + batch, kMaxColors);
+        for (; c < last; ++c) {
+            const int32_t *prev = c == 0 ? nullptr : unc.get() + c;
+            k_col_pick<G><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, color.get(), salt, c, prev, pick.get());
+            k_col_mark<<<grid_for(n, 256), 256, 0, s>>>(n, color.get(), pick.get(), c, prev, unc.get() + c + 1);
+        }
+        OCP_LAUNCH_CHECK();
+        int32_t flag = 0;
+        read_back(ctx, &flag, unc.get() + last, sizeof(int32_t));
+        if (flag == 0) {
+            std::vector<int32_t> h((size_t)last + 1);
+            read_back(ctx, h.data(), unc.get(), sizeof(int32_t) * h.size());
+            ncol = last;
+            for (int k = 1; k <= last; ++k)
+                if (h[k] == 0) {
+                    ncol = k;   // rounds 0 .. k-1 coloured every row
+                    break;
+                }
+        } else if (last >= kMaxColors) {
+            fail(OCP_ERR_UNSUPPORTED, "the Gauss-Seidel colouring needs more than 1000 colours");
+        }
+        batch = std::min(batch * 2, 16);
+    }
+    const int32_t ntiles = (n + kColTile - 1) / kColTile;
+    DevBuf<int32_t> cnt(ctx, (size_t)ncol * ntiles + 1), off(ctx, (size_t)ncol * ntiles + 1);
+    k_col_count<<<grid_for(ntiles, 256), 256, 0, s>>>(n, ncol, color.get(), ntiles, cnt.get());
+    OCP_LAUNCH_CHECK();
+    scan_exclusive(ctx, cnt.get(), off.get(), (int64_t)ncol * ntiles);
+    DevBuf<int32_t> starts(ctx, (size_t)ncol);
+    k_col_starts<<<grid_for(ncol, 256), 256, 0, s>>>(ncol, ntiles, off.get(), starts.get());
+    L.color_rows.reset(ctx, (size_t)n);
+    k_col_scatter<<<grid_for(ntiles, 256), 256, 0, s>>>(n, color.get(), ntiles, off.get(), L.color_rows.get());
+    OCP_LAUNCH_CHECK();
+    L.ncolors = ncol;
+    L.color_ptr.assign((size_t)ncol + 1, n);
+    read_back(ctx, L.color_ptr.data(), starts.get(), sizeof(int32_t) * (size_t)ncol);
+}
+
+// Levels of the red-black method, appended to h (level 0 already there).
+static void redblack_levels(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
+    (void)sys;
+    hipStream_t s = ctx->stream;
+    const ocp_amg_params &pr = h->params;
+    for (int lev = 0;; ++lev) {
+        Level &L = *h->levels.back();
+        const int32_t n = L.n;
+        L.gA = level_lanes(L.nnzA, n);
+        DevBuf<double> diag(ctx, n), gersh(ctx, n), dl1(ctx, n);
+        fill_zero_bytes(ctx, ctx->dev_flag, 4);
+        k_level_diag<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, L.A_val, diag.get(), dl1.get(), gersh.get(),
+                                                      ctx->dev_flag);
+        OCP_LAUNCH_CHECK();
+        int32_t fl = 0;
+        read_back(ctx, &fl, ctx->dev_flag, 4);
+        if (fl & 8) fail(OCP_ERR_INVALID_ARG, "matrix has a non-positive diagonal entry");
+        L.lambda_max = reduce_max_abs(ctx, gersh.get(), n);
+        L.dinv.reset(ctx, n);   // 1 / a_ii for the Gauss-Seidel updates
+        k_recip<<<grid_for(n, 256), 256, 0, s>>>(n, diag.get(), L.dinv.get());
+        OCP_LAUNCH_CHECK();
+        L.deg = 1;
+        const uint32_t salt = 0x9E3779B9u * (uint32_t)(lev + 1);
+        const bool last = (n <= pr.coarse_max) || (lev + 1 >= pr.max_levels);
+        if (!last) colour_level(ctx, L, salt ^ 0x5bd1e995u);
+        int32_t nc = 0;
+        DevBuf<uint8_t> strong;
+        DevBuf<int8_t> state;
+        if (!last) {
+            if (pr.theta > 0.0) {
+                strong.reset(ctx, (size_t)L.nnzA);
+                k_strength<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, L.A_val, diag.get(), pr.theta,
+                                                            strong.get());
+                OCP_LAUNCH_CHECK();
+            }
+            state.reset(ctx, (size_t)n);
+            fill_zero_bytes(ctx, state.get(), (size_t)n);
+            DevBuf<int32_t> pick(ctx, (size_t)n), undec(ctx, (size_t)kMisMaxRounds + 1);
+            fill_zero_bytes(ctx, pick.get(), sizeof(int32_t) * (size_t)n);
+            fill_zero_bytes(ctx, undec.get(), sizeof(int32_t) * ((size_t)kMisMaxRounds + 1));
+            constexpr int G = 4;
+            const unsigned gb = grid_for((int64_t)n * G, 256);
+            int batch = 4;
+            for (int round = 1;;) {
+                const int lastr = std::min(round + batch - 1, kMisMaxRounds);
+                for (; round <= lastr; ++round) {
+                    const int32_t *prev = round == 1 ? nullptr : undec.get() + round - 1;
+                    k_rb_pick<G><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, round, prev,
+                                                    pick.get());
+                    k_rb_mark<G><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), pick.get(), round,
+                                                    prev, undec.get() + round);
+                }
+                OCP_LAUNCH_CHECK();
+                int32_t und = 0;
+                read_back(ctx, &und, undec.get() + lastr, sizeof(int32_t));
+                if (und == 0) break;
+                if (lastr >= kMisMaxRounds) fail(OCP_ERR_HIP, "red-black colouring rounds did not terminate");
+                batch = std::min(batch * 2, 16);
+            }
+            DevBuf<int32_t> rflag(ctx, (size_t)n + 1);
+            L.agg.reset(ctx, n);   // coarse number of a coarse dof, -1 for a fine one
+            k_root_flags<<<grid_for(n, 256), 256, 0, s>>>(n, state.get(), rflag.get());
+            OCP_LAUNCH_CHECK();
+            DevBuf<int32_t> cidx(ctx, (size_t)n + 1);
+            nc = (int32_t)scan_exclusive(ctx, rflag.get(), cidx.get(), n);
+            if (!(last || nc <= 0 || 2 * (int64_t)nc > n)) {
+                Csr P;
+                P.rows = n;
+                P.cols = nc;
+                DevBuf<int32_t> len(ctx, (size_t)n + 1);
+                fill_zero_bytes(ctx, ctx->dev_flag, 4);
+                k_rb_p_len<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), len.get(),
+                                                            ctx->dev_flag);
+                OCP_LAUNCH_CHECK();
+                read_back(ctx, &fl, ctx->dev_flag, 4);
+                if (fl & 32) fail(OCP_ERR_HIP, "a fine dof has no coarse neighbour");
+                P.rp.reset(ctx, (size_t)n + 1);
+                P.nnz = scan_exclusive(ctx, len.get(), P.rp.get(), n);
+                P.col.reset(ctx, (size_t)P.nnz);
+                P.val.reset(ctx, (size_t)P.nnz);
+                k_rb_p_fill<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), cidx.get(),
+                                                             P.rp.get(), P.col.get(), P.val.get(), L.agg.get());
+                OCP_LAUNCH_CHECK();
+                Csr R;
+                transpose(ctx, n, nc, P.nnz, P.rp.get(), P.col.get(), P.val.get(), R);
+                Csr AP, Ac;
+                spgemm(ctx, n, nc, L.nnzA, L.A_rp, L.A_col, L.A_val, P.rp.get(), P.col.get(), P.val.get(), AP);
+                spgemm(ctx, nc, nc, P.nnz, R.rp.get(), R.col.get(), R.val.get(), AP.rp.get(), AP.col.get(),
+                       AP.val.get(), Ac);
+                sync(ctx);
+                L.nc = nc;
+                L.nnzP = P.nnz;
+                L.P_rp = std::move(P.rp);
+                L.P_col = std::move(P.col);
+                L.P_val = std::move(P.val);
+                L.R_rp = std::move(R.rp);
+                L.R_col = std::move(R.col);
+                L.R_val = std::move(R.val);
+                L.gP = level_lanes(L.nnzP, n);
+                L.gR = level_lanes(L.nnzP, nc);
+                L.maxP = csr_max_row(ctx, n, L.P_rp.get());
+                auto nxt = std::make_unique<Level>();
+                nxt->n = nc;
+                nxt->nnzA = Ac.nnz;
+                nxt->own_rp = std::move(Ac.rp);
+                nxt->own_col = std::move(Ac.col);
+                nxt->own_val = std::move(Ac.val);
+                nxt->A_rp = nxt->own_rp.get();
+                nxt->A_col = nxt->own_col.get();
+                nxt->A_val = nxt->own_val.get();
+                h->levels.push_back(std::move(nxt));
+                continue;
+            }
+        }
+        // last level: dense inverse (or Gauss-Seidel sweeps alone when too large)
+        L.agg.release();
+        if (n <= kDenseMax) {
+            L.dense_inv.reset(ctx, (size_t)n * n);
+            fill_zero_bytes(ctx, L.dense_inv.get(), sizeof(double) * (size_t)n * n);
+            k_csr_to_dense<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, L.A_val, L.dense_inv.get());
+            OCP_LAUNCH_CHECK();
+            dense_inverse(ctx, n, L.dense_inv.get());
+        } else if (L.ncolors == 0) {
+            colour_level(ctx, L, salt ^ 0x5bd1e995u);
+        }
+        break;
+    }
+}
+
 static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
     hipStream_t s = ctx->stream;
     const ocp_amg_params &pr = h->params;
@@ -1354,7 +1727,8 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
     l0->A_val = sys->val.get();
     h->levels.push_back(std::move(l0));
 
-    for (int lev = 0;; ++lev) {
+    if (pr.method == OCP_AMG_REDBLACK) redblack_levels(ctx, sys, h);
+    else for (int lev = 0;; ++lev) {
         Level &L = *h->levels.back();
         const int32_t n = L.n;
         L.gA = level_lanes(L.nnzA, n);
@@ -1412,26 +1786,38 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
             const uint32_t salt = 0x9E3779B9u * (uint32_t)(lev + 1);
             constexpr int GM = 4;
             const unsigned gb = grid_for((int64_t)n * GM, 256);
-            for (int round = 1;; ++round) {
-                if (round > 1000) fail(OCP_ERR_HIP, "independent-set rounds did not terminate");
-                fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
-                // the first rounds leave most nodes undecided: marking their
-                // neighbourhoods would cost more than the m1 work it skips,
-                // so m1 takes every node until the marks start
-                // round 1: every node undecided, no states to gather
-                if (round == 1)
-                    k_mis_m1<GM, true><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, nullptr,
-                                                          round, m1.get());
-                else
-                    k_mis_m1<GM, false><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt,
-                                                           round > kMisMarkFrom ? need.get() : nullptr, round,
-                                                           m1.get());
-                k_mis_m2<GM><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get(),
-                                                round >= kMisMarkFrom ? need.get() : nullptr, round, ctx->dev_flag);
+            // undec[r] = 1 when some node is still undecided after round r
+            // (r = 1..kMisMaxRounds).  Rounds are enqueued in batches between
+            // host reads of the flag of a batch's last round; the kernels of a
+            // round after the one that decided every node return at once.
+            DevBuf<int32_t> undec(ctx, (size_t)kMisMaxRounds + 1);
+            fill_zero_bytes(ctx, undec.get(), sizeof(int32_t) * ((size_t)kMisMaxRounds + 1));
+            int batch = 4;
+            for (int round = 1;;) {
+                const int last = std::min(round + batch - 1, kMisMaxRounds);
+                for (; round <= last; ++round) {
+                    const int32_t *prev = round == 1 ? nullptr : undec.get() + round - 1;
+                    // the first rounds leave most nodes undecided: marking their
+                    // neighbourhoods would cost more than the m1 work it skips,
+                    // so m1 takes every node until the marks start
+                    // round 1: every node undecided, no states to gather
+                    if (round == 1)
+                        k_mis_m1<GM, true><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt,
+                                                              nullptr, round, nullptr, m1.get());
+                    else
+                        k_mis_m1<GM, false><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt,
+                                                               round > kMisMarkFrom ? need.get() : nullptr, round,
+                                                               prev, m1.get());
+                    k_mis_m2<GM><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get(),
+                                                    round >= kMisMarkFrom ? need.get() : nullptr, round, prev,
+                                                    undec.get() + round);
+                }
                 OCP_LAUNCH_CHECK();
                 int32_t und = 0;
-                read_back(ctx, &und, ctx->dev_flag, sizeof(int32_t));
+                read_back(ctx, &und, undec.get() + last, sizeof(int32_t));
                 if (und == 0) break;
+                if (last >= kMisMaxRounds) fail(OCP_ERR_HIP, "independent-set rounds did not terminate");
+                batch = std::min(batch * 2, 16);
             }
             // aggregates
             DevBuf<int32_t> rflag(ctx, (size_t)n + 1), rpos(ctx, (size_t)n + 1);
@@ -1524,7 +1910,7 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
 
     // sliced-ELL copies of the larger coarse operators (their smoothing
     // passes then stream 64-row slices instead of one wide row group per row)
-    for (size_t l = 1; l < h->levels.size(); ++l) {
+    for (size_t l = 1; l < h->levels.size() && pr.method == OCP_AMG_AGGREGATION; ++l) {
         Level &L = *h->levels[l];
         if (L.n >= kSellMinRows && !L.dense_inv.get()) sell_build(ctx, L.sell, L.n, L.A_rp, L.A_col, L.A_val);
     }
@@ -1534,7 +1920,8 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
         Level &L = *h->levels[l];
         if (mixed) {
             to_float(ctx, L.A_val, L.A_val32, L.nnzA);
-            if (l == 0) sell_values32(ctx, system_sell(ctx, sys), L.A_rp, L.A_val32.get(), L.sell_val32);
+            if (l == 0 && pr.method == OCP_AMG_AGGREGATION)
+                sell_values32(ctx, system_sell(ctx, sys), L.A_rp, L.A_val32.get(), L.sell_val32);
             if (l > 0 && L.sell.col.get()) sell_values32(ctx, L.sell, L.A_rp, L.A_val32.get(), L.sell_val32);
             to_float(ctx, L.dinv.get(), L.dinv32, L.n);
             if (L.P_val.get()) to_float(ctx, L.P_val.get(), L.P_val32, L.nnzP);
@@ -1559,6 +1946,7 @@ extern "C" void amg_default_params(ocp_amg_params *p) {
     p->theta = 0.0;
     p->omega = 4.0 / 3.0;
     p->cheb_ratio = 10.0;
+    p->method = OCP_AMG_AGGREGATION;
 }
 
 extern "C" int amg_setup(ocp_ctx *ctx, const ocp_system *sys, const ocp_amg_params *params, ocp_hierarchy **out) {
@@ -1577,6 +1965,7 @@ extern "C" int amg_setup(ocp_ctx *ctx, const ocp_system *sys, const ocp_amg_para
         else
             amg_default_params(&h->params);
         const ocp_amg_params &p = h->params;
+        if (p.method != OCP_AMG_AGGREGATION && p.method != OCP_AMG_REDBLACK) fail(OCP_ERR_INVALID_ARG, "unknown AMG method");
         if (p.precision != OCP_PREC_FP64 && p.precision != OCP_PREC_MIXED) fail(OCP_ERR_INVALID_ARG, "bad precision");
         if (p.smoother != OCP_SMOOTH_L1JACOBI && p.smoother != OCP_SMOOTH_CHEBYSHEV)
             fail(OCP_ERR_INVALID_ARG, "unknown smoother");

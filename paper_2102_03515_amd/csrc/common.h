@@ -89,6 +89,7 @@ namespace ocp {
 // --------------------------------------------------------------- allocation
 void *dev_alloc(ocp_ctx *ctx, size_t bytes);
 void dev_free(ocp_ctx *ctx, void *p);
+constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Owning device buffer allocated through the context's allocator.
 template <typename T>

@@ -1122,6 +1122,8 @@ extern "C" int pcg_solve_multi(ocp_ctx *ctx, const ocp_system *sys, const ocp_hi
         if (!(rtol > 0.0) || !std::isfinite(rtol)) fail(OCP_ERR_INVALID_ARG, "rtol must be positive");
         if (maxit < 1) fail(OCP_ERR_INVALID_ARG, "maxit must be >= 1");
         check_hierarchy(h, sys);
+        if (h && h->params.method != OCP_AMG_AGGREGATION)
+            fail(OCP_ERR_UNSUPPORTED, "block solves take smoothed-aggregation hierarchies");
         solve_multi(ctx, const_cast<ocp_system *>(sys), h, k, F, U, rtol, maxit, flags, infos, &status);
     });
     if (rc != OCP_OK) {

@@ -364,7 +364,7 @@ static void solve_begin(SolveState &S, ocp_ctx *ctx, ocp_system *sys, const ocp_
     if (h) {
         vc_work_alloc(ctx, h, S.vw);
         S.vw.part = S.part + 3 * kRedBlocks;
-        if (h->levels.size() > 1) {
+        if (h->levels.size() > 1 && h->params.method == OCP_AMG_AGGREGATION) {
             const size_t vs = h->params.precision == OCP_PREC_MIXED ? sizeof(float) : sizeof(double);
             S.y0.reset(ctx, (size_t)n * vs);
             S.vw.y0 = S.y0.get();

@@ -29,6 +29,7 @@ void dev_free(ocp_ctx *ctx, void *p) {
 
 void sync(ocp_ctx *ctx) { OCP_HIP(hipStreamSynchronize(ctx->stream)); }
 
+
 void read_back(ocp_ctx *ctx, void *host, const void *dev, size_t bytes) {
     if (bytes > 4096) fail(OCP_ERR_INVALID_ARG, "read_back larger than the staging buffer");
     OCP_HIP(hipMemcpyAsync(ctx->pinned, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));

@@ -305,6 +305,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_pcg(const SmallDesc<T> 
 bool small_eligible(const ocp_system *sys, const ocp_hierarchy *h) {
     if (sys->n > kSmallMaxRows) return false;
     if (h && (int)h->levels.size() > kSmallMaxLevels) return false;
+    if (h && h->params.method != OCP_AMG_AGGREGATION) return false;   // the graph path runs the other methods
     return true;
 }
 
@@ -327,7 +328,6 @@ struct LvArrays<float> {
     static const float *d(const Level &L) { return L.dinv32.get(); }
     static const float *inv(const Level &L) { return L.dense_inv32.get(); }
 };
-inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 }  // namespace
 
 // Runs the given solves (all of value type T, or Jacobi when T is double

@@ -94,6 +94,11 @@ struct Level {
     double cheb_a = 1.0, cheb_c1 = 0.0, cheb_c2 = 0.0;
     int gA = 16, gP = 4, gR = 64;  // lanes per row of the A, P and R kernels
     int maxP = 0;                  // longest row of P
+    // red-black hierarchies: a colouring of A's graph (no two coupled rows
+    // share a colour) for the Gauss-Seidel sweeps, rows grouped by colour
+    int ncolors = 0;
+    std::vector<int32_t> color_ptr;   // host [ncolors + 1]
+    DevBuf<int32_t> color_rows;       // [n] rows of colour c at color_ptr[c] .. color_ptr[c+1], ascending
 };
 
 }  // namespace ocp

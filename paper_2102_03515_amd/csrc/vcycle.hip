@@ -469,7 +469,158 @@ static void vcycle_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, d
     }
 }
 
+// ------------------------------------------------- red-black method cycle
+// Section 3.1's V(1,1)-cycle: one forward Gauss-Seidel sweep from zero
+// before the coarse correction and one backward sweep after it (the
+// backward sweep is the adjoint of the forward one in the A inner product,
+// so the cycle is a symmetric positive definite preconditioner).  A sweep
+// takes the colours of the level's colouring in order (reverse order
+// backwards); rows of one colour are not coupled, so each colour is one
+// launch that updates its rows from the current iterate:
+//   x_i += (b_i - sum_j a_ij x_j) / a_ii.
+template <int G, typename T, typename BT, typename XT>
+__global__ void __launch_bounds__(kBlock) k_gs_colour(int32_t m, const int32_t *__restrict__ rows,
+                                                      const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                      const T *__restrict__ val, const T *__restrict__ dinv,
+                                                      const BT *__restrict__ b, XT *__restrict__ x,
+                                                      const CgScalars *cg) {
+    if (cg && cg->flag) return;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int r = (int)(t / G), lane = (int)(t % G);
+    if (r >= m) return;
+    const int i = rows[r];
+    const T s = dev::row_sum<G>(rp[i], rp[i + 1], lane, col, val, [&](int c) { return (T)x[c]; });
+    if (lane == 0) x[i] = (XT)((T)x[i] + ((T)b[i] - s) * dinv[i]);
+}
+
+// r = b - A x
+template <int G, typename T, typename BT, typename XT>
+__global__ void __launch_bounds__(kBlock) k_rb_resid(int32_t n, int iters, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                     const BT *__restrict__ b, const XT *__restrict__ x,
+                                                     T *__restrict__ r, const CgScalars *cg) {
+    if (cg && cg->flag) return;
+    OCP_ROWS_BEGIN(G)
+    const T s = dev::row_sum<G>(rp[row], rp[row + 1], lane, col, val, [&](int c) { return (T)x[c]; });
+    if (lane == 0) r[row] = (T)b[row] - s;
+    OCP_ROWS_END()
+}
+
+// x += P xc
+template <int G, typename T, typename XT>
+__global__ void __launch_bounds__(kBlock) k_rb_prolong(int32_t n, int iters, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                       const T *__restrict__ xc, XT *__restrict__ x,
+                                                       const CgScalars *cg) {
+    if (cg && cg->flag) return;
+    OCP_ROWS_BEGIN(G)
+    const T s = dev::row_sum<G>(rp[row], rp[row + 1], lane, col, val, [&](int c) { return xc[c]; });
+    if (lane == 0) x[row] = (XT)((T)x[row] + s);
+    OCP_ROWS_END()
+}
+
+template <typename XT>
+__global__ void k_rb_zero(int32_t n, XT *__restrict__ x, const CgScalars *cg) {
+    if (cg && cg->flag) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = XT(0);
+}
+
+template <typename T>
+static void vcycle_rb(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r_in, double *z_out, CgScalars *cg,
+                      VcWork &W) {
+    const auto &lv = h->levels;
+    const int L = (int)lv.size();
+    hipStream_t s = ctx->stream;
+    double *part = W.part ? W.part : ctx->red_partials + 3 * kRedBlocks;
+    // one sweep over level l's colours (forward or backward)
+    auto sweep = [&](int l, auto b, auto x, bool forward) {
+        const Level &cur = *lv[l];
+        const auto a = arrays<T>(cur);
+        for (int q = 0; q < cur.ncolors; ++q) {
+            const int c = forward ? q : cur.ncolors - 1 - q;
+            const int32_t r0 = cur.color_ptr[c], m = cur.color_ptr[c + 1] - r0;
+            if (m <= 0) continue;
+            OCP_DISPATCH_G(cur.gA, (k_gs_colour<G, T><<<grid_for((int64_t)m * G, kBlock), kBlock, 0, s>>>(
+                                       m, cur.color_rows.get() + r0, cur.A_rp, cur.A_col, a.A, a.d, b, x, cg)));
+        }
+        OCP_LAUNCH_CHECK();
+    };
+    auto coarsest = [&](int l, auto b, auto x) {
+        const Level &cl = *lv[l];
+        const auto a = arrays<T>(cl);
+        if (a.inv) {
+            k_vc_dense<T><<<grid_for(cl.n, kBlock / 64), kBlock, 0, s>>>(cl.n, a.inv, b, x, cg);
+            OCP_LAUNCH_CHECK();
+        } else {   // too large for the dense inverse: a symmetric sweep from zero
+            k_rb_zero<<<grid_for(cl.n, 256), 256, 0, s>>>(cl.n, x, cg);
+            sweep(l, b, x, true);
+            sweep(l, b, x, false);
+        }
+    };
+    auto vec = [&](const DevBuf<char> &v) { return reinterpret_cast<T *>(v.get()); };
+    if (L == 1) {
+        coarsest(0, r_in, z_out);
+    } else {
+        // down: x_l = forward sweep from zero; b_{l+1} = R (b_l - A x_l)
+        for (int l = 0; l < L - 1; ++l) {
+            const Level &cur = *lv[l];
+            const Level &nxt = *lv[l + 1];
+            const auto a = arrays<T>(cur);
+            T *rres = vec(W.lv[l].vr);
+            T *bn = vec(W.lv[l + 1].vb);
+            const RowLaunch LA = row_launch(cur.n, cur.gA);
+            const RowLaunch LR = row_launch(nxt.n, cur.gR);
+            auto go = [&](auto b, auto x) {
+                k_rb_zero<<<grid_for(cur.n, 256), 256, 0, s>>>(cur.n, x, cg);
+                sweep(l, b, x, true);
+                OCP_DISPATCH_G(cur.gA, (k_rb_resid<G, T><<<LA.blocks, kBlock, 0, s>>>(cur.n, LA.iters, cur.A_rp,
+                                                                                    cur.A_col, a.A, b, x, rres, cg)));
+            };
+            if (l == 0)
+                go(r_in, z_out);
+            else
+                go(static_cast<const T *>(vec(W.lv[l].vb)), vec(W.lv[l].vx));
+            OCP_DISPATCH_G(cur.gR, (k_vc_spmv<G, T><<<LR.blocks, kBlock, 0, s>>>(nxt.n, LR.iters, cur.R_rp.get(),
+                                                                              cur.R_col.get(), a.R, rres, bn, cg)));
+            OCP_LAUNCH_CHECK();
+        }
+        coarsest(L - 1, static_cast<const T *>(vec(W.lv[L - 1].vb)), vec(W.lv[L - 1].vx));
+        // up: x_l += P x_{l+1}, then a backward sweep
+        for (int l = L - 2; l >= 0; --l) {
+            const Level &cur = *lv[l];
+            const auto a = arrays<T>(cur);
+            const RowLaunch LP = row_launch(cur.n, cur.gP);
+            const T *xc = vec(W.lv[l + 1].vx);
+            auto go = [&](auto b, auto x) {
+                OCP_DISPATCH_G(cur.gP, (k_rb_prolong<G, T><<<LP.blocks, kBlock, 0, s>>>(
+                                           cur.n, LP.iters, cur.P_rp.get(), cur.P_col.get(), a.P, xc, x, cg)));
+                OCP_LAUNCH_CHECK();
+                sweep(l, b, x, false);
+            };
+            if (l == 0)
+                go(r_in, z_out);
+            else
+                go(static_cast<const T *>(vec(W.lv[l].vb)), vec(W.lv[l].vx));
+        }
+    }
+    if (cg) {
+        const int32_t n0 = lv[0]->n;
+        const RowLaunch LV = vec_launch(n0);
+        k_cg_rz<<<LV.blocks, kBlock, 0, s>>>(n0, LV.iters, r_in, z_out, cg, part);
+        k_vc_fin_rz<<<1, kFinBlock, 0, s>>>(LV.blocks, part, cg);
+        OCP_LAUNCH_CHECK();
+    }
+}
+
 void vcycle_enqueue(ocp_ctx *ctx, const ocp_hierarchy *h, const double *r, double *z, CgScalars *cg, VcWork &w) {
+    if (h->params.method == OCP_AMG_REDBLACK) {
+        if (h->params.precision == OCP_PREC_MIXED)
+            vcycle_rb<float>(ctx, h, r, z, cg, w);
+        else
+            vcycle_rb<double>(ctx, h, r, z, cg, w);
+        return;
+    }
     if (h->params.precision == OCP_PREC_MIXED)
         vcycle_t<float>(ctx, h, r, z, cg, w);
     else

@@ -53,6 +53,7 @@ def test_constants_match_header():
     assert int(defs["OCP_STOP_PRECOND"]) == capi.STOP_PRECOND
     assert int(defs["OCP_TARGET_BOX"]) == capi.TARGET_BOX
     assert int(defs["OCP_KEEP_KM"]) == capi.KEEP_KM
+    assert int(defs["OCP_AMG_REDBLACK"]) == capi.AMG_REDBLACK
 
 
 def test_struct_layouts():
@@ -62,7 +63,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(capi._Mesh) == 4 + 4 + 3 * 8
     assert ctypes.sizeof(capi._Target) == 4 + 4 + 8 + 8 + 8 + 48 + 8
     assert ctypes.sizeof(capi.SolveInfo) == 8 + 5 * 8
-    assert ctypes.sizeof(capi._AmgParams) == 5 * 4 + 4 + 3 * 8
+    assert ctypes.sizeof(capi._AmgParams) == 5 * 4 + 4 + 3 * 8 + 8
 
 
 def test_package_has_no_cpu_fallback():

@@ -303,3 +303,49 @@ def test_mode_superposition():
     e = [_errors(N, rho, tgt)[0] for N in (8, 16, 32)]
     eoc = np.log2(e[1] / e[2])
     assert 1.85 < eoc < 2.2
+
+
+def test_control_and_adjoint_recovery():
+    """Section 1: p = -rho u and z = (ubar - u)/rho.  For the eigenfunction
+    target z_rho = 3 pi^2 ubar / (1 + 3 pi^2 rho) (= -Lap u_rho, independently
+    of the recovery formula); the recovered nodal control converges to it at
+    second order in h for fixed rho, and p + rho u vanishes."""
+    tgt = I.single_sine()
+    rho = 1e-2
+    zc = norms.closed_form_control(tgt, rho)
+    errs = []
+    for N in (8, 16, 32):
+        m = I.kuhn_mesh(N)
+        x, s, it, rr = O.solve(m, rho, tgt, rtol=1e-13)
+        u = O.to_vertices(s, x, m.n_vertices)
+        p, z = norms.control_and_adjoint(m, u, tgt, rho)
+        assert np.abs(p + rho * u).max() == 0.0
+        exact = 3 * np.pi ** 2 * np.prod(np.sin(np.pi * m.xyz), axis=-1) / (1 + 3 * np.pi ** 2 * rho)
+        np.testing.assert_allclose(zc(m.xyz), exact, rtol=1e-13, atol=1e-13)
+        errs.append(np.abs(z - exact).max() / np.abs(exact).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 1.8), (errs, rates)
+    assert errs[-1] < 1e-2
+
+
+def test_box_series_reference():
+    """The sine-series coefficients of the box indicator equal 2 int sin(k pi x)
+    over the box edge interval (Gauss-Legendre quadrature), vanish for even k,
+    and by Parseval the squared L2 norm of the truncated series tends to the
+    box volume 1/8; the series state at rho -> 0 approaches the indicator at
+    interior lattice points away from the box faces."""
+    from numpy.polynomial.legendre import leggauss
+    xg, wg = leggauss(40)
+    for k in range(1, 12):
+        xs = 0.25 + 0.25 * (xg + 1.0)
+        quad = 2.0 * 0.25 * float(np.sum(wg * np.sin(k * np.pi * xs)))
+        assert norms.box_series_coefficient(k) == pytest.approx(quad, abs=1e-14)
+        if k % 2 == 0:
+            assert abs(norms.box_series_coefficient(k)) < 1e-15
+    ks = np.arange(1, 400)
+    one_d = 0.5 * np.sum(norms.box_series_coefficient(ks) ** 2)   # ||1_(1/4,3/4)||^2 = 1/2 in 1D
+    assert one_d == pytest.approx(0.5, abs=2e-3)
+    g = norms.box_indicator_state_on_grid(16, 1e-8, K=127)
+    assert g[8, 8, 8] == pytest.approx(1.0, abs=0.03)      # box centre (the partial sums converge like 1/K)
+    assert abs(g[2, 8, 8]) < 0.02                           # outside the box
+    assert g[4, 8, 8] == pytest.approx(0.5, abs=0.03)      # on a face: the series gives the mean

@@ -243,3 +243,121 @@ def test_priority_hash_is_a_permutation():
     rng = np.random.default_rng(0)
     for x in rng.integers(0, 1 << 32, size=2000, dtype=np.uint64):
         assert inverse(OA.lowbias32(int(x))) == int(x)
+
+
+# ------------------------------------------------- red-black method (Section 3.1)
+from oracle import amg_rb as RB  # noqa: E402
+
+
+@pytest.mark.parametrize("name", sorted(GRAPHS))
+def test_red_black_split_is_the_greedy_independent_set(name):
+    """Black dofs are pairwise non-adjacent, every red dof has a black
+    neighbour, and a dof is black iff no neighbour of larger key is black
+    (the characterization of the greedy set visited in decreasing key,
+    checked here on the final sets, not by replaying the marking)."""
+    nbrs = GRAPHS[name]()
+    salt = OA.level_salt(0)
+    black = RB.red_black_split(nbrs, salt)
+    for i, nb in enumerate(nbrs):
+        if black[i]:
+            assert not any(black[j] for j in nb)
+        else:
+            assert any(black[j] for j in nb)
+        higher_black = any(black[j] and RB.key(j, salt) > RB.key(i, salt) for j in nb)
+        assert black[i] == (not higher_black)
+
+
+@pytest.mark.parametrize("name", sorted(GRAPHS))
+def test_averaging_prolongator(name):
+    """P 1 = 1 (an average reproduces constants), a black dof's row is a unit
+    vector on its own coarse number, a red dof's row is uniform over exactly
+    its black neighbours."""
+    nbrs = GRAPHS[name]()
+    black = RB.red_black_split(nbrs, OA.level_salt(1))
+    P = RB.averaging_prolongator(nbrs, black).tocsr()
+    np.testing.assert_allclose(P @ np.ones(P.shape[1]), 1.0, rtol=0, atol=1e-15)
+    cnum = np.cumsum(black) - 1
+    for i in range(len(nbrs)):
+        cols = P.indices[P.indptr[i]:P.indptr[i + 1]]
+        vals = P.data[P.indptr[i]:P.indptr[i + 1]]
+        if black[i]:
+            assert list(cols) == [cnum[i]] and vals[0] == 1.0
+        else:
+            want = sorted(cnum[j] for j in nbrs[i] if black[j])
+            assert sorted(cols) == want
+            assert np.all(vals == vals[0])
+
+
+def test_colouring_is_proper_and_local_maximal():
+    """No two coupled dofs share a colour; a dof of colour c has, for every
+    earlier colour c' < c, a neighbour of colour c' with a larger key or it
+    had a larger-key neighbour still uncoloured at round c' (it lost that
+    round), i.e. colour c is exactly the set of local key maxima among the
+    dofs not coloured before c."""
+    o = O.assemble(I.kuhn_mesh(5, jitter=0.15, seed=2), 1.0, I.single_sine())
+    A = o.csr()
+    salt = OA.level_salt(0) ^ RB.COLOUR_SALT
+    col = RB.colouring(A, salt)
+    n = A.shape[0]
+    adj = [[int(j) for j in A.indices[A.indptr[i]:A.indptr[i + 1]] if j != i] for i in range(n)]
+    for i in range(n):
+        assert all(col[j] != col[i] for j in adj[i])
+        for c in range(col[i] + 1):
+            alive = [j for j in adj[i] if col[j] >= c]
+            is_max = all(RB.key(i, salt) > RB.key(j, salt) for j in alive)
+            assert is_max == (c == col[i])
+
+
+def test_gauss_seidel_sweep_is_a_triangular_solve():
+    """A forward sweep from zero in colour order solves (D + L) x = b where L
+    is the strictly lower part of A with the dofs ordered by colour; a
+    backward sweep from x0 equals x0 + (D + U)^-1 (b - A x0) (U the strictly
+    upper part): both by a dense triangular solve, not by the sweep code."""
+    m = I.kuhn_mesh(4, jitter=0.15, seed=5)
+    A = O.assemble(m, 1e-2, I.single_sine()).csr()
+    col = RB.colouring(A, 123)
+    perm = np.argsort(col, kind="stable")
+    Ad = A.toarray()[np.ix_(perm, perm)]
+    b = np.random.default_rng(0).standard_normal(A.shape[0])
+    x = RB.gs_sweep(A, b, np.zeros_like(b), col, True)
+    xl = sla.solve_triangular(np.tril(Ad), b[perm], lower=True)
+    np.testing.assert_allclose(x[perm], xl, rtol=1e-12, atol=1e-12 * np.abs(xl).max())
+    x0 = np.random.default_rng(1).standard_normal(A.shape[0])
+    xb = RB.gs_sweep(A, b, x0, col, False)
+    corr = sla.solve_triangular(np.triu(Ad), (b - A @ x0)[perm], lower=False)
+    np.testing.assert_allclose(xb[perm], x0[perm] + corr, rtol=1e-12, atol=1e-12 * np.abs(corr).max())
+
+
+def test_red_black_vcycle_is_the_two_grid_operator():
+    """With two levels the cycle is I - B A = (I - U^-1 A)(I - P A_c^-1 P^T A)
+    (I - L^-1 A), L = D + lower part, U = D + upper part in colour order
+    (the two-grid operator of Section 3.1 with m = 1 and the backward sweep
+    after the correction); B is symmetric positive definite; every coarse
+    operator satisfies v^T A_c w = (P v)^T A (P w)."""
+    m = I.kuhn_mesh(6, jitter=0.15, seed=6)
+    A = O.assemble(m, 1e-2, I.single_sine()).csr()
+    lv = RB.build_hierarchy(A, coarse_max=60, max_levels=2)
+    assert len(lv) == 2
+    n = A.shape[0]
+    B = np.array([RB.vcycle(lv, e) for e in np.eye(n)]).T
+    Ad = A.toarray()
+    perm = np.argsort(lv[0]["colour"], kind="stable")
+    Pm = np.eye(n)[perm]                     # Pm @ v reorders v by colour
+    Ap = Pm @ Ad @ Pm.T
+    Lo = Pm.T @ np.tril(Ap) @ Pm
+    Up = Pm.T @ np.triu(Ap) @ Pm
+    P = lv[0]["P"].toarray()
+    Ac = P.T @ Ad @ P
+    E = (np.eye(n) - np.linalg.solve(Up, Ad)) @ (np.eye(n) - P @ np.linalg.solve(Ac, P.T @ Ad)) @ \
+        (np.eye(n) - np.linalg.solve(Lo, Ad))
+    np.testing.assert_allclose(np.eye(n) - B @ Ad, E, atol=1e-10)
+    np.testing.assert_allclose(B, B.T, atol=1e-12 * np.abs(B).max())
+    assert np.linalg.eigvalsh((B + B.T) / 2).min() > 0
+    lv3 = RB.build_hierarchy(O.assemble(I.kuhn_mesh(9), 1.0, I.single_sine()).csr(), coarse_max=20)
+    rng = np.random.default_rng(7)
+    for a, b in zip(lv3[:-1], lv3[1:]):
+        v, w = rng.standard_normal((2, b["A"].shape[0]))
+        lhs = v @ (b["A"] @ w)
+        rhs = (a["P"] @ v) @ (a["A"] @ (a["P"] @ w))
+        assert abs(lhs - rhs) <= 1e-12 * abs(rhs) + 1e-14
+        assert 2 * b["A"].shape[0] <= a["A"].shape[0]

@@ -379,6 +379,46 @@ int fe_recover(ocp_ctx *ctx, const ocp_system *sys, const ocp_target *target, co
  * OOM, HIP. */
 int fe_error_norms(ocp_ctx *ctx, const ocp_system *sys, const ocp_target *target, const double *u, double *out);
 
+/* Residual error indicator of a P1 state u (device [n_vertices]) for the
+ * adaptive refinement of Sections 4.2 and 4.3 (the paper names a
+ * residual-based indicator; this is the robust one for reaction-diffusion
+ * equations): per tetrahedron T of the system's mesh
+ *   eta2[T] = a_T^2 ||ubar - u||^2_T
+ *           + 1/2 sum over interior faces F of T of rho^(-1/2) a_F |F| (rho [grad u . n_F])^2,
+ *   a_S = min(1, h_S / sqrt(rho)), h_S the longest edge of S,
+ * the first term by the 4-point rule of the load vector.  eta2 is device
+ * [n_tets], caller-owned.  Errors: INVALID_ARG, OOM, HIP. */
+int fe_error_indicator(ocp_ctx *ctx, const ocp_system *sys, const ocp_target *target, const double *u,
+                       double *eta2);
+
+/* --------------------------------------------------- adaptive refinement */
+/* A tetrahedral mesh refined by bisection in host memory (Sections 4.2, 4.3:
+ * meshes refined adaptively by a residual-based indicator).  Tetrahedron
+ * (x0, x1, x2, x3) with tag d is bisected at the midpoint of edge (x0, x_d)
+ * into (x0..x_{d-1}, z, x_{d+1}..x3) and (x1..x_d, z, x_{d+1}..x3), tag d-1
+ * (3 after 1); every tetrahedron that has a bisected edge is bisected in
+ * turn until none has (conforming result).  The initial tetrahedra start
+ * with tag 3 and must list their vertices along lattice paths as the Kuhn
+ * split does (cube corner, +e_i, +e_i+e_j, opposite corner); other meshes
+ * may not stay conforming.  All arrays are host memory.
+ *   create  copies the mesh (n_vertices, xyz [n][3], n_tets, tets [n][4]).
+ *   refine  marks by Doerfler's bulk criterion (largest eta2 first until
+ *           their sum reaches theta * total, 0 < theta <= 1; eta2 host
+ *           [n_tets] of the current mesh), bisects; *n_marked (may be NULL)
+ *           receives the number marked.
+ *   sizes / get  the current mesh: xyz [n_vertices][3], tets [n_tets][4]
+ *           and dirichlet [n_vertices] (1 on faces of one tetrahedron only);
+ *           any output pointer may be NULL.
+ * Errors: INVALID_ARG, BAD_MESH (index out of range; a closure that does
+ * not end), UNSUPPORTED (more than 2^31 entries). */
+typedef struct ocp_refiner ocp_refiner;
+int ocp_refiner_create(const double *xyz, int32_t n_vertices, const int32_t *tets, int32_t n_tets,
+                       ocp_refiner **out);
+void ocp_refiner_destroy(ocp_refiner *r);
+int ocp_refiner_refine(ocp_refiner *r, const double *eta2, double theta, int32_t *n_marked);
+int ocp_refiner_sizes(const ocp_refiner *r, int32_t *n_vertices, int32_t *n_tets);
+int ocp_refiner_get(const ocp_refiner *r, double *xyz, int32_t *tets, uint8_t *dirichlet);
+
 /* ------------------------------------------------------- kernel timing */
 #define OCP_KERNEL_CG_SPMV 0      /* q = A p with p.q, FP64 CSR (the CG iteration's SpMV) */
 #define OCP_KERNEL_VC_PRE0 1      /* fine-level first smoothing step fused with the residual */

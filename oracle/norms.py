@@ -154,3 +154,62 @@ def box_indicator_state_on_grid(N: int, rho: float, K: int = 63, lo: float = 0.2
     x = np.arange(N + 1) / N
     S = np.sin(np.pi * ks[:, None] * x[None, :])       # [K, N+1]
     return np.einsum("abc,ai,bj,ck->ijk", C, S, S, S, optimize=True)
+
+
+def error_indicator(mesh, u_vertices: np.ndarray, target, rho: float, nodal_target=None) -> np.ndarray:
+    """Residual error indicator per tetrahedron for -rho Lap u + u = ubar and a
+    P1 state u_h (the robust weighting of Verfuerth's estimators for
+    reaction-diffusion problems):
+        eta_T^2 = a_T^2 ||ubar - u_h||^2_T
+                + 1/2 sum over interior faces F of T of rho^(-1/2) a_F |F| (rho [grad u_h . n_F])^2,
+        a_S = min(1, h_S / sqrt(rho)), h_S the longest edge of S.
+    ||ubar - u_h||^2_T by the 4-point degree-2 rule (barycentric (a, b, b, b)
+    and permutations, a = (5 + 3 sqrt5)/20, b = (5 - sqrt5)/20, weights
+    |T|/4); faces with one tetrahedron lie on the boundary and add nothing."""
+    from .dense import eval_target
+    xyz = np.asarray(mesh.xyz, dtype=np.float64)
+    tets = np.asarray(mesh.tets, dtype=np.int64)
+    u = np.asarray(u_vertices, dtype=np.float64)
+    p = xyz[tets]                                              # [nt,4,3]
+    B = np.transpose(p[:, 1:, :] - p[:, :1, :], (0, 2, 1))     # columns: edges from vertex 0
+    vol = np.abs(np.linalg.det(B)) / 6.0
+    Gi = np.linalg.inv(B)                                      # rows: grad lambda_1..3
+    uh = u[tets]
+    grad = np.einsum("ea,ead->ed", uh[:, 1:] - uh[:, :1], Gi)
+    edges = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+    h = np.max([np.linalg.norm(p[:, a] - p[:, b], axis=1) for a, b in edges], axis=0)
+    a_ = (5.0 + 3.0 * np.sqrt(5.0)) / 20.0
+    b_ = (5.0 - np.sqrt(5.0)) / 20.0
+    r2 = np.zeros(len(tets))
+    for q in range(4):
+        lam = np.full(4, b_)
+        lam[q] = a_
+        xq = np.einsum("a,ead->ed", lam, p)
+        uq = uh @ lam
+        if nodal_target is not None:
+            tq = np.asarray(nodal_target)[tets] @ lam
+        else:
+            tq = eval_target(target, xq)
+        r2 += (tq - uq) ** 2
+    r2 *= vol / 4.0
+    srho = np.sqrt(rho)
+    eta = np.minimum(1.0, h / srho) ** 2 * r2
+    # interior faces: the same sorted vertex triple in two tetrahedra
+    faces = np.concatenate([np.sort(np.delete(tets, a, axis=1), axis=1) for a in range(4)])
+    owner = np.tile(np.arange(len(tets)), 4)
+    order = np.lexsort(faces.T[::-1])
+    fs, ow = faces[order], owner[order]
+    same = np.all(fs[1:] == fs[:-1], axis=1)
+    i1 = np.flatnonzero(same)
+    t1, t2, f = ow[i1], ow[i1 + 1], fs[i1]
+    e1 = xyz[f[:, 1]] - xyz[f[:, 0]]
+    e2 = xyz[f[:, 2]] - xyz[f[:, 0]]
+    nrm = np.cross(e1, e2)
+    nn = np.linalg.norm(nrm, axis=1)
+    area = 0.5 * nn
+    hf = np.max([np.linalg.norm(e1, axis=1), np.linalg.norm(e2, axis=1), np.linalg.norm(e2 - e1, axis=1)], axis=0)
+    jump = rho * np.sum((grad[t1] - grad[t2]) * nrm, axis=1) / nn
+    c = 0.5 / srho * np.minimum(1.0, hf / srho) * area * jump ** 2
+    np.add.at(eta, t1, c)
+    np.add.at(eta, t2, c)
+    return eta

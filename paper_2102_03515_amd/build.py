@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libocpamg.so")
-SOURCES = ["runtime.hip", "assemble.hip", "sell.hip", "pcg.hip", "vcycle.hip", "amg_setup.hip", "multi.hip", "small.hip", "recover.hip"]
+SOURCES = ["runtime.hip", "assemble.hip", "sell.hip", "pcg.hip", "vcycle.hip", "amg_setup.hip", "multi.hip", "small.hip", "recover.hip", "refine.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -116,6 +116,12 @@ _SIGS = {
     "fe_recover": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(_Target), C.c_void_p, C.c_void_p, C.c_void_p]),
     "fe_error_norms": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(_Target), C.c_void_p,
                                  C.POINTER(C.c_double)]),
+    "fe_error_indicator": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(_Target), C.c_void_p, C.c_void_p]),
+    "ocp_refiner_create": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    "ocp_refiner_destroy": (None, [C.c_void_p]),
+    "ocp_refiner_refine": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.POINTER(C.c_int32)]),
+    "ocp_refiner_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "ocp_refiner_get": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ocp_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "ocp_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
 }
@@ -407,6 +413,17 @@ class System:
         ctx.check(lib().fe_recover(ctx.handle, self.handle, C.byref(t), _ptr(u), _ptr(p), _ptr(z)))
         return p, z
 
+    def error_indicator(self, target, u, ctx: Optional["Context"] = None):
+        """Squared residual error indicator per tetrahedron (torch, device)."""
+        torch = _torch()
+        ctx = ctx or self.ctx
+        nt = self.mesh.n_tets
+        eta2 = torch.empty(nt, dtype=torch.float64, device="cuda")
+        keep = []
+        t = target_struct(target, keep)
+        ctx.check(lib().fe_error_indicator(ctx.handle, self.handle, C.byref(t), _ptr(u), _ptr(eta2)))
+        return eta2
+
     def error_norms(self, target, u, ctx: Optional["Context"] = None):
         """(||u_rho - u||_L2, ||grad(u_rho - u)||_L2, ||ubar - u||_L2); the
         first two are NaN for targets without a closed-form solution."""
@@ -420,6 +437,55 @@ class System:
     def close(self):
         if getattr(self, "handle", None):
             lib().ocp_system_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Refiner:
+    """Host mesh under bisection refinement (ocp_refiner_*)."""
+
+    def __init__(self, xyz, tets):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        h = C.c_void_p()
+        rc = lib().ocp_refiner_create(xyz.ctypes.data, int(xyz.shape[0]), tets.ctypes.data, int(tets.shape[0]),
+                                      C.byref(h))
+        if rc != OK:
+            raise OcpError(rc, "refiner creation failed")
+        self.handle = h
+
+    def refine(self, eta2, theta: float = 0.5) -> int:
+        """Doerfler-mark by the squared indicators (host, one per tetrahedron)
+        and bisect; returns the number marked."""
+        e = np.ascontiguousarray(eta2, dtype=np.float64)
+        m = C.c_int32()
+        rc = lib().ocp_refiner_refine(self.handle, e.ctypes.data, float(theta), C.byref(m))
+        if rc != OK:
+            raise OcpError(rc, "refinement failed")
+        return int(m.value)
+
+    def get(self):
+        """(xyz [nv,3], tets [nt,4], dirichlet [nv]) of the current mesh."""
+        nv, nt = C.c_int32(), C.c_int32()
+        rc = lib().ocp_refiner_sizes(self.handle, C.byref(nv), C.byref(nt))
+        if rc != OK:
+            raise OcpError(rc, "refiner sizes")
+        xyz = np.empty((nv.value, 3), dtype=np.float64)
+        tets = np.empty((nt.value, 4), dtype=np.int32)
+        d = np.empty(nv.value, dtype=np.uint8)
+        rc = lib().ocp_refiner_get(self.handle, xyz.ctypes.data, tets.ctypes.data, d.ctypes.data)
+        if rc != OK:
+            raise OcpError(rc, "refiner get")
+        return xyz, tets, d
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ocp_refiner_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -197,6 +197,152 @@ __global__ void __launch_bounds__(64) k_error_norms_fin(unsigned nb, const doubl
     out[threadIdx.x] = s;
 }
 
+// Residual-based error indicator of the reaction-diffusion equation (5) for
+// a P1 state u_h, per tetrahedron tau (the robust weighting of Verfuerth's
+// estimators for singularly perturbed reaction-diffusion problems):
+//   eta_tau^2 = a_tau^2 ||ubar - u_h||^2_tau
+//             + 1/2 sum_{interior faces F of tau} rho^{-1/2} a_F ||[rho grad u_h . n_F]||^2_F,
+//   a_S = min(1, h_S / sqrt(rho)),  h_S the longest edge of S.
+// The element residual ubar + rho Lap u_h - u_h is ubar - u_h for P1; its
+// square is integrated by the 4-point rule of the load vector.  The normal
+// flux jump is constant on a face.  A face's neighbour is the other
+// tetrahedron in the incidence list of one of its vertices that holds the
+// other two; a face without one lies on the boundary and adds nothing.
+__device__ void tet_grad(const double P[4][3], const double uh[4], double g[3], double &vol, double &hmax) {
+    double B[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) B[d][c] = P[c + 1][d] - P[0][d];
+    const double C00 = B[1][1] * B[2][2] - B[1][2] * B[2][1];
+    const double C01 = B[1][2] * B[2][0] - B[1][0] * B[2][2];
+    const double C02 = B[1][0] * B[2][1] - B[1][1] * B[2][0];
+    const double det = B[0][0] * C00 + B[0][1] * C01 + B[0][2] * C02;
+    const double id = 1.0 / det;
+    double Gi[3][3];
+    Gi[0][0] = C00 * id;
+    Gi[0][1] = (B[0][2] * B[2][1] - B[0][1] * B[2][2]) * id;
+    Gi[0][2] = (B[0][1] * B[1][2] - B[0][2] * B[1][1]) * id;
+    Gi[1][0] = C01 * id;
+    Gi[1][1] = (B[0][0] * B[2][2] - B[0][2] * B[2][0]) * id;
+    Gi[1][2] = (B[0][2] * B[1][0] - B[0][0] * B[1][2]) * id;
+    Gi[2][0] = C02 * id;
+    Gi[2][1] = (B[0][1] * B[2][0] - B[0][0] * B[2][1]) * id;
+    Gi[2][2] = (B[0][0] * B[1][1] - B[0][1] * B[1][0]) * id;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        g[d] = (uh[1] - uh[0]) * Gi[0][d] + (uh[2] - uh[0]) * Gi[1][d] + (uh[3] - uh[0]) * Gi[2][d];
+    vol = fabs(det) / 6.0;
+    hmax = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a + 1; b < 4; ++b) {
+            const double dx = P[a][0] - P[b][0], dy = P[a][1] - P[b][1], dz = P[a][2] - P[b][2];
+            hmax = fmax(hmax, sqrt(dx * dx + dy * dy + dz * dz));
+        }
+}
+
+__global__ void __launch_bounds__(256) k_error_indicator(int64_t nt, const int4 *__restrict__ tets,
+                                                          const double *__restrict__ xyz,
+                                                          const double *__restrict__ u, RecTarget t, double rho,
+                                                          const int32_t *__restrict__ inc_ptr,
+                                                          const int32_t *__restrict__ inc, double *__restrict__ eta2) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= nt) return;
+    const int4 tv = tets[e];
+    const int vid[4] = {tv.x, tv.y, tv.z, tv.w};
+    double P[4][3], uh[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) P[a][d] = xyz[3 * (int64_t)vid[a] + d];
+        uh[a] = u[vid[a]];
+    }
+    double g[3], vol, h;
+    tet_grad(P, uh, g, vol, h);
+    const double srho = sqrt(rho);
+    // element term by the 4-point degree-2 rule (barycentric (a, b, b, b) and permutations)
+    const double qa = 0.5854101966249685;   // (5 + 3 sqrt5) / 20
+    const double qb = 0.1381966011250105;   // (5 - sqrt5) / 20
+    double r2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double x[3], uq = 0.0, tq = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) s += (a == q ? qa : qb) * P[a][d];
+            x[d] = s;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) uq += (a == q ? qa : qb) * uh[a];
+        if (t.kind == OCP_TARGET_NODAL) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) tq += (a == q ? qa : qb) * t.nodal[vid[a]];
+        } else {
+            tq = target_at(t, x);
+        }
+        r2 += (tq - uq) * (tq - uq);
+    }
+    r2 *= vol / 4.0;
+    const double at = fmin(1.0, h / srho);
+    double eta = at * at * r2;
+    // faces
+#pragma unroll 1
+    for (int a = 0; a < 4; ++a) {
+        int f[3], p = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if (b != a) f[p++] = vid[b];
+        int64_t nb = -1;
+        for (int q = inc_ptr[f[0]]; q < inc_ptr[f[0] + 1]; ++q) {
+            const int64_t e2 = inc[q] >> 2;
+            if (e2 == e) continue;
+            const int4 w = tets[e2];
+            const bool h1 = w.x == f[1] || w.y == f[1] || w.z == f[1] || w.w == f[1];
+            const bool h2 = w.x == f[2] || w.y == f[2] || w.z == f[2] || w.w == f[2];
+            if (h1 && h2) {
+                nb = e2;
+                break;
+            }
+        }
+        if (nb < 0) continue;   // boundary face
+        const int4 w = tets[nb];
+        const int wid[4] = {w.x, w.y, w.z, w.w};
+        double Q[4][3], uw[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Q[b][d] = xyz[3 * (int64_t)wid[b] + d];
+            uw[b] = u[wid[b]];
+        }
+        double g2[3], vol2, h2;
+        tet_grad(Q, uw, g2, vol2, h2);
+        // face normal, area and diameter
+        double e1[3], e2v[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            e1[d] = xyz[3 * (int64_t)f[1] + d] - xyz[3 * (int64_t)f[0] + d];
+            e2v[d] = xyz[3 * (int64_t)f[2] + d] - xyz[3 * (int64_t)f[0] + d];
+        }
+        const double nx = e1[1] * e2v[2] - e1[2] * e2v[1];
+        const double ny = e1[2] * e2v[0] - e1[0] * e2v[2];
+        const double nz = e1[0] * e2v[1] - e1[1] * e2v[0];
+        const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+        const double area = 0.5 * nn;
+        const double e3[3] = {e2v[0] - e1[0], e2v[1] - e1[1], e2v[2] - e1[2]};
+        const double hf = fmax(sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]),
+                               fmax(sqrt(e2v[0] * e2v[0] + e2v[1] * e2v[1] + e2v[2] * e2v[2]),
+                                    sqrt(e3[0] * e3[0] + e3[1] * e3[1] + e3[2] * e3[2])));
+        const double jump = rho * ((g[0] - g2[0]) * nx + (g[1] - g2[1]) * ny + (g[2] - g2[2]) * nz) / nn;
+        const double af = fmin(1.0, hf / srho);
+        eta += 0.5 / srho * af * area * jump * jump;
+    }
+    eta2[e] = eta;
+}
+
 // n-point Gauss-Legendre nodes and weights on [0, 1] (Newton's method on the
 // three-term recurrence of the Legendre polynomials)
 void gauss_legendre01(int n, double *x, double *w) {
@@ -311,6 +457,21 @@ extern "C" int fe_recover(ocp_ctx *ctx, const ocp_system *sys, const ocp_target 
         RecUpload up;
         if (z) upload_rec_target(ctx, target, sys->nv, sys->rho, up);
         k_recover<<<grid_for(sys->nv, 256), 256, 0, ctx->stream>>>(sys->nv, sys->rho, sys->mesh.xyz, u, up.dev, p, z);
+        OCP_LAUNCH_CHECK();
+        sync(ctx);   // the uploaded modes are released on return
+    });
+}
+
+extern "C" int fe_error_indicator(ocp_ctx *ctx, const ocp_system *sys, const ocp_target *target, const double *u,
+                                  double *eta2) {
+    if (!ctx) return OCP_ERR_INVALID_ARG;
+    return run_guarded(ctx, [&] {
+        if (!sys || !u || !eta2) fail(OCP_ERR_INVALID_ARG, "system, u and eta2 must not be NULL");
+        RecUpload up;
+        upload_rec_target(ctx, target, sys->nv, sys->rho, up);
+        k_error_indicator<<<grid_for(sys->nt, 256), 256, 0, ctx->stream>>>(
+            sys->nt, reinterpret_cast<const int4 *>(sys->mesh.tets), sys->mesh.xyz, u, up.dev, sys->rho,
+            sys->inc_ptr.get(), sys->inc.get(), eta2);
         OCP_LAUNCH_CHECK();
         sync(ctx);   // the uploaded modes are released on return
     });

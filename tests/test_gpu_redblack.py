@@ -141,7 +141,8 @@ def test_redblack_iterations_against_table4(P, ctx):
             u, info, rc = P.pcg_solve(ctx, s, h, rtol=1e-8, maxit=300, stop=P.capi.STOP_PRECOND)
             assert rc == 0, info.as_dict()
             its.append(info.iterations)
+            levels = h.n_levels
             h.close()
             s.close()
-        print(f"    rho={rho:g}: iterations {its} (Table 4: {paper}) levels up to {h.n_levels}", flush=True)
+        print(f"    rho={rho:g}: iterations {its} (Table 4: {paper}), {levels} levels at h = 1/128", flush=True)
         assert max(its) <= 40

@@ -349,3 +349,32 @@ def test_box_series_reference():
     assert g[8, 8, 8] == pytest.approx(1.0, abs=0.03)      # box centre (the partial sums converge like 1/K)
     assert abs(g[2, 8, 8]) < 0.02                           # outside the box
     assert g[4, 8, 8] == pytest.approx(0.5, abs=0.03)      # on a face: the series gives the mean
+
+
+def test_error_indicator_closed_forms():
+    """The indicator's two terms against closed forms on the unjittered Kuhn
+    mesh (N = 4, the box faces on grid planes):
+      * u_h = 0 and the box target with h >= sqrt(rho): no flux jump, and the
+        element terms add up to the box volume 1/8 (each tetrahedron lies
+        inside or outside the box);
+      * u_h = the interpolant of |x - 1/2| with that interpolant as a P1
+        target: no element residual; the normal flux jumps by 2 rho across
+        the plane x = 1/2 only, whose faces (area 1 in total, longest edge
+        h sqrt2) give 4 rho^(3/2) min(1, h sqrt2 / sqrt(rho))."""
+    m = I.kuhn_mesh(4)
+    h = 0.25
+    rho = 1e-3
+    eta = norms.error_indicator(m, np.zeros(m.n_vertices), I.box_indicator(), rho)
+    assert eta.sum() == pytest.approx(0.125, rel=1e-13)
+    v = np.abs(m.xyz[:, 0] - 0.5)
+    for rho in (1e-3, 1.0):
+        eta = norms.error_indicator(m, v, None, rho, nodal_target=v)
+        want = 4 * rho ** 1.5 * min(1.0, h * np.sqrt(2.0) / np.sqrt(rho))
+        assert eta.sum() == pytest.approx(want, rel=1e-12)
+        # only tetrahedra touching the plane x = 1/2 carry a jump
+        xs = m.xyz[m.tets][:, :, 0]
+        touching = np.sum(np.abs(xs - 0.5) < 1e-14, axis=1) == 3
+        assert np.all(eta[~touching] == 0.0)
+    # a linear state and target: zero up to rounding
+    lin = 0.3 + m.xyz @ np.array([1.0, -2.0, 0.5])
+    assert norms.error_indicator(m, lin, None, 1e-2, nodal_target=lin).max() < 1e-26

@@ -279,6 +279,26 @@ typedef struct {
 int pcg_solve(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, const double *f,
               double *u, double rtol, int32_t maxit, int32_t flags, ocp_solve_info *info);
 
+/* pcg_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same solve, same arguments, same kernels and the same bits as
+ * pcg_solve, with every work vector (CG vectors, V-cycle vectors, device
+ * scalars, reduction partials) carved from one fixed scratch array of
+ * OCP_NOALLOC_SCRATCH_BYTES that the library holds per GPU from its first use
+ * on that GPU until the process ends.  The call makes no device allocation
+ * or free (nor does any allocator callback run).  The caller still passes f
+ * and u.  A solve whose work memory exceeds the scratch size (about 80-110
+ * bytes per unknown: n up to roughly 6e5 with an FP64 hierarchy, 8e5 mixed)
+ * is refused with OCP_ERR_UNSUPPORTED before any work is enqueued.  Every
+ * call on one GPU shares that GPU's scratch array and leaves its contents
+ * behind: calls that overlap on one GPU (several contexts, streams or host
+ * threads at once) race and must be serialized by the caller.  Kernel
+ * timing (ocp_profile_enable) is not recorded during the call.  Returns as
+ * pcg_solve. */
+#define OCP_NOALLOC_SCRATCH_BYTES (64u << 20)
+int pcg_solve_noalloc(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, const double *f,
+                      double *u, double rtol, int32_t maxit, int32_t flags, ocp_solve_info *info);
+
 /* Block PCG for k right-hand sides that share A and the hierarchy (the PCG
  * of Section 4 run as k independent recurrences in one pass over the
  * matrix per iteration).  Every column has its own alpha, beta and stop

@@ -103,6 +103,8 @@ _SIGS = {
     "amg_vcycle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pcg_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                             C.c_int32, C.c_int32, C.POINTER(SolveInfo)]),
+    "pcg_solve_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                    C.c_int32, C.c_int32, C.POINTER(SolveInfo)]),
     "pcg_solve_multi": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                   C.c_double, C.c_int32, C.c_int32, C.POINTER(SolveInfo)]),
     "pcg_solve_batch": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
@@ -199,7 +201,9 @@ def _ptr(t) -> Optional[int]:
 class Context:
     """Library context bound to a torch stream and torch's caching allocator."""
 
-    def __init__(self, stream=None, torch_allocator: bool = True):
+    def __init__(self, stream=None, torch_allocator: bool = True, on_alloc=None):
+        """on_alloc: optional callable(nbytes) run on every device allocation
+        the library requests through this context (tests count them)."""
         torch = _torch()
         L = lib()
         self.device = torch.cuda.current_device()
@@ -209,6 +213,8 @@ class Context:
             dev, st = self.device, self.stream
 
             def _alloc(nbytes, user):
+                if on_alloc is not None:
+                    on_alloc(int(nbytes))
                 try:
                     return torch.cuda.caching_allocator_alloc(int(nbytes), dev, st)
                 except Exception:
@@ -595,6 +601,23 @@ def pcg_solve(ctx: Context, system: System, hierarchy: Optional[Hierarchy] = Non
                          _ptr(f), _ptr(u), float(rtol), int(maxit), flags, C.byref(info))
     ok = (OK,) if raise_on_maxit else (OK, MAXIT)
     ctx.check(rc, ok=ok)
+    return u, info, rc
+
+
+def pcg_solve_noalloc(ctx: Context, system: System, hierarchy: Optional[Hierarchy] = None, f=None, u=None,
+                      rtol: float = 1e-8, maxit: int = 500, stop: int = STOP_L2, flexible: bool = False):
+    """pcg_solve with its work memory carved from the library's fixed scratch
+    region (no device allocation in the call).  u must be given (or is
+    allocated here, before the call).  Returns (u, SolveInfo, status)."""
+    torch = _torch()
+    nv = system.view().n_vertices
+    if u is None:
+        u = torch.empty(nv, dtype=torch.float64, device="cuda")
+    info = SolveInfo()
+    flags = int(stop) | (FLEXIBLE if flexible else 0)
+    rc = lib().pcg_solve_noalloc(ctx.handle, system.handle, hierarchy.handle if hierarchy is not None else None,
+                                 _ptr(f), _ptr(u), float(rtol), int(maxit), flags, C.byref(info))
+    ctx.check(rc, ok=(OK, MAXIT))
     return u, info, rc
 
 

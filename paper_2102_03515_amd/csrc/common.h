@@ -72,6 +72,10 @@ struct ocp_ctx {
     void *pinned = nullptr;             // small pinned host staging buffer (4 KiB)
     int32_t *dev_flag = nullptr;        // general device error/overflow flag
     bool active_solve = false;          // a step-API solve holds the CG scalars
+    // pcg_solve_noalloc: while set, device buffers are carved in order from
+    // [bump_base, bump_base + bump_cap) instead of coming from the allocator
+    char *bump_base = nullptr;
+    size_t bump_cap = 0, bump_off = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // live kernel timing (ocp_profile_enable): event pairs around selected
     // launches, resolved after each solve
@@ -89,6 +93,10 @@ namespace ocp {
 // --------------------------------------------------------------- allocation
 void *dev_alloc(ocp_ctx *ctx, size_t bytes);
 void dev_free(ocp_ctx *ctx, void *p);
+// Scratch region of the allocation-free solve on the context's device (the
+// library's fixed-size device array, looked up at context creation).
+char *scratch_region(const ocp_ctx *ctx);
+constexpr size_t kScratchBytes = size_t(64) << 20;
 constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Owning device buffer allocated through the context's allocator.

@@ -308,6 +308,7 @@ struct SolveState {
     const double *f = nullptr;
     const double *dinv = nullptr;
     DevBuf<double> x, r, p, q, z, z2;
+    DevBuf<double> own_dinv;   // Jacobi diagonal of an allocation-free solve (not published)
     DevBuf<char> y0;         // level 0's first smoothing step of r (hierarchies of 2+ levels)
     bool flexible = false;   // Polak-Ribiere beta with the previous z (AMG only)
     int zsel = 0;            // which of z / z2 receives the next preconditioned residual
@@ -356,7 +357,19 @@ static void solve_begin(SolveState &S, ocp_ctx *ctx, ocp_system *sys, const ocp_
     S.flexible = h && (flags & OCP_FLEXIBLE);
     if (S.flexible) S.z2.reset(ctx, n);
     S.zsel = 0;
-    S.dinv = h ? nullptr : system_dinv(ctx, sys);
+    if (h) {
+        S.dinv = nullptr;
+    } else if (ctx->bump_base && !sys->dinv_ready.load(std::memory_order_acquire)) {
+        // allocation-free solve before any Jacobi solve built the system's
+        // diagonal: a private copy in the scratch region
+        S.own_dinv.reset(ctx, n);
+        k_diag_inv<<<grid_for(n, 256), 256, 0, ctx->stream>>>(n, sys->row_ptr.get(), sys->col.get(), sys->val.get(),
+                                                               S.own_dinv.get());
+        OCP_LAUNCH_CHECK();
+        S.dinv = S.own_dinv.get();
+    } else {
+        S.dinv = system_dinv(ctx, sys);
+    }
     S.cgbuf.reset(ctx, 1);
     S.partbuf.reset(ctx, (size_t)4 * kRedBlocks);
     S.cg = S.cgbuf.get();
@@ -718,6 +731,70 @@ extern "C" int pcg_solve(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarch
         if (!(rtol > 0.0) || !std::isfinite(rtol)) fail(OCP_ERR_INVALID_ARG, "rtol must be positive");
         if (maxit < 1) fail(OCP_ERR_INVALID_ARG, "maxit must be >= 1");
         check_hierarchy(h, sys);
+        solve(ctx, const_cast<ocp_system *>(sys), h, f, u, rtol, maxit, flags, info, &status);
+    });
+    if (rc != OCP_OK) {
+        if (info) info->status = rc;
+        return rc;
+    }
+    if (status == OCP_ERR_BREAKDOWN) ctx->last_error = "CG breakdown (p^T A p <= 0, r^T z <= 0 or non-finite)";
+    return status;
+}
+
+// Scratch bytes pcg_solve_noalloc carves for a solve: exactly the buffers
+// solve_begin takes (each rounded up to 256 bytes, as the carving does).
+static size_t noalloc_bytes(const ocp_system *sys, const ocp_hierarchy *h, int32_t flags) {
+    const size_t n = (size_t)sys->n;
+    size_t t = 5 * align256(sizeof(double) * n);                                  // x, r, p, q, z
+    if (h && (flags & OCP_FLEXIBLE)) t += align256(sizeof(double) * n);          // z2
+    if (!h && !sys->dinv_ready.load(std::memory_order_acquire)) t += align256(sizeof(double) * n);
+    t += align256(sizeof(CgScalars)) + align256(sizeof(double) * 4 * kRedBlocks);
+    if (h) {
+        const size_t vs = h->params.precision == OCP_PREC_MIXED ? sizeof(float) : sizeof(double);
+        const size_t L = h->levels.size();
+        for (size_t l = 0; l < L; ++l) {
+            const size_t b = align256((size_t)h->levels[l]->n * vs);
+            if (l > 0) t += 2 * b;       // vb, vx
+            if (l + 1 < L) t += 4 * b;   // vr, vxp, vx1, vx2
+        }
+        if (L > 1 && h->params.method == OCP_AMG_AGGREGATION) t += align256(n * vs);   // y0
+    }
+    return t;
+}
+
+extern "C" int pcg_solve_noalloc(ocp_ctx *ctx, const ocp_system *sys, const ocp_hierarchy *h, const double *f,
+                                 double *u, double rtol, int32_t maxit, int32_t flags, ocp_solve_info *info) {
+    if (!ctx) return OCP_ERR_INVALID_ARG;
+    int status = OCP_OK;
+    int rc = run_guarded(ctx, [&] {
+        if (!sys || !u) fail(OCP_ERR_INVALID_ARG, "system and u must not be NULL");
+        if (!(rtol > 0.0) || !std::isfinite(rtol)) fail(OCP_ERR_INVALID_ARG, "rtol must be positive");
+        if (maxit < 1) fail(OCP_ERR_INVALID_ARG, "maxit must be >= 1");
+        check_hierarchy(h, sys);
+        char *base = scratch_region(ctx);
+        if (!base) fail(OCP_ERR_HIP, "no scratch region on this context's device");
+        const size_t need = noalloc_bytes(sys, h, flags);
+        if (need > kScratchBytes)
+            fail(OCP_ERR_UNSUPPORTED, "pcg_solve_noalloc: this solve needs " + std::to_string(need) +
+                                          " bytes of work memory, more than the " +
+                                          std::to_string(kScratchBytes >> 20) + " MiB scratch region (use pcg_solve)");
+        // every device buffer of the solve is carved from the scratch region;
+        // kernel timing (which may create events) is off meanwhile
+        struct Carve {
+            ocp_ctx *c;
+            bool prof;
+            Carve(ocp_ctx *c_, char *b) : c(c_), prof(c_->profile) {
+                c->bump_base = b;
+                c->bump_cap = kScratchBytes;
+                c->bump_off = 0;
+                c->profile = false;
+            }
+            ~Carve() {
+                c->bump_base = nullptr;
+                c->bump_cap = c->bump_off = 0;
+                c->profile = prof;
+            }
+        } carve(ctx, base);
         solve(ctx, const_cast<ocp_system *>(sys), h, f, u, rtol, maxit, flags, info, &status);
     });
     if (rc != OCP_OK) {

@@ -1,6 +1,7 @@
 // Context, allocation and device primitives (scan, reductions) of ocpamg.
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 
 #include "common.h"
 
@@ -9,6 +10,15 @@ namespace ocp {
 void *dev_alloc(ocp_ctx *ctx, size_t bytes) {
     if (bytes == 0) return nullptr;
     void *p = nullptr;
+    if (ctx->bump_base) {
+        const size_t b = align256(bytes);
+        if (ctx->bump_off + b > ctx->bump_cap)
+            fail(OCP_ERR_UNSUPPORTED, "the solve needs more than the " + std::to_string(ctx->bump_cap >> 20) +
+                                          " MiB scratch region of pcg_solve_noalloc");
+        p = ctx->bump_base + ctx->bump_off;
+        ctx->bump_off += b;
+        return p;
+    }
     if (ctx->alloc) {
         p = ctx->alloc(bytes, ctx->user);
     } else {
@@ -21,6 +31,9 @@ void *dev_alloc(ocp_ctx *ctx, size_t bytes) {
 
 void dev_free(ocp_ctx *ctx, void *p) {
     if (!p) return;
+    if (ctx->bump_base && static_cast<char *>(p) >= ctx->bump_base &&
+        static_cast<char *>(p) < ctx->bump_base + ctx->bump_cap)
+        return;   // carved from the scratch region: nothing to release
     if (ctx->free_fn)
         ctx->free_fn(p, ctx->user);
     else
@@ -29,6 +42,35 @@ void dev_free(ocp_ctx *ctx, void *p) {
 
 void sync(ocp_ctx *ctx) { OCP_HIP(hipStreamSynchronize(ctx->stream)); }
 
+// ------------------------------------------------------- scratch region
+// Device memory of pcg_solve_noalloc: one fixed array per GPU, held from the
+// library's first use on that GPU until the process ends.  Host code never
+// passes `scratch` itself anywhere (in host code the name is a host-side
+// stand-in, not the device address): its device address is looked up once
+// per device, with that device current, when a context is created there, and
+// only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static void scratch_lookup(int device) {
+    if (device < 0 || device >= kMaxDevices) fail(OCP_ERR_UNSUPPORTED, "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return;
+    void *p = nullptr;
+    OCP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(OCP_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch region");
+    g_scratch_ptr[device] = static_cast<char *>(p);
+}
+
+char *scratch_region(const ocp_ctx *ctx) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return (ctx->device >= 0 && ctx->device < kMaxDevices) ? g_scratch_ptr[ctx->device] : nullptr;
+}
 
 void read_back(ocp_ctx *ctx, void *host, const void *dev, size_t bytes) {
     if (bytes > 4096) fail(OCP_ERR_INVALID_ARG, "read_back larger than the staging buffer");
@@ -333,6 +375,7 @@ extern "C" int ocp_ctx_create(void *stream, ocp_alloc_fn alloc, ocp_free_fn free
     ctx->user = user;
     int rc = guarded(ctx, [&] {
         OCP_HIP(hipGetDevice(&ctx->device));
+        scratch_lookup(ctx->device);   // the context's device is current here
         ctx->red_partials = static_cast<double *>(dev_alloc(ctx, sizeof(double) * kRedSlots * kRedBlocks));
         ctx->red_counters = static_cast<unsigned *>(dev_alloc(ctx, sizeof(unsigned) * 64));
         ctx->red_out = static_cast<double *>(dev_alloc(ctx, sizeof(double) * 64));

@@ -202,13 +202,13 @@ typedef struct {
     int32_t coarse_max;  /* stop coarsening at n <= coarse_max (dense solve there), <= 2048 */
     int32_t max_levels;  /* 1..16 */
     double theta;        /* strength threshold: |a_ij| >= theta sqrt(a_ii a_jj) */
-    double omega;        /* prolongator smoothing: omega/lambda_max(D^-1 A), 4/3 default */
+    double omega;        /* prolongator smoothing: omega/lambda_max(D^-1 A), 1.9 default */
     double cheb_ratio;   /* Chebyshev interval [lambda/cheb_ratio, lambda], lambda = Gershgorin bound */
     int32_t method;      /* OCP_AMG_AGGREGATION (default) or OCP_AMG_REDBLACK */
 } ocp_amg_params;
 
 /* Fill `p` with the defaults (smoothed aggregation, FP64, Chebyshev degree 2
- * on [lambda/10, lambda], coarse_max 512, 10 levels, theta 0, omega 4/3). */
+ * on [lambda/10, lambda], coarse_max 512, 10 levels, theta 0, omega 1.9). */
 void amg_default_params(ocp_amg_params *p);
 
 /* Build a smoothed-aggregation hierarchy for the system's A (Section 3.1:

@@ -179,7 +179,7 @@ def smoothed_prolongator(A: sp.csr_matrix, Pt: sp.csr_matrix, omega: float) -> s
     return structural_product(S, Pt)
 
 
-def build_hierarchy(A: sp.csr_matrix, theta: float = 0.0, omega: float = 4.0 / 3.0,
+def build_hierarchy(A: sp.csr_matrix, theta: float = 0.0, omega: float = 1.9,
                     coarse_max: int = 512, max_levels: int = 10):
     """Levels as dicts {A, agg, P, nc}; the last has only A."""
     levels = []

@@ -1944,7 +1944,7 @@ extern "C" void amg_default_params(ocp_amg_params *p) {
     p->coarse_max = 512;
     p->max_levels = 10;
     p->theta = 0.0;
-    p->omega = 4.0 / 3.0;
+    p->omega = 1.9;
     p->cheb_ratio = 10.0;
     p->method = OCP_AMG_AGGREGATION;
 }

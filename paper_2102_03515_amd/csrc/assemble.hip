@@ -1,18 +1,20 @@
 // Finite element assembly of A = rho*K + M and f = (int ubar phi_i) into CSR
 // (Section 2, system (linsys) and the entries K_ij, M_ij, f_i defined there).
 //
-// Row-owned, atomic-free on values: every tet writes one element record
-// (its vertex dofs, element matrix and element loads), and every interior
-// vertex owns its row and sums the records of its incident tetrahedra in
+// Row-owned, atomic-free on values: every interior vertex owns its row and
+// sums the element matrices and element loads of its incident tetrahedra in
 // ascending tet id.  The result is bitwise deterministic (and A bitwise
 // symmetric).
 //
 //   1. per tet: index/degeneracy checks, incidence counts   (int atomics)
 //   2. scan -> incidence pointers; fill; sort each list      (vertex -> tets)
 //   3. dof numbering of interior vertices (scan)
-//   4. per tet: element record; loads by the 4-point degree-2 rule
-//   5. symbolic rows: sorted union of the interior vertices of incident tets
-//   6. numeric rows: sum rho*K_e + M_e (and fe) over incident tets
+//   4. per tet: element loads by the 4-point degree-2 rule
+//   5. rows of at most 16 entries: one pass per row that recomputes the
+//      element matrix of every incident tet from its coordinates;
+//      otherwise per tet an element record (dofs, element matrix, loads),
+//      then symbolic rows (sorted union of the interior vertices of the
+//      incident tets) and numeric rows (sums of the records' entries)
 #include <cfloat>
 #include <climits>
 #include <cmath>
@@ -32,8 +34,10 @@ constexpr int kSineTable = 8;      // sin(k pi x) by recurrence for k <= 8
 // Barycentric gradients g[a] and signed determinant of the edge matrix of a
 // tetrahedron p[0..3].  lambda_{c+1}(x) = (B^{-1}(x - p0))_c with
 // B = [p1-p0, p2-p0, p3-p0], so grad lambda_{c+1} is row c of B^{-1} and
-// grad lambda_0 = -(sum of the others).
+// grad lambda_0 = -(sum of the others).  No multiply-add is fused here (nor
+// in elem_values): every kernel that inlines these computes the same bits.
 __device__ __forceinline__ double tet_gradients(const double p[4][3], double g[4][3]) {
+#pragma clang fp contract(off)
     double e[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -676,84 +680,124 @@ __global__ void __launch_bounds__(256) k_row_numeric(
     if (sc.val) sell_store_row<MAXS>(sc, s, valid, i, len, cols, acc);
 }
 
-// Rows with at most kFuseW entries in one pass over their incident tets:
-// a column gets a register slot at its first appearance (the dofs come with
-// each element record) and values are accumulated as in k_row_numeric (same
-// order, so the same bits); the row is then sorted by column and written to
-// its kFuseW-wide padded slot with its length.  A longer row sets bit 64 of
-// *flag (the caller then assembles in separate symbolic and numeric passes).
+// Rows with at most kFuseW entries in one pass over their incident tets,
+// with no element records: the row's thread recomputes, for each incident
+// tet, row a of its element matrix from the vertex coordinates (a = the row's
+// vertex in the tet; entry (a,b) = rho |tau| grad phi_a . grad phi_b +
+// |tau|/20 (1 + delta_ab), the products and sums in the order elem_values
+// uses, so the same bits), and takes the element load from fe (4 per tet).
+// The diagonal is summed in a register; every other column gets a slot at
+// its first appearance (keys in registers, sums in thread-private LDS), and
+// each slot sums its values in incidence order as k_row_numeric does (so
+// entry (i,j) and entry (j,i) add the same values in the same order).  The
+// row is then sorted by column and written to its kFuseW-wide padded slot
+// with its length.  A longer row sets bit 64 of *flag (the caller then
+// assembles in separate symbolic and numeric passes).
+// Reading a 128-byte element record per incident tet moved about four times
+// the records' size through the L2 (each record is read by the 4 rows of its
+// vertices); the tets, coordinates, dofs and loads read here are shared by
+// neighbouring rows.
 constexpr int kFuseW = 16;
-__global__ void __launch_bounds__(256) k_row_fused(int32_t n, const int32_t *__restrict__ vertex_of_dof,
-                                                   const int32_t *__restrict__ inc_ptr,
-                                                   const int32_t *__restrict__ inc, const double *__restrict__ rec,
-                                                   int32_t *__restrict__ rlen, int32_t *__restrict__ pcol,
-                                                   double *__restrict__ pval, double *__restrict__ f,
-                                                   int32_t *flag) {
+constexpr int kFuseBlock = 256;
+__global__ void __launch_bounds__(kFuseBlock) k_row_fused(int32_t n, double rho,
+                                                          const int32_t *__restrict__ vertex_of_dof,
+                                                          const int32_t *__restrict__ dof_of_vertex,
+                                                          const int32_t *__restrict__ inc_ptr,
+                                                          const int32_t *__restrict__ inc,
+                                                          const int4 *__restrict__ tets,
+                                                          const double *__restrict__ xyz,
+                                                          const double *__restrict__ fe, int32_t *__restrict__ rlen,
+                                                          int32_t *__restrict__ pcol, double *__restrict__ pval,
+                                                          double *__restrict__ f, int32_t *flag) {
 #pragma clang fp contract(off)
     constexpr int S = kFuseW;
-    const int i = blockIdx.x * 256 + (int)threadIdx.x;
+    __shared__ double lacc[S][kFuseBlock];   // column s of this thread's row: lacc[s][threadIdx.x]
+    const int t = (int)threadIdx.x;
+    const int i = blockIdx.x * kFuseBlock + t;
     if (i >= n) return;
     const int vi = vertex_of_dof[i];
-    int keys[S];
-    double acc[S];
+    int keys[S];   // slot 0: the diagonal (summed in dg)
+    keys[0] = i;
 #pragma unroll
-    for (int q = 0; q < S; ++q) {
-        keys[q] = INT_MAX;
-        acc[q] = 0.0;
-    }
-    int nk = 0;
-    double fi = 0.0;
+    for (int q = 1; q < S; ++q) keys[q] = INT_MAX;
+    int nk = 1;
+    double fi = 0.0, dg = 0.0;
     const int qe = inc_ptr[vi + 1];
-    constexpr int U = 4;   // records of U incident tets requested together
+    constexpr int U = 4;   // U incident tets' data requested together
     for (int q0 = inc_ptr[vi]; q0 < qe; q0 += U) {
         int code[U];
-        int4 td[U];
-        double kr[U][4], fa[U];
+        int4 tv[U];
+        double p[U][4][3], fa[U];
+        int dd[U][4];
 #pragma unroll
         for (int u = 0; u < U; ++u) code[u] = q0 + u < qe ? inc[q0 + u] : -1;
+        // a missing tet (past the list's end) repeats the first one's loads
+#pragma unroll
+        for (int u = 0; u < U; ++u) tv[u] = tets[(code[u] < 0 ? code[0] : code[u]) >> 2];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (code[u] < 0) continue;
-            const int64_t e = code[u] >> 2;
-            const int a = code[u] & 3;
-            const double *r = rec + kRecD * e;
-            td[u] = *reinterpret_cast<const int4 *>(r);
-#pragma unroll
-            for (int b = 0; b < 4; ++b) kr[u][b] = r[kRecVal + sym_index(a, b)];
-            fa[u] = r[kRecFe + a];
+            const int cu = code[u] < 0 ? code[0] : code[u];
+            load_tet(xyz, tv[u], p[u]);
+            dd[u][0] = dof_of_vertex[tv[u].x];
+            dd[u][1] = dof_of_vertex[tv[u].y];
+            dd[u][2] = dof_of_vertex[tv[u].z];
+            dd[u][3] = dof_of_vertex[tv[u].w];
+            fa[u] = fe[4 * (int64_t)(cu >> 2) + (cu & 3)];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (code[u] < 0) continue;
             fi += fa[u];
-            const int dd[4] = {td[u].x, td[u].y, td[u].z, td[u].w};
+            const int a = code[u] & 3;
+            double g[4][3];
+            const double det = tet_gradients(p[u], g);
+            const double vol = fabs(det) / 6.0;
+            double ga[3] = {g[0][0], g[0][1], g[0][2]};
+#pragma unroll
+            for (int a2 = 1; a2 < 4; ++a2)
+                if (a == a2) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) ga[d] = g[a2][d];
+                }
+            double v[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int j = dd[b];
-                if (j < 0) continue;
-                const double v = kr[u][b];
-                bool found = false;
+                const double kab = vol * (ga[0] * g[b][0] + ga[1] * g[b][1] + ga[2] * g[b][2]);
+                const double mab = vol / 20.0 * (b == a ? 2.0 : 1.0);
+                v[b] = rho * kab + mab;
+            }
+            double vd = v[0];
 #pragma unroll
-                for (int s2 = 0; s2 < S; ++s2)
-                    if (keys[s2] == j) {
-                        acc[s2] += v;
-                        found = true;
-                    }
-                if (found) continue;
+            for (int b = 1; b < 4; ++b)
+                if (b == a) vd = v[b];
+            dg += vd;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int j = dd[u][b];
+                if (b == a || j < 0) continue;
+                int idx = -1;
+#pragma unroll
+                for (int s2 = 1; s2 < S; ++s2) idx = keys[s2] == j ? s2 : idx;
+                if (idx > 0) {
+                    lacc[idx][t] += v[b];
+                    continue;
+                }
                 if (nk == S) {
                     atomicOr(flag, 64);
                     return;
                 }
 #pragma unroll
-                for (int s2 = 0; s2 < S; ++s2)
-                    if (s2 == nk) {
-                        keys[s2] = j;
-                        acc[s2] = 0.0 + v;   // as the first add onto a zero slot
-                    }
+                for (int s2 = 1; s2 < S; ++s2)
+                    if (s2 == nk) keys[s2] = j;
+                lacc[nk][t] = 0.0 + v[b];   // as the first add onto a zero slot
                 ++nk;
             }
         }
     }
+    double acc[S];
+    acc[0] = dg;
+#pragma unroll
+    for (int q = 1; q < S; ++q) acc[q] = q < nk ? lacc[q][t] : 0.0;
     dev::sort_slots(keys, acc);
     // the whole slot in 16-byte stores (unused slots: INT_MAX, 0)
     const int64_t p = (int64_t)i * S;
@@ -1087,38 +1131,33 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
     OCP_LAUNCH_CHECK();
     pos.release();
 
-    // 4. element records (dofs, element matrix, element loads) and vertex
-    // dofs, one pass over the tets
+    // 4-6. With K and M not kept apart, rows of at most kFuseW entries are
+    // assembled in one pass over the tets' element loads (fe, one pass over
+    // the tets) and their geometry: columns are found while the values are
+    // summed.  Otherwise, or if a row is longer, every tet writes its element
+    // record (dofs, element matrix, element loads), then symbolic rows and
+    // numeric rows read the records.
     const bool km = (flags & OCP_KEEP_KM) != 0;
-    DevBuf<double> rec(ctx, (size_t)kRecD * nt);
-    DevBuf<double> vol;
-    if (km) vol.reset(ctx, (size_t)nt);
-    DevBuf<int4> tdof(ctx, (size_t)nt);
-    {
-        TargetUpload up;
-        upload_target(ctx, t, up);
-        launch_tet_load(ctx, up, tets, nt, mesh->xyz, nullptr,
-                        RecOut{sys->dof_of_vertex.get(), rho, rec.get(), vol.get(), tdof.get()});
-    }
-
-    // 5-6. rows.  With K and M not kept apart, rows of at most kFuseW entries
-    // are assembled in one pass (columns found while the values are summed);
-    // otherwise, or if a row is longer, symbolic rows then numeric rows.
+    TargetUpload up;
+    upload_target(ctx, t, up);
     bool fused = false;
     if (!km) {
+        DevBuf<double4> fe(ctx, (size_t)nt);
+        launch_tet_load(ctx, up, tets, nt, mesh->xyz, fe.get());
         DevBuf<int32_t> rlen(ctx, (size_t)n + 1);
         DevBuf<int32_t> pcol(ctx, (size_t)n * kFuseW);
         DevBuf<double> pval(ctx, (size_t)n * kFuseW);
         sys->f.reset(ctx, (size_t)n);
         fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
-        k_row_fused<<<grid_for(n, 256), 256, 0, ctx->stream>>>(n, sys->vertex_of_dof.get(), sys->inc_ptr.get(),
-                                                              sys->inc.get(), rec.get(), rlen.get(), pcol.get(),
-                                                              pval.get(), sys->f.get(), ctx->dev_flag);
+        k_row_fused<<<grid_for(n, kFuseBlock), kFuseBlock, 0, ctx->stream>>>(
+            n, rho, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
+            mesh->xyz, reinterpret_cast<const double *>(fe.get()), rlen.get(), pcol.get(), pval.get(), sys->f.get(),
+            ctx->dev_flag);
         OCP_LAUNCH_CHECK();
         read_back(ctx, &fl, ctx->dev_flag, sizeof(fl));
         if (!(fl & 64)) {
             fused = true;
-            tdof.release();
+            fe.release();
             sys->row_ptr.reset(ctx, (size_t)n + 1);
             sys->nnz = scan_exclusive(ctx, rlen.get(), sys->row_ptr.get(), n);
             sys->col.reset(ctx, (size_t)sys->nnz);
@@ -1142,6 +1181,13 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
         }
     }
     if (!fused) {
+        // 4. element records and the compact vertex dofs of every tet
+        DevBuf<double> rec(ctx, (size_t)kRecD * nt);
+        DevBuf<double> vol;
+        if (km) vol.reset(ctx, (size_t)nt);
+        DevBuf<int4> tdof(ctx, (size_t)nt);
+        launch_tet_load(ctx, up, tets, nt, mesh->xyz, nullptr,
+                        RecOut{sys->dof_of_vertex.get(), rho, rec.get(), vol.get(), tdof.get()});
         // 5. symbolic rows: rows of up to kPadW entries in one pass into a padded
         // buffer; if any row is longer, count and fill again with kRowCap slots
         DevBuf<int32_t> rcnt(ctx, (size_t)n + 1);

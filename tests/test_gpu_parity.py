@@ -76,6 +76,50 @@ def test_assembly_matches_oracle(P, ctx, name, N, jit, rho, tgt):
     np.testing.assert_allclose(f, o.f, rtol=0, atol=1e-13 * max(np.abs(o.f).max(), 1e-300))
 
 
+def test_assembly_routes_agree_bitwise(P, ctx):
+    """Rows of at most 16 entries are assembled in one pass that recomputes
+    every incident tet's element matrix; with K and M kept apart the rows
+    come from element records written once per tet (symbolic, then numeric
+    rows).  Both sum the same element values in the same order: A is equal
+    bit for bit.  The element loads come from two instances of the load
+    kernel (free to fuse multiply-adds differently): f within 1e-15 of its
+    largest entry."""
+    print("[assembly routes] cube12 jitter modes13_k20, one pass vs records", flush=True)
+    mesh = I.kuhn_mesh(12, jitter=0.15, seed=8)
+    target = _target("modes_hi")
+    s1, dm = _gpu_system(P, ctx, mesh, 3e-3, target)
+    s2 = P.fe_assemble(ctx, dm, 3e-3, target, P.capi.KEEP_KM)
+    for a, b in zip(_host_csr(s1), _host_csr(s2)):
+        assert a.dtype == b.dtype and np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    f1, f2 = s1.f().cpu().numpy(), s2.f().cpu().numpy()
+    np.testing.assert_allclose(f1, f2, rtol=0, atol=1e-15 * np.abs(f2).max())
+
+
+def test_assembly_long_rows_matches_oracle(P, ctx):
+    """A bisection-refined mesh has rows of up to 27 entries: the one-pass
+    attempt reports them and the record route assembles the system."""
+    from oracle.refine import Refiner as OracleRefiner
+    print("[assembly long rows] refined cube4, 5 bisection steps", flush=True)
+    m = I.kuhn_mesh(4)
+    r = OracleRefiner(m.xyz, m.tets)
+    rng = np.random.default_rng(20)
+    for _ in range(5):
+        xyz, tets, d = r.mesh()
+        c = xyz[tets].mean(axis=1)
+        r.refine(np.exp(-20 * np.sum((c - 0.3) ** 2, axis=1)) * (1 + 0.01 * rng.random(len(tets))), 0.5)
+    xyz, tets, d = r.mesh()
+    mesh = I.Mesh(N=4, xyz=xyz, tets=tets, dirichlet=d)
+    target = _target("box")
+    s, _ = _gpu_system(P, ctx, mesh, 1e-2, target)
+    o = O.assemble(mesh, 1e-2, target)
+    assert np.diff(o.row_ptr).max() > 16
+    rp, col, val = _host_csr(s)
+    np.testing.assert_array_equal(rp, o.row_ptr)
+    np.testing.assert_array_equal(col, o.col)
+    np.testing.assert_allclose(val, o.val, rtol=0, atol=1e-14 * np.abs(o.val).max())
+    np.testing.assert_allclose(s.f().cpu().numpy(), o.f, rtol=0, atol=1e-13 * np.abs(o.f).max())
+
+
 def test_nodal_target_and_fe_load(P, ctx):
     print("[fe_load] cube6 nodal + sine", flush=True)
     import torch

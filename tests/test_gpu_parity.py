@@ -491,31 +491,46 @@ def test_sell_column_codes_and_plain_columns(P, ctx):
         assert _rel(u.cpu().numpy(), uo) < 1e-10, renum
 
 
+# PCG iterations to 1e-8 on the jittered Kuhn cube (box target), N x rho,
+# as measured with the default hierarchy (smoothed aggregation, omega 1.9);
+# the test allows one more (two in mixed precision)
+ROBUST_N = (16, 32, 64, 128)
+ROBUST_ITS = {1.0: (12, 16, 21, 27), 1e-2: (9, 13, 16, 22), "h2": (8, 8, 8, 8), 1e-6: (7, 7, 7, 7)}
+
+
 def test_iterations_robust_in_h_and_rho(P, ctx):
     """The paper's claim for the solver: iteration counts that do not grow
-    with 1/h (at rho = h^2) and stay bounded over the range of rho (Section 4,
-    Table 4).  With this build's smoothed aggregation the counts at 1e-8 stay
-    within a narrow band."""
-    print("[robustness] N 16..96 at rho = h^2; rho 1e-8..1 at N = 48", flush=True)
-    its_h = []
-    for N in (16, 32, 64, 96):
-        mesh = I.kuhn_mesh(N)
-        s, _ = _gpu_system(P, ctx, mesh, 1.0 / N ** 2, I.random_sine_modes(1000))
-        h = P.amg_setup(ctx, s, precision=P.capi.PREC_MIXED)
-        _, info, rc = P.pcg_solve(ctx, s, h, rtol=1e-8)
-        assert rc == 0 and info.true_rel_res <= 1.0001e-8
-        its_h.append(info.iterations)
-    its_r = []
-    mesh = I.kuhn_mesh(48, jitter=0.15, seed=5)
-    for rho in (1e-8, 1e-6, 1e-4, 1e-2, 1.0):
-        s, _ = _gpu_system(P, ctx, mesh, rho, I.box_indicator())
-        h = P.amg_setup(ctx, s, precision=P.capi.PREC_MIXED)
-        _, info, rc = P.pcg_solve(ctx, s, h, rtol=1e-8)
-        assert rc == 0 and info.true_rel_res <= 1.0001e-8
-        its_r.append(info.iterations)
-    print(f"    iterations vs N (rho=h^2): {its_h}; vs rho at N=48: {its_r}")
-    assert max(its_h) <= 12 and max(its_h) - min(its_h) <= 4
-    assert max(its_r) <= 40
+    with 1/h in the regime the optimality system lives in (rho up to about
+    h^2) and stay bounded over the range of rho (Section 4, Table 4).  Here,
+    on N in {16, 32, 64, 128} x rho in {1, 1e-2, h^2, 1e-6}: flat in N (to
+    one iteration) for rho <= h^2; for the diffusion-dominated rho = 1 and
+    1e-2 this smoothed aggregation grows about like (1/h)^0.4, and the
+    table's bounds pin that growth."""
+    table = {}
+    for N in ROBUST_N:
+        mesh = I.kuhn_mesh(N, jitter=0.15, seed=1)
+        dm = P.upload_mesh(mesh)
+        for key in ROBUST_ITS:
+            rho = 1.0 / N ** 2 if key == "h2" else key
+            print(f"[robustness] N={N} rho={rho:g}", flush=True)
+            s = P.fe_assemble(ctx, dm, rho, I.box_indicator())
+            its = []
+            for prec in (P.capi.PREC_FP64, P.capi.PREC_MIXED):
+                h = P.amg_setup(ctx, s, precision=prec)
+                _, info, rc = P.pcg_solve(ctx, s, h, rtol=1e-8, maxit=200)
+                assert rc == 0 and info.true_rel_res <= 1.0001e-8
+                its.append(info.iterations)
+                h.close()
+            s.close()
+            table[(N, key)] = its
+    for key, bound in ROBUST_ITS.items():
+        row = [table[(N, key)] for N in ROBUST_N]
+        print(f"    rho={key}: fp64 {[r[0] for r in row]}, mixed {[r[1] for r in row]} (measured {list(bound)})")
+        for (f64, mixed), b in zip(row, bound):
+            assert f64 <= b + 1 and mixed <= b + 2
+        if key in ("h2", 1e-6):
+            assert max(r[0] for r in row) - min(r[0] for r in row) <= 1
+    assert table[(128, 1.0)][0] <= 2.5 * table[(16, 1.0)][0]
 
 
 def test_flexible_beta(P, ctx):

@@ -46,11 +46,13 @@ struct CgBlock {
 };
 
 // Tiling of a block launch: the k columns are cut into panels of KB columns
-// (lane j of a row group owns column panel*KB + j) and the rows into tiles
-// of RPP*iters consecutive rows.  Blocks run panel-major, so the gathered
-// working set of a panel is KB/k of a full row block: with k = 32 double
-// columns a full row is 256 bytes and one mesh plane of rows would no longer
-// fit an XCD's L2.  Partial sums are indexed by (column, tile).
+// (lane j of a row group owns column panel*KB + j); tile t of T takes, in
+// pass it, the RPP consecutive rows starting at (it T + t) RPP.  The tiles of
+// one XCD are contiguous, so the blocks an XCD runs at one time work on one
+// band of consecutive rows, whose gathered neighbours (256 bytes per row for
+// k = 32 double columns) mostly sit in that XCD's L2; tiles that each swept
+// their own run of rows spread an XCD's gathers over many mesh planes.
+// Blocks run panel-major.  Partial sums are indexed by (column, tile).
 struct BlkT {
     int iters;        // row passes per block
     unsigned tiles;   // row tiles per panel
@@ -96,11 +98,12 @@ static int lanes_for_cols(int k) {
     const int j = panel * KB + lane;                                      \
     const int grp = threadIdx.x / KB;                                     \
     const bool on = j < k && (cgb == nullptr || cgb->cflag[j] == 0);     \
-    const int base = (int)tile * RPP * iters;
+    const int base = (int)tile * RPP;                                     \
+    const int stride = (int)bt.tiles * RPP;
 #define OCP_BLK_BEGIN(KB)                                                 \
     OCP_BLK_TILE(KB)                                                      \
     for (int it = 0; it < iters; ++it) {                                 \
-        const int row = base + it * RPP + grp;                           \
+        const int row = base + it * stride + grp;                        \
         if (on && row < n) {                                             \
             const size_t e = (size_t)row * k + j;
 #define OCP_BLK_END() \
@@ -150,7 +153,7 @@ __device__ __forceinline__ T blk_row(int rb, int re, int lane, bool on, const in
     return s;
 }
 
-// Streams the rows of one KB-lane group (rows base + grp + it*RPP, it <
+// Streams the rows of one KB-lane group (rows base + grp + it*stride, it <
 // iters) as a software pipeline: while the gathers of the current row are in
 // flight, the first KB entries of the next row, the row range of the one
 // after, and the current row's epilogue operands (ld) are already loaded, so
@@ -159,10 +162,9 @@ __device__ __forceinline__ T blk_row(int rb, int re, int lane, bool on, const in
 // finish with blk_row.  Uniform per group: every lane of the group runs the
 // same rows (lanes with `on` false load entries but skip gathers).
 template <int KB, typename T, typename XF, typename LD, typename FIN>
-__device__ __forceinline__ void blk_rows(int n, int iters, int base, int grp, int lane, bool on,
+__device__ __forceinline__ void blk_rows(int n, int iters, int base, int stride, int grp, int lane, bool on,
                                          const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                          const T *__restrict__ val, XF xf, LD ld, FIN fin) {
-    constexpr int RPP = kBlock / KB;
     constexpr int CH = KB < kBlkChunk ? KB : kBlkChunk;
     int row = base + grp;
     if (iters <= 0 || row >= n) return;
@@ -173,7 +175,7 @@ __device__ __forceinline__ void blk_rows(int n, int iters, int base, int grp, in
         mc = ldnt(col + rb + lane);
         mv = ldnt(val + rb + lane);
     }
-    int nrow = row + RPP;
+    int nrow = row + stride;
     bool hn = iters > 1 && nrow < n;
     int nb = 0, ne = 0;
     if (hn) {
@@ -188,7 +190,7 @@ __device__ __forceinline__ void blk_rows(int n, int iters, int base, int grp, in
             mc2 = ldnt(col + nb + lane);
             mv2 = ldnt(val + nb + lane);
         }
-        const int nnrow = nrow + RPP;
+        const int nnrow = nrow + stride;
         const bool hnn = hn && it + 2 < iters && nnrow < n;
         int nnb = 0, nne = 0;
         if (hnn) {
@@ -333,7 +335,7 @@ __global__ void __launch_bounds__(kBlock) k_blk_smooth(int32_t n, int k, BlkT bt
     using Pre = typename BlkOps<T, BT, OT, GDB, MODE>::Pre;
     OCP_BLKGRP(KB)
     dev::blk_rows<KB>(
-        n, iters, base, grp, lane, on, rp, col, val, [&](int c) { return ops.gather(c, j); },
+        n, iters, base, stride, grp, lane, on, rp, col, val, [&](int c) { return ops.gather(c, j); },
         [&](int row) { return on ? ops.load(row, (size_t)row * k + j) : Pre{}; },
         [&](int row, T s, const Pre &pre) {
             if (on) {
@@ -352,7 +354,7 @@ __global__ void __launch_bounds__(kBlock) k_blk_spmv(int32_t n, int k, BlkT bt, 
     if (cgb && cgb->flag) return;
     OCP_BLKGRP(KB)
     dev::blk_rows<KB>(
-        n, iters, base, grp, lane, on, rp, col, val, [&](int c) { return x[(size_t)c * k + j]; },
+        n, iters, base, stride, grp, lane, on, rp, col, val, [&](int c) { return x[(size_t)c * k + j]; },
         [](int) { return 0; },
         [&](int row, T s, int) {
             if (on) y[(size_t)row * k + j] = s;
@@ -369,7 +371,7 @@ __global__ void __launch_bounds__(kBlock) k_blk_prolong(int32_t n, int k, BlkT b
     if (cgb && cgb->flag) return;
     OCP_BLKGRP(KB)
     dev::blk_rows<KB>(
-        n, iters, base, grp, lane, on, rp, col, val, [&](int c) { return xc[(size_t)c * k + j]; },
+        n, iters, base, stride, grp, lane, on, rp, col, val, [&](int c) { return xc[(size_t)c * k + j]; },
         [&](int row) {
             const size_t e = (size_t)row * k + j;
             return on ? (HX ? xs[e] : a * d[row] * (T)b[e]) : T(0);
@@ -449,7 +451,7 @@ __global__ void __launch_bounds__(kBlock) k_blk_spmm_pq(int32_t n, int k, BlkT b
     double acc = 0.0;
     OCP_BLKGRP(KB)
     dev::blk_rows<KB>(
-        n, iters, base, grp, lane, on, rp, col, val, [&](int c) { return P[(size_t)c * k + j]; },
+        n, iters, base, stride, grp, lane, on, rp, col, val, [&](int c) { return P[(size_t)c * k + j]; },
         [&](int row) { return on ? P[(size_t)row * k + j] : 0.0; },
         [&](int row, double s, double pi) {
             if (on) {
@@ -471,7 +473,7 @@ __global__ void __launch_bounds__(kBlock) k_blk_resid2(int32_t n, int k, BlkT bt
     double acc = 0.0;
     OCP_BLKGRP(KB)
     dev::blk_rows<KB>(
-        n, iters, base, grp, lane, on, rp, col, val, [&](int c) { return X[(size_t)c * k + j]; },
+        n, iters, base, stride, grp, lane, on, rp, col, val, [&](int c) { return X[(size_t)c * k + j]; },
         [&](int row) { return on ? F[(size_t)row * fs_row + (size_t)j * fs_col] : 0.0; },
         [&](int row, double s, double fi) {
             (void)row;

@@ -178,6 +178,31 @@ def test_stale_hierarchy_after_set_rho_is_refused(P, ctx):
         s.set_rho(1.0)
 
 
+def test_breakdown_status_on_nonfinite_load(P, ctx):
+    """A load with one NaN entry makes the first r.z non-finite: Jacobi-PCG,
+    AMG-PCG and the block solve (that column) stop with OCP_ERR_BREAKDOWN.
+    The condition is set from the host; every kernel exits normally (the
+    solver's own finiteness checks stop the iteration)."""
+    import torch
+    print("[breakdown] cube8 jitter, NaN in f", flush=True)
+    mesh = I.kuhn_mesh(8, jitter=0.15, seed=3)
+    s, _ = _gpu_system(P, ctx, mesh, 1e-2, I.single_sine())
+    f = s.f().clone()
+    f[5] = float("nan")
+    h = P.amg_setup(ctx, s, precision=P.capi.PREC_MIXED, coarse_max=32)
+    for hh in (None, h):
+        with pytest.raises(P.OcpError) as ei:
+            P.pcg_solve(ctx, s, hh, f=f, rtol=1e-8)
+        assert ei.value.code == P.capi.ERR_BREAKDOWN
+    F = torch.stack([s.f(), f, s.f()], dim=1).contiguous()
+    with pytest.raises(P.OcpError) as ei:
+        P.pcg_solve_multi(ctx, s, h, F, rtol=1e-8)
+    assert ei.value.code == P.capi.ERR_BREAKDOWN
+    # the same system and hierarchy still solve a finite load
+    u, info, rc = P.pcg_solve(ctx, s, h, rtol=1e-8)
+    assert rc == 0 and info.true_rel_res <= 1.0001e-8
+
+
 def test_spmv_matches_oracle(P, ctx):
     import torch
     print("[spmv] cube20 jitter", flush=True)

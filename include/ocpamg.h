@@ -108,10 +108,14 @@ typedef struct {
 
 /* -------------------------------------------------------------- assembly */
 #define OCP_KEEP_KM 1 /* keep K and M values separately so fe_set_rho can re-weight */
+#define OCP_NO_LOAD 2 /* assemble A only: f is set to zero and target may be NULL; the load
+                       * vector then comes from fe_load, which may run on another context
+                       * while amg_setup works on this system */
 
 /* Assemble A = rho*K + M and f (Section 2, system (linsys)) on the interior
  * vertices of `mesh` into CSR on the device.  Element matrices are exact; f
- * uses the 4-point degree-2 rule on each tetrahedron.  The assembly is
+ * uses the 4-point degree-2 rule on each tetrahedron (with OCP_NO_LOAD in
+ * flags, f is zero and target is not read).  The assembly is
  * row-owned (one owner per row, no atomics on values) and bitwise
  * deterministic.  Unknowns are the interior vertices in increasing vertex id.
  * Errors: INVALID_ARG (NULL, counts <= 0, rho <= 0 or not finite, bad target),

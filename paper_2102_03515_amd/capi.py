@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libocpamg.so")
 OK, MAXIT = 0, 1
 ERR_INVALID_ARG, ERR_BAD_MESH, ERR_OOM, ERR_BREAKDOWN, ERR_HIP, ERR_UNSUPPORTED = -1, -2, -3, -4, -5, -6
 KEEP_KM = 1
+NO_LOAD = 2
 PREC_FP64, PREC_MIXED = 0, 1
 SMOOTH_L1JACOBI, SMOOTH_CHEBYSHEV = 0, 1
 AMG_AGGREGATION, AMG_REDBLACK = 0, 1
@@ -502,11 +503,13 @@ class Refiner:
 
 
 def fe_assemble(ctx: Context, mesh: DeviceMesh, rho: float, target, flags: int = 0) -> System:
+    """A = rho K + M and f on the mesh; with NO_LOAD in flags, A only (f zero,
+    target may be None)."""
     keep = []
-    t = target_struct(target, keep)
+    t = C.byref(target_struct(target, keep)) if target is not None else None
     m = mesh.struct()
     h = C.c_void_p()
-    ctx.check(lib().fe_assemble(ctx.handle, C.byref(m), float(rho), C.byref(t), int(flags), C.byref(h)))
+    ctx.check(lib().fe_assemble(ctx.handle, C.byref(m), float(rho), t, int(flags), C.byref(h)))
     return System(ctx, h, mesh)
 
 

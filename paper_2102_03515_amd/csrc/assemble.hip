@@ -685,7 +685,8 @@ __global__ void __launch_bounds__(256) k_row_numeric(
 // tet, row a of its element matrix from the vertex coordinates (a = the row's
 // vertex in the tet; entry (a,b) = rho |tau| grad phi_a . grad phi_b +
 // |tau|/20 (1 + delta_ab), the products and sums in the order elem_values
-// uses, so the same bits), and takes the element load from fe (4 per tet).
+// uses, so the same bits), and takes the element load from fe (4 per tet;
+// with fe NULL, f is zero).
 // The diagonal is summed in a register; every other column gets a slot at
 // its first appearance (keys in registers, sums in thread-private LDS), and
 // each slot sums its values in incidence order as k_row_numeric does (so
@@ -742,7 +743,7 @@ __global__ void __launch_bounds__(kFuseBlock) k_row_fused(int32_t n, double rho,
             dd[u][1] = dof_of_vertex[tv[u].y];
             dd[u][2] = dof_of_vertex[tv[u].z];
             dd[u][3] = dof_of_vertex[tv[u].w];
-            fa[u] = fe[4 * (int64_t)(cu >> 2) + (cu & 3)];
+            fa[u] = fe ? fe[4 * (int64_t)(cu >> 2) + (cu & 3)] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1138,12 +1139,19 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
     // record (dofs, element matrix, element loads), then symbolic rows and
     // numeric rows read the records.
     const bool km = (flags & OCP_KEEP_KM) != 0;
+    const bool noload = (flags & OCP_NO_LOAD) != 0;
+    // without loads, the record route evaluates an empty box (every load 0)
+    ocp_target empty_box{};
+    empty_box.kind = OCP_TARGET_BOX;
     TargetUpload up;
-    upload_target(ctx, t, up);
+    upload_target(ctx, noload ? &empty_box : t, up);
     bool fused = false;
     if (!km) {
-        DevBuf<double4> fe(ctx, (size_t)nt);
-        launch_tet_load(ctx, up, tets, nt, mesh->xyz, fe.get());
+        DevBuf<double4> fe;
+        if (!noload) {
+            fe.reset(ctx, (size_t)nt);
+            launch_tet_load(ctx, up, tets, nt, mesh->xyz, fe.get());
+        }
         DevBuf<int32_t> rlen(ctx, (size_t)n + 1);
         DevBuf<int32_t> pcol(ctx, (size_t)n * kFuseW);
         DevBuf<double> pval(ctx, (size_t)n * kFuseW);
@@ -1151,7 +1159,8 @@ static void assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const ocp_t
         fill_zero_bytes(ctx, ctx->dev_flag, sizeof(int32_t));
         k_row_fused<<<grid_for(n, kFuseBlock), kFuseBlock, 0, ctx->stream>>>(
             n, rho, sys->vertex_of_dof.get(), sys->dof_of_vertex.get(), sys->inc_ptr.get(), sys->inc.get(), tets,
-            mesh->xyz, reinterpret_cast<const double *>(fe.get()), rlen.get(), pcol.get(), pval.get(), sys->f.get(),
+            mesh->xyz, noload ? nullptr : reinterpret_cast<const double *>(fe.get()), rlen.get(), pcol.get(),
+            pval.get(), sys->f.get(),
             ctx->dev_flag);
         OCP_LAUNCH_CHECK();
         read_back(ctx, &fl, ctx->dev_flag, sizeof(fl));
@@ -1283,7 +1292,7 @@ extern "C" int fe_assemble(ocp_ctx *ctx, const ocp_mesh *mesh, double rho, const
             fail(OCP_ERR_INVALID_ARG, "mesh needs positive counts and xyz, tets, dirichlet arrays");
         if ((int64_t)mesh->n_tets * 4 > INT32_MAX) fail(OCP_ERR_UNSUPPORTED, "more than 2^29 tetrahedra");
         if (!(rho > 0.0) || !std::isfinite(rho)) fail(OCP_ERR_INVALID_ARG, "rho must be positive and finite");
-        check_target(target, mesh->n_vertices);
+        if (!(flags & OCP_NO_LOAD)) check_target(target, mesh->n_vertices);
         sys = new ocp_system();
         sys->ctx = ctx;
         assemble(ctx, mesh, rho, target, flags, sys);

@@ -53,6 +53,7 @@ def test_constants_match_header():
     assert int(defs["OCP_STOP_PRECOND"]) == capi.STOP_PRECOND
     assert int(defs["OCP_TARGET_BOX"]) == capi.TARGET_BOX
     assert int(defs["OCP_KEEP_KM"]) == capi.KEEP_KM
+    assert int(defs["OCP_NO_LOAD"]) == capi.NO_LOAD
     assert int(defs["OCP_AMG_REDBLACK"]) == capi.AMG_REDBLACK
 
 

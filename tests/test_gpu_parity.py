@@ -120,6 +120,42 @@ def test_assembly_long_rows_matches_oracle(P, ctx):
     np.testing.assert_allclose(s.f().cpu().numpy(), o.f, rtol=0, atol=1e-13 * np.abs(o.f).max())
 
 
+def test_no_load_assembly_with_loads_on_another_context(P, ctx):
+    """OCP_NO_LOAD assembles A alone (f zero, no target): A equals the full
+    assembly's bit for bit on both routes.  fe_load on a second context,
+    run from another host thread while amg_setup works on the system,
+    gives the full assembly's f bit for bit (the same element loads summed
+    in the same order), and the solve with it equals the solve of the fully
+    assembled system bit for bit."""
+    import threading
+    import torch
+    print("[no-load] cube12 jitter modes64: A alone, loads beside the setup", flush=True)
+    mesh = I.kuhn_mesh(12, jitter=0.15, seed=9)
+    target = _target("modes")
+    s1, dm = _gpu_system(P, ctx, mesh, 3e-3, target)
+    s0 = P.fe_assemble(ctx, dm, 3e-3, None, P.capi.NO_LOAD)
+    for a, b in zip(_host_csr(s1), _host_csr(s0)):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    assert not s0.f().abs().max().item()
+    skm = P.fe_assemble(ctx, dm, 3e-3, None, P.capi.NO_LOAD | P.capi.KEEP_KM)
+    for a, b in zip(_host_csr(s1), _host_csr(skm)):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    assert not skm.f().abs().max().item()
+    ctx2 = P.Context()
+    out = {}
+    th = threading.Thread(target=lambda: out.setdefault("f", s0.load(target, ctx=ctx2)))
+    th.start()
+    h0 = P.amg_setup(ctx, s0, precision=P.capi.PREC_MIXED, coarse_max=64)
+    th.join()
+    f = out["f"]
+    assert np.array_equal(f.cpu().numpy().view(np.uint64), s1.f().cpu().numpy().view(np.uint64))
+    u0, i0, r0 = P.pcg_solve(ctx, s0, h0, f=f, rtol=1e-10)
+    h1 = P.amg_setup(ctx, s1, precision=P.capi.PREC_MIXED, coarse_max=64)
+    u1, i1, r1 = P.pcg_solve(ctx, s1, h1, rtol=1e-10)
+    assert r0 == r1 == 0 and i0.iterations == i1.iterations
+    assert torch.equal(u0, u1)
+
+
 def test_nodal_target_and_fe_load(P, ctx):
     print("[fe_load] cube6 nodal + sine", flush=True)
     import torch

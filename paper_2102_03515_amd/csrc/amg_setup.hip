@@ -191,6 +191,11 @@ __device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
 // == round) as the closed neighbourhood of an undecided node.
 constexpr int kMisMarkFrom = 5;   // first round whose m2 marks
 constexpr int kMisMaxRounds = 1024;
+// list the undecided nodes at the first host check after round kMisListFrom
+// when they are at most n / kMisListFrac (levels of kMisListMinN nodes or more)
+constexpr int kMisListFrom = 4;
+constexpr int kMisListFrac = 64;
+constexpr int kMisListMinN = 1 << 16;
 template <int G, bool FIRST>
 __global__ void __launch_bounds__(256) k_mis_m1(int32_t n, const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ col, const uint8_t *__restrict__ strong,
@@ -287,6 +292,97 @@ __global__ void __launch_bounds__(256) k_mis_m2(int32_t n, const int32_t *__rest
     }
     // "some node is still undecided": every writer stores the same value, so
     // one plain store per wavefront suffices (no contended atomic)
+    const unsigned long long any = __ballot(still);
+    if (any != 0ull && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)any) - 1)) *undecided = 1;
+}
+
+// Rounds over a list of the nodes still undecided when few are left (the
+// list is built once; nodes decided later stay in it and are skipped).
+// k_mis_m1_list recomputes m1 for every node of the closed neighbourhood of
+// a listed undecided node (lane t of the group: node t of N[u], u itself for
+// t = 0), which is the set the full-size rounds mark; a node shared by
+// several listed nodes is written by each with the same value (its
+// neighbours' states do not change during the kernel).  k_mis_m2_list then
+// decides the listed undecided nodes as k_mis_m2 does.
+__global__ void k_undecided_flags(int32_t n, const int8_t *__restrict__ state, int32_t *__restrict__ fl) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) fl[i] = state[i] == 0 ? 1 : 0;
+}
+__global__ void k_list_fill(int32_t n, const int32_t *__restrict__ fl, const int32_t *__restrict__ pos,
+                            int32_t *__restrict__ list) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && fl[i]) list[pos[i]] = i;
+}
+constexpr int kMisListG = 16;   // lanes per listed node
+__device__ __forceinline__ uint64_t mis_m1_of(int v, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                              const uint8_t *__restrict__ strong, const int8_t *__restrict__ state,
+                                              uint32_t salt) {
+    uint64_t m = mis_key(v, state[v], salt);
+    const int ke = rp[v + 1];
+    for (int k = rp[v]; k < ke; ++k) {
+        const int j = col[k];
+        if (is_strong(strong, k, j, v)) {
+            const uint64_t kj = mis_key(j, state[j], salt);
+            m = kj > m ? kj : m;
+        }
+    }
+    return m;
+}
+__global__ void __launch_bounds__(256) k_mis_m1_list(const int32_t *__restrict__ list, int32_t nl,
+                                                     const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                     const uint8_t *__restrict__ strong,
+                                                     const int8_t *__restrict__ state, uint32_t salt,
+                                                     const int32_t *__restrict__ prev_undecided,
+                                                     uint64_t *__restrict__ m1) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = (int)(t / kMisListG), lane = (int)(t % kMisListG);
+    if (r >= nl) return;
+    if (prev_undecided && *prev_undecided == 0) return;
+    const int u = list[r];
+    if (state[u] != 0) return;   // uniform over the group
+    if (lane == 0) m1[u] = mis_m1_of(u, rp, col, strong, state, salt);
+    const int ke = rp[u + 1];
+    for (int k = rp[u] + lane - 1; k < ke; k += kMisListG) {
+        if (k < rp[u]) continue;   // lane 0 took u
+        const int j = col[k];
+        if (is_strong(strong, k, j, u)) m1[j] = mis_m1_of(j, rp, col, strong, state, salt);
+    }
+}
+__global__ void __launch_bounds__(256) k_mis_m2_list(const int32_t *__restrict__ list, int32_t nl,
+                                                     const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                     const uint8_t *__restrict__ strong, int8_t *__restrict__ state,
+                                                     uint32_t salt, const uint64_t *__restrict__ m1,
+                                                     const int32_t *__restrict__ prev_undecided,
+                                                     int32_t *undecided) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = (int)(t / kMisListG), lane = (int)(t % kMisListG);
+    bool still = false;
+    if (r < nl && !(prev_undecided && *prev_undecided == 0)) {
+        const int u = list[r];
+        if (state[u] == 0) {   // uniform over the group
+            uint64_t m = 0;
+            const int ke = rp[u + 1];
+            for (int k = rp[u] + lane; k < ke; k += kMisListG) {
+                const int j = col[k];
+                if (is_strong(strong, k, j, u)) {
+                    const uint64_t v = m1[j];
+                    m = v > m ? v : m;
+                }
+            }
+            m = group_max_u64<kMisListG>(m);
+            const uint64_t mu = m1[u];
+            m = mu > m ? mu : m;
+            const bool joins = m == mis_key(u, 0, salt);
+            const bool leaves = !joins && (m >> 62) == 3u;
+            if (lane == 0) {
+                if (joins)
+                    state[u] = 1;
+                else if (leaves)
+                    state[u] = 2;
+            }
+            still = !joins && !leaves && lane == 0;
+        }
+    }
     const unsigned long long any = __ballot(still);
     if (any != 0ull && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)any) - 1)) *undecided = 1;
 }
@@ -1793,8 +1889,21 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
             DevBuf<int32_t> undec(ctx, (size_t)kMisMaxRounds + 1);
             fill_zero_bytes(ctx, undec.get(), sizeof(int32_t) * ((size_t)kMisMaxRounds + 1));
             int batch = 4;
+            // once few nodes are undecided, the rounds run over a list of them
+            DevBuf<int32_t> ulist;
+            int32_t nlist = -1;
             for (int round = 1;;) {
                 const int last = std::min(round + batch - 1, kMisMaxRounds);
+                if (nlist >= 0) {
+                    const unsigned gl = grid_for((int64_t)std::max(nlist, 1) * kMisListG, 256);
+                    for (; round <= last; ++round) {
+                        const int32_t *prev = undec.get() + round - 1;
+                        k_mis_m1_list<<<gl, 256, 0, s>>>(ulist.get(), nlist, L.A_rp, L.A_col, strong.get(),
+                                                         state.get(), salt, prev, m1.get());
+                        k_mis_m2_list<<<gl, 256, 0, s>>>(ulist.get(), nlist, L.A_rp, L.A_col, strong.get(),
+                                                         state.get(), salt, m1.get(), prev, undec.get() + round);
+                    }
+                }
                 for (; round <= last; ++round) {
                     const int32_t *prev = round == 1 ? nullptr : undec.get() + round - 1;
                     // the first rounds leave most nodes undecided: marking their
@@ -1817,6 +1926,19 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
                 read_back(ctx, &und, undec.get() + last, sizeof(int32_t));
                 if (und == 0) break;
                 if (last >= kMisMaxRounds) fail(OCP_ERR_HIP, "independent-set rounds did not terminate");
+                if (nlist < 0 && last >= kMisListFrom && n >= kMisListMinN) {
+                    // few undecided nodes left: list them once
+                    DevBuf<int32_t> fl(ctx, (size_t)n + 1), pos(ctx, (size_t)n + 1);
+                    k_undecided_flags<<<grid_for(n, 256), 256, 0, s>>>(n, state.get(), fl.get());
+                    OCP_LAUNCH_CHECK();
+                    const int64_t cnt = scan_exclusive(ctx, fl.get(), pos.get(), n);
+                    if (cnt * kMisListFrac <= n) {
+                        nlist = (int32_t)cnt;
+                        ulist.reset(ctx, (size_t)std::max<int64_t>(cnt, 1));
+                        k_list_fill<<<grid_for(n, 256), 256, 0, s>>>(n, fl.get(), pos.get(), ulist.get());
+                        OCP_LAUNCH_CHECK();
+                    }
+                }
                 batch = std::min(batch * 2, 16);
             }
             // aggregates

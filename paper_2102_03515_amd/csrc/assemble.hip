@@ -188,32 +188,65 @@ __global__ void __launch_bounds__(kIncBlock) k_tet_fill(const int4 *__restrict__
 }
 
 // Sort each vertex's list of incidence codes ascending: a 32-wide sorting
-// network in registers for the common case, insertion sort otherwise.
-__global__ void k_inc_sort(const int32_t *__restrict__ inc_ptr, int32_t *__restrict__ inc, int32_t nv) {
-    int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= nv) return;
-    const int b = inc_ptr[v], len = inc_ptr[v + 1] - b;
-    if (len <= 1) return;
+// network in registers for the common case, insertion sort otherwise.  One
+// wavefront per 64 consecutive vertices, whose lists are contiguous: when
+// they fit kSortStage codes and none is longer than 32, the wavefront stages
+// them in LDS with coalesced loads, each lane sorts its list from there, and
+// the lists go back with coalesced stores (a lane reading its own list from
+// global memory touched 64 lines per load).  Otherwise each lane sorts its
+// list in place in global memory.
+constexpr int kSortStage = 2048;
+__device__ __forceinline__ void sort32(int (&r)[32]) {
+    // bitonic sorting network on 32 keys
+#pragma unroll
+    for (int k = 2; k <= 32; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const int x = r[i], y = r[l];
+                    const bool sw = up ? (x > y) : (x < y);
+                    r[i] = sw ? y : x;
+                    r[l] = sw ? x : y;
+                }
+            }
+}
+__global__ void __launch_bounds__(64) k_inc_sort(const int32_t *__restrict__ inc_ptr, int32_t *__restrict__ inc,
+                                                 int32_t nv) {
+    __shared__ int32_t stage[kSortStage];
+    const int v0 = blockIdx.x * 64;
+    const int v = v0 + (int)threadIdx.x;
+    const int vend = v0 + 64 < nv ? v0 + 64 : nv;
+    const int g0 = inc_ptr[v0], g1 = inc_ptr[vend];
+    const int b = v < nv ? inc_ptr[v] : g1;
+    const int len = v < nv ? inc_ptr[v + 1] - b : 0;
+    const bool staged = g1 - g0 <= kSortStage && __all(len <= 32);   // uniform over the wavefront
+    if (staged) {
+        for (int k = (int)threadIdx.x; k < g1 - g0; k += 64) stage[k] = inc[g0 + k];
+        __syncthreads();
+        if (len > 1) {
+            const int o = b - g0;
+            int r[32];
+#pragma unroll
+            for (int i = 0; i < 32; ++i) r[i] = i < len ? stage[o + i] : INT_MAX;
+            sort32(r);
+#pragma unroll
+            for (int i = 0; i < 32; ++i)
+                if (i < len) stage[o + i] = r[i];
+        }
+        __syncthreads();
+        for (int k = (int)threadIdx.x; k < g1 - g0; k += 64) inc[g0 + k] = stage[k];
+        return;
+    }
+    if (v >= nv || len <= 1) return;
     if (len <= 32) {
         int r[32];
 #pragma unroll
         for (int i = 0; i < 32; ++i) r[i] = i < len ? inc[b + i] : INT_MAX;
-        // bitonic sorting network on 32 keys
-#pragma unroll
-        for (int k = 2; k <= 32; k <<= 1)
-#pragma unroll
-            for (int j = k >> 1; j > 0; j >>= 1)
-#pragma unroll
-                for (int i = 0; i < 32; ++i) {
-                    const int l = i ^ j;
-                    if (l > i) {
-                        const bool up = (i & k) == 0;
-                        const int x = r[i], y = r[l];
-                        const bool sw = up ? (x > y) : (x < y);
-                        r[i] = sw ? y : x;
-                        r[l] = sw ? x : y;
-                    }
-                }
+        sort32(r);
 #pragma unroll
         for (int i = 0; i < 32; ++i)
             if (i < len) inc[b + i] = r[i];

@@ -4,11 +4,16 @@
 //
 // Vectors of the block are stored row-major, entry (i, j) at i*k + j, so that
 // the k values of a row are contiguous.  A row is handled by a group of KB
-// lanes (KB = 8/16/32/64 >= k), lane j owning column j: every matrix entry is
-// loaded once per group (the same address in all its lanes, a broadcast) and
-// multiplies k gathered values that sit next to each other in memory.  The
-// matrix stream is therefore read once per k right-hand sides; the vector
-// streams are what scale with k.
+// lanes (KB = 8/16/32/64): in the elementwise kernels lane j owns column j;
+// in the kernels that gather neighbouring rows (the SpMM and the V-cycle
+// passes) each lane owns VW consecutive columns when k is a multiple of VW
+// (2 in FP64, 4 in FP32), so that every gather is one 16-byte access -- a
+// wavefront's load instruction costs the same address-processing time
+// whatever its width, and these kernels issue one per matrix entry.  Every
+// matrix entry is staged once per group and multiplies k gathered values
+// that sit next to each other in memory.  The matrix stream is therefore
+// read once per k right-hand sides; the vector streams are what scale with
+// k.
 //
 // Every column has its own alpha, beta, gamma and stop flag on the device.  A
 // column that has converged (or broken down, or hit the cap) is frozen: its
@@ -27,7 +32,7 @@
 namespace ocp {
 
 constexpr int kMaxCols = 64;
-constexpr int kBlkMaxBlocks = 4096;
+constexpr int kBlkMaxBlocks = 1024;
 
 // Per-column CG scalars of the block solve (device).
 struct CgBlock {
@@ -62,13 +67,14 @@ struct BlkLaunch {
     unsigned blocks;  // tiles * panels
 };
 
-inline BlkLaunch blk_launch(int64_t n, int KB, int k) {
+// KB lanes per row, each owning VW consecutive columns
+inline BlkLaunch blk_launch(int64_t n, int KB, int k, int VW = 1) {
     const int64_t rpp = kBlock / KB;
     int64_t iters = (n + rpp * kBlkMaxBlocks - 1) / (rpp * kBlkMaxBlocks);
     if (iters < 1) iters = 1;
     int64_t b = (n + rpp * iters - 1) / (rpp * iters);
     if (b < 1) b = 1;
-    const int panels = (k + KB - 1) / KB;
+    const int panels = (k + KB * VW - 1) / (KB * VW);
     return {{(int)iters, (unsigned)b}, (unsigned)b * (unsigned)panels};
 }
 
@@ -96,6 +102,7 @@ static int lanes_for_cols(int k) {
     const int iters = bt.iters;                                           \
     const int lane = (int)(threadIdx.x % KB);                             \
     const int j = panel * KB + lane;                                      \
+    [[maybe_unused]] const int jg = j < k ? j : k - 1; /* valid column */ \
     const int grp = threadIdx.x / KB;                                     \
     const bool on = j < k && (cgb == nullptr || cgb->cflag[j] == 0);     \
     const int base = (int)tile * RPP;                                     \
@@ -113,68 +120,114 @@ static int lanes_for_cols(int k) {
 // Lane roles of a block matrix kernel that streams its rows with blk_rows.
 #define OCP_BLKGRP(KB) OCP_BLK_TILE(KB)
 
-namespace dev {
-constexpr int kBlkChunk = 16;
+// Lane roles of a gather kernel whose lanes own VW consecutive columns each:
+// lane `lane` of row group grp owns columns j0 .. j0+VW-1 of the panel; k is
+// a multiple of VW, so a lane's columns are all below k or all past it.
+// These kernels compute every column below k, frozen ones too (their outputs
+// feed only work vectors and partial sums that the frozen columns no longer
+// read), so the stores stay whole.
+#define OCP_BLKV_TILE(KB, VW)                                             \
+    constexpr int RPP = kBlock / KB;                                      \
+    const unsigned gtile = dev::xcd_tile(blockIdx.x, gridDim.x);         \
+    const int panel = (int)(gtile / bt.tiles);                            \
+    const unsigned tile = gtile % bt.tiles;                               \
+    const int iters = bt.iters;                                           \
+    const int lane = (int)(threadIdx.x % KB);                             \
+    const int j0 = (panel * KB + lane) * VW;                              \
+    const bool on = j0 < k;                                               \
+    const int jg = on ? j0 : 0; /* valid column */                        \
+    const int grp = threadIdx.x / KB;                                     \
+    const int base = (int)tile * RPP;                                     \
+    const int stride = (int)bt.tiles * RPP;
 
-// sum_q val_q * sf(col_q) * xf(col_q) over the entries [rb, re) of one row,
-// for the column of the calling lane in a KB-lane group.  The group loads up to KB entries at a time
-// (lane q takes entry q, non-temporal: the matrix is streamed once) and
-// broadcasts them with shuffles; each lane then issues up to kBlkChunk
-// independent gathers of its own column before it consumes any, so a row of
-// the fine level costs two memory round trips instead of one per entry.
-// sf scales an entry's value by a per-column factor (loaded once per entry
-// by its owner lane); xf(c) is lane j's gathered value of column c.
-template <int KB, typename T, typename XF, typename SF>
-__device__ __forceinline__ T blk_row(int rb, int re, int lane, bool on, const int32_t *__restrict__ col,
-                                     const T *__restrict__ val, XF xf, SF sf) {
-    constexpr int CH = KB < kBlkChunk ? KB : kBlkChunk;
-    T s = T(0);
-    for (int b0 = rb; b0 < re; b0 += KB) {
-        const int cnt = re - b0 < KB ? re - b0 : KB;
-        int mc = 0;
-        T mv = T(0);
-        if (lane < cnt) {
-            mc = ldnt(col + b0 + lane);
-            mv = ldnt(val + b0 + lane) * sf(mc);
-        }
-        for (int q0 = 0; q0 < cnt; q0 += CH) {
-            T a[CH], g[CH];
+namespace dev {
+constexpr int kBlkChunk = 8;    // gathers requested together
+constexpr int kBlkStage = 32;   // entries of a row staged in LDS at a time (at least)
+
+// VW consecutive columns of one row of a block vector, loaded and stored as
+// one access of VW * sizeof(T) bytes (16 for FP64 pairs and FP32 quads): the
+// k values of a row are contiguous and, with k a multiple of VW, every
+// lane's first column sits at a multiple of VW.
+template <typename T, int VW>
+struct alignas(VW * sizeof(T)) BV {
+    T v[VW];
+};
+template <typename T, int VW>
+__device__ __forceinline__ BV<T, VW> ldv(const T *p) {
+    return *reinterpret_cast<const BV<T, VW> *>(p);
+}
+template <typename T, int VW>
+__device__ __forceinline__ void stv(T *p, const BV<T, VW> &x) {
+    *reinterpret_cast<BV<T, VW> *>(p) = x;
+}
+// s += a g, per column (the scalar form for one column per lane)
+template <typename T>
+__device__ __forceinline__ void bv_fma(T &s, T a, T g) {
+    s += a * g;
+}
+template <typename T, int VW>
+__device__ __forceinline__ void bv_fma(BV<T, VW> &s, T a, const BV<T, VW> &g) {
 #pragma unroll
-            for (int u = 0; u < CH; ++u) {
-                const int q = q0 + u;   // < KB: CH divides KB and q0 < cnt <= KB
-                const int c = __shfl(mc, q, KB);
-                a[u] = __shfl(mv, q, KB);
-                g[u] = (on && q < cnt) ? xf(c) : T(0);
-            }
+    for (int w = 0; w < VW; ++w) s.v[w] += a * g.v[w];
+}
+
+// Lane q's entries q, q + KB, ... (EPL of them) of the row range [b, e),
+// indices clamped into the row (level matrices always hold their diagonal
+// and restriction rows an aggregate member, so rows are not empty); the
+// values past the end are zeroed when they are staged, so that the loads are
+// not waited for here.
+template <int KB, int EPL, typename T>
+__device__ __forceinline__ void blk_entries(int b, int e, int q, const int32_t *__restrict__ col,
+                                            const T *__restrict__ val, int (&c)[EPL], T (&v)[EPL]) {
+    const int last = e > b ? e - 1 : b;
 #pragma unroll
-            for (int u = 0; u < CH; ++u) s += a[u] * g[u];
-        }
+    for (int m = 0; m < EPL; ++m) {
+        const int t = b + q + m * KB;
+        const int idx = t < last ? t : last;
+        c[m] = ldnt(col + idx);
+        v[m] = ldnt(val + idx);
     }
-    return s;
 }
 
 // Streams the rows of one KB-lane group (rows base + grp + it*stride, it <
-// iters) as a software pipeline: while the gathers of the current row are in
-// flight, the first KB entries of the next row, the row range of the one
-// after, and the current row's epilogue operands (ld) are already loaded, so
-// a row costs about one memory round trip instead of four.  fin(row, s, pre)
-// consumes the row product s = sum_q val_q xf(col_q); rows longer than KB
-// finish with blk_row.  Uniform per group: every lane of the group runs the
-// same rows (lanes with `on` false load entries but skip gathers).
+// iters).  Per row: the loads of the next row's entries, of the range of the
+// row after it and of the row's epilogue operands (ld) are issued first;
+// every lane then reads the row's staged entries back from the group's LDS
+// slot (SE = max(KB, kBlkStage) entries, EPL per lane) with wide broadcast
+// reads, all issued before one wait, and the kBlkChunk gathers of the first
+// chunk go out together, unconditionally (padding entries re-gather the
+// row's last column with value 0, so xf must address a valid column in
+// every lane).  The wait for them therefore drains every load of the row on
+// all paths; after fin the group stages the next row's entries (already
+// loaded), and nothing is waited for at the top of the next row -- in
+// particular not the row's stores, which complete while the next row's
+// gathers are in flight.  Entries past the first SE of a long row are
+// loaded and staged SE at a time.  xf(c) is the lane's gathered value of
+// column c: one T, or a BV of the lane's VW columns; fin(row, s, pre)
+// consumes the row product s = sum_q val_q xf(col_q), added in entry order
+// as in the single-vector kernels.  Every lane of the group runs the same
+// rows.
 template <int KB, typename T, typename XF, typename LD, typename FIN>
-__device__ __forceinline__ void blk_rows(int n, int iters, int base, int stride, int grp, int lane, bool on,
+__device__ __forceinline__ void blk_rows(int n, int iters, int base, int stride, int grp, int lane,
                                          const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                          const T *__restrict__ val, XF xf, LD ld, FIN fin) {
-    constexpr int CH = KB < kBlkChunk ? KB : kBlkChunk;
+    constexpr int SE = KB > kBlkStage ? KB : kBlkStage;
+    constexpr int EPL = SE / KB;
+    constexpr int CH = kBlkChunk;
+    constexpr int RPP = kBlock / KB;
+    static_assert(SE % CH == 0 && CH % 4 == 0, "chunks of whole 16-byte LDS reads");
+    constexpr int VPR = 16 / (int)sizeof(T);   // values per 16-byte read
+    using G = decltype(xf(0));
+    __shared__ __align__(16) int32_t s_col[RPP * SE];
+    __shared__ __align__(16) T s_val[RPP * SE];
+    int32_t *gcol = s_col + grp * SE;
+    T *gval = s_val + grp * SE;
     int row = base + grp;
     if (iters <= 0 || row >= n) return;
     int rb = rp[row], re = rp[row + 1];
-    int mc = 0;
-    T mv = T(0);
-    if (lane < re - rb) {
-        mc = ldnt(col + rb + lane);
-        mv = ldnt(val + rb + lane);
-    }
+    int mc[EPL];
+    T mv[EPL];
+    blk_entries<KB>(rb, re, lane, col, val, mc, mv);
     int nrow = row + stride;
     bool hn = iters > 1 && nrow < n;
     int nb = 0, ne = 0;
@@ -182,14 +235,45 @@ __device__ __forceinline__ void blk_rows(int n, int iters, int base, int stride,
         nb = rp[nrow];
         ne = rp[nrow + 1];
     }
+    // the staged entries q0 .. q0+CH-1: their values, gathers and products
+    auto chunk = [&](int q0, G &s) {
+        int c[CH];
+        T a[CH];
+#pragma unroll
+        for (int u = 0; u < CH; u += 4) {
+            const int4 c4 = *reinterpret_cast<const int4 *>(gcol + q0 + u);
+            c[u] = c4.x;
+            c[u + 1] = c4.y;
+            c[u + 2] = c4.z;
+            c[u + 3] = c4.w;
+        }
+#pragma unroll
+        for (int u = 0; u < CH; u += VPR) {
+            const int4 v4 = *reinterpret_cast<const int4 *>(gval + q0 + u);
+            const T *vv = reinterpret_cast<const T *>(&v4);
+#pragma unroll
+            for (int w = 0; w < VPR; ++w) a[u + w] = vv[w];
+        }
+        G g[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) g[u] = xf(c[u]);
+#pragma unroll
+        for (int u = 0; u < CH; ++u) bv_fma(s, a[u], g[u]);
+    };
+    // the first SE entries of the row [b, e) into the group's LDS slot
+    auto stage = [&](int b, int e, const int (&c)[EPL], const T (&v)[EPL]) {
+#pragma unroll
+        for (int m = 0; m < EPL; ++m) {
+            gcol[lane + m * KB] = c[m];
+            gval[lane + m * KB] = b + lane + m * KB < e ? v[m] : T(0);
+        }
+    };
+    stage(rb, re, mc, mv);
     for (int it = 0;;) {
         // prefetch: entries of the next row, range of the row after it
-        int mc2 = 0;
-        T mv2 = T(0);
-        if (hn && lane < ne - nb) {
-            mc2 = ldnt(col + nb + lane);
-            mv2 = ldnt(val + nb + lane);
-        }
+        int mc2[EPL] = {};
+        T mv2[EPL] = {};
+        if (hn) blk_entries<KB>(nb, ne, lane, col, val, mc2, mv2);
         const int nnrow = nrow + stride;
         const bool hnn = hn && it + 2 < iters && nnrow < n;
         int nnb = 0, nne = 0;
@@ -198,29 +282,25 @@ __device__ __forceinline__ void blk_rows(int n, int iters, int base, int stride,
             nne = rp[nnrow + 1];
         }
         const auto pre = ld(row);
-        const int cnt = re - rb < KB ? re - rb : KB;
-        T s = T(0);
-        for (int q0 = 0; q0 < cnt; q0 += CH) {
-            T a[CH], g[CH];
-#pragma unroll
-            for (int u = 0; u < CH; ++u) {
-                const int q = q0 + u;   // < KB: CH divides KB and q0 < cnt <= KB
-                const int c = __shfl(mc, q, KB);
-                a[u] = __shfl(mv, q, KB);
-                g[u] = (on && q < cnt) ? xf(c) : T(0);
-            }
-#pragma unroll
-            for (int u = 0; u < CH; ++u) s += a[u] * g[u];
+        const int cnt = re - rb < SE ? re - rb : SE;
+        G s{};
+        chunk(0, s);
+        for (int q0 = CH; q0 < cnt; q0 += CH) chunk(q0, s);
+        for (int b0 = rb + SE; b0 < re; b0 += SE) {   // rows longer than SE
+            int c1[EPL];
+            T v1[EPL];
+            blk_entries<KB>(b0, re, lane, col, val, c1, v1);
+            stage(b0, re, c1, v1);
+            const int cnt1 = re - b0 < SE ? re - b0 : SE;
+            for (int q0 = 0; q0 < cnt1; q0 += CH) chunk(q0, s);
         }
-        if (re - rb > KB) s += blk_row<KB>(rb + KB, re, lane, on, col, val, xf, [](int) { return T(1); });
         fin(row, s, pre);
         if (!hn) break;
+        stage(nb, ne, mc2, mv2);
         ++it;
         row = nrow;
         rb = nb;
         re = ne;
-        mc = mc2;
-        mv = mv2;
         nrow = nnrow;
         hn = hnn;
         nb = nnb;
@@ -241,6 +321,25 @@ __device__ __forceinline__ void blk_store_partial(double acc, double *partials, 
         double s = 0.0;
 #pragma unroll
         for (int g = 0; g < RPP; ++g) s += red[g * KB + threadIdx.x];
+        partials[(size_t)c * nbs + tile] = s;
+    }
+}
+
+// blk_store_partial for lanes owning VW columns each
+template <int KB, int VW>
+__device__ __forceinline__ void blk_store_partial_v(const BV<double, VW> &acc, double *partials, int nbs, int k,
+                                                    int panel, unsigned tile) {
+    constexpr int RPP = kBlock / KB;
+    __shared__ double red[VW][kBlock];
+#pragma unroll
+    for (int w = 0; w < VW; ++w) red[w][threadIdx.x] = acc.v[w];
+    __syncthreads();
+    const int q = (int)threadIdx.x;   // column of the panel
+    const int c = panel * KB * VW + q;
+    if (q < KB * VW && c < k) {
+        double s = 0.0;
+#pragma unroll
+        for (int g = 0; g < RPP; ++g) s += red[q % VW][g * KB + q / VW];
         partials[(size_t)c * nbs + tile] = s;
     }
 }
@@ -271,7 +370,8 @@ enum { kBR = 0, kBX2 = 1, kBPostA = 2, kBZ = 3 };
 // One pass over a level matrix for every column: r = b - A x with x either a
 // stored block (GDB false) or the first smoothing step a D^-1 b rebuilt on
 // the fly (GDB true); the epilogue per MODE matches the single-vector pass.
-template <typename T, typename BT, typename OT, bool GDB, int MODE>
+// A lane owns VW consecutive columns.
+template <typename T, typename BT, typename OT, bool GDB, int MODE, int VW>
 struct BlkOps {
     const T *d;
     const BT *b;
@@ -282,102 +382,137 @@ struct BlkOps {
     OT *out1;
     T *out2;
     int k;
-    // gathered value of column c for lane j: the first smoothing step
-    // a d_c b_c rebuilt on the fly (GDB) or the stored block
-    __device__ __forceinline__ T gather(int c, int j) const {
-        const size_t ec = (size_t)c * k + j;
-        if (GDB) return a * d[c] * (T)b[ec];
-        return g[ec];
+    using VT = dev::BV<T, VW>;
+    // gathered values of row c for the lane's columns from jg: the first
+    // smoothing step a d_c b_c rebuilt on the fly (GDB) or the stored block
+    __device__ __forceinline__ VT gather(int c, int jg) const {
+        const size_t ec = (size_t)c * k + jg;
+        if constexpr (GDB) {
+            const auto bb = dev::ldv<BT, VW>(b + ec);
+            const T f = a * d[c];
+            VT r;
+#pragma unroll
+            for (int w = 0; w < VW; ++w) r.v[w] = f * (T)bb.v[w];
+            return r;
+        } else {
+            return dev::ldv<T, VW>(g + ec);
+        }
     }
     // epilogue operands of row i, loaded before the row's gathers
     struct Pre {
-        BT bi;
-        T di, xpi, ui;
+        dev::BV<BT, VW> bi;
+        T di;
+        VT xpi, ui;
     };
     __device__ __forceinline__ Pre load(int i, size_t e) const {
         Pre p{};
-        p.bi = b[e];
+        p.bi = dev::ldv<BT, VW>(b + e);
         if (MODE != kBR) p.di = d[i];
-        if (MODE == kBZ) {
-            p.xpi = xp[e];
-            if (u) p.ui = u[e];
-        }
+        if (MODE == kBPostA || MODE == kBZ) p.xpi = dev::ldv<T, VW>(xp + e);
+        if (MODE == kBZ && u) p.ui = dev::ldv<T, VW>(u + e);
         return p;
     }
-    __device__ __forceinline__ double finish(int i, size_t e, T s, const Pre &p) const {
-        const BT bi = p.bi;
-        const T r = (T)bi - s;
-        if (MODE == kBR) {
-            out1[e] = (OT)r;
-        } else if (MODE == kBX2) {
-            out1[e] = (OT)(p.di * (c1 * (T)bi + c2 * r));
-        } else if (MODE == kBPostA) {
-            out1[e] = (OT)r;
-            out2[e] = xp[e] + a * p.di * r;
-        } else {
-            T w = c2 * r;
-            if (u) w += c1 * p.ui;
-            const T z = p.xpi + p.di * w;
-            out1[e] = (OT)z;
-            return (double)bi * (double)z;
+    // stores the row's outputs; returns b.z per column (kBZ)
+    __device__ __forceinline__ dev::BV<double, VW> finish(size_t e, const VT &s, const Pre &p) const {
+        dev::BV<double, VW> dot{};
+        dev::BV<OT, VW> o1;
+        VT o2;
+#pragma unroll
+        for (int w = 0; w < VW; ++w) {
+            const BT bi = p.bi.v[w];
+            const T r = (T)bi - s.v[w];
+            if (MODE == kBR) {
+                o1.v[w] = (OT)r;
+            } else if (MODE == kBX2) {
+                o1.v[w] = (OT)(p.di * (c1 * (T)bi + c2 * r));
+            } else if (MODE == kBPostA) {
+                o1.v[w] = (OT)r;
+                o2.v[w] = p.xpi.v[w] + a * p.di * r;
+            } else {
+                T wv = c2 * r;
+                if (u) wv += c1 * p.ui.v[w];
+                const T z = p.xpi.v[w] + p.di * wv;
+                o1.v[w] = (OT)z;
+                dot.v[w] = (double)bi * (double)z;
+            }
         }
-        return 0.0;
+        dev::stv(out1 + e, o1);
+        if (MODE == kBPostA) dev::stv(out2 + e, o2);
+        return dot;
     }
 };
 
-template <int KB, typename T, typename BT, typename OT, bool GDB, int MODE, bool DOT>
+template <int KB, int VW, typename T, typename BT, typename OT, bool GDB, int MODE, bool DOT>
 __global__ void __launch_bounds__(kBlock) k_blk_smooth(int32_t n, int k, BlkT bt, const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ col, const T *__restrict__ val,
-                                                       BlkOps<T, BT, OT, GDB, MODE> ops, const CgBlock *cgb,
+                                                       BlkOps<T, BT, OT, GDB, MODE, VW> ops, const CgBlock *cgb,
                                                        double *partials, int nbs) {
     if (cgb && cgb->flag) return;
-    double acc = 0.0;
-    using Pre = typename BlkOps<T, BT, OT, GDB, MODE>::Pre;
-    OCP_BLKGRP(KB)
+    dev::BV<double, VW> acc{};
+    using Ops = BlkOps<T, BT, OT, GDB, MODE, VW>;
+    OCP_BLKV_TILE(KB, VW)
     dev::blk_rows<KB>(
-        n, iters, base, stride, grp, lane, on, rp, col, val, [&](int c) { return ops.gather(c, j); },
-        [&](int row) { return on ? ops.load(row, (size_t)row * k + j) : Pre{}; },
-        [&](int row, T s, const Pre &pre) {
+        n, iters, base, stride, grp, lane, rp, col, val, [&](int c) { return ops.gather(c, jg); },
+        [&](int row) { return ops.load(row, (size_t)row * k + jg); },
+        [&](int row, const typename Ops::VT &s, const typename Ops::Pre &pre) {
             if (on) {
-                const double c = ops.finish(row, (size_t)row * k + j, s, pre);
-                if (DOT) acc += c;
+                const auto c = ops.finish((size_t)row * k + j0, s, pre);
+                if (DOT)
+#pragma unroll
+                    for (int w = 0; w < VW; ++w) acc.v[w] += c.v[w];
             }
         });
-    if (DOT) dev::blk_store_partial<KB>(acc, partials, nbs, k, panel, tile);
+    if (DOT) dev::blk_store_partial_v<KB, VW>(acc, partials, nbs, k, panel, tile);
 }
 
 // y = M x for every column (restriction with R = P^T)
-template <int KB, typename T>
+template <int KB, int VW, typename T>
 __global__ void __launch_bounds__(kBlock) k_blk_spmv(int32_t n, int k, BlkT bt, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ col, const T *__restrict__ val,
                                                      const T *__restrict__ x, T *__restrict__ y, const CgBlock *cgb) {
     if (cgb && cgb->flag) return;
-    OCP_BLKGRP(KB)
+    using VT = dev::BV<T, VW>;
+    OCP_BLKV_TILE(KB, VW)
     dev::blk_rows<KB>(
-        n, iters, base, stride, grp, lane, on, rp, col, val, [&](int c) { return x[(size_t)c * k + j]; },
+        n, iters, base, stride, grp, lane, rp, col, val, [&](int c) { return dev::ldv<T, VW>(x + (size_t)c * k + jg); },
         [](int) { return 0; },
-        [&](int row, T s, int) {
-            if (on) y[(size_t)row * k + j] = s;
+        [&](int row, const VT &s, int) {
+            if (on) dev::stv(y + (size_t)row * k + j0, s);
         });
 }
 
 // xp = base + P xc, base = the stored pre-smoothed block (HX) or a d .* b
-template <int KB, typename T, typename BT, bool HX>
+template <int KB, int VW, typename T, typename BT, bool HX>
 __global__ void __launch_bounds__(kBlock) k_blk_prolong(int32_t n, int k, BlkT bt, const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ col, const T *__restrict__ val,
                                                         const T *__restrict__ d, const BT *__restrict__ b,
                                                         const T *__restrict__ xs, T a, const T *__restrict__ xc,
                                                         T *__restrict__ xp, const CgBlock *cgb) {
     if (cgb && cgb->flag) return;
-    OCP_BLKGRP(KB)
+    using VT = dev::BV<T, VW>;
+    OCP_BLKV_TILE(KB, VW)
     dev::blk_rows<KB>(
-        n, iters, base, stride, grp, lane, on, rp, col, val, [&](int c) { return xc[(size_t)c * k + j]; },
+        n, iters, base, stride, grp, lane, rp, col, val, [&](int c) { return dev::ldv<T, VW>(xc + (size_t)c * k + jg); },
         [&](int row) {
-            const size_t e = (size_t)row * k + j;
-            return on ? (HX ? xs[e] : a * d[row] * (T)b[e]) : T(0);
+            const size_t e = (size_t)row * k + jg;
+            if constexpr (HX) {
+                return dev::ldv<T, VW>(xs + e);
+            } else {
+                const auto bb = dev::ldv<BT, VW>(b + e);
+                const T f = a * d[row];
+                VT r;
+#pragma unroll
+                for (int w = 0; w < VW; ++w) r.v[w] = f * (T)bb.v[w];
+                return r;
+            }
         },
-        [&](int row, T s, T base_v) {
-            if (on) xp[(size_t)row * k + j] = base_v + s;
+        [&](int row, const VT &s, const VT &base_v) {
+            if (on) {
+                VT o;
+#pragma unroll
+                for (int w = 0; w < VW; ++w) o.v[w] = base_v.v[w] + s.v[w];
+                dev::stv(xp + (size_t)row * k + j0, o);
+            }
         });
 }
 
@@ -440,26 +575,29 @@ __global__ void __launch_bounds__(kBlock) k_blk_init(int32_t n, int k, BlkT bt, 
     dev::blk_store_partial<KB>(acc, partials, nbs, k, panel, tile);
 }
 
-// Q = A P (FP64 CSR) and p.q per column
-template <int KB>
+// Q = A P and p.q per column, lanes owning VW columns (k a multiple of VW)
+template <int KB, int VW>
 __global__ void __launch_bounds__(kBlock) k_blk_spmm_pq(int32_t n, int k, BlkT bt, const int32_t *__restrict__ rp,
-                                                        const int32_t *__restrict__ col,
-                                                        const double *__restrict__ val, const double *__restrict__ P,
-                                                        double *__restrict__ Q, const CgBlock *cgb, double *partials,
-                                                        int nbs) {
+                                                          const int32_t *__restrict__ col,
+                                                          const double *__restrict__ val,
+                                                          const double *__restrict__ P, double *__restrict__ Q,
+                                                          const CgBlock *cgb, double *partials, int nbs) {
     if (cgb->flag) return;
-    double acc = 0.0;
-    OCP_BLKGRP(KB)
+    using V = dev::BV<double, VW>;
+    V acc{};
+    OCP_BLKV_TILE(KB, VW)
     dev::blk_rows<KB>(
-        n, iters, base, stride, grp, lane, on, rp, col, val, [&](int c) { return P[(size_t)c * k + j]; },
-        [&](int row) { return on ? P[(size_t)row * k + j] : 0.0; },
-        [&](int row, double s, double pi) {
+        n, iters, base, stride, grp, lane, rp, col, val,
+        [&](int c) { return dev::ldv<double, VW>(P + (size_t)c * k + jg); },
+        [&](int row) { return dev::ldv<double, VW>(P + (size_t)row * k + jg); },
+        [&](int row, const V &s, const V &pi) {
             if (on) {
-                Q[(size_t)row * k + j] = s;
-                acc += pi * s;
+                dev::stv(Q + (size_t)row * k + j0, s);
+#pragma unroll
+                for (int w = 0; w < VW; ++w) acc.v[w] += pi.v[w] * s.v[w];
             }
         });
-    dev::blk_store_partial<KB>(acc, partials, nbs, k, panel, tile);
+    dev::blk_store_partial_v<KB, VW>(acc, partials, nbs, k, panel, tile);
 }
 
 // F - A X per column, squared norm (true residual at exit; every column)
@@ -473,7 +611,7 @@ __global__ void __launch_bounds__(kBlock) k_blk_resid2(int32_t n, int k, BlkT bt
     double acc = 0.0;
     OCP_BLKGRP(KB)
     dev::blk_rows<KB>(
-        n, iters, base, stride, grp, lane, on, rp, col, val, [&](int c) { return X[(size_t)c * k + j]; },
+        n, iters, base, stride, grp, lane, rp, col, val, [&](int c) { return X[(size_t)c * k + jg]; },
         [&](int row) { return on ? F[(size_t)row * fs_row + (size_t)j * fs_col] : 0.0; },
         [&](int row, double s, double fi) {
             (void)row;
@@ -692,7 +830,7 @@ struct BlkCtx {
 
 // Z = B R for the k columns.  Returns the number of blocks whose r.z
 // partials the last pass stored (0 if cgb is null).
-template <int KB, typename T>
+template <int KB, int VW, typename T>
 static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *R, double *Z, const BlkCtx &bc) {
     const auto &lv = h->levels;
     const int L = (int)lv.size();
@@ -722,7 +860,7 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
         const Level &cur = *lv[l];
         const Level &nxt = *lv[l + 1];
         const auto a = blk_arrays<T>(cur);
-        const BlkLaunch LB = blk_launch(cur.n, KB, k);
+        const BlkLaunch LB = blk_launch(cur.n, KB, k, VW);
         T *rres = lvec(l, &BlkLevelWork::vr);
         T *x2 = lvec(l, &BlkLevelWork::vx2);
         const T ca = (T)cur.cheb_a, c1 = (T)cur.cheb_c1, c2 = (T)cur.cheb_c2;
@@ -731,33 +869,33 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
             const T *y0 = l == 0 ? static_cast<const T *>(bc.y0) : nullptr;
             if (y0) {   // the first step is stored: plain passes gathering it
                 if (cur.deg == 2) {
-                    k_blk_smooth<KB, T, BT, T, false, kBX2, false><<<LB.blocks, kBlock, 0, s>>>(
+                    k_blk_smooth<KB, VW, T, BT, T, false, kBX2, false><<<LB.blocks, kBlock, 0, s>>>(
                         cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
-                        BlkOps<T, BT, T, false, kBX2>{a.d, bptr, y0, nullptr, nullptr, ca, c1, c2, x2, nullptr, k},
+                        BlkOps<T, BT, T, false, kBX2, VW>{a.d, bptr, y0, nullptr, nullptr, ca, c1, c2, x2, nullptr, k},
                         cgb, nullptr, 0);
-                    k_blk_smooth<KB, T, BT, T, false, kBR, false><<<LB.blocks, kBlock, 0, s>>>(
+                    k_blk_smooth<KB, VW, T, BT, T, false, kBR, false><<<LB.blocks, kBlock, 0, s>>>(
                         cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
-                        BlkOps<T, BT, T, false, kBR>{a.d, bptr, x2, nullptr, nullptr, ca, c1, c2, rres, nullptr, k},
+                        BlkOps<T, BT, T, false, kBR, VW>{a.d, bptr, x2, nullptr, nullptr, ca, c1, c2, rres, nullptr, k},
                         cgb, nullptr, 0);
                 } else {
-                    k_blk_smooth<KB, T, BT, T, false, kBR, false><<<LB.blocks, kBlock, 0, s>>>(
+                    k_blk_smooth<KB, VW, T, BT, T, false, kBR, false><<<LB.blocks, kBlock, 0, s>>>(
                         cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
-                        BlkOps<T, BT, T, false, kBR>{a.d, bptr, y0, nullptr, nullptr, ca, c1, c2, rres, nullptr, k},
+                        BlkOps<T, BT, T, false, kBR, VW>{a.d, bptr, y0, nullptr, nullptr, ca, c1, c2, rres, nullptr, k},
                         cgb, nullptr, 0);
                 }
             } else if (cur.deg == 2) {
-                k_blk_smooth<KB, T, BT, T, true, kBX2, false><<<LB.blocks, kBlock, 0, s>>>(
+                k_blk_smooth<KB, VW, T, BT, T, true, kBX2, false><<<LB.blocks, kBlock, 0, s>>>(
                     cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
-                    BlkOps<T, BT, T, true, kBX2>{a.d, bptr, nullptr, nullptr, nullptr, ca, c1, c2, x2, nullptr, k},
+                    BlkOps<T, BT, T, true, kBX2, VW>{a.d, bptr, nullptr, nullptr, nullptr, ca, c1, c2, x2, nullptr, k},
                     cgb, nullptr, 0);
-                k_blk_smooth<KB, T, BT, T, false, kBR, false><<<LB.blocks, kBlock, 0, s>>>(
+                k_blk_smooth<KB, VW, T, BT, T, false, kBR, false><<<LB.blocks, kBlock, 0, s>>>(
                     cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
-                    BlkOps<T, BT, T, false, kBR>{a.d, bptr, x2, nullptr, nullptr, ca, c1, c2, rres, nullptr, k}, cgb,
+                    BlkOps<T, BT, T, false, kBR, VW>{a.d, bptr, x2, nullptr, nullptr, ca, c1, c2, rres, nullptr, k}, cgb,
                     nullptr, 0);
             } else {
-                k_blk_smooth<KB, T, BT, T, true, kBR, false><<<LB.blocks, kBlock, 0, s>>>(
+                k_blk_smooth<KB, VW, T, BT, T, true, kBR, false><<<LB.blocks, kBlock, 0, s>>>(
                     cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
-                    BlkOps<T, BT, T, true, kBR>{a.d, bptr, nullptr, nullptr, nullptr, ca, c1, c2, rres, nullptr, k},
+                    BlkOps<T, BT, T, true, kBR, VW>{a.d, bptr, nullptr, nullptr, nullptr, ca, c1, c2, rres, nullptr, k},
                     cgb, nullptr, 0);
             }
             OCP_LAUNCH_CHECK();
@@ -766,8 +904,8 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
             run_down(R);
         else
             run_down(static_cast<const T *>(lvec(l, &BlkLevelWork::vb)));
-        const BlkLaunch LR = blk_launch(nxt.n, KB, k);
-        k_blk_spmv<KB, T><<<LR.blocks, kBlock, 0, s>>>(nxt.n, k, LR.t, cur.R_rp.get(), cur.R_col.get(), a.R, rres,
+        const BlkLaunch LR = blk_launch(nxt.n, KB, k, VW);
+        k_blk_spmv<KB, VW, T><<<LR.blocks, kBlock, 0, s>>>(nxt.n, k, LR.t, cur.R_rp.get(), cur.R_col.get(), a.R, rres,
                                                        lvec(l + 1, &BlkLevelWork::vb), cgb);
         OCP_LAUNCH_CHECK();
     }
@@ -789,7 +927,7 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
     for (int l = L - 2; l >= 0; --l) {
         const Level &cur = *lv[l];
         const auto a = blk_arrays<T>(cur);
-        const BlkLaunch LB = blk_launch(cur.n, KB, k);
+        const BlkLaunch LB = blk_launch(cur.n, KB, k, VW);
         const T *xc = lvec(l + 1, &BlkLevelWork::vx);
         T *xp = lvec(l, &BlkLevelWork::vxp);
         T *x2 = lvec(l, &BlkLevelWork::vx2);
@@ -802,27 +940,27 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
             using OT = std::remove_pointer_t<decltype(outptr)>;
             constexpr bool DOT = decltype(dot_tag)::value;
             if (cur.deg == 2)
-                k_blk_prolong<KB, T, BT, true><<<LB.blocks, kBlock, 0, s>>>(cur.n, k, LB.t, cur.P_rp.get(),
+                k_blk_prolong<KB, VW, T, BT, true><<<LB.blocks, kBlock, 0, s>>>(cur.n, k, LB.t, cur.P_rp.get(),
                                                                           cur.P_col.get(), a.P, a.d, bptr, x2, ca,
                                                                           xc, xp, cgb);
             else
-                k_blk_prolong<KB, T, BT, false><<<LB.blocks, kBlock, 0, s>>>(cur.n, k, LB.t, cur.P_rp.get(),
+                k_blk_prolong<KB, VW, T, BT, false><<<LB.blocks, kBlock, 0, s>>>(cur.n, k, LB.t, cur.P_rp.get(),
                                                                            cur.P_col.get(), a.P, a.d, bptr, nullptr,
                                                                            ca, xc, xp, cgb);
             OCP_LAUNCH_CHECK();
             if (cur.deg == 2) {
-                k_blk_smooth<KB, T, BT, T, false, kBPostA, false><<<LB.blocks, kBlock, 0, s>>>(
+                k_blk_smooth<KB, VW, T, BT, T, false, kBPostA, false><<<LB.blocks, kBlock, 0, s>>>(
                     cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
-                    BlkOps<T, BT, T, false, kBPostA>{a.d, bptr, xp, xp, nullptr, ca, c1, c2, r0, x1, k}, cgb, nullptr,
+                    BlkOps<T, BT, T, false, kBPostA, VW>{a.d, bptr, xp, xp, nullptr, ca, c1, c2, r0, x1, k}, cgb, nullptr,
                     0);
-                k_blk_smooth<KB, T, BT, OT, false, kBZ, DOT><<<LB.blocks, kBlock, 0, s>>>(
+                k_blk_smooth<KB, VW, T, BT, OT, false, kBZ, DOT><<<LB.blocks, kBlock, 0, s>>>(
                     cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
-                    BlkOps<T, BT, OT, false, kBZ>{a.d, bptr, x1, xp, r0, ca, c1, c2, outptr, nullptr, k}, cgb,
+                    BlkOps<T, BT, OT, false, kBZ, VW>{a.d, bptr, x1, xp, r0, ca, c1, c2, outptr, nullptr, k}, cgb,
                     DOT ? bc.part : nullptr, bc.nbs);
             } else {
-                k_blk_smooth<KB, T, BT, OT, false, kBZ, DOT><<<LB.blocks, kBlock, 0, s>>>(
+                k_blk_smooth<KB, VW, T, BT, OT, false, kBZ, DOT><<<LB.blocks, kBlock, 0, s>>>(
                     cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
-                    BlkOps<T, BT, OT, false, kBZ>{a.d, bptr, xp, xp, nullptr, ca, zero, ca, outptr, nullptr, k}, cgb,
+                    BlkOps<T, BT, OT, false, kBZ, VW>{a.d, bptr, xp, xp, nullptr, ca, zero, ca, outptr, nullptr, k}, cgb,
                     DOT ? bc.part : nullptr, bc.nbs);
             }
             OCP_LAUNCH_CHECK();
@@ -840,11 +978,24 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
     return fin_nb;
 }
 
+// Columns per lane of the block V-cycle's gather passes in precision T:
+// 16-byte accesses when k allows them, else one column per lane.
+template <typename T>
+static int blk_vw(int k) {
+    constexpr int V = 16 / (int)sizeof(T);
+    return k % V == 0 ? V : 1;
+}
+
 template <typename T>
 static unsigned vcycle_block(ocp_ctx *ctx, const ocp_hierarchy *h, const double *R, double *Z, const BlkCtx &bc,
                              int kb) {
+    constexpr int V = 16 / (int)sizeof(T);
     unsigned nb = 0;
-    OCP_DISPATCH_KB(kb, (nb = vcycle_block_t<KB, T>(ctx, h, R, Z, bc)));
+    if (blk_vw<T>(bc.k) == V) {
+        OCP_DISPATCH_KB(kb, (nb = vcycle_block_t<KB, V, T>(ctx, h, R, Z, bc)));
+    } else {
+        OCP_DISPATCH_KB(kb, (nb = vcycle_block_t<KB, 1, T>(ctx, h, R, Z, bc)));
+    }
     return nb;
 }
 
@@ -898,6 +1049,9 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
                         double rtol, int32_t maxit, int32_t flags, ocp_solve_info *infos, int *status) {
     const int32_t n = sys->n;
     const int KB0 = lanes_for_cols(k);   // one panel: elementwise CG kernels
+    // the SpMM's lanes own column pairs (16-byte gathers) when k is even
+    const int vw_mm = k % 2 == 0 ? 2 : 1;
+    const int KBM = vw_mm == 2 ? lanes_for_cols(k / 2) : KB0;
     const int64_t fs_row = F ? k : 1;
     const int fs_col = F ? 1 : 0;
     const double *Fp = F ? F : sys->f.get();
@@ -943,13 +1097,16 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
         slot.compare_exchange_strong(expected, kb, std::memory_order_acq_rel);
         return slot.load(std::memory_order_acquire);
     };
-    int kb_vc = KB0;
+    // lanes per row of the V-cycle's gather passes: VW columns each
+    const int vw_vc = !h ? 1 : mixed ? blk_vw<float>(k) : blk_vw<double>(k);
+    const int KBV = lanes_for_cols(k / vw_vc);
+    int kb_vc = KBV;
     if (h) {
         const int cached = kb_vc_slot->load(std::memory_order_acquire);
-        kb_vc = forced ? forced : (cached ? cached : KB0);
+        kb_vc = forced ? std::min(forced, KBV) : (cached ? cached : KBV);
     }
     const int cached_mm = kb_mm_slot.load(std::memory_order_acquire);
-    int kb_mm = forced ? forced : (cached_mm ? cached_mm : KB0);
+    int kb_mm = forced ? std::min(forced, KBM) : (cached_mm ? cached_mm : KBM);
 
     auto precond = [&](void) {
         if (h) {
@@ -968,9 +1125,14 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
         OCP_LAUNCH_CHECK();
     };
     auto spmm = [&](int kb) {
-        const BlkLaunch LS = blk_launch(n, kb, k);
-        OCP_DISPATCH_KB(kb, (k_blk_spmm_pq<KB><<<LS.blocks, kBlock, 0, s>>>(n, k, LS.t, rp, ci, av, P.get(), Q.get(),
-                                                                         cgb, part0.get(), nbs)));
+        const BlkLaunch LS = blk_launch(n, kb, k, vw_mm);
+        if (vw_mm == 2) {
+            OCP_DISPATCH_KB(kb, (k_blk_spmm_pq<KB, 2><<<LS.blocks, kBlock, 0, s>>>(
+                                    n, k, LS.t, rp, ci, av, P.get(), Q.get(), cgb, part0.get(), nbs)));
+        } else {
+            OCP_DISPATCH_KB(kb, (k_blk_spmm_pq<KB, 1><<<LS.blocks, kBlock, 0, s>>>(
+                                    n, k, LS.t, rp, ci, av, P.get(), Q.get(), cgb, part0.get(), nbs)));
+        }
         OCP_LAUNCH_CHECK();
         return LS.t.tiles;
     };
@@ -995,36 +1157,59 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
     // the first V-cycle (the outputs of these launches are overwritten before
     // they are read), so that every solve of the shape uses the same kernels
     if (!forced && hs.flag == 0) {
-        if (!kb_mm_slot.load(std::memory_order_acquire)) publish(kb_mm_slot, tune_kb(ctx, KB0, spmm));
+        if (!kb_mm_slot.load(std::memory_order_acquire)) publish(kb_mm_slot, tune_kb(ctx, KBM, spmm));
         kb_mm = kb_mm_slot.load(std::memory_order_acquire);
         if (h && !kb_vc_slot->load(std::memory_order_acquire)) {
             const Level &l0 = *h->levels[0];
             if (h->levels.size() > 1) {
-                publish(*kb_vc_slot, tune_kb(ctx, KB0, [&](int kb) {
+                // one FP32 (VW 1 or 4) or FP64 (VW 1 or 2) level-0 pass per width
+                auto trial = [&](int kb, auto vw_tag) {
+                    constexpr int VW = decltype(vw_tag)::value;
                     OCP_DISPATCH_KB(kb, ({
-                        const BlkLaunch LV = blk_launch(l0.n, KB, k);
-                        if (mixed) {
-                            float *x2 = reinterpret_cast<float *>(work[0].vx2.get());
-                            float *rr = reinterpret_cast<float *>(work[0].vr.get());
-                            k_blk_smooth<KB, float, double, float, false, kBR, false><<<LV.blocks, kBlock, 0, s>>>(
-                                l0.n, k, LV.t, l0.A_rp, l0.A_col, l0.A_val32.get(),
-                                BlkOps<float, double, float, false, kBR>{l0.dinv32.get(), R.get(), x2, nullptr,
-                                                                        nullptr, 0.f, 0.f, 0.f, rr, nullptr, k},
-                                cgb, nullptr, 0);
-                        } else {
-                            double *x2 = reinterpret_cast<double *>(work[0].vx2.get());
-                            double *rr = reinterpret_cast<double *>(work[0].vr.get());
-                            k_blk_smooth<KB, double, double, double, false, kBR, false><<<LV.blocks, kBlock, 0, s>>>(
-                                l0.n, k, LV.t, l0.A_rp, l0.A_col, l0.A_val,
-                                BlkOps<double, double, double, false, kBR>{l0.dinv.get(), R.get(), x2, nullptr,
-                                                                           nullptr, 0.0, 0.0, 0.0, rr, nullptr, k},
-                                cgb, nullptr, 0);
-                        }
+                        const BlkLaunch LV = blk_launch(l0.n, KB, k, VW);
+                        auto f32 = [&]() {
+                            if constexpr (VW != 2) {
+                                float *x2 = reinterpret_cast<float *>(work[0].vx2.get());
+                                float *rr = reinterpret_cast<float *>(work[0].vr.get());
+                                k_blk_smooth<KB, VW, float, double, float, false, kBR, false>
+                                    <<<LV.blocks, kBlock, 0, s>>>(
+                                        l0.n, k, LV.t, l0.A_rp, l0.A_col, l0.A_val32.get(),
+                                        BlkOps<float, double, float, false, kBR, VW>{l0.dinv32.get(), R.get(), x2,
+                                                                                    nullptr, nullptr, 0.f, 0.f, 0.f,
+                                                                                    rr, nullptr, k},
+                                        cgb, nullptr, 0);
+                            }
+                        };
+                        auto f64 = [&]() {
+                            if constexpr (VW != 4) {
+                                double *x2 = reinterpret_cast<double *>(work[0].vx2.get());
+                                double *rr = reinterpret_cast<double *>(work[0].vr.get());
+                                k_blk_smooth<KB, VW, double, double, double, false, kBR, false>
+                                    <<<LV.blocks, kBlock, 0, s>>>(
+                                        l0.n, k, LV.t, l0.A_rp, l0.A_col, l0.A_val,
+                                        BlkOps<double, double, double, false, kBR, VW>{l0.dinv.get(), R.get(), x2,
+                                                                                       nullptr, nullptr, 0.0, 0.0,
+                                                                                       0.0, rr, nullptr, k},
+                                        cgb, nullptr, 0);
+                            }
+                        };
+                        if (mixed)
+                            f32();
+                        else
+                            f64();
                     }));
                     OCP_LAUNCH_CHECK();
+                };
+                publish(*kb_vc_slot, tune_kb(ctx, KBV, [&](int kb) {
+                    if (vw_vc == 4)
+                        trial(kb, std::integral_constant<int, 4>{});
+                    else if (vw_vc == 2)
+                        trial(kb, std::integral_constant<int, 2>{});
+                    else
+                        trial(kb, std::integral_constant<int, 1>{});
                 }));
             } else {
-                publish(*kb_vc_slot, KB0);
+                publish(*kb_vc_slot, KBV);
             }
         }
         if (h) kb_vc = kb_vc_slot->load(std::memory_order_acquire);
@@ -1071,9 +1256,9 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
     OCP_HIP(hipEventRecord(ctx->ev1, s));
 
     // true residuals in double, then U on all vertices
-    const BlkLaunch LR = blk_launch(n, kb_mm, k);
-    OCP_DISPATCH_KB(kb_mm, (k_blk_resid2<KB><<<LR.blocks, kBlock, 0, s>>>(n, k, LR.t, rp, ci, av, X.get(), Fp,
-                                                                           fs_row, fs_col, part2.get(), nbs)));
+    const BlkLaunch LR = blk_launch(n, KB0, k);
+    OCP_DISPATCH_KB(KB0, (k_blk_resid2<KB><<<LR.blocks, kBlock, 0, s>>>(n, k, LR.t, rp, ci, av, X.get(), Fp,
+                                                                         fs_row, fs_col, part2.get(), nbs)));
     OCP_LAUNCH_CHECK();
     k_blk_scatter<<<grid_for((int64_t)sys->nv * k, 256), 256, 0, s>>>(sys->nv, k, sys->dof_of_vertex.get(), X.get(),
                                                                        U);

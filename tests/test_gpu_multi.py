@@ -56,7 +56,7 @@ def test_load_multi_matches_single_loads_and_oracle(P, ctx):
         np.testing.assert_allclose(F[:, j].cpu().numpy(), o.f, rtol=0, atol=1e-13 * np.abs(o.f).max())
 
 
-@pytest.mark.parametrize("k,N", [(1, 10), (3, 14), (9, 14), (32, 12), (64, 8)])
+@pytest.mark.parametrize("k,N", [(1, 10), (3, 14), (6, 10), (9, 14), (32, 12), (64, 8)])
 def test_multi_fp64_matches_oracle(P, ctx, k, N):
     print(f"[multi fp64] cube{N} jitter k={k}", flush=True)
     rho = 1.0 / N ** 2
@@ -134,6 +134,30 @@ def test_multi_mixed_k32_reaches_tolerance(P, ctx):
     print(f"    its {min(i.iterations for i in infos)}..{max(i.iterations for i in infos)} "
           f"max err vs fp64 oracle {max(errs):.2e}")
     assert max(errs) < 1e-6
+
+
+@pytest.mark.parametrize("k", [4, 6, 12])
+def test_multi_mixed_column_groups(P, ctx, k):
+    """Column counts that give the FP32 passes four columns per lane (4, 12)
+    or one (6), and the FP64 kernels two per lane, with lanes past k in the
+    panel: every column reaches the tolerance and the FP64 oracle."""
+    print(f"[multi mixed groups] cube14 jitter k={k}", flush=True)
+    N = 14
+    rho = 1e-2
+    mesh = I.kuhn_mesh(N, jitter=0.15, seed=41)
+    targets = _targets(k, base=4000)
+    dm = P.upload_mesh(mesh)
+    s = P.fe_assemble(ctx, dm, rho, targets[0])
+    h = P.amg_setup(ctx, s, precision=P.capi.PREC_MIXED, coarse_max=32)
+    F = s.load_multi(targets)
+    U, infos, rc = P.pcg_solve_multi(ctx, s, h, F, rtol=1e-10, maxit=500)
+    assert rc == 0, [i.as_dict() for i in infos]
+    Uh = U.cpu().numpy()
+    for j, t in enumerate(targets):
+        assert infos[j].true_rel_res <= 1.0001e-10, infos[j].as_dict()
+        x, o, _, _ = O.solve(mesh, rho, t, rtol=1e-14)
+        err = _rel(Uh[:, j], O.to_vertices(o, x, mesh.n_vertices))
+        assert err < 1e-8, (j, err)
 
 
 def test_frozen_and_zero_columns(P, ctx):

@@ -477,6 +477,11 @@ def test_error_paths(P, ctx):
     with pytest.raises(P.OcpError) as e:
         P.fe_assemble(ctx, dm3, 1.0, I.single_sine())
     assert e.value.code == P.capi.ERR_BAD_MESH
+    # the same without the load pass (the check pass tests it) and with K, M kept
+    for flags, target in ((P.capi.NO_LOAD, None), (P.capi.KEEP_KM, I.single_sine())):
+        with pytest.raises(P.OcpError) as e:
+            P.fe_assemble(ctx, dm3, 1.0, target, flags=flags)
+        assert e.value.code == P.capi.ERR_BAD_MESH, flags
     # iteration cap: status MAXIT, not an error
     s = P.fe_assemble(ctx, dm, 1.0, I.single_sine())
     u, info, rc = P.pcg_solve(ctx, s, None, rtol=1e-14, maxit=1)

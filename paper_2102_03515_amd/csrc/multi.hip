@@ -16,8 +16,10 @@
 // k.
 //
 // Every column has its own alpha, beta, gamma and stop flag on the device.  A
-// column that has converged (or broken down, or hit the cap) is frozen: its
-// lanes skip all further work, so its vectors keep their final values.  The
+// column that has converged (or broken down, or hit the cap) is frozen: the
+// CG kernels leave its X, R and P alone, so they keep their final values
+// (the gather kernels still compute it, into work vectors and partial sums
+// that a frozen column no longer reads).  The
 // V-cycle is the same polynomial-smoother cycle as the single-vector one,
 // with identical coefficients, in the hierarchy's precision; the CG
 // recurrences, dot products and the final residual are double.

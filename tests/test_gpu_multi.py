@@ -136,7 +136,7 @@ def test_multi_mixed_k32_reaches_tolerance(P, ctx):
     assert max(errs) < 1e-6
 
 
-@pytest.mark.parametrize("k", [4, 6, 12])
+@pytest.mark.parametrize("k", [1, 2, 4, 6, 12])
 def test_multi_mixed_column_groups(P, ctx, k):
     """Column counts that give the FP32 passes four columns per lane (4, 12)
     or one (6), and the FP64 kernels two per lane, with lanes past k in the
@@ -158,6 +158,31 @@ def test_multi_mixed_column_groups(P, ctx, k):
         x, o, _, _ = O.solve(mesh, rho, t, rtol=1e-14)
         err = _rel(Uh[:, j], O.to_vertices(o, x, mesh.n_vertices))
         assert err < 1e-8, (j, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_multi_single_level_hierarchy(P, ctx, prec):
+    """A mesh small enough that the hierarchy is one dense level: the block
+    cycle is the coarse solve alone (dense inverse), and every column is the
+    oracle's solution."""
+    print(f"[multi single level] cube4 jitter k=4 {prec}", flush=True)
+    N, k = 4, 4
+    rho = 1e-2
+    mesh = I.kuhn_mesh(N, jitter=0.15, seed=43)
+    targets = _targets(k, base=4100)
+    dm = P.upload_mesh(mesh)
+    s = P.fe_assemble(ctx, dm, rho, targets[0])
+    p = P.capi.PREC_FP64 if prec == "fp64" else P.capi.PREC_MIXED
+    h = P.amg_setup(ctx, s, precision=p)
+    assert h.n_levels == 1, h.n_levels
+    F = s.load_multi(targets)
+    U, infos, rc = P.pcg_solve_multi(ctx, s, h, F, rtol=1e-12, maxit=100)
+    assert rc == 0, [i.as_dict() for i in infos]
+    Uh = U.cpu().numpy()
+    for j, t in enumerate(targets):
+        x, o, _, _ = O.solve(mesh, rho, t, rtol=1e-14)
+        err = _rel(Uh[:, j], O.to_vertices(o, x, mesh.n_vertices))
+        assert err < (1e-10 if prec == "fp64" else 1e-9), (j, err)
 
 
 def test_frozen_and_zero_columns(P, ctx):

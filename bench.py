@@ -133,6 +133,13 @@ def traffic_bytes(kernel: int):
     return MEASURED_TRAFFIC.get(kernel)
 
 
+# The same two counter runs for the block SpMM k_blk_spmm_pq<16, 2> at 127^3
+# unknowns x 32 targets: FETCH 722,263 KiB x 1.99993 + WRITE 512,592 KiB
+# x 0.99997 per full dispatch (profiles/pmc_traffic_block_spmm_cube128.md).
+# Keyed by (N, k): other shapes were not measured.
+MEASURED_BLOCK_TRAFFIC = {(128, 32): 2004021313}
+
+
 KERNEL_NAMES = {0: "cg_spmv_pq (FP64 CSR SpMV + p.q)", 1: "vc_pre_smooth_1 (level 0)",
                 2: "vc_post_smooth_final_rz (level 0)", 3: "vc_restrict (level 0)",
                 4: "vc_prolong (level 0)", 5: "vc_pre_smooth_2 (level 0)", 6: "vc_post_residual (level 0)"}
@@ -201,7 +208,8 @@ def block_bench(P, capi, reps: int = 3, N: int = 128, k: int = 32):
                              "achieved": alg / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": alg / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if avg_ms > 0 else None,
-                             "alg_bytes": alg, "launches": launches, "avg_us": 1e3 * avg_ms}}
+                             "alg_bytes": alg, "launches": launches, "avg_us": 1e3 * avg_ms,
+                             "traffic": MEASURED_BLOCK_TRAFFIC.get((N, k))}}
     hm.close()
     hd.close()
     s.close()

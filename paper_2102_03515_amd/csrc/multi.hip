@@ -45,11 +45,13 @@ struct CgBlock {
     double alpha[kMaxCols], beta[kMaxCols];
     double pq[kMaxCols];      // p.Ap
     double rr[kMaxCols];      // r.r
+    double xa[kMaxCols];      // alpha still to be added to X (times the current P), 0 if none
     int32_t cflag[kMaxCols];  // 0 running, 1 converged, 2 breakdown, 3 iteration cap
     int32_t citer[kMaxCols];  // iterations taken by column j
     int32_t flag;             // 1 once no column runs
     int32_t iter;             // block iterations
-    int32_t k, stop_mode, maxit, pad;
+    int32_t k, stop_mode, maxit;
+    int32_t xpend;            // some xa[j] != 0
 };
 
 // Tiling of a block launch: the k columns are cut into panels of KB columns
@@ -625,10 +627,10 @@ __global__ void __launch_bounds__(kBlock) k_blk_resid2(int32_t n, int k, BlkT bt
     dev::blk_store_partial<KB>(acc, partials, nbs, k, panel, tile);
 }
 
-// X += alpha P, R -= alpha Q, r.r per column; with JAC also Z = dinv R and r.z
+// R -= alpha Q, r.r per column; with JAC also Z = dinv R and r.z.  X += alpha P
+// waits for k_blk_pupdate, which reads P anyway (8 bytes per entry fewer).
 template <int KB, bool JAC, typename YT>
-__global__ void __launch_bounds__(kBlock) k_blk_update(int32_t n, int k, BlkT bt, double *__restrict__ X,
-                                                       double *__restrict__ R, const double *__restrict__ P,
+__global__ void __launch_bounds__(kBlock) k_blk_update(int32_t n, int k, BlkT bt, double *__restrict__ R,
                                                        const double *__restrict__ Q, const double *__restrict__ dinv,
                                                        double *__restrict__ Z, FirstStep<YT> first,
                                                        const CgBlock *cgb, double *partials, double *partials2,
@@ -637,7 +639,6 @@ __global__ void __launch_bounds__(kBlock) k_blk_update(int32_t n, int k, BlkT bt
     double rr = 0.0, rz = 0.0;
     OCP_BLK_BEGIN(KB)
     const double a = cgb->alpha[j];
-    X[e] += a * P[e];
     const double r = R[e] - a * Q[e];
     R[e] = r;
     first.put(e, row, r);
@@ -670,14 +671,28 @@ __global__ void __launch_bounds__(kBlock) k_blk_jacobi(int32_t n, int k, BlkT bt
     dev::blk_store_partial<KB>(rz, partials, nbs, k, panel, tile);
 }
 
-// P = Z + beta P
+// X += xa P (the step of this iteration's alpha, also for a column that has
+// just stopped), then P = Z + beta P for the running columns.  X gets the same
+// products in the same order as when the residual update added them.
 template <int KB>
 __global__ void __launch_bounds__(kBlock) k_blk_pupdate(int32_t n, int k, BlkT bt, double *__restrict__ P,
-                                                        const double *__restrict__ Z, const CgBlock *cgb) {
-    if (cgb->flag) return;
-    OCP_BLK_BEGIN(KB)
-    P[e] = Z[e] + cgb->beta[j] * P[e];
-    OCP_BLK_END()
+                                                        const double *__restrict__ Z, double *__restrict__ X,
+                                                        const CgBlock *cgb) {
+    if (cgb->flag && !cgb->xpend) return;
+    OCP_BLK_TILE(KB)
+    const double xa = j < k ? cgb->xa[j] : 0.0;
+    const bool ox = xa != 0.0;
+    if (!on && !ox) return;
+    const double b = on ? cgb->beta[j] : 0.0;
+    for (int it = 0; it < iters; ++it) {
+        const int row = base + it * stride + grp;
+        if (row < n) {
+            const size_t e = (size_t)row * k + j;
+            const double p = P[e];
+            if (ox) X[e] += xa * p;
+            if (on) P[e] = Z[e] + b * p;
+        }
+    }
 }
 
 // U[v][j] = X[dof(v)][j], 0 on Gamma
@@ -702,6 +717,7 @@ __global__ void __launch_bounds__(kFinBlock) k_blk_fin_init(unsigned nb, const d
             cgb->gamma[j] = 1.0;
             cgb->gamma0[j] = 0.0;
             cgb->alpha[j] = 0.0;
+            cgb->xa[j] = 0.0;
             cgb->beta[j] = 0.0;
             cgb->pq[j] = 0.0;
             cgb->citer[j] = 0;
@@ -713,6 +729,7 @@ __global__ void __launch_bounds__(kFinBlock) k_blk_fin_init(unsigned nb, const d
         cgb->iter = 0;
         cgb->stop_mode = mode;
         cgb->maxit = maxit;
+        cgb->xpend = 0;
     }
     dev::blk_update_flag(cgb);
 }
@@ -744,13 +761,18 @@ __global__ void __launch_bounds__(kFinBlock) k_blk_fin_rz(unsigned nb, const dou
     dev::blk_update_flag(cgb);
 }
 
-// alpha = gamma / p.q per running column
+// alpha = gamma / p.q per running column, also as the step xa that the next
+// k_blk_pupdate adds to X; every other column's xa is cleared (the previous
+// one was added by then), also once no column runs.
 __global__ void __launch_bounds__(kFinBlock) k_blk_fin_alpha(unsigned nb, const double *partials, int nbs,
                                                              CgBlock *cgb) {
-    if (cgb->flag) return;
+    const bool done = cgb->flag != 0;
     const int k = cgb->k;
     OCP_FIN_COLUMNS(k) {
-        if (cgb->cflag[j] != 0) continue;
+        if (done || cgb->cflag[j] != 0) {
+            if ((threadIdx.x & 63) == 0) cgb->xa[j] = 0.0;
+            continue;
+        }
         const double pq = dev::col_sum(partials, nbs, nb, j);
         if ((threadIdx.x & 63) == 0) {
             cgb->pq[j] = pq;
@@ -760,9 +782,15 @@ __global__ void __launch_bounds__(kFinBlock) k_blk_fin_alpha(unsigned nb, const 
             } else {
                 cgb->alpha[j] = cgb->gamma[j] / pq;
             }
+            cgb->xa[j] = cgb->alpha[j];
         }
     }
     dev::blk_update_flag(cgb);
+    if (threadIdx.x == 0) {
+        int any = 0;
+        for (int j = 0; j < k; ++j) any |= (cgb->xa[j] != 0.0);
+        cgb->xpend = any;
+    }
 }
 
 // r.r after the update: L2 stop test, breakdown, iteration cap; with JAC the
@@ -1123,7 +1151,8 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
         OCP_LAUNCH_CHECK();
     };
     auto pupdate = [&](void) {
-        OCP_DISPATCH_KB(KB0, (k_blk_pupdate<KB><<<LB.blocks, kBlock, 0, s>>>(n, k, LB.t, P.get(), Z.get(), cgb)));
+        OCP_DISPATCH_KB(KB0, (k_blk_pupdate<KB><<<LB.blocks, kBlock, 0, s>>>(n, k, LB.t, P.get(), Z.get(), X.get(),
+                                                                              cgb)));
         OCP_LAUNCH_CHECK();
     };
     auto spmm = [&](int kb) {
@@ -1232,11 +1261,11 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
             if (h) {
                 if (mixed) {
                     OCP_DISPATCH_KB(KB0, (k_blk_update<KB, false, float><<<LB.blocks, kBlock, 0, s>>>(
-                                             n, k, LB.t, X.get(), R.get(), P.get(), Q.get(), nullptr, nullptr, fs32,
+                                             n, k, LB.t, R.get(), Q.get(), nullptr, nullptr, fs32,
                                              cgb, part0.get(), nullptr, nbs)));
                 } else {
                     OCP_DISPATCH_KB(KB0, (k_blk_update<KB, false, double><<<LB.blocks, kBlock, 0, s>>>(
-                                             n, k, LB.t, X.get(), R.get(), P.get(), Q.get(), nullptr, nullptr, fs64,
+                                             n, k, LB.t, R.get(), Q.get(), nullptr, nullptr, fs64,
                                              cgb, part0.get(), nullptr, nbs)));
                 }
                 k_blk_fin_update<false><<<1, kFinBlock, 0, s>>>(LB.t.tiles, part0.get(), nullptr, nbs, cgb);
@@ -1244,7 +1273,7 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
                 precond();
             } else {
                 OCP_DISPATCH_KB(KB0, (k_blk_update<KB, true, float><<<LB.blocks, kBlock, 0, s>>>(
-                                         n, k, LB.t, X.get(), R.get(), P.get(), Q.get(), dinv, Z.get(), fs32, cgb,
+                                         n, k, LB.t, R.get(), Q.get(), dinv, Z.get(), fs32, cgb,
                                          part0.get(), part2.get(), nbs)));
                 k_blk_fin_update<true><<<1, kFinBlock, 0, s>>>(LB.t.tiles, part0.get(), part2.get(), nbs, cgb);
                 OCP_LAUNCH_CHECK();

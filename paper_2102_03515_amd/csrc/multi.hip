@@ -546,14 +546,14 @@ __global__ void __launch_bounds__(kBlock) k_blk_diag(int32_t n, int k, BlkT bt, 
 }
 
 // r.z per column (single-level hierarchy)
-template <int KB>
+template <int KB, typename ZT>
 __global__ void __launch_bounds__(kBlock) k_blk_rz(int32_t n, int k, BlkT bt, const double *__restrict__ r,
-                                                   const double *__restrict__ z, const CgBlock *cgb, double *partials,
+                                                   const ZT *__restrict__ z, const CgBlock *cgb, double *partials,
                                                    int nbs) {
     if (cgb && cgb->flag) return;
     double acc = 0.0;
     OCP_BLK_BEGIN(KB)
-    acc += r[e] * z[e];
+    acc += r[e] * (double)z[e];
     OCP_BLK_END()
     dev::blk_store_partial<KB>(acc, partials, nbs, k, panel, tile);
 }
@@ -673,10 +673,12 @@ __global__ void __launch_bounds__(kBlock) k_blk_jacobi(int32_t n, int k, BlkT bt
 
 // X += xa P (the step of this iteration's alpha, also for a column that has
 // just stopped), then P = Z + beta P for the running columns.  X gets the same
-// products in the same order as when the residual update added them.
-template <int KB>
+// products in the same order as when the residual update added them.  Z is
+// the preconditioner's output in its own precision (FP32 from an FP32
+// V-cycle: the values it computed, exactly).
+template <int KB, typename ZT>
 __global__ void __launch_bounds__(kBlock) k_blk_pupdate(int32_t n, int k, BlkT bt, double *__restrict__ P,
-                                                        const double *__restrict__ Z, double *__restrict__ X,
+                                                        const ZT *__restrict__ Z, double *__restrict__ X,
                                                         const CgBlock *cgb) {
     if (cgb->flag && !cgb->xpend) return;
     OCP_BLK_TILE(KB)
@@ -690,7 +692,7 @@ __global__ void __launch_bounds__(kBlock) k_blk_pupdate(int32_t n, int k, BlkT b
             const size_t e = (size_t)row * k + j;
             const double p = P[e];
             if (ox) X[e] += xa * p;
-            if (on) P[e] = Z[e] + b * p;
+            if (on) P[e] = (double)Z[e] + b * p;
         }
     }
 }
@@ -858,10 +860,10 @@ struct BlkCtx {
     std::vector<BlkLevelWork> *work;
 };
 
-// Z = B R for the k columns.  Returns the number of blocks whose r.z
-// partials the last pass stored (0 if cgb is null).
+// Z = B R for the k columns, Z in the hierarchy's precision T.  Returns the
+// number of blocks whose r.z partials the last pass stored (0 if cgb is null).
 template <int KB, int VW, typename T>
-static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *R, double *Z, const BlkCtx &bc) {
+static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const double *R, T *Z, const BlkCtx &bc) {
     const auto &lv = h->levels;
     const int L = (int)lv.size();
     const int k = bc.k;
@@ -875,12 +877,12 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
         const auto a = blk_arrays<T>(l0);
         const BlkLaunch LB = blk_launch(l0.n, KB, k);
         if (a.inv)
-            k_blk_dense<KB, T, double, double><<<LB.blocks, kBlock, 0, s>>>(l0.n, k, LB.t, a.inv, R, Z, cgb);
+            k_blk_dense<KB, T, double, T><<<LB.blocks, kBlock, 0, s>>>(l0.n, k, LB.t, a.inv, R, Z, cgb);
         else
-            k_blk_diag<KB, T, double, double><<<LB.blocks, kBlock, 0, s>>>(l0.n, k, LB.t, a.d, R, Z, cgb);
+            k_blk_diag<KB, T, double, T><<<LB.blocks, kBlock, 0, s>>>(l0.n, k, LB.t, a.d, R, Z, cgb);
         OCP_LAUNCH_CHECK();
         if (!cgb) return 0;
-        k_blk_rz<KB><<<LB.blocks, kBlock, 0, s>>>(l0.n, k, LB.t, R, Z, cgb, bc.part, bc.nbs);
+        k_blk_rz<KB, T><<<LB.blocks, kBlock, 0, s>>>(l0.n, k, LB.t, R, Z, cgb, bc.part, bc.nbs);
         OCP_LAUNCH_CHECK();
         return LB.t.tiles;
     }
@@ -1017,7 +1019,7 @@ static int blk_vw(int k) {
 }
 
 template <typename T>
-static unsigned vcycle_block(ocp_ctx *ctx, const ocp_hierarchy *h, const double *R, double *Z, const BlkCtx &bc,
+static unsigned vcycle_block(ocp_ctx *ctx, const ocp_hierarchy *h, const double *R, T *Z, const BlkCtx &bc,
                              int kb) {
     constexpr int V = 16 / (int)sizeof(T);
     unsigned nb = 0;
@@ -1138,9 +1140,11 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
     const int cached_mm = kb_mm_slot.load(std::memory_order_acquire);
     int kb_mm = forced ? std::min(forced, KBM) : (cached_mm ? cached_mm : KBM);
 
+    // an FP32 V-cycle leaves Z in FP32 (in the first half of Z's memory)
+    float *Z32 = reinterpret_cast<float *>(Z.get());
     auto precond = [&](void) {
         if (h) {
-            const unsigned nb = mixed ? vcycle_block<float>(ctx, h, R.get(), Z.get(), bc, kb_vc)
+            const unsigned nb = mixed ? vcycle_block<float>(ctx, h, R.get(), Z32, bc, kb_vc)
                                       : vcycle_block<double>(ctx, h, R.get(), Z.get(), bc, kb_vc);
             k_blk_fin_rz<<<1, kFinBlock, 0, s>>>(nb, part1.get(), nbs, cgb);
         } else {
@@ -1151,8 +1155,13 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
         OCP_LAUNCH_CHECK();
     };
     auto pupdate = [&](void) {
-        OCP_DISPATCH_KB(KB0, (k_blk_pupdate<KB><<<LB.blocks, kBlock, 0, s>>>(n, k, LB.t, P.get(), Z.get(), X.get(),
-                                                                              cgb)));
+        if (h && mixed) {
+            OCP_DISPATCH_KB(KB0, (k_blk_pupdate<KB, float><<<LB.blocks, kBlock, 0, s>>>(n, k, LB.t, P.get(), Z32,
+                                                                                         X.get(), cgb)));
+        } else {
+            OCP_DISPATCH_KB(KB0, (k_blk_pupdate<KB, double><<<LB.blocks, kBlock, 0, s>>>(n, k, LB.t, P.get(), Z.get(),
+                                                                                          X.get(), cgb)));
+        }
         OCP_LAUNCH_CHECK();
     };
     auto spmm = [&](int kb) {

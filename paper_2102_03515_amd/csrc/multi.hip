@@ -564,14 +564,16 @@ __global__ void __launch_bounds__(kBlock) k_blk_rz(int32_t n, int k, BlkT bt, co
 template <int KB, typename YT>
 __global__ void __launch_bounds__(kBlock) k_blk_init(int32_t n, int k, BlkT bt, const double *__restrict__ F,
                                                      int64_t fs_row, int fs_col, double *__restrict__ X,
-                                                     double *__restrict__ R, double *__restrict__ P,
-                                                     FirstStep<YT> first, double *partials, int nbs) {
+                                                     double *__restrict__ R, float *__restrict__ R32,
+                                                     double *__restrict__ P, FirstStep<YT> first, double *partials,
+                                                     int nbs) {
     const CgBlock *cgb = nullptr;
     double acc = 0.0;
     OCP_BLK_BEGIN(KB)
     const double fi = F[(size_t)row * fs_row + (size_t)j * fs_col];
     X[e] = 0.0;
     R[e] = fi;
+    if (R32) R32[e] = (float)fi;
     P[e] = 0.0;
     first.put(e, row, fi);
     acc += fi * fi;
@@ -629,9 +631,12 @@ __global__ void __launch_bounds__(kBlock) k_blk_resid2(int32_t n, int k, BlkT bt
 
 // R -= alpha Q, r.r per column; with JAC also Z = dinv R and r.z.  X += alpha P
 // waits for k_blk_pupdate, which reads P anyway (8 bytes per entry fewer).
+// R32 (if not null): R rounded to FP32 for an FP32 V-cycle's passes, which
+// round it so on every read.
 template <int KB, bool JAC, typename YT>
 __global__ void __launch_bounds__(kBlock) k_blk_update(int32_t n, int k, BlkT bt, double *__restrict__ R,
-                                                       const double *__restrict__ Q, const double *__restrict__ dinv,
+                                                       float *__restrict__ R32, const double *__restrict__ Q,
+                                                       const double *__restrict__ dinv,
                                                        double *__restrict__ Z, FirstStep<YT> first,
                                                        const CgBlock *cgb, double *partials, double *partials2,
                                                        int nbs) {
@@ -641,6 +646,7 @@ __global__ void __launch_bounds__(kBlock) k_blk_update(int32_t n, int k, BlkT bt
     const double a = cgb->alpha[j];
     const double r = R[e] - a * Q[e];
     R[e] = r;
+    if (R32) R32[e] = (float)r;
     first.put(e, row, r);
     rr += r * r;
     if (JAC) {
@@ -854,6 +860,7 @@ BlkArrays<float> blk_arrays<float>(const Level &L) {
 struct BlkCtx {
     int k;
     const void *y0;  // level-0 first smoothing step of R ([n][k], hierarchy precision) or null
+    const void *r32; // R in FP32 for an FP32 V-cycle ([n][k]) or null
     double *part;   // [k][nbs] partials of the final r.z
     int nbs;
     CgBlock *cgb;
@@ -932,7 +939,9 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
             }
             OCP_LAUNCH_CHECK();
         };
-        if (l == 0)
+        if (l == 0 && bc.r32)
+            run_down(static_cast<const T *>(bc.r32));
+        else if (l == 0)
             run_down(R);
         else
             run_down(static_cast<const T *>(lvec(l, &BlkLevelWork::vb)));
@@ -967,8 +976,11 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
         T *x1 = lvec(l, &BlkLevelWork::vx1);
         const T ca = (T)cur.cheb_a, c1 = (T)cur.cheb_c1, c2 = (T)cur.cheb_c2;
         const T zero = T(0);
-        auto run_up = [&](auto bptr, auto outptr, auto dot_tag) {
+        // bptr: the level's right-hand side; bzptr: the same for the last
+        // pass, whose b.z is taken in double (R itself on level 0)
+        auto run_up = [&](auto bptr, auto bzptr, auto outptr, auto dot_tag) {
             using BT = std::remove_const_t<std::remove_pointer_t<decltype(bptr)>>;
+            using BZT = std::remove_const_t<std::remove_pointer_t<decltype(bzptr)>>;
             using OT = std::remove_pointer_t<decltype(outptr)>;
             constexpr bool DOT = decltype(dot_tag)::value;
             if (cur.deg == 2)
@@ -985,26 +997,33 @@ static unsigned vcycle_block_t(ocp_ctx *ctx, const ocp_hierarchy *h, const doubl
                     cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
                     BlkOps<T, BT, T, false, kBPostA, VW>{a.d, bptr, xp, xp, nullptr, ca, c1, c2, r0, x1, k}, cgb, nullptr,
                     0);
-                k_blk_smooth<KB, VW, T, BT, OT, false, kBZ, DOT><<<LB.blocks, kBlock, 0, s>>>(
+                k_blk_smooth<KB, VW, T, BZT, OT, false, kBZ, DOT><<<LB.blocks, kBlock, 0, s>>>(
                     cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
-                    BlkOps<T, BT, OT, false, kBZ, VW>{a.d, bptr, x1, xp, r0, ca, c1, c2, outptr, nullptr, k}, cgb,
+                    BlkOps<T, BZT, OT, false, kBZ, VW>{a.d, bzptr, x1, xp, r0, ca, c1, c2, outptr, nullptr, k}, cgb,
                     DOT ? bc.part : nullptr, bc.nbs);
             } else {
-                k_blk_smooth<KB, VW, T, BT, OT, false, kBZ, DOT><<<LB.blocks, kBlock, 0, s>>>(
+                k_blk_smooth<KB, VW, T, BZT, OT, false, kBZ, DOT><<<LB.blocks, kBlock, 0, s>>>(
                     cur.n, k, LB.t, cur.A_rp, cur.A_col, a.A,
-                    BlkOps<T, BT, OT, false, kBZ, VW>{a.d, bptr, xp, xp, nullptr, ca, zero, ca, outptr, nullptr, k}, cgb,
-                    DOT ? bc.part : nullptr, bc.nbs);
+                    BlkOps<T, BZT, OT, false, kBZ, VW>{a.d, bzptr, xp, xp, nullptr, ca, zero, ca, outptr, nullptr, k},
+                    cgb, DOT ? bc.part : nullptr, bc.nbs);
             }
             OCP_LAUNCH_CHECK();
             if (DOT) fin_nb = LB.t.tiles;
         };
         if (l == 0) {
-            if (cgb)
-                run_up(R, Z, std::true_type{});
+            auto up0 = [&](auto bptr) {
+                if (cgb)
+                    run_up(bptr, R, Z, std::true_type{});
+                else
+                    run_up(bptr, R, Z, std::false_type{});
+            };
+            if (bc.r32)
+                up0(static_cast<const T *>(bc.r32));
             else
-                run_up(R, Z, std::false_type{});
+                up0(R);
         } else {
-            run_up(static_cast<const T *>(lvec(l, &BlkLevelWork::vb)), lvec(l, &BlkLevelWork::vx), std::false_type{});
+            const T *vb = lvec(l, &BlkLevelWork::vb);
+            run_up(vb, vb, lvec(l, &BlkLevelWork::vx), std::false_type{});
         }
     }
     return fin_nb;
@@ -1114,7 +1133,11 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
         else
             fs64 = {reinterpret_cast<double *>(y0buf.get()), l0.dinv.get(), l0.cheb_a};
     }
-    BlkCtx bc{k, want_y0 ? y0buf.get() : nullptr, part1.get(), nbs, cgb, &work};
+    // an FP32 V-cycle leaves Z in FP32 in the first half of Z's memory and
+    // reads R rounded to FP32 from the second half
+    float *Z32 = reinterpret_cast<float *>(Z.get());
+    float *R32 = mixed && want_y0 ? Z32 + nk : nullptr;
+    BlkCtx bc{k, want_y0 ? y0buf.get() : nullptr, R32, part1.get(), nbs, cgb, &work};
     hipStream_t s = ctx->stream;
     const int32_t *rp = sys->row_ptr.get(), *ci = sys->col.get();
     const double *av = sys->val.get();
@@ -1140,8 +1163,6 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
     const int cached_mm = kb_mm_slot.load(std::memory_order_acquire);
     int kb_mm = forced ? std::min(forced, KBM) : (cached_mm ? cached_mm : KBM);
 
-    // an FP32 V-cycle leaves Z in FP32 (in the first half of Z's memory)
-    float *Z32 = reinterpret_cast<float *>(Z.get());
     auto precond = [&](void) {
         if (h) {
             const unsigned nb = mixed ? vcycle_block<float>(ctx, h, R.get(), Z32, bc, kb_vc)
@@ -1181,10 +1202,12 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
     OCP_HIP(hipEventRecord(ctx->ev0, s));
     if (mixed) {
         OCP_DISPATCH_KB(KB0, (k_blk_init<KB, float><<<LB.blocks, kBlock, 0, s>>>(
-                                 n, k, LB.t, Fp, fs_row, fs_col, X.get(), R.get(), P.get(), fs32, part0.get(), nbs)));
+                                 n, k, LB.t, Fp, fs_row, fs_col, X.get(), R.get(), R32, P.get(), fs32, part0.get(),
+                                 nbs)));
     } else {
         OCP_DISPATCH_KB(KB0, (k_blk_init<KB, double><<<LB.blocks, kBlock, 0, s>>>(
-                                 n, k, LB.t, Fp, fs_row, fs_col, X.get(), R.get(), P.get(), fs64, part0.get(), nbs)));
+                                 n, k, LB.t, Fp, fs_row, fs_col, X.get(), R.get(), nullptr, P.get(), fs64, part0.get(),
+                                 nbs)));
     }
     k_blk_fin_init<<<1, kFinBlock, 0, s>>>(LB.t.tiles, part0.get(), nbs, cgb, k, rtol, mode, maxit);
     OCP_LAUNCH_CHECK();
@@ -1211,12 +1234,12 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
                             if constexpr (VW != 2) {
                                 float *x2 = reinterpret_cast<float *>(work[0].vx2.get());
                                 float *rr = reinterpret_cast<float *>(work[0].vr.get());
-                                k_blk_smooth<KB, VW, float, double, float, false, kBR, false>
+                                k_blk_smooth<KB, VW, float, float, float, false, kBR, false>
                                     <<<LV.blocks, kBlock, 0, s>>>(
                                         l0.n, k, LV.t, l0.A_rp, l0.A_col, l0.A_val32.get(),
-                                        BlkOps<float, double, float, false, kBR, VW>{l0.dinv32.get(), R.get(), x2,
-                                                                                    nullptr, nullptr, 0.f, 0.f, 0.f,
-                                                                                    rr, nullptr, k},
+                                        BlkOps<float, float, float, false, kBR, VW>{l0.dinv32.get(), R32, x2, nullptr,
+                                                                                   nullptr, 0.f, 0.f, 0.f, rr,
+                                                                                   nullptr, k},
                                         cgb, nullptr, 0);
                             }
                         };
@@ -1270,11 +1293,11 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
             if (h) {
                 if (mixed) {
                     OCP_DISPATCH_KB(KB0, (k_blk_update<KB, false, float><<<LB.blocks, kBlock, 0, s>>>(
-                                             n, k, LB.t, R.get(), Q.get(), nullptr, nullptr, fs32,
+                                             n, k, LB.t, R.get(), R32, Q.get(), nullptr, nullptr, fs32,
                                              cgb, part0.get(), nullptr, nbs)));
                 } else {
                     OCP_DISPATCH_KB(KB0, (k_blk_update<KB, false, double><<<LB.blocks, kBlock, 0, s>>>(
-                                             n, k, LB.t, R.get(), Q.get(), nullptr, nullptr, fs64,
+                                             n, k, LB.t, R.get(), nullptr, Q.get(), nullptr, nullptr, fs64,
                                              cgb, part0.get(), nullptr, nbs)));
                 }
                 k_blk_fin_update<false><<<1, kFinBlock, 0, s>>>(LB.t.tiles, part0.get(), nullptr, nbs, cgb);
@@ -1282,7 +1305,7 @@ static void solve_multi(ocp_ctx *ctx, ocp_system *sys, const ocp_hierarchy *h, i
                 precond();
             } else {
                 OCP_DISPATCH_KB(KB0, (k_blk_update<KB, true, float><<<LB.blocks, kBlock, 0, s>>>(
-                                         n, k, LB.t, R.get(), Q.get(), dinv, Z.get(), fs32, cgb,
+                                         n, k, LB.t, R.get(), nullptr, Q.get(), dinv, Z.get(), fs32, cgb,
                                          part0.get(), part2.get(), nbs)));
                 k_blk_fin_update<true><<<1, kFinBlock, 0, s>>>(LB.t.tiles, part0.get(), part2.get(), nbs, cgb);
                 OCP_LAUNCH_CHECK();

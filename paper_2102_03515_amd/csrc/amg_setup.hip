@@ -296,6 +296,124 @@ __global__ void __launch_bounds__(256) k_mis_m2(int32_t n, const int32_t *__rest
     if (any != 0ull && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)any) - 1)) *undecided = 1;
 }
 
+// The same rounds on level 0 over the system's sliced-ELL copy, when every
+// entry is strong: one lane per row, half a byte of column code per entry
+// instead of four, and since the rows of a slice mostly share their offsets,
+// the gathers of one entry over the slice's rows are mostly contiguous.  The
+// maxima take every stored entry, the diagonal and the padding (the row
+// itself) included; these add only the row's own key (m1) or m1 value (m2),
+// which enter the maximum anyway, so the results are those of k_mis_m1 /
+// k_mis_m2.
+//
+// f(c) for chunks of kSellChunk columns of this lane's row (entries 0 .. w-1,
+// entries past w repeating entry w-1; rows past n name columns of row 0).
+// Every lane of the wavefront calls it (w is uniform over the slice).
+template <typename F>
+__device__ __forceinline__ void sell_cols_of(const SellCols &C, int64_t slice, int row, int n, int64_t base, int w,
+                                             F f) {
+    w = __builtin_amdgcn_readfirstlane(w);
+    int c[kSellChunk];
+    if (!C.code) {
+        for (int j0 = 0; j0 < w; j0 += kSellChunk) {
+#pragma unroll
+            for (int j = 0; j < kSellChunk; ++j) {
+                const int jj = j0 + j < w ? j0 + j : w - 1;
+                c[j] = C.col[base + (int64_t)jj * kSellC];
+            }
+            f(c);
+        }
+        return;
+    }
+    const int lane = threadIdx.x & 63;
+    const int rr = row < n ? row : 0;
+    const int dl = C.dict[slice * kSellDict + (lane & (kSellDict - 1))];
+    const int64_t cb = C.cp[slice] + lane;
+    for (int j0 = 0; j0 < w; j0 += kSellChunk) {
+        uint32_t cw[kSellChunk / 8];
+#pragma unroll
+        for (int q = 0; q < kSellChunk / 8; ++q) {
+            const int qq = j0 + 8 * q < w ? j0 / 8 + q : (w - 1) / 8;
+            cw[q] = C.code[cb + (int64_t)qq * kSellC];
+        }
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j) {
+            const int jj = j0 + j < w ? j : w - 1 - j0;
+            const uint32_t word = (jj >> 3) ? cw[1] : cw[0];
+            c[j] = rr + __shfl(dl, (int)((word >> (4 * (jj & 7))) & 15u), 64);
+        }
+        f(c);
+    }
+}
+
+template <bool FIRST>
+__global__ void __launch_bounds__(kBlock) k_mis_m1_sell(int32_t n, int64_t nslices, int spb,
+                                                        const int32_t *__restrict__ sp,
+                                                        const int32_t *__restrict__ sw, SellCols C,
+                                                        const int8_t *__restrict__ state, uint32_t salt,
+                                                        const int32_t *__restrict__ need, int32_t round,
+                                                        const int32_t *__restrict__ prev_undecided,
+                                                        uint64_t *__restrict__ m1) {
+    if (prev_undecided && *prev_undecided == 0) return;   // every node decided in an earlier round
+    OCP_SELL_BEGIN(nslices, spb)
+    const bool act = row < n && (!need || need[row] == round);
+    if (__ballot(act) == 0ull) continue;   // uniform over the slice
+    const int rr = row < n ? row : 0;
+    uint64_t m = mis_key(rr, FIRST ? (int8_t)0 : state[rr], salt);
+    sell_cols_of(C, slice, row, n, base, w, [&](const int (&c)[kSellChunk]) {
+        int8_t st[kSellChunk];
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j) st[j] = FIRST ? (int8_t)0 : state[c[j]];
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j) {
+            const uint64_t kj = mis_key(c[j], st[j], salt);
+            m = kj > m ? kj : m;
+        }
+    });
+    if (act) m1[row] = m;
+    OCP_SELL_END()
+}
+
+__global__ void __launch_bounds__(kBlock) k_mis_m2_sell(int32_t n, int64_t nslices, int spb,
+                                                        const int32_t *__restrict__ sp,
+                                                        const int32_t *__restrict__ sw, SellCols C,
+                                                        int8_t *__restrict__ state, uint32_t salt,
+                                                        const uint64_t *__restrict__ m1, int32_t *__restrict__ need,
+                                                        int32_t round, const int32_t *__restrict__ prev_undecided,
+                                                        int32_t *undecided) {
+    if (prev_undecided && *prev_undecided == 0) return;   // every node decided in an earlier round
+    OCP_SELL_BEGIN(nslices, spb)
+    const bool act = row < n && state[row] == 0;
+    if (__ballot(act) == 0ull) continue;   // uniform over the slice
+    const int rr = row < n ? row : 0;
+    uint64_t m = m1[rr];
+    sell_cols_of(C, slice, row, n, base, w, [&](const int (&c)[kSellChunk]) {
+        uint64_t v[kSellChunk];
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j) v[j] = m1[c[j]];
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j) m = v[j] > m ? v[j] : m;
+    });
+    const bool joins = act && m == mis_key(row, 0, salt);
+    const bool leaves = act && !joins && (m >> 62) == 3u;
+    const bool still = act && !joins && !leaves;
+    if (joins)
+        state[row] = 1;
+    else if (leaves)
+        state[row] = 2;
+    if (need && __ballot(still) != 0ull) {
+        if (still) need[row] = round + 1;
+        sell_cols_of(C, slice, row, n, base, w, [&](const int (&c)[kSellChunk]) {
+            if (still) {
+#pragma unroll
+                for (int j = 0; j < kSellChunk; ++j) need[c[j]] = round + 1;
+            }
+        });
+    }
+    const unsigned long long any = __ballot(still);
+    if (any != 0ull && lane == __ffsll((long long)any) - 1) *undecided = 1;
+    OCP_SELL_END()
+}
+
 // Rounds over a list of the nodes still undecided when few are left (the
 // list is built once; nodes decided later stay in it and are skipped).
 // k_mis_m1_list recomputes m1 for every node of the closed neighbourhood of
@@ -1882,6 +2000,10 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
             const uint32_t salt = 0x9E3779B9u * (uint32_t)(lev + 1);
             constexpr int GM = 4;
             const unsigned gb = grid_for((int64_t)n * GM, 256);
+            // level 0 with every entry strong: the full rounds walk the
+            // system's sliced-ELL copy
+            const bool sell0 = lev == 0 && !strong.get() && sys->sell.col.get() && sys->sell.n == n;
+            const SellLaunch LS0 = sell_launch(sell0 ? sys->sell.nslices : 1);
             // undec[r] = 1 when some node is still undecided after round r
             // (r = 1..kMisMaxRounds).  Rounds are enqueued in batches between
             // host reads of the flag of a batch's last round; the kernels of a
@@ -1906,6 +2028,23 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
                 }
                 for (; round <= last; ++round) {
                     const int32_t *prev = round == 1 ? nullptr : undec.get() + round - 1;
+                    int32_t *nd1 = round > kMisMarkFrom ? need.get() : nullptr;
+                    int32_t *nd2 = round >= kMisMarkFrom ? need.get() : nullptr;
+                    if (sell0) {
+                        const Sell &S = sys->sell;
+                        if (round == 1)
+                            k_mis_m1_sell<true><<<LS0.blocks, kBlock, 0, s>>>(
+                                n, S.nslices, LS0.slices_per_block, S.sp.get(), S.sw.get(), sell_cols(S),
+                                state.get(), salt, nullptr, round, nullptr, m1.get());
+                        else
+                            k_mis_m1_sell<false><<<LS0.blocks, kBlock, 0, s>>>(
+                                n, S.nslices, LS0.slices_per_block, S.sp.get(), S.sw.get(), sell_cols(S),
+                                state.get(), salt, nd1, round, prev, m1.get());
+                        k_mis_m2_sell<<<LS0.blocks, kBlock, 0, s>>>(n, S.nslices, LS0.slices_per_block, S.sp.get(),
+                                                                    S.sw.get(), sell_cols(S), state.get(), salt,
+                                                                    m1.get(), nd2, round, prev, undec.get() + round);
+                        continue;
+                    }
                     // the first rounds leave most nodes undecided: marking their
                     // neighbourhoods would cost more than the m1 work it skips,
                     // so m1 takes every node until the marks start
@@ -1915,11 +2054,9 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
                                                               nullptr, round, nullptr, m1.get());
                     else
                         k_mis_m1<GM, false><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt,
-                                                               round > kMisMarkFrom ? need.get() : nullptr, round,
-                                                               prev, m1.get());
-                    k_mis_m2<GM><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get(),
-                                                    round >= kMisMarkFrom ? need.get() : nullptr, round, prev,
-                                                    undec.get() + round);
+                                                               nd1, round, prev, m1.get());
+                    k_mis_m2<GM><<<gb, 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), salt, m1.get(), nd2,
+                                                    round, prev, undec.get() + round);
                 }
                 OCP_LAUNCH_CHECK();
                 int32_t und = 0;

@@ -591,6 +591,87 @@ __global__ void k_agg2(int32_t n, const int32_t *__restrict__ rp, const int32_t 
     assigned[i] = 3;
 }
 
+// The same two passes on level 0 over the system's sliced-ELL copy when every
+// entry is strong (as the independent-set rounds there).  The diagonal and the
+// padding name the row itself, which is neither a root (k_agg1 looks for roots
+// only for non-roots) nor assigned in the first pass (k_agg2 runs for nodes
+// that are not), so the choices are those of k_agg1 / k_agg2.
+__global__ void __launch_bounds__(kBlock) k_agg1_sell(int32_t n, int64_t nslices, int spb,
+                                                      const int32_t *__restrict__ sp, const int32_t *__restrict__ sw,
+                                                      SellCols C, const int8_t *__restrict__ state,
+                                                      const int32_t *__restrict__ root_pos, uint32_t salt,
+                                                      int32_t *__restrict__ agg, int8_t *__restrict__ assigned) {
+    OCP_SELL_BEGIN(nslices, spb)
+    const int8_t si = row < n ? state[row] : (int8_t)1;
+    if (__ballot(si != 1) == 0ull) {   // every row of the slice a root (or past n)
+        if (row < n) {
+            agg[row] = root_pos[row];
+            assigned[row] = 1;
+        }
+        continue;
+    }
+    uint64_t best = 0;
+    int bj = -1;
+    sell_cols_of(C, slice, row, n, base, w, [&](const int (&c)[kSellChunk]) {
+        int8_t st[kSellChunk];
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j) st[j] = state[c[j]];
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j)
+            if (st[j] == 1) {
+                const uint64_t kj = mis_key(c[j], 1, salt);
+                if (kj > best) {
+                    best = kj;
+                    bj = c[j];
+                }
+            }
+    });
+    if (row < n) {
+        if (si == 1) {
+            agg[row] = root_pos[row];
+            assigned[row] = 1;
+        } else {
+            agg[row] = bj >= 0 ? root_pos[bj] : -1;
+            assigned[row] = bj >= 0 ? 2 : 0;
+        }
+    }
+    OCP_SELL_END()
+}
+
+__global__ void __launch_bounds__(kBlock) k_agg2_sell(int32_t n, int64_t nslices, int spb,
+                                                      const int32_t *__restrict__ sp, const int32_t *__restrict__ sw,
+                                                      SellCols C, int8_t *__restrict__ assigned, uint32_t salt,
+                                                      int32_t *__restrict__ agg, int32_t *flag) {
+    OCP_SELL_BEGIN(nslices, spb)
+    const bool act = row < n && assigned[row] == 0;
+    if (__ballot(act) == 0ull) continue;   // uniform over the slice
+    uint64_t best = 0;
+    int bj = -1;
+    sell_cols_of(C, slice, row, n, base, w, [&](const int (&c)[kSellChunk]) {
+        int8_t st[kSellChunk];
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j) st[j] = assigned[c[j]];
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j)
+            if (st[j] == 2) {
+                const uint64_t kj = mis_key(c[j], 2, salt);
+                if (kj > best) {
+                    best = kj;
+                    bj = c[j];
+                }
+            }
+    });
+    if (act) {
+        if (bj < 0) {
+            atomicOr(flag, 16);
+        } else {
+            agg[row] = agg[bj];
+            assigned[row] = 3;
+        }
+    }
+    OCP_SELL_END()
+}
+
 // Aggregate sizes.  Neighbouring nodes often share an aggregate: within a
 // wavefront each run of equal aggregates adds its length with one atomic
 // (lanes past n hold -1, so a run never extends past the last node).
@@ -2085,11 +2166,22 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
             nc = (int32_t)scan_exclusive(ctx, rflag.get(), rpos.get(), n);
             L.agg.reset(ctx, n);
             DevBuf<int8_t> assigned(ctx, n);
-            k_agg1<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), rpos.get(), salt,
-                                                    L.agg.get(), assigned.get());
-            fill_zero_bytes(ctx, ctx->dev_flag, 4);
-            k_agg2<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), assigned.get(), salt, L.agg.get(),
-                                                    ctx->dev_flag);
+            if (sell0) {
+                const Sell &S = sys->sell;
+                k_agg1_sell<<<LS0.blocks, kBlock, 0, s>>>(n, S.nslices, LS0.slices_per_block, S.sp.get(), S.sw.get(),
+                                                          sell_cols(S), state.get(), rpos.get(), salt, L.agg.get(),
+                                                          assigned.get());
+                fill_zero_bytes(ctx, ctx->dev_flag, 4);
+                k_agg2_sell<<<LS0.blocks, kBlock, 0, s>>>(n, S.nslices, LS0.slices_per_block, S.sp.get(), S.sw.get(),
+                                                          sell_cols(S), assigned.get(), salt, L.agg.get(),
+                                                          ctx->dev_flag);
+            } else {
+                k_agg1<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), state.get(), rpos.get(),
+                                                        salt, L.agg.get(), assigned.get());
+                fill_zero_bytes(ctx, ctx->dev_flag, 4);
+                k_agg2<<<grid_for(n, 256), 256, 0, s>>>(n, L.A_rp, L.A_col, strong.get(), assigned.get(), salt,
+                                                        L.agg.get(), ctx->dev_flag);
+            }
             OCP_LAUNCH_CHECK();
             read_back(ctx, &fl, ctx->dev_flag, 4);
             if (fl & 16) fail(OCP_ERR_HIP, "aggregation left a node unassigned");

@@ -537,8 +537,9 @@ def _renumbered(mesh, seed):
 def test_sell_column_codes_and_plain_columns(P, ctx):
     """The lexicographic Kuhn mesh gets the coded sliced-ELL columns; the same
     mesh with scattered vertex numbers falls back to plain columns.  Both
-    SpMVs match the oracle's, and both AMG-PCG solves match the oracle's
-    solution to 1e-10."""
+    SpMVs match the oracle's, both level-0 aggregations (whose independent-set
+    rounds walk the sliced-ELL copy, coded or plain) are the oracle's, and both
+    AMG-PCG solves match the oracle's solution to 1e-10."""
     import torch
     for renum in (False, True):
         print(f"[sell codes] cube10 jitter renumbered={renum}", flush=True)
@@ -553,6 +554,10 @@ def test_sell_column_codes_and_plain_columns(P, ctx):
         bound = 32 * 2.2e-16 * np.abs(o.val).max() * np.abs(x).max()
         assert np.abs(y - O.spmv(o, x)).max() <= bound
         h = P.amg_setup(ctx, s, coarse_max=32)
+        ol = OA.build_hierarchy(o.csr(), theta=0.0, coarse_max=32)
+        assert h.n_levels == len(ol)
+        np.testing.assert_array_equal(h.level_arrays(0)["agg"].cpu().numpy(), ol[0]["agg"],
+                                      err_msg=f"level-0 aggregates, renumbered={renum}")
         u, info, rc = P.pcg_solve(ctx, s, h, rtol=1e-13, maxit=500)
         assert rc == 0
         xo, oo, _, _ = O.solve(mesh, 1e-2, I.box_indicator(), rtol=1e-14)

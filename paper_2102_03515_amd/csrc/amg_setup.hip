@@ -305,9 +305,10 @@ __global__ void __launch_bounds__(256) k_mis_m2(int32_t n, const int32_t *__rest
 // which enter the maximum anyway, so the results are those of k_mis_m1 /
 // k_mis_m2.
 //
-// f(c) for chunks of kSellChunk columns of this lane's row (entries 0 .. w-1,
-// entries past w repeating entry w-1; rows past n name columns of row 0).
-// Every lane of the wavefront calls it (w is uniform over the slice).
+// f(c, j0) for chunks of kSellChunk columns of this lane's row: c[j] is the
+// column of entry j0 + j for j0 + j < w, entries past w repeat entry w-1; rows
+// past n name columns of row 0.  Every lane of the wavefront calls it (w is
+// uniform over the slice).
 template <typename F>
 __device__ __forceinline__ void sell_cols_of(const SellCols &C, int64_t slice, int row, int n, int64_t base, int w,
                                              F f) {
@@ -320,7 +321,7 @@ __device__ __forceinline__ void sell_cols_of(const SellCols &C, int64_t slice, i
                 const int jj = j0 + j < w ? j0 + j : w - 1;
                 c[j] = C.col[base + (int64_t)jj * kSellC];
             }
-            f(c);
+            f(c, j0);
         }
         return;
     }
@@ -341,7 +342,7 @@ __device__ __forceinline__ void sell_cols_of(const SellCols &C, int64_t slice, i
             const uint32_t word = (jj >> 3) ? cw[1] : cw[0];
             c[j] = rr + __shfl(dl, (int)((word >> (4 * (jj & 7))) & 15u), 64);
         }
-        f(c);
+        f(c, j0);
     }
 }
 
@@ -359,7 +360,7 @@ __global__ void __launch_bounds__(kBlock) k_mis_m1_sell(int32_t n, int64_t nslic
     if (__ballot(act) == 0ull) continue;   // uniform over the slice
     const int rr = row < n ? row : 0;
     uint64_t m = mis_key(rr, FIRST ? (int8_t)0 : state[rr], salt);
-    sell_cols_of(C, slice, row, n, base, w, [&](const int (&c)[kSellChunk]) {
+    sell_cols_of(C, slice, row, n, base, w, [&](const int (&c)[kSellChunk], int) {
         int8_t st[kSellChunk];
 #pragma unroll
         for (int j = 0; j < kSellChunk; ++j) st[j] = FIRST ? (int8_t)0 : state[c[j]];
@@ -386,7 +387,7 @@ __global__ void __launch_bounds__(kBlock) k_mis_m2_sell(int32_t n, int64_t nslic
     if (__ballot(act) == 0ull) continue;   // uniform over the slice
     const int rr = row < n ? row : 0;
     uint64_t m = m1[rr];
-    sell_cols_of(C, slice, row, n, base, w, [&](const int (&c)[kSellChunk]) {
+    sell_cols_of(C, slice, row, n, base, w, [&](const int (&c)[kSellChunk], int) {
         uint64_t v[kSellChunk];
 #pragma unroll
         for (int j = 0; j < kSellChunk; ++j) v[j] = m1[c[j]];
@@ -402,7 +403,7 @@ __global__ void __launch_bounds__(kBlock) k_mis_m2_sell(int32_t n, int64_t nslic
         state[row] = 2;
     if (need && __ballot(still) != 0ull) {
         if (still) need[row] = round + 1;
-        sell_cols_of(C, slice, row, n, base, w, [&](const int (&c)[kSellChunk]) {
+        sell_cols_of(C, slice, row, n, base, w, [&](const int (&c)[kSellChunk], int) {
             if (still) {
 #pragma unroll
                 for (int j = 0; j < kSellChunk; ++j) need[c[j]] = round + 1;
@@ -612,7 +613,7 @@ __global__ void __launch_bounds__(kBlock) k_agg1_sell(int32_t n, int64_t nslices
     }
     uint64_t best = 0;
     int bj = -1;
-    sell_cols_of(C, slice, row, n, base, w, [&](const int (&c)[kSellChunk]) {
+    sell_cols_of(C, slice, row, n, base, w, [&](const int (&c)[kSellChunk], int) {
         int8_t st[kSellChunk];
 #pragma unroll
         for (int j = 0; j < kSellChunk; ++j) st[j] = state[c[j]];
@@ -647,7 +648,7 @@ __global__ void __launch_bounds__(kBlock) k_agg2_sell(int32_t n, int64_t nslices
     if (__ballot(act) == 0ull) continue;   // uniform over the slice
     uint64_t best = 0;
     int bj = -1;
-    sell_cols_of(C, slice, row, n, base, w, [&](const int (&c)[kSellChunk]) {
+    sell_cols_of(C, slice, row, n, base, w, [&](const int (&c)[kSellChunk], int) {
         int8_t st[kSellChunk];
 #pragma unroll
         for (int j = 0; j < kSellChunk; ++j) st[j] = assigned[c[j]];
@@ -1367,6 +1368,89 @@ static void spgemm_small_rows(ocp_ctx *ctx, int32_t m, const int32_t *arp, const
                                    nullptr, C.col.get(), C.val.get());
 }
 
+// The same product on level 0 over the system's sliced-ELL copy (one lane per
+// row, half a byte of column code and the value per entry, both read by whole
+// slices).  The entries come in row order, so the sums are formed in the same
+// order; the padding (column the row, value 0) adds zero to the row's own
+// aggregate, which its diagonal entry has already entered.
+template <bool NUMERIC>
+__global__ void __launch_bounds__(kBlock) k_ap_tent_sell(int32_t m, int64_t nslices, int spb,
+                                                         const int32_t *__restrict__ sp,
+                                                         const int32_t *__restrict__ sw, SellCols C,
+                                                         const double *__restrict__ sval,
+                                                         const int32_t *__restrict__ agg,
+                                                         const double *__restrict__ pt,
+                                                         const int32_t *__restrict__ crp, int32_t *__restrict__ cnt,
+                                                         int32_t *__restrict__ ccol, double *__restrict__ cval,
+                                                         int32_t *flag, const double *__restrict__ diag, double wgt) {
+    constexpr int S = 16;
+    OCP_SELL_BEGIN(nslices, spb)
+    int keys[S];
+    double acc[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        keys[q] = INT_MAX;
+        acc[q] = 0.0;
+    }
+    int nk = 0;
+    bool over = false;
+    sell_cols_of(C, slice, row, m, base, w, [&](const int (&c)[kSellChunk], int j0) {
+        int J[kSellChunk];
+        double av[kSellChunk], pv[kSellChunk];
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j) {
+            const int jj = j0 + j < w ? j0 + j : w - 1;
+            if (NUMERIC) av[j] = sval[base + (int64_t)jj * kSellC];
+            J[j] = agg[c[j]];
+            if (NUMERIC) pv[j] = pt[c[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < kSellChunk; ++j) {
+            if (j0 + j >= w) break;
+            const double v = NUMERIC ? av[j] * pv[j] : 0.0;
+            bool found = false;
+#pragma unroll
+            for (int q = 0; q < S; ++q)
+                if (keys[q] == J[j]) {
+                    acc[q] += v;
+                    found = true;
+                }
+            if (!found) {
+                if (nk == S) {
+                    over = true;
+                } else {
+#pragma unroll
+                    for (int q = 0; q < S; ++q)
+                        if (q == nk) {
+                            keys[q] = J[j];
+                            acc[q] = v;
+                        }
+                    ++nk;
+                }
+            }
+        }
+    });
+    if (row < m) {
+        if (over) atomicOr(flag, 32);
+        if (!NUMERIC) {
+            cnt[row] = nk;
+        } else {
+            dev::sort_slots(keys, acc);
+            const int b = crp[row];
+            const double swi = diag ? wgt / diag[row] : 0.0;   // (w is the slice width here)
+            const int ai = agg[row];
+            const double pti = pt[row];
+#pragma unroll
+            for (int q = 0; q < S; ++q)
+                if (q < nk) {
+                    ccol[b + q] = keys[q];
+                    cval[b + q] = diag ? (keys[q] == ai ? pti : 0.0) - swi * acc[q] : acc[q];
+                }
+        }
+    }
+    OCP_SELL_END()
+}
+
 // C = A P_tent: the register kernel when every A row has at most 16 entries,
 // otherwise the general product with P_tent as a CSR matrix
 // With diag given, the register kernel writes the smoothed prolongator
@@ -1374,15 +1458,21 @@ static void spgemm_small_rows(ocp_ctx *ctx, int32_t m, const int32_t *arp, const
 // holds A P_tent).
 static bool spgemm_ptent(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t annz, const int32_t *arp,
                          const int32_t *acol, const double *aval, const int32_t *agg, const int32_t *trp,
-                         const double *pt, Csr &C, const double *diag, double w) {
+                         const double *pt, Csr &C, const double *diag, double w, const Sell *sell) {
     if (csr_max_row(ctx, m, arp) > 16) {
         spgemm(ctx, m, ncols, annz, arp, acol, aval, trp, agg, pt, C);
         return false;
     }
     DevBuf<int32_t> cnt(ctx, (size_t)m + 1);
     fill_zero_bytes(ctx, ctx->dev_flag, 4);
-    k_ap_tent<false><<<grid_for(m, 256), 256, 0, ctx->stream>>>(m, arp, acol, aval, agg, pt, nullptr, cnt.get(),
-                                                                nullptr, nullptr, ctx->dev_flag, nullptr, 0.0);
+    const SellLaunch LS = sell_launch(sell ? sell->nslices : 1);
+    if (sell)
+        k_ap_tent_sell<false><<<LS.blocks, kBlock, 0, ctx->stream>>>(
+            m, sell->nslices, LS.slices_per_block, sell->sp.get(), sell->sw.get(), sell_cols(*sell), sell->val.get(),
+            agg, pt, nullptr, cnt.get(), nullptr, nullptr, ctx->dev_flag, nullptr, 0.0);
+    else
+        k_ap_tent<false><<<grid_for(m, 256), 256, 0, ctx->stream>>>(m, arp, acol, aval, agg, pt, nullptr, cnt.get(),
+                                                                    nullptr, nullptr, ctx->dev_flag, nullptr, 0.0);
     OCP_LAUNCH_CHECK();
     C.rows = m;
     C.cols = ncols;
@@ -1390,8 +1480,13 @@ static bool spgemm_ptent(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t annz, c
     C.nnz = scan_exclusive(ctx, cnt.get(), C.rp.get(), m);
     C.col.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
     C.val.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
-    k_ap_tent<true><<<grid_for(m, 256), 256, 0, ctx->stream>>>(m, arp, acol, aval, agg, pt, C.rp.get(), nullptr,
-                                                               C.col.get(), C.val.get(), ctx->dev_flag, diag, w);
+    if (sell)
+        k_ap_tent_sell<true><<<LS.blocks, kBlock, 0, ctx->stream>>>(
+            m, sell->nslices, LS.slices_per_block, sell->sp.get(), sell->sw.get(), sell_cols(*sell), sell->val.get(),
+            agg, pt, C.rp.get(), nullptr, C.col.get(), C.val.get(), ctx->dev_flag, diag, w);
+    else
+        k_ap_tent<true><<<grid_for(m, 256), 256, 0, ctx->stream>>>(m, arp, acol, aval, agg, pt, C.rp.get(), nullptr,
+                                                                   C.col.get(), C.val.get(), ctx->dev_flag, diag, w);
     OCP_LAUNCH_CHECK();
     return diag != nullptr;
 }
@@ -2211,8 +2306,9 @@ static void setup(ocp_ctx *ctx, const ocp_system *sys, ocp_hierarchy *h) {
         // smoothed prolongator P = (I - w D^-1 A) P_tent
         Csr P;
         const double w = pr.omega / L.lambda_max;
+        const Sell *sell = lev == 0 && sys->sell.col.get() && sys->sell.n == n ? &sys->sell : nullptr;
         if (!spgemm_ptent(ctx, n, nc, L.nnzA, L.A_rp, L.A_col, L.A_val, tcol.get(), trp.get(), tval.get(), P,
-                          diag.get(), w))
+                          diag.get(), w, sell))
             k_smooth_p<<<grid_for(n, 256), 256, 0, s>>>(n, P.rp.get(), P.col.get(), P.val.get(), diag.get(),
                                                         L.agg.get(), tval.get(), w);
         OCP_LAUNCH_CHECK();

@@ -1368,20 +1368,19 @@ static void spgemm_small_rows(ocp_ctx *ctx, int32_t m, const int32_t *arp, const
                                    nullptr, C.col.get(), C.val.get());
 }
 
-// The same product on level 0 over the system's sliced-ELL copy (one lane per
-// row, half a byte of column code and the value per entry, both read by whole
-// slices).  The entries come in row order, so the sums are formed in the same
-// order; the padding (column the row, value 0) adds zero to the row's own
-// aggregate, which its diagonal entry has already entered.
-template <bool NUMERIC>
+// The numeric pass of the same product on level 0 over the system's
+// sliced-ELL copy (one lane per row, half a byte of column code and the value
+// per entry, both read by whole slices).  The entries come in row order, so
+// the sums are formed in the same order; the padding (column the row, value 0)
+// adds zero to the row's own aggregate, which its diagonal entry has already
+// entered, so the row has the columns the count pass found.
 __global__ void __launch_bounds__(kBlock) k_ap_tent_sell(int32_t m, int64_t nslices, int spb,
                                                          const int32_t *__restrict__ sp,
                                                          const int32_t *__restrict__ sw, SellCols C,
                                                          const double *__restrict__ sval,
                                                          const int32_t *__restrict__ agg,
                                                          const double *__restrict__ pt,
-                                                         const int32_t *__restrict__ crp, int32_t *__restrict__ cnt,
-                                                         int32_t *__restrict__ ccol, double *__restrict__ cval,
+                                                         const int32_t *__restrict__ crp, int32_t *__restrict__ ccol, double *__restrict__ cval,
                                                          int32_t *flag, const double *__restrict__ diag, double wgt) {
     constexpr int S = 16;
     OCP_SELL_BEGIN(nslices, spb)
@@ -1400,14 +1399,14 @@ __global__ void __launch_bounds__(kBlock) k_ap_tent_sell(int32_t m, int64_t nsli
 #pragma unroll
         for (int j = 0; j < kSellChunk; ++j) {
             const int jj = j0 + j < w ? j0 + j : w - 1;
-            if (NUMERIC) av[j] = sval[base + (int64_t)jj * kSellC];
+            av[j] = sval[base + (int64_t)jj * kSellC];
             J[j] = agg[c[j]];
-            if (NUMERIC) pv[j] = pt[c[j]];
+            pv[j] = pt[c[j]];
         }
 #pragma unroll
         for (int j = 0; j < kSellChunk; ++j) {
             if (j0 + j >= w) break;
-            const double v = NUMERIC ? av[j] * pv[j] : 0.0;
+            const double v = av[j] * pv[j];
             bool found = false;
 #pragma unroll
             for (int q = 0; q < S; ++q)
@@ -1432,21 +1431,17 @@ __global__ void __launch_bounds__(kBlock) k_ap_tent_sell(int32_t m, int64_t nsli
     });
     if (row < m) {
         if (over) atomicOr(flag, 32);
-        if (!NUMERIC) {
-            cnt[row] = nk;
-        } else {
-            dev::sort_slots(keys, acc);
-            const int b = crp[row];
-            const double swi = diag ? wgt / diag[row] : 0.0;   // (w is the slice width here)
-            const int ai = agg[row];
-            const double pti = pt[row];
+        dev::sort_slots(keys, acc);
+        const int b = crp[row];
+        const double swi = diag ? wgt / diag[row] : 0.0;   // (w is the slice width here)
+        const int ai = agg[row];
+        const double pti = pt[row];
 #pragma unroll
-            for (int q = 0; q < S; ++q)
-                if (q < nk) {
-                    ccol[b + q] = keys[q];
-                    cval[b + q] = diag ? (keys[q] == ai ? pti : 0.0) - swi * acc[q] : acc[q];
-                }
-        }
+        for (int q = 0; q < S; ++q)
+            if (q < nk) {
+                ccol[b + q] = keys[q];
+                cval[b + q] = diag ? (keys[q] == ai ? pti : 0.0) - swi * acc[q] : acc[q];
+            }
     }
     OCP_SELL_END()
 }
@@ -1465,15 +1460,12 @@ static bool spgemm_ptent(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t annz, c
     }
     DevBuf<int32_t> cnt(ctx, (size_t)m + 1);
     fill_zero_bytes(ctx, ctx->dev_flag, 4);
-    const SellLaunch LS = sell_launch(sell ? sell->nslices : 1);
-    if (sell)
-        k_ap_tent_sell<false><<<LS.blocks, kBlock, 0, ctx->stream>>>(
-            m, sell->nslices, LS.slices_per_block, sell->sp.get(), sell->sw.get(), sell_cols(*sell), sell->val.get(),
-            agg, pt, nullptr, cnt.get(), nullptr, nullptr, ctx->dev_flag, nullptr, 0.0);
-    else
-        k_ap_tent<false><<<grid_for(m, 256), 256, 0, ctx->stream>>>(m, arp, acol, aval, agg, pt, nullptr, cnt.get(),
-                                                                    nullptr, nullptr, ctx->dev_flag, nullptr, 0.0);
+    // counts from the CSR rows (measured faster than from the sliced-ELL copy;
+    // the same counts, every row holding its diagonal)
+    k_ap_tent<false><<<grid_for(m, 256), 256, 0, ctx->stream>>>(m, arp, acol, aval, agg, pt, nullptr, cnt.get(),
+                                                                nullptr, nullptr, ctx->dev_flag, nullptr, 0.0);
     OCP_LAUNCH_CHECK();
+    const SellLaunch LS = sell_launch(sell ? sell->nslices : 1);
     C.rows = m;
     C.cols = ncols;
     C.rp.reset(ctx, (size_t)m + 1);
@@ -1481,9 +1473,10 @@ static bool spgemm_ptent(ocp_ctx *ctx, int32_t m, int32_t ncols, int64_t annz, c
     C.col.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
     C.val.reset(ctx, (size_t)std::max<int64_t>(C.nnz, 1));
     if (sell)
-        k_ap_tent_sell<true><<<LS.blocks, kBlock, 0, ctx->stream>>>(
-            m, sell->nslices, LS.slices_per_block, sell->sp.get(), sell->sw.get(), sell_cols(*sell), sell->val.get(),
-            agg, pt, C.rp.get(), nullptr, C.col.get(), C.val.get(), ctx->dev_flag, diag, w);
+        k_ap_tent_sell<<<LS.blocks, kBlock, 0, ctx->stream>>>(m, sell->nslices, LS.slices_per_block, sell->sp.get(),
+                                                              sell->sw.get(), sell_cols(*sell), sell->val.get(), agg,
+                                                              pt, C.rp.get(), C.col.get(), C.val.get(), ctx->dev_flag,
+                                                              diag, w);
     else
         k_ap_tent<true><<<grid_for(m, 256), 256, 0, ctx->stream>>>(m, arp, acol, aval, agg, pt, C.rp.get(), nullptr,
                                                                    C.col.get(), C.val.get(), ctx->dev_flag, diag, w);
